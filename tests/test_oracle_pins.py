@@ -1,0 +1,302 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix
+(closed forms, explicit matrices, invariants, special cases).  CPU only."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+
+def tiny_iqu(fknee=(0.5, 2.0), alpha=(1.0, 2.0), lam=64, interval_len=1024, seed=7):
+    # 8x8 IQU patch, 4 co-pointed detectors, H+V passes, 2^12 samples
+    return synth.raster_iqu(side=8, spp=8, n_det=4, interval_len=interval_len, lam=lam,
+                            fknee_range=fknee, alpha_range=alpha, seed_key=seed)
+
+
+def tiny_i(fknee=1.0, lam=32, seed=11):
+    return synth.raster_i(side=8, spp=4, n_pass=8, interval_len=256, lam=lam,
+                          sigma=1.0, fknee=fknee, alpha=1.0, seed_key=seed)
+
+
+# ------------------------------------------------------------------ P1: taps
+
+def test_inverse_psd_grid_hand_values():
+    # f_m = m * f_samp / n: with n = f_samp = 200 the grid is 1 Hz
+    q = O.inverse_psd(200, sigma=1.0, fknee=1.0, alpha=1.0, f_samp=200.0)
+    assert q[0] == 0.0
+    assert q[1] == pytest.approx(0.5, rel=1e-15)
+    assert q[2] == pytest.approx(2.0 / 3.0, rel=1e-15)
+    q2 = O.inverse_psd(400, sigma=2.0, fknee=3.0, alpha=2.0, f_samp=200.0)
+    # f_2 = 1 Hz: 1 / (4 (1 + 9))
+    assert q2[2] == pytest.approx(1.0 / 40.0, rel=1e-15)
+    qw = O.inverse_psd(64, sigma=0.5, fknee=0.0, alpha=1.0, f_samp=200.0)
+    assert np.all(qw == 4.0)
+
+
+@pytest.mark.parametrize("n", [512, 513, 1000])
+@pytest.mark.parametrize("window", ["gauss", "rect"])
+def test_taps_match_explicit_cosine_sum(n, window):
+    t = O.toeplitz_taps(n, 1.3, 1.7, 1.4, 48, 200.0, window)
+    tc = O.toeplitz_taps_cosine_sum(n, 1.3, 1.7, 1.4, 48, 200.0, window)
+    assert t.shape == (49,)
+    assert np.max(np.abs(t - tc)) <= 1e-13 * np.max(np.abs(tc))
+
+
+def test_taps_white_noise_closed_form():
+    t = O.toeplitz_taps(4096, 2.0, 0.0, 1.0, 256, 200.0)
+    assert t[0] == pytest.approx(0.25, rel=1e-14)
+    assert np.max(np.abs(t[1:])) < 1e-16
+
+
+def test_taps_clipped_to_interval_and_window_values():
+    t = O.toeplitz_taps(100, 1.0, 1.0, 1.0, 500, 200.0, "rect")
+    assert t.shape == (100,)
+    full = np.fft.irfft(O.inverse_psd(1000, 1.0, 1.0, 1.0, 200.0), 1000)
+    tg = O.toeplitz_taps(1000, 1.0, 1.0, 1.0, 50, 200.0, "gauss")
+    assert tg[50] == pytest.approx(full[50] * np.exp(-1.0), rel=1e-12)
+    assert tg[0] == pytest.approx(full[0], rel=1e-15)
+
+
+def test_unwindowed_row_suppresses_the_mean():
+    # q_0 = 0: the full periodic row sums to zero, i.e. N^-1 1_t = 0 for the
+    # unbanded circulant (the near-null direction of eq. AsingVect)
+    n = 1024
+    row = np.fft.irfft(O.inverse_psd(n, 1.0, 1.0, 1.5, 200.0), n)
+    assert abs(row.sum()) < 1e-14 * np.abs(row).sum()
+    assert row[0] > 0 and row[1] < 0
+
+
+def test_symbol_positive_and_bounded_gaussian_window():
+    for (n, lam, fk, al) in [(2 ** 16, 2048, 2.0, 2.0), (2 ** 14, 1024, 5.0, 1.0),
+                             (2 ** 14, 1024, 1.0, 1.0)]:
+        t = O.toeplitz_taps(n, 1.0, fk, al, lam, 200.0)
+        s = O.taps_symbol(t, 1 << 15)
+        assert s.min() > 0.0
+        assert s.max() <= 1.0 + 1e-6
+
+
+# -------------------------------------------------------- P2: Toeplitz apply
+
+def test_banded_sums_equal_explicit_toeplitz_matrices():
+    rng = np.random.default_rng(0)
+    offsets = np.array([0, 700, 730, 2000, 2100])
+    taps = [O.toeplitz_taps(int(offsets[j + 1] - offsets[j]), 1.0, 1.0 + j, 1.5, 64, 200.0)
+            for j in range(4)]
+    y = rng.standard_normal(2100)
+    z = O.toeplitz_apply(y, offsets, taps)
+    ref = np.zeros_like(y)
+    for j in range(4):
+        a, b = offsets[j], offsets[j + 1]
+        ref[a:b] = O.toeplitz_dense(taps[j], b - a) @ y[a:b]
+    assert np.max(np.abs(z - ref)) <= 1e-13 * np.max(np.abs(ref))
+    y2 = rng.standard_normal(2100)
+    lhs = O.toeplitz_apply(y, offsets, taps) @ y2
+    rhs = y @ O.toeplitz_apply(y2, offsets, taps)
+    assert lhs == pytest.approx(rhs, rel=1e-12)
+    ts = np.array([0, 5, 699, 700, 729, 1500, 2099])
+    assert np.allclose(O.toeplitz_apply_at(y, offsets, taps, ts), ref[ts], rtol=0, atol=1e-13)
+
+
+# --------------------------------------------------------------- P3: P, P^T
+
+def test_pointing_adjoint_and_hits():
+    sc = tiny_iqu()
+    pr = O.Problem.from_scan(sc)
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(pr.n_obs * 3)
+    y = rng.standard_normal(pr.n_t)
+    assert pr.depoint(x) @ y == pytest.approx(x @ pr.point(y), rel=1e-12)
+    assert np.array_equal(pr.s, np.full(64, 4 * 2 * 8))  # 4 dets x 2 passes x 8 spp
+
+
+def test_cfg1_geometry_hits_exact():
+    sc = synth.cfg1_raster_i()
+    obs, cid = O.compact(sc.pix)
+    assert obs.shape[0] == 4096
+    assert np.array_equal(O.hits(cid, 4096), np.full(4096, 64, dtype=np.int64))
+
+
+def test_intensity_pointing_of_ones_is_hits():
+    pr = O.Problem.from_scan(tiny_i())
+    assert np.array_equal(pr.point(np.ones(pr.n_t)), pr.s.astype(np.float64))
+
+
+# ------------------------------------------------------------------- P4: A
+
+def test_A_symmetric_positive_definite_and_matches_dense():
+    pr = O.Problem.from_scan(tiny_iqu())
+    A, P, N = O.dense_system(pr)
+    assert np.max(np.abs(A - A.T)) <= 1e-13 * np.max(np.abs(A))
+    np.linalg.cholesky(A)
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal(A.shape[0])
+    assert np.max(np.abs(pr.apply_A(x) - A @ x)) <= 1e-12 * np.max(np.abs(A @ x))
+    d = rng.standard_normal(pr.n_t)
+    assert np.max(np.abs(pr.rhs(d) - P.T @ (N @ d))) <= 1e-12 * np.max(np.abs(P.T @ N @ d))
+
+
+# --------------------------------------------------------- P5: white noise
+
+def test_white_noise_block_jacobi_is_exact_inverse():
+    sc = tiny_iqu(fknee=(0.0, 0.0))
+    sc.fknee[:] = 0.0
+    pr = O.Problem.from_scan(sc)
+    A, _, _ = O.dense_system(pr)
+    B = pr.bj_blocks()
+    Ablk = np.zeros_like(A)
+    for p in range(pr.n_obs):
+        Ablk[3 * p:3 * p + 3, 3 * p:3 * p + 3] = B[p]
+    assert np.max(np.abs(A - Ablk)) <= 1e-13 * np.max(np.abs(A))
+    # explicit form: sum W W^T / sigma^2
+    Wsum = np.zeros((pr.n_obs, 3, 3))
+    np.add.at(Wsum, pr.cid, pr.W[:, :, None] * pr.W[:, None, :])
+    assert np.allclose(B, Wsum / sc.sigma[0] ** 2, rtol=1e-13, atol=1e-13)
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal(pr.n_obs * 3)
+    x, it, st = O.pcg(pr.apply_A, b, lambda r: pr.bj_apply(r, B), tol=1e-12, maxit=10)
+    assert st == 0 and it == 1
+    assert np.allclose(x, pr.bj_apply(b, B), rtol=1e-12, atol=1e-12)
+
+
+# ------------------------------------------------ P6, P10: solves, noiseless
+
+def test_noiseless_data_returns_input_map():
+    sc = tiny_iqu()
+    pr = O.Problem.from_scan(sc)
+    m = pr.sky_to_compact(sc.sky)
+    d = pr.signal(sc.sky)
+    b = pr.rhs(d)
+    x, it, st = O.pcg(pr.apply_A, b, pr.bj_apply, tol=1e-13, maxit=500)
+    assert st == 0
+    assert np.linalg.norm(x - m) / np.linalg.norm(m) < 1e-10
+
+
+def test_pcg_matches_dense_cholesky_solve():
+    sc = tiny_iqu()
+    pr = O.Problem.from_scan(sc)
+    A, P, N = O.dense_system(pr)
+    d = pr.signal(sc.sky) + sc.noise
+    b = pr.rhs(d)
+    L = np.linalg.cholesky(A)
+    xd = np.linalg.solve(L.T, np.linalg.solve(L, b))
+    x, it, st = O.pcg(pr.apply_A, b, pr.bj_apply, tol=1e-14, maxit=1000)
+    assert st == 0
+    assert np.linalg.norm(x - xd) / np.linalg.norm(xd) <= 1e-12
+    # GLS estimator written out (eq. glsSol)
+    xg = np.linalg.solve(P.T @ N @ P, P.T @ N @ d)
+    assert np.linalg.norm(xg - xd) / np.linalg.norm(xd) <= 1e-12
+
+
+def test_pcg_reports_breakdown_and_maxit():
+    pr = O.Problem.from_scan(tiny_i())
+    b = np.random.default_rng(4).standard_normal(pr.n_obs)
+    _, it, st = O.pcg(pr.apply_A, b, lambda r: r, tol=1e-14, maxit=2)
+    assert st == 1 and it == 2
+    _, it, st = O.pcg(lambda v: -pr.apply_A(v), b, lambda r: r, tol=1e-14, maxit=5)
+    assert st == 2
+
+
+# ------------------------------------------------------ P7, P8: coarse space
+
+def test_zs_structure():
+    sc = tiny_iqu(interval_len=256)
+    pr = O.Problem.from_scan(sc)
+    Z = O.coarse_zs(pr)
+    assert Z.shape == (pr.n_obs * 3, 16)
+    assert np.allclose(Z[0::3].sum(axis=1), 1.0, rtol=0, atol=1e-15)
+    assert np.all(Z[1::3] == 0) and np.all(Z[2::3] == 0)
+    sc1 = tiny_i()
+    sc1.offsets = np.array([0, sc1.n_samples])
+    sc1.sigma, sc1.fknee, sc1.alpha = sc1.sigma[:1], sc1.fknee[:1], sc1.alpha[:1]
+    Z1 = O.coarse_zs(O.Problem.from_scan(sc1))
+    assert np.array_equal(Z1, np.ones((64, 1)))
+
+
+def test_two_level_properties():
+    sc = tiny_iqu(interval_len=256)
+    pr = O.Problem.from_scan(sc)
+    Z = O.coarse_zs(pr)
+    C = O.Coarse(pr, Z)
+    # co-pointed detectors see identical hit patterns: rank deficient Z
+    assert C.rank < Z.shape[1]
+    MAZ = np.stack([C.apply(C.AZ[:, j]) for j in range(Z.shape[1])], axis=1)
+    assert np.max(np.abs(MAZ - Z)) <= 1e-10
+    RAZ = np.stack([C.deflation(C.AZ[:, j]) for j in range(Z.shape[1])], axis=1)
+    assert np.max(np.abs(RAZ)) <= 1e-10 * np.max(np.abs(C.AZ))
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((pr.n_obs * 3, 3))
+    Y = X - Z @ (C.Epinv @ (C.AZ.T @ X))     # Y^T A Z = 0
+    assert np.max(np.abs(Y.T @ C.AZ)) <= 1e-10 * np.max(np.abs(X.T @ C.AZ))
+    AY = np.stack([pr.apply_A(Y[:, i]) for i in range(3)], axis=1)
+    lhs = np.stack([C.apply(AY[:, i]) for i in range(3)], axis=1)
+    rhs = np.stack([pr.bj_apply(AY[:, i], C.B) for i in range(3)], axis=1)
+    assert np.max(np.abs(lhs - rhs)) <= 1e-9 * np.max(np.abs(rhs))
+
+
+def test_solution_independent_of_preconditioner():
+    sc = tiny_iqu(interval_len=256)
+    pr = O.Problem.from_scan(sc)
+    b = pr.rhs(pr.signal(sc.sky) + sc.noise)
+    C = O.Coarse(pr, O.coarse_zs(pr))
+    x1, _, s1 = O.pcg(pr.apply_A, b, pr.bj_apply, tol=1e-13, maxit=1000)
+    x2, _, s2 = O.pcg(pr.apply_A, b, C.apply, tol=1e-13, maxit=1000)
+    assert s1 == 0 and s2 == 0
+    assert np.linalg.norm(x1 - x2) / np.linalg.norm(x1) < 1e-10
+
+
+# ------------------------------------------------------- P11: near-null mode
+
+def test_ones_in_near_null_space_with_1f_noise():
+    ratios = []
+    # band wide enough that f_defl = 1/(pi lambda t_samp) ~ 0.25 Hz < f_knee (App. D)
+    for fk in (0.0, 5.0):
+        sc = tiny_i(fknee=fk, lam=255)
+        sc.fknee[:] = fk
+        pr = O.Problem.from_scan(sc)
+        A, _, _ = O.dense_system(pr)
+        one = np.ones(pr.n_obs)
+        ratios.append(np.linalg.norm(A @ one) / (np.linalg.norm(A, 2) * np.linalg.norm(one)))
+    assert ratios[0] > 0.99          # white noise: 1_p is an eigenvector of the top eigenvalue
+    assert ratios[1] < 0.1 * ratios[0]
+
+
+# ------------------------------------------------ P12: CG bound (sanity only)
+
+def test_cg_error_bound_holds():
+    sc = tiny_i()
+    pr = O.Problem.from_scan(sc)
+    A, _, _ = O.dense_system(pr)
+    b = pr.rhs(pr.signal(sc.sky) + sc.noise)
+    x = np.linalg.solve(A, b)
+    ev = np.linalg.eigvalsh(A)
+    kappa = ev[-1] / ev[0]
+    rho = (np.sqrt(kappa) - 1) / (np.sqrt(kappa) + 1)
+    e0 = np.sqrt(x @ A @ x)
+    for j in (1, 3, 6, 10):
+        xj, _, _ = O.pcg(pr.apply_A, b, lambda r: r, tol=0.0, maxit=j)
+        ej = np.sqrt((x - xj) @ A @ (x - xj))
+        assert ej <= 2 * e0 * rho ** j * (1 + 1e-9)
+
+
+# ----------------------------------------------------- adjoint ingredients
+
+def test_tap_derivatives_match_finite_differences():
+    n, lam = 2048, 128
+    p = np.array([1.2, 0.8, 1.4])
+    D = O.tap_derivatives(n, *p, lam, 200.0)
+    for i in range(3):
+        h = 1e-6 * p[i]
+        pp, pm = p.copy(), p.copy()
+        pp[i] += h
+        pm[i] -= h
+        fd = (O.toeplitz_taps(n, *pp, lam, 200.0) - O.toeplitz_taps(n, *pm, lam, 200.0)) / (2 * h)
+        assert np.max(np.abs(fd - D[i])) <= 1e-6 * np.max(np.abs(D[i]))
+
+
+def test_lag_correlations_reproduce_bilinear_form():
+    rng = np.random.default_rng(6)
+    u, v = rng.standard_normal(300), rng.standard_normal(300)
+    t = O.toeplitz_taps(300, 1.0, 1.0, 1.0, 40, 200.0)
+    c = O.lag_correlations(u, v, 40)
+    assert t @ c == pytest.approx(u @ (O.toeplitz_dense(t, 300) @ v), rel=1e-12)
