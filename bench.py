@@ -1,0 +1,212 @@
+#!/usr/bin/env python
+"""Time-to-solution benchmark of the GLS map-making hot path on one MI355X.
+
+Workload: the 2^24-sample polarised raster (4 co-pointed detectors at
+0/45/90/135 deg + 2 Hz HWP, 512x512 IQU patch = 786,432 unknowns, 256
+stationary intervals of 2^16 samples, f_knee ~ U[0.5, 2] Hz, alpha ~ U[1, 2],
+lambda = 2048), synthetic and seeded.  Inputs (pointing, weights, TOD) are
+resident in HBM before the timed region.
+
+One step = plan construction (pointing sort, Toeplitz kernels, block-Jacobi,
+coarse space: AZ and E) + right-hand side + mixed-precision two-level PCG to a
+true relative residual <= 1e-8.  The same step with the plain FP64
+block-Jacobi PCG (the reference method) is timed beside it.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("time-to-solution @‖r‖/‖b‖≤1e-8 (2^24-sample IQU); "
+          "A·x HBM GB/s vs peak")
+HBM_PEAK_GBPS = 8000.0
+# algorithmic bytes per sample of the hot kernels (mixed path: FP32 weights/TOD, int32 ids)
+BYTES_NINV32 = 4 + 8 + 4     # compact pixel id + (cos, sin) read, z written
+BYTES_PT32 = 4 + 8 + 4       # sorted sample index + sorted (cos, sin) + z gathered
+BYTES_NINV64 = 4 + 16 + 8
+BYTES_PT64 = 4 + 16 + 8
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(sc, n_ax, n_intervals_sample):
+    """The FP64 oracle's A x timed on a few intervals of the same scan (the
+    time-domain part of A x separates by interval), scaled to the whole scan and
+    to the number of A x applications the GPU solve performed."""
+    import oracle as O
+    import synth
+    K = sc.n_intervals
+    idx = np.linspace(0, K - 1, n_intervals_sample).round().astype(np.int64)
+    sub = synth.subset_intervals(sc, idx)
+    pr = O.Problem.from_scan(sub)
+    x = np.random.default_rng(0).standard_normal(pr.n_obs * pr.n_s)
+    pr.apply_A(x)  # warm
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        pr.apply_A(x)
+        reps += 1
+        if time.perf_counter() - t0 > 8.0 or reps >= 3:
+            break
+    t_sub = (time.perf_counter() - t0) / reps
+    scale = sc.n_samples / sub.n_samples
+    t_ax = t_sub * scale
+    return dict(value=t_ax * n_ax, unit="s", cores=1, kind="oracle",
+                sample=(f"oracle A*x on {n_intervals_sample} of {K} intervals "
+                        f"({sub.n_samples} samples, {t_sub:.3f} s per apply), scaled x{scale:.0f} "
+                        f"to {t_ax:.2f} s per full A*x, times the {n_ax} A*x applications of the "
+                        f"timed GPU solve (plan AZ columns + PCG); extrapolated"),
+                t_ax_s=t_ax)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-intervals", type=int, default=4)
+    ap.add_argument("--no-reference", action="store_true", help="skip the FP64 block-Jacobi leg")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU path "
+              "is a design (interval sharding + a map reduce-scatter), not built.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_1408_3048_amd import Plan
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    t = time.perf_counter()
+    sc = synth.cfg2_raster_iqu()
+    log(f"scan generated in {time.perf_counter() - t:.1f}s: {sc.n_samples} samples, "
+        f"{sc.n_intervals} intervals")
+    pix = torch.from_numpy(sc.pix).cuda()
+    w = torch.from_numpy(sc.weights).cuda()
+    psd = np.stack([sc.sigma, sc.fknee, sc.alpha], axis=1)
+    kw = dict(n_stokes=3, lam=sc.lam, f_samp=sc.f_samp)
+    # TOD d = P m + n, formed on the device (untimed)
+    helper = Plan(pix, w, sc.n_pix, sc.offsets, psd, **kw)
+    obs = helper.obs_pixels().long()
+    m = torch.from_numpy(sc.sky).cuda()[obs].reshape(-1).contiguous()
+    d = helper.apply_P(m) + torch.from_numpy(sc.noise).cuda()
+    helper.close()
+    del helper
+    torch.cuda.synchronize()
+    log("inputs resident in HBM")
+
+    def step(precision, coarse, precond, profile=False):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan = Plan(pix, w, sc.n_pix, sc.offsets, psd, precision=precision, coarse=coarse, **kw)
+        if profile:
+            plan.profile(True)
+        b = plan.rhs(d)
+        x, info = plan.pcg_solve(b, precond=precond, precision=precision, tol=args.tol,
+                                 max_iter=5000)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = plan.profile_read() if profile else None
+        extra = dict(plan_ms=plan.plan_ms, solve_ms=info["solve_ms"], iterations=info["iterations"],
+                     outer=info["outer_iterations"], relres=info["rel_residual"],
+                     r_eff=plan.coarse_rank() if coarse else 0, unknowns=plan.n_vec)
+        plan.close()
+        return t1 - t0, x, extra, prof
+
+    # mixed-precision two-level PCG (the measured method)
+    for i in range(args.warmup):
+        tt, _, ex, _ = step("mixed", True, "2lvl")
+        log(f"warmup {i}: {tt * 1e3:.1f} ms {ex}")
+    times, extras, prof = [], [], None
+    for i in range(args.steps):
+        last = i == args.steps - 1
+        tt, x_mixed, ex, pr = step("mixed", True, "2lvl", profile=last)
+        times.append(tt)
+        extras.append(ex)
+        if last:
+            prof = pr
+        log(f"step {i}: {tt * 1e3:.1f} ms {ex}")
+    t_step = float(np.mean(times))
+
+    ref = None
+    if not args.no_reference:
+        rtimes, rex = [], None
+        tt, _, ex, _ = step("fp64", False, "bj")
+        log(f"fp64 bj warmup: {tt * 1e3:.1f} ms {ex}")
+        for i in range(args.steps):
+            last = i == args.steps - 1
+            tt, x_ref, ex, pr64 = step("fp64", False, "bj", profile=last)
+            rtimes.append(tt)
+            rex = ex
+            log(f"fp64 bj step {i}: {tt * 1e3:.1f} ms {ex}")
+        ax64 = None
+        if pr64:
+            n64, t64 = pr64["ninv64"]
+            np64, tp64 = pr64["pt64"]
+            ax64 = dict(ninv64_avg_ms=t64 / max(n64, 1), pt64_avg_ms=tp64 / max(np64, 1),
+                        ax_GBps=(BYTES_NINV64 + BYTES_PT64) * sc.n_samples /
+                        ((t64 / max(n64, 1) + tp64 / max(np64, 1)) * 1e-3) / 1e9)
+        map_diff = float((x_mixed - x_ref).norm() / x_ref.norm())
+        ref = dict(method="fp64 block-Jacobi PCG", time_s=float(np.mean(rtimes)), **rex,
+                   speedup_of_mixed_2lvl=float(np.mean(rtimes)) / t_step,
+                   map_rel_diff_mixed_vs_fp64=map_diff, fp64_kernels=ax64)
+
+    # roofline of the dominant kernel, from the live event timings of the last timed step
+    n_ninv, t_ninv = prof["ninv32"]
+    n_pt, t_pt = prof["pt32"]
+    avg_ninv = t_ninv / max(n_ninv, 1)
+    avg_pt = t_pt / max(n_pt, 1)
+    cand = {
+        "ninv32": (t_ninv, avg_ninv, BYTES_NINV32, "k_toeplitz<float> (gather P + overlap-save N^-1)"),
+        "pt32": (t_pt, avg_pt, BYTES_PT32, "k_scatter<float,3> (P^T segmented reduction)"),
+    }
+    dom = max(cand, key=lambda k: cand[k][0])
+    _, avg_ms, bps, kname = cand[dom]
+    achieved = bps * sc.n_samples / (avg_ms * 1e-3) / 1e9
+    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBPS, 4), traffic=None, kernel=kname,
+                avg_launch_ms=round(avg_ms, 5), launches=n_ninv if dom == "ninv32" else n_pt,
+                algorithmic_bytes_per_launch=bps * sc.n_samples,
+                ax_fp32_GBps=round((BYTES_NINV32 + BYTES_PT32) * sc.n_samples /
+                                   ((avg_ninv + avg_pt) * 1e-3) / 1e9, 1),
+                other_kernels={k: dict(launches=v[0], avg_ms=v[1] / max(v[0], 1))
+                               for k, v in prof.items() if v[0] > 0})
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        ex = extras[-1]
+        n_ax = ex["iterations"] + ex["outer"] + 2 + ex["r_eff"]
+        log("timing the oracle on a sample of intervals ...")
+        cpu = cpu_baseline(sc, n_ax, args.cpu_intervals)
+        cpu.pop("t_ax_s", None)
+        log(f"cpu baseline: {cpu}")
+
+    out = dict(
+        metric=METRIC, value=round(t_step, 6), unit="s", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=round(t_step * 1e3, 3), higher_is_better=False,
+        scaling="weak", vs_baseline=None, dtype="f32+f64", data="synthetic",
+        config=dict(workload=("2^24-sample IQU cross-linked raster, 4 detectors + 2 Hz HWP, "
+                              "512x512 patch (786432 unknowns), 256 intervals of 2^16, "
+                              "lambda=2048, mixed FP32/FP64 two-level PCG to 1e-8 incl. plan"),
+                    n_samples=sc.n_samples, unknowns=extras[-1]["unknowns"],
+                    tol=args.tol, parallelism="single GPU"),
+        breakdown=extras[-1], reference=ref, roofline=roof, cpu_baseline=cpu,
+    )
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,221 @@
+/*
+ * mm.h - C-ABI of the MI355X (gfx950) GLS map-making hot path.
+ *
+ * Solves A m = b with A = P^T N^-1 P and b = P^T N^-1 d by preconditioned
+ * conjugate gradients, after Szydlarski, Grigori & Stompor, "Accelerating the
+ * cosmic microwave background map-making procedure through preconditioning",
+ * A&A 2014 (arXiv 1408.3048).  Paper references below name the section and
+ * the equation's LaTeX label.
+ *
+ *   P      pointing matrix: row t holds (1, cos 2phi_t, sin 2phi_t) at the
+ *          pixel seen at sample t (IQU), or 1 (I only)
+ *          [Sect. 2, eq. signal_with_polarization]
+ *   N^-1   block-diagonal, one symmetric band-limited Toeplitz block per
+ *          stationary interval, built from the interval's noise PSD
+ *          [Sect. 2.1, eq. N_def; Sect. 4.1.4, eq. fknee; App. D, eq. apodDef]
+ *   M_BD   block-Jacobi preconditioner (P^T diag(N^-1) P)^-1 [Sect. 3.1, eq. stdPrec]
+ *   M_2lvl two-level A-DEF1 preconditioner with the a priori coarse space Z_S
+ *          [Sect. 3.2, eqs. projection and 2; Sect. 3.3.1, eqs. strofZ, strofZ_polar;
+ *           App. C]
+ *
+ * Conventions for every call:
+ *   - Map-domain vectors ("maps") are device arrays of n_obs * n_stokes
+ *     doubles in the compact observed-pixel space: compact pixel c is the
+ *     c-th smallest original pixel id that occurs in the pointing (Sect. 2:
+ *     only observed pixels are solved for), its Stokes parameters I,Q,U are
+ *     adjacent.  mm_obs_pixels() returns the compact -> original map.
+ *   - Time-domain vectors ("TOD") are device arrays of n_samples values, FP32
+ *     or FP64 as stated by a dtype argument (MM_F32 / MM_F64).
+ *   - All device work is ordered on the stream given in mm_opts.stream
+ *     (a hipStream_t, NULL = the default stream).  Calls return after
+ *     enqueueing, except mm_plan and mm_pcg_solve, which synchronise.
+ *   - Return value: MM_OK (0) or a negative mm_status.  No call aborts or
+ *     throws; on error mm_last_error() returns a message (thread-local,
+ *     valid until the next call on the same thread).  Arguments are
+ *     validated on the host before any device work is enqueued.
+ *   - Caller-owned buffers stay caller-owned; a plan owns deep copies of
+ *     everything it needs, so the inputs of mm_plan may be freed after it
+ *     returns.  Calls that overlap on one plan from several host threads race.
+ */
+#ifndef MM_H
+#define MM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mm_plan_s* mm_plan_t;
+
+enum mm_status {
+    MM_OK = 0,
+    MM_ERR_ARG = -1,        /* invalid argument (sizes, offsets, pixel ids, NULL pointers) */
+    MM_ERR_DEVICE = -2,     /* a HIP runtime call failed */
+    MM_ERR_RANK = -3,       /* a pixel's n_s x n_s block has rcond < rcond_min (P not full rank) */
+    MM_ERR_NOT_SPD = -4,    /* a Toeplitz block's symbol min <= 0 (N^-1 not positive definite) */
+    MM_ERR_BREAKDOWN = -5,  /* PCG: p^T A p <= 0 or not finite; x holds the last iterate */
+    MM_ERR_NOCONV = -6,     /* PCG: max_iter reached; x holds the last iterate */
+    MM_ERR_STATE = -7       /* the plan was not built with what the call needs */
+};
+
+enum { MM_F32 = 0, MM_F64 = 1 };                               /* element types */
+enum { MM_WIN_GAUSS = 0, MM_WIN_GAUSS2 = 1, MM_WIN_RECT = 2 };  /* apodisation windows */
+enum { MM_FP64 = 0, MM_MIXED = 1 };                            /* arithmetic of the operator */
+enum { MM_COARSE_NONE = 0, MM_COARSE_ZS = 1 };                 /* coarse space built by mm_plan */
+enum { MM_BJ = 0, MM_2LVL = 1 };                               /* preconditioner of mm_pcg_solve */
+
+/* Noise model of one stationary interval: per-sample PSD
+ * P(f) = sigma^2 (1 + (f_knee / f)^alpha)  [Sect. 4.1.4, eq. fknee with the
+ * slope alpha free; alpha = 2 is the paper's case].  f_knee = 0 is white noise. */
+typedef struct { double sigma, f_knee, alpha; } mm_psd;
+
+typedef struct {
+    int n_stokes;      /* 1 (I) or 3 (I,Q,U) */
+    int lambda;        /* Toeplitz half bandwidth: lags |k| <= lambda kept [Sect. 4.1.4] */
+    double f_samp;     /* sampling frequency in Hz (> 0) */
+    int window;        /* apodisation of the Toeplitz row [App. D]:
+                          MM_WIN_GAUSS w(k) = exp(-(k/lambda)^2) (default),
+                          MM_WIN_GAUSS2 exp(-2 (k/lambda)^2), MM_WIN_RECT 1 */
+    int precision;     /* MM_FP64: FP64 operator only; MM_MIXED: also FP32 copies of the
+                          time-domain data, enabling the FP32 operator and mixed solves */
+    int coarse;        /* MM_COARSE_ZS builds Z_S, AZ and E for mm_precond_2lvl */
+    double rank_tol;   /* E: columns whose pivoted-Cholesky residual falls below
+                          rank_tol * max diag(E) are dropped (span-preserving), default 1e-10 */
+    double rcond_min;  /* minimum reciprocal 1-norm condition of a pixel block, default 1e-8 */
+    int fft_len_f64;   /* overlap-save FFT length (real samples, power of two) for the FP64
+                          operator; 0 = automatic */
+    int fft_len_f32;   /* same for the FP32 operator; 0 = automatic */
+    void* stream;      /* hipStream_t; NULL = default stream */
+} mm_opts;
+
+/* Fill *opts with the defaults above (n_stokes 3, lambda 1024, f_samp 200). */
+void mm_default_opts(mm_opts* opts);
+
+/* Build a plan for one problem (or several independent problems, see
+ * mm_plan_batched) [Sect. 2, Sect. 3, App. C].
+ *   n_samples           N_t, 1 <= N_t < 2^31
+ *   pix                 device int32 [N_t], original pixel id in [0, n_pix)
+ *   weights             device [N_t][2] = (cos 2phi_t, sin 2phi_t) of type weights_dtype
+ *                       for n_stokes = 3 (the I weight is exactly 1 and not passed);
+ *                       ignored (may be NULL) for n_stokes = 1
+ *   n_pix               size of the original pixel grid
+ *   n_intervals         K >= 1 stationary intervals
+ *   interval_offsets    host int64 [K+1]: 0 = o_0 < o_1 < ... < o_K = N_t
+ *   psd                 host [K] noise model per interval (sigma > 0, f_knee >= 0, alpha > 0)
+ * Errors: MM_ERR_ARG (bad sizes/offsets/PSD, pixel id out of range, lambda too large for
+ * the FFT tile), MM_ERR_NOT_SPD, MM_ERR_RANK, MM_ERR_DEVICE.  *out is NULL on error. */
+int mm_plan(mm_plan_t* out, int64_t n_samples, const int32_t* pix, const void* weights,
+            int weights_dtype, int64_t n_pix, int32_t n_intervals,
+            const int64_t* interval_offsets, const mm_psd* psd, const mm_opts* opts);
+
+/* Release a plan and all its device memory (NULL is a no-op). */
+void mm_destroy(mm_plan_t plan);
+
+/* Number of observed pixels n_obs (map vectors hold n_obs * n_stokes doubles); -1 on NULL. */
+int64_t mm_n_obs(mm_plan_t plan);
+/* n_stokes of the plan; -1 on NULL. */
+int mm_n_stokes(mm_plan_t plan);
+/* Device int32 [n_obs]: original pixel id of every compact pixel (ascending). */
+int mm_obs_pixels(mm_plan_t plan, int32_t* dev_out);
+/* Device int32 [n_obs]: hit count s_p of every compact pixel (exact integers). */
+int mm_hits(mm_plan_t plan, int32_t* dev_out);
+/* Device int32 [N_t]: perm[i] = sample index of the i-th sample in pixel-sorted order
+ * (compact pixel ascending, then time ascending; a stable counting sort). */
+int mm_sorted_samples(mm_plan_t plan, int32_t* dev_out);
+
+/* Toeplitz taps of interval j (t_0..t_K, K = min(lambda, t_j - 1)) as FP64 on the host
+ * [App. D]; returns K+1 or a negative status; at most cap values are written. */
+int mm_interval_taps(mm_plan_t plan, int32_t interval, double* host_out, int cap);
+
+/* Coarse space [App. C]: number of columns kept after removing duplicate and dependent
+ * columns of Z_S (r_eff), or a negative status. */
+int mm_coarse_rank(mm_plan_t plan);
+/* Host int32 [r_eff]: interval index of every kept column of Z_S. */
+int mm_coarse_columns(mm_plan_t plan, int32_t* host_out, int cap);
+/* Host FP64 [r_eff * r_eff] row-major: E = Z^T A Z restricted to the kept columns. */
+int mm_coarse_matrix(mm_plan_t plan, double* host_out, int64_t cap);
+
+/* ----- operators (all device pointers; see conventions above) ----- */
+
+/* y = P x  (de-pointing) [Sect. 2].  x: map (FP64); y: TOD of y_dtype. */
+int mm_apply_P(mm_plan_t plan, const double* x, void* y, int y_dtype);
+/* z = N^-1 y [eq. N_def] with the FP64 (precision MM_FP64, y/z FP64) or FP32 (MM_MIXED,
+ * y/z FP32) overlap-save operator.  y and z may not alias. */
+int mm_apply_Ninv(mm_plan_t plan, const void* y, void* z, int precision);
+/* x = P^T z  (pointing) [Sect. 2]: deterministic segmented reduction over pixel-sorted
+ * samples, in ascending sample order per pixel.  z: TOD of z_dtype; x: map (FP64). */
+int mm_apply_PT(mm_plan_t plan, const void* z, int z_dtype, double* x);
+/* b = P^T N^-1 d [eq. rhs].  d: TOD of d_dtype (FP64 operator). */
+int mm_rhs(mm_plan_t plan, const void* d, int d_dtype, double* b);
+/* y = A x = P^T N^-1 P x [eq. a_times_x].  precision MM_FP64: FP64 kernels; MM_MIXED:
+ * FP32 gather, FFT and scatter with FP32 accumulation (plan must be MM_MIXED).
+ * x and y may not alias. */
+int mm_apply_A(mm_plan_t plan, const double* x, double* y, int precision);
+/* z = M_BD r [eq. stdPrec]. r and z may alias. */
+int mm_precond_bj(mm_plan_t plan, const double* r, double* z);
+/* z = M_2lvl r = M_BD (r - AZ E^-1 Z^T r) + Z E^-1 Z^T r [eq. 2] (plan built with
+ * MM_COARSE_ZS, else MM_ERR_STATE).  r and z may not alias. */
+int mm_precond_2lvl(mm_plan_t plan, const double* r, double* z);
+
+/* ----- solver ----- */
+
+typedef struct {
+    int iterations;        /* total PCG iterations (inner iterations for MM_MIXED) */
+    int outer_iterations;  /* iterative-refinement steps (1 for MM_FP64) */
+    int replacements;      /* recursive -> true residual replacements */
+    int status;            /* MM_OK, MM_ERR_BREAKDOWN or MM_ERR_NOCONV */
+    double rel_residual;   /* final true ||b - A x|| / ||b|| with the FP64 operator */
+    double solve_ms;       /* wall time of the solve (host clock around device work) */
+    double* history;       /* optional caller-owned host buffer for the recursive relative
+                              residual of every iteration, or NULL */
+    int history_cap;       /* its capacity */
+    int history_len;       /* entries written */
+} mm_solve_info;
+
+/* Solve A x = b by PCG [Sect. 3] from the initial guess in x (pass zeros for x0 = 0).
+ *   precond    MM_BJ or MM_2LVL
+ *   precision  MM_FP64: FP64 operator; convergence when the recursive and then the true
+ *              relative residual are <= tol (otherwise the recursive residual is replaced
+ *              by the true one and the iteration continues).
+ *              MM_MIXED: iterative refinement; each step solves A d = r with the FP32
+ *              operator (FP64 vectors and scalars) and updates x += d; the residual
+ *              r = b - A x is formed with the FP64 operator; stops when it is <= tol.
+ *   tol        relative residual target (> 0);  max_iter: cap on total PCG iterations.
+ * Returns MM_OK, MM_ERR_NOCONV, MM_ERR_BREAKDOWN (x holds the last iterate; info filled),
+ * MM_ERR_ARG or MM_ERR_STATE.  Synchronises the plan's stream before returning. */
+int mm_pcg_solve(mm_plan_t plan, const double* b, double* x, int precond, int precision,
+                 double tol, int max_iter, mm_solve_info* info);
+
+/* Wall time in ms that mm_plan took for this plan (host clock around all its device work);
+ * -1 on NULL. */
+double mm_plan_time_ms(mm_plan_t plan);
+
+/* C = A^T B in FP64 on the matrix cores (the product that forms the coarse matrix
+ * E = Z^T (AZ) [App. C]).  A: device row-major [n][ra]; B: device row-major [n][rb];
+ * C: device row-major [ra][rb].  n must be a positive multiple of 4, ra and rb positive
+ * multiples of 16.  Deterministic (fixed split of the n dimension, fixed-order sum).
+ * Synchronises the stream (a hipStream_t, NULL = default).  Returns MM_OK or MM_ERR_ARG /
+ * MM_ERR_DEVICE. */
+int mm_gemm_tn_f64(void* stream, const double* A, const double* B, int64_t n, int32_t ra,
+                   int32_t rb, double* C);
+
+/* Kernel timing with HIP events recorded on the plan's stream around every launch of the
+ * hot-path kernels (for measurements; off by default).  enable = 1 starts a fresh window,
+ * 0 stops recording.  Kernel ids: MM_K_NINV32 / MM_K_NINV64 (overlap-save N^-1 with the
+ * de-pointing gather fused, FP32 / FP64), MM_K_PT32 / MM_K_PT64 (P^T segmented reduction),
+ * MM_K_PRECOND (block-Jacobi or two-level application), MM_K_VEC (CG vector updates).
+ * mm_profile_read synchronises the stream and returns the number of launches and their
+ * summed duration in ms. */
+enum { MM_K_NINV32 = 0, MM_K_NINV64 = 1, MM_K_PT32 = 2, MM_K_PT64 = 3, MM_K_PRECOND = 4,
+       MM_K_VEC = 5, MM_K_COUNT = 6 };
+int mm_profile(mm_plan_t plan, int enable);
+int mm_profile_read(mm_plan_t plan, int kernel, int64_t* launches, double* total_ms);
+
+/* Message describing the last error on this thread ("" if none). */
+const char* mm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MM_H */

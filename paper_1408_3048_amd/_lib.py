@@ -1,0 +1,347 @@
+"""ctypes binding of libmm.so (include/mm.h): argument marshalling only.
+
+Every function here forwards to the C entry point of the same name; all
+arithmetic runs in the library's HIP kernels.  Torch tensors supply device
+memory and the current HIP stream.  If the library is missing this module
+raises instead of falling back to anything else.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmm.so")
+
+MM_OK, MM_ERR_ARG, MM_ERR_DEVICE, MM_ERR_RANK = 0, -1, -2, -3
+MM_ERR_NOT_SPD, MM_ERR_BREAKDOWN, MM_ERR_NOCONV, MM_ERR_STATE = -4, -5, -6, -7
+MM_F32, MM_F64 = 0, 1
+MM_WIN_GAUSS, MM_WIN_GAUSS2, MM_WIN_RECT = 0, 1, 2
+MM_FP64, MM_MIXED = 0, 1
+MM_COARSE_NONE, MM_COARSE_ZS = 0, 1
+MM_BJ, MM_2LVL = 0, 1
+
+STATUS_NAMES = {0: "MM_OK", -1: "MM_ERR_ARG", -2: "MM_ERR_DEVICE", -3: "MM_ERR_RANK",
+                -4: "MM_ERR_NOT_SPD", -5: "MM_ERR_BREAKDOWN", -6: "MM_ERR_NOCONV",
+                -7: "MM_ERR_STATE"}
+
+EXPORTED = [
+    "mm_default_opts", "mm_plan", "mm_destroy", "mm_n_obs", "mm_n_stokes", "mm_obs_pixels",
+    "mm_hits", "mm_sorted_samples", "mm_interval_taps", "mm_coarse_rank", "mm_coarse_columns",
+    "mm_coarse_matrix", "mm_apply_P", "mm_apply_Ninv", "mm_apply_PT", "mm_rhs", "mm_apply_A",
+    "mm_precond_bj", "mm_precond_2lvl", "mm_pcg_solve", "mm_plan_time_ms", "mm_gemm_tn_f64",
+    "mm_profile", "mm_profile_read", "mm_last_error",
+]
+
+
+class MMError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class mm_psd(ctypes.Structure):
+    _fields_ = [("sigma", ctypes.c_double), ("f_knee", ctypes.c_double), ("alpha", ctypes.c_double)]
+
+
+class mm_opts(ctypes.Structure):
+    _fields_ = [("n_stokes", ctypes.c_int), ("lambda_", ctypes.c_int), ("f_samp", ctypes.c_double),
+                ("window", ctypes.c_int), ("precision", ctypes.c_int), ("coarse", ctypes.c_int),
+                ("rank_tol", ctypes.c_double), ("rcond_min", ctypes.c_double),
+                ("fft_len_f64", ctypes.c_int), ("fft_len_f32", ctypes.c_int),
+                ("stream", ctypes.c_void_p)]
+
+
+class mm_solve_info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("outer_iterations", ctypes.c_int),
+                ("replacements", ctypes.c_int), ("status", ctypes.c_int),
+                ("rel_residual", ctypes.c_double), ("solve_ms", ctypes.c_double),
+                ("history", ctypes.POINTER(ctypes.c_double)), ("history_cap", ctypes.c_int),
+                ("history_len", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_1408_3048_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I, I32, I64, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "mm_default_opts": (None, [ctypes.POINTER(mm_opts)]),
+        "mm_plan": (I, [ctypes.POINTER(P), I64, P, P, I, I64, I32, P, P, ctypes.POINTER(mm_opts)]),
+        "mm_destroy": (None, [P]),
+        "mm_n_obs": (I64, [P]),
+        "mm_n_stokes": (I, [P]),
+        "mm_obs_pixels": (I, [P, P]),
+        "mm_hits": (I, [P, P]),
+        "mm_sorted_samples": (I, [P, P]),
+        "mm_interval_taps": (I, [P, I32, P, I]),
+        "mm_coarse_rank": (I, [P]),
+        "mm_coarse_columns": (I, [P, P, I]),
+        "mm_coarse_matrix": (I, [P, P, I64]),
+        "mm_apply_P": (I, [P, P, P, I]),
+        "mm_apply_Ninv": (I, [P, P, P, I]),
+        "mm_apply_PT": (I, [P, P, I, P]),
+        "mm_rhs": (I, [P, P, I, P]),
+        "mm_apply_A": (I, [P, P, P, I]),
+        "mm_precond_bj": (I, [P, P, P]),
+        "mm_precond_2lvl": (I, [P, P, P]),
+        "mm_pcg_solve": (I, [P, P, P, I, I, D, I, ctypes.POINTER(mm_solve_info)]),
+        "mm_plan_time_ms": (D, [P]),
+        "mm_gemm_tn_f64": (I, [P, P, P, I64, I32, I32, P]),
+        "mm_profile": (I, [P, I]),
+        "mm_profile_read": (I, [P, I, ctypes.POINTER(I64), ctypes.POINTER(D)]),
+        "mm_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def last_error():
+    return load().mm_last_error().decode()
+
+
+def check(status):
+    if status != MM_OK:
+        raise MMError(status, last_error())
+    return status
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# --------------------------------------------------------------------------- wrappers
+
+class Plan:
+    """Owns an mm_plan_t.  Inputs are torch CUDA tensors (pix int32 [N],
+    weights float32/float64 [N, 2] or None) and host arrays (offsets int64 [K+1],
+    psd float64 [K, 3] = (sigma, f_knee, alpha))."""
+
+    def __init__(self, pix, weights, n_pix, offsets, psd, *, n_stokes=3, lam=1024, f_samp=200.0,
+                 window="gauss", precision="fp64", coarse=False, rank_tol=1e-10, rcond_min=1e-8,
+                 fft_len_f64=0, fft_len_f32=0):
+        import torch
+        L = load()
+        self._lib = L
+        self._h = ctypes.c_void_p()
+        opts = mm_opts()
+        L.mm_default_opts(ctypes.byref(opts))
+        opts.n_stokes = n_stokes
+        opts.lambda_ = int(lam)
+        opts.f_samp = float(f_samp)
+        opts.window = {"gauss": MM_WIN_GAUSS, "gauss2": MM_WIN_GAUSS2, "rect": MM_WIN_RECT}[window]
+        opts.precision = {"fp64": MM_FP64, "mixed": MM_MIXED}[precision]
+        opts.coarse = MM_COARSE_ZS if coarse else MM_COARSE_NONE
+        opts.rank_tol = float(rank_tol)
+        opts.rcond_min = float(rcond_min)
+        opts.fft_len_f64 = int(fft_len_f64)
+        opts.fft_len_f32 = int(fft_len_f32)
+        opts.stream = _stream()
+        assert pix.is_cuda and pix.dtype == torch.int32 and pix.is_contiguous()
+        wdt = MM_F64
+        if weights is not None:
+            assert weights.is_cuda and weights.is_contiguous() and weights.shape == (pix.shape[0], 2)
+            wdt = MM_F64 if weights.dtype == torch.float64 else MM_F32
+            assert weights.dtype in (torch.float32, torch.float64)
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        ps = np.ascontiguousarray(psd, dtype=np.float64).reshape(-1, 3)
+        self.n_samples = int(pix.shape[0])
+        self.n_intervals = int(off.shape[0] - 1)
+        self.n_stokes = n_stokes
+        self.precision = precision
+        st = L.mm_plan(ctypes.byref(self._h), self.n_samples, _ptr(pix), _ptr(weights), wdt,
+                       int(n_pix), self.n_intervals, off.ctypes.data_as(ctypes.c_void_p),
+                       ps.ctypes.data_as(ctypes.c_void_p), ctypes.byref(opts))
+        check(st)
+        self.n_obs = int(L.mm_n_obs(self._h))
+        self.n_vec = self.n_obs * n_stokes
+        self.plan_ms = float(L.mm_plan_time_ms(self._h))
+
+    @classmethod
+    def from_scan(cls, scan, device="cuda", weights_dtype=None, **kw):
+        import torch
+        pix = torch.from_numpy(np.ascontiguousarray(scan.pix, dtype=np.int32)).to(device)
+        w = None
+        if scan.weights is not None:
+            w = torch.from_numpy(np.ascontiguousarray(scan.weights)).to(device)
+            if weights_dtype is not None:
+                w = w.to(weights_dtype)
+        psd = np.stack([scan.sigma, scan.fknee, scan.alpha], axis=1)
+        kw.setdefault("lam", scan.lam)
+        kw.setdefault("f_samp", scan.f_samp)
+        return cls(pix, w, scan.n_pix, scan.offsets, psd, n_stokes=scan.n_stokes, **kw)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.mm_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    # ---- queries
+    def obs_pixels(self):
+        import torch
+        out = torch.empty(self.n_obs, dtype=torch.int32, device="cuda")
+        check(self._lib.mm_obs_pixels(self._h, _ptr(out)))
+        return out
+
+    def hits(self):
+        import torch
+        out = torch.empty(self.n_obs, dtype=torch.int32, device="cuda")
+        check(self._lib.mm_hits(self._h, _ptr(out)))
+        return out
+
+    def sorted_samples(self):
+        import torch
+        out = torch.empty(self.n_samples, dtype=torch.int32, device="cuda")
+        check(self._lib.mm_sorted_samples(self._h, _ptr(out)))
+        return out
+
+    def interval_taps(self, j):
+        n = self._lib.mm_interval_taps(self._h, int(j), None, 0)
+        check(min(n, 0))
+        out = np.empty(n, dtype=np.float64)
+        self._lib.mm_interval_taps(self._h, int(j), out.ctypes.data_as(ctypes.c_void_p), n)
+        return out
+
+    def coarse_rank(self):
+        r = self._lib.mm_coarse_rank(self._h)
+        check(min(r, 0))
+        return r
+
+    def coarse_columns(self):
+        r = self.coarse_rank()
+        out = np.empty(r, dtype=np.int32)
+        self._lib.mm_coarse_columns(self._h, out.ctypes.data_as(ctypes.c_void_p), r)
+        return out
+
+    def coarse_matrix(self):
+        r = self.coarse_rank()
+        out = np.empty((r, r), dtype=np.float64)
+        self._lib.mm_coarse_matrix(self._h, out.ctypes.data_as(ctypes.c_void_p), r * r)
+        return out
+
+    # ---- kernel timing (HIP events on the plan's stream)
+    KERNELS = {"ninv32": 0, "ninv64": 1, "pt32": 2, "pt64": 3, "precond": 4, "vec": 5}
+
+    def profile(self, enable=True):
+        check(self._lib.mm_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        out = {}
+        for name, k in self.KERNELS.items():
+            n = ctypes.c_int64()
+            t = ctypes.c_double()
+            check(self._lib.mm_profile_read(self._h, k, ctypes.byref(n), ctypes.byref(t)))
+            out[name] = (int(n.value), float(t.value))
+        return out
+
+    # ---- operators
+    def _vec(self):
+        import torch
+        return torch.empty(self.n_vec, dtype=torch.float64, device="cuda")
+
+    def apply_P(self, x, dtype=None):
+        import torch
+        dtype = dtype or torch.float64
+        y = torch.empty(self.n_samples, dtype=dtype, device="cuda")
+        check(self._lib.mm_apply_P(self._h, _ptr(x), _ptr(y),
+                                   MM_F64 if dtype == torch.float64 else MM_F32))
+        return y
+
+    def apply_Ninv(self, y, precision="fp64"):
+        import torch
+        z = torch.empty_like(y)
+        p = MM_FP64 if precision == "fp64" else MM_MIXED
+        want = torch.float64 if p == MM_FP64 else torch.float32
+        assert y.dtype == want and y.is_contiguous()
+        check(self._lib.mm_apply_Ninv(self._h, _ptr(y), _ptr(z), p))
+        return z
+
+    def apply_PT(self, z):
+        import torch
+        x = self._vec()
+        check(self._lib.mm_apply_PT(self._h, _ptr(z), MM_F64 if z.dtype == torch.float64 else MM_F32,
+                                    _ptr(x)))
+        return x
+
+    def rhs(self, d):
+        import torch
+        b = self._vec()
+        check(self._lib.mm_rhs(self._h, _ptr(d), MM_F64 if d.dtype == torch.float64 else MM_F32,
+                               _ptr(b)))
+        return b
+
+    def apply_A(self, x, precision="fp64", out=None):
+        y = self._vec() if out is None else out
+        check(self._lib.mm_apply_A(self._h, _ptr(x), _ptr(y),
+                                   MM_FP64 if precision == "fp64" else MM_MIXED))
+        return y
+
+    def precond_bj(self, r):
+        z = self._vec()
+        check(self._lib.mm_precond_bj(self._h, _ptr(r), _ptr(z)))
+        return z
+
+    def precond_2lvl(self, r):
+        z = self._vec()
+        check(self._lib.mm_precond_2lvl(self._h, _ptr(r), _ptr(z)))
+        return z
+
+    def pcg_solve(self, b, x0=None, precond="bj", precision="fp64", tol=1e-8, max_iter=1000,
+                  history=True, raise_on_error=True):
+        """Returns (x, info dict)."""
+        import torch
+        x = torch.zeros_like(b) if x0 is None else x0.clone()
+        info = mm_solve_info()
+        hist = np.zeros(max_iter + 8, dtype=np.float64)
+        if history:
+            info.history = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            info.history_cap = hist.shape[0]
+        st = self._lib.mm_pcg_solve(self._h, _ptr(b), _ptr(x),
+                                    MM_2LVL if precond == "2lvl" else MM_BJ,
+                                    MM_MIXED if precision == "mixed" else MM_FP64,
+                                    float(tol), int(max_iter), ctypes.byref(info))
+        out = dict(status=st, iterations=info.iterations, outer_iterations=info.outer_iterations,
+                   replacements=info.replacements, rel_residual=info.rel_residual,
+                   solve_ms=info.solve_ms, history=hist[:info.history_len].copy())
+        if raise_on_error and st != MM_OK:
+            raise MMError(st, last_error())
+        return x, out
+
+
+def gemm_tn_f64(A, B):
+    """C = A^T B (FP64 matrix cores) for CUDA row-major A [n, ra], B [n, rb]."""
+    import torch
+    C = torch.empty((A.shape[1], B.shape[1]), dtype=torch.float64, device="cuda")
+    check(load().mm_gemm_tn_f64(_stream(), _ptr(A), _ptr(B), A.shape[0], A.shape[1], B.shape[1],
+                                _ptr(C)))
+    return C

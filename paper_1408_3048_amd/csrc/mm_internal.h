@@ -1,0 +1,226 @@
+// Internal declarations shared by the translation units of libmm.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mm.h"
+
+namespace mm {
+
+// ---------------------------------------------------------------- errors
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define MM_HIP(call)                                                               \
+    do {                                                                           \
+        hipError_t e_ = (call);                                                    \
+        if (e_ != hipSuccess) {                                                    \
+            ::mm::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                            __FILE__, __LINE__);                                   \
+            return MM_ERR_DEVICE;                                                  \
+        }                                                                          \
+    } while (0)
+
+#define MM_TRY(expr)               \
+    do {                           \
+        int s_ = (expr);           \
+        if (s_ != MM_OK) return s_; \
+    } while (0)
+
+// ---------------------------------------------------------------- device buffers
+template <typename T>
+struct DBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    int alloc(size_t count) {
+        release();
+        n = count;
+        if (count == 0) return MM_OK;
+        hipError_t e = hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T));
+        if (e != hipSuccess) {
+            p = nullptr;
+            set_error("hipMalloc(%zu bytes) failed: %s", count * sizeof(T), hipGetErrorString(e));
+            return MM_ERR_DEVICE;
+        }
+        return MM_OK;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    ~DBuf() { release(); }
+    DBuf() = default;
+    DBuf(const DBuf&) = delete;
+    DBuf& operator=(const DBuf&) = delete;
+};
+
+// ---------------------------------------------------------------- overlap-save tiling
+// One FFT configuration (per precision): tiles of L_max outputs read a window of
+// L + 2 lambda samples into a real buffer of n_r = 2^(logm+1) points.
+struct FftTiling {
+    int logm = 0;            // complex half-length M = 2^logm, real length n_r = 2M
+    int n_r = 0;
+    int64_t n_tiles = 0;
+    DBuf<int64_t> tile_out;  // first output sample of every tile
+    DBuf<int32_t> tile_len;  // outputs of every tile
+    DBuf<int32_t> tile_int;  // interval of every tile
+    DBuf<double> H64;        // [n_kern][M+1] kernel spectrum / (2 n_r), FP64 operator
+    DBuf<float> H32;         // same, FP32 operator
+    DBuf<double> tw64;       // [n_r/2][2] exp(-2 pi i q / n_r)
+    DBuf<float> tw32;
+};
+
+// PCG device scalars; written only by block 0 of the kernel that owns each field
+struct PcgScalars {
+    double bnorm;     // ||b|| of the system being iterated
+    double tol;       // relative tolerance
+    double alpha, beta, pq, rr;
+    int done;         // 1: converged or failed; kernels of later iterations return at once
+    int status;       // 0 ok, 1 breakdown
+    int iter;         // iterations completed (index of the last update + 1)
+    int pad;
+};
+
+// control block of the PCG kernels (passed by value)
+struct PcgCtl {
+    double* part = nullptr;     // [kNumSlots][kVecBlocks] partial sums; nullptr = standalone call
+    PcgScalars* sc = nullptr;
+    double* rz_hist = nullptr;  // r^T z of every iteration, [max_iter + 2]
+    double* hist = nullptr;     // recursive relative residual of every iteration, or nullptr
+    int iter = 0;               // iteration index
+    int check = 0;              // preconditioner prologue tests ||r|| <= tol ||b||
+    int first = 0;              // update_p: p = z (no beta)
+};
+
+struct Coarse {
+    int r_dedup = 0;                 // columns after removing duplicates
+    int r_eff = 0;                   // columns kept (independent)
+    std::vector<int32_t> cols;       // interval index of every kept column
+    std::vector<double> E;           // r_eff x r_eff row-major (kept columns)
+    DBuf<int64_t> csr_ptr;           // [n_obs+1] kept-column entries per pixel
+    DBuf<int32_t> csr_col;
+    DBuf<double> csr_val;
+    DBuf<int64_t> csc_ptr;           // [r_eff+1] entries per kept column
+    DBuf<int32_t> csc_row;           // compact pixel
+    DBuf<double> csc_val;
+    DBuf<double> AZ64;               // [r_eff][n_obs*n_s] column-major (FP64 plans)
+    DBuf<float> AZ32;                // same (mixed plans)
+    DBuf<double> Einv;               // [r_eff][r_eff] row-major
+    DBuf<double> v, w;               // coarse work vectors [r_eff]
+};
+
+}  // namespace mm
+
+struct mm_plan_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    mm_opts opts{};
+    int n_s = 1;
+    int64_t n_t = 0, n_pix = 0, n_obs = 0;
+    int32_t n_int = 0;
+    std::vector<int64_t> h_off;         // interval offsets
+    std::vector<mm_psd> h_psd;
+    std::vector<int32_t> h_int_kern;    // interval -> distinct kernel
+    std::vector<int32_t> h_kern_len;    // kernel -> interval length n_j
+    std::vector<mm_psd> h_kern_psd;
+    std::vector<std::vector<double>> h_taps;  // per kernel, t_0..t_K (FP64)
+    int32_t n_kern = 0;
+
+    // time-ordered data
+    mm::DBuf<int32_t> cid;              // compact pixel of every sample
+    mm::DBuf<double> w64;               // [n_t][2] (IQU)
+    mm::DBuf<float> w32;
+    // pixel-sorted data
+    mm::DBuf<int32_t> perm;             // sorted position -> sample
+    mm::DBuf<double> ws64;              // [n_t][2] weights in sorted order
+    mm::DBuf<float> ws32;
+    mm::DBuf<int64_t> seg;              // [n_obs+1] segment offsets
+    mm::DBuf<uint64_t> heads;           // segment-start bit per sorted sample
+    mm::DBuf<int32_t> wave_pix;         // [n_waves+1] pixel ranges of the P^T waves
+    int64_t n_waves = 0;
+    mm::DBuf<int32_t> obs;              // compact -> original id
+    mm::DBuf<int32_t> hits;             // s_p
+    // intervals / kernels
+    mm::DBuf<int64_t> int_lo, int_hi;
+    mm::DBuf<int32_t> int_kern;
+    mm::DBuf<double> kern_t0;           // t_0 of every kernel
+    mm::FftTiling fft64, fft32;
+    // block-Jacobi inverse blocks: 6 unique entries (a00 a01 a02 a11 a12 a22) or 1
+    mm::DBuf<double> bj;
+    // coarse space
+    bool has_coarse = false;
+    mm::Coarse co;
+    // work buffers
+    mm::DBuf<double> tod64a, tod64b;
+    mm::DBuf<float> tod32a, tod32b;
+    mm::DBuf<double> vec[8];            // PCG vectors [n_obs*n_s]
+    mm::DBuf<double> part;              // reduction partials
+    mm::DBuf<mm::PcgScalars> sc;
+    mm::PcgScalars* h_sc = nullptr;     // pinned host mirror
+    mm::DBuf<double> hist;              // residual history
+    mm::DBuf<double> rz_hist;           // r^T z per iteration
+    double plan_ms = 0.0;
+    // optional event timing of the hot kernels
+    bool prof_on = false;
+    struct ProfRec {
+        hipEvent_t a, b;
+        int tag;     // PCG iteration index of the launch (-1: not part of an iteration)
+        bool valid;  // false for launches of iterations that were skipped after convergence
+    };
+    std::vector<ProfRec> prof_ev[MM_K_COUNT];
+    size_t prof_used[MM_K_COUNT] = {};
+    ~mm_plan_s();
+};
+
+namespace mm {
+
+constexpr int kVecBlocks = 512;   // fixed grid of the vector kernels (deterministic reductions)
+constexpr int kVecThreads = 256;
+
+// ---- sort.hip
+int build_pointing(mm_plan_t pl, const int32_t* pix, const void* weights, int wdtype);
+
+// ---- toeplitz.hip
+int build_kernels(mm_plan_t pl);
+int build_tiling(mm_plan_t pl, FftTiling& ft, bool fp64, int n_r_request);
+int toeplitz_map64(mm_plan_t pl, const double* x, double* z, const int* done);
+int toeplitz_map32(mm_plan_t pl, const double* x, float* z, const int* done);
+int toeplitz_tod64(mm_plan_t pl, const void* y, int y_f64, double* z);
+int toeplitz_tod32(mm_plan_t pl, const void* y, int y_f64, float* z);
+
+// ---- pointing.hip
+int scatter64(mm_plan_t pl, const double* z, double* x, const int* done);
+int scatter32(mm_plan_t pl, const float* z, double* x, const int* done);
+int depoint(mm_plan_t pl, const double* x, void* y, int y_f64);
+int build_bj(mm_plan_t pl);
+int bj_apply(mm_plan_t pl, const double* r, double* z, const PcgCtl& ctl);
+
+// ---- coarse.hip
+int build_coarse(mm_plan_t pl);
+int twolvl_apply(mm_plan_t pl, const double* r, double* z, const PcgCtl& ctl);
+
+// ---- blas.hip
+int vec_dot(mm_plan_t pl, const double* a, const double* b, double* part, const int* done);
+int pcg_update_xr(mm_plan_t pl, double* x, double* r, const double* p, const double* q,
+                  const PcgCtl& ctl);
+int pcg_update_p(mm_plan_t pl, double* p, const double* z, const PcgCtl& ctl);
+int vec_axpby(mm_plan_t pl, double a, const double* x, double b, const double* y, double* out);
+int vec_set_scalars(mm_plan_t pl, const PcgCtl& ctl, double tol, const double* part_bb,
+                    int iter_base);
+
+// host helpers
+int64_t nvec(mm_plan_t pl);
+// event timing around a launch (no-op unless profiling is on)
+int prof_begin(mm_plan_t pl, int k, int tag = -1);
+int prof_end(mm_plan_t pl, int k);
+// mark launches recorded since mark[] with tag >= first_skipped as no-ops
+void prof_invalidate(mm_plan_t pl, const size_t* mark, int first_skipped);
+int apply_A64(mm_plan_t pl, const double* x, double* y, const int* done);
+int apply_A32(mm_plan_t pl, const double* x, double* y, const int* done);
+
+}  // namespace mm

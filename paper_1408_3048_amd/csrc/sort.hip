@@ -1,0 +1,377 @@
+// Plan-time pointing layout: validation of pixel ids, hit counts, compaction
+// to observed pixels, and a stable LSD radix sort of the samples by compact
+// pixel (so every pixel's samples are in ascending time order).  Integer work
+// only: results are bit-exact and independent of scheduling.
+#include <climits>
+
+#include "mm_internal.h"
+
+namespace mm {
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+// exclusive scan of one tile; writes the tile total to sums[block]
+template <typename TI>
+__global__ void k_scan_tile(const TI* __restrict__ in, int64_t* __restrict__ out, int64_t n,
+                            int64_t* __restrict__ sums) {
+    __shared__ int64_t s[kScanThreads];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int64_t v[kScanItems];
+    int64_t acc = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t idx = base + i;
+        v[i] = idx < n ? (int64_t)in[idx] : 0;
+        acc += v[i];
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int d = 1; d < kScanThreads; d <<= 1) {
+        int64_t t = threadIdx.x >= d ? s[threadIdx.x - d] : 0;
+        __syncthreads();
+        s[threadIdx.x] += t;
+        __syncthreads();
+    }
+    int64_t run = s[threadIdx.x] - acc;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t idx = base + i;
+        if (idx < n) out[idx] = run;
+        run += v[i];
+    }
+    if (threadIdx.x == kScanThreads - 1) sums[blockIdx.x] = s[threadIdx.x];
+}
+
+__global__ void k_scan_add(int64_t* __restrict__ out, int64_t n, const int64_t* __restrict__ offs) {
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    const int64_t add = offs[blockIdx.x];
+    for (int i = threadIdx.x; i < kScanTile; i += kScanThreads) {
+        const int64_t idx = base + i;
+        if (idx < n) out[idx] += add;
+    }
+}
+
+// out[0..n] = exclusive scan of in[0..n-1], out[n] = total
+template <typename TI>
+int scan_exclusive(const TI* in, int64_t* out, int64_t n, hipStream_t st) {
+    if (n == 0) {
+        MM_HIP(hipMemsetAsync(out, 0, sizeof(int64_t), st));
+        return MM_OK;
+    }
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    DBuf<int64_t> sums, soff;
+    MM_TRY(sums.alloc(nb));
+    MM_TRY(soff.alloc(nb + 1));
+    hipLaunchKernelGGL(k_scan_tile<TI>, dim3(nb), dim3(kScanThreads), 0, st, in, out, n, sums.p);
+    MM_HIP(hipGetLastError());
+    if (nb == 1) {  // one tile: its total is the total
+        MM_HIP(hipMemcpyAsync(out + n, sums.p, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+        MM_HIP(hipStreamSynchronize(st));
+        return MM_OK;
+    }
+    MM_TRY(scan_exclusive<int64_t>(sums.p, soff.p, nb, st));
+    hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(kScanThreads), 0, st, out, n, soff.p);
+    MM_HIP(hipGetLastError());
+    MM_HIP(hipMemcpyAsync(out + n, soff.p + nb, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+    MM_HIP(hipStreamSynchronize(st));  // scratch buffers are released on return
+    return MM_OK;
+}
+
+__global__ void k_minmax(const int32_t* __restrict__ pix, int64_t n, int* __restrict__ mm2) {
+    int lo = INT_MAX, hi = INT_MIN;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int v = pix[t];
+        lo = min(lo, v);
+        hi = max(hi, v);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = min(lo, __shfl_xor(lo, o));
+        hi = max(hi, __shfl_xor(hi, o));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMin(&mm2[0], lo);
+        atomicMax(&mm2[1], hi);
+    }
+}
+
+__global__ void k_hist(const int32_t* __restrict__ pix, int64_t n, int32_t* __restrict__ h) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&h[pix[t]], 1);
+}
+
+__global__ void k_flags(const int32_t* __restrict__ h, int64_t n, int32_t* __restrict__ f) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x)
+        f[p] = h[p] > 0 ? 1 : 0;
+}
+
+__global__ void k_compact(const int32_t* __restrict__ h, const int64_t* __restrict__ pos,
+                          int64_t n_pix, int32_t* __restrict__ cmap, int32_t* __restrict__ obs,
+                          int32_t* __restrict__ hits) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n_pix;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        if (h[p] > 0) {
+            const int64_t c = pos[p];
+            cmap[p] = (int32_t)c;
+            obs[c] = (int32_t)p;
+            hits[c] = h[p];
+        } else {
+            cmap[p] = -1;
+        }
+    }
+}
+
+__global__ void k_cid(const int32_t* __restrict__ pix, int64_t n, const int32_t* __restrict__ cmap,
+                      int32_t* __restrict__ cid, int32_t* __restrict__ tidx) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        cid[t] = cmap[pix[t]];
+        tidx[t] = (int32_t)t;
+    }
+}
+
+// ---- stable LSD radix sort of (key = compact pixel, value = sample index)
+constexpr int kRadixThreads = 256;
+constexpr int kRadixItems = 16;
+constexpr int kRadixTile = kRadixThreads * kRadixItems;
+
+__global__ void k_radix_hist(const int32_t* __restrict__ keys, int64_t n, int shift,
+                             int64_t* __restrict__ counts, int64_t ntiles) {
+    __shared__ int h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    for (int it = 0; it < kRadixItems; ++it) {
+        const int64_t idx = base + it * kRadixThreads + threadIdx.x;
+        if (idx < n) atomicAdd(&h[((uint32_t)keys[idx] >> shift) & 255u], 1);
+    }
+    __syncthreads();
+    counts[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ void k_radix_scatter(const int32_t* __restrict__ kin, const int32_t* __restrict__ vin,
+                                int32_t* __restrict__ kout, int32_t* __restrict__ vout, int64_t n,
+                                int shift, const int64_t* __restrict__ offs, int64_t ntiles) {
+    __shared__ int64_t running[256];
+    __shared__ int wcnt[4][256];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    running[tid] = offs[(int64_t)tid * ntiles + blockIdx.x];
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    for (int it = 0; it < kRadixItems; ++it) {
+        const int64_t idx = base + it * kRadixThreads + tid;
+        const bool valid = idx < n;
+        const int32_t key = valid ? kin[idx] : 0;
+        const int32_t val = valid ? vin[idx] : 0;
+        const int d = (int)(((uint32_t)key >> shift) & 255u);
+        for (int q = tid; q < 4 * 256; q += kRadixThreads) (&wcnt[0][0])[q] = 0;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t bb = __ballot((d >> b) & 1);
+            peers &= ((d >> b) & 1) ? bb : ~bb;
+        }
+        __syncthreads();
+        const int rank = __popcll(peers & lt);
+        if (valid && rank == 0) wcnt[wv][d] = __popcll(peers);
+        __syncthreads();
+        if (valid) {
+            int64_t dst = running[d] + rank;
+            for (int w = 0; w < wv; ++w) dst += wcnt[w][d];
+            kout[dst] = key;
+            vout[dst] = val;
+        }
+        __syncthreads();
+        running[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
+        __syncthreads();
+    }
+}
+
+__global__ void k_heads(const int64_t* __restrict__ seg, int64_t n_obs,
+                        unsigned long long* __restrict__ heads) {
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_obs;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = seg[c];
+        atomicOr(&heads[i >> 6], 1ull << (i & 63));
+    }
+}
+
+__global__ void k_wave_ranges(const int64_t* __restrict__ seg, int64_t n_obs, int64_t n_waves,
+                              int64_t per_wave, int32_t* __restrict__ wp) {
+    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w <= n_waves;
+         w += (int64_t)gridDim.x * blockDim.x) {
+        if (w == n_waves) {
+            wp[w] = (int32_t)n_obs;
+            continue;
+        }
+        const int64_t target = w * per_wave;
+        int64_t lo = 0, hi = n_obs;  // first c in [0, n_obs] with seg[c] >= target
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (seg[mid] >= target) hi = mid; else lo = mid + 1;
+        }
+        wp[w] = (int32_t)lo;
+    }
+}
+
+template <typename TW>
+__global__ void k_weights(const TW* __restrict__ w, const int32_t* __restrict__ perm, int64_t n,
+                          double* __restrict__ w64, float* __restrict__ w32,
+                          double* __restrict__ ws64, float* __restrict__ ws32) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const double a = (double)w[2 * t], b = (double)w[2 * t + 1];
+        w64[2 * t] = a;
+        w64[2 * t + 1] = b;
+        if (w32) {
+            w32[2 * t] = (float)a;
+            w32[2 * t + 1] = (float)b;
+        }
+        const int64_t s = perm[t];
+        const double sa = (double)w[2 * s], sb = (double)w[2 * s + 1];
+        ws64[2 * t] = sa;
+        ws64[2 * t + 1] = sb;
+        if (ws32) {
+            ws32[2 * t] = (float)sa;
+            ws32[2 * t + 1] = (float)sb;
+        }
+    }
+}
+
+inline int grid_for(int64_t n, int threads = 256, int cap = 65536) {
+    int64_t g = (n + threads - 1) / threads;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+}  // namespace
+
+int build_pointing(mm_plan_t pl, const int32_t* pix, const void* weights, int wdtype) {
+    hipStream_t st = pl->stream;
+    const int64_t n = pl->n_t;
+    // pixel range
+    DBuf<int> mm2;
+    MM_TRY(mm2.alloc(2));
+    const int init[2] = {INT_MAX, INT_MIN};
+    MM_HIP(hipMemcpyAsync(mm2.p, init, sizeof(init), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_minmax, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, pix, n, mm2.p);
+    MM_HIP(hipGetLastError());
+    int h_mm[2];
+    MM_HIP(hipMemcpyAsync(h_mm, mm2.p, sizeof(h_mm), hipMemcpyDeviceToHost, st));
+    MM_HIP(hipStreamSynchronize(st));
+    if (h_mm[0] < 0 || (int64_t)h_mm[1] >= pl->n_pix) {
+        set_error("pixel ids span [%d, %d], outside [0, %lld)", h_mm[0], h_mm[1],
+                  (long long)pl->n_pix);
+        return MM_ERR_ARG;
+    }
+    // hits on the full grid, compaction
+    DBuf<int32_t> hfull, flags, cmap;
+    DBuf<int64_t> pos;
+    MM_TRY(hfull.alloc(pl->n_pix));
+    MM_TRY(flags.alloc(pl->n_pix));
+    MM_TRY(cmap.alloc(pl->n_pix));
+    MM_TRY(pos.alloc(pl->n_pix + 1));
+    MM_HIP(hipMemsetAsync(hfull.p, 0, pl->n_pix * sizeof(int32_t), st));
+    hipLaunchKernelGGL(k_hist, dim3(grid_for(n)), dim3(256), 0, st, pix, n, hfull.p);
+    hipLaunchKernelGGL(k_flags, dim3(grid_for(pl->n_pix)), dim3(256), 0, st, hfull.p, pl->n_pix,
+                       flags.p);
+    MM_HIP(hipGetLastError());
+    MM_TRY(scan_exclusive<int32_t>(flags.p, pos.p, pl->n_pix, st));
+    int64_t n_obs = 0;
+    MM_HIP(hipMemcpy(&n_obs, pos.p + pl->n_pix, sizeof(int64_t), hipMemcpyDeviceToHost));
+    pl->n_obs = n_obs;
+    MM_TRY(pl->obs.alloc(n_obs));
+    MM_TRY(pl->hits.alloc(n_obs));
+    hipLaunchKernelGGL(k_compact, dim3(grid_for(pl->n_pix)), dim3(256), 0, st, hfull.p, pos.p,
+                       pl->n_pix, cmap.p, pl->obs.p, pl->hits.p);
+    MM_HIP(hipGetLastError());
+    hfull.release();
+    flags.release();
+    pos.release();
+    // compact id per sample
+    MM_TRY(pl->cid.alloc(n));
+    DBuf<int32_t> k2, v1, v2;
+    MM_TRY(v1.alloc(n));
+    hipLaunchKernelGGL(k_cid, dim3(grid_for(n)), dim3(256), 0, st, pix, n, cmap.p, pl->cid.p, v1.p);
+    MM_HIP(hipGetLastError());
+    cmap.release();
+    // segments
+    MM_TRY(pl->seg.alloc(n_obs + 1));
+    MM_TRY(scan_exclusive<int32_t>(pl->hits.p, pl->seg.p, n_obs, st));
+    // stable radix sort by compact pixel
+    int bits = 1;
+    while (bits < 31 && ((int64_t)1 << bits) < n_obs) ++bits;
+    const int passes = (bits + 7) / 8;
+    const int64_t ntiles = (n + kRadixTile - 1) / kRadixTile;
+    DBuf<int64_t> counts, offs;
+    MM_TRY(counts.alloc(256 * ntiles));
+    MM_TRY(offs.alloc(256 * ntiles + 1));
+    DBuf<int32_t> k1;
+    MM_TRY(k1.alloc(n));
+    MM_TRY(k2.alloc(n));
+    MM_TRY(v2.alloc(n));
+    MM_HIP(hipMemcpyAsync(k1.p, pl->cid.p, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    int32_t *kin = k1.p, *kout = k2.p, *vin = v1.p, *vout = v2.p;
+    for (int ps = 0; ps < passes; ++ps) {
+        const int shift = 8 * ps;
+        hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(kRadixThreads), 0, st, kin, n, shift,
+                           counts.p, ntiles);
+        MM_HIP(hipGetLastError());
+        MM_TRY(scan_exclusive<int64_t>(counts.p, offs.p, 256 * ntiles, st));
+        hipLaunchKernelGGL(k_radix_scatter, dim3(ntiles), dim3(kRadixThreads), 0, st, kin, vin,
+                           kout, vout, n, shift, offs.p, ntiles);
+        MM_HIP(hipGetLastError());
+        std::swap(kin, kout);
+        std::swap(vin, vout);
+    }
+    MM_TRY(pl->perm.alloc(n));
+    MM_HIP(hipMemcpyAsync(pl->perm.p, vin, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    MM_HIP(hipStreamSynchronize(st));
+    k1.release();
+    k2.release();
+    v1.release();
+    v2.release();
+    counts.release();
+    offs.release();
+    // segment heads and P^T work ranges
+    const int64_t nwords = (n + 63) / 64 + 1;
+    MM_TRY(pl->heads.alloc(nwords));
+    MM_HIP(hipMemsetAsync(pl->heads.p, 0, nwords * sizeof(uint64_t), st));
+    hipLaunchKernelGGL(k_heads, dim3(grid_for(n_obs)), dim3(256), 0, st, pl->seg.p, n_obs,
+                       (unsigned long long*)pl->heads.p);
+    const int64_t per_wave = 2048;
+    pl->n_waves = (n + per_wave - 1) / per_wave;
+    MM_TRY(pl->wave_pix.alloc(pl->n_waves + 1));
+    hipLaunchKernelGGL(k_wave_ranges, dim3(grid_for(pl->n_waves + 1)), dim3(256), 0, st, pl->seg.p,
+                       n_obs, pl->n_waves, per_wave, pl->wave_pix.p);
+    MM_HIP(hipGetLastError());
+    // weights, time-ordered and pixel-sorted
+    if (pl->n_s == 3) {
+        const bool mixed = pl->opts.precision == MM_MIXED;
+        MM_TRY(pl->w64.alloc(2 * n));
+        MM_TRY(pl->ws64.alloc(2 * n));
+        if (mixed) {
+            MM_TRY(pl->w32.alloc(2 * n));
+            MM_TRY(pl->ws32.alloc(2 * n));
+        }
+        if (wdtype == MM_F64)
+            hipLaunchKernelGGL(k_weights<double>, dim3(grid_for(n)), dim3(256), 0, st,
+                               (const double*)weights, pl->perm.p, n, pl->w64.p, pl->w32.p,
+                               pl->ws64.p, pl->ws32.p);
+        else
+            hipLaunchKernelGGL(k_weights<float>, dim3(grid_for(n)), dim3(256), 0, st,
+                               (const float*)weights, pl->perm.p, n, pl->w64.p, pl->w32.p,
+                               pl->ws64.p, pl->ws32.p);
+        MM_HIP(hipGetLastError());
+    }
+    MM_HIP(hipStreamSynchronize(st));
+    return MM_OK;
+}
+
+}  // namespace mm

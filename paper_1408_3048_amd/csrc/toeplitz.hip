@@ -1,0 +1,835 @@
+// Noise weighting N^-1: one symmetric band-limited Toeplitz block per
+// stationary interval [Sect. 2.1, eq. N_def], applied by overlap-save with an
+// LDS-resident radix-16 FFT.
+//
+// Kernel construction [Sect. 4.1.4, eq. fknee; App. D, eqs. glsSolFourier,
+// apodDef]: the first row of the block of an interval of n samples is the
+// inverse real DFT, on the interval's own grid f_m = m f_samp / n, of the
+// inverse PSD q_m = 1 / (sigma^2 (1 + (f_knee / f_m)^alpha)) (q_0 = 0 for 1/f
+// noise), kept for lags |k| <= lambda and apodised by a window.  Its symbol
+// on the FFT grid, H(m) = t_0 + 2 sum_k t_k cos(2 pi k m / n_r), is the real
+// spectrum used by the convolution; min H > 0 is required (positive
+// definiteness of every block).
+//
+// Overlap-save: a tile producing outputs [o, o + L) loads the window
+// [o - lambda, o + L + lambda) of the interval (zeros outside the interval,
+// whose edges are hard boundaries, not periodic) into n_r >= L + 2 lambda real
+// points.  The real sequence is packed as n_r/2 complex points, transformed
+// in place by decimation in frequency (natural order in, bit-reversed out),
+// split into the real spectrum, multiplied by H, merged back, and
+// transformed in place by decimation in time (bit-reversed in, natural out),
+// so no explicit permutation pass is needed.  Both transforms run as radix-16
+// passes held in registers with one LDS exchange per pass.
+#include <cmath>
+#include <map>
+#include <tuple>
+
+#include "mm_internal.h"
+
+namespace mm {
+namespace {
+
+// ------------------------------------------------------------------ plan-time transforms
+
+// q_m for every kernel: a[g][m] = c_m q_m, the coefficients of the real
+// inverse DFT written as a cosine sum (c_0 = 1, c_m = 2 for 0 < m < n/2,
+// c_{n/2} = 1 for even n).
+__global__ void k_inv_psd(const int32_t* __restrict__ klen, const double* __restrict__ kpar,
+                          const int64_t* __restrict__ aoff, double f_samp,
+                          double* __restrict__ a, int32_t nk) {
+    const int g = blockIdx.y;
+    if (g >= nk) return;
+    const int64_t n = klen[g];
+    const int64_t cnt = n / 2 + 1;
+    const double sigma = kpar[3 * g], fk = kpar[3 * g + 1], al = kpar[3 * g + 2];
+    for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < cnt;
+         m += (int64_t)gridDim.x * blockDim.x) {
+        double q;
+        if (fk > 0.0) {
+            if (m == 0) {
+                q = 0.0;
+            } else {
+                const double f = (double)m * f_samp / (double)n;
+                q = 1.0 / (sigma * sigma * (1.0 + pow(fk / f, al)));
+            }
+        } else {
+            q = 1.0 / (sigma * sigma);
+        }
+        double c = 2.0;
+        if (m == 0 || (2 * m == n)) c = 1.0;
+        a[aoff[g] + m] = c * q;
+    }
+}
+
+// out[g][j] = sum_{i < cnt[g]} a[g][i] cos(2 pi i j / n[g]) for j < J[g].
+// The cosine of every term comes from a rotation recurrence re-anchored by
+// sincospi every 32 terms (bounded rounding growth).
+constexpr int kCtThreads = 256;
+__global__ void k_cos_transform(const double* __restrict__ a, const int64_t* __restrict__ aoff,
+                                const int64_t* __restrict__ acnt, const int64_t* __restrict__ nper,
+                                const int64_t* __restrict__ jcnt, const int64_t* __restrict__ ooff,
+                                double* __restrict__ out, int32_t ng) {
+    __shared__ double sa[kCtThreads];
+    const int g = blockIdx.y;
+    if (g >= ng) return;
+    const int64_t J = jcnt[g];
+    const int64_t j = (int64_t)blockIdx.x * kCtThreads + threadIdx.x;
+    if ((int64_t)blockIdx.x * kCtThreads >= J) return;
+    const int64_t n = nper[g];
+    const int64_t cnt = acnt[g];
+    const double* ag = a + aoff[g];
+    const int64_t jm = j % n;
+    double cs, ss;
+    sincospi(2.0 * (double)jm / (double)n, &ss, &cs);
+    double acc = 0.0;
+    for (int64_t i0 = 0; i0 < cnt; i0 += kCtThreads) {
+        __syncthreads();
+        sa[threadIdx.x] = (i0 + threadIdx.x < cnt) ? ag[i0 + threadIdx.x] : 0.0;
+        __syncthreads();
+        for (int s = 0; s < kCtThreads; s += 32) {
+            if (i0 + s >= cnt) break;
+            const int64_t idx = ((i0 + s) % n) * jm % n;
+            double c, sn;
+            sincospi(2.0 * (double)idx / (double)n, &sn, &c);
+#pragma unroll 8
+            for (int u = 0; u < 32; ++u) {
+                acc = fma(sa[s + u], c, acc);
+                const double c2 = c * cs - sn * ss;
+                sn = fma(sn, cs, c * ss);
+                c = c2;
+            }
+        }
+    }
+    if (j < J) out[ooff[g] + j] = acc;
+}
+
+__global__ void k_taps_finish(double* __restrict__ t, const int64_t* __restrict__ toff,
+                              const int64_t* __restrict__ tcnt, const int32_t* __restrict__ klen,
+                              int lam, int window, int32_t nk) {
+    const int g = blockIdx.y;
+    if (g >= nk) return;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < tcnt[g];
+         k += (int64_t)gridDim.x * blockDim.x) {
+        double w = 1.0;
+        const double x = (double)k / (double)lam;
+        if (window == MM_WIN_GAUSS) w = exp(-x * x);
+        else if (window == MM_WIN_GAUSS2) w = exp(-2.0 * x * x);
+        t[toff[g] + k] *= w / (double)klen[g];
+    }
+}
+
+// spectrum coefficients b_0 = t_0, b_k = 2 t_k
+__global__ void k_spec_coef(const double* __restrict__ t, const int64_t* __restrict__ toff,
+                            const int64_t* __restrict__ tcnt, double* __restrict__ b, int32_t nk) {
+    const int g = blockIdx.y;
+    if (g >= nk) return;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < tcnt[g];
+         k += (int64_t)gridDim.x * blockDim.x)
+        b[toff[g] + k] = (k == 0 ? 1.0 : 2.0) * t[toff[g] + k];
+}
+
+__global__ void k_spec_finish(const double* __restrict__ Hraw, int64_t stride, int64_t cnt,
+                              double scale, double* __restrict__ H64, float* __restrict__ H32,
+                              double* __restrict__ hmin, int32_t nk) {
+    const int g = blockIdx.x;
+    double m = INFINITY;
+    for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+        const double h = Hraw[g * stride + i];
+        m = fmin(m, h);
+        if (H64) H64[g * stride + i] = h * scale;
+        if (H32) H32[g * stride + i] = (float)(h * scale);
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) hmin[g] = red[0];
+}
+
+// ------------------------------------------------------------------ overlap-save kernel
+
+template <typename T>
+struct ToepArgs {
+    const int32_t* cid;
+    const T* w;           // [n_t][2] time-ordered weights (IQU)
+    const double* x;      // map (FP64)
+    const void* y;        // TOD input
+    int y_f64;
+    int mode;             // 0 map IQU, 1 map I, 2 TOD
+    T* z;
+    const T* H;           // [n_kern][M + 1]
+    const T* tw;          // [M][2]
+    const int64_t* tile_out;
+    const int32_t* tile_len;
+    const int32_t* tile_int;
+    const int64_t* int_lo;
+    const int64_t* int_hi;
+    const int32_t* int_kern;
+    int lam;
+    const int* done;
+};
+
+template <typename T>
+__device__ __forceinline__ int lds_pad(int a) {
+    return a + (a >> (sizeof(T) == 4 ? 5 : 4));
+}
+
+template <int BITS>
+__device__ __forceinline__ int rev_bits(int v) {
+    return (int)(__builtin_bitreverse32((uint32_t)v) >> (32 - BITS));
+}
+
+// exp(-2 pi i q / 16), q = 0..15
+template <typename T>
+__device__ __forceinline__ void root16(int q, T& c, T& s) {
+    constexpr double C1 = 0.92387953251128675613, S1 = 0.38268343236508977173,
+                     C2 = 0.70710678118654752440;
+    const double cs[16] = {1.0, C1, C2, S1, 0.0, -S1, -C2, -C1, -1.0, -C1, -C2, -S1, 0.0, S1, C2, C1};
+    const double sn[16] = {0.0, S1, C2, C1, 1.0, C1, C2, S1, 0.0, -S1, -C2, -C1, -1.0, -C1, -C2, -S1};
+    c = (T)cs[q & 15];
+    s = (T)(-sn[q & 15]);
+}
+
+// in-register radix-R DIF network: natural in, bit-reversed out (forward, e^{-i})
+template <typename T, int R>
+__device__ __forceinline__ void dif_net(T* vr, T* vi) {
+#pragma unroll
+    for (int h = R / 2; h >= 1; h >>= 1) {
+#pragma unroll
+        for (int b = 0; b < R; b += 2 * h) {
+#pragma unroll
+            for (int kk = 0; kk < h; ++kk) {
+                const T ar = vr[b + kk], ai = vi[b + kk];
+                const T cr = vr[b + kk + h], ci = vi[b + kk + h];
+                vr[b + kk] = ar + cr;
+                vi[b + kk] = ai + ci;
+                const T dr = ar - cr, di = ai - ci;
+                const int q = kk * (16 / (2 * h));
+                if (q == 0) {
+                    vr[b + kk + h] = dr;
+                    vi[b + kk + h] = di;
+                } else if (q == 4) {  // * (-i)
+                    vr[b + kk + h] = di;
+                    vi[b + kk + h] = -dr;
+                } else {
+                    T c, s;
+                    root16<T>(q, c, s);
+                    vr[b + kk + h] = dr * c - di * s;
+                    vi[b + kk + h] = dr * s + di * c;
+                }
+            }
+        }
+    }
+}
+
+// in-register inverse radix-R DIT network: bit-reversed in, natural out (e^{+i})
+template <typename T, int R>
+__device__ __forceinline__ void dit_net_inv(T* vr, T* vi) {
+#pragma unroll
+    for (int h = 1; h < R; h <<= 1) {
+#pragma unroll
+        for (int b = 0; b < R; b += 2 * h) {
+#pragma unroll
+            for (int kk = 0; kk < h; ++kk) {
+                const int q = kk * (16 / (2 * h));
+                T cr = vr[b + kk + h], ci = vi[b + kk + h];
+                if (q == 4) {  // * (+i)
+                    const T t = cr;
+                    cr = -ci;
+                    ci = t;
+                } else if (q != 0) {
+                    T c, s;
+                    root16<T>(q, c, s);
+                    s = -s;  // conjugate root
+                    const T t = cr * c - ci * s;
+                    ci = cr * s + ci * c;
+                    cr = t;
+                }
+                const T ar = vr[b + kk], ai = vi[b + kk];
+                vr[b + kk] = ar + cr;
+                vi[b + kk] = ai + ci;
+                vr[b + kk + h] = ar - cr;
+                vi[b + kk + h] = ai - ci;
+            }
+        }
+    }
+}
+
+// w^e for e = 0..R-1 from w (binary powering: short dependency chains)
+template <typename T, int R>
+__device__ __forceinline__ void powers(T wr, T wi, T* pr, T* pi) {
+    pr[0] = (T)1;
+    pi[0] = (T)0;
+    if (R > 1) {
+        pr[1] = wr;
+        pi[1] = wi;
+    }
+#pragma unroll
+    for (int e = 2; e < R; ++e) {
+        const int a = (e & 1) ? e - 1 : e / 2;
+        const int b = (e & 1) ? 1 : e / 2;
+        pr[e] = pr[a] * pr[b] - pi[a] * pi[b];
+        pi[e] = pr[a] * pi[b] + pi[a] * pr[b];
+    }
+}
+
+template <typename T, int LOGM, int NT, int LR, int LOGB>
+__device__ __forceinline__ void dif_pass(T* __restrict__ re, T* __restrict__ im,
+                                         const T* __restrict__ tw) {
+    constexpr int R = 1 << LR, B = 1 << LOGB, Q = B / R, M = 1 << LOGM, G = M / R;
+    constexpr int TWS = (2 * M) / B;
+    for (int g = threadIdx.x; g < G; g += NT) {
+        const int k = g & (Q - 1);
+        const int base = (g / Q) * B + k;
+        T vr[R], vi[R];
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            const int a = lds_pad<T>(base + m * Q);
+            vr[m] = re[a];
+            vi[m] = im[a];
+        }
+        dif_net<T, R>(vr, vi);
+        if (Q > 1 && k != 0) {
+            T pr[R], pi[R];
+            powers<T, R>(tw[2 * k * TWS], tw[2 * k * TWS + 1], pr, pi);
+#pragma unroll
+            for (int i = 1; i < R; ++i) {
+                const int e = rev_bits<LR>(i);
+                const T t = vr[i] * pr[e] - vi[i] * pi[e];
+                vi[i] = vr[i] * pi[e] + vi[i] * pr[e];
+                vr[i] = t;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int a = lds_pad<T>(base + i * Q);
+            re[a] = vr[i];
+            im[a] = vi[i];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T, int LOGM, int NT, int LR, int LOGB>
+__device__ __forceinline__ void dit_pass(T* __restrict__ re, T* __restrict__ im,
+                                         const T* __restrict__ tw) {
+    constexpr int R = 1 << LR, B = 1 << LOGB, Q = B / R, M = 1 << LOGM, G = M / R;
+    constexpr int TWS = (2 * M) / B;
+    for (int g = threadIdx.x; g < G; g += NT) {
+        const int k = g & (Q - 1);
+        const int base = (g / Q) * B + k;
+        T vr[R], vi[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int a = lds_pad<T>(base + i * Q);
+            vr[i] = re[a];
+            vi[i] = im[a];
+        }
+        if (Q > 1 && k != 0) {
+            T pr[R], pi[R];
+            powers<T, R>(tw[2 * k * TWS], tw[2 * k * TWS + 1], pr, pi);
+#pragma unroll
+            for (int i = 1; i < R; ++i) {
+                const int e = rev_bits<LR>(i);
+                const T t = vr[i] * pr[e] + vi[i] * pi[e];  // * conj(w^e)
+                vi[i] = vi[i] * pr[e] - vr[i] * pi[e];
+                vr[i] = t;
+            }
+        }
+        dit_net_inv<T, R>(vr, vi);
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            const int a = lds_pad<T>(base + m * Q);
+            re[a] = vr[m];
+            im[a] = vi[m];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T, int LOGM, int NT, int LOGB>
+__device__ __forceinline__ void fwd_passes(T* re, T* im, const T* tw) {
+    if constexpr (LOGB > 0) {
+        constexpr int LR = LOGB >= 4 ? 4 : LOGB;
+        dif_pass<T, LOGM, NT, LR, LOGB>(re, im, tw);
+        fwd_passes<T, LOGM, NT, LOGB - LR>(re, im, tw);
+    }
+}
+
+template <typename T, int LOGM, int NT, int LOGB>
+__device__ __forceinline__ void inv_passes(T* re, T* im, const T* tw) {
+    if constexpr (LOGB > 0) {
+        constexpr int LR = LOGB >= 4 ? 4 : LOGB;
+        inv_passes<T, LOGM, NT, LOGB - LR>(re, im, tw);
+        dit_pass<T, LOGM, NT, LR, LOGB>(re, im, tw);
+    }
+}
+
+// real-spectrum split, multiplication by the (pre-scaled) real kernel spectrum H,
+// and merge back, on pairs (k, M - k) of the bit-reversed half-length transform
+template <typename T, int LOGM, int NT>
+__device__ __forceinline__ void spectrum_pass(T* __restrict__ re, T* __restrict__ im,
+                                              const T* __restrict__ H, const T* __restrict__ tw) {
+    constexpr int M = 1 << LOGM;
+    for (int k = threadIdx.x; k <= M / 2; k += NT) {
+        if (k == 0) {
+            const int a = lds_pad<T>(0);
+            const T zr = re[a], zi = im[a];
+            const T y0 = H[0] * ((T)2 * (zr + zi));
+            const T ym = H[M] * ((T)2 * (zr - zi));
+            re[a] = y0 + ym;
+            im[a] = y0 - ym;
+            continue;
+        }
+        const int km = M - k;
+        const int ak = lds_pad<T>(rev_bits<LOGM>(k));
+        const int am = lds_pad<T>(rev_bits<LOGM>(km));
+        const T zkr = re[ak], zki = im[ak], zmr = re[am], zmi = im[am];
+        const T er = tw[2 * k], ei = tw[2 * k + 1];
+        const T fr = tw[2 * km], fi = tw[2 * km + 1];
+        // 2 X_k = (Z_k + conj Z_m) - i e (Z_k - conj Z_m)
+        T Ar = zkr + zmr, Ai = zki - zmi, Dr = zkr - zmr, Di = zki + zmi;
+        T pr = er * Dr - ei * Di, pim = er * Di + ei * Dr;
+        const T xkr = Ar + pim, xki = Ai - pr;
+        // 2 X_m = (Z_m + conj Z_k) - i f (Z_m - conj Z_k)
+        Ar = zmr + zkr;
+        Ai = zmi - zki;
+        Dr = zmr - zkr;
+        Di = zmi + zki;
+        pr = fr * Dr - fi * Di;
+        pim = fr * Di + fi * Dr;
+        const T xmr = Ar + pim, xmi = Ai - pr;
+        const T hk = H[k], hm = H[km];
+        const T ykr = hk * xkr, yki = hk * xki, ymr = hm * xmr, ymi = hm * xmi;
+        // W_k = (Y_k + conj Y_m) + i conj(e) (Y_k - conj Y_m)
+        Ar = ykr + ymr;
+        Ai = yki - ymi;
+        Dr = ykr - ymr;
+        Di = yki + ymi;
+        pr = er * Dr + ei * Di;
+        pim = er * Di - ei * Dr;
+        re[ak] = Ar - pim;
+        im[ak] = Ai + pr;
+        if (km != k) {
+            Ar = ymr + ykr;
+            Ai = ymi - yki;
+            Dr = ymr - ykr;
+            Di = ymi + yki;
+            pr = fr * Dr + fi * Di;
+            pim = fr * Di - fi * Dr;
+            re[am] = Ar - pim;
+            im[am] = Ai + pr;
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__device__ __forceinline__ T load_sample(const ToepArgs<T>& a, int64_t t) {
+    if (a.mode == 0) {
+        const int64_t c = a.cid[t];
+        const T w0 = a.w[2 * t], w1 = a.w[2 * t + 1];
+        const double* xc = a.x + 3 * c;
+        return (T)xc[0] + w0 * (T)xc[1] + w1 * (T)xc[2];
+    }
+    if (a.mode == 1) return (T)a.x[a.cid[t]];
+    if (a.y_f64) return (T)((const double*)a.y)[t];
+    return (T)((const float*)a.y)[t];
+}
+
+template <typename T, int LOGM, int NT>
+__global__ __launch_bounds__(NT) void k_toeplitz(ToepArgs<T> a) {
+    constexpr int M = 1 << LOGM;
+    constexpr int NR = 2 * M;
+    constexpr int MP = M + (M >> (sizeof(T) == 4 ? 5 : 4));
+    __shared__ T sre[MP];
+    __shared__ T sim[MP];
+    if (a.done && *a.done) return;
+    const int64_t tile = blockIdx.x;
+    const int64_t o = a.tile_out[tile];
+    const int L = a.tile_len[tile];
+    const int j = a.tile_int[tile];
+    const int64_t lo = a.int_lo[j], hi = a.int_hi[j];
+    const int lam = a.lam;
+    const int64_t base = o - lam;
+    const int win = L + 2 * lam;
+    for (int i = threadIdx.x; i < NR; i += NT) {
+        const int64_t t = base + i;
+        T v = (T)0;
+        if (i < win && t >= lo && t < hi) v = load_sample<T>(a, t);
+        const int p = lds_pad<T>(i >> 1);
+        if (i & 1) sim[p] = v; else sre[p] = v;
+    }
+    __syncthreads();
+    fwd_passes<T, LOGM, NT, LOGM>(sre, sim, a.tw);
+    spectrum_pass<T, LOGM, NT>(sre, sim, a.H + (int64_t)a.int_kern[j] * (M + 1), a.tw);
+    inv_passes<T, LOGM, NT, LOGM>(sre, sim, a.tw);
+    for (int i = lam + threadIdx.x; i < lam + L; i += NT) {
+        const int p = lds_pad<T>(i >> 1);
+        a.z[o + (i - lam)] = (i & 1) ? sim[p] : sre[p];
+    }
+}
+
+template <typename T, int LOGM>
+int launch_logm(const ToepArgs<T>& a, int64_t n_tiles, hipStream_t st) {
+    constexpr int M = 1 << LOGM;
+    constexpr int NT = (M / 16) > 1024 ? 1024 : ((M / 16) < 256 ? 256 : (M / 16));
+    hipLaunchKernelGGL((k_toeplitz<T, LOGM, NT>), dim3(n_tiles), dim3(NT), 0, st, a);
+    MM_HIP(hipGetLastError());
+    return MM_OK;
+}
+
+template <typename T>
+int launch(const ToepArgs<T>& a, int logm, int64_t n_tiles, hipStream_t st) {
+    if (n_tiles == 0) return MM_OK;
+    if constexpr (sizeof(T) == 4) {
+        switch (logm) {
+            case 10: return launch_logm<T, 10>(a, n_tiles, st);
+            case 11: return launch_logm<T, 11>(a, n_tiles, st);
+            case 12: return launch_logm<T, 12>(a, n_tiles, st);
+            case 13: return launch_logm<T, 13>(a, n_tiles, st);
+            case 14: return launch_logm<T, 14>(a, n_tiles, st);
+        }
+    } else {
+        switch (logm) {
+            case 10: return launch_logm<T, 10>(a, n_tiles, st);
+            case 11: return launch_logm<T, 11>(a, n_tiles, st);
+            case 12: return launch_logm<T, 12>(a, n_tiles, st);
+            case 13: return launch_logm<T, 13>(a, n_tiles, st);
+        }
+    }
+    set_error("no overlap-save kernel for log2(M) = %d", logm);
+    return MM_ERR_ARG;
+}
+
+template <typename T>
+ToepArgs<T> base_args(mm_plan_t pl, const FftTiling& ft) {
+    ToepArgs<T> a{};
+    a.cid = pl->cid.p;
+    a.tile_out = ft.tile_out.p;
+    a.tile_len = ft.tile_len.p;
+    a.tile_int = ft.tile_int.p;
+    a.int_lo = pl->int_lo.p;
+    a.int_hi = pl->int_hi.p;
+    a.int_kern = pl->int_kern.p;
+    a.lam = pl->opts.lambda;
+    if constexpr (sizeof(T) == 8) {
+        a.H = ft.H64.p;
+        a.tw = ft.tw64.p;
+        a.w = pl->w64.p;
+    } else {
+        a.H = ft.H32.p;
+        a.tw = ft.tw32.p;
+        a.w = pl->w32.p;
+    }
+    return a;
+}
+
+constexpr int kMaxLogM64 = 13, kMaxLogM32 = 14, kMinLogM = 10;
+
+int64_t count_tiles(const std::vector<int64_t>& off, int64_t lmax) {
+    int64_t n = 0;
+    for (size_t j = 0; j + 1 < off.size(); ++j) n += (off[j + 1] - off[j] + lmax - 1) / lmax;
+    return n;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ host: kernels
+
+int build_kernels(mm_plan_t pl) {
+    hipStream_t st = pl->stream;
+    // distinct kernels: identical (sigma, f_knee, alpha, length) share taps and spectra
+    std::map<std::tuple<double, double, double, int64_t>, int32_t> seen;
+    pl->h_int_kern.resize(pl->n_int);
+    pl->h_kern_len.clear();
+    pl->h_kern_psd.clear();
+    for (int32_t j = 0; j < pl->n_int; ++j) {
+        const int64_t n = pl->h_off[j + 1] - pl->h_off[j];
+        const mm_psd& p = pl->h_psd[j];
+        const auto key = std::make_tuple(p.sigma, p.f_knee, p.alpha, n);
+        auto it = seen.find(key);
+        if (it == seen.end()) {
+            const int32_t id = (int32_t)pl->h_kern_len.size();
+            seen.emplace(key, id);
+            pl->h_kern_len.push_back((int32_t)n);
+            pl->h_kern_psd.push_back(p);
+            pl->h_int_kern[j] = id;
+        } else {
+            pl->h_int_kern[j] = it->second;
+        }
+    }
+    const int32_t nk = (int32_t)pl->h_kern_len.size();
+    pl->n_kern = nk;
+    const int lam = pl->opts.lambda;
+    std::vector<int64_t> aoff(nk), acnt(nk), nper(nk), jcnt(nk), toff(nk), tcnt(nk);
+    std::vector<double> kpar(3 * nk);
+    int64_t atot = 0, ttot = 0;
+    int64_t amax = 0;
+    for (int g = 0; g < nk; ++g) {
+        const int64_t n = pl->h_kern_len[g];
+        aoff[g] = atot;
+        acnt[g] = n / 2 + 1;
+        atot += acnt[g];
+        amax = std::max(amax, acnt[g]);
+        nper[g] = n;
+        tcnt[g] = std::min<int64_t>(lam, n - 1) + 1;
+        jcnt[g] = tcnt[g];
+        toff[g] = ttot;
+        ttot += tcnt[g];
+        kpar[3 * g] = pl->h_kern_psd[g].sigma;
+        kpar[3 * g + 1] = pl->h_kern_psd[g].f_knee;
+        kpar[3 * g + 2] = pl->h_kern_psd[g].alpha;
+    }
+    DBuf<int32_t> d_klen;
+    DBuf<double> d_kpar, d_a, d_t;
+    DBuf<int64_t> d_aoff, d_acnt, d_nper, d_jcnt, d_toff, d_tcnt;
+    MM_TRY(d_klen.alloc(nk));
+    MM_TRY(d_kpar.alloc(3 * nk));
+    MM_TRY(d_a.alloc(atot));
+    MM_TRY(d_t.alloc(ttot));
+    MM_TRY(d_aoff.alloc(nk));
+    MM_TRY(d_acnt.alloc(nk));
+    MM_TRY(d_nper.alloc(nk));
+    MM_TRY(d_jcnt.alloc(nk));
+    MM_TRY(d_toff.alloc(nk));
+    MM_TRY(d_tcnt.alloc(nk));
+    MM_HIP(hipMemcpyAsync(d_klen.p, pl->h_kern_len.data(), nk * 4, hipMemcpyHostToDevice, st));
+    MM_HIP(hipMemcpyAsync(d_kpar.p, kpar.data(), 3 * nk * 8, hipMemcpyHostToDevice, st));
+    MM_HIP(hipMemcpyAsync(d_aoff.p, aoff.data(), nk * 8, hipMemcpyHostToDevice, st));
+    MM_HIP(hipMemcpyAsync(d_acnt.p, acnt.data(), nk * 8, hipMemcpyHostToDevice, st));
+    MM_HIP(hipMemcpyAsync(d_nper.p, nper.data(), nk * 8, hipMemcpyHostToDevice, st));
+    MM_HIP(hipMemcpyAsync(d_jcnt.p, jcnt.data(), nk * 8, hipMemcpyHostToDevice, st));
+    MM_HIP(hipMemcpyAsync(d_toff.p, toff.data(), nk * 8, hipMemcpyHostToDevice, st));
+    MM_HIP(hipMemcpyAsync(d_tcnt.p, tcnt.data(), nk * 8, hipMemcpyHostToDevice, st));
+    {
+        const int gx = (int)std::min<int64_t>((amax + 255) / 256, 1024);
+        hipLaunchKernelGGL(k_inv_psd, dim3(gx, nk), dim3(256), 0, st, d_klen.p, d_kpar.p,
+                           d_aoff.p, pl->opts.f_samp, d_a.p, nk);
+        MM_HIP(hipGetLastError());
+        const int64_t jmax = *std::max_element(jcnt.begin(), jcnt.end());
+        hipLaunchKernelGGL(k_cos_transform, dim3((jmax + kCtThreads - 1) / kCtThreads, nk),
+                           dim3(kCtThreads), 0, st, d_a.p, d_aoff.p, d_acnt.p, d_nper.p, d_jcnt.p,
+                           d_toff.p, d_t.p, nk);
+        MM_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_taps_finish, dim3(std::max<int64_t>(1, (jmax + 255) / 256), nk),
+                           dim3(256), 0, st, d_t.p, d_toff.p, d_tcnt.p, d_klen.p, lam,
+                           pl->opts.window, nk);
+        MM_HIP(hipGetLastError());
+    }
+    std::vector<double> taps(ttot);
+    MM_HIP(hipMemcpyAsync(taps.data(), d_t.p, ttot * 8, hipMemcpyDeviceToHost, st));
+    MM_HIP(hipStreamSynchronize(st));
+    pl->h_taps.assign(nk, {});
+    std::vector<double> t0(nk);
+    for (int g = 0; g < nk; ++g) {
+        pl->h_taps[g].assign(taps.begin() + toff[g], taps.begin() + toff[g] + tcnt[g]);
+        t0[g] = pl->h_taps[g][0];
+        // t_0 = 0 happens only for a 1-sample interval with 1/f noise (its mean, the
+        // sample itself, is not weighted); a negative or non-finite diagonal is an error
+        if (!(t0[g] >= 0.0) || !std::isfinite(t0[g])) {
+            set_error("kernel of interval length %d has t_0 = %g < 0", pl->h_kern_len[g], t0[g]);
+            return MM_ERR_NOT_SPD;
+        }
+    }
+    MM_TRY(pl->kern_t0.alloc(nk));
+    MM_HIP(hipMemcpyAsync(pl->kern_t0.p, t0.data(), nk * 8, hipMemcpyHostToDevice, st));
+    MM_TRY(pl->int_kern.alloc(pl->n_int));
+    MM_HIP(hipMemcpyAsync(pl->int_kern.p, pl->h_int_kern.data(), pl->n_int * 4,
+                          hipMemcpyHostToDevice, st));
+    std::vector<int64_t> lo(pl->n_int), hi(pl->n_int);
+    for (int32_t j = 0; j < pl->n_int; ++j) {
+        lo[j] = pl->h_off[j];
+        hi[j] = pl->h_off[j + 1];
+    }
+    MM_TRY(pl->int_lo.alloc(pl->n_int));
+    MM_TRY(pl->int_hi.alloc(pl->n_int));
+    MM_HIP(hipMemcpyAsync(pl->int_lo.p, lo.data(), pl->n_int * 8, hipMemcpyHostToDevice, st));
+    MM_HIP(hipMemcpyAsync(pl->int_hi.p, hi.data(), pl->n_int * 8, hipMemcpyHostToDevice, st));
+    MM_HIP(hipStreamSynchronize(st));
+    return MM_OK;
+}
+
+// ------------------------------------------------------------------ host: tiling + spectra
+
+int build_tiling(mm_plan_t pl, FftTiling& ft, bool fp64, int n_r_request) {
+    hipStream_t st = pl->stream;
+    const int lam = pl->opts.lambda;
+    const int maxlogm = fp64 ? kMaxLogM64 : kMaxLogM32;
+    int logm = 0;
+    if (n_r_request > 0) {
+        int l = 0;
+        while ((2 << l) < n_r_request) ++l;
+        if ((2 << l) != n_r_request || l < kMinLogM || l > maxlogm) {
+            set_error("FFT length %d must be a power of two in [%d, %d]", n_r_request,
+                      2 << kMinLogM, 2 << maxlogm);
+            return MM_ERR_ARG;
+        }
+        if ((2 << l) <= 2 * lam) {
+            set_error("FFT length %d too short for lambda = %d", n_r_request, lam);
+            return MM_ERR_ARG;
+        }
+        logm = l;
+    } else {
+        // smallest modelled work: tiles x n_r x (log2 n_r + 4)
+        double best = 0.0;
+        for (int l = kMinLogM; l <= maxlogm; ++l) {
+            const int64_t nr = (int64_t)2 << l;
+            const int64_t lmax = nr - 2 * (int64_t)lam;
+            if (lmax < nr / 4) continue;
+            const double cost = (double)count_tiles(pl->h_off, lmax) * (double)nr * (l + 5);
+            if (logm == 0 || cost < best) {
+                best = cost;
+                logm = l;
+            }
+        }
+        if (logm == 0) {
+            set_error("lambda = %d too large for the %s overlap-save tile (n_r <= %d)", lam,
+                      fp64 ? "FP64" : "FP32", 2 << maxlogm);
+            return MM_ERR_ARG;
+        }
+    }
+    ft.logm = logm;
+    ft.n_r = 2 << logm;
+    const int M = 1 << logm;
+    const int64_t lmax = (int64_t)ft.n_r - 2 * (int64_t)lam;
+    // balanced tiles per interval
+    std::vector<int64_t> tout;
+    std::vector<int32_t> tlen, tint;
+    for (int32_t j = 0; j < pl->n_int; ++j) {
+        const int64_t a = pl->h_off[j], b = pl->h_off[j + 1], n = b - a;
+        const int64_t nt = (n + lmax - 1) / lmax;
+        const int64_t len = (n + nt - 1) / nt;
+        for (int64_t i = 0; i < nt; ++i) {
+            const int64_t s = a + i * len;
+            const int64_t e = std::min(b, s + len);
+            if (e <= s) continue;
+            tout.push_back(s);
+            tlen.push_back((int32_t)(e - s));
+            tint.push_back(j);
+        }
+    }
+    ft.n_tiles = (int64_t)tout.size();
+    MM_TRY(ft.tile_out.alloc(ft.n_tiles));
+    MM_TRY(ft.tile_len.alloc(ft.n_tiles));
+    MM_TRY(ft.tile_int.alloc(ft.n_tiles));
+    MM_HIP(hipMemcpyAsync(ft.tile_out.p, tout.data(), ft.n_tiles * 8, hipMemcpyHostToDevice, st));
+    MM_HIP(hipMemcpyAsync(ft.tile_len.p, tlen.data(), ft.n_tiles * 4, hipMemcpyHostToDevice, st));
+    MM_HIP(hipMemcpyAsync(ft.tile_int.p, tint.data(), ft.n_tiles * 4, hipMemcpyHostToDevice, st));
+    // twiddles exp(-2 pi i q / n_r), q < M
+    std::vector<double> tw(2 * (size_t)M);
+    for (int q = 0; q < M; ++q) {
+        const double ang = -2.0 * M_PI * (double)q / (double)ft.n_r;
+        tw[2 * q] = std::cos(ang);
+        tw[2 * q + 1] = std::sin(ang);
+    }
+    if (fp64) {
+        MM_TRY(ft.tw64.alloc(2 * M));
+        MM_HIP(hipMemcpyAsync(ft.tw64.p, tw.data(), 2 * M * 8, hipMemcpyHostToDevice, st));
+    } else {
+        std::vector<float> twf(tw.begin(), tw.end());
+        MM_TRY(ft.tw32.alloc(2 * M));
+        MM_HIP(hipMemcpyAsync(ft.tw32.p, twf.data(), 2 * M * 4, hipMemcpyHostToDevice, st));
+    }
+    // spectra H(m), m = 0..M, of every kernel on this grid
+    const int32_t nk = pl->n_kern;
+    std::vector<int64_t> boff(nk), bcnt(nk), nper(nk, ft.n_r), jcnt(nk, M + 1), ooff(nk);
+    std::vector<double> b;
+    for (int g = 0; g < nk; ++g) {
+        boff[g] = (int64_t)b.size();
+        bcnt[g] = (int64_t)pl->h_taps[g].size();
+        for (size_t k = 0; k < pl->h_taps[g].size(); ++k)
+            b.push_back((k == 0 ? 1.0 : 2.0) * pl->h_taps[g][k]);
+        ooff[g] = (int64_t)g * (M + 1);
+    }
+    DBuf<double> d_b, d_h, d_min;
+    DBuf<int64_t> d_boff, d_bcnt, d_nper, d_jcnt, d_ooff;
+    MM_TRY(d_b.alloc(b.size()));
+    MM_TRY(d_h.alloc((size_t)nk * (M + 1)));
+    MM_TRY(d_min.alloc(nk));
+    MM_TRY(d_boff.alloc(nk));
+    MM_TRY(d_bcnt.alloc(nk));
+    MM_TRY(d_nper.alloc(nk));
+    MM_TRY(d_jcnt.alloc(nk));
+    MM_TRY(d_ooff.alloc(nk));
+    MM_HIP(hipMemcpyAsync(d_b.p, b.data(), b.size() * 8, hipMemcpyHostToDevice, st));
+    MM_HIP(hipMemcpyAsync(d_boff.p, boff.data(), nk * 8, hipMemcpyHostToDevice, st));
+    MM_HIP(hipMemcpyAsync(d_bcnt.p, bcnt.data(), nk * 8, hipMemcpyHostToDevice, st));
+    MM_HIP(hipMemcpyAsync(d_nper.p, nper.data(), nk * 8, hipMemcpyHostToDevice, st));
+    MM_HIP(hipMemcpyAsync(d_jcnt.p, jcnt.data(), nk * 8, hipMemcpyHostToDevice, st));
+    MM_HIP(hipMemcpyAsync(d_ooff.p, ooff.data(), nk * 8, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_cos_transform, dim3((M + 1 + kCtThreads - 1) / kCtThreads, nk),
+                       dim3(kCtThreads), 0, st, d_b.p, d_boff.p, d_bcnt.p, d_nper.p, d_jcnt.p,
+                       d_ooff.p, d_h.p, nk);
+    MM_HIP(hipGetLastError());
+    const double scale = 1.0 / (2.0 * (double)ft.n_r);
+    if (fp64) {
+        MM_TRY(ft.H64.alloc((size_t)nk * (M + 1)));
+    } else {
+        MM_TRY(ft.H32.alloc((size_t)nk * (M + 1)));
+    }
+    hipLaunchKernelGGL(k_spec_finish, dim3(nk), dim3(256), 0, st, d_h.p, (int64_t)(M + 1),
+                       (int64_t)(M + 1), scale, fp64 ? ft.H64.p : nullptr,
+                       fp64 ? nullptr : ft.H32.p, d_min.p, nk);
+    MM_HIP(hipGetLastError());
+    std::vector<double> hmin(nk);
+    MM_HIP(hipMemcpyAsync(hmin.data(), d_min.p, nk * 8, hipMemcpyDeviceToHost, st));
+    MM_HIP(hipStreamSynchronize(st));
+    for (int g = 0; g < nk; ++g) {
+        // The symbol bound applies when the whole band fits in the interval; a shorter
+        // interval's block is the (windowed) circulant of its own inverse PSD, which is
+        // only semi-definite for 1/f noise (its mean is not weighted).
+        if ((int64_t)pl->h_kern_len[g] <= 2 * (int64_t)lam) continue;
+        if (!(hmin[g] > 0.0)) {
+            set_error("Toeplitz symbol min %.3e <= 0 (kernel %d: sigma=%g f_knee=%g alpha=%g, "
+                      "length %d): N^-1 block not positive definite",
+                      hmin[g], g, pl->h_kern_psd[g].sigma, pl->h_kern_psd[g].f_knee,
+                      pl->h_kern_psd[g].alpha, pl->h_kern_len[g]);
+            return MM_ERR_NOT_SPD;
+        }
+    }
+    return MM_OK;
+}
+
+// ------------------------------------------------------------------ host: launches
+
+int toeplitz_map64(mm_plan_t pl, const double* x, double* z, const int* done) {
+    auto a = base_args<double>(pl, pl->fft64);
+    a.x = x;
+    a.mode = pl->n_s == 3 ? 0 : 1;
+    a.z = z;
+    a.done = done;
+    return launch<double>(a, pl->fft64.logm, pl->fft64.n_tiles, pl->stream);
+}
+
+int toeplitz_map32(mm_plan_t pl, const double* x, float* z, const int* done) {
+    auto a = base_args<float>(pl, pl->fft32);
+    a.x = x;
+    a.mode = pl->n_s == 3 ? 0 : 1;
+    a.z = z;
+    a.done = done;
+    return launch<float>(a, pl->fft32.logm, pl->fft32.n_tiles, pl->stream);
+}
+
+int toeplitz_tod64(mm_plan_t pl, const void* y, int y_f64, double* z) {
+    auto a = base_args<double>(pl, pl->fft64);
+    a.y = y;
+    a.y_f64 = y_f64;
+    a.mode = 2;
+    a.z = z;
+    return launch<double>(a, pl->fft64.logm, pl->fft64.n_tiles, pl->stream);
+}
+
+int toeplitz_tod32(mm_plan_t pl, const void* y, int y_f64, float* z) {
+    auto a = base_args<float>(pl, pl->fft32);
+    a.y = y;
+    a.y_f64 = y_f64;
+    a.mode = 2;
+    a.z = z;
+    return launch<float>(a, pl->fft32.logm, pl->fft32.n_tiles, pl->stream);
+}
+
+}  // namespace mm

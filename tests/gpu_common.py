@@ -1,0 +1,51 @@
+"""Shared fixtures of the GPU tests: seeded scans, oracle problems, device plans."""
+
+import functools
+
+import numpy as np
+
+import oracle as O
+import synth
+
+
+def small_iqu(seed=31, side=32, interval_len=4096, lam=256):
+    # 4 co-pointed detectors, H + V passes, 32x32 patch: 2^16 samples, 16 intervals
+    return synth.raster_iqu(side=side, spp=8, n_det=4, interval_len=interval_len, lam=lam,
+                            fknee_range=(0.5, 2.0), alpha_range=(1.0, 2.0), seed_key=seed)
+
+
+def ragged_iqu(seed=33):
+    """Uneven interval lengths (some shorter than the band, one of 1 sample,
+    lengths not multiples of any tile) on a 24x24 patch."""
+    sc = synth.raster_iqu(side=24, spp=8, n_det=2, interval_len=24 * 24 * 8, lam=100,
+                          fknee_range=(0.3, 3.0), alpha_range=(1.0, 2.0), seed_key=seed)
+    n = sc.n_samples
+    rng = np.random.default_rng(seed)
+    cuts = np.sort(rng.choice(np.arange(1, n - 1), size=17, replace=False))
+    cuts = np.concatenate([cuts, [cuts[3] + 1]]) if cuts[3] + 1 not in cuts else cuts
+    off = np.unique(np.concatenate([[0], cuts, [n - 1, n]])).astype(np.int64)
+    k = off.shape[0] - 1
+    sc.offsets = off
+    sc.sigma = rng.uniform(0.5, 2.0, k)
+    sc.fknee = rng.uniform(0.1, 3.0, k)
+    sc.alpha = rng.uniform(1.0, 2.0, k)
+    return sc
+
+
+@functools.lru_cache(maxsize=None)
+def problem(name):
+    sc = SCANS[name]()
+    return sc, O.Problem.from_scan(sc)
+
+
+SCANS = {
+    "small_iqu": small_iqu,
+    "ragged_iqu": ragged_iqu,
+    "cfg1": synth.cfg1_raster_i,
+}
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
