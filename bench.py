@@ -164,6 +164,14 @@ def main():
                    speedup_of_mixed_2lvl=float(np.mean(rtimes)) / t_step,
                    map_rel_diff_mixed_vs_fp64=map_diff, fp64_kernels=ax64)
 
+    # iteration counts of the other two combinations (one untimed run each, for context)
+    legs = {}
+    if not args.no_reference:
+        for prec, pc in (("fp64", "2lvl"), ("mixed", "bj")):
+            tt, _, ex, _ = step(prec, pc == "2lvl", pc)
+            legs[f"{prec}_{pc}"] = dict(time_s=tt, **ex)
+            log(f"{prec} {pc}: {tt * 1e3:.1f} ms {ex}")
+
     # roofline of the dominant kernel, from the live event timings of the last timed step
     n_ninv, t_ninv = prof["ninv32"]
     n_pt, t_pt = prof["pt32"]
@@ -203,7 +211,7 @@ def main():
                               "lambda=2048, mixed FP32/FP64 two-level PCG to 1e-8 incl. plan"),
                     n_samples=sc.n_samples, unknowns=extras[-1]["unknowns"],
                     tol=args.tol, parallelism="single GPU"),
-        breakdown=extras[-1], reference=ref, roofline=roof, cpu_baseline=cpu,
+        breakdown=extras[-1], reference=ref, other_legs=legs, roofline=roof, cpu_baseline=cpu,
     )
     print(json.dumps(out), flush=True)
 

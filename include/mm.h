@@ -61,7 +61,7 @@ enum mm_status {
 
 enum { MM_F32 = 0, MM_F64 = 1 };                               /* element types */
 enum { MM_WIN_GAUSS = 0, MM_WIN_GAUSS2 = 1, MM_WIN_RECT = 2 };  /* apodisation windows */
-enum { MM_FP64 = 0, MM_MIXED = 1 };                            /* arithmetic of the operator */
+enum { MM_FP64 = 0, MM_MIXED = 1, MM_MIXED_IR = 2 };          /* arithmetic of the operator */
 enum { MM_COARSE_NONE = 0, MM_COARSE_ZS = 1 };                 /* coarse space built by mm_plan */
 enum { MM_BJ = 0, MM_2LVL = 1 };                               /* preconditioner of mm_pcg_solve */
 
@@ -178,9 +178,14 @@ typedef struct {
  *   precision  MM_FP64: FP64 operator; convergence when the recursive and then the true
  *              relative residual are <= tol (otherwise the recursive residual is replaced
  *              by the true one and the iteration continues).
- *              MM_MIXED: iterative refinement; each step solves A d = r with the FP32
- *              operator (FP64 vectors and scalars) and updates x += d; the residual
- *              r = b - A x is formed with the FP64 operator; stops when it is <= tol.
+ *              MM_MIXED: PCG with the FP32 operator (FP64 vectors, scalars and coarse
+ *              solve) whose recursive residual is replaced by the FP64 true residual
+ *              b - A x each time it has dropped by 100x since the last replacement and
+ *              when it reaches tol (the search direction is kept); stops when the true
+ *              relative residual is <= tol.
+ *              MM_MIXED_IR: classic iterative refinement; each step solves A d = r with
+ *              the FP32-operator PCG from d = 0 and updates x += d; r = b - A x is formed
+ *              with the FP64 operator; stops when it is <= tol.
  *   tol        relative residual target (> 0);  max_iter: cap on total PCG iterations.
  * Returns MM_OK, MM_ERR_NOCONV, MM_ERR_BREAKDOWN (x holds the last iterate; info filled),
  * MM_ERR_ARG or MM_ERR_STATE.  Synchronises the plan's stream before returning. */

@@ -20,7 +20,7 @@ MM_OK, MM_ERR_ARG, MM_ERR_DEVICE, MM_ERR_RANK = 0, -1, -2, -3
 MM_ERR_NOT_SPD, MM_ERR_BREAKDOWN, MM_ERR_NOCONV, MM_ERR_STATE = -4, -5, -6, -7
 MM_F32, MM_F64 = 0, 1
 MM_WIN_GAUSS, MM_WIN_GAUSS2, MM_WIN_RECT = 0, 1, 2
-MM_FP64, MM_MIXED = 0, 1
+MM_FP64, MM_MIXED, MM_MIXED_IR = 0, 1, 2
 MM_COARSE_NONE, MM_COARSE_ZS = 0, 1
 MM_BJ, MM_2LVL = 0, 1
 
@@ -328,7 +328,8 @@ class Plan:
             info.history_cap = hist.shape[0]
         st = self._lib.mm_pcg_solve(self._h, _ptr(b), _ptr(x),
                                     MM_2LVL if precond == "2lvl" else MM_BJ,
-                                    MM_MIXED if precision == "mixed" else MM_FP64,
+                                    {"fp64": MM_FP64, "mixed": MM_MIXED,
+                                     "mixed_ir": MM_MIXED_IR}[precision],
                                     float(tol), int(max_iter), ctypes.byref(info))
         out = dict(status=st, iterations=info.iterations, outer_iterations=info.outer_iterations,
                    replacements=info.replacements, rel_residual=info.rel_residual,

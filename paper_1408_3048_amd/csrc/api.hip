@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "mm_device.h"
@@ -22,6 +23,39 @@ void set_error(const char* fmt, ...) {
 }
 
 void clear_error() { g_err.clear(); }
+
+static thread_local hipStream_t g_alloc_stream = nullptr;
+void set_alloc_stream(hipStream_t st) { g_alloc_stream = st; }
+hipStream_t alloc_stream() { return g_alloc_stream; }
+
+int pool_alloc(void** p, size_t bytes, hipStream_t st) {
+    static thread_local int configured_dev = -1;
+    int dev = 0;
+    MM_HIP(hipGetDevice(&dev));
+    if (configured_dev != dev) {
+        hipMemPool_t pool;
+        if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+            uint64_t thr = UINT64_MAX;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+        }
+        configured_dev = dev;
+    }
+    hipError_t e = hipMallocAsync(p, bytes, st);
+    if (e != hipSuccess) {
+        set_error("hipMallocAsync(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+        return MM_ERR_DEVICE;
+    }
+    return MM_OK;
+}
+
+void pool_free(void* p, hipStream_t st) { (void)hipFreeAsync(p, st); }
+
+// RAII: the stream for allocations made during one API call
+struct AllocStream {
+    hipStream_t prev;
+    explicit AllocStream(hipStream_t st) : prev(g_alloc_stream) { g_alloc_stream = st; }
+    ~AllocStream() { g_alloc_stream = prev; }
+};
 
 int prof_begin(mm_plan_t pl, int k, int tag) {
     if (!pl->prof_on) return MM_OK;
@@ -86,6 +120,9 @@ namespace {
 
 using clk = std::chrono::steady_clock;
 
+// mixed precision: replace the recursive residual each time it has dropped this much
+constexpr double kReplaceRatio = 1e-2;
+
 double ms_since(clk::time_point t0) {
     return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
 }
@@ -134,7 +171,8 @@ struct CoreResult {
 // PCG on A x = b from the x passed in.  op32: FP32 operator.  x_zero: x is zero (r = b).
 // replace: on recursive convergence test the FP64 true residual and replace r if needed.
 int pcg_core(mm_plan_t pl, const double* b, double* x, int pc, bool op32, bool x_zero, double tol,
-             int max_iter, bool replace, CoreResult* res, mm_solve_info* info, int hist_off) {
+             int max_iter, bool replace, CoreResult* res, mm_solve_info* info, int hist_off,
+             double replace_ratio = 0.0) {
     const int64_t n = nvec(pl);
     double* r = pl->vec[0].p;
     double* z = pl->vec[1].p;
@@ -182,6 +220,7 @@ int pcg_core(mm_plan_t pl, const double* b, double* x, int pc, bool op32, bool x
     }
     int i = 0;
     const int chunk = 4;
+    double last_rel = 1.0;
     while (i < max_iter) {
         const int i_end = std::min(max_iter, i + chunk);
         for (int it = i; it < i_end; ++it) {
@@ -200,7 +239,36 @@ int pcg_core(mm_plan_t pl, const double* b, double* x, int pc, bool op32, bool x
         }
         MM_TRY(read_scalars(pl));
         i = i_end;
-        if (!pl->h_sc->done) continue;
+        if (!pl->h_sc->done) {
+            // reliable update: the recursive residual has fallen by replace_ratio since the
+            // last replacement -> replace it by the FP64 true residual, keep p
+            if (replace_ratio > 0.0) {
+                const double rel = std::sqrt(pl->h_sc->rr) / pl->h_sc->bnorm;
+                if (rel < replace_ratio * last_rel) {
+                    const int ndone = pl->h_sc->iter;
+                    MM_TRY(apply_A64(pl, x, q, nullptr));
+                    MM_TRY(vec_axpby(pl, 1.0, b, -1.0, q, r));
+                    double rr = 0.0;
+                    MM_TRY(norm2(pl, r, &rr));
+                    last_rel = std::sqrt(rr) / pl->h_sc->bnorm;
+                    res->replacements++;
+                    if (last_rel <= tol) {
+                        res->iters = ndone;
+                        res->hist_len = ndone;
+                        res->status = MM_OK;
+                        return MM_OK;
+                    }
+                    PcgCtl c2 = ctl;
+                    c2.iter = ndone - 1;
+                    c2.check = 0;
+                    c2.hist = nullptr;
+                    MM_TRY(precond(pl, pc, r, z, c2));
+                    c2.rz_only = 1;
+                    MM_TRY(pcg_update_p(pl, p, z, c2));
+                }
+            }
+            continue;
+        }
         const int ndone = pl->h_sc->iter;
         prof_invalidate(pl, mark, ndone);
         res->iters = ndone;
@@ -220,6 +288,7 @@ int pcg_core(mm_plan_t pl, const double* b, double* x, int pc, bool op32, bool x
         double rr = 0.0;
         MM_TRY(norm2(pl, t, &rr));
         const double rel = std::sqrt(rr) / pl->h_sc->bnorm;
+        last_rel = rel;
         if (rel <= tol) {
             res->status = MM_OK;
             return MM_OK;
@@ -372,18 +441,30 @@ int mm_plan(mm_plan_t* out, int64_t n_samples, const int32_t* pix, const void* w
     pl->h_off.assign(interval_offsets, interval_offsets + n_intervals + 1);
     pl->h_psd.assign(psd, psd + n_intervals);
     pl->stream = (hipStream_t)opts->stream;
+    AllocStream alloc_scope(pl->stream);
     if (hipGetDevice(&pl->device) != hipSuccess) {
         set_error("no HIP device available");
         return fail(MM_ERR_DEVICE);
     }
     int s;
+    const bool verbose = std::getenv("MM_PLAN_TIMING") != nullptr;
+    auto tick = [&](const char* what) {
+        if (!verbose) return;
+        (void)hipStreamSynchronize(pl->stream);
+        std::fprintf(stderr, "[mm_plan] %-10s %8.3f ms\n", what, ms_since(t0));
+    };
     if ((s = build_pointing(pl, pix, weights, weights_dtype)) != MM_OK) return fail(s);
+    tick("pointing");
     if ((s = build_kernels(pl)) != MM_OK) return fail(s);
+    tick("taps");
     if ((s = build_tiling(pl, pl->fft64, true, opts->fft_len_f64)) != MM_OK) return fail(s);
+    tick("tiling64");
     const bool mixed = opts->precision == MM_MIXED;
     if (mixed && (s = build_tiling(pl, pl->fft32, false, opts->fft_len_f32)) != MM_OK)
         return fail(s);
+    tick("tiling32");
     if ((s = build_bj(pl)) != MM_OK) return fail(s);
+    tick("bj");
     const int64_t n = pl->n_obs * pl->n_s;
     if ((s = pl->tod64a.alloc(pl->n_t)) != MM_OK) return fail(s);
     if (mixed && (s = pl->tod32a.alloc(pl->n_t)) != MM_OK) return fail(s);
@@ -397,7 +478,9 @@ int mm_plan(mm_plan_t* out, int64_t n_samples, const int32_t* pix, const void* w
         return fail(MM_ERR_DEVICE);
     }
     if ((s = ensure_solver_buffers(pl, 1000)) != MM_OK) return fail(s);
+    tick("buffers");
     if (opts->coarse == MM_COARSE_ZS && (s = build_coarse(pl)) != MM_OK) return fail(s);
+    tick("coarse");
     if (hipStreamSynchronize(pl->stream) != hipSuccess) {
         set_error("device error during plan construction");
         return fail(MM_ERR_DEVICE);
@@ -410,7 +493,7 @@ int mm_plan(mm_plan_t* out, int64_t n_samples, const int32_t* pix, const void* w
 void mm_destroy(mm_plan_t pl) {
     if (!pl) return;
     (void)hipStreamSynchronize(pl->stream);
-    delete pl;
+    delete pl;  // buffers go back to the stream-ordered pool
 }
 
 int64_t mm_n_obs(mm_plan_t pl) { return pl ? pl->n_obs : -1; }
@@ -474,6 +557,7 @@ int mm_coarse_matrix(mm_plan_t pl, double* host_out, int64_t cap) {
 int mm_gemm_tn_f64(void* stream, const double* A, const double* B, int64_t n, int32_t ra,
                    int32_t rb, double* C) {
     clear_error();
+    AllocStream alloc_scope((hipStream_t)stream);
     if (!A || !B || !C || n < 4 || n % 4 || ra < 16 || rb < 16 || ra % 16 || rb % 16) {
         set_error("mm_gemm_tn_f64: n must be a positive multiple of 4, ra and rb multiples of 16");
         return MM_ERR_ARG;
@@ -587,11 +671,11 @@ int mm_pcg_solve(mm_plan_t pl, const double* b, double* x, int pc, int precision
         set_error("MM_2LVL needs a plan built with opts.coarse = MM_COARSE_ZS");
         return MM_ERR_STATE;
     }
-    if (precision != MM_FP64 && precision != MM_MIXED) {
-        set_error("precision must be MM_FP64 or MM_MIXED");
+    if (precision != MM_FP64 && precision != MM_MIXED && precision != MM_MIXED_IR) {
+        set_error("precision must be MM_FP64, MM_MIXED or MM_MIXED_IR");
         return MM_ERR_ARG;
     }
-    if (precision == MM_MIXED && pl->opts.precision != MM_MIXED) {
+    if (precision != MM_FP64 && pl->opts.precision != MM_MIXED) {
         set_error("mixed solve requested from a plan built with precision MM_FP64");
         return MM_ERR_STATE;
     }
@@ -604,6 +688,7 @@ int mm_pcg_solve(mm_plan_t pl, const double* b, double* x, int pc, int precision
         return MM_ERR_ARG;
     }
     const auto t0 = clk::now();
+    AllocStream alloc_scope(pl->stream);
     MM_TRY(ensure_solver_buffers(pl, max_iter));
     mm_solve_info loc{};
     if (!info) info = &loc;
@@ -613,9 +698,11 @@ int mm_pcg_solve(mm_plan_t pl, const double* b, double* x, int pc, int precision
     info->history_len = 0;
     int status = MM_OK;
     std::vector<double> hist_all;
-    if (precision == MM_FP64) {
+    if (precision == MM_FP64 || precision == MM_MIXED) {
+        const bool op32 = precision == MM_MIXED;
         CoreResult res;
-        MM_TRY(pcg_core(pl, b, x, pc, false, false, tol, max_iter, true, &res, info, 0));
+        MM_TRY(pcg_core(pl, b, x, pc, op32, false, tol, max_iter, true, &res, info, 0,
+                        op32 ? kReplaceRatio : 0.0));
         info->iterations = res.iters;
         info->outer_iterations = 1;
         info->replacements = res.replacements;

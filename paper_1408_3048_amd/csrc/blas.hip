@@ -67,6 +67,7 @@ __global__ __launch_bounds__(kVecThreads) void k_update_p(double* __restrict__ p
         ctl.rz_hist[ctl.iter + 1] = rz_new;
         ctl.sc->beta = beta;
     }
+    if (ctl.rz_only) return;
     for (int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kVecThreads)
         p[i] = ctl.first ? z[i] : z[i] + beta * p[i];

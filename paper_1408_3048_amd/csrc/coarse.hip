@@ -16,6 +16,9 @@
 // z = M_BD (r - (AZ) w) + Z w.
 #include <algorithm>
 #include <cmath>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <unordered_map>
 
@@ -105,6 +108,28 @@ __global__ void k_col_to_vec(const int32_t* __restrict__ rows, const double* __r
         out[(int64_t)rows[i] * ns] = vals[i];
 }
 
+// Z_S rows restricted to the kept columns: count pass (out == nullptr) or fill pass
+__global__ void k_csr_filter(const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                             const double* __restrict__ val, int64_t n_obs,
+                             const int32_t* __restrict__ colmap, const int64_t* __restrict__ optr,
+                             int64_t* __restrict__ cnt, int32_t* __restrict__ ocol,
+                             double* __restrict__ oval) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n_obs;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        int64_t o = optr ? optr[p] : 0;
+        for (int64_t e = ptr[p]; e < ptr[p + 1]; ++e) {
+            const int32_t a = colmap[col[e]];
+            if (a < 0) continue;
+            if (ocol) {
+                ocol[o] = a;
+                oval[o] = val[e];
+            }
+            ++o;
+        }
+        if (cnt) cnt[p] = o;
+    }
+}
+
 // dense Z_I, row-major [n_obs_pad][rp] from per-column entry lists
 __global__ void k_dense_z(const int64_t* __restrict__ cptr, const int32_t* __restrict__ rows,
                           const double* __restrict__ vals, int32_t r, int32_t rp,
@@ -177,12 +202,15 @@ __global__ void k_sum_parts(const double* __restrict__ part, int64_t m, int32_t 
     }
 }
 
-// v = Z^T r (one wave per kept column), optional convergence test in the prologue
-__global__ __launch_bounds__(256) void k_ztr(const int64_t* __restrict__ cptr,
+// v = Z^T r: each kept column's entries are split over `slices` waves whose partial sums
+// go to vpart[column][slice]; optional convergence test in the prologue
+__global__ __launch_bounds__(256) void k_ztr(const int64_t* __restrict__ cbeg,
+                                             const int64_t* __restrict__ cend,
                                              const int32_t* __restrict__ rows,
                                              const double* __restrict__ vals,
                                              const double* __restrict__ r, int ns, int32_t rk,
-                                             double* __restrict__ v, PcgCtl ctl) {
+                                             int32_t slices, double* __restrict__ vpart,
+                                             PcgCtl ctl) {
     __shared__ double red[256];
     if (ctl.part) {
         if (ctl.sc->done) return;
@@ -198,25 +226,32 @@ __global__ __launch_bounds__(256) void k_ztr(const int64_t* __restrict__ cptr,
         }
     }
     const int lane = threadIdx.x & 63;
-    const int32_t c = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (c >= rk) return;
+    const int64_t wv = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wv >= (int64_t)rk * slices) return;
+    const int32_t c = (int32_t)(wv / slices), sl = (int32_t)(wv % slices);
+    const int64_t e0 = cbeg[c], len = cend[c] - e0;
+    const int64_t a = e0 + len * sl / slices, b = e0 + len * (sl + 1) / slices;
     double s = 0.0;
-    for (int64_t e = cptr[c] + lane; e < cptr[c + 1]; e += 64)
-        s += vals[e] * r[(int64_t)rows[e] * ns];
+    for (int64_t e = a + lane; e < b; e += 64) s += vals[e] * r[(int64_t)rows[e] * ns];
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0) v[c] = s;
+    if (lane == 0) vpart[wv] = s;
 }
 
-// w = E^-1 v (one wave per row)
+// w = E^-1 v with v[c] = sum of the slice partials of column c (one wave per row)
 __global__ __launch_bounds__(256) void k_einv(const double* __restrict__ Einv,
-                                              const double* __restrict__ v, int32_t rk,
-                                              double* __restrict__ w, const PcgScalars* sc) {
+                                              const double* __restrict__ vpart, int32_t rk,
+                                              int32_t slices, double* __restrict__ w,
+                                              const PcgScalars* sc) {
     if (sc && sc->done) return;
     const int lane = threadIdx.x & 63;
     const int32_t a = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (a >= rk) return;
     double s = 0.0;
-    for (int32_t c = lane; c < rk; c += 64) s += Einv[(int64_t)a * rk + c] * v[c];
+    for (int32_t c = lane; c < rk; c += 64) {
+        double v = 0.0;
+        for (int32_t q = 0; q < slices; ++q) v += vpart[(int64_t)c * slices + q];
+        s += Einv[(int64_t)a * rk + c] * v;
+    }
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
     if (lane == 0) w[a] = s;
 }
@@ -369,6 +404,14 @@ int gemm_tn_f64(hipStream_t st, const double* A, const double* B, int64_t n, int
 
 int build_coarse(mm_plan_t pl) {
     hipStream_t st = pl->stream;
+    const bool verbose = std::getenv("MM_PLAN_TIMING") != nullptr;
+    const auto c0 = std::chrono::steady_clock::now();
+    auto tick = [&](const char* what) {
+        if (!verbose) return;
+        (void)hipStreamSynchronize(st);
+        std::fprintf(stderr, "[coarse ] %-10s %8.3f ms\n", what,
+                     std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - c0).count());
+    };
     Coarse& co = pl->co;
     const int64_t n_obs = pl->n_obs, ns = pl->n_s, nv = n_obs * ns;
     // Z_S in CSR form (per pixel, ascending interval)
@@ -454,6 +497,7 @@ int build_coarse(mm_plan_t pl) {
     }
     const int32_t rd = (int32_t)uniq.size();
     co.r_dedup = rd;
+    tick("zs+dedup");
     // AZ for the distinct columns
     const bool mixed = pl->opts.precision == MM_MIXED;
     DBuf<double> azd;
@@ -496,6 +540,7 @@ int build_coarse(mm_plan_t pl) {
             MM_TRY(apply_A64(pl, zc.p, azd.p + (size_t)u * nv, nullptr));
         }
     }
+    tick("AZ");
     // E = Z^T (AZ) on the matrix cores
     const int32_t rp = (rd + 15) / 16 * 16;
     const int64_t npad = (n_obs + 3) / 4 * 4;
@@ -522,6 +567,7 @@ int build_coarse(mm_plan_t pl) {
     for (int32_t a = 0; a < rd; ++a)
         for (int32_t b = 0; b < rd; ++b)
             E[(size_t)a * rd + b] = 0.5 * (Ep[(size_t)a * rp + b] + Ep[(size_t)b * rp + a]);
+    tick("E");
     // independent subset and E^-1 on it
     std::vector<int> sel = pivoted_cholesky_select(E, rd, pl->opts.rank_tol);
     const int32_t k = (int32_t)sel.size();
@@ -542,59 +588,59 @@ int build_coarse(mm_plan_t pl) {
     for (int32_t a = 0; a < k; ++a) co.cols[a] = uniq[sel[a]];
     MM_TRY(co.Einv.alloc((size_t)k * k));
     MM_HIP(hipMemcpyAsync(co.Einv.p, Einv.data(), Einv.size() * 8, hipMemcpyHostToDevice, st));
-    // kept AZ columns
-    if (mixed) {
-        MM_TRY(co.AZ32.alloc((size_t)k * nv));
-        for (int32_t a = 0; a < k; ++a)
-            MM_HIP(hipMemcpyAsync(co.AZ32.p + (size_t)a * nv, azf.p + (size_t)sel[a] * nv, nv * 4,
-                                  hipMemcpyDeviceToDevice, st));
-    } else {
-        MM_TRY(co.AZ64.alloc((size_t)k * nv));
-        for (int32_t a = 0; a < k; ++a)
-            MM_HIP(hipMemcpyAsync(co.AZ64.p + (size_t)a * nv, azd.p + (size_t)sel[a] * nv, nv * 8,
-                                  hipMemcpyDeviceToDevice, st));
-    }
-    // kept columns: CSC and CSR
-    std::vector<int64_t> kptr(k + 1, 0);
-    std::vector<int32_t> krow;
-    std::vector<double> kval;
-    std::vector<int32_t> colmap(K, -1);
+    // kept AZ columns: compact in place (sel is increasing and sel[a] >= a, so a source
+    // column is never overwritten before it is copied)
     for (int32_t a = 0; a < k; ++a) {
-        const int32_t j = co.cols[a];
-        colmap[j] = a;
-        krow.insert(krow.end(), crow.begin() + ccnt[j], crow.begin() + ccnt[j + 1]);
-        kval.insert(kval.end(), cval.begin() + ccnt[j], cval.begin() + ccnt[j + 1]);
-        kptr[a + 1] = (int64_t)krow.size();
+        if (sel[a] == a) continue;
+        if (mixed)
+            MM_HIP(hipMemcpyAsync(azf.p + (size_t)a * nv, azf.p + (size_t)sel[a] * nv, nv * 4,
+                                  hipMemcpyDeviceToDevice, st));
+        else
+            MM_HIP(hipMemcpyAsync(azd.p + (size_t)a * nv, azd.p + (size_t)sel[a] * nv, nv * 8,
+                                  hipMemcpyDeviceToDevice, st));
     }
-    std::vector<int64_t> rptr(n_obs + 1, 0);
-    std::vector<int32_t> rcol;
-    std::vector<double> rval;
-    for (int64_t p = 0; p < n_obs; ++p) {
-        for (int64_t e = hptr[p]; e < hptr[p + 1]; ++e) {
-            const int32_t a = colmap[hcol[e]];
-            if (a >= 0) {
-                rcol.push_back(a);
-                rval.push_back(hval[e]);
-            }
-        }
-        rptr[p + 1] = (int64_t)rcol.size();
+    if (mixed) co.AZ32.swap(azf);
+    else co.AZ64.swap(azd);
+    // kept columns by column: entry ranges into the distinct-column lists
+    std::vector<int64_t> kb(k), ke(k);
+    int64_t maxlen = 1;
+    for (int32_t a = 0; a < k; ++a) {
+        kb[a] = uptr[sel[a]];
+        ke[a] = uptr[sel[a] + 1];
+        maxlen = std::max(maxlen, ke[a] - kb[a]);
     }
-    MM_TRY(co.csc_ptr.alloc(k + 1));
-    MM_TRY(co.csc_row.alloc(krow.size()));
-    MM_TRY(co.csc_val.alloc(kval.size()));
+    co.csc_row.swap(drow);
+    co.csc_val.swap(dval);
+    MM_TRY(co.csc_beg.alloc(k));
+    MM_TRY(co.csc_end.alloc(k));
+    MM_HIP(hipMemcpyAsync(co.csc_beg.p, kb.data(), k * 8, hipMemcpyHostToDevice, st));
+    MM_HIP(hipMemcpyAsync(co.csc_end.p, ke.data(), k * 8, hipMemcpyHostToDevice, st));
+    // kept columns by pixel (CSR), filtered on the device from the full Z_S rows
+    std::vector<int32_t> colmap(K, -1);
+    for (int32_t a = 0; a < k; ++a) colmap[co.cols[a]] = a;
+    DBuf<int32_t> dmap;
+    DBuf<int64_t> kcnt;
+    MM_TRY(dmap.alloc(K));
+    MM_TRY(kcnt.alloc(n_obs));
+    MM_HIP(hipMemcpyAsync(dmap.p, colmap.data(), K * 4, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_csr_filter, dim3(grid_for(n_obs)), dim3(256), 0, st, ptr.p, col.p, val.p,
+                       n_obs, dmap.p, (const int64_t*)nullptr, kcnt.p, (int32_t*)nullptr,
+                       (double*)nullptr);
+    MM_HIP(hipGetLastError());
     MM_TRY(co.csr_ptr.alloc(n_obs + 1));
-    MM_TRY(co.csr_col.alloc(std::max<size_t>(1, rcol.size())));
-    MM_TRY(co.csr_val.alloc(std::max<size_t>(1, rval.size())));
-    MM_HIP(hipMemcpyAsync(co.csc_ptr.p, kptr.data(), (k + 1) * 8, hipMemcpyHostToDevice, st));
-    MM_HIP(hipMemcpyAsync(co.csc_row.p, krow.data(), krow.size() * 4, hipMemcpyHostToDevice, st));
-    MM_HIP(hipMemcpyAsync(co.csc_val.p, kval.data(), kval.size() * 8, hipMemcpyHostToDevice, st));
-    MM_HIP(hipMemcpyAsync(co.csr_ptr.p, rptr.data(), (n_obs + 1) * 8, hipMemcpyHostToDevice, st));
-    if (!rcol.empty()) {
-        MM_HIP(hipMemcpyAsync(co.csr_col.p, rcol.data(), rcol.size() * 4, hipMemcpyHostToDevice, st));
-        MM_HIP(hipMemcpyAsync(co.csr_val.p, rval.data(), rval.size() * 8, hipMemcpyHostToDevice, st));
-    }
+    MM_TRY(scan_exclusive_i64(kcnt.p, co.csr_ptr.p, n_obs, st));
+    int64_t kn = 0;
+    MM_HIP(hipMemcpy(&kn, co.csr_ptr.p + n_obs, 8, hipMemcpyDeviceToHost));
+    MM_TRY(co.csr_col.alloc(std::max<int64_t>(1, kn)));
+    MM_TRY(co.csr_val.alloc(std::max<int64_t>(1, kn)));
+    hipLaunchKernelGGL(k_csr_filter, dim3(grid_for(n_obs)), dim3(256), 0, st, ptr.p, col.p, val.p,
+                       n_obs, dmap.p, (const int64_t*)co.csr_ptr.p, (int64_t*)nullptr,
+                       co.csr_col.p, co.csr_val.p);
+    MM_HIP(hipGetLastError());
     MM_TRY(co.v.alloc(k));
     MM_TRY(co.w.alloc(k));
+    co.zslices = (int)std::min<int64_t>(256, std::max<int64_t>(1, (maxlen + 511) / 512));
+    MM_TRY(co.vpart.alloc((size_t)k * co.zslices));
     MM_HIP(hipStreamSynchronize(st));
     pl->has_coarse = true;
     return MM_OK;
@@ -604,10 +650,11 @@ int twolvl_apply(mm_plan_t pl, const double* r, double* z, const PcgCtl& ctl) {
     Coarse& co = pl->co;
     hipStream_t st = pl->stream;
     const int32_t k = co.r_eff;
-    hipLaunchKernelGGL(k_ztr, dim3((k + 3) / 4), dim3(256), 0, st, co.csc_ptr.p, co.csc_row.p,
-                       co.csc_val.p, r, pl->n_s, k, co.v.p, ctl);
-    hipLaunchKernelGGL(k_einv, dim3((k + 3) / 4), dim3(256), 0, st, co.Einv.p, co.v.p, k, co.w.p,
-                       ctl.part ? ctl.sc : nullptr);
+    const int64_t nw = (int64_t)k * co.zslices;
+    hipLaunchKernelGGL(k_ztr, dim3((nw + 3) / 4), dim3(256), 0, st, co.csc_beg.p, co.csc_end.p,
+                       co.csc_row.p, co.csc_val.p, r, pl->n_s, k, co.zslices, co.vpart.p, ctl);
+    hipLaunchKernelGGL(k_einv, dim3((k + 3) / 4), dim3(256), 0, st, co.Einv.p, co.vpart.p, k,
+                       co.zslices, co.w.p, ctl.part ? ctl.sc : nullptr);
     const size_t shm = (size_t)k * sizeof(double);
     if (pl->n_s == 3) {
         if (co.AZ32.p)

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/mm.h"
@@ -32,26 +33,41 @@ void clear_error();
     } while (0)
 
 // ---------------------------------------------------------------- device buffers
+// Device buffers are stream-ordered allocations (hipMallocAsync) from the device's
+// default memory pool, whose release threshold is raised at first use so that memory
+// freed by one plan is reused by the next without returning to the driver.  The stream
+// is the one current for the calling API entry (set_alloc_stream).
+void set_alloc_stream(hipStream_t st);
+hipStream_t alloc_stream();
+int pool_alloc(void** p, size_t bytes, hipStream_t st);
+void pool_free(void* p, hipStream_t st);
+
 template <typename T>
 struct DBuf {
     T* p = nullptr;
     size_t n = 0;
+    hipStream_t st = nullptr;
     int alloc(size_t count) {
         release();
         n = count;
         if (count == 0) return MM_OK;
-        hipError_t e = hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T));
-        if (e != hipSuccess) {
+        st = alloc_stream();
+        const int s = pool_alloc(reinterpret_cast<void**>(&p), count * sizeof(T), st);
+        if (s != MM_OK) {
             p = nullptr;
-            set_error("hipMalloc(%zu bytes) failed: %s", count * sizeof(T), hipGetErrorString(e));
-            return MM_ERR_DEVICE;
+            n = 0;
         }
-        return MM_OK;
+        return s;
     }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) pool_free(p, st);
         p = nullptr;
         n = 0;
+    }
+    void swap(DBuf& o) {
+        std::swap(p, o.p);
+        std::swap(n, o.n);
+        std::swap(st, o.st);
     }
     ~DBuf() { release(); }
     DBuf() = default;
@@ -95,6 +111,7 @@ struct PcgCtl {
     int iter = 0;               // iteration index
     int check = 0;              // preconditioner prologue tests ||r|| <= tol ||b||
     int first = 0;              // update_p: p = z (no beta)
+    int rz_only = 0;            // update_p: only record r^T z (after a residual replacement)
 };
 
 struct Coarse {
@@ -105,13 +122,15 @@ struct Coarse {
     DBuf<int64_t> csr_ptr;           // [n_obs+1] kept-column entries per pixel
     DBuf<int32_t> csr_col;
     DBuf<double> csr_val;
-    DBuf<int64_t> csc_ptr;           // [r_eff+1] entries per kept column
-    DBuf<int32_t> csc_row;           // compact pixel
+    DBuf<int64_t> csc_beg, csc_end;  // [r_eff] entry range of every kept column
+    DBuf<int32_t> csc_row;           // compact pixel (entries of all distinct columns)
     DBuf<double> csc_val;
     DBuf<double> AZ64;               // [r_eff][n_obs*n_s] column-major (FP64 plans)
     DBuf<float> AZ32;                // same (mixed plans)
     DBuf<double> Einv;               // [r_eff][r_eff] row-major
     DBuf<double> v, w;               // coarse work vectors [r_eff]
+    int zslices = 1;                 // waves per column in Z^T r
+    DBuf<double> vpart;              // [r_eff][zslices] partial sums of Z^T r
 };
 
 }  // namespace mm
@@ -184,6 +203,8 @@ constexpr int kVecThreads = 256;
 
 // ---- sort.hip
 int build_pointing(mm_plan_t pl, const int32_t* pix, const void* weights, int wdtype);
+// out[0..n] = exclusive scan of in[0..n-1] (int64), out[n] = total; synchronises st
+int scan_exclusive_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t st);
 
 // ---- toeplitz.hip
 int build_kernels(mm_plan_t pl);

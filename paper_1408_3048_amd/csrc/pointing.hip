@@ -8,13 +8,123 @@
 namespace mm {
 namespace {
 
-// x[p, s] = sum_{t in p} W[t, s] z_t.  Each wave owns a contiguous range of
-// whole pixels (about 2048 samples) and walks it in chunks of 64 sorted
-// samples: every lane forms W_t z_t for one sample, a segmented inclusive
-// scan over the wave (segment starts are flagged by the head bitmask) sums
-// the runs of each pixel, and the lane at a segment's end writes the total.
-// Segments that straddle chunks carry their partial sum into the next chunk.
-// The summation order is fixed by the plan, so results are deterministic.
+// Wave-level segmented reduction over pixel-sorted samples.
+//
+// A wave owns the sorted samples [i0, i1) of whole pixels p0, p0+1, ... and walks
+// them in chunks of 64*E samples aligned to E: lane l holds samples c + E l + e
+// (e < E), loaded with aligned vector loads so E gathers are in flight per lane.
+// Each lane first sums its own samples segment by segment, then one segmented
+// inclusive scan over the 64 lane summaries (flag: the lane holds a segment
+// start) gives every lane the partial sum entering it; the sample at a pixel's
+// last position emits the pixel total.  A segment left open at the end of a
+// chunk carries its sum into the next chunk.  The order of additions is fixed by
+// the plan, so results are deterministic; samples outside [i0, i1) are zeros.
+// `load(base, valid, v)` fills v[e][.] for the E samples; `emit(pixel, val)`.
+template <typename T, int NV, int E, class Load, class Emit>
+__device__ __forceinline__ void seg_reduce(int64_t i0, int64_t i1, int64_t p0,
+                                           const unsigned long long* __restrict__ heads,
+                                           Load&& load, Emit&& emit) {
+    static_assert(64 % E == 0, "E must divide 64");
+    const int lane = threadIdx.x & 63;
+    T carry[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) carry[q] = (T)0;
+    int64_t pprev = p0 - 1;
+    for (int64_t c = i0 & ~(int64_t)(E - 1); c < i1; c += 64 * E) {
+        const int64_t base = c + (int64_t)E * lane;
+        bool valid[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) valid[e] = base + e >= i0 && base + e < i1;
+        uint32_t hb = 0;
+        if (base < i1) hb = (uint32_t)(heads[base >> 6] >> (base & 63)) & ((1u << E) - 1u);
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            if (!valid[e]) hb &= ~(1u << e);
+        T v[E][NV];
+        load(base, valid, v);
+        // lane-local segmented prefix sums
+        T sl[E][NV];
+        T run[NV];
+        bool seen[E];
+        bool any = false;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const bool h = (hb >> e) & 1u;
+#pragma unroll
+            for (int q = 0; q < NV; ++q) run[q] = (e == 0 || h) ? v[e][q] : run[q] + v[e][q];
+            any = any || h;
+            seen[e] = any;
+#pragma unroll
+            for (int q = 0; q < NV; ++q) sl[e][q] = run[q];
+        }
+        // segmented inclusive scan over lanes of (any, run)
+        T acc[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) acc[q] = run[q];
+        int f = any ? 1 : 0;
+        int hc = __popc(hb), hcs = hc;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            T u[NV];
+#pragma unroll
+            for (int q = 0; q < NV; ++q) u[q] = __shfl_up(acc[q], d);
+            const int fu = __shfl_up(f, d);
+            const int cu = __shfl_up(hcs, d);
+            if (lane >= d) {
+                if (!f) {
+#pragma unroll
+                    for (int q = 0; q < NV; ++q) acc[q] += u[q];
+                }
+                f |= fu;
+                hcs += cu;
+            }
+        }
+        // partial sum entering this lane (from earlier lanes and the previous chunk)
+        T pre[NV];
+        int fex = __shfl_up(f, 1);
+#pragma unroll
+        for (int q = 0; q < NV; ++q) pre[q] = __shfl_up(acc[q], 1);
+        if (lane == 0) {
+            fex = 0;
+#pragma unroll
+            for (int q = 0; q < NV; ++q) pre[q] = (T)0;
+        }
+        if (!fex) {
+#pragma unroll
+            for (int q = 0; q < NV; ++q) pre[q] += carry[q];
+        }
+        // segment ends and totals
+        bool next_head_last = false;
+        const int64_t il = base + E;
+        if (valid[E - 1] && il < i1) next_head_last = (heads[il >> 6] >> (il & 63)) & 1ull;
+        int64_t pix = pprev + (hcs - hc);
+        T last[NV];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if ((hb >> e) & 1u) ++pix;
+            T tot[NV];
+#pragma unroll
+            for (int q = 0; q < NV; ++q) tot[q] = seen[e] ? sl[e][q] : sl[e][q] + pre[q];
+            const int64_t i = base + e;
+            bool end = false;
+            if (valid[e]) {
+                if (i + 1 == i1) end = true;
+                else if (e < E - 1) end = (hb >> (e + 1)) & 1u;
+                else end = next_head_last;
+            }
+            if (end) emit(pix, tot);
+            if (e == E - 1) {
+#pragma unroll
+                for (int q = 0; q < NV; ++q) last[q] = (valid[e] && !end) ? tot[q] : (T)0;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NV; ++q) carry[q] = __shfl(last[q], 63);
+        pprev += __shfl(hcs, 63);
+    }
+}
+
+// x[p, s] = sum_{t in p} W[t, s] z_t (P^T), E = 4 samples per lane
 template <typename T, int NS>
 __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ perm,
                                                  const T* __restrict__ ws, const T* __restrict__ z,
@@ -23,71 +133,58 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ per
                                                  const int64_t* __restrict__ seg, int64_t n_waves,
                                                  double* __restrict__ out,
                                                  const int* __restrict__ done) {
+    constexpr int E = 4;
     if (done && *done) return;
-    const int lane = threadIdx.x & 63;
     const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (w >= n_waves) return;
     const int32_t p0 = wave_pix[w], p1 = wave_pix[w + 1];
     if (p0 >= p1) return;
-    const int64_t i0 = seg[p0], i1 = seg[p1];
-    T carry[NS];
+    const int64_t i1 = seg[p1];
+    auto load = [&](int64_t base, const bool* valid, T (*v)[NS]) {
+        if (base >= i1) {  // whole lane past the range: no loads
 #pragma unroll
-    for (int s = 0; s < NS; ++s) carry[s] = (T)0;
-    int64_t pprev = (int64_t)p0 - 1;
-    const unsigned long long le = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
-    for (int64_t c = i0; c < i1; c += 64) {
-        const int64_t i = c + lane;
-        const bool valid = i < i1;
-        T v[NS];
-        bool head = false, end = false;
-        if (valid) {
-            const int64_t t = perm[i];
-            const T zt = z[t];
-            v[0] = zt;
-            if constexpr (NS == 3) {
-                v[1] = ws[2 * i] * zt;
-                v[2] = ws[2 * i + 1] * zt;
+            for (int e = 0; e < E; ++e)
+#pragma unroll
+                for (int q = 0; q < NS; ++q) v[e][q] = (T)0;
+            return;
+        }
+        // aligned vector loads; perm and ws carry a zeroed tail of 8 samples
+        const int4 t4 = *reinterpret_cast<const int4*>(perm + base);
+        const int tt[4] = {t4.x, t4.y, t4.z, t4.w};
+        T zz[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) zz[e] = valid[e] ? z[tt[e]] : (T)0;
+        if constexpr (NS == 3) {
+            T wv[2 * E];
+            if constexpr (sizeof(T) == 4) {
+                const float4 a = *reinterpret_cast<const float4*>(ws + 2 * base);
+                const float4 b = *reinterpret_cast<const float4*>(ws + 2 * base + 4);
+                wv[0] = a.x; wv[1] = a.y; wv[2] = a.z; wv[3] = a.w;
+                wv[4] = b.x; wv[5] = b.y; wv[6] = b.z; wv[7] = b.w;
+            } else {
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const double2 a = *reinterpret_cast<const double2*>(ws + 2 * (base + e));
+                    wv[2 * e] = a.x;
+                    wv[2 * e + 1] = a.y;
+                }
             }
-            head = (heads[i >> 6] >> (i & 63)) & 1ull;
-            const int64_t i2 = i + 1;
-            end = (i2 == i1) || ((heads[i2 >> 6] >> (i2 & 63)) & 1ull);
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                v[e][0] = zz[e];
+                v[e][1] = wv[2 * e] * zz[e];
+                v[e][2] = wv[2 * e + 1] * zz[e];
+            }
         } else {
 #pragma unroll
-            for (int s = 0; s < NS; ++s) v[s] = (T)0;
+            for (int e = 0; e < E; ++e) v[e][0] = zz[e];
         }
-        const unsigned long long hm = __ballot(head);
-        int f = head ? 1 : 0;
+    };
+    auto emit = [&](int64_t pix, const T* tot) {
 #pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            T u[NS];
-#pragma unroll
-            for (int s = 0; s < NS; ++s) u[s] = __shfl_up(v[s], d);
-            const int fu = __shfl_up(f, d);
-            if (lane >= d) {
-                if (!f) {
-#pragma unroll
-                    for (int s = 0; s < NS; ++s) v[s] += u[s];
-                }
-                f |= fu;
-            }
-        }
-        const bool cont = (hm & le) == 0ull;
-        const int64_t pix = pprev + __popcll(hm & le);
-        T tot[NS];
-#pragma unroll
-        for (int s = 0; s < NS; ++s) tot[s] = cont ? v[s] + carry[s] : v[s];
-        if (valid && end) {
-#pragma unroll
-            for (int s = 0; s < NS; ++s) out[pix * NS + s] = (double)tot[s];
-        }
-        const int open63 = __shfl((valid && !end) ? 1 : 0, 63);
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const T c63 = __shfl(tot[s], 63);
-            carry[s] = open63 ? c63 : (T)0;
-        }
-        pprev = __shfl(pix, 63);
-    }
+        for (int q = 0; q < NS; ++q) out[pix * NS + q] = (double)tot[q];
+    };
+    seg_reduce<T, NS, E>(seg[p0], i1, p0, heads, load, emit);
 }
 
 // y_t = sum_s W[t, s] x[c(t), s]
@@ -116,38 +213,52 @@ __device__ __forceinline__ int32_t interval_of(const int64_t* __restrict__ lo, i
     return a;
 }
 
-// B_p = sum_{t in p} t_0^{(j(t))} W_t W_t^T, summed in ascending t; inverse and
-// reciprocal 1-norm condition number.  bad[0] receives the smallest failing pixel.
-__global__ void k_bj_build(const int32_t* __restrict__ perm, const double* __restrict__ ws,
-                           const int64_t* __restrict__ seg, int64_t n_obs, int ns,
-                           const int64_t* __restrict__ int_lo, int32_t n_int,
-                           const int32_t* __restrict__ int_kern, const double* __restrict__ t0,
-                           double rcond_min, double* __restrict__ bj, int* __restrict__ bad,
-                           double* __restrict__ rc_out) {
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_obs;
-         c += (int64_t)gridDim.x * blockDim.x) {
-        double b00 = 0, b01 = 0, b02 = 0, b11 = 0, b12 = 0, b22 = 0;
-        for (int64_t i = seg[c]; i < seg[c + 1]; ++i) {
-            const int64_t t = perm[i];
+// B_p = sum_{t in p} t_0^{(j(t))} W_t W_t^T (P^T diag(N^-1) P), accumulated in FP64 with
+// the segmented reduction of P^T; the lane at a pixel's last sample inverts the block
+// and tests its reciprocal 1-norm condition number.  bad[0] receives the smallest
+// failing pixel.
+template <int NV>
+__global__ __launch_bounds__(256) void k_bj_build(
+    const int32_t* __restrict__ perm, const double* __restrict__ ws,
+    const unsigned long long* __restrict__ heads, const int32_t* __restrict__ wave_pix,
+    const int64_t* __restrict__ seg, int64_t n_waves, const int64_t* __restrict__ int_lo,
+    int32_t n_int, const int32_t* __restrict__ int_kern, const double* __restrict__ t0,
+    double rcond_min, double* __restrict__ bj, int* __restrict__ bad, double* __restrict__ rc_out) {
+    constexpr int E = 4;
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= n_waves) return;
+    const int32_t p0 = wave_pix[w], p1 = wave_pix[w + 1];
+    if (p0 >= p1) return;
+    auto load = [&](int64_t base, const bool* valid, double (*v)[NV]) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if (!valid[e]) {
+#pragma unroll
+                for (int q = 0; q < NV; ++q) v[e][q] = 0.0;
+                continue;
+            }
+            const int64_t t = perm[base + e];
             const double d = t0[int_kern[interval_of(int_lo, n_int, t)]];
-            if (ns == 3) {
-                const double u = ws[2 * i], v = ws[2 * i + 1];
-                b00 += d;
-                b01 += d * u;
-                b02 += d * v;
-                b11 += d * u * u;
-                b12 += d * u * v;
-                b22 += d * v * v;
+            if constexpr (NV == 6) {
+                const double a = ws[2 * (base + e)], b = ws[2 * (base + e) + 1];
+                v[e][0] = d;
+                v[e][1] = d * a;
+                v[e][2] = d * b;
+                v[e][3] = d * a * a;
+                v[e][4] = d * a * b;
+                v[e][5] = d * b * b;
             } else {
-                b00 += d;
+                v[e][0] = d;
             }
         }
+    };
+    auto emit = [&](int64_t c, const double* B) {
         double rc;
-        if (ns == 1) {
-            bj[c] = 1.0 / b00;
-            rc = b00 > 0.0 ? 1.0 : 0.0;
+        if constexpr (NV == 1) {
+            bj[c] = 1.0 / B[0];
+            rc = B[0] > 0.0 ? 1.0 : 0.0;
         } else {
-            // inverse of the symmetric block by cofactors
+            const double b00 = B[0], b01 = B[1], b02 = B[2], b11 = B[3], b12 = B[4], b22 = B[5];
             const double c00 = b11 * b22 - b12 * b12;
             const double c01 = b02 * b12 - b01 * b22;
             const double c02 = b01 * b12 - b02 * b11;
@@ -174,7 +285,8 @@ __global__ void k_bj_build(const int32_t* __restrict__ perm, const double* __res
         }
         if (rc_out) rc_out[c] = rc;
         if (!(rc >= rcond_min)) atomicMin(bad, (int)c);
-    }
+    };
+    seg_reduce<double, NV, E>(seg[p0], seg[p1], p0, heads, load, emit);
 }
 
 // z = M_BD r (+ partial r^T z; optional convergence test on ||r|| in the prologue)
@@ -273,9 +385,17 @@ int build_bj(mm_plan_t pl) {
     MM_TRY(rc.alloc(pl->n_obs));
     const int big = 0x7fffffff;
     MM_HIP(hipMemcpyAsync(bad.p, &big, sizeof(int), hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_bj_build, dim3(grid_for(pl->n_obs, 128)), dim3(128), 0, st, pl->perm.p,
-                       pl->ws64.p, pl->seg.p, pl->n_obs, pl->n_s, pl->int_lo.p, pl->n_int,
-                       pl->int_kern.p, pl->kern_t0.p, pl->opts.rcond_min, pl->bj.p, bad.p, rc.p);
+    const int64_t nb = (pl->n_waves + 3) / 4;
+    if (pl->n_s == 3)
+        hipLaunchKernelGGL(k_bj_build<6>, dim3(nb), dim3(256), 0, st, pl->perm.p, pl->ws64.p,
+                           (const unsigned long long*)pl->heads.p, pl->wave_pix.p, pl->seg.p,
+                           pl->n_waves, pl->int_lo.p, pl->n_int, pl->int_kern.p, pl->kern_t0.p,
+                           pl->opts.rcond_min, pl->bj.p, bad.p, rc.p);
+    else
+        hipLaunchKernelGGL(k_bj_build<1>, dim3(nb), dim3(256), 0, st, pl->perm.p, pl->ws64.p,
+                           (const unsigned long long*)pl->heads.p, pl->wave_pix.p, pl->seg.p,
+                           pl->n_waves, pl->int_lo.p, pl->n_int, pl->int_kern.p, pl->kern_t0.p,
+                           pl->opts.rcond_min, pl->bj.p, bad.p, rc.p);
     MM_HIP(hipGetLastError());
     int h_bad = big;
     MM_HIP(hipMemcpyAsync(&h_bad, bad.p, sizeof(int), hipMemcpyDeviceToHost, st));

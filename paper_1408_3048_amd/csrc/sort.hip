@@ -10,6 +10,7 @@ namespace mm {
 namespace {
 
 constexpr int kScanThreads = 256;
+constexpr int64_t kSortedPad = 8;
 constexpr int kScanItems = 4;
 constexpr int kScanTile = kScanThreads * kScanItems;
 
@@ -81,6 +82,7 @@ int scan_exclusive(const TI* in, int64_t* out, int64_t n, hipStream_t st) {
 }
 
 __global__ void k_minmax(const int32_t* __restrict__ pix, int64_t n, int* __restrict__ mm2) {
+    __shared__ int slo[4], shi[4];
     int lo = INT_MAX, hi = INT_MIN;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
          t += (int64_t)gridDim.x * blockDim.x) {
@@ -93,15 +95,40 @@ __global__ void k_minmax(const int32_t* __restrict__ pix, int64_t n, int* __rest
         hi = max(hi, __shfl_xor(hi, o));
     }
     if ((threadIdx.x & 63) == 0) {
+        slo[threadIdx.x >> 6] = lo;
+        shi[threadIdx.x >> 6] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+            lo = min(lo, slo[w]);
+            hi = max(hi, shi[w]);
+        }
         atomicMin(&mm2[0], lo);
         atomicMax(&mm2[1], hi);
     }
 }
 
+// hit counts: every thread counts runs of equal pixel ids in 8 consecutive samples and
+// adds each run once (scans revisit a pixel for several consecutive samples)
 __global__ void k_hist(const int32_t* __restrict__ pix, int64_t n, int32_t* __restrict__ h) {
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
-         t += (int64_t)gridDim.x * blockDim.x)
-        atomicAdd(&h[pix[t]], 1);
+    const int64_t ng = (n + 7) / 8;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ng;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t0 = 8 * g, t1 = t0 + 8 < n ? t0 + 8 : n;
+        int cur = pix[t0], cnt = 1;
+        for (int64_t t = t0 + 1; t < t1; ++t) {
+            const int v = pix[t];
+            if (v == cur) {
+                ++cnt;
+            } else {
+                atomicAdd(&h[cur], cnt);
+                cur = v;
+                cnt = 1;
+            }
+        }
+        atomicAdd(&h[cur], cnt);
+    }
 }
 
 __global__ void k_flags(const int32_t* __restrict__ h, int64_t n, int32_t* __restrict__ f) {
@@ -252,6 +279,10 @@ inline int grid_for(int64_t n, int threads = 256, int cap = 65536) {
 
 }  // namespace
 
+int scan_exclusive_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t st) {
+    return scan_exclusive<int64_t>(in, out, n, st);
+}
+
 int build_pointing(mm_plan_t pl, const int32_t* pix, const void* weights, int wdtype) {
     hipStream_t st = pl->stream;
     const int64_t n = pl->n_t;
@@ -260,7 +291,7 @@ int build_pointing(mm_plan_t pl, const int32_t* pix, const void* weights, int wd
     MM_TRY(mm2.alloc(2));
     const int init[2] = {INT_MAX, INT_MIN};
     MM_HIP(hipMemcpyAsync(mm2.p, init, sizeof(init), hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_minmax, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, pix, n, mm2.p);
+    hipLaunchKernelGGL(k_minmax, dim3(grid_for(n, 256, 1024)), dim3(256), 0, st, pix, n, mm2.p);
     MM_HIP(hipGetLastError());
     int h_mm[2];
     MM_HIP(hipMemcpyAsync(h_mm, mm2.p, sizeof(h_mm), hipMemcpyDeviceToHost, st));
@@ -278,7 +309,7 @@ int build_pointing(mm_plan_t pl, const int32_t* pix, const void* weights, int wd
     MM_TRY(cmap.alloc(pl->n_pix));
     MM_TRY(pos.alloc(pl->n_pix + 1));
     MM_HIP(hipMemsetAsync(hfull.p, 0, pl->n_pix * sizeof(int32_t), st));
-    hipLaunchKernelGGL(k_hist, dim3(grid_for(n)), dim3(256), 0, st, pix, n, hfull.p);
+    hipLaunchKernelGGL(k_hist, dim3(grid_for((n + 7) / 8)), dim3(256), 0, st, pix, n, hfull.p);
     hipLaunchKernelGGL(k_flags, dim3(grid_for(pl->n_pix)), dim3(256), 0, st, hfull.p, pl->n_pix,
                        flags.p);
     MM_HIP(hipGetLastError());
@@ -330,7 +361,9 @@ int build_pointing(mm_plan_t pl, const int32_t* pix, const void* weights, int wd
         std::swap(kin, kout);
         std::swap(vin, vout);
     }
-    MM_TRY(pl->perm.alloc(n));
+    // sorted arrays carry a zeroed tail of kSortedPad samples for aligned vector loads
+    MM_TRY(pl->perm.alloc(n + kSortedPad));
+    MM_HIP(hipMemsetAsync(pl->perm.p + n, 0, kSortedPad * sizeof(int32_t), st));
     MM_HIP(hipMemcpyAsync(pl->perm.p, vin, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
     MM_HIP(hipStreamSynchronize(st));
     k1.release();
@@ -355,10 +388,12 @@ int build_pointing(mm_plan_t pl, const int32_t* pix, const void* weights, int wd
     if (pl->n_s == 3) {
         const bool mixed = pl->opts.precision == MM_MIXED;
         MM_TRY(pl->w64.alloc(2 * n));
-        MM_TRY(pl->ws64.alloc(2 * n));
+        MM_TRY(pl->ws64.alloc(2 * (n + kSortedPad)));
+        MM_HIP(hipMemsetAsync(pl->ws64.p + 2 * n, 0, 2 * kSortedPad * sizeof(double), st));
         if (mixed) {
             MM_TRY(pl->w32.alloc(2 * n));
-            MM_TRY(pl->ws32.alloc(2 * n));
+            MM_TRY(pl->ws32.alloc(2 * (n + kSortedPad)));
+            MM_HIP(hipMemsetAsync(pl->ws32.p + 2 * n, 0, 2 * kSortedPad * sizeof(float), st));
         }
         if (wdtype == MM_F64)
             hipLaunchKernelGGL(k_weights<double>, dim3(grid_for(n)), dim3(256), 0, st,

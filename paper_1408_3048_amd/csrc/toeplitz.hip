@@ -35,12 +35,12 @@ namespace {
 // inverse DFT written as a cosine sum (c_0 = 1, c_m = 2 for 0 < m < n/2,
 // c_{n/2} = 1 for even n).
 __global__ void k_inv_psd(const int32_t* __restrict__ klen, const double* __restrict__ kpar,
-                          const int64_t* __restrict__ aoff, double f_samp,
-                          double* __restrict__ a, int32_t nk) {
+                          const int64_t* __restrict__ aoff, const int64_t* __restrict__ acnt,
+                          double f_samp, double* __restrict__ a, int32_t nk) {
     const int g = blockIdx.y;
     if (g >= nk) return;
     const int64_t n = klen[g];
-    const int64_t cnt = n / 2 + 1;
+    const int64_t cnt = acnt[g];  // n/2 + 1, or 0 for kernels whose taps come from the FFT path
     const double sigma = kpar[3 * g], fk = kpar[3 * g + 1], al = kpar[3 * g + 2];
     for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < cnt;
          m += (int64_t)gridDim.x * blockDim.x) {
@@ -158,7 +158,7 @@ struct ToepArgs {
     const double* x;      // map (FP64)
     const void* y;        // TOD input
     int y_f64;
-    int mode;             // 0 map IQU, 1 map I, 2 TOD
+    int mode;             // 0 map IQU, 1 map I, 2 TOD FP64, 3 TOD FP32
     T* z;
     const T* H;           // [n_kern][M + 1]
     const T* tw;          // [M][2]
@@ -427,23 +427,79 @@ __device__ __forceinline__ void spectrum_pass(T* __restrict__ re, T* __restrict_
     __syncthreads();
 }
 
-template <typename T>
-__device__ __forceinline__ T load_sample(const ToepArgs<T>& a, int64_t t) {
-    if (a.mode == 0) {
-        const int64_t c = a.cid[t];
-        const T w0 = a.w[2 * t], w1 = a.w[2 * t + 1];
-        const double* xc = a.x + 3 * c;
-        return (T)xc[0] + w0 * (T)xc[1] + w1 * (T)xc[2];
+// Load phase: the tile's window [o - lambda, o + L + lambda) of the interval, zero
+// outside, packed as complex points (even sample -> real, odd -> imaginary).  Each
+// thread handles 8 samples at a time and issues their index loads, weight loads and
+// map gathers as independent batches, so several memory requests per thread are in
+// flight.  Out-of-window samples load a valid index (the interval start) and are
+// masked to zero.
+template <typename T, int LOGM, int NT, int MODE>
+__device__ __forceinline__ void load_window(const ToepArgs<T>& a, T* __restrict__ sre,
+                                            T* __restrict__ sim, int64_t base, int win,
+                                            int64_t lo, int64_t hi) {
+    constexpr int NR = 2 << LOGM;
+    constexpr int PER = NR / NT;
+    constexpr int B = PER < 8 ? PER : 8;
+    static_assert(PER % B == 0, "tile must split into batches");
+    for (int b0 = 0; b0 < PER; b0 += B) {
+        int64_t tt[B];
+        bool ok[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const int i = threadIdx.x + (b0 + u) * NT;
+            const int64_t t = base + i;
+            ok[u] = i < win && t >= lo && t < hi;
+            tt[u] = ok[u] ? t : lo;
+        }
+        T v[B];
+        if constexpr (MODE == 0) {  // map, I/Q/U
+            int32_t cc[B];
+            T w0[B], w1[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) cc[u] = a.cid[tt[u]];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                w0[u] = a.w[2 * tt[u]];
+                w1[u] = a.w[2 * tt[u] + 1];
+            }
+            double x0[B], x1[B], x2[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const double* xc = a.x + 3 * (int64_t)cc[u];
+                x0[u] = xc[0];
+                x1[u] = xc[1];
+                x2[u] = xc[2];
+            }
+#pragma unroll
+            for (int u = 0; u < B; ++u)
+                v[u] = ok[u] ? (T)x0[u] + w0[u] * (T)x1[u] + w1[u] * (T)x2[u] : (T)0;
+        } else if constexpr (MODE == 1) {  // map, I only
+            int32_t cc[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) cc[u] = a.cid[tt[u]];
+#pragma unroll
+            for (int u = 0; u < B; ++u) v[u] = ok[u] ? (T)a.x[cc[u]] : (T)0;
+        } else if constexpr (MODE == 2) {  // TOD, FP64
+            const double* y = (const double*)a.y;
+#pragma unroll
+            for (int u = 0; u < B; ++u) v[u] = ok[u] ? (T)y[tt[u]] : (T)0;
+        } else {  // TOD, FP32
+            const float* y = (const float*)a.y;
+#pragma unroll
+            for (int u = 0; u < B; ++u) v[u] = ok[u] ? (T)y[tt[u]] : (T)0;
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const int i = threadIdx.x + (b0 + u) * NT;
+            const int p = lds_pad<T>(i >> 1);
+            if (i & 1) sim[p] = v[u]; else sre[p] = v[u];
+        }
     }
-    if (a.mode == 1) return (T)a.x[a.cid[t]];
-    if (a.y_f64) return (T)((const double*)a.y)[t];
-    return (T)((const float*)a.y)[t];
 }
 
-template <typename T, int LOGM, int NT>
+template <typename T, int LOGM, int NT, int MODE>
 __global__ __launch_bounds__(NT) void k_toeplitz(ToepArgs<T> a) {
     constexpr int M = 1 << LOGM;
-    constexpr int NR = 2 * M;
     constexpr int MP = M + (M >> (sizeof(T) == 4 ? 5 : 4));
     __shared__ T sre[MP];
     __shared__ T sim[MP];
@@ -454,15 +510,7 @@ __global__ __launch_bounds__(NT) void k_toeplitz(ToepArgs<T> a) {
     const int j = a.tile_int[tile];
     const int64_t lo = a.int_lo[j], hi = a.int_hi[j];
     const int lam = a.lam;
-    const int64_t base = o - lam;
-    const int win = L + 2 * lam;
-    for (int i = threadIdx.x; i < NR; i += NT) {
-        const int64_t t = base + i;
-        T v = (T)0;
-        if (i < win && t >= lo && t < hi) v = load_sample<T>(a, t);
-        const int p = lds_pad<T>(i >> 1);
-        if (i & 1) sim[p] = v; else sre[p] = v;
-    }
+    load_window<T, LOGM, NT, MODE>(a, sre, sim, o - lam, L + 2 * lam, lo, hi);
     __syncthreads();
     fwd_passes<T, LOGM, NT, LOGM>(sre, sim, a.tw);
     spectrum_pass<T, LOGM, NT>(sre, sim, a.H + (int64_t)a.int_kern[j] * (M + 1), a.tw);
@@ -473,11 +521,141 @@ __global__ __launch_bounds__(NT) void k_toeplitz(ToepArgs<T> a) {
     }
 }
 
+// ------------------------------------------------------------------ plan-time FFTs (FP64)
+//
+// X_m, m = 0..mmax <= M, of the real sequence packed in (re, im) after the forward
+// passes (bit-reversed order): X_m = ((Z_m + conj Z_{M-m}) - i e^{-2 pi i m/N} (Z_m - conj Z_{M-m})) / 2
+template <int LOGM, int NT, class Out>
+__device__ __forceinline__ void real_dft_out(const double* __restrict__ re, const double* __restrict__ im,
+                                             const double* __restrict__ tw, int mmax, Out&& out) {
+    constexpr int M = 1 << LOGM;
+    for (int m = threadIdx.x; m <= mmax; m += NT) {
+        double xr, xi;
+        if (m == 0 || m == M) {
+            const int a = lds_pad<double>(0);
+            xr = m == 0 ? re[a] + im[a] : re[a] - im[a];
+            xi = 0.0;
+        } else {
+            const int ak = lds_pad<double>(rev_bits<LOGM>(m));
+            const int am = lds_pad<double>(rev_bits<LOGM>(M - m));
+            const double zkr = re[ak], zki = im[ak], zmr = re[am], zmi = im[am];
+            const double Ar = zkr + zmr, Ai = zki - zmi, Dr = zkr - zmr, Di = zki + zmi;
+            const double er = tw[2 * m], ei = tw[2 * m + 1];
+            const double pr = er * Dr - ei * Di, pim = er * Di + ei * Dr;
+            xr = 0.5 * (Ar + pim);
+            xi = 0.5 * (Ai - pr);
+        }
+        out(m, xr, xi);
+    }
+}
+
+// symbol on the n_r = 2M grid: H(m) = t_0 + 2 sum_k t_k cos(2 pi k m / n_r), the real DFT
+// of the even kernel h (h_0 = t_0, h_k = h_{n_r-k} = t_k for k <= K)
+template <int LOGM, int NT>
+__global__ __launch_bounds__(NT) void k_spec_fft(const double* __restrict__ taps,
+                                                 const int64_t* __restrict__ toff,
+                                                 const int64_t* __restrict__ tcnt,
+                                                 const double* __restrict__ tw,
+                                                 double* __restrict__ H) {
+    constexpr int M = 1 << LOGM, NR = 2 * M;
+    constexpr int MP = M + (M >> 4);
+    __shared__ double sre[MP];
+    __shared__ double sim[MP];
+    const int g = blockIdx.x;
+    const double* t = taps + toff[g];
+    const int K = (int)tcnt[g] - 1;
+    for (int i = threadIdx.x; i < NR; i += NT) {
+        double v = 0.0;
+        if (i <= K) v = t[i];
+        else if (i >= NR - K) v = t[NR - i];
+        const int p = lds_pad<double>(i >> 1);
+        if (i & 1) sim[p] = v; else sre[p] = v;
+    }
+    __syncthreads();
+    fwd_passes<double, LOGM, NT, LOGM>(sre, sim, tw);
+    double* Hg = H + (int64_t)g * (M + 1);
+    real_dft_out<LOGM, NT>(sre, sim, tw, M, [&](int m, double xr, double) { Hg[m] = xr; });
+}
+
+// taps by decimation in time: for an interval of n = R * 2M samples,
+//   t_k = (1/n) sum_{b<R} Re[ e^{2 pi i b k / n} conj(X_b(k)) ],  X_b = real DFT over a of
+//   Q(R a + b), Q(m) = q(min(m, n - m)) the inverse PSD on the interval's grid.
+// Block (b, g) writes Re[...] for k <= K to part[g][b][k]; k_taps_sum adds over b.
+template <int LOGM, int NT>
+__global__ __launch_bounds__(NT) void k_taps_fft(const int32_t* __restrict__ kid,
+                                                 const int32_t* __restrict__ klen,
+                                                 const double* __restrict__ kpar,
+                                                 const int64_t* __restrict__ tcnt, double f_samp,
+                                                 const double* __restrict__ tw, int kstride,
+                                                 int rmax, double* __restrict__ part) {
+    constexpr int M = 1 << LOGM, NR = 2 * M;
+    constexpr int MP = M + (M >> 4);
+    __shared__ double sre[MP];
+    __shared__ double sim[MP];
+    const int gi = blockIdx.y;
+    const int g = kid[gi];
+    const int64_t n = klen[g];
+    const int R = (int)(n / NR);
+    const int b = blockIdx.x;
+    if (b >= R) return;
+    const double sigma = kpar[3 * g], fk = kpar[3 * g + 1], al = kpar[3 * g + 2];
+    for (int i = threadIdx.x; i < NR; i += NT) {
+        int64_t m = (int64_t)R * i + b;
+        if (m > n - m) m = n - m;
+        double q;
+        if (fk > 0.0) {
+            q = m == 0 ? 0.0
+                       : 1.0 / (sigma * sigma * (1.0 + pow(fk / ((double)m * f_samp / (double)n), al)));
+        } else {
+            q = 1.0 / (sigma * sigma);
+        }
+        const int p = lds_pad<double>(i >> 1);
+        if (i & 1) sim[p] = q; else sre[p] = q;
+    }
+    __syncthreads();
+    fwd_passes<double, LOGM, NT, LOGM>(sre, sim, tw);
+    const int K = (int)tcnt[g] - 1;
+    double* out = part + ((int64_t)gi * rmax + b) * kstride;
+    real_dft_out<LOGM, NT>(sre, sim, tw, K, [&](int k, double xr, double xi) {
+        double sn, cs;
+        sincospi(2.0 * (double)((int64_t)b * k % n) / (double)n, &sn, &cs);
+        out[k] = cs * xr + sn * xi;
+    });
+}
+
+__global__ void k_taps_sum(const int32_t* __restrict__ kid, const int32_t* __restrict__ klen,
+                           const int64_t* __restrict__ toff, const int64_t* __restrict__ tcnt,
+                           const double* __restrict__ part, int kstride, int rmax, int lam,
+                           int window, double* __restrict__ t, int nr) {
+    const int gi = blockIdx.y;
+    const int g = kid[gi];
+    const int64_t n = klen[g];
+    const int R = (int)(n / nr);
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < tcnt[g];
+         k += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int b = 0; b < R; ++b) s += part[((int64_t)gi * rmax + b) * kstride + k];
+        double w = 1.0;
+        const double x = (double)k / (double)lam;
+        if (window == MM_WIN_GAUSS) w = exp(-x * x);
+        else if (window == MM_WIN_GAUSS2) w = exp(-2.0 * x * x);
+        t[toff[g] + k] = s * w / (double)n;
+    }
+}
+
+constexpr int kPlanLogM = 13;  // plan-time FP64 FFTs: n_r = 16384 real points
+constexpr int kPlanNT = 512;
+
 template <typename T, int LOGM>
 int launch_logm(const ToepArgs<T>& a, int64_t n_tiles, hipStream_t st) {
     constexpr int M = 1 << LOGM;
     constexpr int NT = (M / 16) > 1024 ? 1024 : ((M / 16) < 256 ? 256 : (M / 16));
-    hipLaunchKernelGGL((k_toeplitz<T, LOGM, NT>), dim3(n_tiles), dim3(NT), 0, st, a);
+    switch (a.mode) {
+        case 0: hipLaunchKernelGGL((k_toeplitz<T, LOGM, NT, 0>), dim3(n_tiles), dim3(NT), 0, st, a); break;
+        case 1: hipLaunchKernelGGL((k_toeplitz<T, LOGM, NT, 1>), dim3(n_tiles), dim3(NT), 0, st, a); break;
+        case 2: hipLaunchKernelGGL((k_toeplitz<T, LOGM, NT, 2>), dim3(n_tiles), dim3(NT), 0, st, a); break;
+        default: hipLaunchKernelGGL((k_toeplitz<T, LOGM, NT, 3>), dim3(n_tiles), dim3(NT), 0, st, a); break;
+    }
     MM_HIP(hipGetLastError());
     return MM_OK;
 }
@@ -569,10 +747,15 @@ int build_kernels(mm_plan_t pl) {
     std::vector<double> kpar(3 * nk);
     int64_t atot = 0, ttot = 0;
     int64_t amax = 0;
+    constexpr int64_t kNs = (int64_t)2 << kPlanLogM;
+    std::vector<int32_t> fft_ids;
     for (int g = 0; g < nk; ++g) {
         const int64_t n = pl->h_kern_len[g];
+        const int64_t K = std::min<int64_t>(lam, n - 1);
+        const bool by_fft = n % kNs == 0 && K < kNs / 2;
+        if (by_fft) fft_ids.push_back(g);
         aoff[g] = atot;
-        acnt[g] = n / 2 + 1;
+        acnt[g] = by_fft ? 0 : n / 2 + 1;
         atot += acnt[g];
         amax = std::max(amax, acnt[g]);
         nper[g] = n;
@@ -589,7 +772,7 @@ int build_kernels(mm_plan_t pl) {
     DBuf<int64_t> d_aoff, d_acnt, d_nper, d_jcnt, d_toff, d_tcnt;
     MM_TRY(d_klen.alloc(nk));
     MM_TRY(d_kpar.alloc(3 * nk));
-    MM_TRY(d_a.alloc(atot));
+    MM_TRY(d_a.alloc(std::max<int64_t>(1, atot)));
     MM_TRY(d_t.alloc(ttot));
     MM_TRY(d_aoff.alloc(nk));
     MM_TRY(d_acnt.alloc(nk));
@@ -606,9 +789,9 @@ int build_kernels(mm_plan_t pl) {
     MM_HIP(hipMemcpyAsync(d_toff.p, toff.data(), nk * 8, hipMemcpyHostToDevice, st));
     MM_HIP(hipMemcpyAsync(d_tcnt.p, tcnt.data(), nk * 8, hipMemcpyHostToDevice, st));
     {
-        const int gx = (int)std::min<int64_t>((amax + 255) / 256, 1024);
+        const int gx = (int)std::max<int64_t>(1, std::min<int64_t>((amax + 255) / 256, 1024));
         hipLaunchKernelGGL(k_inv_psd, dim3(gx, nk), dim3(256), 0, st, d_klen.p, d_kpar.p,
-                           d_aoff.p, pl->opts.f_samp, d_a.p, nk);
+                           d_aoff.p, d_acnt.p, pl->opts.f_samp, d_a.p, nk);
         MM_HIP(hipGetLastError());
         const int64_t jmax = *std::max_element(jcnt.begin(), jcnt.end());
         hipLaunchKernelGGL(k_cos_transform, dim3((jmax + kCtThreads - 1) / kCtThreads, nk),
@@ -618,6 +801,36 @@ int build_kernels(mm_plan_t pl) {
         hipLaunchKernelGGL(k_taps_finish, dim3(std::max<int64_t>(1, (jmax + 255) / 256), nk),
                            dim3(256), 0, st, d_t.p, d_toff.p, d_tcnt.p, d_klen.p, lam,
                            pl->opts.window, nk);
+        MM_HIP(hipGetLastError());
+    }
+    if (!fft_ids.empty()) {
+        // decimation-in-time FFT path for interval lengths that are multiples of 2^(kPlanLogM+1)
+        const int nf = (int)fft_ids.size();
+        int rmax = 1, kmax = 1;
+        for (int g : fft_ids) {
+            rmax = std::max<int>(rmax, (int)(pl->h_kern_len[g] / kNs));
+            kmax = std::max<int>(kmax, (int)tcnt[g]);
+        }
+        std::vector<double> tw(kNs);
+        for (int64_t q = 0; q < kNs / 2; ++q) {
+            const double ang = -2.0 * M_PI * (double)q / (double)kNs;
+            tw[2 * q] = std::cos(ang);
+            tw[2 * q + 1] = std::sin(ang);
+        }
+        DBuf<double> d_tw, d_part;
+        DBuf<int32_t> d_kid;
+        MM_TRY(d_tw.alloc(kNs));
+        MM_TRY(d_kid.alloc(nf));
+        MM_TRY(d_part.alloc((size_t)nf * rmax * kmax));
+        MM_HIP(hipMemcpyAsync(d_tw.p, tw.data(), kNs * 8, hipMemcpyHostToDevice, st));
+        MM_HIP(hipMemcpyAsync(d_kid.p, fft_ids.data(), nf * 4, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL((k_taps_fft<kPlanLogM, kPlanNT>), dim3(rmax, nf), dim3(kPlanNT), 0, st,
+                           d_kid.p, d_klen.p, d_kpar.p, d_tcnt.p, pl->opts.f_samp, d_tw.p, kmax,
+                           rmax, d_part.p);
+        MM_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_taps_sum, dim3((kmax + 255) / 256, nf), dim3(256), 0, st, d_kid.p,
+                           d_klen.p, d_toff.p, d_tcnt.p, d_part.p, kmax, rmax, lam,
+                           pl->opts.window, d_t.p, (int)kNs);
         MM_HIP(hipGetLastError());
     }
     std::vector<double> taps(ttot);
@@ -736,35 +949,62 @@ int build_tiling(mm_plan_t pl, FftTiling& ft, bool fp64, int n_r_request) {
     }
     // spectra H(m), m = 0..M, of every kernel on this grid
     const int32_t nk = pl->n_kern;
-    std::vector<int64_t> boff(nk), bcnt(nk), nper(nk, ft.n_r), jcnt(nk, M + 1), ooff(nk);
-    std::vector<double> b;
-    for (int g = 0; g < nk; ++g) {
-        boff[g] = (int64_t)b.size();
-        bcnt[g] = (int64_t)pl->h_taps[g].size();
-        for (size_t k = 0; k < pl->h_taps[g].size(); ++k)
-            b.push_back((k == 0 ? 1.0 : 2.0) * pl->h_taps[g][k]);
-        ooff[g] = (int64_t)g * (M + 1);
-    }
-    DBuf<double> d_b, d_h, d_min;
-    DBuf<int64_t> d_boff, d_bcnt, d_nper, d_jcnt, d_ooff;
-    MM_TRY(d_b.alloc(b.size()));
+    DBuf<double> d_h, d_min;
     MM_TRY(d_h.alloc((size_t)nk * (M + 1)));
     MM_TRY(d_min.alloc(nk));
-    MM_TRY(d_boff.alloc(nk));
-    MM_TRY(d_bcnt.alloc(nk));
-    MM_TRY(d_nper.alloc(nk));
-    MM_TRY(d_jcnt.alloc(nk));
-    MM_TRY(d_ooff.alloc(nk));
-    MM_HIP(hipMemcpyAsync(d_b.p, b.data(), b.size() * 8, hipMemcpyHostToDevice, st));
-    MM_HIP(hipMemcpyAsync(d_boff.p, boff.data(), nk * 8, hipMemcpyHostToDevice, st));
-    MM_HIP(hipMemcpyAsync(d_bcnt.p, bcnt.data(), nk * 8, hipMemcpyHostToDevice, st));
-    MM_HIP(hipMemcpyAsync(d_nper.p, nper.data(), nk * 8, hipMemcpyHostToDevice, st));
-    MM_HIP(hipMemcpyAsync(d_jcnt.p, jcnt.data(), nk * 8, hipMemcpyHostToDevice, st));
-    MM_HIP(hipMemcpyAsync(d_ooff.p, ooff.data(), nk * 8, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_cos_transform, dim3((M + 1 + kCtThreads - 1) / kCtThreads, nk),
-                       dim3(kCtThreads), 0, st, d_b.p, d_boff.p, d_bcnt.p, d_nper.p, d_jcnt.p,
-                       d_ooff.p, d_h.p, nk);
-    MM_HIP(hipGetLastError());
+    std::vector<int64_t> toff(nk), tcnt(nk);
+    std::vector<double> flat;
+    for (int g = 0; g < nk; ++g) {
+        toff[g] = (int64_t)flat.size();
+        tcnt[g] = (int64_t)pl->h_taps[g].size();
+        flat.insert(flat.end(), pl->h_taps[g].begin(), pl->h_taps[g].end());
+    }
+    DBuf<double> d_taps;
+    DBuf<int64_t> d_toff, d_tcnt;
+    MM_TRY(d_taps.alloc(flat.size()));
+    MM_TRY(d_toff.alloc(nk));
+    MM_TRY(d_tcnt.alloc(nk));
+    MM_HIP(hipMemcpyAsync(d_taps.p, flat.data(), flat.size() * 8, hipMemcpyHostToDevice, st));
+    MM_HIP(hipMemcpyAsync(d_toff.p, toff.data(), nk * 8, hipMemcpyHostToDevice, st));
+    MM_HIP(hipMemcpyAsync(d_tcnt.p, tcnt.data(), nk * 8, hipMemcpyHostToDevice, st));
+    if (logm == kPlanLogM) {
+        DBuf<double> d_tw;
+        MM_TRY(d_tw.alloc(2 * M));
+        MM_HIP(hipMemcpyAsync(d_tw.p, tw.data(), 2 * M * 8, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL((k_spec_fft<kPlanLogM, kPlanNT>), dim3(nk), dim3(kPlanNT), 0, st,
+                           d_taps.p, d_toff.p, d_tcnt.p, d_tw.p, d_h.p);
+        MM_HIP(hipGetLastError());
+        MM_HIP(hipStreamSynchronize(st));
+    } else {
+        std::vector<int64_t> boff(nk), bcnt(nk), nper(nk, ft.n_r), jcnt(nk, M + 1), ooff(nk);
+        std::vector<double> b;
+        for (int g = 0; g < nk; ++g) {
+            boff[g] = (int64_t)b.size();
+            bcnt[g] = (int64_t)pl->h_taps[g].size();
+            for (size_t k = 0; k < pl->h_taps[g].size(); ++k)
+                b.push_back((k == 0 ? 1.0 : 2.0) * pl->h_taps[g][k]);
+            ooff[g] = (int64_t)g * (M + 1);
+        }
+        DBuf<double> d_b;
+        DBuf<int64_t> d_boff, d_bcnt, d_nper, d_jcnt, d_ooff;
+        MM_TRY(d_b.alloc(b.size()));
+        MM_TRY(d_boff.alloc(nk));
+        MM_TRY(d_bcnt.alloc(nk));
+        MM_TRY(d_nper.alloc(nk));
+        MM_TRY(d_jcnt.alloc(nk));
+        MM_TRY(d_ooff.alloc(nk));
+        MM_HIP(hipMemcpyAsync(d_b.p, b.data(), b.size() * 8, hipMemcpyHostToDevice, st));
+        MM_HIP(hipMemcpyAsync(d_boff.p, boff.data(), nk * 8, hipMemcpyHostToDevice, st));
+        MM_HIP(hipMemcpyAsync(d_bcnt.p, bcnt.data(), nk * 8, hipMemcpyHostToDevice, st));
+        MM_HIP(hipMemcpyAsync(d_nper.p, nper.data(), nk * 8, hipMemcpyHostToDevice, st));
+        MM_HIP(hipMemcpyAsync(d_jcnt.p, jcnt.data(), nk * 8, hipMemcpyHostToDevice, st));
+        MM_HIP(hipMemcpyAsync(d_ooff.p, ooff.data(), nk * 8, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_cos_transform, dim3((M + 1 + kCtThreads - 1) / kCtThreads, nk),
+                           dim3(kCtThreads), 0, st, d_b.p, d_boff.p, d_bcnt.p, d_nper.p, d_jcnt.p,
+                           d_ooff.p, d_h.p, nk);
+        MM_HIP(hipGetLastError());
+        MM_HIP(hipStreamSynchronize(st));
+    }
     const double scale = 1.0 / (2.0 * (double)ft.n_r);
     if (fp64) {
         MM_TRY(ft.H64.alloc((size_t)nk * (M + 1)));
@@ -818,7 +1058,7 @@ int toeplitz_tod64(mm_plan_t pl, const void* y, int y_f64, double* z) {
     auto a = base_args<double>(pl, pl->fft64);
     a.y = y;
     a.y_f64 = y_f64;
-    a.mode = 2;
+    a.mode = y_f64 ? 2 : 3;
     a.z = z;
     return launch<double>(a, pl->fft64.logm, pl->fft64.n_tiles, pl->stream);
 }
@@ -827,7 +1067,7 @@ int toeplitz_tod32(mm_plan_t pl, const void* y, int y_f64, float* z) {
     auto a = base_args<float>(pl, pl->fft32);
     a.y = y;
     a.y_f64 = y_f64;
-    a.mode = 2;
+    a.mode = y_f64 ? 2 : 3;
     a.z = z;
     return launch<float>(a, pl->fft32.logm, pl->fft32.n_tiles, pl->stream);
 }

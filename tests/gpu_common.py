@@ -38,7 +38,15 @@ def problem(name):
     return sc, O.Problem.from_scan(sc)
 
 
+def long_iqu(seed=35):
+    # one 2^16-sample interval: taps by the decimated FFT with 4 sub-transforms
+    sc = synth.raster_iqu(side=64, spp=8, n_det=1, interval_len=2 ** 16, lam=512,
+                          fknee_range=(0.5, 2.0), alpha_range=(1.0, 2.0), seed_key=seed)
+    return sc
+
+
 SCANS = {
+    "long_iqu": long_iqu,
     "small_iqu": small_iqu,
     "ragged_iqu": ragged_iqu,
     "cfg1": synth.cfg1_raster_i,

@@ -57,7 +57,7 @@ def test_integer_layout_bit_exact(plans, name):
     assert np.array_equal(pl.sorted_samples().cpu().numpy(), perm_or)
 
 
-@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("name", CASES + ["long_iqu"])
 def test_taps(plans, name):
     sc, pr = problem(name)
     pl = plans(name, precision="mixed")
@@ -99,6 +99,25 @@ def test_apply_A_rhs_bj(plans, name):
     d = rng.standard_normal(pr.n_t)
     assert rel(pl.rhs(dev(d)).cpu().numpy(), pr.rhs(d)) <= 1e-11
     assert rel(pl.precond_bj(dev(x)).cpu().numpy(), pr.bj_apply(x)) <= 1e-13
+
+
+@pytest.mark.parametrize("n_r", [4096, 16384, 32768])
+def test_ninv_forced_fft_lengths(n_r):
+    # every overlap-save tile size, with spectra from the plan-time FFT (n_r = 16384) or
+    # direct sums (other lengths); FP64 operator limited to n_r <= 16384
+    sc, pr = problem("long_iqu")
+    kw = dict(fft_len_f32=n_r, precision="mixed")
+    if n_r <= 16384:
+        kw["fft_len_f64"] = n_r
+    pl = Plan.from_scan(sc, **kw)
+    y = np.random.default_rng(8).standard_normal(pr.n_t)
+    zr = pr.ninv(y)
+    if n_r <= 16384:
+        assert rel(pl.apply_Ninv(dev(y)).cpu().numpy(), zr) <= 1e-11
+    y32 = y.astype(np.float32)
+    z32 = pl.apply_Ninv(dev(y32), precision="mixed").cpu().numpy()
+    assert rel(z32, pr.ninv(y32.astype(np.float64))) <= 2e-5
+    pl.close()
 
 
 def test_determinism_bitwise(plans):
