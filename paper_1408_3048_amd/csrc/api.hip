@@ -467,6 +467,8 @@ int mm_plan(mm_plan_t* out, int64_t n_samples, const int32_t* pix, const void* w
     tick("bj");
     const int64_t n = pl->n_obs * pl->n_s;
     if ((s = pl->tod64a.alloc(pl->n_t)) != MM_OK) return fail(s);
+    if (pl->n_s == 3 && (s = pl->xp64.alloc(4 * pl->n_obs)) != MM_OK) return fail(s);
+    if (pl->n_s == 3 && mixed && (s = pl->xp32.alloc(4 * pl->n_obs)) != MM_OK) return fail(s);
     if (mixed && (s = pl->tod32a.alloc(pl->n_t)) != MM_OK) return fail(s);
     for (auto& v : pl->vec)
         if ((s = v.alloc(n)) != MM_OK) return fail(s);

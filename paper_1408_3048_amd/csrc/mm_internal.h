@@ -176,6 +176,8 @@ struct mm_plan_s {
     mm::Coarse co;
     // work buffers
     mm::DBuf<double> tod64a, tod64b;
+    mm::DBuf<double> xp64;              // packed map (I, Q, U, 0) for the fused gather
+    mm::DBuf<float> xp32;
     mm::DBuf<float> tod32a, tod32b;
     mm::DBuf<double> vec[8];            // PCG vectors [n_obs*n_s]
     mm::DBuf<double> part;              // reduction partials

@@ -23,6 +23,7 @@
 #include <cmath>
 #include <map>
 #include <tuple>
+#include <type_traits>
 
 #include "mm_internal.h"
 
@@ -155,7 +156,8 @@ template <typename T>
 struct ToepArgs {
     const int32_t* cid;
     const T* w;           // [n_t][2] time-ordered weights (IQU)
-    const double* x;      // map (FP64)
+    const double* x;      // map (FP64); I-only mode reads it directly
+    const T* xp;          // map packed as [n_obs][4] = (I, Q, U, 0) in T (IQU mode)
     const void* y;        // TOD input
     int y_f64;
     int mode;             // 0 map IQU, 1 map I, 2 TOD FP64, 3 TOD FP32
@@ -172,9 +174,70 @@ struct ToepArgs {
     const int* done;
 };
 
+// LDS layout of the complex work array (M points).  Element a lives at
+// swz(a) = a ^ (((a >> 5) ^ (a >> 10)) & 31), a bijection within every block of 32
+// points that keeps the radix-16 passes, the spectrum pass and the load/store phases
+// free of bank conflicts on the 64-bank LDS, except one pass with 2-way conflicts
+// (checked by enumerating every access pattern), with no padding.  FP32 points are
+// stored interleaved (one 8-byte access per point), FP64 as split real and imaginary
+// arrays (two 8-byte accesses).
+__device__ __forceinline__ int swz(int a) { return a ^ (((a >> 5) ^ (a >> 10)) & 31); }
+
 template <typename T>
-__device__ __forceinline__ int lds_pad(int a) {
-    return a + (a >> (sizeof(T) == 4 ? 5 : 4));
+struct CBuf;
+
+template <>
+struct CBuf<float> {
+    float2* c;
+    __device__ __forceinline__ void get(int a, float& re, float& im) const {
+        const float2 v = c[swz(a)];
+        re = v.x;
+        im = v.y;
+    }
+    __device__ __forceinline__ void put(int a, float re, float im) const {
+        c[swz(a)] = make_float2(re, im);
+    }
+    __device__ __forceinline__ void put_part(int a, int part, float v) const {
+        reinterpret_cast<float*>(c)[2 * swz(a) + part] = v;
+    }
+    __device__ __forceinline__ float get_part(int a, int part) const {
+        return reinterpret_cast<const float*>(c)[2 * swz(a) + part];
+    }
+};
+
+template <>
+struct CBuf<double> {
+    double* re;
+    double* im;
+    __device__ __forceinline__ void get(int a, double& r, double& i) const {
+        const int p = swz(a);
+        r = re[p];
+        i = im[p];
+    }
+    __device__ __forceinline__ void put(int a, double r, double i) const {
+        const int p = swz(a);
+        re[p] = r;
+        im[p] = i;
+    }
+    __device__ __forceinline__ void put_part(int a, int part, double v) const {
+        (part ? im : re)[swz(a)] = v;
+    }
+    __device__ __forceinline__ double get_part(int a, int part) const {
+        return (part ? im : re)[swz(a)];
+    }
+};
+
+// the M-point complex buffer over 2 M sizeof(T) bytes of LDS
+template <typename T>
+__device__ __forceinline__ CBuf<T> make_cbuf(unsigned char* smem, int M) {
+    CBuf<T> b;
+    if constexpr (sizeof(T) == 4) {
+        b.c = reinterpret_cast<float2*>(smem);
+    } else {
+        b.re = reinterpret_cast<double*>(smem);
+        b.im = b.re + M;
+    }
+    return b;
 }
 
 template <int BITS>
@@ -277,8 +340,7 @@ __device__ __forceinline__ void powers(T wr, T wi, T* pr, T* pi) {
 }
 
 template <typename T, int LOGM, int NT, int LR, int LOGB>
-__device__ __forceinline__ void dif_pass(T* __restrict__ re, T* __restrict__ im,
-                                         const T* __restrict__ tw) {
+__device__ __forceinline__ void dif_pass(const CBuf<T>& buf, const T* __restrict__ tw) {
     constexpr int R = 1 << LR, B = 1 << LOGB, Q = B / R, M = 1 << LOGM, G = M / R;
     constexpr int TWS = (2 * M) / B;
     for (int g = threadIdx.x; g < G; g += NT) {
@@ -286,11 +348,7 @@ __device__ __forceinline__ void dif_pass(T* __restrict__ re, T* __restrict__ im,
         const int base = (g / Q) * B + k;
         T vr[R], vi[R];
 #pragma unroll
-        for (int m = 0; m < R; ++m) {
-            const int a = lds_pad<T>(base + m * Q);
-            vr[m] = re[a];
-            vi[m] = im[a];
-        }
+        for (int m = 0; m < R; ++m) buf.get(base + m * Q, vr[m], vi[m]);
         dif_net<T, R>(vr, vi);
         if (Q > 1 && k != 0) {
             T pr[R], pi[R];
@@ -304,18 +362,13 @@ __device__ __forceinline__ void dif_pass(T* __restrict__ re, T* __restrict__ im,
             }
         }
 #pragma unroll
-        for (int i = 0; i < R; ++i) {
-            const int a = lds_pad<T>(base + i * Q);
-            re[a] = vr[i];
-            im[a] = vi[i];
-        }
+        for (int i = 0; i < R; ++i) buf.put(base + i * Q, vr[i], vi[i]);
     }
     __syncthreads();
 }
 
 template <typename T, int LOGM, int NT, int LR, int LOGB>
-__device__ __forceinline__ void dit_pass(T* __restrict__ re, T* __restrict__ im,
-                                         const T* __restrict__ tw) {
+__device__ __forceinline__ void dit_pass(const CBuf<T>& buf, const T* __restrict__ tw) {
     constexpr int R = 1 << LR, B = 1 << LOGB, Q = B / R, M = 1 << LOGM, G = M / R;
     constexpr int TWS = (2 * M) / B;
     for (int g = threadIdx.x; g < G; g += NT) {
@@ -323,11 +376,7 @@ __device__ __forceinline__ void dit_pass(T* __restrict__ re, T* __restrict__ im,
         const int base = (g / Q) * B + k;
         T vr[R], vi[R];
 #pragma unroll
-        for (int i = 0; i < R; ++i) {
-            const int a = lds_pad<T>(base + i * Q);
-            vr[i] = re[a];
-            vi[i] = im[a];
-        }
+        for (int i = 0; i < R; ++i) buf.get(base + i * Q, vr[i], vi[i]);
         if (Q > 1 && k != 0) {
             T pr[R], pi[R];
             powers<T, R>(tw[2 * k * TWS], tw[2 * k * TWS + 1], pr, pi);
@@ -341,53 +390,50 @@ __device__ __forceinline__ void dit_pass(T* __restrict__ re, T* __restrict__ im,
         }
         dit_net_inv<T, R>(vr, vi);
 #pragma unroll
-        for (int m = 0; m < R; ++m) {
-            const int a = lds_pad<T>(base + m * Q);
-            re[a] = vr[m];
-            im[a] = vi[m];
-        }
+        for (int m = 0; m < R; ++m) buf.put(base + m * Q, vr[m], vi[m]);
     }
     __syncthreads();
 }
 
 template <typename T, int LOGM, int NT, int LOGB>
-__device__ __forceinline__ void fwd_passes(T* re, T* im, const T* tw) {
+__device__ __forceinline__ void fwd_passes(const CBuf<T>& buf, const T* tw) {
     if constexpr (LOGB > 0) {
         constexpr int LR = LOGB >= 4 ? 4 : LOGB;
-        dif_pass<T, LOGM, NT, LR, LOGB>(re, im, tw);
-        fwd_passes<T, LOGM, NT, LOGB - LR>(re, im, tw);
+        dif_pass<T, LOGM, NT, LR, LOGB>(buf, tw);
+        fwd_passes<T, LOGM, NT, LOGB - LR>(buf, tw);
     }
 }
 
 template <typename T, int LOGM, int NT, int LOGB>
-__device__ __forceinline__ void inv_passes(T* re, T* im, const T* tw) {
+__device__ __forceinline__ void inv_passes(const CBuf<T>& buf, const T* tw) {
     if constexpr (LOGB > 0) {
         constexpr int LR = LOGB >= 4 ? 4 : LOGB;
-        inv_passes<T, LOGM, NT, LOGB - LR>(re, im, tw);
-        dit_pass<T, LOGM, NT, LR, LOGB>(re, im, tw);
+        inv_passes<T, LOGM, NT, LOGB - LR>(buf, tw);
+        dit_pass<T, LOGM, NT, LR, LOGB>(buf, tw);
     }
 }
 
 // real-spectrum split, multiplication by the (pre-scaled) real kernel spectrum H,
 // and merge back, on pairs (k, M - k) of the bit-reversed half-length transform
 template <typename T, int LOGM, int NT>
-__device__ __forceinline__ void spectrum_pass(T* __restrict__ re, T* __restrict__ im,
-                                              const T* __restrict__ H, const T* __restrict__ tw) {
+__device__ __forceinline__ void spectrum_pass(const CBuf<T>& buf, const T* __restrict__ H,
+                                              const T* __restrict__ tw) {
     constexpr int M = 1 << LOGM;
     for (int k = threadIdx.x; k <= M / 2; k += NT) {
         if (k == 0) {
-            const int a = lds_pad<T>(0);
-            const T zr = re[a], zi = im[a];
+            T zr, zi;
+            buf.get(0, zr, zi);
             const T y0 = H[0] * ((T)2 * (zr + zi));
             const T ym = H[M] * ((T)2 * (zr - zi));
-            re[a] = y0 + ym;
-            im[a] = y0 - ym;
+            buf.put(0, y0 + ym, y0 - ym);
             continue;
         }
         const int km = M - k;
-        const int ak = lds_pad<T>(rev_bits<LOGM>(k));
-        const int am = lds_pad<T>(rev_bits<LOGM>(km));
-        const T zkr = re[ak], zki = im[ak], zmr = re[am], zmi = im[am];
+        const int ak = rev_bits<LOGM>(k);
+        const int am = rev_bits<LOGM>(km);
+        T zkr, zki, zmr, zmi;
+        buf.get(ak, zkr, zki);
+        buf.get(am, zmr, zmi);
         const T er = tw[2 * k], ei = tw[2 * k + 1];
         const T fr = tw[2 * km], fi = tw[2 * km + 1];
         // 2 X_k = (Z_k + conj Z_m) - i e (Z_k - conj Z_m)
@@ -411,8 +457,7 @@ __device__ __forceinline__ void spectrum_pass(T* __restrict__ re, T* __restrict_
         Di = yki + ymi;
         pr = er * Dr + ei * Di;
         pim = er * Di - ei * Dr;
-        re[ak] = Ar - pim;
-        im[ak] = Ai + pr;
+        buf.put(ak, Ar - pim, Ai + pr);
         if (km != k) {
             Ar = ymr + ykr;
             Ai = ymi - yki;
@@ -420,8 +465,7 @@ __device__ __forceinline__ void spectrum_pass(T* __restrict__ re, T* __restrict_
             Di = ymi + yki;
             pr = fr * Dr + fi * Di;
             pim = fr * Di - fi * Dr;
-            re[am] = Ar - pim;
-            im[am] = Ai + pr;
+            buf.put(am, Ar - pim, Ai + pr);
         }
     }
     __syncthreads();
@@ -434,12 +478,11 @@ __device__ __forceinline__ void spectrum_pass(T* __restrict__ re, T* __restrict_
 // flight.  Out-of-window samples load a valid index (the interval start) and are
 // masked to zero.
 template <typename T, int LOGM, int NT, int MODE>
-__device__ __forceinline__ void load_window(const ToepArgs<T>& a, T* __restrict__ sre,
-                                            T* __restrict__ sim, int64_t base, int win,
-                                            int64_t lo, int64_t hi) {
+__device__ __forceinline__ void load_window(const ToepArgs<T>& a, const CBuf<T>& buf,
+                                            int64_t base, int win, int64_t lo, int64_t hi) {
     constexpr int NR = 2 << LOGM;
     constexpr int PER = NR / NT;
-    constexpr int B = PER < 8 ? PER : 8;
+    constexpr int B = PER < 16 ? PER : 16;
     static_assert(PER % B == 0, "tile must split into batches");
     for (int b0 = 0; b0 < PER; b0 += B) {
         int64_t tt[B];
@@ -452,27 +495,21 @@ __device__ __forceinline__ void load_window(const ToepArgs<T>& a, T* __restrict_
             tt[u] = ok[u] ? t : lo;
         }
         T v[B];
-        if constexpr (MODE == 0) {  // map, I/Q/U
+        if constexpr (MODE == 0) {  // map, I/Q/U: one packed-map gather per sample
+            typedef typename std::conditional<sizeof(T) == 4, float4, double4>::type T4;
+            typedef typename std::conditional<sizeof(T) == 4, float2, double2>::type T2;
             int32_t cc[B];
-            T w0[B], w1[B];
+            T2 ww[B];
 #pragma unroll
             for (int u = 0; u < B; ++u) cc[u] = a.cid[tt[u]];
 #pragma unroll
-            for (int u = 0; u < B; ++u) {
-                w0[u] = a.w[2 * tt[u]];
-                w1[u] = a.w[2 * tt[u] + 1];
-            }
-            double x0[B], x1[B], x2[B];
+            for (int u = 0; u < B; ++u) ww[u] = reinterpret_cast<const T2*>(a.w)[tt[u]];
+            T4 xx[B];
 #pragma unroll
-            for (int u = 0; u < B; ++u) {
-                const double* xc = a.x + 3 * (int64_t)cc[u];
-                x0[u] = xc[0];
-                x1[u] = xc[1];
-                x2[u] = xc[2];
-            }
+            for (int u = 0; u < B; ++u) xx[u] = reinterpret_cast<const T4*>(a.xp)[cc[u]];
 #pragma unroll
             for (int u = 0; u < B; ++u)
-                v[u] = ok[u] ? (T)x0[u] + w0[u] * (T)x1[u] + w1[u] * (T)x2[u] : (T)0;
+                v[u] = ok[u] ? xx[u].x + ww[u].x * xx[u].y + ww[u].y * xx[u].z : (T)0;
         } else if constexpr (MODE == 1) {  // map, I only
             int32_t cc[B];
 #pragma unroll
@@ -491,8 +528,7 @@ __device__ __forceinline__ void load_window(const ToepArgs<T>& a, T* __restrict_
 #pragma unroll
         for (int u = 0; u < B; ++u) {
             const int i = threadIdx.x + (b0 + u) * NT;
-            const int p = lds_pad<T>(i >> 1);
-            if (i & 1) sim[p] = v[u]; else sre[p] = v[u];
+            buf.put_part(i >> 1, i & 1, v[u]);
         }
     }
 }
@@ -500,9 +536,8 @@ __device__ __forceinline__ void load_window(const ToepArgs<T>& a, T* __restrict_
 template <typename T, int LOGM, int NT, int MODE>
 __global__ __launch_bounds__(NT) void k_toeplitz(ToepArgs<T> a) {
     constexpr int M = 1 << LOGM;
-    constexpr int MP = M + (M >> (sizeof(T) == 4 ? 5 : 4));
-    __shared__ T sre[MP];
-    __shared__ T sim[MP];
+    __shared__ __align__(16) unsigned char smem[2 * M * sizeof(T)];
+    const CBuf<T> buf = make_cbuf<T>(smem, M);
     if (a.done && *a.done) return;
     const int64_t tile = blockIdx.x;
     const int64_t o = a.tile_out[tile];
@@ -510,15 +545,12 @@ __global__ __launch_bounds__(NT) void k_toeplitz(ToepArgs<T> a) {
     const int j = a.tile_int[tile];
     const int64_t lo = a.int_lo[j], hi = a.int_hi[j];
     const int lam = a.lam;
-    load_window<T, LOGM, NT, MODE>(a, sre, sim, o - lam, L + 2 * lam, lo, hi);
+    load_window<T, LOGM, NT, MODE>(a, buf, o - lam, L + 2 * lam, lo, hi);
     __syncthreads();
-    fwd_passes<T, LOGM, NT, LOGM>(sre, sim, a.tw);
-    spectrum_pass<T, LOGM, NT>(sre, sim, a.H + (int64_t)a.int_kern[j] * (M + 1), a.tw);
-    inv_passes<T, LOGM, NT, LOGM>(sre, sim, a.tw);
-    for (int i = lam + threadIdx.x; i < lam + L; i += NT) {
-        const int p = lds_pad<T>(i >> 1);
-        a.z[o + (i - lam)] = (i & 1) ? sim[p] : sre[p];
-    }
+    fwd_passes<T, LOGM, NT, LOGM>(buf, a.tw);
+    spectrum_pass<T, LOGM, NT>(buf, a.H + (int64_t)a.int_kern[j] * (M + 1), a.tw);
+    inv_passes<T, LOGM, NT, LOGM>(buf, a.tw);
+    for (int i = lam + threadIdx.x; i < lam + L; i += NT) a.z[o + (i - lam)] = buf.get_part(i >> 1, i & 1);
 }
 
 // ------------------------------------------------------------------ plan-time FFTs (FP64)
@@ -526,19 +558,20 @@ __global__ __launch_bounds__(NT) void k_toeplitz(ToepArgs<T> a) {
 // X_m, m = 0..mmax <= M, of the real sequence packed in (re, im) after the forward
 // passes (bit-reversed order): X_m = ((Z_m + conj Z_{M-m}) - i e^{-2 pi i m/N} (Z_m - conj Z_{M-m})) / 2
 template <int LOGM, int NT, class Out>
-__device__ __forceinline__ void real_dft_out(const double* __restrict__ re, const double* __restrict__ im,
-                                             const double* __restrict__ tw, int mmax, Out&& out) {
+__device__ __forceinline__ void real_dft_out(const CBuf<double>& buf, const double* __restrict__ tw,
+                                             int mmax, Out&& out) {
     constexpr int M = 1 << LOGM;
     for (int m = threadIdx.x; m <= mmax; m += NT) {
         double xr, xi;
         if (m == 0 || m == M) {
-            const int a = lds_pad<double>(0);
-            xr = m == 0 ? re[a] + im[a] : re[a] - im[a];
+            double zr, zi;
+            buf.get(0, zr, zi);
+            xr = m == 0 ? zr + zi : zr - zi;
             xi = 0.0;
         } else {
-            const int ak = lds_pad<double>(rev_bits<LOGM>(m));
-            const int am = lds_pad<double>(rev_bits<LOGM>(M - m));
-            const double zkr = re[ak], zki = im[ak], zmr = re[am], zmi = im[am];
+            double zkr, zki, zmr, zmi;
+            buf.get(rev_bits<LOGM>(m), zkr, zki);
+            buf.get(rev_bits<LOGM>(M - m), zmr, zmi);
             const double Ar = zkr + zmr, Ai = zki - zmi, Dr = zkr - zmr, Di = zki + zmi;
             const double er = tw[2 * m], ei = tw[2 * m + 1];
             const double pr = er * Dr - ei * Di, pim = er * Di + ei * Dr;
@@ -558,9 +591,8 @@ __global__ __launch_bounds__(NT) void k_spec_fft(const double* __restrict__ taps
                                                  const double* __restrict__ tw,
                                                  double* __restrict__ H) {
     constexpr int M = 1 << LOGM, NR = 2 * M;
-    constexpr int MP = M + (M >> 4);
-    __shared__ double sre[MP];
-    __shared__ double sim[MP];
+    __shared__ __align__(16) unsigned char smem[2 * M * sizeof(double)];
+    const CBuf<double> buf = make_cbuf<double>(smem, M);
     const int g = blockIdx.x;
     const double* t = taps + toff[g];
     const int K = (int)tcnt[g] - 1;
@@ -568,13 +600,12 @@ __global__ __launch_bounds__(NT) void k_spec_fft(const double* __restrict__ taps
         double v = 0.0;
         if (i <= K) v = t[i];
         else if (i >= NR - K) v = t[NR - i];
-        const int p = lds_pad<double>(i >> 1);
-        if (i & 1) sim[p] = v; else sre[p] = v;
+        buf.put_part(i >> 1, i & 1, v);
     }
     __syncthreads();
-    fwd_passes<double, LOGM, NT, LOGM>(sre, sim, tw);
+    fwd_passes<double, LOGM, NT, LOGM>(buf, tw);
     double* Hg = H + (int64_t)g * (M + 1);
-    real_dft_out<LOGM, NT>(sre, sim, tw, M, [&](int m, double xr, double) { Hg[m] = xr; });
+    real_dft_out<LOGM, NT>(buf, tw, M, [&](int m, double xr, double) { Hg[m] = xr; });
 }
 
 // taps by decimation in time: for an interval of n = R * 2M samples,
@@ -589,9 +620,8 @@ __global__ __launch_bounds__(NT) void k_taps_fft(const int32_t* __restrict__ kid
                                                  const double* __restrict__ tw, int kstride,
                                                  int rmax, double* __restrict__ part) {
     constexpr int M = 1 << LOGM, NR = 2 * M;
-    constexpr int MP = M + (M >> 4);
-    __shared__ double sre[MP];
-    __shared__ double sim[MP];
+    __shared__ __align__(16) unsigned char smem[2 * M * sizeof(double)];
+    const CBuf<double> buf = make_cbuf<double>(smem, M);
     const int gi = blockIdx.y;
     const int g = kid[gi];
     const int64_t n = klen[g];
@@ -609,14 +639,13 @@ __global__ __launch_bounds__(NT) void k_taps_fft(const int32_t* __restrict__ kid
         } else {
             q = 1.0 / (sigma * sigma);
         }
-        const int p = lds_pad<double>(i >> 1);
-        if (i & 1) sim[p] = q; else sre[p] = q;
+        buf.put_part(i >> 1, i & 1, q);
     }
     __syncthreads();
-    fwd_passes<double, LOGM, NT, LOGM>(sre, sim, tw);
+    fwd_passes<double, LOGM, NT, LOGM>(buf, tw);
     const int K = (int)tcnt[g] - 1;
     double* out = part + ((int64_t)gi * rmax + b) * kstride;
-    real_dft_out<LOGM, NT>(sre, sim, tw, K, [&](int k, double xr, double xi) {
+    real_dft_out<LOGM, NT>(buf, tw, K, [&](int k, double xr, double xi) {
         double sn, cs;
         sincospi(2.0 * (double)((int64_t)b * k % n) / (double)n, &sn, &cs);
         out[k] = cs * xr + sn * xi;
@@ -681,6 +710,30 @@ int launch(const ToepArgs<T>& a, int logm, int64_t n_tiles, hipStream_t st) {
     }
     set_error("no overlap-save kernel for log2(M) = %d", logm);
     return MM_ERR_ARG;
+}
+
+// (I, Q, U) per pixel -> (I, Q, U, 0) in T, one aligned 16/32-byte record per pixel
+template <typename T>
+__global__ void k_pack_map(const double* __restrict__ x, int64_t n_obs, T* __restrict__ xp,
+                           const int* __restrict__ done) {
+    if (done && *done) return;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_obs;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        xp[4 * c] = (T)x[3 * c];
+        xp[4 * c + 1] = (T)x[3 * c + 1];
+        xp[4 * c + 2] = (T)x[3 * c + 2];
+        xp[4 * c + 3] = (T)0;
+    }
+}
+
+template <typename T>
+int pack_map(mm_plan_t pl, const double* x, T* xp, const int* done) {
+    int64_t g = (pl->n_obs + 255) / 256;
+    if (g > 8192) g = 8192;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(k_pack_map<T>, dim3(g), dim3(256), 0, pl->stream, x, pl->n_obs, xp, done);
+    MM_HIP(hipGetLastError());
+    return MM_OK;
 }
 
 template <typename T>
@@ -1039,6 +1092,10 @@ int build_tiling(mm_plan_t pl, FftTiling& ft, bool fp64, int n_r_request) {
 int toeplitz_map64(mm_plan_t pl, const double* x, double* z, const int* done) {
     auto a = base_args<double>(pl, pl->fft64);
     a.x = x;
+    if (pl->n_s == 3) {
+        MM_TRY(pack_map<double>(pl, x, pl->xp64.p, done));
+        a.xp = pl->xp64.p;
+    }
     a.mode = pl->n_s == 3 ? 0 : 1;
     a.z = z;
     a.done = done;
@@ -1048,6 +1105,10 @@ int toeplitz_map64(mm_plan_t pl, const double* x, double* z, const int* done) {
 int toeplitz_map32(mm_plan_t pl, const double* x, float* z, const int* done) {
     auto a = base_args<float>(pl, pl->fft32);
     a.x = x;
+    if (pl->n_s == 3) {
+        MM_TRY(pack_map<float>(pl, x, pl->xp32.p, done));
+        a.xp = pl->xp32.p;
+    }
     a.mode = pl->n_s == 3 ? 0 : 1;
     a.z = z;
     a.done = done;
