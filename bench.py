@@ -16,6 +16,7 @@ Prints one JSON line on stdout; progress goes to stderr.
 """
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -34,6 +35,21 @@ BYTES_NINV32 = 4 + 8 + 4     # compact pixel id + (cos, sin) read, z written
 BYTES_PT32 = 4 + 8 + 4       # sorted sample index + sorted (cos, sin) + z gathered
 BYTES_NINV64 = 4 + 16 + 8
 BYTES_PT64 = 4 + 16 + 8
+
+# HBM traffic of the dominant kernel per launch, from two rocprofv3 --pmc runs of this
+# script (FETCH_SIZE, then WRITE_SIZE, median over the launches of the timed solve), each
+# scaled by what the same counter reads for a plain 256 MiB device copy (--copy-calibration):
+# FETCH_SIZE reads 128 MiB for the 256 MiB read (factor 2.0), WRITE_SIZE 256 MiB (factor 1.0).
+# The figures hold only for the kernel source they were taken on (sha256 below); after any
+# change to that file the traffic is reported as null until the counters are taken again.
+TRAFFIC = {
+    "ninv32": dict(source="paper_1408_3048_amd/csrc/toeplitz.hip",
+                   sha256="bd0c4c3ee070d34551ee3de728d7d623f4b2f38a60b4b91d625cebd146c3e279",
+                   fetch_kib=198015.25, write_kib=65576.0, fetch_factor=2.0, write_factor=1.0),
+    "pt32": dict(source="paper_1408_3048_amd/csrc/pointing.hip",
+                 sha256="a03c930bc0d427fb915e4be6c6118e59cc34e488ee306bacc2169a58e0fb81b8",
+                 fetch_kib=151759.125, write_kib=6769.59, fetch_factor=2.0, write_factor=1.0),
+}
 
 
 def log(*a):
@@ -69,6 +85,36 @@ def cpu_baseline(sc, n_ax, n_intervals_sample):
                 t_ax_s=t_ax)
 
 
+def kernel_traffic(name):
+    """HBM bytes per launch of a kernel from the stored counter figures, or None when its
+    source has changed since they were taken."""
+    t = TRAFFIC[name]
+    if t["sha256"] is None:
+        return None
+    with open(os.path.join(ROOT, t["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != t["sha256"]:
+            return None
+    return round(1024 * (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"]))
+
+
+def copy_calibration():
+    """A plain device copy of 256 MiB, three times: the known-size reference for the
+    FETCH_SIZE and WRITE_SIZE counters."""
+    import torch
+    a = torch.ones(2 ** 25, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(3):
+        b.copy_(a)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / 3
+    print(json.dumps(dict(copy_bytes_read=a.numel() * 8, copy_bytes_written=b.numel() * 8,
+                          avg_ms=ms, GBps=2 * a.numel() * 8 / (ms * 1e-3) / 1e9)), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,12 +124,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-intervals", type=int, default=4)
     ap.add_argument("--no-reference", action="store_true", help="skip the FP64 block-Jacobi leg")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run the 256 MiB copy that calibrates the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU path "
               "is a design (interval sharding + a map reduce-scatter), not built.",
               file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     import torch
     import synth
@@ -185,7 +236,7 @@ def main():
     _, avg_ms, bps, kname = cand[dom]
     achieved = bps * sc.n_samples / (avg_ms * 1e-3) / 1e9
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBPS, 4), traffic=None, kernel=kname,
+                frac=round(achieved / HBM_PEAK_GBPS, 4), traffic=kernel_traffic(dom), kernel=kname,
                 avg_launch_ms=round(avg_ms, 5), launches=n_ninv if dom == "ninv32" else n_pt,
                 algorithmic_bytes_per_launch=bps * sc.n_samples,
                 ax_fp32_GBps=round((BYTES_NINV32 + BYTES_PT32) * sc.n_samples /
