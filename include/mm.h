@@ -87,13 +87,18 @@ typedef struct {
                           operator; 0 = automatic */
     int fft_len_f32;   /* same for the FP32 operator; 0 = automatic */
     void* stream;      /* hipStream_t; NULL = default stream */
+    int graph;         /* 1 (default): mm_pcg_solve captures one PCG iteration in a HIP graph
+                          on a plan-owned non-blocking stream and replays it; 0: plain
+                          launches on the caller's stream */
+    int autotune;      /* 1: mm_plan times the candidate FFT lengths on the plan's own data
+                          and keeps the fastest (when fft_len_* is 0); 0 (default): cost model */
 } mm_opts;
 
-/* Fill *opts with the defaults above (n_stokes 3, lambda 1024, f_samp 200). */
+/* Fill *opts with the defaults above (n_stokes 3, lambda 1024, f_samp 200, graph 1). */
 void mm_default_opts(mm_opts* opts);
 
-/* Build a plan for one problem (or several independent problems, see
- * mm_plan_batched) [Sect. 2, Sect. 3, App. C].
+/* Build a plan for one problem [Sect. 2, Sect. 3, App. C]; the same as mm_plan_batched
+ * with one problem.
  *   n_samples           N_t, 1 <= N_t < 2^31
  *   pix                 device int32 [N_t], original pixel id in [0, n_pix)
  *   weights             device [N_t][2] = (cos 2phi_t, sin 2phi_t) of type weights_dtype
@@ -108,6 +113,33 @@ void mm_default_opts(mm_opts* opts);
 int mm_plan(mm_plan_t* out, int64_t n_samples, const int32_t* pix, const void* weights,
             int weights_dtype, int64_t n_pix, int32_t n_intervals,
             const int64_t* interval_offsets, const mm_psd* psd, const mm_opts* opts);
+
+/* Build one plan for n_problems independent problems solved together (many noise
+ * realisations or scans of uneven length): A, M_BD and the coarse space are block
+ * diagonal over the problems, every operator launch covers all problems at once, and
+ * mm_pcg_solve iterates each problem under its own scalars, convergence test and mask
+ * (a problem that has converged takes no further part in the launches).
+ *   problem_intervals   host int32 [n_problems+1]: problem b owns the intervals
+ *                       [problem_intervals[b], problem_intervals[b+1]) and hence the samples
+ *                       [interval_offsets[problem_intervals[b]], ...); 0 = first < ... =
+ *                       n_intervals
+ *   pix                 pixel ids must be disjoint and increasing across problems (every id
+ *                       of problem b below every id of problem b+1; e.g. b * n_pix_b + local
+ *                       id), so that problem b's observed pixels form the compact block
+ *                       [off_b, off_{b+1}) (mm_problem_pixels)
+ * Other arguments as mm_plan.  Each problem's results equal, bit for bit, those of a plan
+ * built for that problem alone with the same FFT lengths.  Errors as mm_plan; MM_ERR_ARG
+ * also for overlapping pixel ranges. */
+int mm_plan_batched(mm_plan_t* out, int32_t n_problems, const int32_t* problem_intervals,
+                    int64_t n_samples, const int32_t* pix, const void* weights,
+                    int weights_dtype, int64_t n_pix, int32_t n_intervals,
+                    const int64_t* interval_offsets, const mm_psd* psd, const mm_opts* opts);
+
+/* Number of problems of the plan (1 for mm_plan); -1 on NULL. */
+int mm_n_problems(mm_plan_t plan);
+/* Host int64 [n_problems+1]: first compact pixel of every problem (map vector entries of
+ * problem b: [n_stokes * off_b, n_stokes * off_{b+1})). */
+int mm_problem_pixels(mm_plan_t plan, int64_t* host_out);
 
 /* Release a plan and all its device memory (NULL is a no-op). */
 void mm_destroy(mm_plan_t plan);
@@ -133,8 +165,11 @@ int mm_interval_taps(mm_plan_t plan, int32_t interval, double* host_out, int cap
 int mm_coarse_rank(mm_plan_t plan);
 /* Host int32 [r_eff]: interval index of every kept column of Z_S. */
 int mm_coarse_columns(mm_plan_t plan, int32_t* host_out, int cap);
-/* Host FP64 [r_eff * r_eff] row-major: E = Z^T A Z restricted to the kept columns. */
+/* Host FP64: E = Z^T A Z restricted to the kept columns, row-major; for a batched plan the
+ * diagonal block of every problem, concatenated (sum of r_b^2 values). */
 int mm_coarse_matrix(mm_plan_t plan, double* host_out, int64_t cap);
+/* Host int32 [n_problems+1]: first kept column of every problem. */
+int mm_coarse_problem_columns(mm_plan_t plan, int32_t* host_out, int cap);
 
 /* ----- operators (all device pointers; see conventions above) ----- */
 
@@ -173,7 +208,8 @@ typedef struct {
     int history_len;       /* entries written */
 } mm_solve_info;
 
-/* Solve A x = b by PCG [Sect. 3] from the initial guess in x (pass zeros for x0 = 0).
+/* Solve A x = b by PCG [Sect. 3] from the initial guess in x (pass zeros for x0 = 0);
+ * for a batched plan every problem b solves A_b x_b = b_b (its block of the vectors).
  *   precond    MM_BJ or MM_2LVL
  *   precision  MM_FP64: FP64 operator; convergence when the recursive and then the true
  *              relative residual are <= tol (otherwise the recursive residual is replaced
@@ -185,10 +221,13 @@ typedef struct {
  *              relative residual is <= tol.
  *              MM_MIXED_IR: classic iterative refinement; each step solves A d = r with
  *              the FP32-operator PCG from d = 0 and updates x += d; r = b - A x is formed
- *              with the FP64 operator; stops when it is <= tol.
- *   tol        relative residual target (> 0);  max_iter: cap on total PCG iterations.
- * Returns MM_OK, MM_ERR_NOCONV, MM_ERR_BREAKDOWN (x holds the last iterate; info filled),
- * MM_ERR_ARG or MM_ERR_STATE.  Synchronises the plan's stream before returning. */
+ *              with the FP64 operator; stops when it is <= tol (single-problem plans).
+ *   tol        relative residual target (> 0) of every problem;
+ *   max_iter   cap on PCG iterations (per problem).
+ *   info       NULL or host array of mm_n_problems(plan) entries, one per problem.
+ * Returns MM_OK when every problem converged, else the status of the first that did not
+ * (MM_ERR_NOCONV, MM_ERR_BREAKDOWN; x holds the last iterates; info filled), or
+ * MM_ERR_ARG / MM_ERR_STATE.  Synchronises the plan's stream before returning. */
 int mm_pcg_solve(mm_plan_t plan, const double* b, double* x, int precond, int precision,
                  double tol, int max_iter, mm_solve_info* info);
 

@@ -33,7 +33,8 @@ EXPORTED = [
     "mm_hits", "mm_sorted_samples", "mm_interval_taps", "mm_coarse_rank", "mm_coarse_columns",
     "mm_coarse_matrix", "mm_apply_P", "mm_apply_Ninv", "mm_apply_PT", "mm_rhs", "mm_apply_A",
     "mm_precond_bj", "mm_precond_2lvl", "mm_pcg_solve", "mm_plan_time_ms", "mm_gemm_tn_f64",
-    "mm_profile", "mm_profile_read", "mm_last_error",
+    "mm_profile", "mm_profile_read", "mm_last_error", "mm_plan_batched", "mm_n_problems",
+    "mm_problem_pixels", "mm_coarse_problem_columns",
 ]
 
 
@@ -52,7 +53,7 @@ class mm_opts(ctypes.Structure):
                 ("window", ctypes.c_int), ("precision", ctypes.c_int), ("coarse", ctypes.c_int),
                 ("rank_tol", ctypes.c_double), ("rcond_min", ctypes.c_double),
                 ("fft_len_f64", ctypes.c_int), ("fft_len_f32", ctypes.c_int),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("graph", ctypes.c_int), ("autotune", ctypes.c_int)]
 
 
 class mm_solve_info(ctypes.Structure):
@@ -102,6 +103,11 @@ def load():
         "mm_profile": (I, [P, I]),
         "mm_profile_read": (I, [P, I, ctypes.POINTER(I64), ctypes.POINTER(D)]),
         "mm_last_error": (ctypes.c_char_p, []),
+        "mm_plan_batched": (I, [ctypes.POINTER(P), I32, P, I64, P, P, I, I64, I32, P, P,
+                                ctypes.POINTER(mm_opts)]),
+        "mm_n_problems": (I, [P]),
+        "mm_problem_pixels": (I, [P, P]),
+        "mm_coarse_problem_columns": (I, [P, P, I]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -135,11 +141,13 @@ def _stream():
 class Plan:
     """Owns an mm_plan_t.  Inputs are torch CUDA tensors (pix int32 [N],
     weights float32/float64 [N, 2] or None) and host arrays (offsets int64 [K+1],
-    psd float64 [K, 3] = (sigma, f_knee, alpha))."""
+    psd float64 [K, 3] = (sigma, f_knee, alpha)).  problem_intervals (int32
+    [B+1]) makes a batched plan of B independent problems (mm_plan_batched)."""
 
     def __init__(self, pix, weights, n_pix, offsets, psd, *, n_stokes=3, lam=1024, f_samp=200.0,
                  window="gauss", precision="fp64", coarse=False, rank_tol=1e-10, rcond_min=1e-8,
-                 fft_len_f64=0, fft_len_f32=0):
+                 fft_len_f64=0, fft_len_f32=0, problem_intervals=None, graph=True,
+                 autotune=False):
         import torch
         L = load()
         self._lib = L
@@ -157,6 +165,8 @@ class Plan:
         opts.fft_len_f64 = int(fft_len_f64)
         opts.fft_len_f32 = int(fft_len_f32)
         opts.stream = _stream()
+        opts.graph = 1 if graph else 0
+        opts.autotune = 1 if autotune else 0
         assert pix.is_cuda and pix.dtype == torch.int32 and pix.is_contiguous()
         wdt = MM_F64
         if weights is not None:
@@ -169,12 +179,21 @@ class Plan:
         self.n_intervals = int(off.shape[0] - 1)
         self.n_stokes = n_stokes
         self.precision = precision
-        st = L.mm_plan(ctypes.byref(self._h), self.n_samples, _ptr(pix), _ptr(weights), wdt,
-                       int(n_pix), self.n_intervals, off.ctypes.data_as(ctypes.c_void_p),
-                       ps.ctypes.data_as(ctypes.c_void_p), ctypes.byref(opts))
+        if problem_intervals is None:
+            st = L.mm_plan(ctypes.byref(self._h), self.n_samples, _ptr(pix), _ptr(weights), wdt,
+                           int(n_pix), self.n_intervals, off.ctypes.data_as(ctypes.c_void_p),
+                           ps.ctypes.data_as(ctypes.c_void_p), ctypes.byref(opts))
+        else:
+            pint = np.ascontiguousarray(problem_intervals, dtype=np.int32)
+            st = L.mm_plan_batched(ctypes.byref(self._h), int(pint.shape[0] - 1),
+                                   pint.ctypes.data_as(ctypes.c_void_p), self.n_samples,
+                                   _ptr(pix), _ptr(weights), wdt, int(n_pix), self.n_intervals,
+                                   off.ctypes.data_as(ctypes.c_void_p),
+                                   ps.ctypes.data_as(ctypes.c_void_p), ctypes.byref(opts))
         check(st)
         self.n_obs = int(L.mm_n_obs(self._h))
         self.n_vec = self.n_obs * n_stokes
+        self.n_problems = int(L.mm_n_problems(self._h))
         self.plan_ms = float(L.mm_plan_time_ms(self._h))
 
     @classmethod
@@ -189,6 +208,8 @@ class Plan:
         psd = np.stack([scan.sigma, scan.fknee, scan.alpha], axis=1)
         kw.setdefault("lam", scan.lam)
         kw.setdefault("f_samp", scan.f_samp)
+        if getattr(scan, "problem_offsets", None) is not None:
+            kw.setdefault("problem_intervals", scan.problem_offsets)
         return cls(pix, w, scan.n_pix, scan.offsets, psd, n_stokes=scan.n_stokes, **kw)
 
     def close(self):
@@ -243,10 +264,35 @@ class Plan:
         self._lib.mm_coarse_columns(self._h, out.ctypes.data_as(ctypes.c_void_p), r)
         return out
 
+    def problem_pixels(self):
+        """Host int64 [B+1]: first compact pixel of every problem."""
+        out = np.empty(self.n_problems + 1, dtype=np.int64)
+        check(self._lib.mm_problem_pixels(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def coarse_problem_columns(self):
+        out = np.empty(self.n_problems + 1, dtype=np.int32)
+        r = self._lib.mm_coarse_problem_columns(self._h, out.ctypes.data_as(ctypes.c_void_p),
+                                                self.n_problems + 1)
+        check(min(r, 0))
+        return out
+
     def coarse_matrix(self):
+        """E restricted to the kept columns (r_eff x r_eff); for a batched plan the list of
+        per-problem diagonal blocks."""
         r = self.coarse_rank()
-        out = np.empty((r, r), dtype=np.float64)
-        self._lib.mm_coarse_matrix(self._h, out.ctypes.data_as(ctypes.c_void_p), r * r)
+        if self.n_problems == 1:
+            out = np.empty((r, r), dtype=np.float64)
+            self._lib.mm_coarse_matrix(self._h, out.ctypes.data_as(ctypes.c_void_p), r * r)
+            return out
+        co = self.coarse_problem_columns()
+        sizes = np.diff(co)
+        flat = np.empty(int((sizes.astype(np.int64) ** 2).sum()), dtype=np.float64)
+        self._lib.mm_coarse_matrix(self._h, flat.ctypes.data_as(ctypes.c_void_p), flat.shape[0])
+        out, o = [], 0
+        for k in sizes:
+            out.append(flat[o:o + k * k].reshape(k, k))
+            o += k * k
         return out
 
     # ---- kernel timing (HIP events on the plan's stream)
@@ -318,22 +364,36 @@ class Plan:
 
     def pcg_solve(self, b, x0=None, precond="bj", precision="fp64", tol=1e-8, max_iter=1000,
                   history=True, raise_on_error=True):
-        """Returns (x, info dict)."""
+        """Returns (x, info dict); for a batched plan info["problems"] lists the info of
+        every problem and the top-level fields are those of problem 0 plus totals."""
         import torch
         x = torch.zeros_like(b) if x0 is None else x0.clone()
-        info = mm_solve_info()
-        hist = np.zeros(max_iter + 8, dtype=np.float64)
-        if history:
-            info.history = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-            info.history_cap = hist.shape[0]
+        B = self.n_problems
+        infos = (mm_solve_info * B)()
+        hists = []
+        for i in range(B):
+            h = np.zeros(max_iter + 8 if history else 1, dtype=np.float64)
+            hists.append(h)
+            if history:
+                infos[i].history = h.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+                infos[i].history_cap = h.shape[0]
         st = self._lib.mm_pcg_solve(self._h, _ptr(b), _ptr(x),
                                     MM_2LVL if precond == "2lvl" else MM_BJ,
                                     {"fp64": MM_FP64, "mixed": MM_MIXED,
                                      "mixed_ir": MM_MIXED_IR}[precision],
-                                    float(tol), int(max_iter), ctypes.byref(info))
-        out = dict(status=st, iterations=info.iterations, outer_iterations=info.outer_iterations,
-                   replacements=info.replacements, rel_residual=info.rel_residual,
-                   solve_ms=info.solve_ms, history=hist[:info.history_len].copy())
+                                    float(tol), int(max_iter), infos)
+        per = [dict(status=infos[i].status, iterations=infos[i].iterations,
+                    outer_iterations=infos[i].outer_iterations,
+                    replacements=infos[i].replacements, rel_residual=infos[i].rel_residual,
+                    solve_ms=infos[i].solve_ms, history=hists[i][:infos[i].history_len].copy())
+               for i in range(B)]
+        out = dict(per[0])
+        out["status"] = st
+        if B > 1:
+            out["problems"] = per
+            out["iterations_max"] = max(p["iterations"] for p in per)
+            out["iterations_sum"] = sum(p["iterations"] for p in per)
+            out["rel_residual_max"] = max(p["rel_residual"] for p in per)
         if raise_on_error and st != MM_OK:
             raise MMError(st, last_error())
         return x, out

@@ -87,30 +87,32 @@ void prof_invalidate(mm_plan_t pl, const size_t* mark, int first_skipped) {
             if (pl->prof_ev[k][i].tag >= first_skipped) pl->prof_ev[k][i].valid = false;
 }
 
-static int apply_A64_tag(mm_plan_t pl, const double* x, double* y, const int* done, int tag) {
+static int apply_A64_tag(mm_plan_t pl, const double* x, double* y, const int* mask, int tag) {
+    MM_TRY(pack_map64(pl, x));
     MM_TRY(prof_begin(pl, MM_K_NINV64, tag));
-    MM_TRY(toeplitz_map64(pl, x, pl->tod64a.p, done));
+    MM_TRY(toeplitz_map64(pl, x, pl->tod64a.p, mask));
     MM_TRY(prof_end(pl, MM_K_NINV64));
     MM_TRY(prof_begin(pl, MM_K_PT64, tag));
-    MM_TRY(scatter64(pl, pl->tod64a.p, y, done));
+    MM_TRY(scatter64(pl, pl->tod64a.p, y, mask));
     return prof_end(pl, MM_K_PT64);
 }
 
-static int apply_A32_tag(mm_plan_t pl, const double* x, double* y, const int* done, int tag) {
+static int apply_A32_tag(mm_plan_t pl, const double* x, double* y, const int* mask, int tag) {
+    MM_TRY(pack_map32(pl, x));
     MM_TRY(prof_begin(pl, MM_K_NINV32, tag));
-    MM_TRY(toeplitz_map32(pl, x, pl->tod32a.p, done));
+    MM_TRY(toeplitz_map32(pl, x, pl->tod32a.p, mask));
     MM_TRY(prof_end(pl, MM_K_NINV32));
     MM_TRY(prof_begin(pl, MM_K_PT32, tag));
-    MM_TRY(scatter32(pl, pl->tod32a.p, y, done));
+    MM_TRY(scatter32(pl, pl->tod32a.p, y, mask));
     return prof_end(pl, MM_K_PT32);
 }
 
-int apply_A64(mm_plan_t pl, const double* x, double* y, const int* done) {
-    return apply_A64_tag(pl, x, y, done, -1);
+int apply_A64(mm_plan_t pl, const double* x, double* y, const int* mask) {
+    return apply_A64_tag(pl, x, y, mask, -1);
 }
 
-int apply_A32(mm_plan_t pl, const double* x, double* y, const int* done) {
-    return apply_A32_tag(pl, x, y, done, -1);
+int apply_A32(mm_plan_t pl, const double* x, double* y, const int* mask) {
+    return apply_A32_tag(pl, x, y, mask, -1);
 }
 
 int gemm_tn_f64(hipStream_t st, const double* A, const double* B, int64_t n, int32_t ra,
@@ -120,8 +122,11 @@ namespace {
 
 using clk = std::chrono::steady_clock;
 
-// mixed precision: replace the recursive residual each time it has dropped this much
+// mixed precision: evaluate the true residual each time the recursive one has dropped
+// by this factor since the last evaluation
 constexpr double kReplaceRatio = 1e-2;
+// iterations launched between two reads of the problem states
+constexpr int kChunk = 4;
 
 double ms_since(clk::time_point t0) {
     return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
@@ -133,189 +138,201 @@ int precond(mm_plan_t pl, int pc, const double* r, double* z, const PcgCtl& ctl,
     return prof_end(pl, MM_K_PRECOND);
 }
 
+void drop_graphs(mm_plan_t pl) {
+    for (auto& row : pl->gexec)
+        for (auto& g : row)
+            if (g) {
+                (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
+}
+
 int ensure_solver_buffers(mm_plan_t pl, int max_iter) {
-    if (pl->rz_hist.n < (size_t)max_iter + 2) MM_TRY(pl->rz_hist.alloc((size_t)max_iter + 2));
-    if (pl->hist.n < (size_t)max_iter + 1) MM_TRY(pl->hist.alloc((size_t)max_iter + 1));
+    const int hs = max_iter + 2;
+    if (pl->hstride < hs) {
+        drop_graphs(pl);  // captured launches hold the old pointers
+        pl->hstride = hs;
+        MM_TRY(pl->rz_hist.alloc((size_t)pl->n_prob * hs));
+        MM_TRY(pl->hist.alloc((size_t)pl->n_prob * hs));
+    }
     return MM_OK;
 }
 
 int read_scalars(mm_plan_t pl) {
-    MM_HIP(hipMemcpyAsync(pl->h_sc, pl->sc.p, sizeof(PcgScalars), hipMemcpyDeviceToHost,
-                          pl->stream));
+    MM_HIP(hipMemcpyAsync(pl->h_sc, pl->sc.p, sizeof(PcgScalars) * pl->n_prob,
+                          hipMemcpyDeviceToHost, pl->stream));
     MM_HIP(hipStreamSynchronize(pl->stream));
     return MM_OK;
 }
 
-// ||v||^2 on the host (deterministic device reduction)
-int norm2(mm_plan_t pl, const double* v, double* out) {
-    double* part = pl->part.p + kSlotAux * kVecBlocks;
-    MM_TRY(vec_dot(pl, v, v, part, nullptr));
-    std::vector<double> h(kVecBlocks);
-    MM_HIP(hipMemcpyAsync(h.data(), part, kVecBlocks * 8, hipMemcpyDeviceToHost, pl->stream));
+// ||v_b||^2 of every problem on the host (partials from the device, summed in order)
+int prob_sq_norms(mm_plan_t pl, const double* v, std::vector<double>& out) {
+    PcgCtl c = batch_ctl(pl);
+    MM_TRY(vec_dot(pl, v, v, kSlotAux, c));
+    const int B = pl->n_prob;
+    std::vector<double> h((size_t)B * kVecBlocks);
+    MM_HIP(hipMemcpyAsync(h.data(), pl->part.p + (size_t)kSlotAux * B * kVecBlocks,
+                          h.size() * 8, hipMemcpyDeviceToHost, pl->stream));
     MM_HIP(hipStreamSynchronize(pl->stream));
-    // same fixed tree as the device prologue reductions is not needed here: a single
-    // sequential host sum is deterministic too
-    double s = 0.0;
-    for (double v2 : h) s += v2;
-    *out = s;
+    out.assign(B, 0.0);
+    for (int b = 0; b < B; ++b)
+        for (int k = 0; k < kVecBlocks; ++k) out[b] += h[(size_t)b * kVecBlocks + k];
     return MM_OK;
 }
 
-struct CoreResult {
-    int iters = 0;
-    int replacements = 0;
-    int status = MM_OK;
-    int hist_len = 0;
+// One PCG iteration for every iterating problem (mask act): q = A p, alpha, x and r,
+// convergence test, z = M r, beta and p.  Launch arguments do not change between
+// iterations, so the sequence can be captured once and replayed.
+int pcg_iteration(mm_plan_t pl, int pc, bool op32, double* x, double* r, double* z, double* p,
+                  double* q, int tag) {
+    PcgCtl c = batch_ctl(pl);
+    c.mask = pl->act.p;
+    MM_TRY(op32 ? apply_A32_tag(pl, p, q, c.mask, tag) : apply_A64_tag(pl, p, q, c.mask, tag));
+    MM_TRY(prof_begin(pl, MM_K_VEC, tag));
+    MM_TRY(vec_dot(pl, p, q, kSlotPQ, c));
+    MM_TRY(pcg_update_xr(pl, x, r, p, q, c));
+    MM_TRY(prof_end(pl, MM_K_VEC));
+    return MM_OK;
+}
+
+struct EngineArgs {
+    int pc = MM_BJ;
+    bool op32 = false;
+    bool x_zero = false;
+    double tol = 1e-8;
+    int max_iter = 1000;
+    bool replace = true;
+    double replace_ratio = 0.0;
 };
 
-// PCG on A x = b from the x passed in.  op32: FP32 operator.  x_zero: x is zero (r = b).
-// replace: on recursive convergence test the FP64 true residual and replace r if needed.
-int pcg_core(mm_plan_t pl, const double* b, double* x, int pc, bool op32, bool x_zero, double tol,
-             int max_iter, bool replace, CoreResult* res, mm_solve_info* info, int hist_off,
-             double replace_ratio = 0.0) {
-    const int64_t n = nvec(pl);
+// the part of an iteration after the x, r update
+int pcg_iteration_tail(mm_plan_t pl, const EngineArgs& ea, double* r, double* z, double* p,
+                       int tag) {
+    PcgCtl c = batch_ctl(pl);
+    c.mask = pl->act.p;
+    c.replace = ea.replace;
+    c.replace_ratio = ea.replace_ratio;
+    c.max_iter = ea.max_iter;
+    MM_TRY(pcg_check(pl, c, 0));
+    MM_TRY(precond(pl, ea.pc, r, z, c, tag));
+    MM_TRY(prof_begin(pl, MM_K_VEC, tag));
+    MM_TRY(pcg_update_p(pl, p, z, c));
+    return prof_end(pl, MM_K_VEC);
+}
+
+int full_iteration(mm_plan_t pl, const EngineArgs& ea, double* x, double* r, double* z, double* p,
+                   double* q, int tag) {
+    MM_TRY(pcg_iteration(pl, ea.pc, ea.op32, x, r, z, p, q, tag));
+    return pcg_iteration_tail(pl, ea, r, z, p, tag);
+}
+
+// PCG on A x_b = b_b for every problem b of the plan, from x (or x = 0 when x_zero).
+// Every decision is taken on the device per problem; the host launches iterations in
+// chunks, reads the problem states between chunks and runs the true-residual evaluation
+// (FP64 operator) for the problems that asked for one.  On return pl->sc holds the
+// per-problem results (state, iterations, evaluations).
+int pcg_engine(mm_plan_t pl, const double* b, double* x, const EngineArgs& ea) {
+    const int B = pl->n_prob;
     double* r = pl->vec[0].p;
     double* z = pl->vec[1].p;
     double* p = pl->vec[2].p;
     double* q = pl->vec[3].p;
-    double* t = pl->vec[4].p;
+    double* xw = pl->vec[4].p;  // iterate (plan-owned, so captured launches stay valid)
+    const int64_t n = nvec(pl);
     hipStream_t st = pl->stream;
-    PcgCtl ctl;
-    ctl.part = pl->part.p;
-    ctl.sc = pl->sc.p;
-    ctl.rz_hist = pl->rz_hist.p;
-    ctl.hist = pl->hist.p;
-    const int* done = &pl->sc.p->done;
-    auto A = [&](const double* in, double* out, const int* dn, int tag = -1) {
-        return op32 ? apply_A32_tag(pl, in, out, dn, tag) : apply_A64_tag(pl, in, out, dn, tag);
-    };
-    size_t mark[MM_K_COUNT];
-    for (int k = 0; k < MM_K_COUNT; ++k) mark[k] = pl->prof_used[k];
-    // r = b - A x
-    if (x_zero) {
+    PcgCtl all = batch_ctl(pl);
+    all.replace = ea.replace;
+    all.replace_ratio = ea.replace_ratio;
+    all.max_iter = ea.max_iter;
+    MM_HIP(hipMemsetAsync(pl->part.p, 0, pl->part.n * sizeof(double), st));
+    if (ea.x_zero) {
+        MM_HIP(hipMemsetAsync(xw, 0, n * 8, st));
         MM_HIP(hipMemcpyAsync(r, b, n * 8, hipMemcpyDeviceToDevice, st));
     } else {
-        MM_TRY(A(x, q, nullptr));
-        MM_TRY(vec_axpby(pl, 1.0, b, -1.0, q, r));
+        MM_HIP(hipMemcpyAsync(xw, x, n * 8, hipMemcpyDeviceToDevice, st));
+        MM_TRY(ea.op32 ? apply_A32(pl, xw, q, nullptr) : apply_A64(pl, xw, q, nullptr));
+        MM_TRY(vec_residual(pl, b, q, r, all));
     }
-    MM_TRY(vec_dot(pl, b, b, pl->part.p + kSlotAux * kVecBlocks, nullptr));
-    MM_TRY(vec_set_scalars(pl, ctl, tol, pl->part.p + kSlotAux * kVecBlocks, 0));
-    // initial residual test
-    MM_TRY(vec_dot(pl, r, r, pl->part.p + kSlotRR * kVecBlocks, nullptr));
-    ctl.iter = 0;
-    ctl.check = 1;
-    ctl.hist = nullptr;
-    MM_TRY(precond(pl, pc, r, z, ctl));
-    ctl.check = 0;
-    ctl.hist = pl->hist.p;
-    ctl.iter = -1;
-    ctl.first = 1;
-    MM_TRY(pcg_update_p(pl, p, z, ctl));
-    ctl.first = 0;
+    MM_TRY(vec_dot(pl, b, b, kSlotAux, all));
+    MM_TRY(pcg_init(pl, all, ea.tol, 1));
+    MM_TRY(vec_zero_flagged(pl, xw, pl->sel.p, all));  // b_b = 0: x_b = 0 exactly
+    MM_TRY(pcg_resume(pl, all));                          // clears the flags
+    PcgCtl ca = all;
+    ca.mask = pl->act.p;
+    MM_TRY(vec_dot(pl, r, r, kSlotRR, ca));
+    MM_TRY(pcg_check(pl, ca, 1));
+    MM_TRY(precond(pl, ea.pc, r, z, ca));
+    ca.first = 1;
+    MM_TRY(pcg_update_p(pl, p, z, ca));
     MM_TRY(read_scalars(pl));
-    if (pl->h_sc->done) {  // b - A x0 already small enough
-        res->iters = 0;
-        res->status = MM_OK;
-        return MM_OK;
+    auto count = [&](int state) {
+        int k = 0;
+        for (int i = 0; i < B; ++i) k += pl->h_sc[i].state == state;
+        return k;
+    };
+    // graph of one iteration for this operator / preconditioner and control arguments
+    const bool use_graph = pl->opts.graph != 0 && !pl->prof_on && pl->gstream != nullptr &&
+                           pl->stream == pl->gstream;
+    const int gi = ea.op32 ? 1 : 0, gj = ea.pc == MM_2LVL ? 1 : 0;
+    hipGraphExec_t& gx = pl->gexec[gi][gj];
+    auto& key = pl->gkey[gi][gj];
+    if (use_graph && gx &&
+        (key.replace != (int)ea.replace || key.ratio != ea.replace_ratio ||
+         key.max_iter != ea.max_iter)) {
+        (void)hipGraphExecDestroy(gx);
+        gx = nullptr;
     }
-    int i = 0;
-    const int chunk = 4;
-    double last_rel = 1.0;
-    while (i < max_iter) {
-        const int i_end = std::min(max_iter, i + chunk);
-        for (int it = i; it < i_end; ++it) {
-            ctl.iter = it;
-            MM_TRY(A(p, q, done, it));
-            MM_TRY(prof_begin(pl, MM_K_VEC, it));
-            MM_TRY(vec_dot(pl, p, q, pl->part.p + kSlotPQ * kVecBlocks, done));
-            MM_TRY(pcg_update_xr(pl, x, r, p, q, ctl));
-            MM_TRY(prof_end(pl, MM_K_VEC));
-            ctl.check = 1;
-            MM_TRY(precond(pl, pc, r, z, ctl, it));
-            ctl.check = 0;
-            MM_TRY(prof_begin(pl, MM_K_VEC, it));
-            MM_TRY(pcg_update_p(pl, p, z, ctl));
-            MM_TRY(prof_end(pl, MM_K_VEC));
+    if (use_graph && !gx) {
+        hipGraph_t g = nullptr;
+        MM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        const int s1 = full_iteration(pl, ea, xw, r, z, p, q, -1);
+        const hipError_t e1 = hipStreamEndCapture(st, &g);
+        if (s1 != MM_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return s1;
+        }
+        MM_HIP(e1);
+        const hipError_t e2 = hipGraphInstantiate(&gx, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e2 != hipSuccess) gx = nullptr;
+        MM_HIP(e2);
+        key.replace = (int)ea.replace;
+        key.ratio = ea.replace_ratio;
+        key.max_iter = ea.max_iter;
+    }
+    const bool graph_ok = use_graph && gx;
+    int host_it = 0;
+    const int guard = 4 * ea.max_iter + 64;
+    for (int loop = 0; count(kActive) > 0; ++loop) {
+        if (loop > guard) {
+            set_error("PCG driver did not terminate");
+            return MM_ERR_DEVICE;
+        }
+        size_t mark[MM_K_COUNT];
+        for (int k = 0; k < MM_K_COUNT; ++k) mark[k] = pl->prof_used[k];
+        const int it0 = B == 1 ? pl->h_sc[0].iter : 0;
+        const int chunk_start = host_it;
+        for (int c = 0; c < kChunk; ++c, ++host_it) {
+            if (graph_ok) MM_HIP(hipGraphLaunch(gx, st));
+            else MM_TRY(full_iteration(pl, ea, xw, r, z, p, q, host_it));
         }
         MM_TRY(read_scalars(pl));
-        i = i_end;
-        if (!pl->h_sc->done) {
-            // reliable update: the recursive residual has fallen by replace_ratio since the
-            // last replacement -> replace it by the FP64 true residual, keep p
-            if (replace_ratio > 0.0) {
-                const double rel = std::sqrt(pl->h_sc->rr) / pl->h_sc->bnorm;
-                if (rel < replace_ratio * last_rel) {
-                    const int ndone = pl->h_sc->iter;
-                    MM_TRY(apply_A64(pl, x, q, nullptr));
-                    MM_TRY(vec_axpby(pl, 1.0, b, -1.0, q, r));
-                    double rr = 0.0;
-                    MM_TRY(norm2(pl, r, &rr));
-                    last_rel = std::sqrt(rr) / pl->h_sc->bnorm;
-                    res->replacements++;
-                    if (last_rel <= tol) {
-                        res->iters = ndone;
-                        res->hist_len = ndone;
-                        res->status = MM_OK;
-                        return MM_OK;
-                    }
-                    PcgCtl c2 = ctl;
-                    c2.iter = ndone - 1;
-                    c2.check = 0;
-                    c2.hist = nullptr;
-                    MM_TRY(precond(pl, pc, r, z, c2));
-                    c2.rz_only = 1;
-                    MM_TRY(pcg_update_p(pl, p, z, c2));
-                }
-            }
-            continue;
+        if (B == 1) prof_invalidate(pl, mark, chunk_start + (pl->h_sc[0].iter - it0));
+        if (count(kCheck) > 0) {
+            // true residual b - A x (FP64 operator) of the problems that asked for it
+            PcgCtl cs = all;
+            cs.mask = pl->sel.p;
+            MM_TRY(pcg_select(pl, all));
+            MM_TRY(apply_A64(pl, xw, q, pl->sel.p));
+            MM_TRY(vec_residual(pl, b, q, r, cs));
+            MM_TRY(pcg_decide(pl, cs));
+            MM_TRY(precond(pl, ea.pc, r, z, cs));
+            MM_TRY(pcg_update_p(pl, p, z, cs));
+            MM_TRY(pcg_resume(pl, all));
+            MM_TRY(read_scalars(pl));
         }
-        const int ndone = pl->h_sc->iter;
-        prof_invalidate(pl, mark, ndone);
-        res->iters = ndone;
-        res->hist_len = ndone;
-        if (pl->h_sc->status != 0) {
-            res->status = MM_ERR_BREAKDOWN;
-            set_error("PCG breakdown at iteration %d (p^T A p = %g)", ndone, pl->h_sc->pq);
-            return MM_OK;
-        }
-        if (!replace) {
-            res->status = MM_OK;
-            return MM_OK;
-        }
-        // true residual with the FP64 operator
-        MM_TRY(apply_A64(pl, x, q, nullptr));
-        MM_TRY(vec_axpby(pl, 1.0, b, -1.0, q, t));
-        double rr = 0.0;
-        MM_TRY(norm2(pl, t, &rr));
-        const double rel = std::sqrt(rr) / pl->h_sc->bnorm;
-        last_rel = rel;
-        if (rel <= tol) {
-            res->status = MM_OK;
-            return MM_OK;
-        }
-        // residual replacement, then continue from iteration ndone
-        res->replacements++;
-        MM_HIP(hipMemcpyAsync(r, t, n * 8, hipMemcpyDeviceToDevice, st));
-        const int zero = 0;
-        MM_HIP(hipMemcpyAsync(&pl->sc.p->done, &zero, sizeof(int), hipMemcpyHostToDevice, st));
-        ctl.iter = ndone - 1;
-        ctl.check = 0;
-        PcgCtl c2 = ctl;
-        c2.hist = nullptr;
-        MM_TRY(precond(pl, pc, r, z, c2));
-        MM_TRY(pcg_update_p(pl, p, z, ctl));
-        i = ndone;
     }
-    MM_TRY(read_scalars(pl));
-    res->iters = pl->h_sc->iter;
-    res->hist_len = res->iters;
-    if (pl->h_sc->done && pl->h_sc->status == 0 && !replace) {
-        res->status = MM_OK;
-        return MM_OK;
-    }
-    res->status = pl->h_sc->status ? MM_ERR_BREAKDOWN : MM_ERR_NOCONV;
-    if (res->status == MM_ERR_NOCONV)
-        set_error("PCG did not converge in %d iterations", max_iter);
+    MM_HIP(hipMemcpyAsync(x, xw, n * 8, hipMemcpyDeviceToDevice, st));
     return MM_OK;
 }
 
@@ -338,6 +355,13 @@ using namespace mm;
 
 mm_plan_s::~mm_plan_s() {
     if (h_sc) (void)hipHostFree(h_sc);
+    for (auto& row : gexec)
+        for (auto& g : row)
+            if (g) (void)hipGraphExecDestroy(g);
+    if (gstream) {
+        (void)hipStreamSynchronize(gstream);
+        (void)hipStreamDestroy(gstream);
+    }
     for (auto& v : prof_ev)
         for (auto& r : v) {
             (void)hipEventDestroy(r.a);
@@ -363,11 +387,28 @@ void mm_default_opts(mm_opts* o) {
     o->fft_len_f64 = 0;
     o->fft_len_f32 = 0;
     o->stream = nullptr;
+    o->graph = 1;
+    o->autotune = 0;
 }
 
 int mm_plan(mm_plan_t* out, int64_t n_samples, const int32_t* pix, const void* weights,
             int weights_dtype, int64_t n_pix, int32_t n_intervals,
             const int64_t* interval_offsets, const mm_psd* psd, const mm_opts* opts) {
+    if (n_intervals < 1) {
+        clear_error();
+        if (out) *out = nullptr;
+        set_error("n_intervals must be >= 1");
+        return MM_ERR_ARG;
+    }
+    const int32_t pint[2] = {0, n_intervals};
+    return mm_plan_batched(out, 1, pint, n_samples, pix, weights, weights_dtype, n_pix,
+                           n_intervals, interval_offsets, psd, opts);
+}
+
+int mm_plan_batched(mm_plan_t* out, int32_t n_problems, const int32_t* problem_intervals,
+                    int64_t n_samples, const int32_t* pix, const void* weights,
+                    int weights_dtype, int64_t n_pix, int32_t n_intervals,
+                    const int64_t* interval_offsets, const mm_psd* psd, const mm_opts* opts) {
     clear_error();
     const auto t0 = clk::now();
     if (!out) {
@@ -420,6 +461,17 @@ int mm_plan(mm_plan_t* out, int64_t n_samples, const int32_t* pix, const void* w
             return MM_ERR_ARG;
         }
     }
+    if (n_problems < 1 || !problem_intervals || problem_intervals[0] != 0 ||
+        problem_intervals[n_problems] != n_intervals) {
+        set_error("problem_intervals must be given for n_problems >= 1 problems, from 0 to "
+                  "n_intervals");
+        return MM_ERR_ARG;
+    }
+    for (int32_t b = 0; b < n_problems; ++b)
+        if (problem_intervals[b + 1] <= problem_intervals[b]) {
+            set_error("problem_intervals not strictly increasing at %d", b);
+            return MM_ERR_ARG;
+        }
     if (opts->lambda < 0 || !(opts->f_samp > 0.0) || opts->window < 0 || opts->window > 2 ||
         (opts->precision != MM_FP64 && opts->precision != MM_MIXED) ||
         (opts->coarse != MM_COARSE_NONE && opts->coarse != MM_COARSE_ZS) ||
@@ -440,6 +492,10 @@ int mm_plan(mm_plan_t* out, int64_t n_samples, const int32_t* pix, const void* w
     pl->n_int = n_intervals;
     pl->h_off.assign(interval_offsets, interval_offsets + n_intervals + 1);
     pl->h_psd.assign(psd, psd + n_intervals);
+    pl->n_prob = n_problems;
+    pl->h_pint.assign(problem_intervals, problem_intervals + n_problems + 1);
+    pl->h_samp.resize(n_problems + 1);
+    for (int32_t b = 0; b <= n_problems; ++b) pl->h_samp[b] = interval_offsets[problem_intervals[b]];
     pl->stream = (hipStream_t)opts->stream;
     AllocStream alloc_scope(pl->stream);
     if (hipGetDevice(&pl->device) != hipSuccess) {
@@ -454,6 +510,7 @@ int mm_plan(mm_plan_t* out, int64_t n_samples, const int32_t* pix, const void* w
         std::fprintf(stderr, "[mm_plan] %-10s %8.3f ms\n", what, ms_since(t0));
     };
     if ((s = build_pointing(pl, pix, weights, weights_dtype)) != MM_OK) return fail(s);
+    if ((s = build_batch_layout(pl)) != MM_OK) return fail(s);
     tick("pointing");
     if ((s = build_kernels(pl)) != MM_OK) return fail(s);
     tick("taps");
@@ -472,9 +529,12 @@ int mm_plan(mm_plan_t* out, int64_t n_samples, const int32_t* pix, const void* w
     if (mixed && (s = pl->tod32a.alloc(pl->n_t)) != MM_OK) return fail(s);
     for (auto& v : pl->vec)
         if ((s = v.alloc(n)) != MM_OK) return fail(s);
-    if ((s = pl->part.alloc(kNumSlots * kVecBlocks)) != MM_OK) return fail(s);
-    if ((s = pl->sc.alloc(1)) != MM_OK) return fail(s);
-    if (hipHostMalloc((void**)&pl->h_sc, sizeof(PcgScalars), hipHostMallocDefault) != hipSuccess) {
+    if ((s = pl->part.alloc((size_t)kNumSlots * pl->n_prob * kVecBlocks)) != MM_OK) return fail(s);
+    if ((s = pl->sc.alloc(pl->n_prob)) != MM_OK) return fail(s);
+    if ((s = pl->act.alloc(pl->n_prob)) != MM_OK) return fail(s);
+    if ((s = pl->sel.alloc(pl->n_prob)) != MM_OK) return fail(s);
+    if (hipHostMalloc((void**)&pl->h_sc, sizeof(PcgScalars) * pl->n_prob, hipHostMallocDefault) !=
+        hipSuccess) {
         pl->h_sc = nullptr;
         set_error("hipHostMalloc failed");
         return fail(MM_ERR_DEVICE);
@@ -499,6 +559,17 @@ void mm_destroy(mm_plan_t pl) {
 }
 
 int64_t mm_n_obs(mm_plan_t pl) { return pl ? pl->n_obs : -1; }
+int mm_n_problems(mm_plan_t pl) { return pl ? pl->n_prob : -1; }
+
+int mm_problem_pixels(mm_plan_t pl, int64_t* host_out) {
+    clear_error();
+    if (!pl || !host_out) {
+        set_error("NULL argument");
+        return MM_ERR_ARG;
+    }
+    for (int b = 0; b <= pl->n_prob; ++b) host_out[b] = pl->h_ooff[b];
+    return MM_OK;
+}
 int mm_n_stokes(mm_plan_t pl) { return pl ? pl->n_s : -1; }
 
 int mm_obs_pixels(mm_plan_t pl, int32_t* dev_out) {
@@ -515,7 +586,19 @@ int mm_hits(mm_plan_t pl, int32_t* dev_out) {
 
 int mm_sorted_samples(mm_plan_t pl, int32_t* dev_out) {
     MM_TRY(check_vec_args(pl, dev_out, dev_out));
-    MM_HIP(hipMemcpyAsync(dev_out, pl->perm.p, pl->n_t * 4, hipMemcpyDeviceToDevice, pl->stream));
+    if (pl->n_prob == 1) {
+        MM_HIP(hipMemcpyAsync(dev_out, pl->perm.p, pl->n_t * 4, hipMemcpyDeviceToDevice,
+                              pl->stream));
+        return MM_OK;
+    }
+    // without the alignment gaps between problems
+    int64_t o = 0;
+    for (int b = 0; b < pl->n_prob; ++b) {
+        const int64_t len = pl->h_samp[b + 1] - pl->h_samp[b];
+        MM_HIP(hipMemcpyAsync(dev_out + o, pl->perm.p + pl->h_soff[b], len * 4,
+                              hipMemcpyDeviceToDevice, pl->stream));
+        o += len;
+    }
     return MM_OK;
 }
 
@@ -552,7 +635,14 @@ int mm_coarse_columns(mm_plan_t pl, int32_t* host_out, int cap) {
 int mm_coarse_matrix(mm_plan_t pl, double* host_out, int64_t cap) {
     const int r = mm_coarse_rank(pl);
     if (r < 0) return r;
-    for (int64_t e = 0; e < (int64_t)r * r && e < cap; ++e) host_out[e] = pl->co.E[e];
+    for (int64_t e = 0; e < (int64_t)pl->co.E.size() && e < cap; ++e) host_out[e] = pl->co.E[e];
+    return r;
+}
+
+int mm_coarse_problem_columns(mm_plan_t pl, int32_t* host_out, int cap) {
+    const int r = mm_coarse_rank(pl);
+    if (r < 0) return r;
+    for (int b = 0; b <= pl->n_prob && b < cap; ++b) host_out[b] = pl->co.h_col_off[b];
     return r;
 }
 
@@ -644,7 +734,9 @@ int mm_apply_A(mm_plan_t pl, const double* x, double* y, int precision) {
 int mm_precond_bj(mm_plan_t pl, const double* r, double* z) {
     clear_error();
     MM_TRY(check_vec_args(pl, r, z));
-    return bj_apply(pl, r, z, PcgCtl{});
+    PcgCtl c = batch_ctl(pl);
+    c.part = nullptr;
+    return bj_apply(pl, r, z, c);
 }
 
 int mm_precond_2lvl(mm_plan_t pl, const double* r, double* z) {
@@ -658,7 +750,9 @@ int mm_precond_2lvl(mm_plan_t pl, const double* r, double* z) {
         set_error("r and z may not alias");
         return MM_ERR_ARG;
     }
-    return twolvl_apply(pl, r, z, PcgCtl{});
+    PcgCtl c = batch_ctl(pl);
+    c.part = nullptr;
+    return twolvl_apply(pl, r, z, c);
 }
 
 int mm_pcg_solve(mm_plan_t pl, const double* b, double* x, int pc, int precision, double tol,
@@ -681,6 +775,10 @@ int mm_pcg_solve(mm_plan_t pl, const double* b, double* x, int pc, int precision
         set_error("mixed solve requested from a plan built with precision MM_FP64");
         return MM_ERR_STATE;
     }
+    if (precision == MM_MIXED_IR && pl->n_prob > 1) {
+        set_error("MM_MIXED_IR is available for single-problem plans only");
+        return MM_ERR_ARG;
+    }
     if (!(tol > 0.0) || max_iter < 1) {
         set_error("tol must be > 0 and max_iter >= 1");
         return MM_ERR_ARG;
@@ -690,94 +788,140 @@ int mm_pcg_solve(mm_plan_t pl, const double* b, double* x, int pc, int precision
         return MM_ERR_ARG;
     }
     const auto t0 = clk::now();
-    AllocStream alloc_scope(pl->stream);
+    const int B = pl->n_prob;
+    // the solve runs on the plan's own non-blocking stream (graph capture needs one),
+    // ordered after the caller's stream and synchronised before returning
+    hipStream_t user = pl->stream;
+    AllocStream alloc_scope(user);  // plan buffers always live on the caller's stream
     MM_TRY(ensure_solver_buffers(pl, max_iter));
-    mm_solve_info loc{};
-    if (!info) info = &loc;
-    info->iterations = 0;
-    info->outer_iterations = 0;
-    info->replacements = 0;
-    info->history_len = 0;
-    int status = MM_OK;
-    std::vector<double> hist_all;
+    if (pl->opts.graph && !pl->gstream)
+        MM_HIP(hipStreamCreateWithFlags(&pl->gstream, hipStreamNonBlocking));
+    if (pl->opts.graph) {
+        MM_HIP(hipStreamSynchronize(user));
+        pl->stream = pl->gstream;
+    }
+    struct Restore {
+        mm_plan_t pl;
+        hipStream_t user;
+        ~Restore() {
+            (void)hipStreamSynchronize(pl->stream);
+            pl->stream = user;
+        }
+    } restore{pl, user};
+    std::vector<mm_solve_info> loc(B);
+    mm_solve_info* inf = info ? info : loc.data();
+    for (int i = 0; i < B; ++i) {
+        inf[i].iterations = 0;
+        inf[i].outer_iterations = 0;
+        inf[i].replacements = 0;
+        inf[i].history_len = 0;
+    }
+    std::vector<int> status(B, MM_OK);
+    std::vector<std::vector<double>> hist_all(B);
+    auto fetch_hist = [&](int bprob, int len, double scale) -> int {
+        if (len <= 0) return MM_OK;
+        std::vector<double> h(len);
+        MM_HIP(hipMemcpy(h.data(), pl->hist.p + (size_t)bprob * pl->hstride, len * 8,
+                         hipMemcpyDeviceToHost));
+        for (double v : h) hist_all[bprob].push_back(v * scale);
+        return MM_OK;
+    };
     if (precision == MM_FP64 || precision == MM_MIXED) {
-        const bool op32 = precision == MM_MIXED;
-        CoreResult res;
-        MM_TRY(pcg_core(pl, b, x, pc, op32, false, tol, max_iter, true, &res, info, 0,
-                        op32 ? kReplaceRatio : 0.0));
-        info->iterations = res.iters;
-        info->outer_iterations = 1;
-        info->replacements = res.replacements;
-        status = res.status;
-        if (res.hist_len > 0) {
-            hist_all.resize(res.hist_len);
-            MM_HIP(hipMemcpy(hist_all.data(), pl->hist.p, res.hist_len * 8, hipMemcpyDeviceToHost));
+        EngineArgs ea;
+        ea.pc = pc;
+        ea.op32 = precision == MM_MIXED;
+        ea.x_zero = false;
+        ea.tol = tol;
+        ea.max_iter = max_iter;
+        ea.replace = true;
+        ea.replace_ratio = ea.op32 ? kReplaceRatio : 0.0;
+        MM_TRY(pcg_engine(pl, b, x, ea));
+        MM_TRY(read_scalars(pl));
+        for (int i = 0; i < B; ++i) {
+            const PcgScalars& sc = pl->h_sc[i];
+            inf[i].iterations = sc.iter;
+            inf[i].outer_iterations = 1;
+            inf[i].replacements = sc.evals;
+            status[i] = sc.state == kDone ? MM_OK
+                        : sc.state == kBreakdown ? MM_ERR_BREAKDOWN : MM_ERR_NOCONV;
+            MM_TRY(fetch_hist(i, sc.iter, 1.0));
         }
     } else {
-        // iterative refinement: r = b - A64 x; solve A32 d = r by PCG; x += d
+        // iterative refinement: r = b - A64 x; solve A32 d = r by PCG from d = 0; x += d
         const int64_t n = nvec(pl);
-        double bb = 0.0;
-        MM_TRY(norm2(pl, b, &bb));
-        const double bn = std::sqrt(bb);
+        std::vector<double> bb;
+        MM_TRY(prob_sq_norms(pl, b, bb));
+        const double bn = std::sqrt(bb[0]);
         double* rout = pl->vec[5].p;
         double* d = pl->vec[6].p;
         double* tq = pl->vec[7].p;
         int total = 0;
-        status = MM_ERR_NOCONV;
+        status[0] = MM_ERR_NOCONV;
         for (int outer = 0; outer < 30 && total < max_iter; ++outer) {
             MM_TRY(apply_A64(pl, x, tq, nullptr));
             MM_TRY(vec_axpby(pl, 1.0, b, -1.0, tq, rout));
-            double rr = 0.0;
-            MM_TRY(norm2(pl, rout, &rr));
-            const double rel = bn > 0.0 ? std::sqrt(rr) / bn : 0.0;
-            info->outer_iterations = outer;
+            std::vector<double> rr;
+            MM_TRY(prob_sq_norms(pl, rout, rr));
+            const double rel = bn > 0.0 ? std::sqrt(rr[0]) / bn : 0.0;
+            inf[0].outer_iterations = outer;
             if (rel <= tol) {
-                status = MM_OK;
+                status[0] = MM_OK;
                 break;
             }
             double eta = 0.1 * tol / rel;
             if (eta < 1e-6) eta = 1e-6;
             if (eta > 0.5) eta = 0.5;
-            MM_HIP(hipMemsetAsync(d, 0, n * 8, pl->stream));
-            CoreResult res;
-            MM_TRY(pcg_core(pl, rout, d, pc, true, true, eta, max_iter - total, false, &res, info, 0));
-            if (res.hist_len > 0) {
-                std::vector<double> h(res.hist_len);
-                MM_HIP(hipMemcpy(h.data(), pl->hist.p, res.hist_len * 8, hipMemcpyDeviceToHost));
-                for (double v : h) hist_all.push_back(v * rel);  // relative to ||b||
-            }
-            total += res.iters;
+            EngineArgs ea;
+            ea.pc = pc;
+            ea.op32 = true;
+            ea.x_zero = true;
+            ea.tol = eta;
+            ea.max_iter = max_iter - total;
+            ea.replace = false;
+            MM_TRY(pcg_engine(pl, rout, d, ea));
+            MM_TRY(read_scalars(pl));
+            const PcgScalars& sc = pl->h_sc[0];
+            MM_TRY(fetch_hist(0, sc.iter, rel));  // relative to ||b||
+            total += sc.iter;
             MM_TRY(vec_axpby(pl, 1.0, x, 1.0, d, x));
-            if (res.status == MM_ERR_BREAKDOWN) {
-                status = MM_ERR_BREAKDOWN;
+            if (sc.state == kBreakdown) {
+                status[0] = MM_ERR_BREAKDOWN;
                 break;
             }
-            info->outer_iterations = outer + 1;
+            inf[0].outer_iterations = outer + 1;
         }
-        info->iterations = total;
+        inf[0].iterations = total;
     }
-    // final true residual (FP64 operator)
+    // final true residual of every problem (FP64 operator)
     {
-        double bb = 0.0, rr = 0.0;
-        MM_TRY(norm2(pl, b, &bb));
+        PcgCtl all = batch_ctl(pl);
+        MM_TRY(vec_dot(pl, b, b, kSlotAux, all));
+        MM_TRY(pcg_init(pl, all, tol, 0));  // bnorm per problem
         MM_TRY(apply_A64(pl, x, pl->vec[3].p, nullptr));
-        MM_TRY(vec_axpby(pl, 1.0, b, -1.0, pl->vec[3].p, pl->vec[4].p));
-        MM_TRY(norm2(pl, pl->vec[4].p, &rr));
-        info->rel_residual = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
-        if (status == MM_ERR_NOCONV && info->rel_residual <= tol) status = MM_OK;
+        MM_TRY(vec_residual(pl, b, pl->vec[3].p, pl->vec[4].p, all));
+        MM_TRY(pcg_final(pl, all));
+        MM_TRY(read_scalars(pl));
     }
-    if (info->history && info->history_cap > 0) {
-        const int m = std::min<int>(info->history_cap, (int)hist_all.size());
-        for (int k = 0; k < m; ++k) info->history[k] = hist_all[k];
-        info->history_len = m;
+    int ret = MM_OK;
+    for (int i = 0; i < B; ++i) {
+        inf[i].rel_residual = pl->h_sc[i].rel;
+        if (status[i] == MM_ERR_NOCONV && inf[i].rel_residual <= tol) status[i] = MM_OK;
+        if (inf[i].history && inf[i].history_cap > 0) {
+            const int m = std::min<int>(inf[i].history_cap, (int)hist_all[i].size());
+            for (int k = 0; k < m; ++k) inf[i].history[k] = hist_all[i][k];
+            inf[i].history_len = m;
+        }
+        inf[i].status = status[i];
+        if (status[i] != MM_OK && ret == MM_OK) ret = status[i];
     }
     MM_HIP(hipStreamSynchronize(pl->stream));
-    info->solve_ms = ms_since(t0);
-    info->status = status;
-    if (status == MM_ERR_NOCONV && g_err.empty())
-        set_error("no convergence to %g within %d iterations (relres %g)", tol, max_iter,
-                  info->rel_residual);
-    return status;
+    const double ms = ms_since(t0);
+    for (int i = 0; i < B; ++i) inf[i].solve_ms = ms;
+    if (ret == MM_ERR_NOCONV && g_err.empty())
+        set_error("no convergence to %g within %d iterations", tol, max_iter);
+    if (ret == MM_ERR_BREAKDOWN && g_err.empty())
+        set_error("PCG breakdown (p^T A p <= 0 or not finite)");
+    return ret;
 }
 
 double mm_plan_time_ms(mm_plan_t pl) { return pl ? pl->plan_ms : -1.0; }

@@ -46,13 +46,14 @@ __device__ __forceinline__ int32_t interval_of(const int64_t* __restrict__ lo, i
 
 // number of distinct intervals among each pixel's samples (ascending in t)
 __global__ void k_zs_count(const int32_t* __restrict__ perm, const int64_t* __restrict__ seg,
-                           int64_t n_obs, const int64_t* __restrict__ int_lo, int32_t n_int,
+                           const int32_t* __restrict__ hits, int64_t n_obs,
+                           const int64_t* __restrict__ int_lo, int32_t n_int,
                            int64_t* __restrict__ nnz) {
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_obs;
          c += (int64_t)gridDim.x * blockDim.x) {
         int64_t cnt = 0;
         int32_t last = -1;
-        for (int64_t i = seg[c]; i < seg[c + 1]; ++i) {
+        for (int64_t i = seg[c]; i < seg[c] + hits[c]; ++i) {
             const int32_t j = interval_of(int_lo, n_int, perm[i]);
             if (j != last) {
                 ++cnt;
@@ -64,16 +65,17 @@ __global__ void k_zs_count(const int32_t* __restrict__ perm, const int64_t* __re
 }
 
 __global__ void k_zs_fill(const int32_t* __restrict__ perm, const int64_t* __restrict__ seg,
-                          int64_t n_obs, const int64_t* __restrict__ int_lo, int32_t n_int,
+                          const int32_t* __restrict__ hits, int64_t n_obs,
+                          const int64_t* __restrict__ int_lo, int32_t n_int,
                           const int64_t* __restrict__ ptr, int32_t* __restrict__ col,
                           double* __restrict__ val) {
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_obs;
          c += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t s = seg[c + 1] - seg[c];
+        const int64_t s = hits[c];
         int64_t o = ptr[c];
         int32_t last = -1;
         int64_t run = 0;
-        for (int64_t i = seg[c]; i < seg[c + 1]; ++i) {
+        for (int64_t i = seg[c]; i < seg[c] + s; ++i) {
             const int32_t j = interval_of(int_lo, n_int, perm[i]);
             if (j != last) {
                 if (last >= 0) {
@@ -94,18 +96,41 @@ __global__ void k_zs_fill(const int32_t* __restrict__ perm, const int64_t* __res
 }
 
 
-__global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        b[i] = (float)a[i];
-}
-
-// scatter column entries (pixel, value) into a zeroed map vector (I rows)
-__global__ void k_col_to_vec(const int32_t* __restrict__ rows, const double* __restrict__ vals,
-                             int64_t cnt, int ns, double* __restrict__ out) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
+// scatter the entries (pixel, value) of the columns ucol[0..gridDim.y) into a zeroed map
+// vector (I rows); the columns of one layer belong to different problems
+__global__ void k_cols_to_vec(const int32_t* __restrict__ ucol, const int64_t* __restrict__ uptr,
+                              const int32_t* __restrict__ rows, const double* __restrict__ vals,
+                              int ns, double* __restrict__ out) {
+    const int32_t u = ucol[blockIdx.y];
+    for (int64_t i = uptr[u] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < uptr[u + 1];
          i += (int64_t)gridDim.x * blockDim.x)
         out[(int64_t)rows[i] * ns] = vals[i];
+}
+
+// copy problem lp[y]'s slice of the map vector y into column `col` of its AZ block
+template <typename TA>
+__global__ void k_store_az(const int32_t* __restrict__ lp, const double* __restrict__ y,
+                           const int64_t* __restrict__ ooff, int ns,
+                           const int64_t* __restrict__ blk_off, int32_t col,
+                           TA* __restrict__ az) {
+    const int32_t b = lp[blockIdx.y];
+    const int64_t v0 = ooff[b] * ns, n = (ooff[b + 1] - ooff[b]) * ns;
+    TA* dst = az + blk_off[b] + (int64_t)col * n;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = (TA)y[v0 + i];
+}
+
+// copy n[c] values from src + so[c] to dst + d_o[c] for every column c = blockIdx.y
+template <typename TA>
+__global__ void k_copy_cols(const TA* __restrict__ src, TA* __restrict__ dst,
+                            const int64_t* __restrict__ so, const int64_t* __restrict__ d_o,
+                            const int64_t* __restrict__ n) {
+    const int32_t c = blockIdx.y;
+    const int64_t a = so[c], d = d_o[c], m = n[c];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[d + i] = src[a + i];
 }
 
 // Z_S rows restricted to the kept columns: count pass (out == nullptr) or fill pass
@@ -130,18 +155,19 @@ __global__ void k_csr_filter(const int64_t* __restrict__ ptr, const int32_t* __r
     }
 }
 
-// dense Z_I, row-major [n_obs_pad][rp] from per-column entry lists
+// dense Z_I of one problem, row-major [n_obs_pad][rp] from per-column entry lists (rows
+// relative to the problem's first pixel row0)
 __global__ void k_dense_z(const int64_t* __restrict__ cptr, const int32_t* __restrict__ rows,
-                          const double* __restrict__ vals, int32_t r, int32_t rp,
+                          const double* __restrict__ vals, int32_t r, int32_t rp, int64_t row0,
                           double* __restrict__ zd) {
     const int32_t c = blockIdx.y;
     if (c >= r) return;
     for (int64_t i = cptr[c] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cptr[c + 1];
          i += (int64_t)gridDim.x * blockDim.x)
-        zd[(int64_t)rows[i] * rp + c] = vals[i];
+        zd[((int64_t)rows[i] - row0) * rp + c] = vals[i];
 }
 
-// AZ_I row-major [n_obs_pad][rp] from column-major AZ [r][n_vec] (I rows)
+// AZ_I row-major [n_obs_pad][rp] from one problem's column-major AZ block [r][n_vec] (I rows)
 template <typename TA>
 __global__ void k_az_rows(const TA* __restrict__ az, int64_t n_vec, int64_t n_obs, int ns,
                           int32_t r, int32_t rp, double* __restrict__ out) {
@@ -202,82 +228,90 @@ __global__ void k_sum_parts(const double* __restrict__ part, int64_t m, int32_t 
     }
 }
 
-// v = Z^T r: each kept column's entries are split over `slices` waves whose partial sums
-// go to vpart[column][slice]; optional convergence test in the prologue
+// v = Z^T r: kept column c owns the slices [vslice[c], vslice[c+1]) of 512 entries; one
+// wave per slice writes its partial sum to vpart[slice]
 __global__ __launch_bounds__(256) void k_ztr(const int64_t* __restrict__ cbeg,
                                              const int64_t* __restrict__ cend,
                                              const int32_t* __restrict__ rows,
                                              const double* __restrict__ vals,
                                              const double* __restrict__ r, int ns, int32_t rk,
-                                             int32_t slices, double* __restrict__ vpart,
-                                             PcgCtl ctl) {
-    __shared__ double red[256];
-    if (ctl.part) {
-        if (ctl.sc->done) return;
-        if (ctl.check) {
-            const double rr = reduce_partials(ctl.part + kSlotRR * kVecBlocks, kVecBlocks, red);
-            const double rel = sqrt(rr) / ctl.sc->bnorm;
-            if (blockIdx.x == 0 && threadIdx.x == 0) {
-                ctl.sc->rr = rr;
-                if (ctl.hist) ctl.hist[ctl.iter] = rel;
-                if (rel <= ctl.sc->tol) ctl.sc->done = 1;
-            }
-            if (rel <= ctl.sc->tol) return;
-        }
-    }
+                                             const int32_t* __restrict__ vslice, int64_t n_slices,
+                                             const int32_t* __restrict__ col_prob,
+                                             double* __restrict__ vpart,
+                                             const int* __restrict__ mask) {
     const int lane = threadIdx.x & 63;
     const int64_t wv = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (wv >= (int64_t)rk * slices) return;
-    const int32_t c = (int32_t)(wv / slices), sl = (int32_t)(wv % slices);
-    const int64_t e0 = cbeg[c], len = cend[c] - e0;
-    const int64_t a = e0 + len * sl / slices, b = e0 + len * (sl + 1) / slices;
+    if (wv >= n_slices) return;
+    int32_t lo = 0, hi = rk - 1;  // column: largest c with vslice[c] <= wv
+    while (lo < hi) {
+        const int32_t m = (lo + hi + 1) >> 1;
+        if (vslice[m] <= wv) lo = m; else hi = m - 1;
+    }
+    const int32_t c = lo;
+    if (mask && !mask[col_prob[c]]) return;
+    const int64_t a = cbeg[c] + (wv - vslice[c]) * 512;
+    const int64_t b = a + 512 < cend[c] ? a + 512 : cend[c];
     double s = 0.0;
     for (int64_t e = a + lane; e < b; e += 64) s += vals[e] * r[(int64_t)rows[e] * ns];
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
     if (lane == 0) vpart[wv] = s;
 }
 
-// w = E^-1 v with v[c] = sum of the slice partials of column c (one wave per row)
+// w = E^-1 v per problem, with v[c] = sum of the slice partials of column c (one wave per
+// kept column a, summing over the columns of a's problem)
 __global__ __launch_bounds__(256) void k_einv(const double* __restrict__ Einv,
-                                              const double* __restrict__ vpart, int32_t rk,
-                                              int32_t slices, double* __restrict__ w,
-                                              const PcgScalars* sc) {
-    if (sc && sc->done) return;
+                                              const int64_t* __restrict__ einv_off,
+                                              const int32_t* __restrict__ col_off,
+                                              const int32_t* __restrict__ col_prob,
+                                              const double* __restrict__ vpart,
+                                              const int32_t* __restrict__ vslice, int32_t rk,
+                                              double* __restrict__ w,
+                                              const int* __restrict__ mask) {
     const int lane = threadIdx.x & 63;
     const int32_t a = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (a >= rk) return;
+    const int32_t b = col_prob[a];
+    if (mask && !mask[b]) return;
+    const int32_t c0 = col_off[b], r = col_off[b + 1] - c0;
+    const double* E = Einv + einv_off[b] + (int64_t)(a - c0) * r;
     double s = 0.0;
-    for (int32_t c = lane; c < rk; c += 64) {
+    for (int32_t q = lane; q < r; q += 64) {
+        const int32_t c = c0 + q;
         double v = 0.0;
-        for (int32_t q = 0; q < slices; ++q) v += vpart[(int64_t)c * slices + q];
-        s += Einv[(int64_t)a * rk + c] * v;
+        for (int32_t t = vslice[c]; t < vslice[c + 1]; ++t) v += vpart[t];
+        s += E[q] * v;
     }
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
     if (lane == 0) w[a] = s;
 }
 
-// z = M_BD (r - AZ w) + Z w, partial r^T z
+// z = M_BD (r - AZ w) + Z w per pixel of every masked problem, partials of r^T z
 template <typename TA, int NS>
 __global__ __launch_bounds__(kVecThreads) void k_2lvl(
     const double* __restrict__ r, double* __restrict__ z, const double* __restrict__ bj,
-    const TA* __restrict__ az, int64_t n_obs, int32_t rk, const double* __restrict__ w,
+    const TA* __restrict__ az, const int64_t* __restrict__ az_off,
+    const int32_t* __restrict__ col_off, const double* __restrict__ w,
     const int64_t* __restrict__ zptr, const int32_t* __restrict__ zcol,
     const double* __restrict__ zval, PcgCtl ctl) {
     __shared__ double red[kVecThreads];
     extern __shared__ double sw[];
-    if (ctl.part && ctl.sc->done) return;
-    for (int c = threadIdx.x; c < rk; c += kVecThreads) sw[c] = w[c];
+    const VecBlock vb = vec_block(ctl, NS, false);
+    if (ctl.mask && !ctl.mask[vb.b]) return;
+    const int32_t c0 = col_off[vb.b], rk = col_off[vb.b + 1] - c0;
+    for (int c = threadIdx.x; c < rk; c += kVecThreads) sw[c] = w[c0 + c];
     __syncthreads();
-    const int64_t nv = n_obs * NS;
+    const int64_t nv = vb.n * NS;
+    const TA* azb = az + az_off[vb.b];
     double acc = 0.0;
-    for (int64_t p = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; p < n_obs;
-         p += (int64_t)gridDim.x * kVecThreads) {
+    for (int64_t q = (int64_t)vb.k * kVecThreads + threadIdx.x; q < vb.n;
+         q += (int64_t)kVecBlocks * kVecThreads) {
+        const int64_t p = vb.base + q;
         double u[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) u[s] = r[p * NS + s];
         for (int32_t c = 0; c < rk; ++c) {
             const double wc = sw[c];
-            const TA* col = az + (int64_t)c * nv + p * NS;
+            const TA* col = azb + (int64_t)c * nv + q * NS;
 #pragma unroll
             for (int s = 0; s < NS; ++s) u[s] -= (double)col[s] * wc;
         }
@@ -291,7 +325,7 @@ __global__ __launch_bounds__(kVecThreads) void k_2lvl(
             zz[2] = m[2] * u[0] + m[4] * u[1] + m[5] * u[2];
         }
         double zw = 0.0;
-        for (int64_t e = zptr[p]; e < zptr[p + 1]; ++e) zw += zval[e] * sw[zcol[e]];
+        for (int64_t e = zptr[p]; e < zptr[p + 1]; ++e) zw += zval[e] * sw[zcol[e] - c0];
         zz[0] += zw;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
@@ -299,7 +333,7 @@ __global__ __launch_bounds__(kVecThreads) void k_2lvl(
             acc += r[p * NS + s] * zz[s];
         }
     }
-    if (ctl.part) write_partial(acc, ctl.part + kSlotRZ * kVecBlocks, red);
+    if (ctl.part) write_partial_at(acc, slot_part(ctl, kSlotRZ, vb.b), vb.k, red);
 }
 
 // pivoted Cholesky of a symmetric PSD matrix: indices of a maximal set of columns whose
@@ -413,23 +447,17 @@ int build_coarse(mm_plan_t pl) {
                      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - c0).count());
     };
     Coarse& co = pl->co;
+    const int B = pl->n_prob;
     const int64_t n_obs = pl->n_obs, ns = pl->n_s, nv = n_obs * ns;
+    const std::vector<int64_t>& oo = pl->h_ooff;
     // Z_S in CSR form (per pixel, ascending interval)
     DBuf<int64_t> nnz, ptr;
     MM_TRY(nnz.alloc(n_obs));
     MM_TRY(ptr.alloc(n_obs + 1));
     hipLaunchKernelGGL(k_zs_count, dim3(grid_for(n_obs, 128)), dim3(128), 0, st, pl->perm.p,
-                       pl->seg.p, n_obs, pl->int_lo.p, pl->n_int, nnz.p);
+                       pl->seg.p, pl->hits.p, n_obs, pl->int_lo.p, pl->n_int, nnz.p);
     MM_HIP(hipGetLastError());
-    {
-        // exclusive scan on host (n_obs values)
-        std::vector<int64_t> h(n_obs), hp(n_obs + 1);
-        MM_HIP(hipMemcpyAsync(h.data(), nnz.p, n_obs * 8, hipMemcpyDeviceToHost, st));
-        MM_HIP(hipStreamSynchronize(st));
-        hp[0] = 0;
-        for (int64_t c = 0; c < n_obs; ++c) hp[c + 1] = hp[c] + h[c];
-        MM_HIP(hipMemcpyAsync(ptr.p, hp.data(), (n_obs + 1) * 8, hipMemcpyHostToDevice, st));
-    }
+    MM_TRY(scan_exclusive_i64(nnz.p, ptr.p, n_obs, st));
     int64_t total = 0;
     MM_HIP(hipMemcpyAsync(&total, ptr.p + n_obs, 8, hipMemcpyDeviceToHost, st));
     MM_HIP(hipStreamSynchronize(st));
@@ -438,7 +466,7 @@ int build_coarse(mm_plan_t pl) {
     MM_TRY(col.alloc(total));
     MM_TRY(val.alloc(total));
     hipLaunchKernelGGL(k_zs_fill, dim3(grid_for(n_obs, 128)), dim3(128), 0, st, pl->perm.p,
-                       pl->seg.p, n_obs, pl->int_lo.p, pl->n_int, ptr.p, col.p, val.p);
+                       pl->seg.p, pl->hits.p, n_obs, pl->int_lo.p, pl->n_int, ptr.p, col.p, val.p);
     MM_HIP(hipGetLastError());
     std::vector<int64_t> hptr(n_obs + 1);
     std::vector<int32_t> hcol(total);
@@ -497,16 +525,30 @@ int build_coarse(mm_plan_t pl) {
     }
     const int32_t rd = (int32_t)uniq.size();
     co.r_dedup = rd;
+    // distinct columns per problem (columns of distinct problems have disjoint rows, so
+    // none is merged across problems; intervals are problem-ordered)
+    std::vector<int32_t> ud_off(B + 1, 0);
+    {
+        int32_t u = 0;
+        for (int b = 0; b < B; ++b) {
+            ud_off[b] = u;
+            while (u < rd && uniq[u] < pl->h_pint[b + 1]) ++u;
+        }
+        ud_off[B] = rd;
+    }
+    int32_t rd_max = 0;
+    std::vector<int64_t> azd_off(B + 1, 0);
+    for (int b = 0; b < B; ++b) {
+        const int32_t r_b = ud_off[b + 1] - ud_off[b];
+        if (r_b == 0) {
+            set_error("problem %d has no coarse-space column", b);
+            return MM_ERR_RANK;
+        }
+        rd_max = std::max(rd_max, r_b);
+        azd_off[b + 1] = azd_off[b] + (int64_t)r_b * (oo[b + 1] - oo[b]) * ns;
+    }
     tick("zs+dedup");
-    // AZ for the distinct columns
-    const bool mixed = pl->opts.precision == MM_MIXED;
-    DBuf<double> azd;
-    DBuf<float> azf;
-    if (mixed) MM_TRY(azf.alloc((size_t)rd * nv));
-    else MM_TRY(azd.alloc((size_t)rd * nv));
-    DBuf<double> zc, tmp;
-    MM_TRY(zc.alloc(nv));
-    MM_TRY(tmp.alloc(nv));
+    // entry lists of the distinct columns
     DBuf<int32_t> drow;
     DBuf<double> dval;
     DBuf<int64_t> dptr;
@@ -525,99 +567,199 @@ int build_coarse(mm_plan_t pl) {
     MM_HIP(hipMemcpyAsync(drow.p, urow.data(), urow.size() * 4, hipMemcpyHostToDevice, st));
     MM_HIP(hipMemcpyAsync(dval.p, uval.data(), uval.size() * 8, hipMemcpyHostToDevice, st));
     MM_HIP(hipMemcpyAsync(dptr.p, uptr.data(), (rd + 1) * 8, hipMemcpyHostToDevice, st));
-    for (int32_t u = 0; u < rd; ++u) {
-        MM_HIP(hipMemsetAsync(zc.p, 0, nv * 8, st));
-        const int64_t cnt = uptr[u + 1] - uptr[u];
-        hipLaunchKernelGGL(k_col_to_vec, dim3(grid_for(cnt)), dim3(256), 0, st,
-                           drow.p + uptr[u], dval.p + uptr[u], cnt, (int)ns, zc.p);
-        MM_HIP(hipGetLastError());
-        if (mixed) {
-            MM_TRY(apply_A32(pl, zc.p, tmp.p, nullptr));
-            hipLaunchKernelGGL(k_to_f32, dim3(grid_for(nv)), dim3(256), 0, st, (const double*)tmp.p,
-                               azf.p + (size_t)u * nv, nv);
+    // AZ of the distinct columns, block per problem: A is block diagonal over the problems,
+    // so one application to the sum of every problem's k-th column gives all k-th columns
+    const bool mixed = pl->opts.precision == MM_MIXED;
+    DBuf<double> azd;
+    DBuf<float> azf;
+    if (mixed) MM_TRY(azf.alloc((size_t)azd_off[B]));
+    else MM_TRY(azd.alloc((size_t)azd_off[B]));
+    DBuf<double> zc, tmp;
+    MM_TRY(zc.alloc(nv));
+    MM_TRY(tmp.alloc(nv));
+    DBuf<int64_t> d_azd_off;
+    MM_TRY(d_azd_off.alloc(B + 1));
+    MM_HIP(hipMemcpyAsync(d_azd_off.p, azd_off.data(), (B + 1) * 8, hipMemcpyHostToDevice, st));
+    DBuf<int32_t> lcols, lprob;
+    MM_TRY(lcols.alloc((size_t)rd_max * B));
+    MM_TRY(lprob.alloc((size_t)rd_max * B));
+    {
+        std::vector<int32_t> hc, hp;
+        std::vector<int32_t> lcnt(rd_max, 0);
+        for (int32_t k = 0; k < rd_max; ++k)
+            for (int b = 0; b < B; ++b)
+                if (ud_off[b] + k < ud_off[b + 1]) {
+                    hc.push_back(ud_off[b] + k);
+                    hp.push_back(b);
+                    lcnt[k]++;
+                }
+        MM_HIP(hipMemcpyAsync(lcols.p, hc.data(), hc.size() * 4, hipMemcpyHostToDevice, st));
+        MM_HIP(hipMemcpyAsync(lprob.p, hp.data(), hp.size() * 4, hipMemcpyHostToDevice, st));
+        int64_t lo = 0;
+        for (int32_t k = 0; k < rd_max; ++k) {
+            const int nl = lcnt[k];
+            MM_HIP(hipMemsetAsync(zc.p, 0, nv * 8, st));
+            hipLaunchKernelGGL(k_cols_to_vec, dim3(16, nl), dim3(256), 0, st, lcols.p + lo, dptr.p,
+                               drow.p, dval.p, (int)ns, zc.p);
             MM_HIP(hipGetLastError());
-        } else {
-            MM_TRY(apply_A64(pl, zc.p, azd.p + (size_t)u * nv, nullptr));
+            if (mixed) {
+                MM_TRY(apply_A32(pl, zc.p, tmp.p, nullptr));
+                hipLaunchKernelGGL(k_store_az<float>, dim3(64, nl), dim3(256), 0, st, lprob.p + lo,
+                                   (const double*)tmp.p, pl->ooff.p, (int)ns,
+                                   (const int64_t*)d_azd_off.p, k, azf.p);
+            } else {
+                MM_TRY(apply_A64(pl, zc.p, tmp.p, nullptr));
+                hipLaunchKernelGGL(k_store_az<double>, dim3(64, nl), dim3(256), 0, st, lprob.p + lo,
+                                   (const double*)tmp.p, pl->ooff.p, (int)ns,
+                                   (const int64_t*)d_azd_off.p, k, azd.p);
+            }
+            MM_HIP(hipGetLastError());
+            lo += nl;
         }
     }
+    zc.release();
+    tmp.release();
     tick("AZ");
-    // E = Z^T (AZ) on the matrix cores
-    const int32_t rp = (rd + 15) / 16 * 16;
-    const int64_t npad = (n_obs + 3) / 4 * 4;
+    // per problem: E_b = Z_b^T (AZ)_b on the matrix cores, independent subset, E_b^-1
+    int64_t npad_max = 0;
+    for (int b = 0; b < B; ++b) npad_max = std::max<int64_t>(npad_max, (oo[b + 1] - oo[b] + 3) / 4 * 4);
+    const int32_t rp_max = (rd_max + 15) / 16 * 16;
     DBuf<double> zd, azr, dE;
-    MM_TRY(zd.alloc((size_t)npad * rp));
-    MM_TRY(azr.alloc((size_t)npad * rp));
-    MM_TRY(dE.alloc((size_t)rp * rp));
-    MM_HIP(hipMemsetAsync(zd.p, 0, (size_t)npad * rp * 8, st));
-    MM_HIP(hipMemsetAsync(azr.p, 0, (size_t)npad * rp * 8, st));
-    hipLaunchKernelGGL(k_dense_z, dim3(64, rd), dim3(256), 0, st, dptr.p, drow.p, dval.p, rd, rp, zd.p);
-    if (mixed)
-        hipLaunchKernelGGL(k_az_rows<float>, dim3(grid_for(n_obs, 256, 4096), rd), dim3(256), 0, st,
-                           azf.p, nv, n_obs, (int)ns, rd, rp, azr.p);
-    else
-        hipLaunchKernelGGL(k_az_rows<double>, dim3(grid_for(n_obs, 256, 4096), rd), dim3(256), 0,
-                           st, azd.p, nv, n_obs, (int)ns, rd, rp, azr.p);
-    MM_HIP(hipGetLastError());
-    MM_TRY(gemm_tn_f64(st, zd.p, azr.p, npad, rp, rp, dE.p));
-    std::vector<double> Ep((size_t)rp * rp);
-    MM_HIP(hipMemcpy(Ep.data(), dE.p, Ep.size() * 8, hipMemcpyDeviceToHost));
+    MM_TRY(zd.alloc((size_t)npad_max * rp_max));
+    MM_TRY(azr.alloc((size_t)npad_max * rp_max));
+    MM_TRY(dE.alloc((size_t)rp_max * rp_max));
+    std::vector<std::vector<int>> sels(B);
+    std::vector<double> Eall, Einv_all;
+    co.h_col_off.assign(B + 1, 0);
+    co.h_einv_off.assign(B + 1, 0);
+    co.h_az_off.assign(B + 1, 0);
+    co.cols.clear();
+    co.r_max = 0;
+    for (int b = 0; b < B; ++b) {
+        const int32_t rb = ud_off[b + 1] - ud_off[b];
+        const int64_t nob = oo[b + 1] - oo[b];
+        const int32_t rp = (rb + 15) / 16 * 16;
+        const int64_t npad = (nob + 3) / 4 * 4;
+        MM_HIP(hipMemsetAsync(zd.p, 0, (size_t)npad * rp * 8, st));
+        MM_HIP(hipMemsetAsync(azr.p, 0, (size_t)npad * rp * 8, st));
+        hipLaunchKernelGGL(k_dense_z, dim3(64, rb), dim3(256), 0, st, dptr.p + ud_off[b], drow.p,
+                           dval.p, rb, rp, oo[b], zd.p);
+        if (mixed)
+            hipLaunchKernelGGL(k_az_rows<float>, dim3(grid_for(nob, 256, 4096), rb), dim3(256), 0,
+                               st, azf.p + azd_off[b], nob * ns, nob, (int)ns, rb, rp, azr.p);
+        else
+            hipLaunchKernelGGL(k_az_rows<double>, dim3(grid_for(nob, 256, 4096), rb), dim3(256), 0,
+                               st, azd.p + azd_off[b], nob * ns, nob, (int)ns, rb, rp, azr.p);
+        MM_HIP(hipGetLastError());
+        MM_TRY(gemm_tn_f64(st, zd.p, azr.p, npad, rp, rp, dE.p));
+        std::vector<double> Ep((size_t)rp * rp);
+        MM_HIP(hipMemcpy(Ep.data(), dE.p, Ep.size() * 8, hipMemcpyDeviceToHost));
+        std::vector<double> E((size_t)rb * rb);
+        for (int32_t i = 0; i < rb; ++i)
+            for (int32_t j = 0; j < rb; ++j)
+                E[(size_t)i * rb + j] = 0.5 * (Ep[(size_t)i * rp + j] + Ep[(size_t)j * rp + i]);
+        std::vector<int> sel = pivoted_cholesky_select(E, rb, pl->opts.rank_tol);
+        const int32_t k = (int32_t)sel.size();
+        if (k == 0) {
+            set_error("coarse matrix E of problem %d is zero", b);
+            return MM_ERR_RANK;
+        }
+        std::vector<double> Es((size_t)k * k), Einv;
+        for (int32_t i = 0; i < k; ++i)
+            for (int32_t j = 0; j < k; ++j) Es[(size_t)i * k + j] = E[(size_t)sel[i] * rb + sel[j]];
+        if (!spd_inverse(Es, k, Einv)) {
+            set_error("coarse matrix E of problem %d not positive definite on the selected columns",
+                      b);
+            return MM_ERR_RANK;
+        }
+        Eall.insert(Eall.end(), Es.begin(), Es.end());
+        Einv_all.insert(Einv_all.end(), Einv.begin(), Einv.end());
+        for (int32_t i = 0; i < k; ++i) co.cols.push_back(uniq[ud_off[b] + sel[i]]);
+        co.h_col_off[b + 1] = co.h_col_off[b] + k;
+        co.h_einv_off[b + 1] = co.h_einv_off[b] + (int64_t)k * k;
+        co.h_az_off[b + 1] = co.h_az_off[b] + (int64_t)k * nob * ns;
+        co.r_max = std::max(co.r_max, k);
+        sels[b] = std::move(sel);
+    }
     zd.release();
     azr.release();
-    std::vector<double> E((size_t)rd * rd);
-    for (int32_t a = 0; a < rd; ++a)
-        for (int32_t b = 0; b < rd; ++b)
-            E[(size_t)a * rd + b] = 0.5 * (Ep[(size_t)a * rp + b] + Ep[(size_t)b * rp + a]);
+    dE.release();
+    const int32_t keff = co.h_col_off[B];
+    co.r_eff = keff;
+    co.E = std::move(Eall);
     tick("E");
-    // independent subset and E^-1 on it
-    std::vector<int> sel = pivoted_cholesky_select(E, rd, pl->opts.rank_tol);
-    const int32_t k = (int32_t)sel.size();
-    if (k == 0) {
-        set_error("coarse matrix E is zero");
-        return MM_ERR_RANK;
+    MM_TRY(co.Einv.alloc(Einv_all.size()));
+    MM_HIP(hipMemcpyAsync(co.Einv.p, Einv_all.data(), Einv_all.size() * 8, hipMemcpyHostToDevice,
+                          st));
+    // kept AZ columns into the final per-problem blocks
+    {
+        std::vector<int64_t> so(keff), d_o(keff), cn(keff);
+        for (int b = 0; b < B; ++b) {
+            const int64_t n_b = (oo[b + 1] - oo[b]) * ns;
+            for (size_t i = 0; i < sels[b].size(); ++i) {
+                const int32_t a = co.h_col_off[b] + (int32_t)i;
+                so[a] = azd_off[b] + (int64_t)sels[b][i] * n_b;
+                d_o[a] = co.h_az_off[b] + (int64_t)i * n_b;
+                cn[a] = n_b;
+            }
+        }
+        DBuf<int64_t> dso, ddo, dcn;
+        MM_TRY(dso.alloc(keff));
+        MM_TRY(ddo.alloc(keff));
+        MM_TRY(dcn.alloc(keff));
+        MM_HIP(hipMemcpyAsync(dso.p, so.data(), keff * 8, hipMemcpyHostToDevice, st));
+        MM_HIP(hipMemcpyAsync(ddo.p, d_o.data(), keff * 8, hipMemcpyHostToDevice, st));
+        MM_HIP(hipMemcpyAsync(dcn.p, cn.data(), keff * 8, hipMemcpyHostToDevice, st));
+        if (mixed) {
+            MM_TRY(co.AZ32.alloc((size_t)co.h_az_off[B]));
+            hipLaunchKernelGGL(k_copy_cols<float>, dim3(64, keff), dim3(256), 0, st,
+                               (const float*)azf.p, co.AZ32.p, (const int64_t*)dso.p,
+                               (const int64_t*)ddo.p, (const int64_t*)dcn.p);
+        } else {
+            MM_TRY(co.AZ64.alloc((size_t)co.h_az_off[B]));
+            hipLaunchKernelGGL(k_copy_cols<double>, dim3(64, keff), dim3(256), 0, st,
+                               (const double*)azd.p, co.AZ64.p, (const int64_t*)dso.p,
+                               (const int64_t*)ddo.p, (const int64_t*)dcn.p);
+        }
+        MM_HIP(hipGetLastError());
+        MM_HIP(hipStreamSynchronize(st));
     }
-    std::vector<double> Es((size_t)k * k), Einv;
-    for (int32_t a = 0; a < k; ++a)
-        for (int32_t b = 0; b < k; ++b) Es[(size_t)a * k + b] = E[(size_t)sel[a] * rd + sel[b]];
-    if (!spd_inverse(Es, k, Einv)) {
-        set_error("coarse matrix E not positive definite on the selected columns");
-        return MM_ERR_RANK;
-    }
-    co.r_eff = k;
-    co.E = Es;
-    co.cols.resize(k);
-    for (int32_t a = 0; a < k; ++a) co.cols[a] = uniq[sel[a]];
-    MM_TRY(co.Einv.alloc((size_t)k * k));
-    MM_HIP(hipMemcpyAsync(co.Einv.p, Einv.data(), Einv.size() * 8, hipMemcpyHostToDevice, st));
-    // kept AZ columns: compact in place (sel is increasing and sel[a] >= a, so a source
-    // column is never overwritten before it is copied)
-    for (int32_t a = 0; a < k; ++a) {
-        if (sel[a] == a) continue;
-        if (mixed)
-            MM_HIP(hipMemcpyAsync(azf.p + (size_t)a * nv, azf.p + (size_t)sel[a] * nv, nv * 4,
-                                  hipMemcpyDeviceToDevice, st));
-        else
-            MM_HIP(hipMemcpyAsync(azd.p + (size_t)a * nv, azd.p + (size_t)sel[a] * nv, nv * 8,
-                                  hipMemcpyDeviceToDevice, st));
-    }
-    if (mixed) co.AZ32.swap(azf);
-    else co.AZ64.swap(azd);
-    // kept columns by column: entry ranges into the distinct-column lists
-    std::vector<int64_t> kb(k), ke(k);
-    int64_t maxlen = 1;
-    for (int32_t a = 0; a < k; ++a) {
-        kb[a] = uptr[sel[a]];
-        ke[a] = uptr[sel[a] + 1];
-        maxlen = std::max(maxlen, ke[a] - kb[a]);
-    }
+    azf.release();
+    azd.release();
+    // kept columns by column: entry ranges into the distinct-column lists; Z^T r slices
+    std::vector<int64_t> kb(keff), ke(keff);
+    std::vector<int32_t> vs(keff + 1, 0), cprob(keff);
+    for (int b = 0; b < B; ++b)
+        for (size_t i = 0; i < sels[b].size(); ++i) {
+            const int32_t a = co.h_col_off[b] + (int32_t)i;
+            const int32_t u = ud_off[b] + sels[b][i];
+            kb[a] = uptr[u];
+            ke[a] = uptr[u + 1];
+            cprob[a] = b;
+        }
+    for (int32_t a = 0; a < keff; ++a)
+        vs[a + 1] = vs[a] + (int32_t)std::max<int64_t>(1, (ke[a] - kb[a] + 511) / 512);
+    co.n_slices = vs[keff];
     co.csc_row.swap(drow);
     co.csc_val.swap(dval);
-    MM_TRY(co.csc_beg.alloc(k));
-    MM_TRY(co.csc_end.alloc(k));
-    MM_HIP(hipMemcpyAsync(co.csc_beg.p, kb.data(), k * 8, hipMemcpyHostToDevice, st));
-    MM_HIP(hipMemcpyAsync(co.csc_end.p, ke.data(), k * 8, hipMemcpyHostToDevice, st));
+    MM_TRY(co.csc_beg.alloc(keff));
+    MM_TRY(co.csc_end.alloc(keff));
+    MM_TRY(co.vslice.alloc(keff + 1));
+    MM_TRY(co.col_prob.alloc(keff));
+    MM_TRY(co.col_off.alloc(B + 1));
+    MM_TRY(co.az_off.alloc(B + 1));
+    MM_TRY(co.einv_off.alloc(B + 1));
+    MM_HIP(hipMemcpyAsync(co.csc_beg.p, kb.data(), keff * 8, hipMemcpyHostToDevice, st));
+    MM_HIP(hipMemcpyAsync(co.csc_end.p, ke.data(), keff * 8, hipMemcpyHostToDevice, st));
+    MM_HIP(hipMemcpyAsync(co.vslice.p, vs.data(), (keff + 1) * 4, hipMemcpyHostToDevice, st));
+    MM_HIP(hipMemcpyAsync(co.col_prob.p, cprob.data(), keff * 4, hipMemcpyHostToDevice, st));
+    MM_HIP(hipMemcpyAsync(co.col_off.p, co.h_col_off.data(), (B + 1) * 4, hipMemcpyHostToDevice, st));
+    MM_HIP(hipMemcpyAsync(co.az_off.p, co.h_az_off.data(), (B + 1) * 8, hipMemcpyHostToDevice, st));
+    MM_HIP(hipMemcpyAsync(co.einv_off.p, co.h_einv_off.data(), (B + 1) * 8, hipMemcpyHostToDevice,
+                          st));
     // kept columns by pixel (CSR), filtered on the device from the full Z_S rows
     std::vector<int32_t> colmap(K, -1);
-    for (int32_t a = 0; a < k; ++a) colmap[co.cols[a]] = a;
+    for (int32_t a = 0; a < keff; ++a) colmap[co.cols[a]] = a;
     DBuf<int32_t> dmap;
     DBuf<int64_t> kcnt;
     MM_TRY(dmap.alloc(K));
@@ -637,10 +779,8 @@ int build_coarse(mm_plan_t pl) {
                        n_obs, dmap.p, (const int64_t*)co.csr_ptr.p, (int64_t*)nullptr,
                        co.csr_col.p, co.csr_val.p);
     MM_HIP(hipGetLastError());
-    MM_TRY(co.v.alloc(k));
-    MM_TRY(co.w.alloc(k));
-    co.zslices = (int)std::min<int64_t>(256, std::max<int64_t>(1, (maxlen + 511) / 512));
-    MM_TRY(co.vpart.alloc((size_t)k * co.zslices));
+    MM_TRY(co.w.alloc(keff));
+    MM_TRY(co.vpart.alloc(co.n_slices));
     MM_HIP(hipStreamSynchronize(st));
     pl->has_coarse = true;
     return MM_OK;
@@ -650,30 +790,31 @@ int twolvl_apply(mm_plan_t pl, const double* r, double* z, const PcgCtl& ctl) {
     Coarse& co = pl->co;
     hipStream_t st = pl->stream;
     const int32_t k = co.r_eff;
-    const int64_t nw = (int64_t)k * co.zslices;
-    hipLaunchKernelGGL(k_ztr, dim3((nw + 3) / 4), dim3(256), 0, st, co.csc_beg.p, co.csc_end.p,
-                       co.csc_row.p, co.csc_val.p, r, pl->n_s, k, co.zslices, co.vpart.p, ctl);
-    hipLaunchKernelGGL(k_einv, dim3((k + 3) / 4), dim3(256), 0, st, co.Einv.p, co.vpart.p, k,
-                       co.zslices, co.w.p, ctl.part ? ctl.sc : nullptr);
-    const size_t shm = (size_t)k * sizeof(double);
+    hipLaunchKernelGGL(k_ztr, dim3((co.n_slices + 3) / 4), dim3(256), 0, st, co.csc_beg.p,
+                       co.csc_end.p, co.csc_row.p, co.csc_val.p, r, pl->n_s, k, co.vslice.p,
+                       co.n_slices, co.col_prob.p, co.vpart.p, ctl.mask);
+    hipLaunchKernelGGL(k_einv, dim3((k + 3) / 4), dim3(256), 0, st, co.Einv.p, co.einv_off.p,
+                       co.col_off.p, co.col_prob.p, co.vpart.p, co.vslice.p, k, co.w.p, ctl.mask);
+    const size_t shm = (size_t)co.r_max * sizeof(double);
+    const dim3 g(pl->n_pblk), t(kVecThreads);
     if (pl->n_s == 3) {
         if (co.AZ32.p)
-            hipLaunchKernelGGL((k_2lvl<float, 3>), dim3(kVecBlocks), dim3(kVecThreads), shm, st, r,
-                               z, pl->bj.p, co.AZ32.p, pl->n_obs, k, co.w.p, co.csr_ptr.p,
-                               co.csr_col.p, co.csr_val.p, ctl);
+            hipLaunchKernelGGL((k_2lvl<float, 3>), g, t, shm, st, r, z, pl->bj.p, co.AZ32.p,
+                               co.az_off.p, co.col_off.p, co.w.p, co.csr_ptr.p, co.csr_col.p,
+                               co.csr_val.p, ctl);
         else
-            hipLaunchKernelGGL((k_2lvl<double, 3>), dim3(kVecBlocks), dim3(kVecThreads), shm, st, r,
-                               z, pl->bj.p, co.AZ64.p, pl->n_obs, k, co.w.p, co.csr_ptr.p,
-                               co.csr_col.p, co.csr_val.p, ctl);
+            hipLaunchKernelGGL((k_2lvl<double, 3>), g, t, shm, st, r, z, pl->bj.p, co.AZ64.p,
+                               co.az_off.p, co.col_off.p, co.w.p, co.csr_ptr.p, co.csr_col.p,
+                               co.csr_val.p, ctl);
     } else {
         if (co.AZ32.p)
-            hipLaunchKernelGGL((k_2lvl<float, 1>), dim3(kVecBlocks), dim3(kVecThreads), shm, st, r,
-                               z, pl->bj.p, co.AZ32.p, pl->n_obs, k, co.w.p, co.csr_ptr.p,
-                               co.csr_col.p, co.csr_val.p, ctl);
+            hipLaunchKernelGGL((k_2lvl<float, 1>), g, t, shm, st, r, z, pl->bj.p, co.AZ32.p,
+                               co.az_off.p, co.col_off.p, co.w.p, co.csr_ptr.p, co.csr_col.p,
+                               co.csr_val.p, ctl);
         else
-            hipLaunchKernelGGL((k_2lvl<double, 1>), dim3(kVecBlocks), dim3(kVecThreads), shm, st, r,
-                               z, pl->bj.p, co.AZ64.p, pl->n_obs, k, co.w.p, co.csr_ptr.p,
-                               co.csr_col.p, co.csr_val.p, ctl);
+            hipLaunchKernelGGL((k_2lvl<double, 1>), g, t, shm, st, r, z, pl->bj.p, co.AZ64.p,
+                               co.az_off.p, co.col_off.p, co.w.p, co.csr_ptr.p, co.csr_col.p,
+                               co.csr_val.p, ctl);
     }
     MM_HIP(hipGetLastError());
     return MM_OK;

@@ -39,7 +39,56 @@ __device__ __forceinline__ void write_partial(double v, double* __restrict__ par
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
+// block tree sum of v written to part[k] (k: the block's index within its problem)
+__device__ __forceinline__ void write_partial_at(double v, double* __restrict__ part, int k,
+                                                 double* red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = blockDim.x >> 1; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[k] = red[0];
+}
+
 // slots of the partial buffer
 constexpr int kSlotPQ = 0, kSlotRR = 1, kSlotRZ = 2, kSlotAux = 3, kNumSlots = 4;
+
+// problem b of block g given the block offsets off[0..B] (off[0] = 0, non-decreasing):
+// the largest b with off[b] <= g
+__device__ __forceinline__ int block_problem(const int32_t* __restrict__ off, int B, int g) {
+    int a = 0, b = B - 1;
+    while (a < b) {
+        const int m = (a + b + 1) >> 1;
+        if (off[m] <= g) a = m; else b = m - 1;
+    }
+    return a;
+}
+
+// the partials of problem b in a slot
+__device__ __forceinline__ double* slot_part(const PcgCtl& c, int slot, int b) {
+    return c.part + ((int64_t)slot * c.B + b) * kVecBlocks;
+}
+
+// a block's place in a per-problem vector launch
+struct VecBlock {
+    int b;        // problem
+    int k;        // block index within the problem
+    int64_t base; // first element (or pixel) of the problem
+    int64_t n;    // elements (or pixels) of the problem
+};
+
+// elements == true: n_s entries per pixel; false: pixels
+__device__ __forceinline__ VecBlock vec_block(const PcgCtl& c, int ns, bool elements) {
+    VecBlock v;
+    const int32_t* off = elements ? c.eblk : c.pblk;
+    v.b = block_problem(off, c.B, blockIdx.x);
+    v.k = blockIdx.x - off[v.b];
+    const int64_t o0 = c.ooff[v.b], o1 = c.ooff[v.b + 1];
+    const int64_t m = elements ? ns : 1;
+    v.base = o0 * m;
+    v.n = (o1 - o0) * m;
+    return v;
+}
 
 }  // namespace mm

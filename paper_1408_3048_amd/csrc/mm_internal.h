@@ -91,46 +91,88 @@ struct FftTiling {
     DBuf<float> tw32;
 };
 
-// PCG device scalars; written only by block 0 of the kernel that owns each field
+// States of one problem's PCG.  kCheck: the recursive residual met the tolerance or has
+// dropped by the replacement ratio since the last true-residual evaluation; the problem
+// pauses until the host evaluates b - A x for it.
+enum PcgState {
+    kActive = 0,
+    kCheck = 1,
+    kDone = 2,
+    kBreakdown = 3,
+    kMaxIter = 4,
+    kResume = 5,  // true residual evaluated and copied into r; z and p follow
+};
+
+// Per-problem PCG scalars.  Every field has one writer per launch: block 0 of the
+// problem in the vector kernels, or the problem's block in the one-block-per-problem
+// control kernels.
 struct PcgScalars {
-    double bnorm;     // ||b|| of the system being iterated
+    double bnorm;     // ||b_b||
     double tol;       // relative tolerance
     double alpha, beta, pq, rr;
-    int done;         // 1: converged or failed; kernels of later iterations return at once
+    double rel;       // last recursive (or evaluated true) relative residual
+    double last_rel;  // true relative residual at the last evaluation (1 at the start)
+    int state;        // PcgState
     int status;       // 0 ok, 1 breakdown
-    int iter;         // iterations completed (index of the last update + 1)
+    int iter;         // iterations completed
+    int iter_next;    // iter + 1 once the current iteration's x, r update ran
+    int evals;        // true-residual evaluations that replaced r
     int pad;
 };
 
-// control block of the PCG kernels (passed by value)
+// Control block of the PCG kernels (passed by value).  A batch of B independent problems
+// shares every launch; problem b owns the compact pixels [ooff[b], ooff[b+1]).  Vector
+// kernels map block g to (problem b, block k < kVecBlocks of b) through the block offsets
+// eblk (elements, n_s per pixel) or pblk (pixels); the partial sums of b go to
+// part[(slot * B + b) * kVecBlocks + k], so each problem's reductions follow the same tree
+// whatever else is in the batch.
 struct PcgCtl {
-    double* part = nullptr;     // [kNumSlots][kVecBlocks] partial sums; nullptr = standalone call
-    PcgScalars* sc = nullptr;
-    double* rz_hist = nullptr;  // r^T z of every iteration, [max_iter + 2]
-    double* hist = nullptr;     // recursive relative residual of every iteration, or nullptr
-    int iter = 0;               // iteration index
-    int check = 0;              // preconditioner prologue tests ||r|| <= tol ||b||
-    int first = 0;              // update_p: p = z (no beta)
-    int rz_only = 0;            // update_p: only record r^T z (after a residual replacement)
+    double* part = nullptr;      // [kNumSlots][B][kVecBlocks]; nullptr: plain operator call
+    PcgScalars* sc = nullptr;    // [B]
+    const int* mask = nullptr;   // [B] problems that take part in this launch (nullptr: all)
+    int* act = nullptr;          // [B] problems that iterate (cleared when a problem stops)
+    double* rz_hist = nullptr;   // [B][hstride] r^T z after every iteration
+    double* hist = nullptr;      // [B][hstride] recursive relative residual, or nullptr
+    const int32_t* eblk = nullptr;
+    const int32_t* pblk = nullptr;
+    const int64_t* ooff = nullptr;
+    int B = 1;
+    int hstride = 0;
+    int first = 0;               // update_p: p = z
+    int replace = 1;             // recursive convergence triggers a true-residual evaluation
+    int max_iter = 0;
+    double replace_ratio = 0.0;  // > 0: also evaluate when ||r|| fell by this factor
 };
 
+// Coarse space, block diagonal over the problems of a batch: problem b keeps the columns
+// [col_off[b], col_off[b+1]) (all of them supported on its own pixels), its AZ block is
+// [r_b][n_b] column-major at az_off[b] (n_b = n_s * its pixels) and its E^-1 block is
+// r_b x r_b row-major at einv_off[b].
 struct Coarse {
-    int r_dedup = 0;                 // columns after removing duplicates
-    int r_eff = 0;                   // columns kept (independent)
+    int r_dedup = 0;                 // columns after removing duplicates (all problems)
+    int r_eff = 0;                   // columns kept (independent), all problems
+    int r_max = 0;                   // largest r_b
     std::vector<int32_t> cols;       // interval index of every kept column
-    std::vector<double> E;           // r_eff x r_eff row-major (kept columns)
+    std::vector<int32_t> h_col_off;  // [B+1]
+    std::vector<int64_t> h_az_off;   // [B+1]
+    std::vector<int64_t> h_einv_off; // [B+1]
+    std::vector<double> E;           // E blocks, row-major, concatenated like Einv
+    DBuf<int32_t> col_off;           // [B+1]
+    DBuf<int32_t> col_prob;          // [r_eff] problem of every kept column
+    DBuf<int64_t> az_off, einv_off;  // [B+1]
     DBuf<int64_t> csr_ptr;           // [n_obs+1] kept-column entries per pixel
-    DBuf<int32_t> csr_col;
+    DBuf<int32_t> csr_col;           // global kept-column index
     DBuf<double> csr_val;
     DBuf<int64_t> csc_beg, csc_end;  // [r_eff] entry range of every kept column
     DBuf<int32_t> csc_row;           // compact pixel (entries of all distinct columns)
     DBuf<double> csc_val;
-    DBuf<double> AZ64;               // [r_eff][n_obs*n_s] column-major (FP64 plans)
+    DBuf<double> AZ64;               // AZ blocks (FP64 plans)
     DBuf<float> AZ32;                // same (mixed plans)
-    DBuf<double> Einv;               // [r_eff][r_eff] row-major
-    DBuf<double> v, w;               // coarse work vectors [r_eff]
-    int zslices = 1;                 // waves per column in Z^T r
-    DBuf<double> vpart;              // [r_eff][zslices] partial sums of Z^T r
+    DBuf<double> Einv;               // E^-1 blocks
+    DBuf<double> w;                  // coarse solution [r_eff]
+    DBuf<int32_t> vslice;            // [r_eff+1] first Z^T r slice of every kept column
+    int64_t n_slices = 0;            // slices of 512 entries over all kept columns
+    DBuf<double> vpart;              // [n_slices] partial sums of Z^T r
 };
 
 }  // namespace mm
@@ -142,6 +184,18 @@ struct mm_plan_s {
     int n_s = 1;
     int64_t n_t = 0, n_pix = 0, n_obs = 0;
     int32_t n_int = 0;
+    // batch of independent problems (1 for a plain plan): problem b owns the intervals
+    // [h_pint[b], h_pint[b+1]), the samples [h_samp[b], h_samp[b+1]) and the compact
+    // pixels [h_ooff[b], h_ooff[b+1])
+    int32_t n_prob = 1;
+    std::vector<int32_t> h_pint;
+    std::vector<int64_t> h_samp, h_ooff;
+    std::vector<int64_t> h_soff;        // [B+1] first padded sorted position of every problem
+    int64_t n_sorted = 0;               // padded sorted length (problems start 8-aligned)
+    mm::DBuf<int32_t> int_prob;         // [n_int] problem of every interval
+    mm::DBuf<int64_t> ooff;             // [B+1] compact pixel offsets
+    mm::DBuf<int32_t> eblk, pblk;       // [B+1] vector-kernel block offsets (elements, pixels)
+    int32_t n_eblk = 0, n_pblk = 0;     // grid sizes of the vector kernels
     std::vector<int64_t> h_off;         // interval offsets
     std::vector<mm_psd> h_psd;
     std::vector<int32_t> h_int_kern;    // interval -> distinct kernel
@@ -158,9 +212,11 @@ struct mm_plan_s {
     mm::DBuf<int32_t> perm;             // sorted position -> sample
     mm::DBuf<double> ws64;              // [n_t][2] weights in sorted order
     mm::DBuf<float> ws32;
-    mm::DBuf<int64_t> seg;              // [n_obs+1] segment offsets
+    mm::DBuf<int64_t> seg;              // [n_obs+1] first sorted position of every pixel;
+                                        // pixel c holds [seg[c], seg[c] + hits[c])
     mm::DBuf<uint64_t> heads;           // segment-start bit per sorted sample
     mm::DBuf<int32_t> wave_pix;         // [n_waves+1] pixel ranges of the P^T waves
+    mm::DBuf<int32_t> wave_prob;        // [n_waves] problem of every wave
     int64_t n_waves = 0;
     mm::DBuf<int32_t> obs;              // compact -> original id
     mm::DBuf<int32_t> hits;             // s_p
@@ -180,11 +236,21 @@ struct mm_plan_s {
     mm::DBuf<float> xp32;
     mm::DBuf<float> tod32a, tod32b;
     mm::DBuf<double> vec[8];            // PCG vectors [n_obs*n_s]
-    mm::DBuf<double> part;              // reduction partials
-    mm::DBuf<mm::PcgScalars> sc;
-    mm::PcgScalars* h_sc = nullptr;     // pinned host mirror
-    mm::DBuf<double> hist;              // residual history
-    mm::DBuf<double> rz_hist;           // r^T z per iteration
+    mm::DBuf<double> part;              // reduction partials [kNumSlots][B][kVecBlocks]
+    mm::DBuf<mm::PcgScalars> sc;        // [B]
+    mm::PcgScalars* h_sc = nullptr;     // pinned host mirror [B]
+    mm::DBuf<int> act, sel;             // [B] masks: iterating / in a residual evaluation
+    mm::DBuf<double> hist;              // residual history [B][hstride]
+    mm::DBuf<double> rz_hist;           // r^T z per iteration [B][hstride]
+    int hstride = 0;
+    // captured PCG iteration (one per operator precision / preconditioner)
+    hipStream_t gstream = nullptr;      // non-blocking stream the graphs are captured on
+    hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    struct GraphKey {          // control arguments baked into a captured iteration
+        int replace = -1;
+        double ratio = 0.0;
+        int max_iter = 0;
+    } gkey[2][2];
     double plan_ms = 0.0;
     // optional event timing of the hot kernels
     bool prof_on = false;
@@ -211,14 +277,18 @@ int scan_exclusive_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s
 // ---- toeplitz.hip
 int build_kernels(mm_plan_t pl);
 int build_tiling(mm_plan_t pl, FftTiling& ft, bool fp64, int n_r_request);
-int toeplitz_map64(mm_plan_t pl, const double* x, double* z, const int* done);
-int toeplitz_map32(mm_plan_t pl, const double* x, float* z, const int* done);
+// map-mode N^-1 P x; mask: per-problem flags (nullptr = all problems); the IQU map must
+// have been packed by pack_map64/32 first
+int pack_map64(mm_plan_t pl, const double* x);
+int pack_map32(mm_plan_t pl, const double* x);
+int toeplitz_map64(mm_plan_t pl, const double* x, double* z, const int* mask);
+int toeplitz_map32(mm_plan_t pl, const double* x, float* z, const int* mask);
 int toeplitz_tod64(mm_plan_t pl, const void* y, int y_f64, double* z);
 int toeplitz_tod32(mm_plan_t pl, const void* y, int y_f64, float* z);
 
 // ---- pointing.hip
-int scatter64(mm_plan_t pl, const double* z, double* x, const int* done);
-int scatter32(mm_plan_t pl, const float* z, double* x, const int* done);
+int scatter64(mm_plan_t pl, const double* z, double* x, const int* mask);
+int scatter32(mm_plan_t pl, const float* z, double* x, const int* mask);
 int depoint(mm_plan_t pl, const double* x, void* y, int y_f64);
 int build_bj(mm_plan_t pl);
 int bj_apply(mm_plan_t pl, const double* r, double* z, const PcgCtl& ctl);
@@ -227,14 +297,25 @@ int bj_apply(mm_plan_t pl, const double* r, double* z, const PcgCtl& ctl);
 int build_coarse(mm_plan_t pl);
 int twolvl_apply(mm_plan_t pl, const double* r, double* z, const PcgCtl& ctl);
 
-// ---- blas.hip
-int vec_dot(mm_plan_t pl, const double* a, const double* b, double* part, const int* done);
+// ---- blas.hip (per-problem vector kernels; ctl supplies the batch layout and mask)
+int build_batch_layout(mm_plan_t pl);
+PcgCtl batch_ctl(mm_plan_t pl);
+// part slot `slot` of every masked problem <- partials of a^T b
+int vec_dot(mm_plan_t pl, const double* a, const double* b, int slot, const PcgCtl& ctl);
 int pcg_update_xr(mm_plan_t pl, double* x, double* r, const double* p, const double* q,
                   const PcgCtl& ctl);
 int pcg_update_p(mm_plan_t pl, double* p, const double* z, const PcgCtl& ctl);
+// out = b - y for masked problems, with partials of ||out||^2 in the Aux slot
+int vec_residual(mm_plan_t pl, const double* b, const double* y, double* out, const PcgCtl& ctl);
 int vec_axpby(mm_plan_t pl, double a, const double* x, double b, const double* y, double* out);
-int vec_set_scalars(mm_plan_t pl, const PcgCtl& ctl, double tol, const double* part_bb,
-                    int iter_base);
+int vec_zero_flagged(mm_plan_t pl, double* x, const int* flag, const PcgCtl& ctl);
+// control kernels (one block per problem)
+int pcg_init(mm_plan_t pl, const PcgCtl& ctl, double tol, int zero_b_done);
+int pcg_check(mm_plan_t pl, const PcgCtl& ctl, int initial);
+int pcg_decide(mm_plan_t pl, const PcgCtl& ctl);
+int pcg_select(mm_plan_t pl, const PcgCtl& ctl);
+int pcg_resume(mm_plan_t pl, const PcgCtl& ctl);
+int pcg_final(mm_plan_t pl, const PcgCtl& ctl);
 
 // host helpers
 int64_t nvec(mm_plan_t pl);
@@ -243,7 +324,7 @@ int prof_begin(mm_plan_t pl, int k, int tag = -1);
 int prof_end(mm_plan_t pl, int k);
 // mark launches recorded since mark[] with tag >= first_skipped as no-ops
 void prof_invalidate(mm_plan_t pl, const size_t* mark, int first_skipped);
-int apply_A64(mm_plan_t pl, const double* x, double* y, const int* done);
-int apply_A32(mm_plan_t pl, const double* x, double* y, const int* done);
+int apply_A64(mm_plan_t pl, const double* x, double* y, const int* mask);
+int apply_A32(mm_plan_t pl, const double* x, double* y, const int* mask);
 
 }  // namespace mm

@@ -130,16 +130,18 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ per
                                                  const T* __restrict__ ws, const T* __restrict__ z,
                                                  const unsigned long long* __restrict__ heads,
                                                  const int32_t* __restrict__ wave_pix,
-                                                 const int64_t* __restrict__ seg, int64_t n_waves,
+                                                 const int64_t* __restrict__ seg,
+                                                 const int32_t* __restrict__ hits, int64_t n_waves,
                                                  double* __restrict__ out,
-                                                 const int* __restrict__ done) {
+                                                 const int* __restrict__ mask,
+                                                 const int32_t* __restrict__ wave_prob) {
     constexpr int E = 4;
-    if (done && *done) return;
     const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (w >= n_waves) return;
+    if (mask && !mask[wave_prob[w]]) return;
     const int32_t p0 = wave_pix[w], p1 = wave_pix[w + 1];
     if (p0 >= p1) return;
-    const int64_t i1 = seg[p1];
+    const int64_t i1 = seg[p1 - 1] + hits[p1 - 1];
     auto load = [&](int64_t base, const bool* valid, T (*v)[NS]) {
         if (base >= i1) {  // whole lane past the range: no loads
 #pragma unroll
@@ -221,7 +223,8 @@ template <int NV>
 __global__ __launch_bounds__(256) void k_bj_build(
     const int32_t* __restrict__ perm, const double* __restrict__ ws,
     const unsigned long long* __restrict__ heads, const int32_t* __restrict__ wave_pix,
-    const int64_t* __restrict__ seg, int64_t n_waves, const int64_t* __restrict__ int_lo,
+    const int64_t* __restrict__ seg, const int32_t* __restrict__ hits, int64_t n_waves,
+    const int64_t* __restrict__ int_lo,
     int32_t n_int, const int32_t* __restrict__ int_kern, const double* __restrict__ t0,
     double rcond_min, double* __restrict__ bj, int* __restrict__ bad, double* __restrict__ rc_out) {
     constexpr int E = 4;
@@ -286,32 +289,22 @@ __global__ __launch_bounds__(256) void k_bj_build(
         if (rc_out) rc_out[c] = rc;
         if (!(rc >= rcond_min)) atomicMin(bad, (int)c);
     };
-    seg_reduce<double, NV, E>(seg[p0], seg[p1], p0, heads, load, emit);
+    seg_reduce<double, NV, E>(seg[p0], seg[p1 - 1] + hits[p1 - 1], p0, heads, load, emit);
 }
 
-// z = M_BD r (+ partial r^T z; optional convergence test on ||r|| in the prologue)
+// z = M_BD r per pixel of every masked problem (+ partials of r^T z for the PCG)
 template <int NS>
 __global__ __launch_bounds__(kVecThreads) void k_bj_apply(const double* __restrict__ r,
                                                           double* __restrict__ z,
                                                           const double* __restrict__ bj,
-                                                          int64_t n_obs, PcgCtl ctl) {
+                                                          PcgCtl ctl) {
     __shared__ double red[kVecThreads];
-    if (ctl.part) {
-        if (ctl.sc->done) return;
-        if (ctl.check) {
-            const double rr = reduce_partials(ctl.part + kSlotRR * kVecBlocks, kVecBlocks, red);
-            const double rel = sqrt(rr) / ctl.sc->bnorm;
-            if (blockIdx.x == 0 && threadIdx.x == 0) {
-                ctl.sc->rr = rr;
-                if (ctl.hist) ctl.hist[ctl.iter] = rel;
-                if (rel <= ctl.sc->tol) ctl.sc->done = 1;
-            }
-            if (rel <= ctl.sc->tol) return;
-        }
-    }
+    const VecBlock vb = vec_block(ctl, NS, false);
+    if (ctl.mask && !ctl.mask[vb.b]) return;
     double acc = 0.0;
-    for (int64_t c = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; c < n_obs;
-         c += (int64_t)gridDim.x * kVecThreads) {
+    for (int64_t q = (int64_t)vb.k * kVecThreads + threadIdx.x; q < vb.n;
+         q += (int64_t)kVecBlocks * kVecThreads) {
+        const int64_t c = vb.base + q;
         if constexpr (NS == 1) {
             const double rv = r[c];
             const double zv = bj[c] * rv;
@@ -329,7 +322,7 @@ __global__ __launch_bounds__(kVecThreads) void k_bj_apply(const double* __restri
             acc += r0 * z0 + r1 * z1 + r2 * z2;
         }
     }
-    if (ctl.part) write_partial(acc, ctl.part + kSlotRZ * kVecBlocks, red);
+    if (ctl.part) write_partial_at(acc, slot_part(ctl, kSlotRZ, vb.b), vb.k, red);
 }
 
 inline int grid_for(int64_t n, int threads = 256, int cap = 65536) {
@@ -340,29 +333,29 @@ inline int grid_for(int64_t n, int threads = 256, int cap = 65536) {
 }
 
 template <typename T>
-int scatter_t(mm_plan_t pl, const T* z, const T* ws, double* x, const int* done) {
+int scatter_t(mm_plan_t pl, const T* z, const T* ws, double* x, const int* mask) {
     const int64_t nb = (pl->n_waves + 3) / 4;
     if (nb == 0) return MM_OK;
     if (pl->n_s == 3)
         hipLaunchKernelGGL((k_scatter<T, 3>), dim3(nb), dim3(256), 0, pl->stream, pl->perm.p, ws, z,
                            (const unsigned long long*)pl->heads.p, pl->wave_pix.p, pl->seg.p,
-                           pl->n_waves, x, done);
+                           pl->hits.p, pl->n_waves, x, mask, pl->wave_prob.p);
     else
         hipLaunchKernelGGL((k_scatter<T, 1>), dim3(nb), dim3(256), 0, pl->stream, pl->perm.p, ws, z,
                            (const unsigned long long*)pl->heads.p, pl->wave_pix.p, pl->seg.p,
-                           pl->n_waves, x, done);
+                           pl->hits.p, pl->n_waves, x, mask, pl->wave_prob.p);
     MM_HIP(hipGetLastError());
     return MM_OK;
 }
 
 }  // namespace
 
-int scatter64(mm_plan_t pl, const double* z, double* x, const int* done) {
-    return scatter_t<double>(pl, z, pl->ws64.p, x, done);
+int scatter64(mm_plan_t pl, const double* z, double* x, const int* mask) {
+    return scatter_t<double>(pl, z, pl->ws64.p, x, mask);
 }
 
-int scatter32(mm_plan_t pl, const float* z, double* x, const int* done) {
-    return scatter_t<float>(pl, z, pl->ws32.p, x, done);
+int scatter32(mm_plan_t pl, const float* z, double* x, const int* mask) {
+    return scatter_t<float>(pl, z, pl->ws32.p, x, mask);
 }
 
 int depoint(mm_plan_t pl, const double* x, void* y, int y_f64) {
@@ -389,12 +382,14 @@ int build_bj(mm_plan_t pl) {
     if (pl->n_s == 3)
         hipLaunchKernelGGL(k_bj_build<6>, dim3(nb), dim3(256), 0, st, pl->perm.p, pl->ws64.p,
                            (const unsigned long long*)pl->heads.p, pl->wave_pix.p, pl->seg.p,
-                           pl->n_waves, pl->int_lo.p, pl->n_int, pl->int_kern.p, pl->kern_t0.p,
+                           pl->hits.p, pl->n_waves, pl->int_lo.p, pl->n_int, pl->int_kern.p,
+                           pl->kern_t0.p,
                            pl->opts.rcond_min, pl->bj.p, bad.p, rc.p);
     else
         hipLaunchKernelGGL(k_bj_build<1>, dim3(nb), dim3(256), 0, st, pl->perm.p, pl->ws64.p,
                            (const unsigned long long*)pl->heads.p, pl->wave_pix.p, pl->seg.p,
-                           pl->n_waves, pl->int_lo.p, pl->n_int, pl->int_kern.p, pl->kern_t0.p,
+                           pl->hits.p, pl->n_waves, pl->int_lo.p, pl->n_int, pl->int_kern.p,
+                           pl->kern_t0.p,
                            pl->opts.rcond_min, pl->bj.p, bad.p, rc.p);
     MM_HIP(hipGetLastError());
     int h_bad = big;
@@ -415,11 +410,11 @@ int build_bj(mm_plan_t pl) {
 
 int bj_apply(mm_plan_t pl, const double* r, double* z, const PcgCtl& ctl) {
     if (pl->n_s == 3)
-        hipLaunchKernelGGL(k_bj_apply<3>, dim3(kVecBlocks), dim3(kVecThreads), 0, pl->stream, r, z,
-                           pl->bj.p, pl->n_obs, ctl);
+        hipLaunchKernelGGL(k_bj_apply<3>, dim3(pl->n_pblk), dim3(kVecThreads), 0, pl->stream, r, z,
+                           pl->bj.p, ctl);
     else
-        hipLaunchKernelGGL(k_bj_apply<1>, dim3(kVecBlocks), dim3(kVecThreads), 0, pl->stream, r, z,
-                           pl->bj.p, pl->n_obs, ctl);
+        hipLaunchKernelGGL(k_bj_apply<1>, dim3(pl->n_pblk), dim3(kVecThreads), 0, pl->stream, r, z,
+                           pl->bj.p, ctl);
     MM_HIP(hipGetLastError());
     return MM_OK;
 }

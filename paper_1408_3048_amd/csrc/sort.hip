@@ -228,16 +228,44 @@ __global__ void k_heads(const int64_t* __restrict__ seg, int64_t n_obs,
     }
 }
 
-__global__ void k_wave_ranges(const int64_t* __restrict__ seg, int64_t n_obs, int64_t n_waves,
-                              int64_t per_wave, int32_t* __restrict__ wp) {
+// largest b in [0, B) with off[b] <= v (off non-decreasing, off[0] <= v)
+__device__ __forceinline__ int find_range(const int64_t* __restrict__ off, int B, int64_t v) {
+    int a = 0, b = B - 1;
+    while (a < b) {
+        const int m = (a + b + 1) >> 1;
+        if (off[m] <= v) a = m; else b = m - 1;
+    }
+    return a;
+}
+
+// per-problem pixel id range (samples of problem b: [samp[b], samp[b+1]))
+__global__ void k_prob_minmax(const int32_t* __restrict__ pix, int64_t n,
+                              const int64_t* __restrict__ samp, int B, int* __restrict__ lo,
+                              int* __restrict__ hi) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int b = find_range(samp, B, t);
+        atomicMin(&lo[b], pix[t]);
+        atomicMax(&hi[b], pix[t]);
+    }
+}
+
+// P^T work ranges: the sorted samples of problem b (from its padded start soff[b]) are cut
+// at soff[b] + k per_wave, each wave taking whole pixels; wave w belongs to problem wprob[w]
+__global__ void k_wave_ranges(const int64_t* __restrict__ seg, const int64_t* __restrict__ ooff,
+                              const int64_t* __restrict__ soff, const int64_t* __restrict__ woff,
+                              int B, int64_t n_obs, int64_t n_waves, int64_t per_wave,
+                              int32_t* __restrict__ wp, int32_t* __restrict__ wprob) {
     for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w <= n_waves;
          w += (int64_t)gridDim.x * blockDim.x) {
         if (w == n_waves) {
             wp[w] = (int32_t)n_obs;
             continue;
         }
-        const int64_t target = w * per_wave;
-        int64_t lo = 0, hi = n_obs;  // first c in [0, n_obs] with seg[c] >= target
+        const int b = find_range(woff, B, w);
+        wprob[w] = b;
+        const int64_t target = soff[b] + (w - woff[b]) * per_wave;
+        int64_t lo = ooff[b], hi = ooff[b + 1];  // first c in [ooff[b], ooff[b+1]] with seg[c] >= target
         while (lo < hi) {
             const int64_t mid = (lo + hi) >> 1;
             if (seg[mid] >= target) hi = mid; else lo = mid + 1;
@@ -246,18 +274,51 @@ __global__ void k_wave_ranges(const int64_t* __restrict__ seg, int64_t n_obs, in
     }
 }
 
+// contiguous sorted order -> padded layout: sorted position i of problem b moves to
+// i - s0[b] + soff[b]; seg shifts with it (pad positions keep perm = -1)
+__global__ void k_pad_sorted(const int32_t* __restrict__ vin, int64_t n,
+                             const int64_t* __restrict__ s0, const int64_t* __restrict__ soff,
+                             int B, int32_t* __restrict__ perm) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int b = find_range(s0, B, i);
+        perm[i - s0[b] + soff[b]] = vin[i];
+    }
+}
+
+__global__ void k_pad_seg(int64_t* __restrict__ seg, int64_t n_obs, const int64_t* __restrict__ ooff,
+                          const int64_t* __restrict__ s0, const int64_t* __restrict__ soff, int B,
+                          int64_t n_sorted) {
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c <= n_obs;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        if (c == n_obs) {
+            seg[c] = n_sorted;
+            continue;
+        }
+        const int b = find_range(ooff, B, c);
+        seg[c] = seg[c] - s0[b] + soff[b];
+    }
+}
+
 template <typename TW>
 __global__ void k_weights(const TW* __restrict__ w, const int32_t* __restrict__ perm, int64_t n,
-                          double* __restrict__ w64, float* __restrict__ w32,
+                          int64_t n_sorted, double* __restrict__ w64, float* __restrict__ w32,
                           double* __restrict__ ws64, float* __restrict__ ws32) {
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_sorted;
          t += (int64_t)gridDim.x * blockDim.x) {
-        const double a = (double)w[2 * t], b = (double)w[2 * t + 1];
-        w64[2 * t] = a;
-        w64[2 * t + 1] = b;
-        if (w32) {
-            w32[2 * t] = (float)a;
-            w32[2 * t + 1] = (float)b;
+        if (t < n) {
+            const double a = (double)w[2 * t], b = (double)w[2 * t + 1];
+            w64[2 * t] = a;
+            w64[2 * t + 1] = b;
+            if (w32) {
+                w32[2 * t] = (float)a;
+                w32[2 * t + 1] = (float)b;
+            }
+        }
+        if (perm[t] < 0) {  // pad position
+            ws64[2 * t] = ws64[2 * t + 1] = 0.0;
+            if (ws32) ws32[2 * t] = ws32[2 * t + 1] = 0.0f;
+            continue;
         }
         const int64_t s = perm[t];
         const double sa = (double)w[2 * s], sb = (double)w[2 * s + 1];
@@ -286,20 +347,39 @@ int scan_exclusive_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s
 int build_pointing(mm_plan_t pl, const int32_t* pix, const void* weights, int wdtype) {
     hipStream_t st = pl->stream;
     const int64_t n = pl->n_t;
-    // pixel range
-    DBuf<int> mm2;
-    MM_TRY(mm2.alloc(2));
-    const int init[2] = {INT_MAX, INT_MIN};
-    MM_HIP(hipMemcpyAsync(mm2.p, init, sizeof(init), hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_minmax, dim3(grid_for(n, 256, 1024)), dim3(256), 0, st, pix, n, mm2.p);
+    const int B = pl->n_prob;
+    // pixel range of every problem; problems must use disjoint, increasing id ranges so that
+    // the compact pixels of problem b form one block [ooff[b], ooff[b+1])
+    DBuf<int> lo, hi;
+    DBuf<int64_t> samp;
+    MM_TRY(lo.alloc(B));
+    MM_TRY(hi.alloc(B));
+    MM_TRY(samp.alloc(B + 1));
+    {
+        std::vector<int> l(B, INT_MAX), h(B, INT_MIN);
+        MM_HIP(hipMemcpyAsync(lo.p, l.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
+        MM_HIP(hipMemcpyAsync(hi.p, h.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
+        MM_HIP(hipMemcpyAsync(samp.p, pl->h_samp.data(), (B + 1) * 8, hipMemcpyHostToDevice, st));
+    }
+    hipLaunchKernelGGL(k_prob_minmax, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, pix, n, samp.p,
+                       B, lo.p, hi.p);
     MM_HIP(hipGetLastError());
-    int h_mm[2];
-    MM_HIP(hipMemcpyAsync(h_mm, mm2.p, sizeof(h_mm), hipMemcpyDeviceToHost, st));
+    std::vector<int> h_lo(B), h_hi(B);
+    MM_HIP(hipMemcpyAsync(h_lo.data(), lo.p, B * sizeof(int), hipMemcpyDeviceToHost, st));
+    MM_HIP(hipMemcpyAsync(h_hi.data(), hi.p, B * sizeof(int), hipMemcpyDeviceToHost, st));
     MM_HIP(hipStreamSynchronize(st));
-    if (h_mm[0] < 0 || (int64_t)h_mm[1] >= pl->n_pix) {
-        set_error("pixel ids span [%d, %d], outside [0, %lld)", h_mm[0], h_mm[1],
-                  (long long)pl->n_pix);
-        return MM_ERR_ARG;
+    for (int b = 0; b < B; ++b) {
+        if (h_lo[b] < 0 || (int64_t)h_hi[b] >= pl->n_pix) {
+            set_error("pixel ids%s span [%d, %d], outside [0, %lld)", B > 1 ? " of a problem" : "",
+                      h_lo[b], h_hi[b], (long long)pl->n_pix);
+            return MM_ERR_ARG;
+        }
+        if (b > 0 && h_lo[b] <= h_hi[b - 1]) {
+            set_error("pixel ids of problem %d (from %d) do not all exceed those of problem %d "
+                      "(up to %d): batched problems need disjoint increasing pixel id ranges",
+                      b, h_lo[b], b - 1, h_hi[b - 1]);
+            return MM_ERR_ARG;
+        }
     }
     // hits on the full grid, compaction
     DBuf<int32_t> hfull, flags, cmap;
@@ -317,14 +397,22 @@ int build_pointing(mm_plan_t pl, const int32_t* pix, const void* weights, int wd
     int64_t n_obs = 0;
     MM_HIP(hipMemcpy(&n_obs, pos.p + pl->n_pix, sizeof(int64_t), hipMemcpyDeviceToHost));
     pl->n_obs = n_obs;
+    // compact pixel offsets of the problems: observed pixels below each problem's first id
+    pl->h_ooff.assign(B + 1, n_obs);
+    for (int b = 0; b < B; ++b)
+        MM_HIP(hipMemcpyAsync(&pl->h_ooff[b], pos.p + h_lo[b], sizeof(int64_t),
+                              hipMemcpyDeviceToHost, st));
     MM_TRY(pl->obs.alloc(n_obs));
     MM_TRY(pl->hits.alloc(n_obs));
     hipLaunchKernelGGL(k_compact, dim3(grid_for(pl->n_pix)), dim3(256), 0, st, hfull.p, pos.p,
                        pl->n_pix, cmap.p, pl->obs.p, pl->hits.p);
     MM_HIP(hipGetLastError());
+    MM_HIP(hipStreamSynchronize(st));
     hfull.release();
     flags.release();
     pos.release();
+    MM_TRY(pl->ooff.alloc(B + 1));
+    MM_HIP(hipMemcpyAsync(pl->ooff.p, pl->h_ooff.data(), (B + 1) * 8, hipMemcpyHostToDevice, st));
     // compact id per sample
     MM_TRY(pl->cid.alloc(n));
     DBuf<int32_t> k2, v1, v2;
@@ -332,7 +420,7 @@ int build_pointing(mm_plan_t pl, const int32_t* pix, const void* weights, int wd
     hipLaunchKernelGGL(k_cid, dim3(grid_for(n)), dim3(256), 0, st, pix, n, cmap.p, pl->cid.p, v1.p);
     MM_HIP(hipGetLastError());
     cmap.release();
-    // segments
+    // segments (contiguous sorted order for now)
     MM_TRY(pl->seg.alloc(n_obs + 1));
     MM_TRY(scan_exclusive<int32_t>(pl->hits.p, pl->seg.p, n_obs, st));
     // stable radix sort by compact pixel
@@ -361,10 +449,37 @@ int build_pointing(mm_plan_t pl, const int32_t* pix, const void* weights, int wd
         std::swap(kin, kout);
         std::swap(vin, vout);
     }
+    // padded layout: every problem's sorted samples start at a multiple of 8, so the
+    // P^T lane and wave structure of a problem does not depend on what precedes it
+    std::vector<int64_t> s0(B + 1);
+    for (int b = 0; b < B; ++b)
+        MM_HIP(hipMemcpyAsync(&s0[b], pl->seg.p + pl->h_ooff[b], 8, hipMemcpyDeviceToHost, st));
+    MM_HIP(hipStreamSynchronize(st));
+    s0[B] = n;
+    pl->h_soff.assign(B + 1, 0);
+    for (int b = 0; b < B; ++b)
+        pl->h_soff[b + 1] = (pl->h_soff[b] + (s0[b + 1] - s0[b]) + kSortedPad - 1) / kSortedPad *
+                            kSortedPad;
+    const int64_t ns_sorted = B == 1 ? n : pl->h_soff[B];
+    pl->n_sorted = ns_sorted;
+    DBuf<int64_t> ds0, dsoff;
+    MM_TRY(ds0.alloc(B + 1));
+    MM_TRY(dsoff.alloc(B + 1));
+    MM_HIP(hipMemcpyAsync(ds0.p, s0.data(), (B + 1) * 8, hipMemcpyHostToDevice, st));
+    MM_HIP(hipMemcpyAsync(dsoff.p, pl->h_soff.data(), (B + 1) * 8, hipMemcpyHostToDevice, st));
     // sorted arrays carry a zeroed tail of kSortedPad samples for aligned vector loads
-    MM_TRY(pl->perm.alloc(n + kSortedPad));
-    MM_HIP(hipMemsetAsync(pl->perm.p + n, 0, kSortedPad * sizeof(int32_t), st));
-    MM_HIP(hipMemcpyAsync(pl->perm.p, vin, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    MM_TRY(pl->perm.alloc(ns_sorted + kSortedPad));
+    MM_HIP(hipMemsetAsync(pl->perm.p + ns_sorted, 0, kSortedPad * sizeof(int32_t), st));
+    if (B == 1) {
+        MM_HIP(hipMemcpyAsync(pl->perm.p, vin, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    } else {
+        MM_HIP(hipMemsetAsync(pl->perm.p, 0xff, ns_sorted * sizeof(int32_t), st));
+        hipLaunchKernelGGL(k_pad_sorted, dim3(grid_for(n)), dim3(256), 0, st, vin, n, ds0.p,
+                           dsoff.p, B, pl->perm.p);
+        hipLaunchKernelGGL(k_pad_seg, dim3(grid_for(n_obs + 1)), dim3(256), 0, st, pl->seg.p, n_obs,
+                           pl->ooff.p, ds0.p, dsoff.p, B, ns_sorted);
+        MM_HIP(hipGetLastError());
+    }
     MM_HIP(hipStreamSynchronize(st));
     k1.release();
     k2.release();
@@ -372,37 +487,45 @@ int build_pointing(mm_plan_t pl, const int32_t* pix, const void* weights, int wd
     v2.release();
     counts.release();
     offs.release();
-    // segment heads and P^T work ranges
-    const int64_t nwords = (n + 63) / 64 + 1;
+    // segment heads and P^T work ranges (per problem)
+    const int64_t nwords = (ns_sorted + 63) / 64 + 1;
     MM_TRY(pl->heads.alloc(nwords));
     MM_HIP(hipMemsetAsync(pl->heads.p, 0, nwords * sizeof(uint64_t), st));
     hipLaunchKernelGGL(k_heads, dim3(grid_for(n_obs)), dim3(256), 0, st, pl->seg.p, n_obs,
                        (unsigned long long*)pl->heads.p);
+    MM_HIP(hipGetLastError());
     const int64_t per_wave = 2048;
-    pl->n_waves = (n + per_wave - 1) / per_wave;
+    std::vector<int64_t> woff(B + 1, 0);
+    for (int b = 0; b < B; ++b) woff[b + 1] = woff[b] + (s0[b + 1] - s0[b] + per_wave - 1) / per_wave;
+    pl->n_waves = woff[B];
+    DBuf<int64_t> dwoff;
+    MM_TRY(dwoff.alloc(B + 1));
+    MM_HIP(hipMemcpyAsync(dwoff.p, woff.data(), (B + 1) * 8, hipMemcpyHostToDevice, st));
     MM_TRY(pl->wave_pix.alloc(pl->n_waves + 1));
+    MM_TRY(pl->wave_prob.alloc(std::max<int64_t>(1, pl->n_waves)));
     hipLaunchKernelGGL(k_wave_ranges, dim3(grid_for(pl->n_waves + 1)), dim3(256), 0, st, pl->seg.p,
-                       n_obs, pl->n_waves, per_wave, pl->wave_pix.p);
+                       pl->ooff.p, dsoff.p, dwoff.p, B, n_obs, pl->n_waves, per_wave,
+                       pl->wave_pix.p, pl->wave_prob.p);
     MM_HIP(hipGetLastError());
     // weights, time-ordered and pixel-sorted
     if (pl->n_s == 3) {
         const bool mixed = pl->opts.precision == MM_MIXED;
         MM_TRY(pl->w64.alloc(2 * n));
-        MM_TRY(pl->ws64.alloc(2 * (n + kSortedPad)));
-        MM_HIP(hipMemsetAsync(pl->ws64.p + 2 * n, 0, 2 * kSortedPad * sizeof(double), st));
+        MM_TRY(pl->ws64.alloc(2 * (ns_sorted + kSortedPad)));
+        MM_HIP(hipMemsetAsync(pl->ws64.p + 2 * ns_sorted, 0, 2 * kSortedPad * sizeof(double), st));
         if (mixed) {
             MM_TRY(pl->w32.alloc(2 * n));
-            MM_TRY(pl->ws32.alloc(2 * (n + kSortedPad)));
-            MM_HIP(hipMemsetAsync(pl->ws32.p + 2 * n, 0, 2 * kSortedPad * sizeof(float), st));
+            MM_TRY(pl->ws32.alloc(2 * (ns_sorted + kSortedPad)));
+            MM_HIP(hipMemsetAsync(pl->ws32.p + 2 * ns_sorted, 0, 2 * kSortedPad * sizeof(float), st));
         }
         if (wdtype == MM_F64)
-            hipLaunchKernelGGL(k_weights<double>, dim3(grid_for(n)), dim3(256), 0, st,
-                               (const double*)weights, pl->perm.p, n, pl->w64.p, pl->w32.p,
-                               pl->ws64.p, pl->ws32.p);
+            hipLaunchKernelGGL(k_weights<double>, dim3(grid_for(ns_sorted)), dim3(256), 0, st,
+                               (const double*)weights, pl->perm.p, n, ns_sorted, pl->w64.p,
+                               pl->w32.p, pl->ws64.p, pl->ws32.p);
         else
-            hipLaunchKernelGGL(k_weights<float>, dim3(grid_for(n)), dim3(256), 0, st,
-                               (const float*)weights, pl->perm.p, n, pl->w64.p, pl->w32.p,
-                               pl->ws64.p, pl->ws32.p);
+            hipLaunchKernelGGL(k_weights<float>, dim3(grid_for(ns_sorted)), dim3(256), 0, st,
+                               (const float*)weights, pl->perm.p, n, ns_sorted, pl->w64.p,
+                               pl->w32.p, pl->ws64.p, pl->ws32.p);
         MM_HIP(hipGetLastError());
     }
     MM_HIP(hipStreamSynchronize(st));

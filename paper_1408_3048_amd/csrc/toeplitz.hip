@@ -171,7 +171,8 @@ struct ToepArgs {
     const int64_t* int_hi;
     const int32_t* int_kern;
     int lam;
-    const int* done;
+    const int* mask;          // per-problem flags: tiles of problems with mask 0 are skipped
+    const int32_t* int_prob;  // problem of every interval
 };
 
 // LDS layout of the complex work array (M points).  Element a lives at
@@ -538,11 +539,11 @@ __global__ __launch_bounds__(NT) void k_toeplitz(ToepArgs<T> a) {
     constexpr int M = 1 << LOGM;
     __shared__ __align__(16) unsigned char smem[2 * M * sizeof(T)];
     const CBuf<T> buf = make_cbuf<T>(smem, M);
-    if (a.done && *a.done) return;
     const int64_t tile = blockIdx.x;
+    const int j = a.tile_int[tile];
+    if (a.mask && !a.mask[a.int_prob[j]]) return;
     const int64_t o = a.tile_out[tile];
     const int L = a.tile_len[tile];
-    const int j = a.tile_int[tile];
     const int64_t lo = a.int_lo[j], hi = a.int_hi[j];
     const int lam = a.lam;
     load_window<T, LOGM, NT, MODE>(a, buf, o - lam, L + 2 * lam, lo, hi);
@@ -714,9 +715,7 @@ int launch(const ToepArgs<T>& a, int logm, int64_t n_tiles, hipStream_t st) {
 
 // (I, Q, U) per pixel -> (I, Q, U, 0) in T, one aligned 16/32-byte record per pixel
 template <typename T>
-__global__ void k_pack_map(const double* __restrict__ x, int64_t n_obs, T* __restrict__ xp,
-                           const int* __restrict__ done) {
-    if (done && *done) return;
+__global__ void k_pack_map(const double* __restrict__ x, int64_t n_obs, T* __restrict__ xp) {
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_obs;
          c += (int64_t)gridDim.x * blockDim.x) {
         xp[4 * c] = (T)x[3 * c];
@@ -727,11 +726,11 @@ __global__ void k_pack_map(const double* __restrict__ x, int64_t n_obs, T* __res
 }
 
 template <typename T>
-int pack_map(mm_plan_t pl, const double* x, T* xp, const int* done) {
+int pack_map(mm_plan_t pl, const double* x, T* xp) {
     int64_t g = (pl->n_obs + 255) / 256;
     if (g > 8192) g = 8192;
     if (g < 1) g = 1;
-    hipLaunchKernelGGL(k_pack_map<T>, dim3(g), dim3(256), 0, pl->stream, x, pl->n_obs, xp, done);
+    hipLaunchKernelGGL(k_pack_map<T>, dim3(g), dim3(256), 0, pl->stream, x, pl->n_obs, xp);
     MM_HIP(hipGetLastError());
     return MM_OK;
 }
@@ -746,6 +745,7 @@ ToepArgs<T> base_args(mm_plan_t pl, const FftTiling& ft) {
     a.int_lo = pl->int_lo.p;
     a.int_hi = pl->int_hi.p;
     a.int_kern = pl->int_kern.p;
+    a.int_prob = pl->int_prob.p;
     a.lam = pl->opts.lambda;
     if constexpr (sizeof(T) == 8) {
         a.H = ft.H64.p;
@@ -1089,29 +1089,31 @@ int build_tiling(mm_plan_t pl, FftTiling& ft, bool fp64, int n_r_request) {
 
 // ------------------------------------------------------------------ host: launches
 
-int toeplitz_map64(mm_plan_t pl, const double* x, double* z, const int* done) {
+int pack_map64(mm_plan_t pl, const double* x) {
+    return pl->n_s == 3 ? pack_map<double>(pl, x, pl->xp64.p) : MM_OK;
+}
+
+int pack_map32(mm_plan_t pl, const double* x) {
+    return pl->n_s == 3 ? pack_map<float>(pl, x, pl->xp32.p) : MM_OK;
+}
+
+int toeplitz_map64(mm_plan_t pl, const double* x, double* z, const int* mask) {
     auto a = base_args<double>(pl, pl->fft64);
     a.x = x;
-    if (pl->n_s == 3) {
-        MM_TRY(pack_map<double>(pl, x, pl->xp64.p, done));
-        a.xp = pl->xp64.p;
-    }
+    if (pl->n_s == 3) a.xp = pl->xp64.p;
     a.mode = pl->n_s == 3 ? 0 : 1;
     a.z = z;
-    a.done = done;
+    a.mask = mask;
     return launch<double>(a, pl->fft64.logm, pl->fft64.n_tiles, pl->stream);
 }
 
-int toeplitz_map32(mm_plan_t pl, const double* x, float* z, const int* done) {
+int toeplitz_map32(mm_plan_t pl, const double* x, float* z, const int* mask) {
     auto a = base_args<float>(pl, pl->fft32);
     a.x = x;
-    if (pl->n_s == 3) {
-        MM_TRY(pack_map<float>(pl, x, pl->xp32.p, done));
-        a.xp = pl->xp32.p;
-    }
+    if (pl->n_s == 3) a.xp = pl->xp32.p;
     a.mode = pl->n_s == 3 ? 0 : 1;
     a.z = z;
-    a.done = done;
+    a.mask = mask;
     return launch<float>(a, pl->fft32.logm, pl->fft32.n_tiles, pl->stream);
 }
 
