@@ -85,6 +85,45 @@ def cpu_baseline(sc, n_ax, n_intervals_sample):
                 t_ax_s=t_ax)
 
 
+def batched_leg(tol, warmup=1):
+    """The batched Monte Carlo workload: 256 independent noise-only problems of uneven
+    length (2^16..2^20 samples before dropping out-of-patch samples) over 128x128 IQU
+    patches, one batched plan, mixed-precision two-level PCG to tol for all problems at
+    once.  Reported: plan + solve wall time and right-hand sides per second."""
+    import torch
+    import synth
+    from paper_1408_3048_amd import Plan
+    t = time.perf_counter()
+    sc = synth.cfg4_batched_iqu()
+    log(f"batched scans generated in {time.perf_counter() - t:.1f}s: {sc.n_samples} samples, "
+        f"{len(sc.problem_offsets) - 1} problems, {sc.offsets.shape[0] - 1} intervals")
+    pix = torch.from_numpy(sc.pix).cuda()
+    w = torch.from_numpy(sc.weights).cuda()
+    d = torch.from_numpy(sc.noise).cuda()
+    psd = np.stack([sc.sigma, sc.fknee, sc.alpha], axis=1)
+    res = None
+    for i in range(warmup + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan = Plan(pix, w, sc.n_pix, sc.offsets, psd, n_stokes=3, lam=sc.lam, f_samp=sc.f_samp,
+                    precision="mixed", coarse=True, problem_intervals=sc.problem_offsets)
+        b = plan.rhs(d)
+        x, info = plan.pcg_solve(b, precond="2lvl", precision="mixed", tol=tol, max_iter=5000,
+                                 history=False)
+        torch.cuda.synchronize()
+        tt = time.perf_counter() - t0
+        its = [p["iterations"] for p in info["problems"]]
+        res = dict(problems=plan.n_problems, n_samples=sc.n_samples, unknowns=plan.n_vec,
+                   time_s=tt, plan_ms=plan.plan_ms, solve_ms=info["solve_ms"],
+                   rhs_per_s=plan.n_problems / tt, samples_per_s=sc.n_samples / tt,
+                   iterations_max=max(its), iterations_mean=float(np.mean(its)),
+                   rel_residual_max=info["rel_residual_max"], r_eff=plan.coarse_rank(),
+                   method="mixed two-level PCG, one batched plan, graph-captured iterations")
+        log(f"batched {'warmup' if i < warmup else 'timed'}: {tt * 1e3:.1f} ms {res}")
+        plan.close()
+    return res
+
+
 def kernel_traffic(name):
     """HBM bytes per launch of a kernel from the stored counter figures, or None when its
     source has changed since they were taken."""
@@ -124,6 +163,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-intervals", type=int, default=4)
     ap.add_argument("--no-reference", action="store_true", help="skip the FP64 block-Jacobi leg")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 256-problem batched Monte Carlo leg")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="1: FFT tile lengths picked by timing at plan time (cached per process)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the 256 MiB copy that calibrates the HBM byte counters")
     args = ap.parse_args()
@@ -162,7 +205,8 @@ def main():
     def step(precision, coarse, precond, profile=False):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        plan = Plan(pix, w, sc.n_pix, sc.offsets, psd, precision=precision, coarse=coarse, **kw)
+        plan = Plan(pix, w, sc.n_pix, sc.offsets, psd, precision=precision, coarse=coarse,
+                    autotune=bool(args.autotune), **kw)
         if profile:
             plan.profile(True)
         b = plan.rhs(d)
@@ -172,6 +216,7 @@ def main():
         t1 = time.perf_counter()
         prof = plan.profile_read() if profile else None
         extra = dict(plan_ms=plan.plan_ms, solve_ms=info["solve_ms"], iterations=info["iterations"],
+                     fft_lengths=plan.fft_lengths(),
                      outer=info["outer_iterations"], relres=info["rel_residual"],
                      r_eff=plan.coarse_rank() if coarse else 0, unknowns=plan.n_vec)
         plan.close()
@@ -244,6 +289,10 @@ def main():
                 other_kernels={k: dict(launches=v[0], avg_ms=v[1] / max(v[0], 1))
                                for k, v in prof.items() if v[0] > 0})
 
+    batched = None
+    if not args.no_batched:
+        batched = batched_leg(args.tol)
+
     cpu = None
     if not args.no_cpu_baseline:
         ex = extras[-1]
@@ -262,7 +311,8 @@ def main():
                               "lambda=2048, mixed FP32/FP64 two-level PCG to 1e-8 incl. plan"),
                     n_samples=sc.n_samples, unknowns=extras[-1]["unknowns"],
                     tol=args.tol, parallelism="single GPU"),
-        breakdown=extras[-1], reference=ref, other_legs=legs, roofline=roof, cpu_baseline=cpu,
+        breakdown=extras[-1], reference=ref, other_legs=legs, batched=batched, roofline=roof,
+        cpu_baseline=cpu,
     )
     print(json.dumps(out), flush=True)
 

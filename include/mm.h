@@ -231,6 +231,10 @@ typedef struct {
 int mm_pcg_solve(mm_plan_t plan, const double* b, double* x, int precond, int precision,
                  double tol, int max_iter, mm_solve_info* info);
 
+/* FFT lengths (real samples per overlap-save tile) the plan uses for the FP64 and the
+ * FP32 operator (0 for an operator the plan does not have). */
+int mm_fft_lengths(mm_plan_t plan, int* n_r_f64, int* n_r_f32);
+
 /* Wall time in ms that mm_plan took for this plan (host clock around all its device work);
  * -1 on NULL. */
 double mm_plan_time_ms(mm_plan_t plan);

@@ -34,7 +34,7 @@ EXPORTED = [
     "mm_coarse_matrix", "mm_apply_P", "mm_apply_Ninv", "mm_apply_PT", "mm_rhs", "mm_apply_A",
     "mm_precond_bj", "mm_precond_2lvl", "mm_pcg_solve", "mm_plan_time_ms", "mm_gemm_tn_f64",
     "mm_profile", "mm_profile_read", "mm_last_error", "mm_plan_batched", "mm_n_problems",
-    "mm_problem_pixels", "mm_coarse_problem_columns",
+    "mm_problem_pixels", "mm_coarse_problem_columns", "mm_fft_lengths",
 ]
 
 
@@ -108,6 +108,7 @@ def load():
         "mm_n_problems": (I, [P]),
         "mm_problem_pixels": (I, [P, P]),
         "mm_coarse_problem_columns": (I, [P, P, I]),
+        "mm_fft_lengths": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -263,6 +264,12 @@ class Plan:
         out = np.empty(r, dtype=np.int32)
         self._lib.mm_coarse_columns(self._h, out.ctypes.data_as(ctypes.c_void_p), r)
         return out
+
+    def fft_lengths(self):
+        """(n_r of the FP64 operator, n_r of the FP32 operator or 0)."""
+        a, b = ctypes.c_int(), ctypes.c_int()
+        check(self._lib.mm_fft_lengths(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     def problem_pixels(self):
         """Host int64 [B+1]: first compact pixel of every problem."""

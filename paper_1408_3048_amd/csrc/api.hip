@@ -514,10 +514,15 @@ int mm_plan_batched(mm_plan_t* out, int32_t n_problems, const int32_t* problem_i
     tick("pointing");
     if ((s = build_kernels(pl)) != MM_OK) return fail(s);
     tick("taps");
-    if ((s = build_tiling(pl, pl->fft64, true, opts->fft_len_f64)) != MM_OK) return fail(s);
+    const bool tune64 = opts->autotune && opts->fft_len_f64 == 0;
+    const bool tune32 = opts->autotune && opts->fft_len_f32 == 0;
+    if ((s = tune64 ? autotune_tiling(pl, pl->fft64, true)
+                    : build_tiling(pl, pl->fft64, true, opts->fft_len_f64)) != MM_OK)
+        return fail(s);
     tick("tiling64");
     const bool mixed = opts->precision == MM_MIXED;
-    if (mixed && (s = build_tiling(pl, pl->fft32, false, opts->fft_len_f32)) != MM_OK)
+    if (mixed && (s = tune32 ? autotune_tiling(pl, pl->fft32, false)
+                             : build_tiling(pl, pl->fft32, false, opts->fft_len_f32)) != MM_OK)
         return fail(s);
     tick("tiling32");
     if ((s = build_bj(pl)) != MM_OK) return fail(s);
@@ -925,6 +930,17 @@ int mm_pcg_solve(mm_plan_t pl, const double* b, double* x, int pc, int precision
 }
 
 double mm_plan_time_ms(mm_plan_t pl) { return pl ? pl->plan_ms : -1.0; }
+
+int mm_fft_lengths(mm_plan_t pl, int* n64, int* n32) {
+    clear_error();
+    if (!pl || !n64 || !n32) {
+        set_error("NULL argument");
+        return MM_ERR_ARG;
+    }
+    *n64 = pl->fft64.n_r;
+    *n32 = pl->opts.precision == MM_MIXED ? pl->fft32.n_r : 0;
+    return MM_OK;
+}
 
 int mm_profile(mm_plan_t pl, int enable) {
     clear_error();

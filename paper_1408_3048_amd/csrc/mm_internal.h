@@ -277,6 +277,8 @@ int scan_exclusive_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s
 // ---- toeplitz.hip
 int build_kernels(mm_plan_t pl);
 int build_tiling(mm_plan_t pl, FftTiling& ft, bool fp64, int n_r_request);
+// the admissible tile length whose map-mode launch is fastest on this plan's data
+int autotune_tiling(mm_plan_t pl, FftTiling& ft, bool fp64);
 // map-mode N^-1 P x; mask: per-problem flags (nullptr = all problems); the IQU map must
 // have been packed by pack_map64/32 first
 int pack_map64(mm_plan_t pl, const double* x);

@@ -238,15 +238,54 @@ __device__ __forceinline__ int find_range(const int64_t* __restrict__ off, int B
     return a;
 }
 
-// per-problem pixel id range (samples of problem b: [samp[b], samp[b+1]))
+// per-problem pixel id range (samples of problem b: [samp[b], samp[b+1])): every thread
+// scans 64 consecutive samples keeping a running range per problem; ranges are combined
+// over the wave when all its lanes end in the same problem, so the atomics stay few
 __global__ void k_prob_minmax(const int32_t* __restrict__ pix, int64_t n,
                               const int64_t* __restrict__ samp, int B, int* __restrict__ lo,
                               int* __restrict__ hi) {
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const int b = find_range(samp, B, t);
-        atomicMin(&lo[b], pix[t]);
-        atomicMax(&hi[b], pix[t]);
+    constexpr int64_t kRun = 64;
+    const int64_t ng = (n + kRun - 1) / kRun;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // every lane runs the same number of rounds so the wave reduction below is uniform
+    const int64_t rounds = (ng + stride - 1) / stride;
+    for (int64_t rd = 0; rd < rounds; ++rd) {
+        const int64_t g = g0 + rd * stride;
+        int b = -1, l = INT_MAX, h = INT_MIN;
+        if (g < ng) {
+            const int64_t t0 = g * kRun, t1 = t0 + kRun < n ? t0 + kRun : n;
+            b = find_range(samp, B, t0);
+            int64_t next = samp[b + 1];
+            for (int64_t t = t0; t < t1; ++t) {
+                if (t >= next) {  // problem boundary inside the run
+                    atomicMin(&lo[b], l);
+                    atomicMax(&hi[b], h);
+                    l = INT_MAX;
+                    h = INT_MIN;
+                    b = find_range(samp, B, t);
+                    next = samp[b + 1];
+                }
+                const int v = pix[t];
+                l = min(l, v);
+                h = max(h, v);
+            }
+        }
+        const int b0 = __shfl(b, 0);
+        const bool same = __all(b == b0);
+        if (same && b0 >= 0) {
+            for (int o = 32; o > 0; o >>= 1) {
+                l = min(l, __shfl_xor(l, o));
+                h = max(h, __shfl_xor(h, o));
+            }
+            if ((threadIdx.x & 63) == 0) {
+                atomicMin(&lo[b0], l);
+                atomicMax(&hi[b0], h);
+            }
+        } else if (b >= 0) {
+            atomicMin(&lo[b], l);
+            atomicMax(&hi[b], h);
+        }
     }
 }
 
@@ -361,8 +400,8 @@ int build_pointing(mm_plan_t pl, const int32_t* pix, const void* weights, int wd
         MM_HIP(hipMemcpyAsync(hi.p, h.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
         MM_HIP(hipMemcpyAsync(samp.p, pl->h_samp.data(), (B + 1) * 8, hipMemcpyHostToDevice, st));
     }
-    hipLaunchKernelGGL(k_prob_minmax, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, pix, n, samp.p,
-                       B, lo.p, hi.p);
+    hipLaunchKernelGGL(k_prob_minmax, dim3(grid_for((n + 63) / 64, 256, 4096)), dim3(256), 0, st,
+                       pix, n, samp.p, B, lo.p, hi.p);
     MM_HIP(hipGetLastError());
     std::vector<int> h_lo(B), h_hi(B);
     MM_HIP(hipMemcpyAsync(h_lo.data(), lo.p, B * sizeof(int), hipMemcpyDeviceToHost, st));

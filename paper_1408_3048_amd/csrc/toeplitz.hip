@@ -22,6 +22,7 @@
 // passes held in registers with one LDS exchange per pass.
 #include <cmath>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <type_traits>
 
@@ -1133,6 +1134,104 @@ int toeplitz_tod32(mm_plan_t pl, const void* y, int y_f64, float* z) {
     a.mode = y_f64 ? 2 : 3;
     a.z = z;
     return launch<float>(a, pl->fft32.logm, pl->fft32.n_tiles, pl->stream);
+}
+
+// ------------------------------------------------------------------ FFT length autotuner
+//
+// Every admissible tile length is built and its map-mode launch (gather + overlap-save,
+// the kernel of A x) timed on the plan's own pointing and intervals; the fastest is
+// kept.  Choices are cached per process by the interval-length profile, lambda, n_s
+// and precision, so plans of the same workload tune once.
+
+namespace {
+
+void swap_tiling(FftTiling& a, FftTiling& b) {
+    std::swap(a.logm, b.logm);
+    std::swap(a.n_r, b.n_r);
+    std::swap(a.n_tiles, b.n_tiles);
+    a.tile_out.swap(b.tile_out);
+    a.tile_len.swap(b.tile_len);
+    a.tile_int.swap(b.tile_int);
+    a.H64.swap(b.H64);
+    a.H32.swap(b.H32);
+    a.tw64.swap(b.tw64);
+    a.tw32.swap(b.tw32);
+}
+
+std::mutex g_tune_mu;
+std::map<std::vector<int64_t>, int> g_tune_cache;
+
+template <typename T>
+int time_map_launch(mm_plan_t pl, FftTiling& ft, T* xp, const double* x, T* z, float* ms) {
+    auto a = base_args<T>(pl, ft);
+    a.x = x;
+    a.xp = xp;
+    a.mode = pl->n_s == 3 ? 0 : 1;
+    a.z = z;
+    hipEvent_t e0, e1;
+    MM_HIP(hipEventCreate(&e0));
+    MM_HIP(hipEventCreate(&e1));
+    int s = launch<T>(a, ft.logm, ft.n_tiles, pl->stream);  // warm-up
+    if (s == MM_OK) {
+        (void)hipEventRecord(e0, pl->stream);
+        for (int r = 0; r < 3 && s == MM_OK; ++r) s = launch<T>(a, ft.logm, ft.n_tiles, pl->stream);
+        (void)hipEventRecord(e1, pl->stream);
+        (void)hipEventSynchronize(e1);
+        (void)hipEventElapsedTime(ms, e0, e1);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return s;
+}
+
+}  // namespace
+
+int autotune_tiling(mm_plan_t pl, FftTiling& ft, bool fp64) {
+    const int lam = pl->opts.lambda;
+    const int maxlogm = fp64 ? kMaxLogM64 : kMaxLogM32;
+    std::vector<int64_t> key;
+    key.reserve(pl->n_int + 4);
+    key.push_back(fp64);
+    key.push_back(lam);
+    key.push_back(pl->n_s);
+    for (int32_t j = 0; j < pl->n_int; ++j) key.push_back(pl->h_off[j + 1] - pl->h_off[j]);
+    int cached = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) cached = it->second;
+    }
+    if (cached) return build_tiling(pl, ft, fp64, 2 << cached);
+    const int64_t nx = pl->n_obs * pl->n_s;
+    DBuf<double> x;
+    DBuf<unsigned char> xp, z;
+    MM_TRY(x.alloc(nx));
+    MM_TRY(xp.alloc((size_t)4 * pl->n_obs * (fp64 ? 8 : 4)));
+    MM_TRY(z.alloc((size_t)pl->n_t * (fp64 ? 8 : 4)));
+    MM_HIP(hipMemsetAsync(x.p, 0, nx * 8, pl->stream));
+    MM_HIP(hipMemsetAsync(xp.p, 0, xp.n, pl->stream));
+    int best_l = 0;
+    float best_ms = 0.0f;
+    for (int l = kMinLogM + 1; l <= maxlogm; ++l) {
+        const int64_t nr = (int64_t)2 << l;
+        if (nr - 2 * (int64_t)lam < nr / 4) continue;
+        FftTiling cand;
+        MM_TRY(build_tiling(pl, cand, fp64, (int)nr));
+        float ms = 0.0f;
+        if (fp64)
+            MM_TRY(time_map_launch<double>(pl, cand, (double*)xp.p, x.p, (double*)z.p, &ms));
+        else
+            MM_TRY(time_map_launch<float>(pl, cand, (float*)xp.p, x.p, (float*)z.p, &ms));
+        if (best_l == 0 || ms < best_ms) {
+            best_ms = ms;
+            best_l = l;
+            swap_tiling(ft, cand);
+        }
+    }
+    if (best_l == 0) return build_tiling(pl, ft, fp64, 0);  // reports the error
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = best_l;
+    return MM_OK;
 }
 
 }  // namespace mm
