@@ -50,7 +50,7 @@ __all__ = [
     "compact", "hits", "interval_of_sample", "inverse_psd", "toeplitz_taps",
     "toeplitz_taps_cosine_sum", "taps_symbol", "toeplitz_apply", "toeplitz_apply_at",
     "toeplitz_dense", "Problem", "pcg", "dense_system", "coarse_zs", "Coarse",
-    "tap_derivatives", "lag_correlations",
+    "tap_derivatives", "lag_correlations", "map_gradients_dense", "map_dense",
 ]
 
 
@@ -447,3 +447,43 @@ def lag_correlations(u, v, K):
     for k in range(1, c.shape[0]):
         c[k] = u[:-k] @ v[k:] + u[k:] @ v[:-k]
     return c
+
+
+def map_gradients_dense(prob: Problem, d, g):
+    """Gradients of a loss L(m_hat) of the GLS map m_hat = A^-1 P^T N^-1 d (eq. glsSol),
+    given g = dL/dm_hat, from explicit dense matrices (tiny problems):
+
+      mu = A^-1 g                      (A symmetric)
+      dL/dd = N^-1 P mu                (m_hat is linear in d)
+      dL/dtheta_j = (P mu)_j^T (dT_j/dtheta_j) (d - P m_hat)_j
+
+    the last line from d m_hat = A^-1 P^T dN^-1 (d - P m_hat), dN^-1 being block j's
+    Toeplitz derivative (taps from tap_derivatives) and theta_j = (sigma, f_knee, alpha).
+    Returns (m_hat, dL/dd, dL/dtheta [n_int, 3], mu)."""
+    A, P, N = dense_system(prob)
+    d = np.asarray(d, dtype=np.float64)
+    L = np.linalg.cholesky(A)
+
+    def solve(rhs):
+        return np.linalg.solve(L.T, np.linalg.solve(L, rhs))
+
+    m = solve(P.T @ (N @ d))
+    mu = solve(np.asarray(g, dtype=np.float64))
+    u = P @ mu
+    v = d - P @ m
+    grad_d = N @ u
+    n_int = len(prob.offsets) - 1
+    grad_t = np.zeros((n_int, 3))
+    for j in range(n_int):
+        a, b = int(prob.offsets[j]), int(prob.offsets[j + 1])
+        D = tap_derivatives(b - a, prob.sigma[j], prob.fknee[j], prob.alpha[j], prob.lam,
+                            prob.f_samp, prob.window)
+        for i in range(3):
+            grad_t[j, i] = u[a:b] @ (toeplitz_dense(D[i], b - a) @ v[a:b])
+    return m, grad_d, grad_t, mu
+
+
+def map_dense(prob: Problem, d):
+    """m_hat = A^-1 P^T N^-1 d by a dense Cholesky solve (tiny problems)."""
+    A, P, N = dense_system(prob)
+    return np.linalg.solve(A, P.T @ (N @ np.asarray(d, dtype=np.float64)))
