@@ -235,6 +235,38 @@ int mm_pcg_solve(mm_plan_t plan, const double* b, double* x, int precond, int pr
  * FP32 operator (0 for an operator the plan does not have). */
 int mm_fft_lengths(mm_plan_t plan, int* n_r_f64, int* n_r_f32);
 
+/* ----- adjoint (gradients of a loss of the map) ----- */
+
+/* Lag cross-correlations per stationary interval j of two TOD vectors u, v (device FP64
+ * [N_t]): c_j(0) = sum_t u_t v_t and c_j(k) = sum_t (u_t v_{t+k} + u_{t+k} v_t) for
+ * k = 1..K_j = min(lambda, t_j - 1), t and t+k in interval j, so that u_j^T T_j v_j =
+ * sum_k t_k c_j(k) for the band Toeplitz block T_j [Sect. 2.1, eq. N_def].  dev_out:
+ * device FP64 [n_intervals][lambda+1], zero past K_j.  Deterministic.  Synchronises. */
+int mm_lag_correlations(mm_plan_t plan, const double* u, const double* v, double* dev_out);
+
+/* Derivatives of the windowed Toeplitz taps of every interval with respect to its noise
+ * parameters (sigma, f_knee, alpha) [Sect. 4.1.4, eq. fknee; App. D]: host FP64
+ * [n_intervals][3][lambda+1], zero past K_j; at most cap values written.  The f_knee and
+ * alpha derivatives of a white-noise interval (f_knee = 0) are 0. */
+int mm_tap_derivatives(mm_plan_t plan, double* host_out, int64_t cap);
+
+/* Gradients of a loss L(m_hat) of the GLS map m_hat = A^-1 P^T N^-1 d [Sect. 2.1, eq.
+ * glsSol] given g = dL/dm_hat, by one more PCG solve mu = A^-1 g (A is symmetric):
+ *   dL/dd        = N^-1 P mu                                   (FP64 operator)
+ *   dL/dtheta_j  = (P mu)_j^T (dT_j/dtheta_j) (d - P m_hat)_j,  theta_j = (sigma, f_knee, alpha)
+ *   m_hat, g       device maps (m_hat as returned by mm_pcg_solve for the same d)
+ *   d              device TOD of d_dtype
+ *   precond, precision, tol, max_iter   of the mu solve, as in mm_pcg_solve
+ *   mu_out         device map receiving mu, or NULL
+ *   grad_d         device TOD of grad_d_dtype, or NULL
+ *   grad_psd       host FP64 [n_intervals][3], or NULL
+ *   info           as in mm_pcg_solve (the mu solve), or NULL
+ * Returns the status of the mu solve (gradients are formed only when it is MM_OK), or
+ * MM_ERR_ARG / MM_ERR_STATE / MM_ERR_DEVICE.  Synchronises. */
+int mm_adjoint(mm_plan_t plan, const double* m_hat, const double* g, const void* d, int d_dtype,
+               int precond, int precision, double tol, int max_iter, double* mu_out,
+               void* grad_d, int grad_d_dtype, double* grad_psd, mm_solve_info* info);
+
 /* Wall time in ms that mm_plan took for this plan (host clock around all its device work);
  * -1 on NULL. */
 double mm_plan_time_ms(mm_plan_t plan);

@@ -50,7 +50,7 @@ __all__ = [
     "compact", "hits", "interval_of_sample", "inverse_psd", "toeplitz_taps",
     "toeplitz_taps_cosine_sum", "taps_symbol", "toeplitz_apply", "toeplitz_apply_at",
     "toeplitz_dense", "Problem", "pcg", "dense_system", "coarse_zs", "Coarse",
-    "tap_derivatives", "lag_correlations", "map_gradients_dense", "map_dense",
+    "tap_derivatives", "lag_correlations", "map_gradients_dense", "map_dense", "map_gradients",
 ]
 
 
@@ -487,3 +487,39 @@ def map_dense(prob: Problem, d):
     """m_hat = A^-1 P^T N^-1 d by a dense Cholesky solve (tiny problems)."""
     A, P, N = dense_system(prob)
     return np.linalg.solve(A, P.T @ (N @ np.asarray(d, dtype=np.float64)))
+
+
+def map_gradients(prob: Problem, d, g):
+    """The gradients of map_gradients_dense without dense time-domain matrices, for
+    problems with up to a few thousand unknowns: A is assembled column by column from
+    the banded operator (apply_A), the noise-parameter gradient is the bilinear form
+    (P mu)_j^T (dT_j/dtheta) (d - P m_hat)_j = sum_k dt_k c_j(k) with the lag
+    correlations c_j of lag_correlations.  Returns (m_hat, dL/dd, dL/dtheta, mu)."""
+    n = prob.n_obs * prob.n_s
+    A = np.empty((n, n))
+    e = np.zeros(n)
+    for i in range(n):
+        e[i] = 1.0
+        A[:, i] = prob.apply_A(e)
+        e[i] = 0.0
+    A = 0.5 * (A + A.T)
+    L = np.linalg.cholesky(A)
+
+    def solve(rhs):
+        return np.linalg.solve(L.T, np.linalg.solve(L, rhs))
+
+    d = np.asarray(d, dtype=np.float64)
+    m = solve(prob.rhs(d))
+    mu = solve(np.asarray(g, dtype=np.float64))
+    u = prob.depoint(mu)
+    v = d - prob.depoint(m)
+    grad_d = prob.ninv(u)
+    n_int = len(prob.offsets) - 1
+    grad_t = np.zeros((n_int, 3))
+    for j in range(n_int):
+        a, b = int(prob.offsets[j]), int(prob.offsets[j + 1])
+        D = tap_derivatives(b - a, prob.sigma[j], prob.fknee[j], prob.alpha[j], prob.lam,
+                            prob.f_samp, prob.window)
+        c = lag_correlations(u[a:b], v[a:b], D.shape[1] - 1)
+        grad_t[j] = D @ c
+    return m, grad_d, grad_t, mu

@@ -34,7 +34,8 @@ EXPORTED = [
     "mm_coarse_matrix", "mm_apply_P", "mm_apply_Ninv", "mm_apply_PT", "mm_rhs", "mm_apply_A",
     "mm_precond_bj", "mm_precond_2lvl", "mm_pcg_solve", "mm_plan_time_ms", "mm_gemm_tn_f64",
     "mm_profile", "mm_profile_read", "mm_last_error", "mm_plan_batched", "mm_n_problems",
-    "mm_problem_pixels", "mm_coarse_problem_columns", "mm_fft_lengths",
+    "mm_problem_pixels", "mm_coarse_problem_columns", "mm_fft_lengths", "mm_lag_correlations",
+    "mm_tap_derivatives", "mm_adjoint",
 ]
 
 
@@ -109,6 +110,9 @@ def load():
         "mm_problem_pixels": (I, [P, P]),
         "mm_coarse_problem_columns": (I, [P, P, I]),
         "mm_fft_lengths": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I)]),
+        "mm_lag_correlations": (I, [P, P, P, P]),
+        "mm_tap_derivatives": (I, [P, P, I64]),
+        "mm_adjoint": (I, [P, P, P, P, I, I, I, D, I, P, P, I, P, ctypes.POINTER(mm_solve_info)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -195,6 +199,7 @@ class Plan:
         self.n_obs = int(L.mm_n_obs(self._h))
         self.n_vec = self.n_obs * n_stokes
         self.n_problems = int(L.mm_n_problems(self._h))
+        self.lam = int(lam)
         self.plan_ms = float(L.mm_plan_time_ms(self._h))
 
     @classmethod
@@ -368,6 +373,42 @@ class Plan:
         z = self._vec()
         check(self._lib.mm_precond_2lvl(self._h, _ptr(r), _ptr(z)))
         return z
+
+    # ---- adjoint
+    def lag_correlations(self, u, v):
+        """c[j, k], k = 0..lambda: lag cross-correlations of FP64 TOD u, v per interval."""
+        import torch
+        c = torch.empty((self.n_intervals, self.lam + 1), dtype=torch.float64, device="cuda")
+        check(self._lib.mm_lag_correlations(self._h, _ptr(u), _ptr(v), _ptr(c)))
+        return c
+
+    def tap_derivatives(self):
+        """dt[j, i, k]: derivatives of interval j's taps w.r.t. (sigma, f_knee, alpha)[i]."""
+        out = np.zeros((self.n_intervals, 3, self.lam + 1), dtype=np.float64)
+        check(self._lib.mm_tap_derivatives(self._h, out.ctypes.data_as(ctypes.c_void_p),
+                                           out.size))
+        return out
+
+    def adjoint(self, m_hat, g, d, precond="bj", precision="fp64", tol=1e-10, max_iter=3000,
+                grad_d_dtype=None, want_psd=True):
+        """(dL/dd, dL/dpsd [K, 3] numpy, mu, info) for g = dL/dm_hat."""
+        import torch
+        grad_d_dtype = grad_d_dtype or d.dtype
+        gd = torch.empty(self.n_samples, dtype=grad_d_dtype, device="cuda")
+        gp = np.zeros((self.n_intervals, 3), dtype=np.float64)
+        mu = torch.empty(self.n_vec, dtype=torch.float64, device="cuda")
+        infos = (mm_solve_info * self.n_problems)()
+        st = self._lib.mm_adjoint(
+            self._h, _ptr(m_hat), _ptr(g), _ptr(d), MM_F64 if d.dtype == torch.float64 else MM_F32,
+            MM_2LVL if precond == "2lvl" else MM_BJ,
+            {"fp64": MM_FP64, "mixed": MM_MIXED, "mixed_ir": MM_MIXED_IR}[precision], float(tol),
+            int(max_iter), _ptr(mu), _ptr(gd),
+            MM_F64 if grad_d_dtype == torch.float64 else MM_F32,
+            gp.ctypes.data_as(ctypes.c_void_p) if want_psd else None, infos)
+        check(st)
+        info = dict(iterations=infos[0].iterations, rel_residual=infos[0].rel_residual,
+                    solve_ms=infos[0].solve_ms)
+        return gd, gp, mu, info
 
     def pcg_solve(self, b, x0=None, precond="bj", precision="fp64", tol=1e-8, max_iter=1000,
                   history=True, raise_on_error=True):

@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmm.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "sort.hip", "toeplitz.hip", "pointing.hip", "coarse.hip", "blas.hip"]
+SOURCES = ["api.hip", "sort.hip", "toeplitz.hip", "pointing.hip", "coarse.hip", "blas.hip",
+           "adjoint.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

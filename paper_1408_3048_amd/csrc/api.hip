@@ -931,6 +931,59 @@ int mm_pcg_solve(mm_plan_t pl, const double* b, double* x, int pc, int precision
 
 double mm_plan_time_ms(mm_plan_t pl) { return pl ? pl->plan_ms : -1.0; }
 
+int mm_lag_correlations(mm_plan_t pl, const double* u, const double* v, double* dev_out) {
+    clear_error();
+    MM_TRY(check_vec_args(pl, u, v));
+    if (!dev_out) {
+        set_error("NULL output");
+        return MM_ERR_ARG;
+    }
+    AllocStream alloc_scope(pl->stream);
+    return lag_correlations(pl, u, v, dev_out);
+}
+
+int mm_tap_derivatives(mm_plan_t pl, double* host_out, int64_t cap) {
+    clear_error();
+    if (!pl || !host_out) {
+        set_error("NULL argument");
+        return MM_ERR_ARG;
+    }
+    AllocStream alloc_scope(pl->stream);
+    std::vector<double> dt;
+    MM_TRY(tap_derivatives(pl, dt));
+    for (int64_t e = 0; e < (int64_t)dt.size() && e < cap; ++e) host_out[e] = dt[e];
+    return MM_OK;
+}
+
+int mm_adjoint(mm_plan_t pl, const double* m_hat, const double* g, const void* d, int d_dtype,
+               int pc, int precision, double tol, int max_iter, double* mu_out, void* grad_d,
+               int grad_d_dtype, double* grad_psd, mm_solve_info* info) {
+    clear_error();
+    MM_TRY(check_vec_args(pl, m_hat, g));
+    if (!d || (d_dtype != MM_F32 && d_dtype != MM_F64) ||
+        (grad_d && grad_d_dtype != MM_F32 && grad_d_dtype != MM_F64)) {
+        set_error("d (and grad_d) need a device pointer and dtype MM_F32 or MM_F64");
+        return MM_ERR_ARG;
+    }
+    DBuf<double> mu_tmp;
+    double* mu = mu_out;
+    {
+        AllocStream alloc_scope(pl->stream);
+        if (!mu) {
+            MM_TRY(mu_tmp.alloc(nvec(pl)));
+            mu = mu_tmp.p;
+        }
+        MM_HIP(hipMemsetAsync(mu, 0, nvec(pl) * 8, pl->stream));
+    }
+    const int s = mm_pcg_solve(pl, g, mu, pc, precision, tol, max_iter, info);
+    if (s != MM_OK) return s;
+    AllocStream alloc_scope(pl->stream);
+    MM_TRY(adjoint_tod(pl, m_hat, mu, d, d_dtype == MM_F64, grad_d, grad_d_dtype == MM_F64,
+                       grad_psd));
+    MM_HIP(hipStreamSynchronize(pl->stream));
+    return MM_OK;
+}
+
 int mm_fft_lengths(mm_plan_t pl, int* n64, int* n32) {
     clear_error();
     if (!pl || !n64 || !n32) {

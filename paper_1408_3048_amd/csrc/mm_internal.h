@@ -279,6 +279,19 @@ int build_kernels(mm_plan_t pl);
 int build_tiling(mm_plan_t pl, FftTiling& ft, bool fp64, int n_r_request);
 // the admissible tile length whose map-mode launch is fastest on this plan's data
 int autotune_tiling(mm_plan_t pl, FftTiling& ft, bool fp64);
+// windowed taps of every distinct kernel (what 0) or of the inverse-PSD derivative with
+// respect to sigma / f_knee / alpha (what 1 / 2 / 3), host, flat with offsets and counts
+int kernel_taps(mm_plan_t pl, int what, std::vector<double>& taps, std::vector<int64_t>& toff,
+                std::vector<int64_t>& tcnt);
+
+// ---- adjoint.hip
+// c[j][k], k = 0..lambda (device, zero past K_j): lag cross-correlations of u and v per interval
+int lag_correlations(mm_plan_t pl, const double* u, const double* v, double* c);
+// dt[j][i][k] (host [n_int][3][lambda+1]): tap derivatives of every interval
+int tap_derivatives(mm_plan_t pl, std::vector<double>& dt);
+// TOD and noise-parameter gradients from m_hat and mu = A^-1 g
+int adjoint_tod(mm_plan_t pl, const double* m_hat, const double* mu, const void* d, int d_f64,
+                void* grad_d, int grad_d_f64, double* grad_psd);
 // map-mode N^-1 P x; mask: per-problem flags (nullptr = all problems); the IQU map must
 // have been packed by pack_map64/32 first
 int pack_map64(mm_plan_t pl, const double* x);

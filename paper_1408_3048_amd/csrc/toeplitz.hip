@@ -33,12 +33,32 @@ namespace {
 
 // ------------------------------------------------------------------ plan-time transforms
 
-// q_m for every kernel: a[g][m] = c_m q_m, the coefficients of the real
-// inverse DFT written as a cosine sum (c_0 = 1, c_m = 2 for 0 < m < n/2,
-// c_{n/2} = 1 for even n).
+// Inverse PSD q_m = 1 / (sigma^2 (1 + (f_knee / f_m)^alpha)) at f_m = m f_samp / n
+// [Sect. 4.1.4, eq. fknee], q_0 = 0 for 1/f noise (1/sigma^2 for white noise), or its
+// derivative with respect to sigma (what = 1), f_knee (2) or alpha (3); the f_knee and
+// alpha derivatives are taken as 0 for white noise.
+__device__ __forceinline__ double inv_psd_at(int64_t m, int64_t n, double f_samp, double sigma,
+                                             double fk, double al, int what) {
+    if (fk > 0.0) {
+        if (m == 0) return 0.0;
+        const double f = (double)m * f_samp / (double)n;
+        const double ratio = pow(fk / f, al);
+        const double q = 1.0 / (sigma * sigma * (1.0 + ratio));
+        if (what == 0) return q;
+        if (what == 1) return -2.0 * q / sigma;
+        if (what == 2) return -q * (al * ratio / fk) / (1.0 + ratio);
+        return -q * ratio * log(fk / f) / (1.0 + ratio);
+    }
+    const double q = 1.0 / (sigma * sigma);
+    return what == 0 ? q : (what == 1 ? -2.0 * q / sigma : 0.0);
+}
+
+// q_m (or a derivative) for every kernel: a[g][m] = c_m q_m, the coefficients of the real
+// inverse DFT written as a cosine sum (c_0 = 1, c_m = 2 for 0 < m < n/2, c_{n/2} = 1 for
+// even n).
 __global__ void k_inv_psd(const int32_t* __restrict__ klen, const double* __restrict__ kpar,
                           const int64_t* __restrict__ aoff, const int64_t* __restrict__ acnt,
-                          double f_samp, double* __restrict__ a, int32_t nk) {
+                          double f_samp, double* __restrict__ a, int32_t nk, int what) {
     const int g = blockIdx.y;
     if (g >= nk) return;
     const int64_t n = klen[g];
@@ -46,17 +66,7 @@ __global__ void k_inv_psd(const int32_t* __restrict__ klen, const double* __rest
     const double sigma = kpar[3 * g], fk = kpar[3 * g + 1], al = kpar[3 * g + 2];
     for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < cnt;
          m += (int64_t)gridDim.x * blockDim.x) {
-        double q;
-        if (fk > 0.0) {
-            if (m == 0) {
-                q = 0.0;
-            } else {
-                const double f = (double)m * f_samp / (double)n;
-                q = 1.0 / (sigma * sigma * (1.0 + pow(fk / f, al)));
-            }
-        } else {
-            q = 1.0 / (sigma * sigma);
-        }
+        const double q = inv_psd_at(m, n, f_samp, sigma, fk, al, what);
         double c = 2.0;
         if (m == 0 || (2 * m == n)) c = 1.0;
         a[aoff[g] + m] = c * q;
@@ -620,7 +630,7 @@ __global__ __launch_bounds__(NT) void k_taps_fft(const int32_t* __restrict__ kid
                                                  const double* __restrict__ kpar,
                                                  const int64_t* __restrict__ tcnt, double f_samp,
                                                  const double* __restrict__ tw, int kstride,
-                                                 int rmax, double* __restrict__ part) {
+                                                 int rmax, double* __restrict__ part, int what) {
     constexpr int M = 1 << LOGM, NR = 2 * M;
     __shared__ __align__(16) unsigned char smem[2 * M * sizeof(double)];
     const CBuf<double> buf = make_cbuf<double>(smem, M);
@@ -634,14 +644,7 @@ __global__ __launch_bounds__(NT) void k_taps_fft(const int32_t* __restrict__ kid
     for (int i = threadIdx.x; i < NR; i += NT) {
         int64_t m = (int64_t)R * i + b;
         if (m > n - m) m = n - m;
-        double q;
-        if (fk > 0.0) {
-            q = m == 0 ? 0.0
-                       : 1.0 / (sigma * sigma * (1.0 + pow(fk / ((double)m * f_samp / (double)n), al)));
-        } else {
-            q = 1.0 / (sigma * sigma);
-        }
-        buf.put_part(i >> 1, i & 1, q);
+        buf.put_part(i >> 1, i & 1, inv_psd_at(m, n, f_samp, sigma, fk, al, what));
     }
     __syncthreads();
     fwd_passes<double, LOGM, NT, LOGM>(buf, tw);
@@ -772,32 +775,18 @@ int64_t count_tiles(const std::vector<int64_t>& off, int64_t lmax) {
 
 // ------------------------------------------------------------------ host: kernels
 
-int build_kernels(mm_plan_t pl) {
+// Windowed taps t_0..t_K of every distinct kernel (what = 0) or of the derivative of the
+// inverse PSD with respect to sigma, f_knee or alpha (what = 1, 2, 3), on the host, flat
+// with offsets toff and counts tcnt [App. D: the Toeplitz row is the inverse DFT of the
+// inverse PSD on the interval's grid].
+int kernel_taps(mm_plan_t pl, int what, std::vector<double>& taps, std::vector<int64_t>& toff,
+                std::vector<int64_t>& tcnt) {
     hipStream_t st = pl->stream;
-    // distinct kernels: identical (sigma, f_knee, alpha, length) share taps and spectra
-    std::map<std::tuple<double, double, double, int64_t>, int32_t> seen;
-    pl->h_int_kern.resize(pl->n_int);
-    pl->h_kern_len.clear();
-    pl->h_kern_psd.clear();
-    for (int32_t j = 0; j < pl->n_int; ++j) {
-        const int64_t n = pl->h_off[j + 1] - pl->h_off[j];
-        const mm_psd& p = pl->h_psd[j];
-        const auto key = std::make_tuple(p.sigma, p.f_knee, p.alpha, n);
-        auto it = seen.find(key);
-        if (it == seen.end()) {
-            const int32_t id = (int32_t)pl->h_kern_len.size();
-            seen.emplace(key, id);
-            pl->h_kern_len.push_back((int32_t)n);
-            pl->h_kern_psd.push_back(p);
-            pl->h_int_kern[j] = id;
-        } else {
-            pl->h_int_kern[j] = it->second;
-        }
-    }
-    const int32_t nk = (int32_t)pl->h_kern_len.size();
-    pl->n_kern = nk;
+    const int32_t nk = pl->n_kern;
     const int lam = pl->opts.lambda;
-    std::vector<int64_t> aoff(nk), acnt(nk), nper(nk), jcnt(nk), toff(nk), tcnt(nk);
+    std::vector<int64_t> aoff(nk), acnt(nk), nper(nk), jcnt(nk);
+    toff.assign(nk, 0);
+    tcnt.assign(nk, 0);
     std::vector<double> kpar(3 * nk);
     int64_t atot = 0, ttot = 0;
     int64_t amax = 0;
@@ -845,7 +834,7 @@ int build_kernels(mm_plan_t pl) {
     {
         const int gx = (int)std::max<int64_t>(1, std::min<int64_t>((amax + 255) / 256, 1024));
         hipLaunchKernelGGL(k_inv_psd, dim3(gx, nk), dim3(256), 0, st, d_klen.p, d_kpar.p,
-                           d_aoff.p, d_acnt.p, pl->opts.f_samp, d_a.p, nk);
+                           d_aoff.p, d_acnt.p, pl->opts.f_samp, d_a.p, nk, what);
         MM_HIP(hipGetLastError());
         const int64_t jmax = *std::max_element(jcnt.begin(), jcnt.end());
         hipLaunchKernelGGL(k_cos_transform, dim3((jmax + kCtThreads - 1) / kCtThreads, nk),
@@ -880,16 +869,46 @@ int build_kernels(mm_plan_t pl) {
         MM_HIP(hipMemcpyAsync(d_kid.p, fft_ids.data(), nf * 4, hipMemcpyHostToDevice, st));
         hipLaunchKernelGGL((k_taps_fft<kPlanLogM, kPlanNT>), dim3(rmax, nf), dim3(kPlanNT), 0, st,
                            d_kid.p, d_klen.p, d_kpar.p, d_tcnt.p, pl->opts.f_samp, d_tw.p, kmax,
-                           rmax, d_part.p);
+                           rmax, d_part.p, what);
         MM_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_taps_sum, dim3((kmax + 255) / 256, nf), dim3(256), 0, st, d_kid.p,
                            d_klen.p, d_toff.p, d_tcnt.p, d_part.p, kmax, rmax, lam,
                            pl->opts.window, d_t.p, (int)kNs);
         MM_HIP(hipGetLastError());
     }
-    std::vector<double> taps(ttot);
+    taps.resize(ttot);
     MM_HIP(hipMemcpyAsync(taps.data(), d_t.p, ttot * 8, hipMemcpyDeviceToHost, st));
     MM_HIP(hipStreamSynchronize(st));
+    return MM_OK;
+}
+
+int build_kernels(mm_plan_t pl) {
+    hipStream_t st = pl->stream;
+    // distinct kernels: identical (sigma, f_knee, alpha, length) share taps and spectra
+    std::map<std::tuple<double, double, double, int64_t>, int32_t> seen;
+    pl->h_int_kern.resize(pl->n_int);
+    pl->h_kern_len.clear();
+    pl->h_kern_psd.clear();
+    for (int32_t j = 0; j < pl->n_int; ++j) {
+        const int64_t n = pl->h_off[j + 1] - pl->h_off[j];
+        const mm_psd& p = pl->h_psd[j];
+        const auto key = std::make_tuple(p.sigma, p.f_knee, p.alpha, n);
+        auto it = seen.find(key);
+        if (it == seen.end()) {
+            const int32_t id = (int32_t)pl->h_kern_len.size();
+            seen.emplace(key, id);
+            pl->h_kern_len.push_back((int32_t)n);
+            pl->h_kern_psd.push_back(p);
+            pl->h_int_kern[j] = id;
+        } else {
+            pl->h_int_kern[j] = it->second;
+        }
+    }
+    const int32_t nk = (int32_t)pl->h_kern_len.size();
+    pl->n_kern = nk;
+    std::vector<int64_t> toff, tcnt;
+    std::vector<double> taps;
+    MM_TRY(kernel_taps(pl, 0, taps, toff, tcnt));
     pl->h_taps.assign(nk, {});
     std::vector<double> t0(nk);
     for (int g = 0; g < nk; ++g) {

@@ -335,3 +335,13 @@ def test_dense_map_gradients_match_finite_differences():
             vals.append(g @ O.map_dense(pp, d))
         fd = (vals[0] - vals[1]) / (2 * h)
         assert fd == pytest.approx(gt[j, i], rel=1e-5, abs=1e-9 * np.abs(gt).max()), (j, i)
+
+
+def test_banded_map_gradients_equal_dense_ones():
+    sc, pr = _tiny_adjoint_problem(seed=8)
+    d = sc.noise + pr.signal(sc.sky)
+    g = np.random.default_rng(12).standard_normal(pr.n_obs * pr.n_s)
+    ref = O.map_gradients_dense(pr, d, g)
+    got = O.map_gradients(pr, d, g)
+    for a, b in zip(got, ref):
+        assert np.max(np.abs(a - b)) <= 1e-9 * np.max(np.abs(b))
