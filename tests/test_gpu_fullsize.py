@@ -1,0 +1,137 @@
+"""Parity at the workloads' full sizes, on outputs the oracle computes one by one.
+
+- 2^24-sample IQU raster in the benchmark's launch configuration (mixed-precision plan
+  with the coarse space and autotuned FFT tiles): integer layout bit-exact over the whole
+  scan; A x, b and N^-1 y at sampled pixels / samples; the noiseless solve returns the
+  input map.
+- One detector's share (2^24 samples) of the 2^28-sample ring scan: lambda = 4096,
+  2^18-sample intervals, skewed hit counts (1 to 60); A x at sampled pixels including the
+  most and least observed ones.
+- The 256-problem batched Monte Carlo plan: A x at sampled pixels of several problems.
+- The 2^22-sample case of the differentiated solve: A x at sampled pixels.
+"""
+
+import functools
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle as O  # noqa: E402
+import synth  # noqa: E402
+from paper_1408_3048_amd import Plan  # noqa: E402
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _sampled_A(pl, pr, x, pixels, ns):
+    ref = pr.apply_A_at(x, pixels)
+    y64 = pl.apply_A(dev(x)).cpu().numpy().reshape(-1, ns)[pixels]
+    y32 = pl.apply_A(dev(x), precision="mixed").cpu().numpy().reshape(-1, ns)[pixels]
+    return _rel(y64, ref), _rel(y32, ref)
+
+
+@functools.lru_cache(maxsize=None)
+def cfg2():
+    sc = synth.cfg2_raster_iqu()
+    return sc, O.Problem.from_scan(sc)
+
+
+def test_cfg2_fullsize_layout_operators_and_solution():
+    sc, pr = cfg2()
+    pl = Plan.from_scan(sc, precision="mixed", coarse=True, autotune=True)
+    # integer layout over all 2^24 samples
+    assert np.array_equal(pl.obs_pixels().cpu().numpy(), pr.obs)
+    assert np.array_equal(pl.hits().cpu().numpy(), pr.s)
+    assert np.array_equal(pl.sorted_samples().cpu().numpy(), np.argsort(pr.cid, kind="stable"))
+    rng = np.random.default_rng(40)
+    x = rng.standard_normal(pr.n_obs * pr.n_s)
+    pixels = np.concatenate([rng.choice(pr.n_obs, 30, replace=False), [0, pr.n_obs - 1]])
+    e64, e32 = _sampled_A(pl, pr, x, pixels, 3)
+    assert e64 <= 1e-11 and e32 <= 5e-5, (e64, e32)
+    # N^-1 (FP64, FP32) at sampled samples, b = P^T N^-1 d at sampled pixels
+    d = sc.noise
+    ts = np.sort(rng.choice(pr.n_t, 200, replace=False))
+    zr = O.toeplitz_apply_at(d, pr.offsets, pr.taps, ts)
+    assert _rel(pl.apply_Ninv(dev(d)).cpu().numpy()[ts], zr) <= 1e-11
+    d32 = d.astype(np.float32)
+    z32 = pl.apply_Ninv(dev(d32), precision="mixed").cpu().numpy()[ts]
+    assert _rel(z32, O.toeplitz_apply_at(d32.astype(np.float64), pr.offsets, pr.taps, ts)) <= 5e-5
+    b = pl.rhs(dev(d)).cpu().numpy().reshape(-1, 3)
+    bref = np.stack([pr.W[np.nonzero(pr.cid == p)[0]].T @
+                     O.toeplitz_apply_at(d, pr.offsets, pr.taps, np.nonzero(pr.cid == p)[0])
+                     for p in pixels])
+    assert _rel(b[pixels], bref) <= 1e-11
+    # noiseless data: the FP64 two-level solve and the mixed solve return the input map
+    m = pr.sky_to_compact(sc.sky)
+    dn = pl.apply_P(dev(m))
+    xs, info = pl.pcg_solve(pl.rhs(dn), precond="2lvl", precision="fp64", tol=1e-12,
+                            max_iter=3000)
+    assert _rel(xs.cpu().numpy(), m) <= 1e-7, info["rel_residual"]
+    xm, info = pl.pcg_solve(pl.rhs(dn), precond="2lvl", precision="mixed", tol=1e-10,
+                            max_iter=3000)
+    assert _rel(xm.cpu().numpy(), m) <= 1e-5
+    pl.close()
+
+
+def test_ring_share_fullsize_sampled_operator():
+    sc = synth.cfg3_ring_iqu(det_subset=[0])
+    pr = O.Problem.from_scan(sc)
+    # one detector leaves pixels with fewer than 3 hits: their IQU blocks are singular,
+    # which only the block-Jacobi preconditioner (not tested here) cares about
+    pl = Plan.from_scan(sc, precision="mixed", rcond_min=0.0, autotune=True)
+    assert np.array_equal(pl.hits().cpu().numpy(), pr.s)
+    rng = np.random.default_rng(41)
+    x = rng.standard_normal(pr.n_obs * pr.n_s)
+    pixels = np.concatenate([rng.choice(pr.n_obs, 24, replace=False),
+                             [int(np.argmax(pr.s)), int(np.argmin(pr.s))]])
+    e64, e32 = _sampled_A(pl, pr, x, pixels, 3)
+    assert e64 <= 1e-11 and e32 <= 5e-5, (e64, e32)
+    pl.close()
+
+
+def test_batched_fullsize_sampled_operator():
+    sc = synth.cfg4_batched_iqu()
+    pl = Plan.from_scan(sc, precision="mixed", coarse=True)
+    assert pl.n_problems == 256
+    off3 = pl.problem_pixels() * 3
+    rng = np.random.default_rng(42)
+    x = rng.standard_normal(pl.n_vec)
+    y64 = pl.apply_A(dev(x)).cpu().numpy()
+    y32 = pl.apply_A(dev(x), precision="mixed").cpu().numpy()
+    lengths = np.diff(sc.offsets[sc.problem_offsets])
+    for b in (0, int(np.argmax(lengths)), int(np.argmin(lengths)), 255):
+        s1 = synth.cfg4_batched_iqu(problems=[b])
+        pr = O.Problem.from_scan(s1)
+        assert pr.n_obs * 3 == off3[b + 1] - off3[b]
+        xb = x[off3[b]:off3[b + 1]]
+        pixels = rng.choice(pr.n_obs, 12, replace=False)
+        ref = pr.apply_A_at(xb, pixels)
+        assert _rel(y64[off3[b]:off3[b + 1]].reshape(-1, 3)[pixels], ref) <= 1e-11, b
+        assert _rel(y32[off3[b]:off3[b + 1]].reshape(-1, 3)[pixels], ref) <= 5e-5, b
+    pl.close()
+
+
+def test_cfg5_fullsize_sampled_operator():
+    sc = synth.cfg5_raster_iqu()
+    pr = O.Problem.from_scan(sc)
+    pl = Plan.from_scan(sc, precision="mixed", coarse=True, autotune=True)
+    rng = np.random.default_rng(43)
+    x = rng.standard_normal(pr.n_obs * pr.n_s)
+    pixels = rng.choice(pr.n_obs, 24, replace=False)
+    e64, e32 = _sampled_A(pl, pr, x, pixels, 3)
+    assert e64 <= 1e-11 and e32 <= 5e-5, (e64, e32)
+    pl.close()
