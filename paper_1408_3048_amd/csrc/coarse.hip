@@ -96,13 +96,87 @@ __global__ void k_zs_fill(const int32_t* __restrict__ perm, const int64_t* __res
 }
 
 
+// entry -> pixel of the Z_S rows (CSR) and the identity permutation
+__global__ void k_expand_rows(const int64_t* __restrict__ ptr, int64_t n_obs,
+                              int32_t* __restrict__ rowid, int32_t* __restrict__ eidx) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n_obs;
+         p += (int64_t)gridDim.x * blockDim.x)
+        for (int64_t e = ptr[p]; e < ptr[p + 1]; ++e) {
+            rowid[e] = (int32_t)p;
+            eidx[e] = (int32_t)e;
+        }
+}
+
+// Z_S by column (CSC) from the entries stably sorted by column: rows ascend within a
+// column; [cbeg[j], cend[j]) are column j's entries (every interval has samples, so no
+// column is empty)
+__global__ void k_csc_fill(const int32_t* __restrict__ skey, const int32_t* __restrict__ sidx,
+                           int64_t total, const int32_t* __restrict__ rowid,
+                           const double* __restrict__ val, int32_t* __restrict__ crow,
+                           double* __restrict__ cval, int64_t* __restrict__ cbeg,
+                           int64_t* __restrict__ cend) {
+    for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < total;
+         d += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t e = sidx[d], k = skey[d];
+        crow[d] = rowid[e];
+        cval[d] = val[e];
+        if (d == 0 || skey[d - 1] != k) cbeg[k] = d;
+        if (d == total - 1 || skey[d + 1] != k) cend[k] = d + 1;
+    }
+}
+
+// the SplitMix64 finaliser (Steele, Lea & Flood 2014) as a 64-bit mixing function
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// order-independent hash of every column: wrapping sum over its entries of
+// mix(mix(row) ^ bits(value)); equal columns have equal hashes
+__global__ __launch_bounds__(256) void k_col_hash(const int64_t* __restrict__ cbeg,
+                                                  const int64_t* __restrict__ cend,
+                                                  const int32_t* __restrict__ crow,
+                                                  const double* __restrict__ cval,
+                                                  unsigned long long* __restrict__ hash) {
+    __shared__ unsigned long long red[256];
+    const int j = blockIdx.x;
+    unsigned long long h = 0;
+    for (int64_t e = cbeg[j] + threadIdx.x; e < cend[j]; e += 256)
+        h += mix64(mix64((uint64_t)crow[e]) ^ (uint64_t)__double_as_longlong(cval[e]));
+    red[threadIdx.x] = h;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) hash[j] = red[0];
+}
+
+// neq[i] = 1 unless columns ca[i] and cb[i] (same entry count) hold identical entries
+__global__ __launch_bounds__(256) void k_cols_equal(const int32_t* __restrict__ ca,
+                                                    const int32_t* __restrict__ cb,
+                                                    const int64_t* __restrict__ cbeg,
+                                                    const int64_t* __restrict__ cend,
+                                                    const int32_t* __restrict__ crow,
+                                                    const double* __restrict__ cval,
+                                                    int* __restrict__ neq) {
+    const int i = blockIdx.x;
+    const int64_t a0 = cbeg[ca[i]], b0 = cbeg[cb[i]], n = cend[ca[i]] - a0;
+    for (int64_t e = threadIdx.x; e < n; e += 256)
+        if (crow[a0 + e] != crow[b0 + e] ||
+            __double_as_longlong(cval[a0 + e]) != __double_as_longlong(cval[b0 + e]))
+            neq[i] = 1;
+}
+
 // scatter the entries (pixel, value) of the columns ucol[0..gridDim.y) into a zeroed map
 // vector (I rows); the columns of one layer belong to different problems
-__global__ void k_cols_to_vec(const int32_t* __restrict__ ucol, const int64_t* __restrict__ uptr,
-                              const int32_t* __restrict__ rows, const double* __restrict__ vals,
-                              int ns, double* __restrict__ out) {
+__global__ void k_cols_to_vec(const int32_t* __restrict__ ucol, const int64_t* __restrict__ ub,
+                              const int64_t* __restrict__ ue, const int32_t* __restrict__ rows,
+                              const double* __restrict__ vals, int ns, double* __restrict__ out) {
     const int32_t u = ucol[blockIdx.y];
-    for (int64_t i = uptr[u] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < uptr[u + 1];
+    for (int64_t i = ub[u] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ue[u];
          i += (int64_t)gridDim.x * blockDim.x)
         out[(int64_t)rows[i] * ns] = vals[i];
 }
@@ -157,12 +231,12 @@ __global__ void k_csr_filter(const int64_t* __restrict__ ptr, const int32_t* __r
 
 // dense Z_I of one problem, row-major [n_obs_pad][rp] from per-column entry lists (rows
 // relative to the problem's first pixel row0)
-__global__ void k_dense_z(const int64_t* __restrict__ cptr, const int32_t* __restrict__ rows,
-                          const double* __restrict__ vals, int32_t r, int32_t rp, int64_t row0,
-                          double* __restrict__ zd) {
+__global__ void k_dense_z(const int64_t* __restrict__ cb, const int64_t* __restrict__ ce,
+                          const int32_t* __restrict__ rows, const double* __restrict__ vals,
+                          int32_t r, int32_t rp, int64_t row0, double* __restrict__ zd) {
     const int32_t c = blockIdx.y;
     if (c >= r) return;
-    for (int64_t i = cptr[c] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cptr[c + 1];
+    for (int64_t i = cb[c] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ce[c];
          i += (int64_t)gridDim.x * blockDim.x)
         zd[((int64_t)rows[i] - row0) * rp + c] = vals[i];
 }
@@ -468,61 +542,80 @@ int build_coarse(mm_plan_t pl) {
     hipLaunchKernelGGL(k_zs_fill, dim3(grid_for(n_obs, 128)), dim3(128), 0, st, pl->perm.p,
                        pl->seg.p, pl->hits.p, n_obs, pl->int_lo.p, pl->n_int, ptr.p, col.p, val.p);
     MM_HIP(hipGetLastError());
-    std::vector<int64_t> hptr(n_obs + 1);
-    std::vector<int32_t> hcol(total);
-    std::vector<double> hval(total);
-    MM_HIP(hipMemcpyAsync(hptr.data(), ptr.p, (n_obs + 1) * 8, hipMemcpyDeviceToHost, st));
-    MM_HIP(hipMemcpyAsync(hcol.data(), col.p, total * 4, hipMemcpyDeviceToHost, st));
-    MM_HIP(hipMemcpyAsync(hval.data(), val.p, total * 8, hipMemcpyDeviceToHost, st));
-    MM_HIP(hipStreamSynchronize(st));
-    // per-column entry lists (ascending pixel), duplicate columns merged
+    tick("zs");
+    // Z_S by column on the device: entries stably sorted by column (rows stay ascending)
     const int32_t K = pl->n_int;
-    std::vector<int64_t> ccnt(K + 1, 0);
-    for (int64_t e = 0; e < total; ++e) ccnt[hcol[e] + 1]++;
-    for (int32_t j = 0; j < K; ++j) ccnt[j + 1] += ccnt[j];
-    std::vector<int32_t> crow(total);
-    std::vector<double> cval(total);
+    DBuf<int32_t> rowid, eidx, skey, sidx, crow;
+    DBuf<double> cval;
+    DBuf<int64_t> cbeg, cend;
+    DBuf<unsigned long long> chash;
+    MM_TRY(rowid.alloc(total));
+    MM_TRY(eidx.alloc(total));
+    MM_TRY(skey.alloc(total));
+    MM_TRY(sidx.alloc(total));
+    MM_TRY(crow.alloc(total));
+    MM_TRY(cval.alloc(total));
+    MM_TRY(cbeg.alloc(K));
+    MM_TRY(cend.alloc(K));
+    MM_TRY(chash.alloc(K));
+    hipLaunchKernelGGL(k_expand_rows, dim3(grid_for(n_obs)), dim3(256), 0, st, ptr.p, n_obs,
+                       rowid.p, eidx.p);
+    MM_HIP(hipGetLastError());
+    MM_TRY(radix_sort_pairs(col.p, eidx.p, total, K - 1, skey.p, sidx.p, st));
+    hipLaunchKernelGGL(k_csc_fill, dim3(grid_for(total)), dim3(256), 0, st, skey.p, sidx.p, total,
+                       rowid.p, val.p, crow.p, cval.p, cbeg.p, cend.p);
+    hipLaunchKernelGGL(k_col_hash, dim3(K), dim3(256), 0, st, cbeg.p, cend.p, crow.p, cval.p,
+                       chash.p);
+    MM_HIP(hipGetLastError());
+    std::vector<unsigned long long> hh(K);
+    std::vector<int64_t> hb(K), he(K);
+    MM_HIP(hipMemcpyAsync(hh.data(), chash.p, K * 8, hipMemcpyDeviceToHost, st));
+    MM_HIP(hipMemcpyAsync(hb.data(), cbeg.p, K * 8, hipMemcpyDeviceToHost, st));
+    MM_HIP(hipMemcpyAsync(he.data(), cend.p, K * 8, hipMemcpyDeviceToHost, st));
+    MM_HIP(hipStreamSynchronize(st));
+    rowid.release();
+    eidx.release();
+    skey.release();
+    sidx.release();
+    // duplicate columns: proposed by (hash, entry count), confirmed by an exact comparison;
+    // a column keeps the first (lowest) interval with the same content as representative
+    std::vector<int32_t> cand_a, cand_b;
     {
-        std::vector<int64_t> fillp(ccnt.begin(), ccnt.end() - 1);
-        for (int64_t p = 0; p < n_obs; ++p)
-            for (int64_t e = hptr[p]; e < hptr[p + 1]; ++e) {
-                const int64_t d = fillp[hcol[e]]++;
-                crow[d] = (int32_t)p;
-                cval[d] = hval[e];
-            }
-    }
-    std::vector<int32_t> uniq;  // representative interval of every distinct column
-    {
-        std::unordered_map<uint64_t, std::vector<int32_t>> buckets;
+        std::unordered_map<uint64_t, int32_t> first;
         for (int32_t j = 0; j < K; ++j) {
-            if (ccnt[j + 1] == ccnt[j]) continue;  // empty column (cannot happen: every interval has samples)
-            uint64_t h = 1469598103934665603ull;
-            for (int64_t e = ccnt[j]; e < ccnt[j + 1]; ++e) {
-                uint64_t bits;
-                std::memcpy(&bits, &cval[e], 8);
-                h = (h ^ (uint64_t)crow[e]) * 1099511628211ull;
-                h = (h ^ bits) * 1099511628211ull;
-            }
-            auto& bk = buckets[h];
-            bool dup = false;
-            for (int32_t u : bk) {
-                if (ccnt[u + 1] - ccnt[u] != ccnt[j + 1] - ccnt[j]) continue;
-                bool same = true;
-                for (int64_t e = 0; e < ccnt[j + 1] - ccnt[j] && same; ++e)
-                    same = crow[ccnt[u] + e] == crow[ccnt[j] + e] &&
-                           cval[ccnt[u] + e] == cval[ccnt[j] + e];
-                if (same) {
-                    dup = true;
-                    break;
-                }
-            }
-            if (!dup) {
-                bk.push_back(j);
-                uniq.push_back(j);
+            const uint64_t key = hh[j] ^ ((uint64_t)(he[j] - hb[j]) * 0x9E3779B97F4A7C15ull);
+            auto it = first.find(key);
+            if (it == first.end()) {
+                first.emplace(key, j);
+            } else if (he[it->second] - hb[it->second] == he[j] - hb[j]) {
+                cand_a.push_back(j);
+                cand_b.push_back(it->second);
             }
         }
-        std::sort(uniq.begin(), uniq.end());
     }
+    std::vector<char> dup(K, 0);
+    if (!cand_a.empty()) {
+        const int nc = (int)cand_a.size();
+        DBuf<int32_t> da, db;
+        DBuf<int> neq;
+        MM_TRY(da.alloc(nc));
+        MM_TRY(db.alloc(nc));
+        MM_TRY(neq.alloc(nc));
+        MM_HIP(hipMemcpyAsync(da.p, cand_a.data(), nc * 4, hipMemcpyHostToDevice, st));
+        MM_HIP(hipMemcpyAsync(db.p, cand_b.data(), nc * 4, hipMemcpyHostToDevice, st));
+        MM_HIP(hipMemsetAsync(neq.p, 0, nc * sizeof(int), st));
+        hipLaunchKernelGGL(k_cols_equal, dim3(nc), dim3(256), 0, st, da.p, db.p, cbeg.p, cend.p,
+                           crow.p, cval.p, neq.p);
+        MM_HIP(hipGetLastError());
+        std::vector<int> hn(nc);
+        MM_HIP(hipMemcpyAsync(hn.data(), neq.p, nc * sizeof(int), hipMemcpyDeviceToHost, st));
+        MM_HIP(hipStreamSynchronize(st));
+        for (int i = 0; i < nc; ++i)
+            if (!hn[i]) dup[cand_a[i]] = 1;
+    }
+    std::vector<int32_t> uniq;  // representative interval of every distinct column
+    for (int32_t j = 0; j < K; ++j)
+        if (!dup[j]) uniq.push_back(j);
     const int32_t rd = (int32_t)uniq.size();
     co.r_dedup = rd;
     // distinct columns per problem (columns of distinct problems have disjoint rows, so
@@ -547,26 +640,18 @@ int build_coarse(mm_plan_t pl) {
         rd_max = std::max(rd_max, r_b);
         azd_off[b + 1] = azd_off[b] + (int64_t)r_b * (oo[b + 1] - oo[b]) * ns;
     }
-    tick("zs+dedup");
-    // entry lists of the distinct columns
-    DBuf<int32_t> drow;
-    DBuf<double> dval;
-    DBuf<int64_t> dptr;
-    std::vector<int64_t> uptr(rd + 1, 0);
-    std::vector<int32_t> urow;
-    std::vector<double> uval;
+    tick("dedup");
+    // entry ranges of the distinct columns in the CSC arrays
+    std::vector<int64_t> ub(rd), ue(rd);
     for (int32_t u = 0; u < rd; ++u) {
-        const int32_t j = uniq[u];
-        urow.insert(urow.end(), crow.begin() + ccnt[j], crow.begin() + ccnt[j + 1]);
-        uval.insert(uval.end(), cval.begin() + ccnt[j], cval.begin() + ccnt[j + 1]);
-        uptr[u + 1] = (int64_t)urow.size();
+        ub[u] = hb[uniq[u]];
+        ue[u] = he[uniq[u]];
     }
-    MM_TRY(drow.alloc(urow.size()));
-    MM_TRY(dval.alloc(uval.size()));
-    MM_TRY(dptr.alloc(rd + 1));
-    MM_HIP(hipMemcpyAsync(drow.p, urow.data(), urow.size() * 4, hipMemcpyHostToDevice, st));
-    MM_HIP(hipMemcpyAsync(dval.p, uval.data(), uval.size() * 8, hipMemcpyHostToDevice, st));
-    MM_HIP(hipMemcpyAsync(dptr.p, uptr.data(), (rd + 1) * 8, hipMemcpyHostToDevice, st));
+    DBuf<int64_t> dub, due;
+    MM_TRY(dub.alloc(rd));
+    MM_TRY(due.alloc(rd));
+    MM_HIP(hipMemcpyAsync(dub.p, ub.data(), rd * 8, hipMemcpyHostToDevice, st));
+    MM_HIP(hipMemcpyAsync(due.p, ue.data(), rd * 8, hipMemcpyHostToDevice, st));
     // AZ of the distinct columns, block per problem: A is block diagonal over the problems,
     // so one application to the sum of every problem's k-th column gives all k-th columns
     const bool mixed = pl->opts.precision == MM_MIXED;
@@ -599,8 +684,8 @@ int build_coarse(mm_plan_t pl) {
         for (int32_t k = 0; k < rd_max; ++k) {
             const int nl = lcnt[k];
             MM_HIP(hipMemsetAsync(zc.p, 0, nv * 8, st));
-            hipLaunchKernelGGL(k_cols_to_vec, dim3(16, nl), dim3(256), 0, st, lcols.p + lo, dptr.p,
-                               drow.p, dval.p, (int)ns, zc.p);
+            hipLaunchKernelGGL(k_cols_to_vec, dim3(16, nl), dim3(256), 0, st, lcols.p + lo, dub.p,
+                               due.p, crow.p, cval.p, (int)ns, zc.p);
             MM_HIP(hipGetLastError());
             if (mixed) {
                 MM_TRY(apply_A32(pl, zc.p, tmp.p, nullptr));
@@ -642,8 +727,8 @@ int build_coarse(mm_plan_t pl) {
         const int64_t npad = (nob + 3) / 4 * 4;
         MM_HIP(hipMemsetAsync(zd.p, 0, (size_t)npad * rp * 8, st));
         MM_HIP(hipMemsetAsync(azr.p, 0, (size_t)npad * rp * 8, st));
-        hipLaunchKernelGGL(k_dense_z, dim3(64, rb), dim3(256), 0, st, dptr.p + ud_off[b], drow.p,
-                           dval.p, rb, rp, oo[b], zd.p);
+        hipLaunchKernelGGL(k_dense_z, dim3(64, rb), dim3(256), 0, st, dub.p + ud_off[b],
+                           due.p + ud_off[b], crow.p, cval.p, rb, rp, oo[b], zd.p);
         if (mixed)
             hipLaunchKernelGGL(k_az_rows<float>, dim3(grid_for(nob, 256, 4096), rb), dim3(256), 0,
                                st, azf.p + azd_off[b], nob * ns, nob, (int)ns, rb, rp, azr.p);
@@ -691,6 +776,7 @@ int build_coarse(mm_plan_t pl) {
     MM_TRY(co.Einv.alloc(Einv_all.size()));
     MM_HIP(hipMemcpyAsync(co.Einv.p, Einv_all.data(), Einv_all.size() * 8, hipMemcpyHostToDevice,
                           st));
+    tick("Einv");
     // kept AZ columns into the final per-problem blocks
     {
         std::vector<int64_t> so(keff), d_o(keff), cn(keff);
@@ -726,6 +812,7 @@ int build_coarse(mm_plan_t pl) {
     }
     azf.release();
     azd.release();
+    tick("AZ kept");
     // kept columns by column: entry ranges into the distinct-column lists; Z^T r slices
     std::vector<int64_t> kb(keff), ke(keff);
     std::vector<int32_t> vs(keff + 1, 0), cprob(keff);
@@ -733,15 +820,15 @@ int build_coarse(mm_plan_t pl) {
         for (size_t i = 0; i < sels[b].size(); ++i) {
             const int32_t a = co.h_col_off[b] + (int32_t)i;
             const int32_t u = ud_off[b] + sels[b][i];
-            kb[a] = uptr[u];
-            ke[a] = uptr[u + 1];
+            kb[a] = ub[u];
+            ke[a] = ue[u];
             cprob[a] = b;
         }
     for (int32_t a = 0; a < keff; ++a)
         vs[a + 1] = vs[a] + (int32_t)std::max<int64_t>(1, (ke[a] - kb[a] + 511) / 512);
     co.n_slices = vs[keff];
-    co.csc_row.swap(drow);
-    co.csc_val.swap(dval);
+    co.csc_row.swap(crow);
+    co.csc_val.swap(cval);
     MM_TRY(co.csc_beg.alloc(keff));
     MM_TRY(co.csc_end.alloc(keff));
     MM_TRY(co.vslice.alloc(keff + 1));
@@ -757,6 +844,7 @@ int build_coarse(mm_plan_t pl) {
     MM_HIP(hipMemcpyAsync(co.az_off.p, co.h_az_off.data(), (B + 1) * 8, hipMemcpyHostToDevice, st));
     MM_HIP(hipMemcpyAsync(co.einv_off.p, co.h_einv_off.data(), (B + 1) * 8, hipMemcpyHostToDevice,
                           st));
+    tick("csc");
     // kept columns by pixel (CSR), filtered on the device from the full Z_S rows
     std::vector<int32_t> colmap(K, -1);
     for (int32_t a = 0; a < keff; ++a) colmap[co.cols[a]] = a;
@@ -782,6 +870,7 @@ int build_coarse(mm_plan_t pl) {
     MM_TRY(co.w.alloc(keff));
     MM_TRY(co.vpart.alloc(co.n_slices));
     MM_HIP(hipStreamSynchronize(st));
+    tick("csr");
     pl->has_coarse = true;
     return MM_OK;
 }

@@ -273,6 +273,9 @@ constexpr int kVecThreads = 256;
 int build_pointing(mm_plan_t pl, const int32_t* pix, const void* weights, int wdtype);
 // out[0..n] = exclusive scan of in[0..n-1] (int64), out[n] = total; synchronises st
 int scan_exclusive_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t st);
+// stable LSD radix sort of (key, value) pairs, keys in [0, key_max]; synchronises st
+int radix_sort_pairs(const int32_t* keys, const int32_t* vals, int64_t n, int32_t key_max,
+                     int32_t* keys_out, int32_t* vals_out, hipStream_t st);
 
 // ---- toeplitz.hip
 int build_kernels(mm_plan_t pl);

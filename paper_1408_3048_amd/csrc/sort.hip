@@ -383,6 +383,42 @@ int scan_exclusive_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s
     return scan_exclusive<int64_t>(in, out, n, st);
 }
 
+int radix_sort_pairs(const int32_t* keys, const int32_t* vals, int64_t n, int32_t key_max,
+                     int32_t* keys_out, int32_t* vals_out, hipStream_t st) {
+    if (n == 0) return MM_OK;
+    int bits = 1;
+    while (bits < 31 && ((int64_t)1 << bits) <= key_max) ++bits;
+    const int passes = (bits + 7) / 8;
+    const int64_t ntiles = (n + kRadixTile - 1) / kRadixTile;
+    DBuf<int64_t> counts, offs;
+    DBuf<int32_t> ka, kb, va, vb;
+    MM_TRY(counts.alloc(256 * ntiles));
+    MM_TRY(offs.alloc(256 * ntiles + 1));
+    MM_TRY(ka.alloc(n));
+    MM_TRY(kb.alloc(n));
+    MM_TRY(va.alloc(n));
+    MM_TRY(vb.alloc(n));
+    MM_HIP(hipMemcpyAsync(ka.p, keys, n * 4, hipMemcpyDeviceToDevice, st));
+    MM_HIP(hipMemcpyAsync(va.p, vals, n * 4, hipMemcpyDeviceToDevice, st));
+    int32_t *kin = ka.p, *kout = kb.p, *vin = va.p, *vout = vb.p;
+    for (int ps = 0; ps < passes; ++ps) {
+        const int shift = 8 * ps;
+        hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(kRadixThreads), 0, st, kin, n, shift,
+                           counts.p, ntiles);
+        MM_HIP(hipGetLastError());
+        MM_TRY(scan_exclusive<int64_t>(counts.p, offs.p, 256 * ntiles, st));
+        hipLaunchKernelGGL(k_radix_scatter, dim3(ntiles), dim3(kRadixThreads), 0, st, kin, vin,
+                           kout, vout, n, shift, offs.p, ntiles);
+        MM_HIP(hipGetLastError());
+        std::swap(kin, kout);
+        std::swap(vin, vout);
+    }
+    MM_HIP(hipMemcpyAsync(keys_out, kin, n * 4, hipMemcpyDeviceToDevice, st));
+    MM_HIP(hipMemcpyAsync(vals_out, vin, n * 4, hipMemcpyDeviceToDevice, st));
+    MM_HIP(hipStreamSynchronize(st));  // scratch is released on return
+    return MM_OK;
+}
+
 int build_pointing(mm_plan_t pl, const int32_t* pix, const void* weights, int wdtype) {
     hipStream_t st = pl->stream;
     const int64_t n = pl->n_t;
