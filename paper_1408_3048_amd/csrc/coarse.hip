@@ -680,6 +680,9 @@ int build_coarse(mm_plan_t pl) {
                 }
         MM_HIP(hipMemcpyAsync(lcols.p, hc.data(), hc.size() * 4, hipMemcpyHostToDevice, st));
         MM_HIP(hipMemcpyAsync(lprob.p, hp.data(), hp.size() * 4, hipMemcpyHostToDevice, st));
+        int64_t nb_max = 1;  // largest problem vector
+        for (int b = 0; b < B; ++b) nb_max = std::max<int64_t>(nb_max, (oo[b + 1] - oo[b]) * ns);
+        const int sgx = (int)std::min<int64_t>(1024, (nb_max + 255) / 256);
         int64_t lo = 0;
         for (int32_t k = 0; k < rd_max; ++k) {
             const int nl = lcnt[k];
@@ -689,12 +692,12 @@ int build_coarse(mm_plan_t pl) {
             MM_HIP(hipGetLastError());
             if (mixed) {
                 MM_TRY(apply_A32(pl, zc.p, tmp.p, nullptr));
-                hipLaunchKernelGGL(k_store_az<float>, dim3(64, nl), dim3(256), 0, st, lprob.p + lo,
+                hipLaunchKernelGGL(k_store_az<float>, dim3(sgx, nl), dim3(256), 0, st, lprob.p + lo,
                                    (const double*)tmp.p, pl->ooff.p, (int)ns,
                                    (const int64_t*)d_azd_off.p, k, azf.p);
             } else {
                 MM_TRY(apply_A64(pl, zc.p, tmp.p, nullptr));
-                hipLaunchKernelGGL(k_store_az<double>, dim3(64, nl), dim3(256), 0, st, lprob.p + lo,
+                hipLaunchKernelGGL(k_store_az<double>, dim3(sgx, nl), dim3(256), 0, st, lprob.p + lo,
                                    (const double*)tmp.p, pl->ooff.p, (int)ns,
                                    (const int64_t*)d_azd_off.p, k, azd.p);
             }

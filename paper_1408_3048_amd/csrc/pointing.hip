@@ -124,8 +124,9 @@ __device__ __forceinline__ void seg_reduce(int64_t i0, int64_t i1, int64_t p0,
     }
 }
 
-// x[p, s] = sum_{t in p} W[t, s] z_t (P^T), E = 4 samples per lane
-template <typename T, int NS>
+// x[p, s] = sum_{t in p} W[t, s] z_t (P^T), E samples per lane (a multiple of 4): one
+// chunk of 64 E samples keeps E gathers of z per lane in flight
+template <typename T, int NS, int E>
 __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ perm,
                                                  const T* __restrict__ ws, const T* __restrict__ z,
                                                  const unsigned long long* __restrict__ heads,
@@ -135,7 +136,7 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ per
                                                  double* __restrict__ out,
                                                  const int* __restrict__ mask,
                                                  const int32_t* __restrict__ wave_prob) {
-    constexpr int E = 4;
+    static_assert(E % 4 == 0, "E must be a multiple of 4");
     const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (w >= n_waves) return;
     if (mask && !mask[wave_prob[w]]) return;
@@ -151,18 +152,29 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ per
             return;
         }
         // aligned vector loads; perm and ws carry a zeroed tail of 8 samples
-        const int4 t4 = *reinterpret_cast<const int4*>(perm + base);
-        const int tt[4] = {t4.x, t4.y, t4.z, t4.w};
+        int tt[E];
+#pragma unroll
+        for (int g = 0; g < E / 4; ++g) {
+            const int4 t4 = *reinterpret_cast<const int4*>(perm + base + 4 * g);
+            tt[4 * g] = t4.x;
+            tt[4 * g + 1] = t4.y;
+            tt[4 * g + 2] = t4.z;
+            tt[4 * g + 3] = t4.w;
+        }
         T zz[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) zz[e] = valid[e] ? z[tt[e]] : (T)0;
         if constexpr (NS == 3) {
             T wv[2 * E];
             if constexpr (sizeof(T) == 4) {
-                const float4 a = *reinterpret_cast<const float4*>(ws + 2 * base);
-                const float4 b = *reinterpret_cast<const float4*>(ws + 2 * base + 4);
-                wv[0] = a.x; wv[1] = a.y; wv[2] = a.z; wv[3] = a.w;
-                wv[4] = b.x; wv[5] = b.y; wv[6] = b.z; wv[7] = b.w;
+#pragma unroll
+                for (int g = 0; g < E / 2; ++g) {
+                    const float4 a = *reinterpret_cast<const float4*>(ws + 2 * base + 4 * g);
+                    wv[4 * g] = a.x;
+                    wv[4 * g + 1] = a.y;
+                    wv[4 * g + 2] = a.z;
+                    wv[4 * g + 3] = a.w;
+                }
             } else {
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
@@ -336,13 +348,15 @@ template <typename T>
 int scatter_t(mm_plan_t pl, const T* z, const T* ws, double* x, const int* mask) {
     const int64_t nb = (pl->n_waves + 3) / 4;
     if (nb == 0) return MM_OK;
+    // 4 samples per lane: 8 gathers more per lane cost the residency they would add
+    constexpr int E = 4;
     if (pl->n_s == 3)
-        hipLaunchKernelGGL((k_scatter<T, 3>), dim3(nb), dim3(256), 0, pl->stream, pl->perm.p, ws, z,
-                           (const unsigned long long*)pl->heads.p, pl->wave_pix.p, pl->seg.p,
+        hipLaunchKernelGGL((k_scatter<T, 3, E>), dim3(nb), dim3(256), 0, pl->stream, pl->perm.p, ws,
+                           z, (const unsigned long long*)pl->heads.p, pl->wave_pix.p, pl->seg.p,
                            pl->hits.p, pl->n_waves, x, mask, pl->wave_prob.p);
     else
-        hipLaunchKernelGGL((k_scatter<T, 1>), dim3(nb), dim3(256), 0, pl->stream, pl->perm.p, ws, z,
-                           (const unsigned long long*)pl->heads.p, pl->wave_pix.p, pl->seg.p,
+        hipLaunchKernelGGL((k_scatter<T, 1, E>), dim3(nb), dim3(256), 0, pl->stream, pl->perm.p, ws,
+                           z, (const unsigned long long*)pl->heads.p, pl->wave_pix.p, pl->seg.p,
                            pl->hits.p, pl->n_waves, x, mask, pl->wave_prob.p);
     MM_HIP(hipGetLastError());
     return MM_OK;
