@@ -35,20 +35,38 @@ BYTES_NINV32 = 4 + 8 + 4     # compact pixel id + (cos, sin) read, z written
 BYTES_PT32 = 4 + 8 + 4       # sorted sample index + sorted (cos, sin) + z gathered
 BYTES_NINV64 = 4 + 16 + 8
 BYTES_PT64 = 4 + 16 + 8
+# FP32 vector peak without packed FP32 instructions (the library is built without them):
+# 256 CUs x 64 lanes x 2 flops (FMA) x 2.4 GHz
+FP32_VALU_PEAK_TFLOPS = 78.6
+
+
+def fft_tile_flops(offsets, lam, n_r):
+    """Tiles of the overlap-save N^-1 and its algorithmic flops per launch: per tile a
+    forward and an inverse real FFT of n_r points, each a complex FFT of M = n_r/2 points
+    (5 M log2 M flops) plus the O(M) real-to-complex split, spectrum product and merge
+    (10 M flops in all): 10 M log2 M + 10 M."""
+    lmax = n_r - 2 * lam
+    lens = np.diff(np.asarray(offsets, dtype=np.int64))
+    tiles = int(np.sum((lens + lmax - 1) // lmax))
+    M = n_r // 2
+    per_tile = 10 * M * np.log2(M) + 10 * M
+    return tiles, float(tiles * per_tile)
 
 # HBM traffic of the dominant kernel per launch, from two rocprofv3 --pmc runs of this
 # script (FETCH_SIZE, then WRITE_SIZE, median over the launches of the timed solve), each
 # scaled by what the same counter reads for a plain 256 MiB device copy (--copy-calibration):
 # FETCH_SIZE reads 128 MiB for the 256 MiB read (factor 2.0), WRITE_SIZE 256 MiB (factor 1.0).
+# The factor 2 is that of 128-byte read requests, which FETCH_SIZE counts as 64 bytes; the
+# TCC_EA0_RDREQ_{32B,64B,128B} counters show both kernels read with 128-byte requests too.
 # The figures hold only for the kernel source they were taken on (sha256 below); after any
 # change to that file the traffic is reported as null until the counters are taken again.
 TRAFFIC = {
     "ninv32": dict(source="paper_1408_3048_amd/csrc/toeplitz.hip",
-                   sha256="bd0c4c3ee070d34551ee3de728d7d623f4b2f38a60b4b91d625cebd146c3e279",
-                   fetch_kib=198015.25, write_kib=65576.0, fetch_factor=2.0, write_factor=1.0),
+                   sha256="7acc442ffd2ddd79eeef1f101af789d21f781b0078a6aa8dd923d09a3d7ce73c",
+                   fetch_kib=286084.8125, write_kib=65536.0, fetch_factor=2.0, write_factor=1.0),
     "pt32": dict(source="paper_1408_3048_amd/csrc/pointing.hip",
-                 sha256="a03c930bc0d427fb915e4be6c6118e59cc34e488ee306bacc2169a58e0fb81b8",
-                 fetch_kib=151759.125, write_kib=6769.59, fetch_factor=2.0, write_factor=1.0),
+                 sha256="53f8c7d69fb28776fe71aa5f890c9f8c5c35f447a3b70c724a45cf164829388d",
+                 fetch_kib=152719.8125, write_kib=6798.66, fetch_factor=2.0, write_factor=1.0),
 }
 
 
@@ -167,6 +185,9 @@ def main():
                     help="skip the 256-problem batched Monte Carlo leg")
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: FFT tile lengths picked by timing at plan time (cached per process)")
+    ap.add_argument("--fft-len-f32", type=int, default=0,
+                    help="fixed FP32 overlap-save length instead of the autotuner (profiling runs)")
+    ap.add_argument("--fft-len-f64", type=int, default=0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the 256 MiB copy that calibrates the HBM byte counters")
     args = ap.parse_args()
@@ -206,7 +227,8 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         plan = Plan(pix, w, sc.n_pix, sc.offsets, psd, precision=precision, coarse=coarse,
-                    autotune=bool(args.autotune), **kw)
+                    autotune=bool(args.autotune), fft_len_f32=args.fft_len_f32,
+                    fft_len_f64=args.fft_len_f64, **kw)
         if profile:
             plan.profile(True)
         b = plan.rhs(d)
@@ -273,21 +295,37 @@ def main():
     n_pt, t_pt = prof["pt32"]
     avg_ninv = t_ninv / max(n_ninv, 1)
     avg_pt = t_pt / max(n_pt, 1)
-    cand = {
-        "ninv32": (t_ninv, avg_ninv, BYTES_NINV32, "k_toeplitz<float> (gather P + overlap-save N^-1)"),
-        "pt32": (t_pt, avg_pt, BYTES_PT32, "k_scatter<float,3> (P^T segmented reduction)"),
+    n_r32 = extras[-1]["fft_lengths"][1]
+    tiles, flops = fft_tile_flops(sc.offsets, sc.lam, n_r32)
+    hbm = {
+        "ninv32": dict(GBps=round(BYTES_NINV32 * sc.n_samples / (avg_ninv * 1e-3) / 1e9, 1),
+                       algorithmic_bytes_per_launch=BYTES_NINV32 * sc.n_samples,
+                       traffic=kernel_traffic("ninv32"), avg_ms=round(avg_ninv, 5)),
+        "pt32": dict(GBps=round(BYTES_PT32 * sc.n_samples / (avg_pt * 1e-3) / 1e9, 1),
+                     algorithmic_bytes_per_launch=BYTES_PT32 * sc.n_samples,
+                     traffic=kernel_traffic("pt32"), avg_ms=round(avg_pt, 5),
+                     frac=round(BYTES_PT32 * sc.n_samples / (avg_pt * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)),
+        "ax_fp32_GBps": round((BYTES_NINV32 + BYTES_PT32) * sc.n_samples /
+                              ((avg_ninv + avg_pt) * 1e-3) / 1e9, 1),
     }
-    dom = max(cand, key=lambda k: cand[k][0])
-    _, avg_ms, bps, kname = cand[dom]
-    achieved = bps * sc.n_samples / (avg_ms * 1e-3) / 1e9
-    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBPS, 4), traffic=kernel_traffic(dom), kernel=kname,
-                avg_launch_ms=round(avg_ms, 5), launches=n_ninv if dom == "ninv32" else n_pt,
-                algorithmic_bytes_per_launch=bps * sc.n_samples,
-                ax_fp32_GBps=round((BYTES_NINV32 + BYTES_PT32) * sc.n_samples /
-                                   ((avg_ninv + avg_pt) * 1e-3) / 1e9, 1),
-                other_kernels={k: dict(launches=v[0], avg_ms=v[1] / max(v[0], 1))
-                               for k, v in prof.items() if v[0] > 0})
+    if t_ninv >= t_pt:  # the overlap-save FFT kernel: VALU-issue bound
+        achieved = flops / (avg_ninv * 1e-3) / 1e12
+        roof = dict(bound="alu", achieved=round(achieved, 2), peak=FP32_VALU_PEAK_TFLOPS,
+                    unit="TFLOP/s", frac=round(achieved / FP32_VALU_PEAK_TFLOPS, 4),
+                    traffic=kernel_traffic("ninv32"),
+                    kernel="k_toeplitz<float> (gather P + overlap-save N^-1)",
+                    avg_launch_ms=round(avg_ninv, 5), launches=n_ninv, tiles=tiles, n_r=n_r32,
+                    algorithmic_flops_per_launch=flops)
+    else:
+        achieved = BYTES_PT32 * sc.n_samples / (avg_pt * 1e-3) / 1e9
+        roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBPS, 4), traffic=kernel_traffic("pt32"),
+                    kernel="k_scatter<float,3> (P^T segmented reduction)",
+                    avg_launch_ms=round(avg_pt, 5), launches=n_pt,
+                    algorithmic_bytes_per_launch=BYTES_PT32 * sc.n_samples)
+    roof["hbm_view"] = hbm
+    roof["other_kernels"] = {k: dict(launches=v[0], avg_ms=v[1] / max(v[0], 1))
+                             for k, v in prof.items() if v[0] > 0}
 
     batched = None
     if not args.no_batched:
