@@ -111,6 +111,18 @@ int apply_A64(mm_plan_t pl, const double* x, double* y, const int* mask) {
     return apply_A64_tag(pl, x, y, mask, -1);
 }
 
+int apply_A64_sparse(mm_plan_t pl, const double* x, double* y) {
+    MM_TRY(pack_map64(pl, x));
+    MM_TRY(toeplitz_map64(pl, x, pl->tod64a.p, nullptr, true));
+    return scatter64(pl, pl->tod64a.p, y, nullptr);
+}
+
+int apply_A32_sparse(mm_plan_t pl, const double* x, double* y) {
+    MM_TRY(pack_map32(pl, x));
+    MM_TRY(toeplitz_map32(pl, x, pl->tod32a.p, nullptr, true));
+    return scatter32(pl, pl->tod32a.p, y, nullptr);
+}
+
 int apply_A32(mm_plan_t pl, const double* x, double* y, const int* mask) {
     return apply_A32_tag(pl, x, y, mask, -1);
 }

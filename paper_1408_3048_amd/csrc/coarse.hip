@@ -691,12 +691,12 @@ int build_coarse(mm_plan_t pl) {
                                due.p, crow.p, cval.p, (int)ns, zc.p);
             MM_HIP(hipGetLastError());
             if (mixed) {
-                MM_TRY(apply_A32(pl, zc.p, tmp.p, nullptr));
+                MM_TRY(apply_A32_sparse(pl, zc.p, tmp.p));
                 hipLaunchKernelGGL(k_store_az<float>, dim3(sgx, nl), dim3(256), 0, st, lprob.p + lo,
                                    (const double*)tmp.p, pl->ooff.p, (int)ns,
                                    (const int64_t*)d_azd_off.p, k, azf.p);
             } else {
-                MM_TRY(apply_A64(pl, zc.p, tmp.p, nullptr));
+                MM_TRY(apply_A64_sparse(pl, zc.p, tmp.p));
                 hipLaunchKernelGGL(k_store_az<double>, dim3(sgx, nl), dim3(256), 0, st, lprob.p + lo,
                                    (const double*)tmp.p, pl->ooff.p, (int)ns,
                                    (const int64_t*)d_azd_off.p, k, azd.p);

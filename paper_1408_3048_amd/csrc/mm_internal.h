@@ -299,8 +299,10 @@ int adjoint_tod(mm_plan_t pl, const double* m_hat, const double* mu, const void*
 // have been packed by pack_map64/32 first
 int pack_map64(mm_plan_t pl, const double* x);
 int pack_map32(mm_plan_t pl, const double* x);
-int toeplitz_map64(mm_plan_t pl, const double* x, double* z, const int* mask);
-int toeplitz_map32(mm_plan_t pl, const double* x, float* z, const int* mask);
+int toeplitz_map64(mm_plan_t pl, const double* x, double* z, const int* mask,
+                   bool skip_zero = false);
+int toeplitz_map32(mm_plan_t pl, const double* x, float* z, const int* mask,
+                   bool skip_zero = false);
 int toeplitz_tod64(mm_plan_t pl, const void* y, int y_f64, double* z);
 int toeplitz_tod32(mm_plan_t pl, const void* y, int y_f64, float* z);
 
@@ -344,5 +346,8 @@ int prof_end(mm_plan_t pl, int k);
 void prof_invalidate(mm_plan_t pl, const size_t* mark, int first_skipped);
 int apply_A64(mm_plan_t pl, const double* x, double* y, const int* mask);
 int apply_A32(mm_plan_t pl, const double* x, double* y, const int* mask);
+// A x for mostly-zero x (the coarse-space columns): all-zero tiles skip the transform
+int apply_A64_sparse(mm_plan_t pl, const double* x, double* y);
+int apply_A32_sparse(mm_plan_t pl, const double* x, double* y);
 
 }  // namespace mm

@@ -184,6 +184,7 @@ struct ToepArgs {
     int lam;
     const int* mask;          // per-problem flags: tiles of problems with mask 0 are skipped
     const int32_t* int_prob;  // problem of every interval
+    int skip_zero;            // map modes: all-zero windows skip the transform
 };
 
 // LDS layout of the complex work array (M points).  Element a lives at
@@ -521,7 +522,10 @@ __device__ __forceinline__ bool load_window(const ToepArgs<T>& a, const CBuf<T>&
                                             int64_t base, int win, int64_t lo, int64_t hi) {
     constexpr int NR = 2 << LOGM;
     constexpr int PER = NR / NT;
-    constexpr int B = PER < 16 ? PER : 16;
+    // gathers in flight per thread: 8 for the IQU map gather (its registers bound the
+    // occupancy), 16 otherwise
+    constexpr int BMAX = MODE == 0 ? 8 : 16;
+    constexpr int B = PER < BMAX ? PER : BMAX;
     static_assert(PER % B == 0, "tile must split into batches");
     static_assert(NT % 2 == 0, "even thread count");
     // point (tid + c NT) / 2 = tid / 2 + c NT / 2 with bit-disjoint terms
@@ -529,14 +533,14 @@ __device__ __forceinline__ bool load_window(const ToepArgs<T>& a, const CBuf<T>&
     bool nz = false;
 #pragma unroll
     for (int b0 = 0; b0 < PER; b0 += B) {
-        int64_t tt[B];
+        int32_t tt[B];  // sample indices (n_samples < 2^31)
         bool ok[B];
 #pragma unroll
         for (int u = 0; u < B; ++u) {
             const int i = threadIdx.x + (b0 + u) * NT;
             const int64_t t = base + i;
             ok[u] = i < win && t >= lo && t < hi;
-            tt[u] = ok[u] ? t : lo;
+            tt[u] = (int32_t)(ok[u] ? t : lo);
         }
         T v[B];
         if constexpr (MODE == 0) {  // map, I/Q/U: one packed-map gather per sample
@@ -578,8 +582,23 @@ __device__ __forceinline__ bool load_window(const ToepArgs<T>& a, const CBuf<T>&
     return nz;
 }
 
-template <typename T, int LOGM, int NT, int MODE>
-__global__ __launch_bounds__(NT) void k_toeplitz(ToepArgs<T> a) {
+// waves per SIMD that the tile's LDS allows (160 KB per CU, 4 SIMDs per CU), capped where
+// the butterflies and gathers would spill (4 waves = 128 VGPRs for FP32, 3 = 170
+// for FP64): the register budget the compiler must meet so that LDS bounds occupancy
+template <typename T, int LOGM, int NT>
+constexpr int tile_waves_per_simd() {
+    constexpr int bytes = 2 * (1 << LOGM) * (int)sizeof(T);
+    constexpr int blocks = (160 * 1024) / bytes;
+    constexpr int w = blocks * (NT / 64) / 4;
+    constexpr int cap = sizeof(T) == 4 ? 4 : 3;
+    return w < 1 ? 1 : (w > cap ? cap : w);
+}
+
+// SKIPZ: a tile whose input window is all zero writes zeros and skips the transform (the
+// exact result; used for the sparse A Z columns; costs a block vote in LDS)
+template <typename T, int LOGM, int NT, int MODE, bool SKIPZ>
+__global__ __launch_bounds__(NT, (tile_waves_per_simd<T, LOGM, NT>())) void k_toeplitz(
+    ToepArgs<T> a) {
     constexpr int M = 1 << LOGM;
     __shared__ __align__(16) unsigned char smem[2 * M * sizeof(T)];
     const CBuf<T> buf = make_cbuf<T>(smem, M);
@@ -591,9 +610,14 @@ __global__ __launch_bounds__(NT) void k_toeplitz(ToepArgs<T> a) {
     const int64_t lo = a.int_lo[j], hi = a.int_hi[j];
     const int lam = a.lam;
     const bool nz = load_window<T, LOGM, NT, MODE>(a, buf, o - lam, L + 2 * lam, lo, hi);
-    if (!__syncthreads_or(nz)) {  // zero window: the exact result is zero (e.g. A Z columns)
-        for (int i = threadIdx.x; i < L; i += NT) a.z[o + i] = (T)0;
-        return;
+    if constexpr (SKIPZ) {
+        if (!__syncthreads_or(nz)) {  // zero window: the exact result is zero
+            for (int i = threadIdx.x; i < L; i += NT) a.z[o + i] = (T)0;
+            return;
+        }
+    } else {
+        (void)nz;
+        __syncthreads();
     }
     fwd_passes<T, LOGM, NT, LOGM>(buf, a.tw);
     spectrum_pass<T, LOGM, NT>(buf, a.H + (int64_t)a.int_kern[j] * (M + 1), a.tw);
@@ -720,11 +744,18 @@ template <typename T, int LOGM>
 int launch_logm(const ToepArgs<T>& a, int64_t n_tiles, hipStream_t st) {
     constexpr int M = 1 << LOGM;
     constexpr int NT = (M / 16) > 1024 ? 1024 : ((M / 16) < 256 ? 256 : (M / 16));
-    switch (a.mode) {
-        case 0: hipLaunchKernelGGL((k_toeplitz<T, LOGM, NT, 0>), dim3(n_tiles), dim3(NT), 0, st, a); break;
-        case 1: hipLaunchKernelGGL((k_toeplitz<T, LOGM, NT, 1>), dim3(n_tiles), dim3(NT), 0, st, a); break;
-        case 2: hipLaunchKernelGGL((k_toeplitz<T, LOGM, NT, 2>), dim3(n_tiles), dim3(NT), 0, st, a); break;
-        default: hipLaunchKernelGGL((k_toeplitz<T, LOGM, NT, 3>), dim3(n_tiles), dim3(NT), 0, st, a); break;
+    if (a.skip_zero) {
+        if (a.mode == 0)
+            hipLaunchKernelGGL((k_toeplitz<T, LOGM, NT, 0, true>), dim3(n_tiles), dim3(NT), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_toeplitz<T, LOGM, NT, 1, true>), dim3(n_tiles), dim3(NT), 0, st, a);
+    } else {
+        switch (a.mode) {
+            case 0: hipLaunchKernelGGL((k_toeplitz<T, LOGM, NT, 0, false>), dim3(n_tiles), dim3(NT), 0, st, a); break;
+            case 1: hipLaunchKernelGGL((k_toeplitz<T, LOGM, NT, 1, false>), dim3(n_tiles), dim3(NT), 0, st, a); break;
+            case 2: hipLaunchKernelGGL((k_toeplitz<T, LOGM, NT, 2, false>), dim3(n_tiles), dim3(NT), 0, st, a); break;
+            default: hipLaunchKernelGGL((k_toeplitz<T, LOGM, NT, 3, false>), dim3(n_tiles), dim3(NT), 0, st, a); break;
+        }
     }
     MM_HIP(hipGetLastError());
     return MM_OK;
@@ -1169,8 +1200,9 @@ int pack_map32(mm_plan_t pl, const double* x) {
     return pl->n_s == 3 ? pack_map<float>(pl, x, pl->xp32.p) : MM_OK;
 }
 
-int toeplitz_map64(mm_plan_t pl, const double* x, double* z, const int* mask) {
+int toeplitz_map64(mm_plan_t pl, const double* x, double* z, const int* mask, bool skip_zero) {
     auto a = base_args<double>(pl, pl->fft64);
+    a.skip_zero = skip_zero;
     a.x = x;
     if (pl->n_s == 3) a.xp = pl->xp64.p;
     a.mode = pl->n_s == 3 ? 0 : 1;
@@ -1179,8 +1211,9 @@ int toeplitz_map64(mm_plan_t pl, const double* x, double* z, const int* mask) {
     return launch<double>(a, pl->fft64.logm, pl->fft64.n_tiles, pl->stream);
 }
 
-int toeplitz_map32(mm_plan_t pl, const double* x, float* z, const int* mask) {
+int toeplitz_map32(mm_plan_t pl, const double* x, float* z, const int* mask, bool skip_zero) {
     auto a = base_args<float>(pl, pl->fft32);
+    a.skip_zero = skip_zero;
     a.x = x;
     if (pl->n_s == 3) a.xp = pl->xp32.p;
     a.mode = pl->n_s == 3 ? 0 : 1;
