@@ -51,6 +51,7 @@ __all__ = [
     "toeplitz_taps_cosine_sum", "taps_symbol", "toeplitz_apply", "toeplitz_apply_at",
     "toeplitz_dense", "Problem", "pcg", "dense_system", "coarse_zs", "Coarse",
     "tap_derivatives", "lag_correlations", "map_gradients_dense", "map_dense", "map_gradients",
+    "pcg_lanczos", "lanczos_tridiagonal", "ritz_pairs", "deflation_space",
 ]
 
 
@@ -523,3 +524,79 @@ def map_gradients(prob: Problem, d, g):
         c = lag_correlations(u[a:b], v[a:b], D.shape[1] - 1)
         grad_t[j] = D @ c
     return m, grad_d, grad_t, mu
+
+
+# --------------------------------------------------------------------------
+# a posteriori coarse space Z_D (Sect. 3.3.2, App. A)
+# --------------------------------------------------------------------------
+
+def pcg_lanczos(apply_A, b, precond, tol=1e-8, maxit=1000):
+    """PCG from x0 = 0 that keeps what the Krylov process learns about M A: the step
+    lengths alpha_k, the residual products rz_k = r_k^T z_k and the preconditioned
+    residuals z_k (k = 0 .. m).  Stops on the recursive relative residual.
+    Returns (x, alphas [m], rz [m+1], Zk [n, m+1])."""
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros_like(b)
+    r = b.copy()
+    bn = np.linalg.norm(b)
+    z = precond(r)
+    rz = [r @ z]
+    zs = [z.copy()]
+    alphas = []
+    p = z.copy()
+    for _ in range(maxit):
+        q = apply_A(p)
+        a = rz[-1] / (p @ q)
+        alphas.append(a)
+        x += a * p
+        r -= a * q
+        z = precond(r)
+        rz.append(r @ z)
+        zs.append(z.copy())
+        if np.linalg.norm(r) / bn <= tol:
+            break
+        p = z + (rz[-1] / rz[-2]) * p
+    return x, np.array(alphas), np.array(rz), np.stack(zs, axis=1)
+
+
+def lanczos_tridiagonal(alphas, rz):
+    """The Lanczos matrix T_m of M A that CG builds implicitly (M symmetric positive
+    definite, the Krylov basis orthonormal in the M^-1 inner product): with
+    beta_k = rz_k / rz_{k-1},
+      T[k, k]   = 1/alpha_k + beta_k / alpha_{k-1}   (second term absent for k = 0)
+      T[k, k+1] = T[k+1, k] = sqrt(beta_{k+1}) / alpha_k,
+    in the basis w_k = (-1)^k z_k / sqrt(rz_k) (z_k^T A z_{k+1} = -rz_{k+1} / alpha_k).
+    The CG counterpart of the Arnoldi relation of App. A (H_m symmetric tridiagonal)."""
+    m = alphas.shape[0]
+    beta = rz[1:] / rz[:-1]
+    T = np.zeros((m, m))
+    for k in range(m):
+        T[k, k] = 1.0 / alphas[k] + (beta[k - 1] / alphas[k - 1] if k > 0 else 0.0)
+        if k + 1 < m:
+            T[k, k + 1] = T[k + 1, k] = np.sqrt(beta[k]) / alphas[k]
+    return T
+
+
+def ritz_pairs(alphas, rz, Zk):
+    """Ritz values theta_i and vectors y_i = W_m s_i of M A from one PCG run (eq.
+    approxEigen with B = M_BD A): W_m has columns (-1)^k z_k / sqrt(rz_k), T_m s_i =
+    theta_i s_i.  Also returns the error estimates |sqrt(beta_m)/alpha_{m-1} s_i[m-1]|,
+    the size of the last term of eq. approxEigen in the M^-1 norm."""
+    m = alphas.shape[0]
+    T = lanczos_tridiagonal(alphas, rz)
+    theta, S = np.linalg.eigh(T)
+    W = Zk[:, :m] * ((-1.0) ** np.arange(m) / np.sqrt(rz[:m]))
+    est = np.abs(np.sqrt(rz[m] / rz[m - 1]) / alphas[m - 1] * S[m - 1, :])
+    return theta, W @ S, est
+
+
+def deflation_space(prob: Problem, b, eps_tol=0.2, tol=1e-8, maxit=1000, max_cols=None):
+    """Z_D (Sect. 3.3.2): the Ritz vectors of M_BD A with Ritz values below eps_tol, from
+    a block-Jacobi PCG solve of A x' = b'."""
+    B = prob.bj_blocks()
+    _, al, rz, Zk = pcg_lanczos(prob.apply_A, b, lambda r: prob.bj_apply(r, B), tol, maxit)
+    theta, Y, _ = ritz_pairs(al, rz, Zk)
+    keep = np.nonzero(theta < eps_tol)[0]
+    if max_cols is not None:
+        keep = keep[:max_cols]
+    return Y[:, keep], theta

@@ -345,3 +345,68 @@ def test_banded_map_gradients_equal_dense_ones():
     got = O.map_gradients(pr, d, g)
     for a, b in zip(got, ref):
         assert np.max(np.abs(a - b)) <= 1e-9 * np.max(np.abs(b))
+
+
+# ----------------------------------------------------- a posteriori coarse space
+
+def _small_iqu_problem(seed=9):
+    """8x8 IQU, 2 detectors, one 1024-sample interval per detector, strong 1/f noise
+    (f_knee 5-10 Hz, alpha 2): M_BD A has 11 eigenvalues below 0.2."""
+    import synth
+    sc = synth.raster_iqu(side=8, spp=8, n_det=2, interval_len=1024, lam=32,
+                          fknee_range=(5.0, 10.0), alpha_range=(2.0, 2.0), seed_key=seed)
+    return sc, O.Problem.from_scan(sc)
+
+
+def test_lanczos_matrix_is_m_a_in_the_krylov_basis():
+    """T_m = W^T M^-1 (M A) W = W^T A W for W the normalised preconditioned residuals
+    with alternating signs: the CG coefficients reproduce the projected operator."""
+    sc, pr = _small_iqu_problem()
+    B = pr.bj_blocks()
+    b = pr.rhs(sc.noise)
+    _, al, rz, Zk = O.pcg_lanczos(pr.apply_A, b, lambda r: pr.bj_apply(r, B), tol=1e-6)
+    m = al.shape[0]
+    W = Zk[:, :m] * ((-1.0) ** np.arange(m) / np.sqrt(rz[:m]))
+    AW = np.stack([pr.apply_A(W[:, k]) for k in range(m)], axis=1)
+    T = O.lanczos_tridiagonal(al, rz)
+    assert np.max(np.abs(W.T @ AW - T)) <= 1e-8 * np.max(np.abs(T))
+
+
+def test_ritz_values_converge_to_eigenvalues_of_preconditioned_operator():
+    sc, pr = _small_iqu_problem()
+    B = pr.bj_blocks()
+    b = pr.rhs(sc.noise)
+    _, al, rz, Zk = O.pcg_lanczos(pr.apply_A, b, lambda r: pr.bj_apply(r, B), tol=1e-13,
+                                  maxit=2000)
+    theta, Y, est = O.ritz_pairs(al, rz, Zk)
+    A, P, N = O.dense_system(pr)
+    n = A.shape[0]
+    Mb = np.zeros((n, n))
+    for p in range(pr.n_obs):
+        Mb[3 * p:3 * p + 3, 3 * p:3 * p + 3] = np.linalg.inv(B[p])
+    ev = np.sort(np.linalg.eigvals(Mb @ A).real)
+    # the smallest (isolated) Ritz value is a converged eigenvalue of M_BD A; all Ritz
+    # values lie inside the spectrum
+    assert theta[0] == pytest.approx(ev[0], rel=1e-8)
+    assert ev[0] * (1 - 1e-10) <= theta.min() and theta.max() <= ev[-1] * (1 + 1e-10)
+    # eq. approxEigen: ||M A y - theta y|| (M^-1 norm) equals the last-term estimate
+    i = 0
+    res = Mb @ (A @ Y[:, i]) - theta[i] * Y[:, i]
+    Minv = np.linalg.inv(Mb)
+    assert np.sqrt(res @ Minv @ res) == pytest.approx(est[i], rel=1e-4, abs=1e-10)
+
+
+def test_deflation_space_two_level_properties():
+    sc, pr = _small_iqu_problem()
+    b = pr.rhs(sc.noise)
+    Zd, theta = O.deflation_space(pr, b, eps_tol=0.2, tol=1e-10, maxit=2000)
+    assert Zd.shape[1] >= 1 and np.all(theta[:Zd.shape[1]] < 0.2)
+    co = O.Coarse(pr, Zd)
+    AZ = np.stack([pr.apply_A(Zd[:, j]) for j in range(Zd.shape[1])], axis=1)
+    MAZ = np.stack([co.apply(AZ[:, j]) for j in range(Zd.shape[1])], axis=1)
+    assert np.max(np.abs(MAZ - Zd)) <= 1e-8 * np.max(np.abs(Zd))
+    # the a posteriori preconditioner needs fewer iterations than block Jacobi on a new RHS
+    b2 = pr.rhs(np.roll(sc.noise, 777))
+    _, it_bj, _ = O.pcg(pr.apply_A, b2, pr.bj_apply, tol=1e-8, maxit=2000)
+    x2, it_d, st = O.pcg(pr.apply_A, b2, co.apply, tol=1e-8, maxit=2000)
+    assert st == 0 and it_d < it_bj
