@@ -161,7 +161,7 @@ int mm_sorted_samples(mm_plan_t plan, int32_t* dev_out);
 int mm_interval_taps(mm_plan_t plan, int32_t interval, double* host_out, int cap);
 
 /* Coarse space [App. C]: number of columns kept after removing duplicate and dependent
- * columns of Z_S (r_eff), or a negative status. */
+ * columns of Z_S (or of Z_D after mm_coarse_from_krylov) (r_eff), or a negative status. */
 int mm_coarse_rank(mm_plan_t plan);
 /* Host int32 [r_eff]: interval index of every kept column of Z_S. */
 int mm_coarse_columns(mm_plan_t plan, int32_t* host_out, int cap);
@@ -189,8 +189,9 @@ int mm_rhs(mm_plan_t plan, const void* d, int d_dtype, double* b);
 int mm_apply_A(mm_plan_t plan, const double* x, double* y, int precision);
 /* z = M_BD r [eq. stdPrec]. r and z may alias. */
 int mm_precond_bj(mm_plan_t plan, const double* r, double* z);
-/* z = M_2lvl r = M_BD (r - AZ E^-1 Z^T r) + Z E^-1 Z^T r [eq. 2] (plan built with
- * MM_COARSE_ZS, else MM_ERR_STATE).  r and z may not alias. */
+/* z = M_2lvl r = M_BD (r - AZ E^-1 Z^T r) + Z E^-1 Z^T r [eq. 2] with the plan's coarse
+ * space (Z_S from MM_COARSE_ZS, or Z_D from mm_coarse_from_krylov; none: MM_ERR_STATE).
+ * r and z may not alias. */
 int mm_precond_2lvl(mm_plan_t plan, const double* r, double* z);
 
 /* ----- solver ----- */
@@ -230,6 +231,53 @@ typedef struct {
  * MM_ERR_ARG / MM_ERR_STATE.  Synchronises the plan's stream before returning. */
 int mm_pcg_solve(mm_plan_t plan, const double* b, double* x, int precond, int precision,
                  double tol, int max_iter, mm_solve_info* info);
+
+/* ----- a posteriori coarse space Z_D [Sect. 3.3.2; App. A] ----- */
+
+/* Solve A x = b by block-Jacobi PCG (FP64 operator, from x0 = 0 regardless of x's
+ * contents, every problem of a batched plan at once) and build the two-level
+ * preconditioner's coarse space from what the solve learns about M_BD A: PCG is the
+ * Lanczos process on M_BD A, so its step lengths and preconditioned residuals give the
+ * Lanczos matrix T (symmetric tridiagonal) and the basis W (columns (-1)^k z_k /
+ * sqrt(r_k^T z_k)); the Ritz pairs (theta_i, y_i = W s_i), T s_i = theta_i s_i [App. A,
+ * eq. approxEigen with B = M_BD A], with theta_i < eps_tol become the columns of Z_D
+ * (dense, every Stokes row), per problem.  AZ_D and E_D = Z_D^T A Z_D are then formed
+ * as for Z_S (pivoted-Cholesky selection with opts.rank_tol), and Z_D replaces the plan's
+ * coarse space: later mm_pcg_solve / mm_precond_2lvl calls with MM_2LVL use
+ * M_2lvl,D [eq. 2 with Z = Z_D].  Mixed plans keep Z_D and AZ_D in FP32.
+ *   b, x        device maps: right-hand side, and the solution of this first system
+ *   tol, max_iter   of the recording solve, as in mm_pcg_solve
+ *   krylov_dim  basis vectors kept (the first krylov_dim PCG steps; 0: max_iter); the
+ *               library holds krylov_dim * n_map FP64 values of device memory during
+ *               the call
+ *   eps_tol     Ritz-value threshold (the paper uses 0.2)
+ *   max_cols    at most this many columns per problem (the smallest Ritz values; 0: no cap)
+ *   info        NULL or host array of mm_n_problems(plan) entries (the recording solve)
+ * Returns MM_OK; MM_ERR_NOCONV when the solve stopped at max_iter (Z_D is still built
+ * from the recorded steps); MM_ERR_RANK when no problem has a Ritz value below eps_tol
+ * (the coarse space is then unchanged); MM_ERR_BREAKDOWN, MM_ERR_ARG, MM_ERR_DEVICE.
+ * Synchronises the plan's stream. */
+int mm_coarse_from_krylov(mm_plan_t plan, const double* b, double* x, double tol, int max_iter,
+                          int krylov_dim, double eps_tol, int max_cols, mm_solve_info* info);
+
+/* Host-only helper of mm_coarse_from_krylov (no device work): the Ritz values below
+ * eps_tol (ascending, at most max_cols) of the Lanczos matrix of m PCG steps with step
+ * lengths alpha[0..m) and products rz[0..m) = r_k^T z_k, T[k][k] = 1/alpha_k +
+ * beta_k/alpha_{k-1}, T[k][k+1] = sqrt(beta_{k+1})/alpha_k, beta_k = rz_k/rz_{k-1}
+ * [App. A]; theta_out[max_cols]; s_out (or NULL) receives the unit eigenvectors,
+ * row-major [m][r] (largest-magnitude entry positive).  Returns r >= 0 or an error. */
+int mm_lanczos_ritz(const double* alpha, const double* rz, int m, double eps_tol, int max_cols,
+                    double* theta_out, double* s_out);
+
+/* Kind of the plan's coarse space: 0 none, 1 Z_S (mm_plan, MM_COARSE_ZS), 2 Z_D. */
+int mm_coarse_kind(mm_plan_t plan);
+/* Host FP64 [r_eff]: Ritz value of every kept Z_D column (mm_coarse_columns gives its
+ * index among its problem's Ritz values below eps_tol).  MM_ERR_STATE unless Z_D. */
+int mm_coarse_ritz_values(mm_plan_t plan, double* host_out, int cap);
+/* The kept Z_D columns, FP64, into device dev_out: problem after problem, each block
+ * column-major [r_b][n_stokes * pixels_b]; returns the number of values (dev_out NULL:
+ * only the count).  MM_ERR_STATE unless Z_D. */
+int64_t mm_coarse_dense_columns(mm_plan_t plan, double* dev_out);
 
 /* FFT lengths (real samples per overlap-save tile) the plan uses for the FP64 and the
  * FP32 operator (0 for an operator the plan does not have). */

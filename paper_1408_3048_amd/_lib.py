@@ -35,7 +35,8 @@ EXPORTED = [
     "mm_precond_bj", "mm_precond_2lvl", "mm_pcg_solve", "mm_plan_time_ms", "mm_gemm_tn_f64",
     "mm_profile", "mm_profile_read", "mm_last_error", "mm_plan_batched", "mm_n_problems",
     "mm_problem_pixels", "mm_coarse_problem_columns", "mm_fft_lengths", "mm_lag_correlations",
-    "mm_tap_derivatives", "mm_adjoint",
+    "mm_tap_derivatives", "mm_adjoint", "mm_coarse_from_krylov", "mm_lanczos_ritz",
+    "mm_coarse_kind", "mm_coarse_ritz_values", "mm_coarse_dense_columns",
 ]
 
 
@@ -113,6 +114,11 @@ def load():
         "mm_lag_correlations": (I, [P, P, P, P]),
         "mm_tap_derivatives": (I, [P, P, I64]),
         "mm_adjoint": (I, [P, P, P, P, I, I, I, D, I, P, P, I, P, ctypes.POINTER(mm_solve_info)]),
+        "mm_coarse_from_krylov": (I, [P, P, P, D, I, I, D, I, ctypes.POINTER(mm_solve_info)]),
+        "mm_lanczos_ritz": (I, [P, P, I, D, I, P, P]),
+        "mm_coarse_kind": (I, [P]),
+        "mm_coarse_ritz_values": (I, [P, P, I]),
+        "mm_coarse_dense_columns": (I64, [P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -410,12 +416,7 @@ class Plan:
                     solve_ms=infos[0].solve_ms)
         return gd, gp, mu, info
 
-    def pcg_solve(self, b, x0=None, precond="bj", precision="fp64", tol=1e-8, max_iter=1000,
-                  history=True, raise_on_error=True):
-        """Returns (x, info dict); for a batched plan info["problems"] lists the info of
-        every problem and the top-level fields are those of problem 0 plus totals."""
-        import torch
-        x = torch.zeros_like(b) if x0 is None else x0.clone()
+    def _infos(self, max_iter, history):
         B = self.n_problems
         infos = (mm_solve_info * B)()
         hists = []
@@ -425,11 +426,24 @@ class Plan:
             if history:
                 infos[i].history = h.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
                 infos[i].history_cap = h.shape[0]
+        return infos, hists
+
+    def pcg_solve(self, b, x0=None, precond="bj", precision="fp64", tol=1e-8, max_iter=1000,
+                  history=True, raise_on_error=True):
+        """Returns (x, info dict); for a batched plan info["problems"] lists the info of
+        every problem and the top-level fields are those of problem 0 plus totals."""
+        import torch
+        x = torch.zeros_like(b) if x0 is None else x0.clone()
+        infos, hists = self._infos(max_iter, history)
         st = self._lib.mm_pcg_solve(self._h, _ptr(b), _ptr(x),
                                     MM_2LVL if precond == "2lvl" else MM_BJ,
                                     {"fp64": MM_FP64, "mixed": MM_MIXED,
                                      "mixed_ir": MM_MIXED_IR}[precision],
                                     float(tol), int(max_iter), infos)
+        return x, self._info_dict(st, infos, hists, raise_on_error)
+
+    def _info_dict(self, st, infos, hists, raise_on_error):
+        B = self.n_problems
         per = [dict(status=infos[i].status, iterations=infos[i].iterations,
                     outer_iterations=infos[i].outer_iterations,
                     replacements=infos[i].replacements, rel_residual=infos[i].rel_residual,
@@ -444,7 +458,69 @@ class Plan:
             out["rel_residual_max"] = max(p["rel_residual"] for p in per)
         if raise_on_error and st != MM_OK:
             raise MMError(st, last_error())
-        return x, out
+        return out
+
+    # ---- a posteriori coarse space
+    def coarse_from_krylov(self, b, tol=1e-8, max_iter=1000, krylov_dim=0, eps_tol=0.2,
+                           max_cols=0, history=True, raise_on_error=True):
+        """Block-Jacobi FP64 PCG solve of A x = b that records its Krylov process and
+        replaces the plan's coarse space with Z_D (Ritz vectors of M_BD A with Ritz value
+        below eps_tol).  Returns (x, info dict) like pcg_solve."""
+        import torch
+        x = torch.zeros_like(b)
+        infos, hists = self._infos(max_iter, history)
+        st = self._lib.mm_coarse_from_krylov(self._h, _ptr(b), _ptr(x), float(tol),
+                                             int(max_iter), int(krylov_dim), float(eps_tol),
+                                             int(max_cols), infos)
+        return x, self._info_dict(st, infos, hists, raise_on_error)
+
+    def coarse_kind(self):
+        """0: none, 1: Z_S, 2: Z_D."""
+        k = self._lib.mm_coarse_kind(self._h)
+        check(min(k, 0))
+        return k
+
+    def ritz_values(self):
+        """Ritz value of every kept Z_D column (host FP64 [r_eff])."""
+        r = self.coarse_rank()
+        out = np.empty(r, dtype=np.float64)
+        check(min(self._lib.mm_coarse_ritz_values(self._h, out.ctypes.data_as(ctypes.c_void_p),
+                                                  r), 0))
+        return out
+
+    def dense_columns(self):
+        """The kept Z_D columns: list over problems of CUDA FP64 [r_b, n_stokes * pixels_b]."""
+        import torch
+        n = self._lib.mm_coarse_dense_columns(self._h, None)
+        check(min(n, 0))
+        flat = torch.empty(max(int(n), 1), dtype=torch.float64, device="cuda")
+        check(min(self._lib.mm_coarse_dense_columns(self._h, _ptr(flat)), 0))
+        co = self.coarse_problem_columns()
+        pp = self.problem_pixels()
+        out, o = [], 0
+        for b in range(self.n_problems):
+            r, nb = int(co[b + 1] - co[b]), int(pp[b + 1] - pp[b]) * self.n_stokes
+            out.append(flat[o:o + r * nb].reshape(r, nb))
+            o += r * nb
+        return out
+
+
+def lanczos_ritz(alpha, rz, eps_tol=0.2, max_cols=None):
+    """Host helper of the Z_D construction: (theta [r], S [m, r]) of the Lanczos matrix of
+    m PCG steps with step lengths alpha[0..m) and r^T z products rz[0..m), Ritz values
+    below eps_tol."""
+    alpha = np.ascontiguousarray(alpha, dtype=np.float64)
+    rz = np.ascontiguousarray(rz, dtype=np.float64)
+    m = alpha.shape[0]
+    cap = int(max_cols) if max_cols else m
+    theta = np.empty(cap, dtype=np.float64)
+    S = np.empty(m * cap, dtype=np.float64)
+    r = load().mm_lanczos_ritz(alpha.ctypes.data_as(ctypes.c_void_p),
+                               rz.ctypes.data_as(ctypes.c_void_p), m, float(eps_tol), cap,
+                               theta.ctypes.data_as(ctypes.c_void_p),
+                               S.ctypes.data_as(ctypes.c_void_p))
+    check(min(r, 0))
+    return theta[:r].copy(), S[:m * r].reshape(m, r).copy()
 
 
 def gemm_tn_f64(A, B):

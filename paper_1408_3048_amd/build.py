@@ -13,7 +13,7 @@ SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmm.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["api.hip", "sort.hip", "toeplitz.hip", "pointing.hip", "coarse.hip", "blas.hip",
-           "adjoint.hip"]
+           "adjoint.hip", "krylov.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -130,6 +130,15 @@ int apply_A32(mm_plan_t pl, const double* x, double* y, const int* mask) {
 int gemm_tn_f64(hipStream_t st, const double* A, const double* B, int64_t n, int32_t ra,
                 int32_t rb, double* dev_C);
 
+void drop_graphs(mm_plan_t pl) {
+    for (auto& row : pl->gexec)
+        for (auto& g : row)
+            if (g) {
+                (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
+}
+
 namespace {
 
 using clk = std::chrono::steady_clock;
@@ -148,15 +157,6 @@ int precond(mm_plan_t pl, int pc, const double* r, double* z, const PcgCtl& ctl,
     MM_TRY(prof_begin(pl, MM_K_PRECOND, tag));
     MM_TRY(pc == MM_2LVL ? twolvl_apply(pl, r, z, ctl) : bj_apply(pl, r, z, ctl));
     return prof_end(pl, MM_K_PRECOND);
-}
-
-void drop_graphs(mm_plan_t pl) {
-    for (auto& row : pl->gexec)
-        for (auto& g : row)
-            if (g) {
-                (void)hipGraphExecDestroy(g);
-                g = nullptr;
-            }
 }
 
 int ensure_solver_buffers(mm_plan_t pl, int max_iter) {
@@ -760,7 +760,8 @@ int mm_precond_2lvl(mm_plan_t pl, const double* r, double* z) {
     clear_error();
     MM_TRY(check_vec_args(pl, r, z));
     if (!pl->has_coarse) {
-        set_error("plan built without a coarse space (opts.coarse = MM_COARSE_ZS)");
+        set_error("plan without a coarse space (opts.coarse = MM_COARSE_ZS or "
+                  "mm_coarse_from_krylov)");
         return MM_ERR_STATE;
     }
     if (r == z) {
@@ -781,7 +782,8 @@ int mm_pcg_solve(mm_plan_t pl, const double* b, double* x, int pc, int precision
         return MM_ERR_ARG;
     }
     if (pc == MM_2LVL && !pl->has_coarse) {
-        set_error("MM_2LVL needs a plan built with opts.coarse = MM_COARSE_ZS");
+        set_error("MM_2LVL needs a coarse space (opts.coarse = MM_COARSE_ZS or "
+                  "mm_coarse_from_krylov)");
         return MM_ERR_STATE;
     }
     if (precision != MM_FP64 && precision != MM_MIXED && precision != MM_MIXED_IR) {
@@ -939,6 +941,125 @@ int mm_pcg_solve(mm_plan_t pl, const double* b, double* x, int pc, int precision
     if (ret == MM_ERR_BREAKDOWN && g_err.empty())
         set_error("PCG breakdown (p^T A p <= 0 or not finite)");
     return ret;
+}
+
+int mm_coarse_from_krylov(mm_plan_t pl, const double* b, double* x, double tol, int max_iter,
+                          int krylov_dim, double eps_tol, int max_cols, mm_solve_info* info) {
+    clear_error();
+    MM_TRY(check_vec_args(pl, b, x));
+    if (!(tol > 0.0) || max_iter < 1 || krylov_dim < 0 || !(eps_tol > 0.0) || max_cols < 0) {
+        set_error("tol > 0, max_iter >= 1, krylov_dim >= 0, eps_tol > 0 and max_cols >= 0 "
+                  "required");
+        return MM_ERR_ARG;
+    }
+    if (b == x) {
+        set_error("b and x may not alias");
+        return MM_ERR_ARG;
+    }
+    const int B = pl->n_prob;
+    const int kcap = krylov_dim > 0 ? std::min(krylov_dim, max_iter) : max_iter;
+    const int64_t n = nvec(pl);
+    AllocStream alloc_scope(pl->stream);
+    MM_TRY(ensure_solver_buffers(pl, max_iter));
+    DBuf<double> basis, ahist;
+    MM_TRY(basis.alloc((size_t)kcap * n));
+    MM_TRY(ahist.alloc((size_t)B * pl->hstride));
+    // the recording solve: FP64 operator, block Jacobi, plain launches (a captured
+    // iteration would keep the recording pointers)
+    struct Recording {
+        mm_plan_t pl;
+        int graph;
+        ~Recording() {
+            pl->krec = mm_plan_s::KrylovRec{};
+            pl->opts.graph = graph;
+            drop_graphs(pl);
+        }
+    } rec{pl, pl->opts.graph};
+    drop_graphs(pl);
+    pl->opts.graph = 0;
+    pl->krec.basis = basis.p;
+    pl->krec.alpha = ahist.p;
+    pl->krec.cap = kcap;
+    std::vector<mm_solve_info> loc(B);
+    mm_solve_info* inf = info ? info : loc.data();
+    if (!info)
+        for (auto& i : loc) std::memset(&i, 0, sizeof(i));
+    const int solve_status = mm_pcg_solve(pl, b, x, MM_BJ, MM_FP64, tol, max_iter, inf);
+    if (solve_status != MM_OK && solve_status != MM_ERR_NOCONV) return solve_status;
+    const std::string solve_err = g_err;
+    // Lanczos data of every problem: alpha_k and r^T z_k for the recorded steps
+    const int hs = pl->hstride;
+    std::vector<double> ha((size_t)B * hs), hr((size_t)B * hs);
+    MM_HIP(hipMemcpyAsync(ha.data(), ahist.p, ha.size() * 8, hipMemcpyDeviceToHost, pl->stream));
+    MM_HIP(hipMemcpyAsync(hr.data(), pl->rz_hist.p, hr.size() * 8, hipMemcpyDeviceToHost,
+                          pl->stream));
+    MM_HIP(hipStreamSynchronize(pl->stream));
+    std::vector<std::vector<double>> G(B), theta(B);
+    std::vector<int> m(B);
+    for (int i = 0; i < B; ++i) {
+        m[i] = std::min(inf[i].iterations, kcap);
+        std::vector<double> S;
+        const double* al = ha.data() + (size_t)i * hs;
+        const double* rz = hr.data() + (size_t)i * hs;
+        MM_TRY(ritz_select(al, rz, m[i], eps_tol, max_cols, theta[i], S));
+        const int r = (int)theta[i].size();
+        G[i].resize((size_t)m[i] * r);
+        for (int k = 0; k < m[i]; ++k) {
+            const double sc = ((k & 1) ? -1.0 : 1.0) / std::sqrt(rz[k]);
+            for (int c = 0; c < r; ++c) G[i][(size_t)k * r + c] = sc * S[(size_t)k * r + c];
+        }
+    }
+    MM_TRY(build_coarse_dense(pl, basis.p, n, G, m, theta));
+    if (solve_status != MM_OK) g_err = solve_err;
+    return solve_status;
+}
+
+int mm_lanczos_ritz(const double* alpha, const double* rz, int m, double eps_tol, int max_cols,
+                    double* theta_out, double* s_out) {
+    clear_error();
+    if (!alpha || !rz || m < 1 || !(eps_tol > 0.0) || max_cols < 1 || !theta_out) {
+        set_error("alpha, rz, theta_out non-NULL, m >= 1, eps_tol > 0, max_cols >= 1 required");
+        return MM_ERR_ARG;
+    }
+    std::vector<double> theta, S;
+    MM_TRY(ritz_select(alpha, rz, m, eps_tol, max_cols, theta, S));
+    const int r = (int)theta.size();
+    for (int i = 0; i < r; ++i) theta_out[i] = theta[i];
+    if (s_out)
+        for (size_t e = 0; e < S.size(); ++e) s_out[e] = S[e];
+    return r;
+}
+
+int mm_coarse_kind(mm_plan_t pl) {
+    if (!pl) {
+        set_error("plan is NULL");
+        return MM_ERR_ARG;
+    }
+    return pl->has_coarse ? pl->co.kind : 0;
+}
+
+int mm_coarse_ritz_values(mm_plan_t pl, double* host_out, int cap) {
+    const int r = mm_coarse_rank(pl);
+    if (r < 0) return r;
+    if (pl->co.kind != 2) {
+        set_error("the plan's coarse space is not Z_D");
+        return MM_ERR_STATE;
+    }
+    for (int a = 0; a < r && a < cap; ++a) host_out[a] = pl->co.ritz[a];
+    return r;
+}
+
+int64_t mm_coarse_dense_columns(mm_plan_t pl, double* dev_out) {
+    clear_error();
+    const int r = mm_coarse_rank(pl);
+    if (r < 0) return r;
+    if (pl->co.kind != 2) {
+        set_error("the plan's coarse space is not Z_D");
+        return MM_ERR_STATE;
+    }
+    const int64_t total = pl->co.h_az_off[pl->n_prob];
+    if (dev_out) MM_TRY(coarse_dense_columns(pl, dev_out));
+    return total;
 }
 
 double mm_plan_time_ms(mm_plan_t pl) { return pl ? pl->plan_ms : -1.0; }

@@ -56,6 +56,7 @@ __global__ __launch_bounds__(kVecThreads) void k_update_xr(double* __restrict__ 
         s.alpha = alpha;
         s.pq = pq;
         s.iter_next = s.iter + 1;
+        if (c.alpha_hist) c.alpha_hist[(int64_t)v.b * c.hstride + s.iter] = alpha;
     }
     double acc = 0.0;
     for (int64_t i = (int64_t)v.k * kVecThreads + threadIdx.x; i < v.n;
@@ -88,10 +89,15 @@ __global__ __launch_bounds__(kVecThreads) void k_update_p(double* __restrict__ p
         rh[it] = rz_new;
         s.beta = beta;
     }
+    // Krylov recording: z of this iteration (rewritten when a residual evaluation resumes
+    // the same iteration, together with rz_hist[it])
+    double* kz = c.krylov && it < c.kcap ? c.krylov + (int64_t)it * c.knv : nullptr;
     for (int64_t i = (int64_t)v.k * kVecThreads + threadIdx.x; i < v.n;
          i += (int64_t)kVecBlocks * kVecThreads) {
         const int64_t e = v.base + i;
-        p[e] = c.first ? z[e] : z[e] + beta * p[e];
+        const double zv = z[e];
+        p[e] = c.first ? zv : zv + beta * p[e];
+        if (kz) kz[e] = zv;
     }
 }
 
@@ -283,6 +289,12 @@ PcgCtl batch_ctl(mm_plan_t pl) {
     c.ooff = pl->ooff.p;
     c.B = pl->n_prob;
     c.hstride = pl->hstride;
+    if (pl->krec.basis) {
+        c.krylov = pl->krec.basis;
+        c.alpha_hist = pl->krec.alpha;
+        c.kcap = pl->krec.cap;
+        c.knv = nvec(pl);
+    }
     return c;
 }
 

@@ -359,14 +359,16 @@ __global__ __launch_bounds__(256) void k_einv(const double* __restrict__ Einv,
     if (lane == 0) w[a] = s;
 }
 
-// z = M_BD (r - AZ w) + Z w per pixel of every masked problem, partials of r^T z
-template <typename TA, int NS>
+// z = M_BD (r - AZ w) + Z w per pixel of every masked problem, partials of r^T z.
+// DZ: Z is dense (Z_D blocks laid out like AZ, every Stokes row); else the sparse Z_S rows
+// (I rows only) in CSR form.
+template <typename TA, int NS, bool DZ>
 __global__ __launch_bounds__(kVecThreads) void k_2lvl(
     const double* __restrict__ r, double* __restrict__ z, const double* __restrict__ bj,
     const TA* __restrict__ az, const int64_t* __restrict__ az_off,
     const int32_t* __restrict__ col_off, const double* __restrict__ w,
     const int64_t* __restrict__ zptr, const int32_t* __restrict__ zcol,
-    const double* __restrict__ zval, PcgCtl ctl) {
+    const double* __restrict__ zval, const TA* __restrict__ zd, PcgCtl ctl) {
     __shared__ double red[kVecThreads];
     extern __shared__ double sw[];
     const VecBlock vb = vec_block(ctl, NS, false);
@@ -380,14 +382,22 @@ __global__ __launch_bounds__(kVecThreads) void k_2lvl(
     for (int64_t q = (int64_t)vb.k * kVecThreads + threadIdx.x; q < vb.n;
          q += (int64_t)kVecBlocks * kVecThreads) {
         const int64_t p = vb.base + q;
-        double u[NS];
+        double u[NS], zw[NS];
 #pragma unroll
-        for (int s = 0; s < NS; ++s) u[s] = r[p * NS + s];
+        for (int s = 0; s < NS; ++s) {
+            u[s] = r[p * NS + s];
+            zw[s] = 0.0;
+        }
         for (int32_t c = 0; c < rk; ++c) {
             const double wc = sw[c];
             const TA* col = azb + (int64_t)c * nv + q * NS;
 #pragma unroll
             for (int s = 0; s < NS; ++s) u[s] -= (double)col[s] * wc;
+            if constexpr (DZ) {
+                const TA* zc = zd + az_off[vb.b] + (int64_t)c * nv + q * NS;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) zw[s] += (double)zc[s] * wc;
+            }
         }
         double zz[NS];
         if constexpr (NS == 1) {
@@ -398,9 +408,13 @@ __global__ __launch_bounds__(kVecThreads) void k_2lvl(
             zz[1] = m[1] * u[0] + m[3] * u[1] + m[4] * u[2];
             zz[2] = m[2] * u[0] + m[4] * u[1] + m[5] * u[2];
         }
-        double zw = 0.0;
-        for (int64_t e = zptr[p]; e < zptr[p + 1]; ++e) zw += zval[e] * sw[zcol[e] - c0];
-        zz[0] += zw;
+        if constexpr (DZ) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) zz[s] += zw[s];
+        } else {
+            for (int64_t e = zptr[p]; e < zptr[p + 1]; ++e) zw[0] += zval[e] * sw[zcol[e] - c0];
+            zz[0] += zw[0];
+        }
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             z[p * NS + s] = zz[s];
@@ -408,6 +422,100 @@ __global__ __launch_bounds__(kVecThreads) void k_2lvl(
         }
     }
     if (ctl.part) write_partial_at(acc, slot_part(ctl, kSlotRZ, vb.b), vb.k, red);
+}
+
+// ---------------------------------------------------------------- dense Z_D
+// Z_D columns [c0, c0 + 16) of one problem (c0 = 16 blockIdx.y): out[c][e] =
+// sum_k basis[k][v0 + e] G[k][c], k < m, for its n vector entries e
+template <typename TA>
+__global__ __launch_bounds__(256) void k_ritz_vectors(const double* __restrict__ basis,
+                                                      int64_t stride, int64_t v0, int64_t n,
+                                                      int32_t m, const double* __restrict__ G,
+                                                      int32_t r, TA* __restrict__ out) {
+    const int32_t c0 = blockIdx.y * 16;
+    const int32_t nc = min(16, r - c0);
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        double acc[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc[j] = 0.0;
+        const double* bp = basis + v0 + e;
+        for (int32_t k = 0; k < m; ++k) {
+            const double v = bp[(int64_t)k * stride];
+            const double* g = G + (int64_t)k * r + c0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                if (j < nc) acc[j] = fma(v, g[j], acc[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+            if (j < nc) out[(int64_t)(c0 + j) * n + e] = (TA)acc[j];
+    }
+}
+
+__global__ void k_f32_to_f64(const float* __restrict__ a, double* __restrict__ b, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        b[i] = (double)a[i];
+}
+
+// column `col` of the dense block of problem lp[y] into its slice of a zeroed map vector
+template <typename TA>
+__global__ void k_zd_to_vec(const int32_t* __restrict__ lp, const TA* __restrict__ zd,
+                            const int64_t* __restrict__ ooff, int ns,
+                            const int64_t* __restrict__ blk_off, int32_t col,
+                            double* __restrict__ out) {
+    const int32_t b = lp[blockIdx.y];
+    const int64_t v0 = ooff[b] * ns, n = (ooff[b + 1] - ooff[b]) * ns;
+    const TA* src = zd + blk_off[b] + (int64_t)col * n;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[v0 + i] = (double)src[i];
+}
+
+// column-major [r][n] block -> row-major [npad][rp] FP64 (rows past n and columns past r
+// are left as they are: zeroed by the caller)
+template <typename TA>
+__global__ void k_cols_to_rows(const TA* __restrict__ src, int64_t n, int32_t r, int32_t rp,
+                               double* __restrict__ dst) {
+    const int32_t c = blockIdx.y;
+    if (c >= r) return;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x)
+        dst[e * rp + c] = (double)src[(int64_t)c * n + e];
+}
+
+// v = Z_D^T r: kept column c owns the slices [vslice[c], vslice[c+1]) of 512 entries of its
+// dense block; one wave per slice writes its partial sum to vpart[slice]
+template <typename TA>
+__global__ __launch_bounds__(256) void k_ztr_dense(const TA* __restrict__ zd,
+                                                   const int64_t* __restrict__ blk_off,
+                                                   const int32_t* __restrict__ col_off,
+                                                   const int32_t* __restrict__ col_prob,
+                                                   const int64_t* __restrict__ ooff, int ns,
+                                                   const double* __restrict__ r, int32_t rk,
+                                                   const int32_t* __restrict__ vslice,
+                                                   int64_t n_slices, double* __restrict__ vpart,
+                                                   const int* __restrict__ mask) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wv = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wv >= n_slices) return;
+    int32_t lo = 0, hi = rk - 1;
+    while (lo < hi) {
+        const int32_t m = (lo + hi + 1) >> 1;
+        if (vslice[m] <= wv) lo = m; else hi = m - 1;
+    }
+    const int32_t c = lo;
+    const int32_t b = col_prob[c];
+    if (mask && !mask[b]) return;
+    const int64_t v0 = ooff[b] * ns, n = (ooff[b + 1] - ooff[b]) * ns;
+    const TA* zc = zd + blk_off[b] + (int64_t)(c - col_off[b]) * n;
+    const int64_t a = (wv - vslice[c]) * 512;
+    const int64_t e_end = a + 512 < n ? a + 512 : n;
+    double s = 0.0;
+    for (int64_t e = a + lane; e < e_end; e += 64) s += (double)zc[e] * r[v0 + e];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) vpart[wv] = s;
 }
 
 // pivoted Cholesky of a symmetric PSD matrix: indices of a maximal set of columns whose
@@ -874,12 +982,369 @@ int build_coarse(mm_plan_t pl) {
     MM_TRY(co.vpart.alloc(co.n_slices));
     MM_HIP(hipStreamSynchronize(st));
     tick("csr");
+    co.kind = 1;
     pl->has_coarse = true;
     return MM_OK;
 }
 
+// Z_D [Sect. 3.3.2]: the selected Ritz vectors y = W s of every problem, stored densely
+// (all Stokes rows) in the layout of the AZ blocks, in the precision of AZ.  AZ_D follows
+// from one A application per column index (A is block diagonal over the problems), E_D =
+// Z_D^T AZ_D per problem on the matrix cores, and the pivoted Cholesky selection keeps an
+// independent subset (the Lanczos process in finite precision can return near-copies of a
+// converged Ritz vector).  Replaces the plan's coarse space.
+int build_coarse_dense(mm_plan_t pl, const double* basis, int64_t basis_stride,
+                       const std::vector<std::vector<double>>& G, const std::vector<int>& m,
+                       const std::vector<std::vector<double>>& theta) {
+    hipStream_t st = pl->stream;
+    const int B = pl->n_prob;
+    const int64_t ns = pl->n_s, nv = pl->n_obs * pl->n_s;
+    const std::vector<int64_t>& oo = pl->h_ooff;
+    const bool mixed = pl->opts.precision == MM_MIXED;
+    std::vector<int32_t> rb(B);
+    std::vector<int64_t> zoff(B + 1, 0), goff(B + 1, 0);
+    int32_t r_all = 0, r_max = 0;
+    for (int b = 0; b < B; ++b) {
+        rb[b] = (int32_t)theta[b].size();
+        zoff[b + 1] = zoff[b] + (int64_t)rb[b] * (oo[b + 1] - oo[b]) * ns;
+        goff[b + 1] = goff[b] + (int64_t)m[b] * rb[b];
+        r_all += rb[b];
+        r_max = std::max(r_max, rb[b]);
+    }
+    if (r_all == 0) {
+        set_error("no Ritz value below eps_tol: Z_D would be empty");
+        return MM_ERR_RANK;
+    }
+    DBuf<double> zd64, az64;
+    DBuf<float> zd32, az32;
+    if (mixed) {
+        MM_TRY(zd32.alloc((size_t)zoff[B]));
+        MM_TRY(az32.alloc((size_t)zoff[B]));
+    } else {
+        MM_TRY(zd64.alloc((size_t)zoff[B]));
+        MM_TRY(az64.alloc((size_t)zoff[B]));
+    }
+    {
+        std::vector<double> hg((size_t)std::max<int64_t>(1, goff[B]));
+        for (int b = 0; b < B; ++b) std::copy(G[b].begin(), G[b].end(), hg.begin() + goff[b]);
+        DBuf<double> dG;
+        MM_TRY(dG.alloc(hg.size()));
+        MM_HIP(hipMemcpyAsync(dG.p, hg.data(), hg.size() * 8, hipMemcpyHostToDevice, st));
+        for (int b = 0; b < B; ++b) {
+            if (rb[b] == 0) continue;
+            const int64_t nb = (oo[b + 1] - oo[b]) * ns;
+            const dim3 g(grid_for(nb, 256, 4096), (rb[b] + 15) / 16);
+            if (mixed)
+                hipLaunchKernelGGL(k_ritz_vectors<float>, g, dim3(256), 0, st, basis, basis_stride,
+                                   oo[b] * ns, nb, m[b], (const double*)dG.p + goff[b], rb[b],
+                                   zd32.p + zoff[b]);
+            else
+                hipLaunchKernelGGL(k_ritz_vectors<double>, g, dim3(256), 0, st, basis,
+                                   basis_stride, oo[b] * ns, nb, m[b],
+                                   (const double*)dG.p + goff[b], rb[b], zd64.p + zoff[b]);
+            MM_HIP(hipGetLastError());
+        }
+        MM_HIP(hipStreamSynchronize(st));
+    }
+    // AZ_D, one A application per column index over all problems
+    {
+        DBuf<int64_t> dzoff;
+        DBuf<int32_t> lprob;
+        DBuf<double> x, y;
+        MM_TRY(dzoff.alloc(B + 1));
+        MM_TRY(lprob.alloc((size_t)r_max * B));
+        MM_TRY(x.alloc(nv));
+        MM_TRY(y.alloc(nv));
+        MM_HIP(hipMemcpyAsync(dzoff.p, zoff.data(), (B + 1) * 8, hipMemcpyHostToDevice, st));
+        std::vector<int32_t> hp;
+        std::vector<int32_t> lcnt(r_max, 0);
+        for (int32_t k = 0; k < r_max; ++k)
+            for (int b = 0; b < B; ++b)
+                if (k < rb[b]) {
+                    hp.push_back(b);
+                    lcnt[k]++;
+                }
+        MM_HIP(hipMemcpyAsync(lprob.p, hp.data(), hp.size() * 4, hipMemcpyHostToDevice, st));
+        int64_t nb_max = 1;
+        for (int b = 0; b < B; ++b) nb_max = std::max<int64_t>(nb_max, (oo[b + 1] - oo[b]) * ns);
+        const int sgx = (int)std::min<int64_t>(1024, (nb_max + 255) / 256);
+        int64_t lo = 0;
+        for (int32_t k = 0; k < r_max; ++k) {
+            const dim3 g(sgx, lcnt[k]);
+            MM_HIP(hipMemsetAsync(x.p, 0, nv * 8, st));
+            if (mixed) {
+                hipLaunchKernelGGL(k_zd_to_vec<float>, g, dim3(256), 0, st, lprob.p + lo,
+                                   (const float*)zd32.p, pl->ooff.p, (int)ns,
+                                   (const int64_t*)dzoff.p, k, x.p);
+                MM_HIP(hipGetLastError());
+                MM_TRY(apply_A32_sparse(pl, x.p, y.p));
+                hipLaunchKernelGGL(k_store_az<float>, g, dim3(256), 0, st, lprob.p + lo,
+                                   (const double*)y.p, pl->ooff.p, (int)ns,
+                                   (const int64_t*)dzoff.p, k, az32.p);
+            } else {
+                hipLaunchKernelGGL(k_zd_to_vec<double>, g, dim3(256), 0, st, lprob.p + lo,
+                                   (const double*)zd64.p, pl->ooff.p, (int)ns,
+                                   (const int64_t*)dzoff.p, k, x.p);
+                MM_HIP(hipGetLastError());
+                MM_TRY(apply_A64_sparse(pl, x.p, y.p));
+                hipLaunchKernelGGL(k_store_az<double>, g, dim3(256), 0, st, lprob.p + lo,
+                                   (const double*)y.p, pl->ooff.p, (int)ns,
+                                   (const int64_t*)dzoff.p, k, az64.p);
+            }
+            MM_HIP(hipGetLastError());
+            lo += lcnt[k];
+        }
+        MM_HIP(hipStreamSynchronize(st));
+    }
+    // E_b = Z_b^T AZ_b, independent subset, E_b^-1
+    int64_t npad_max = 4;
+    for (int b = 0; b < B; ++b)
+        npad_max = std::max<int64_t>(npad_max, ((oo[b + 1] - oo[b]) * ns + 3) / 4 * 4);
+    const int32_t rp_max = (r_max + 15) / 16 * 16;
+    std::vector<std::vector<int>> sels(B);
+    std::vector<int32_t> col_off(B + 1, 0), cols;
+    std::vector<int64_t> az_off(B + 1, 0), einv_off(B + 1, 0);
+    std::vector<double> Eall, Einv_all, ritz;
+    int32_t keep_max = 0;
+    {
+        DBuf<double> zr, azr, dE;
+        MM_TRY(zr.alloc((size_t)npad_max * rp_max));
+        MM_TRY(azr.alloc((size_t)npad_max * rp_max));
+        MM_TRY(dE.alloc((size_t)rp_max * rp_max));
+        for (int b = 0; b < B; ++b) {
+            const int32_t r = rb[b];
+            const int64_t nb = (oo[b + 1] - oo[b]) * ns;
+            if (r > 0) {
+                const int32_t rp = (r + 15) / 16 * 16;
+                const int64_t npad = (nb + 3) / 4 * 4;
+                MM_HIP(hipMemsetAsync(zr.p, 0, (size_t)npad * rp * 8, st));
+                MM_HIP(hipMemsetAsync(azr.p, 0, (size_t)npad * rp * 8, st));
+                const dim3 g(grid_for(nb, 256, 4096), r);
+                if (mixed) {
+                    hipLaunchKernelGGL(k_cols_to_rows<float>, g, dim3(256), 0, st,
+                                       (const float*)zd32.p + zoff[b], nb, r, rp, zr.p);
+                    hipLaunchKernelGGL(k_cols_to_rows<float>, g, dim3(256), 0, st,
+                                       (const float*)az32.p + zoff[b], nb, r, rp, azr.p);
+                } else {
+                    hipLaunchKernelGGL(k_cols_to_rows<double>, g, dim3(256), 0, st,
+                                       (const double*)zd64.p + zoff[b], nb, r, rp, zr.p);
+                    hipLaunchKernelGGL(k_cols_to_rows<double>, g, dim3(256), 0, st,
+                                       (const double*)az64.p + zoff[b], nb, r, rp, azr.p);
+                }
+                MM_HIP(hipGetLastError());
+                MM_TRY(gemm_tn_f64(st, zr.p, azr.p, npad, rp, rp, dE.p));
+                std::vector<double> Ep((size_t)rp * rp);
+                MM_HIP(hipMemcpy(Ep.data(), dE.p, Ep.size() * 8, hipMemcpyDeviceToHost));
+                std::vector<double> E((size_t)r * r);
+                for (int32_t i = 0; i < r; ++i)
+                    for (int32_t j = 0; j < r; ++j)
+                        E[(size_t)i * r + j] = 0.5 * (Ep[(size_t)i * rp + j] + Ep[(size_t)j * rp + i]);
+                sels[b] = pivoted_cholesky_select(E, r, pl->opts.rank_tol);
+                const int32_t k = (int32_t)sels[b].size();
+                if (k == 0) {
+                    set_error("coarse matrix E_D of problem %d is zero", b);
+                    return MM_ERR_RANK;
+                }
+                std::vector<double> Es((size_t)k * k), Einv;
+                for (int32_t i = 0; i < k; ++i)
+                    for (int32_t j = 0; j < k; ++j)
+                        Es[(size_t)i * k + j] = E[(size_t)sels[b][i] * r + sels[b][j]];
+                if (!spd_inverse(Es, k, Einv)) {
+                    set_error("coarse matrix E_D of problem %d not positive definite on the "
+                              "selected columns", b);
+                    return MM_ERR_RANK;
+                }
+                Eall.insert(Eall.end(), Es.begin(), Es.end());
+                Einv_all.insert(Einv_all.end(), Einv.begin(), Einv.end());
+                for (int32_t i = 0; i < k; ++i) {
+                    cols.push_back(sels[b][i]);
+                    ritz.push_back(theta[b][sels[b][i]]);
+                }
+                keep_max = std::max(keep_max, k);
+            }
+            const int32_t k = (int32_t)sels[b].size();
+            col_off[b + 1] = col_off[b] + k;
+            einv_off[b + 1] = einv_off[b] + (int64_t)k * k;
+            az_off[b + 1] = az_off[b] + (int64_t)k * nb;
+        }
+    }
+    const int32_t keff = col_off[B];
+    // kept columns of Z_D and AZ_D into the final blocks
+    DBuf<double> fz64, faz64;
+    DBuf<float> fz32, faz32;
+    {
+        std::vector<int64_t> so(keff), d_o(keff), cn(keff);
+        for (int b = 0; b < B; ++b) {
+            const int64_t nb = (oo[b + 1] - oo[b]) * ns;
+            for (size_t i = 0; i < sels[b].size(); ++i) {
+                const int32_t a = col_off[b] + (int32_t)i;
+                so[a] = zoff[b] + (int64_t)sels[b][i] * nb;
+                d_o[a] = az_off[b] + (int64_t)i * nb;
+                cn[a] = nb;
+            }
+        }
+        DBuf<int64_t> dso, ddo, dcn;
+        MM_TRY(dso.alloc(keff));
+        MM_TRY(ddo.alloc(keff));
+        MM_TRY(dcn.alloc(keff));
+        MM_HIP(hipMemcpyAsync(dso.p, so.data(), keff * 8, hipMemcpyHostToDevice, st));
+        MM_HIP(hipMemcpyAsync(ddo.p, d_o.data(), keff * 8, hipMemcpyHostToDevice, st));
+        MM_HIP(hipMemcpyAsync(dcn.p, cn.data(), keff * 8, hipMemcpyHostToDevice, st));
+        const dim3 g(64, keff);
+        if (mixed) {
+            MM_TRY(fz32.alloc((size_t)az_off[B]));
+            MM_TRY(faz32.alloc((size_t)az_off[B]));
+            hipLaunchKernelGGL(k_copy_cols<float>, g, dim3(256), 0, st, (const float*)zd32.p,
+                               fz32.p, (const int64_t*)dso.p, (const int64_t*)ddo.p,
+                               (const int64_t*)dcn.p);
+            hipLaunchKernelGGL(k_copy_cols<float>, g, dim3(256), 0, st, (const float*)az32.p,
+                               faz32.p, (const int64_t*)dso.p, (const int64_t*)ddo.p,
+                               (const int64_t*)dcn.p);
+        } else {
+            MM_TRY(fz64.alloc((size_t)az_off[B]));
+            MM_TRY(faz64.alloc((size_t)az_off[B]));
+            hipLaunchKernelGGL(k_copy_cols<double>, g, dim3(256), 0, st, (const double*)zd64.p,
+                               fz64.p, (const int64_t*)dso.p, (const int64_t*)ddo.p,
+                               (const int64_t*)dcn.p);
+            hipLaunchKernelGGL(k_copy_cols<double>, g, dim3(256), 0, st, (const double*)az64.p,
+                               faz64.p, (const int64_t*)dso.p, (const int64_t*)ddo.p,
+                               (const int64_t*)dcn.p);
+        }
+        MM_HIP(hipGetLastError());
+        MM_HIP(hipStreamSynchronize(st));
+    }
+    // Z^T r slices and the per-column tables
+    std::vector<int32_t> vs(keff + 1, 0), cprob(keff);
+    for (int b = 0; b < B; ++b) {
+        const int64_t nb = (oo[b + 1] - oo[b]) * ns;
+        for (int32_t a = col_off[b]; a < col_off[b + 1]; ++a) {
+            cprob[a] = b;
+            vs[a + 1] = vs[a] + (int32_t)((nb + 511) / 512);
+        }
+    }
+    DBuf<int32_t> d_vs, d_cprob, d_coloff;
+    DBuf<int64_t> d_azoff, d_einvoff;
+    DBuf<double> d_einv, d_w, d_vpart;
+    MM_TRY(d_vs.alloc(keff + 1));
+    MM_TRY(d_cprob.alloc(keff));
+    MM_TRY(d_coloff.alloc(B + 1));
+    MM_TRY(d_azoff.alloc(B + 1));
+    MM_TRY(d_einvoff.alloc(B + 1));
+    MM_TRY(d_einv.alloc(Einv_all.size()));
+    MM_TRY(d_w.alloc(keff));
+    MM_TRY(d_vpart.alloc(vs[keff]));
+    MM_HIP(hipMemcpyAsync(d_vs.p, vs.data(), (keff + 1) * 4, hipMemcpyHostToDevice, st));
+    MM_HIP(hipMemcpyAsync(d_cprob.p, cprob.data(), keff * 4, hipMemcpyHostToDevice, st));
+    MM_HIP(hipMemcpyAsync(d_coloff.p, col_off.data(), (B + 1) * 4, hipMemcpyHostToDevice, st));
+    MM_HIP(hipMemcpyAsync(d_azoff.p, az_off.data(), (B + 1) * 8, hipMemcpyHostToDevice, st));
+    MM_HIP(hipMemcpyAsync(d_einvoff.p, einv_off.data(), (B + 1) * 8, hipMemcpyHostToDevice, st));
+    MM_HIP(hipMemcpyAsync(d_einv.p, Einv_all.data(), Einv_all.size() * 8, hipMemcpyHostToDevice,
+                          st));
+    MM_HIP(hipStreamSynchronize(st));
+    // install (captured iterations hold the old coarse-space pointers)
+    drop_graphs(pl);
+    Coarse& co = pl->co;
+    co.kind = 2;
+    co.r_dedup = r_all;
+    co.r_eff = keff;
+    co.r_max = keep_max;
+    co.cols = std::move(cols);
+    co.ritz = std::move(ritz);
+    co.h_col_off = col_off;
+    co.h_az_off = az_off;
+    co.h_einv_off = einv_off;
+    co.E = std::move(Eall);
+    co.col_off.swap(d_coloff);
+    co.col_prob.swap(d_cprob);
+    co.az_off.swap(d_azoff);
+    co.einv_off.swap(d_einvoff);
+    co.Einv.swap(d_einv);
+    co.w.swap(d_w);
+    co.vslice.swap(d_vs);
+    co.vpart.swap(d_vpart);
+    co.n_slices = vs[keff];
+    co.AZ64.swap(faz64);
+    co.AZ32.swap(faz32);
+    co.ZD64.swap(fz64);
+    co.ZD32.swap(fz32);
+    co.csr_ptr.release();
+    co.csr_col.release();
+    co.csr_val.release();
+    co.csc_beg.release();
+    co.csc_end.release();
+    co.csc_row.release();
+    co.csc_val.release();
+    pl->has_coarse = true;
+    return MM_OK;
+}
+
+// the kept Z_D blocks in FP64 (the layout of AZ)
+int coarse_dense_columns(mm_plan_t pl, double* out) {
+    Coarse& co = pl->co;
+    const int64_t n = co.h_az_off[pl->n_prob];
+    hipStream_t st = pl->stream;
+    if (co.ZD64.p) {
+        MM_HIP(hipMemcpyAsync(out, co.ZD64.p, n * 8, hipMemcpyDeviceToDevice, st));
+    } else {
+        hipLaunchKernelGGL(k_f32_to_f64, dim3(grid_for(n)), dim3(256), 0, st,
+                           (const float*)co.ZD32.p, out, n);
+        MM_HIP(hipGetLastError());
+    }
+    MM_HIP(hipStreamSynchronize(st));
+    return MM_OK;
+}
+
+namespace {
+
+int twolvl_apply_dense(mm_plan_t pl, const double* r, double* z, const PcgCtl& ctl) {
+    Coarse& co = pl->co;
+    hipStream_t st = pl->stream;
+    const int32_t k = co.r_eff;
+    const int ns = pl->n_s;
+    const dim3 gs((unsigned)((co.n_slices + 3) / 4)), t256(256);
+    if (co.ZD32.p)
+        hipLaunchKernelGGL(k_ztr_dense<float>, gs, t256, 0, st, (const float*)co.ZD32.p,
+                           co.az_off.p, co.col_off.p, co.col_prob.p, pl->ooff.p, ns, r, k,
+                           co.vslice.p, co.n_slices, co.vpart.p, ctl.mask);
+    else
+        hipLaunchKernelGGL(k_ztr_dense<double>, gs, t256, 0, st, (const double*)co.ZD64.p,
+                           co.az_off.p, co.col_off.p, co.col_prob.p, pl->ooff.p, ns, r, k,
+                           co.vslice.p, co.n_slices, co.vpart.p, ctl.mask);
+    hipLaunchKernelGGL(k_einv, dim3((k + 3) / 4), dim3(256), 0, st, co.Einv.p, co.einv_off.p,
+                       co.col_off.p, co.col_prob.p, co.vpart.p, co.vslice.p, k, co.w.p, ctl.mask);
+    const size_t shm = (size_t)co.r_max * sizeof(double);
+    const dim3 g(pl->n_pblk), t(kVecThreads);
+    const int64_t* np64 = nullptr;
+    const int32_t* np32 = nullptr;
+    const double* npd = nullptr;
+    if (ns == 3) {
+        if (co.AZ32.p)
+            hipLaunchKernelGGL((k_2lvl<float, 3, true>), g, t, shm, st, r, z, pl->bj.p, co.AZ32.p,
+                               co.az_off.p, co.col_off.p, co.w.p, np64, np32, npd,
+                               (const float*)co.ZD32.p, ctl);
+        else
+            hipLaunchKernelGGL((k_2lvl<double, 3, true>), g, t, shm, st, r, z, pl->bj.p,
+                               co.AZ64.p, co.az_off.p, co.col_off.p, co.w.p, np64, np32, npd,
+                               (const double*)co.ZD64.p, ctl);
+    } else {
+        if (co.AZ32.p)
+            hipLaunchKernelGGL((k_2lvl<float, 1, true>), g, t, shm, st, r, z, pl->bj.p, co.AZ32.p,
+                               co.az_off.p, co.col_off.p, co.w.p, np64, np32, npd,
+                               (const float*)co.ZD32.p, ctl);
+        else
+            hipLaunchKernelGGL((k_2lvl<double, 1, true>), g, t, shm, st, r, z, pl->bj.p,
+                               co.AZ64.p, co.az_off.p, co.col_off.p, co.w.p, np64, np32, npd,
+                               (const double*)co.ZD64.p, ctl);
+    }
+    MM_HIP(hipGetLastError());
+    return MM_OK;
+}
+
+}  // namespace
+
 int twolvl_apply(mm_plan_t pl, const double* r, double* z, const PcgCtl& ctl) {
     Coarse& co = pl->co;
+    if (co.kind == 2) return twolvl_apply_dense(pl, r, z, ctl);
     hipStream_t st = pl->stream;
     const int32_t k = co.r_eff;
     hipLaunchKernelGGL(k_ztr, dim3((co.n_slices + 3) / 4), dim3(256), 0, st, co.csc_beg.p,
@@ -891,22 +1356,22 @@ int twolvl_apply(mm_plan_t pl, const double* r, double* z, const PcgCtl& ctl) {
     const dim3 g(pl->n_pblk), t(kVecThreads);
     if (pl->n_s == 3) {
         if (co.AZ32.p)
-            hipLaunchKernelGGL((k_2lvl<float, 3>), g, t, shm, st, r, z, pl->bj.p, co.AZ32.p,
+            hipLaunchKernelGGL((k_2lvl<float, 3, false>), g, t, shm, st, r, z, pl->bj.p, co.AZ32.p,
                                co.az_off.p, co.col_off.p, co.w.p, co.csr_ptr.p, co.csr_col.p,
-                               co.csr_val.p, ctl);
+                               co.csr_val.p, (const float*)nullptr, ctl);
         else
-            hipLaunchKernelGGL((k_2lvl<double, 3>), g, t, shm, st, r, z, pl->bj.p, co.AZ64.p,
+            hipLaunchKernelGGL((k_2lvl<double, 3, false>), g, t, shm, st, r, z, pl->bj.p, co.AZ64.p,
                                co.az_off.p, co.col_off.p, co.w.p, co.csr_ptr.p, co.csr_col.p,
-                               co.csr_val.p, ctl);
+                               co.csr_val.p, (const double*)nullptr, ctl);
     } else {
         if (co.AZ32.p)
-            hipLaunchKernelGGL((k_2lvl<float, 1>), g, t, shm, st, r, z, pl->bj.p, co.AZ32.p,
+            hipLaunchKernelGGL((k_2lvl<float, 1, false>), g, t, shm, st, r, z, pl->bj.p, co.AZ32.p,
                                co.az_off.p, co.col_off.p, co.w.p, co.csr_ptr.p, co.csr_col.p,
-                               co.csr_val.p, ctl);
+                               co.csr_val.p, (const float*)nullptr, ctl);
         else
-            hipLaunchKernelGGL((k_2lvl<double, 1>), g, t, shm, st, r, z, pl->bj.p, co.AZ64.p,
+            hipLaunchKernelGGL((k_2lvl<double, 1, false>), g, t, shm, st, r, z, pl->bj.p, co.AZ64.p,
                                co.az_off.p, co.col_off.p, co.w.p, co.csr_ptr.p, co.csr_col.p,
-                               co.csr_val.p, ctl);
+                               co.csr_val.p, (const double*)nullptr, ctl);
     }
     MM_HIP(hipGetLastError());
     return MM_OK;

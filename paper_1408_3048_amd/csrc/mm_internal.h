@@ -142,6 +142,13 @@ struct PcgCtl {
     int replace = 1;             // recursive convergence triggers a true-residual evaluation
     int max_iter = 0;
     double replace_ratio = 0.0;  // > 0: also evaluate when ||r|| fell by this factor
+    // Krylov recording (nullptr: off): z of iteration k of every problem into
+    // krylov[k * knv + element] for k < kcap, and the step length of iteration k into
+    // alpha_hist[b * hstride + k]
+    double* krylov = nullptr;
+    double* alpha_hist = nullptr;
+    int64_t knv = 0;
+    int kcap = 0;
 };
 
 // Coarse space, block diagonal over the problems of a batch: problem b keeps the columns
@@ -149,10 +156,13 @@ struct PcgCtl {
 // [r_b][n_b] column-major at az_off[b] (n_b = n_s * its pixels) and its E^-1 block is
 // r_b x r_b row-major at einv_off[b].
 struct Coarse {
+    int kind = 0;                    // 0 none, 1 Z_S (sparse, I rows), 2 Z_D (dense Ritz vectors)
     int r_dedup = 0;                 // columns after removing duplicates (all problems)
     int r_eff = 0;                   // columns kept (independent), all problems
     int r_max = 0;                   // largest r_b
-    std::vector<int32_t> cols;       // interval index of every kept column
+    std::vector<int32_t> cols;       // Z_S: interval of every kept column; Z_D: index of its
+                                     // Ritz value among the problem's ascending Ritz values
+    std::vector<double> ritz;        // Z_D: Ritz value of every kept column
     std::vector<int32_t> h_col_off;  // [B+1]
     std::vector<int64_t> h_az_off;   // [B+1]
     std::vector<int64_t> h_einv_off; // [B+1]
@@ -168,6 +178,8 @@ struct Coarse {
     DBuf<double> csc_val;
     DBuf<double> AZ64;               // AZ blocks (FP64 plans)
     DBuf<float> AZ32;                // same (mixed plans)
+    DBuf<double> ZD64;               // Z_D blocks, same layout as AZ (FP64 plans)
+    DBuf<float> ZD32;                // same (mixed plans)
     DBuf<double> Einv;               // E^-1 blocks
     DBuf<double> w;                  // coarse solution [r_eff]
     DBuf<int32_t> vslice;            // [r_eff+1] first Z^T r slice of every kept column
@@ -243,6 +255,12 @@ struct mm_plan_s {
     mm::DBuf<double> hist;              // residual history [B][hstride]
     mm::DBuf<double> rz_hist;           // r^T z per iteration [B][hstride]
     int hstride = 0;
+    // Krylov recording of a solve (set only while mm_coarse_from_krylov runs)
+    struct KrylovRec {
+        double* basis = nullptr;        // [cap][n_obs * n_s]
+        double* alpha = nullptr;        // [B][hstride]
+        int cap = 0;
+    } krec;
     // captured PCG iteration (one per operator precision / preconditioner)
     hipStream_t gstream = nullptr;      // non-blocking stream the graphs are captured on
     hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
@@ -315,7 +333,23 @@ int bj_apply(mm_plan_t pl, const double* r, double* z, const PcgCtl& ctl);
 
 // ---- coarse.hip
 int build_coarse(mm_plan_t pl);
+// Z_D [Sect. 3.3.2]: column i of problem b is sum_k basis[k][problem b's slice] G_b[k][i]
+// (G_b row-major [m_b][r_b]); replaces the plan's coarse space with Z_D, its AZ and E^-1
+int build_coarse_dense(mm_plan_t pl, const double* basis, int64_t basis_stride,
+                       const std::vector<std::vector<double>>& G, const std::vector<int>& m,
+                       const std::vector<std::vector<double>>& theta);
 int twolvl_apply(mm_plan_t pl, const double* r, double* z, const PcgCtl& ctl);
+// the kept Z_D blocks, FP64, into out (h_az_off[B] values)
+int coarse_dense_columns(mm_plan_t pl, double* out);
+
+// ---- krylov.hip
+// Ritz pairs of the Lanczos matrix that m PCG steps (step lengths alpha[0..m), r^T z
+// products rz[0..m)) build implicitly: the eigenvalues theta below eps_tol, ascending (at
+// most max_cols of them, max_cols <= 0: no cap), and their unit eigenvectors, S row-major
+// [m][r]
+int ritz_select(const double* alpha, const double* rz, int m, double eps_tol, int max_cols,
+                std::vector<double>& theta, std::vector<double>& S);
+void drop_graphs(mm_plan_t pl);
 
 // ---- blas.hip (per-problem vector kernels; ctl supplies the batch layout and mask)
 int build_batch_layout(mm_plan_t pl);
