@@ -142,6 +142,52 @@ def batched_leg(tol, warmup=1):
     return res
 
 
+def multi_rhs_leg(pix, w, sc, psd, m, noise, tol, n_rhs, autotune, krylov_dim=256):
+    """One plan, n_rhs right-hand sides (the same sky with the noise timeline rolled by a
+    different offset each time): plan time once, then the mean solve time per RHS, for the
+    mixed two-level solver with Z_S, the mixed two-level solver with the a posteriori Z_D
+    (built from the FP64 block-Jacobi solve of the first RHS, which that solve's time
+    includes), the mixed block-Jacobi and the FP64 block-Jacobi solvers."""
+    import torch
+    from paper_1408_3048_amd import Plan
+    out = {}
+    kw = dict(n_stokes=3, lam=sc.lam, f_samp=sc.f_samp, autotune=autotune)
+    for name, precision, coarse, precond in (("mixed_2lvl", "mixed", True, "2lvl"),
+                                             ("mixed_2lvl_zd", "mixed", False, "zd"),
+                                             ("mixed_bj", "mixed", False, "bj"),
+                                             ("fp64_bj", "fp64", False, "bj")):
+        torch.cuda.synchronize()
+        plan = Plan(pix, w, sc.n_pix, sc.offsets, psd, precision=precision, coarse=coarse, **kw)
+        sig = plan.apply_P(m)
+        times, its, extra = [], [], {}
+        for k in range(n_rhs):
+            d = sig + torch.roll(noise, shifts=1 + 7919 * k)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if precond == "zd" and k == 0:
+                x, info = plan.coarse_from_krylov(plan.rhs(d), tol=tol, max_iter=5000,
+                                                  krylov_dim=krylov_dim, eps_tol=0.2,
+                                                  history=False)
+            else:
+                x, info = plan.pcg_solve(plan.rhs(d), precond="2lvl" if precond == "zd" else precond,
+                                         precision=precision, tol=tol, max_iter=5000, history=False)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            its.append(info["iterations"])
+            if precond == "zd" and k == 0:
+                extra = dict(first_rhs_fp64_bj_and_zd_build_ms=1e3 * times[0],
+                             first_rhs_iterations=info["iterations"], zd_rank=plan.coarse_rank(),
+                             ritz_min=float(plan.ritz_values().min()), krylov_dim=krylov_dim)
+        rest = its[1:] if precond == "zd" else its
+        out[name] = dict(plan_ms=plan.plan_ms, solve_ms_mean=1e3 * float(np.mean(times[1:] or times)),
+                         iterations_mean=float(np.mean(rest or its)), n_rhs=n_rhs,
+                         ms_per_rhs_incl_plan=(plan.plan_ms + 1e3 * float(np.sum(times))) / n_rhs,
+                         **extra)
+        log(f"multi-rhs {name}: {out[name]}")
+        plan.close()
+    return out
+
+
 def kernel_traffic(name):
     """HBM bytes per launch of a kernel from the stored counter figures, or None when its
     source has changed since they were taken."""
@@ -183,6 +229,8 @@ def main():
     ap.add_argument("--no-reference", action="store_true", help="skip the FP64 block-Jacobi leg")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 256-problem batched Monte Carlo leg")
+    ap.add_argument("--multi-rhs", type=int, default=8,
+                    help="right-hand sides of the plan-reuse leg (0 skips it)")
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: FFT tile lengths picked by timing at plan time (cached per process)")
     ap.add_argument("--fft-len-f32", type=int, default=0,
@@ -327,6 +375,11 @@ def main():
     roof["other_kernels"] = {k: dict(launches=v[0], avg_ms=v[1] / max(v[0], 1))
                              for k, v in prof.items() if v[0] > 0}
 
+    multi = None
+    if args.multi_rhs > 0 and not args.no_reference:
+        multi = multi_rhs_leg(pix, w, sc, psd, m, torch.from_numpy(sc.noise).cuda(), args.tol,
+                              args.multi_rhs, bool(args.autotune))
+
     batched = None
     if not args.no_batched:
         batched = batched_leg(args.tol)
@@ -349,7 +402,8 @@ def main():
                               "lambda=2048, mixed FP32/FP64 two-level PCG to 1e-8 incl. plan"),
                     n_samples=sc.n_samples, unknowns=extras[-1]["unknowns"],
                     tol=args.tol, parallelism="single GPU"),
-        breakdown=extras[-1], reference=ref, other_legs=legs, batched=batched, roofline=roof,
+        breakdown=extras[-1], reference=ref, other_legs=legs, multi_rhs=multi, batched=batched,
+        roofline=roof,
         cpu_baseline=cpu,
     )
     print(json.dumps(out), flush=True)

@@ -485,37 +485,109 @@ __global__ void k_cols_to_rows(const TA* __restrict__ src, int64_t n, int32_t r,
         dst[e * rp + c] = (double)src[(int64_t)c * n + e];
 }
 
-// v = Z_D^T r: kept column c owns the slices [vslice[c], vslice[c+1]) of 512 entries of its
-// dense block; one wave per slice writes its partial sum to vpart[slice]
+// v = Z_D^T r, first stage: block g takes the chunk [ch*kZtChunk, +kZtChunk) of its
+// problem's vector (ch = g - ch_off[b]) and writes the chunk's partial sum of every kept
+// column i of the problem to cpart[i * n_ch + g] (r and every column read once,
+// coalesced; fixed reduction order)
+constexpr int kZtChunk = 1024;
 template <typename TA>
-__global__ __launch_bounds__(256) void k_ztr_dense(const TA* __restrict__ zd,
-                                                   const int64_t* __restrict__ blk_off,
-                                                   const int32_t* __restrict__ col_off,
-                                                   const int32_t* __restrict__ col_prob,
-                                                   const int64_t* __restrict__ ooff, int ns,
-                                                   const double* __restrict__ r, int32_t rk,
-                                                   const int32_t* __restrict__ vslice,
-                                                   int64_t n_slices, double* __restrict__ vpart,
-                                                   const int* __restrict__ mask) {
-    const int lane = threadIdx.x & 63;
-    const int64_t wv = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (wv >= n_slices) return;
-    int32_t lo = 0, hi = rk - 1;
+__global__ __launch_bounds__(256) void k_ztr_chunks(const TA* __restrict__ zd,
+                                                    const int64_t* __restrict__ blk_off,
+                                                    const int32_t* __restrict__ col_off,
+                                                    const int64_t* __restrict__ ch_off, int B,
+                                                    const int64_t* __restrict__ ooff, int ns,
+                                                    const double* __restrict__ r, int32_t r_max,
+                                                    int64_t n_ch, double* __restrict__ cpart,
+                                                    const int* __restrict__ mask) {
+    extern __shared__ double red[];  // [4][r_max]
+    const int64_t g = blockIdx.x;
+    int lo = 0, hi = B - 1;  // problem: largest b with ch_off[b] <= g
     while (lo < hi) {
-        const int32_t m = (lo + hi + 1) >> 1;
-        if (vslice[m] <= wv) lo = m; else hi = m - 1;
+        const int m = (lo + hi + 1) >> 1;
+        if (ch_off[m] <= g) lo = m; else hi = m - 1;
     }
-    const int32_t c = lo;
-    const int32_t b = col_prob[c];
+    const int b = lo;
     if (mask && !mask[b]) return;
+    const int32_t rb = col_off[b + 1] - col_off[b];
     const int64_t v0 = ooff[b] * ns, n = (ooff[b + 1] - ooff[b]) * ns;
-    const TA* zc = zd + blk_off[b] + (int64_t)(c - col_off[b]) * n;
-    const int64_t a = (wv - vslice[c]) * 512;
-    const int64_t e_end = a + 512 < n ? a + 512 : n;
-    double s = 0.0;
-    for (int64_t e = a + lane; e < e_end; e += 64) s += (double)zc[e] * r[v0 + e];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0) vpart[wv] = s;
+    const int64_t e0 = (g - ch_off[b]) * kZtChunk;
+    constexpr int E = kZtChunk / 256;
+    // entries past the vector end read its last entry against r = 0, and columns past
+    // the last read the last column (their sums are not stored), so that the loads carry
+    // no branches and the eight columns of a step are in flight together
+    double rv[E];
+    int64_t ee[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+        const int64_t e = e0 + j * 256 + threadIdx.x;
+        rv[j] = e < n ? r[v0 + e] : 0.0;
+        ee[j] = e < n ? e : n - 1;
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const TA* zb = zd + blk_off[b];
+    for (int32_t c0 = 0; c0 < rb; c0 += 8) {
+        double acc[8];
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) {
+            const TA* zc = zb + (int64_t)min(c0 + cc, rb - 1) * n;
+            double a = 0.0;
+#pragma unroll
+            for (int j = 0; j < E; ++j) a = fma((double)zc[ee[j]], rv[j], a);
+            acc[cc] = a;
+        }
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) {
+            double a = acc[cc];
+            for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+            if (lane == 0 && c0 + cc < rb) red[wv * r_max + c0 + cc] = a;
+        }
+    }
+    __syncthreads();
+    for (int32_t c = threadIdx.x; c < rb; c += 256)
+        cpart[c * n_ch + g] = ((red[c] + red[r_max + c]) + red[2 * r_max + c]) + red[3 * r_max + c];
+}
+
+// second stage, one block per problem: v_i = sum of the chunk partials of column i (one
+// wave per column, four independent load streams per lane, fixed order) into LDS, then
+// w = E^-1 v
+constexpr int kCsThreads = 1024;
+__global__ __launch_bounds__(kCsThreads) void k_coarse_solve(const double* __restrict__ cpart,
+                                                      const int64_t* __restrict__ ch_off,
+                                                      const int32_t* __restrict__ col_off,
+                                                      const double* __restrict__ Einv,
+                                                      const int64_t* __restrict__ einv_off,
+                                                      int32_t r_max, int64_t n_ch,
+                                                      double* __restrict__ w,
+                                                      const int* __restrict__ mask) {
+    extern __shared__ double sv[];  // [r_max]
+    const int b = blockIdx.x;
+    if (mask && !mask[b]) return;
+    const int32_t c0 = col_off[b], rb = col_off[b + 1] - c0;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t g1 = ch_off[b + 1];
+    for (int32_t i = wv; i < rb; i += kCsThreads / 64) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        const double* ci = cpart + (int64_t)i * n_ch;
+        int64_t g = ch_off[b] + lane;
+        for (; g + 192 < g1; g += 256) {
+            s0 += ci[g];
+            s1 += ci[g + 64];
+            s2 += ci[g + 128];
+            s3 += ci[g + 192];
+        }
+        for (; g < g1; g += 64) s0 += ci[g];
+        double s = (s0 + s1) + (s2 + s3);
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+        if (lane == 0) sv[i] = s;
+    }
+    __syncthreads();
+    const double* E = Einv + einv_off[b];
+    for (int32_t a = wv; a < rb; a += kCsThreads / 64) {  // one wave per row of E^-1
+        double s = 0.0;
+        for (int32_t q = lane; q < rb; q += 64) s += E[(int64_t)a * rb + q] * sv[q];
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+        if (lane == 0) w[c0 + a] = s;
+    }
 }
 
 // pivoted Cholesky of a symmetric PSD matrix: indices of a maximal set of columns whose
@@ -1213,27 +1285,28 @@ int build_coarse_dense(mm_plan_t pl, const double* basis, int64_t basis_stride,
         MM_HIP(hipGetLastError());
         MM_HIP(hipStreamSynchronize(st));
     }
-    // Z^T r slices and the per-column tables
-    std::vector<int32_t> vs(keff + 1, 0), cprob(keff);
+    // per-column tables; Z^T r goes through per-chunk partials (kZtChunk entries each)
+    std::vector<int32_t> cprob(keff);
+    std::vector<int64_t> choff(B + 1, 0);
     for (int b = 0; b < B; ++b) {
         const int64_t nb = (oo[b + 1] - oo[b]) * ns;
-        for (int32_t a = col_off[b]; a < col_off[b + 1]; ++a) {
-            cprob[a] = b;
-            vs[a + 1] = vs[a] + (int32_t)((nb + 511) / 512);
-        }
+        choff[b + 1] = choff[b] + (nb + kZtChunk - 1) / kZtChunk;
+        for (int32_t a = col_off[b]; a < col_off[b + 1]; ++a) cprob[a] = b;
     }
-    DBuf<int32_t> d_vs, d_cprob, d_coloff;
+    DBuf<int64_t> d_choff;
+    DBuf<double> d_cpart;
+    MM_TRY(d_choff.alloc(B + 1));
+    MM_TRY(d_cpart.alloc((size_t)choff[B] * keep_max));
+    MM_HIP(hipMemcpyAsync(d_choff.p, choff.data(), (B + 1) * 8, hipMemcpyHostToDevice, st));
+    DBuf<int32_t> d_cprob, d_coloff;
     DBuf<int64_t> d_azoff, d_einvoff;
-    DBuf<double> d_einv, d_w, d_vpart;
-    MM_TRY(d_vs.alloc(keff + 1));
+    DBuf<double> d_einv, d_w;
     MM_TRY(d_cprob.alloc(keff));
     MM_TRY(d_coloff.alloc(B + 1));
     MM_TRY(d_azoff.alloc(B + 1));
     MM_TRY(d_einvoff.alloc(B + 1));
     MM_TRY(d_einv.alloc(Einv_all.size()));
     MM_TRY(d_w.alloc(keff));
-    MM_TRY(d_vpart.alloc(vs[keff]));
-    MM_HIP(hipMemcpyAsync(d_vs.p, vs.data(), (keff + 1) * 4, hipMemcpyHostToDevice, st));
     MM_HIP(hipMemcpyAsync(d_cprob.p, cprob.data(), keff * 4, hipMemcpyHostToDevice, st));
     MM_HIP(hipMemcpyAsync(d_coloff.p, col_off.data(), (B + 1) * 4, hipMemcpyHostToDevice, st));
     MM_HIP(hipMemcpyAsync(d_azoff.p, az_off.data(), (B + 1) * 8, hipMemcpyHostToDevice, st));
@@ -1260,9 +1333,12 @@ int build_coarse_dense(mm_plan_t pl, const double* basis, int64_t basis_stride,
     co.einv_off.swap(d_einvoff);
     co.Einv.swap(d_einv);
     co.w.swap(d_w);
-    co.vslice.swap(d_vs);
-    co.vpart.swap(d_vpart);
-    co.n_slices = vs[keff];
+    co.vslice.release();
+    co.vpart.release();
+    co.n_slices = 0;
+    co.ch_off.swap(d_choff);
+    co.cpart.swap(d_cpart);
+    co.n_chunks = choff[B];
     co.AZ64.swap(faz64);
     co.AZ32.swap(faz32);
     co.ZD64.swap(fz64);
@@ -1301,17 +1377,20 @@ int twolvl_apply_dense(mm_plan_t pl, const double* r, double* z, const PcgCtl& c
     hipStream_t st = pl->stream;
     const int32_t k = co.r_eff;
     const int ns = pl->n_s;
-    const dim3 gs((unsigned)((co.n_slices + 3) / 4)), t256(256);
+    const dim3 gc((unsigned)co.n_chunks), t256(256);
+    const size_t zsh = (size_t)4 * co.r_max * sizeof(double);
     if (co.ZD32.p)
-        hipLaunchKernelGGL(k_ztr_dense<float>, gs, t256, 0, st, (const float*)co.ZD32.p,
-                           co.az_off.p, co.col_off.p, co.col_prob.p, pl->ooff.p, ns, r, k,
-                           co.vslice.p, co.n_slices, co.vpart.p, ctl.mask);
+        hipLaunchKernelGGL(k_ztr_chunks<float>, gc, t256, zsh, st, (const float*)co.ZD32.p,
+                           co.az_off.p, co.col_off.p, co.ch_off.p, pl->n_prob, pl->ooff.p, ns,
+                           r, co.r_max, co.n_chunks, co.cpart.p, ctl.mask);
     else
-        hipLaunchKernelGGL(k_ztr_dense<double>, gs, t256, 0, st, (const double*)co.ZD64.p,
-                           co.az_off.p, co.col_off.p, co.col_prob.p, pl->ooff.p, ns, r, k,
-                           co.vslice.p, co.n_slices, co.vpart.p, ctl.mask);
-    hipLaunchKernelGGL(k_einv, dim3((k + 3) / 4), dim3(256), 0, st, co.Einv.p, co.einv_off.p,
-                       co.col_off.p, co.col_prob.p, co.vpart.p, co.vslice.p, k, co.w.p, ctl.mask);
+        hipLaunchKernelGGL(k_ztr_chunks<double>, gc, t256, zsh, st, (const double*)co.ZD64.p,
+                           co.az_off.p, co.col_off.p, co.ch_off.p, pl->n_prob, pl->ooff.p, ns,
+                           r, co.r_max, co.n_chunks, co.cpart.p, ctl.mask);
+    hipLaunchKernelGGL(k_coarse_solve, dim3(pl->n_prob), dim3(kCsThreads),
+                       (size_t)co.r_max * sizeof(double),
+                       st, (const double*)co.cpart.p, co.ch_off.p, co.col_off.p, co.Einv.p,
+                       co.einv_off.p, co.r_max, co.n_chunks, co.w.p, ctl.mask);
     const size_t shm = (size_t)co.r_max * sizeof(double);
     const dim3 g(pl->n_pblk), t(kVecThreads);
     const int64_t* np64 = nullptr;

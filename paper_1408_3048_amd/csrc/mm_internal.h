@@ -185,6 +185,9 @@ struct Coarse {
     DBuf<int32_t> vslice;            // [r_eff+1] first Z^T r slice of every kept column
     int64_t n_slices = 0;            // slices of 512 entries over all kept columns
     DBuf<double> vpart;              // [n_slices] partial sums of Z^T r
+    DBuf<int64_t> ch_off;            // Z_D: [B+1] first Z^T r chunk of every problem
+    DBuf<double> cpart;              // Z_D: [n_chunks][r_max] chunk partials of Z^T r
+    int64_t n_chunks = 0;
 };
 
 }  // namespace mm
