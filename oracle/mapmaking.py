@@ -10,6 +10,7 @@ Citations refer to the paper's sections and equations (LaTeX labels):
   Sect. 2.1 (GLS problem)             eqs. glsSol, N_def, Sdef, linear_system, rhs, a_times_x
   Sect. 3.1 (preconditioning)         eqs. err_bound, stdPrec
   Sect. 3.2 (two-level)               eqs. projection, 2 (A-DEF1)
+  App. B (alternative two-level)      eq. ADEF2 (A-DEF2) and its initial guess
   Sect. 3.3.1 (a priori coarse space) eqs. AsingVect, strofZ, strofZ_polar
   Sect. 4.1.4 (noise)                 eq. fknee; band half-width lambda_T
   App. C (implementation)             precomputed AZ and E; 4-step application
@@ -38,8 +39,9 @@ Pins (tests marked "not gpu"): taps vs. explicit cosine sums and the white
 noise closed form; banded sums vs. explicit dense Toeplitz matrices; P/P^T
 adjointness and integer hits; symmetry and positive definiteness of A; white
 noise => M_BD = A^-1 and one-iteration convergence; noiseless data => the
-input map; M_2lvl A Z = Z and R A Z = 0; PCG vs. dense Cholesky on tiny
-problems; gradients vs. finite differences of a dense solve.
+input map; M_2lvl A Z = Z and R A Z = 0; M_alt A and M_2lvl A share their
+spectrum; PCG vs. dense Cholesky on tiny problems; gradients vs. finite
+differences of a dense solve; the CG Lanczos matrix equals W^T A W.
 """
 
 from __future__ import annotations
@@ -372,6 +374,19 @@ class Coarse:
     def deflation(self, y):
         """R y = (I - A Z E^+ Z^T) y (eq. projection)."""
         return y - self.AZ @ (self.Epinv @ (self.Z.T @ y))
+
+    def apply_adef2(self, r):
+        """A-DEF2 (App. B, eq. ADEF2): M_alt r = R^T M_BD r + Z E^+ Z^T r, with
+        R^T = I - Z E^+ (A Z)^T since A and E are symmetric."""
+        y = self.prob.bj_apply(r, self.B)
+        return y - self.Z @ (self.Epinv @ (self.AZ.T @ y)) + self.Z @ (self.Epinv @ (self.Z.T @ r))
+
+    def adef2_start(self, b, x0=None):
+        """The initial guess with which A-DEF2 PCG is equivalent to PCG with an SPD
+        preconditioner (App. B): x0 + Z E^+ Z^T (b - A x0), i.e. Z E^+ Z^T b + R^T x0;
+        its residual R (b - A x0) has Z^T r = 0."""
+        x0 = np.zeros_like(b) if x0 is None else np.asarray(x0, dtype=np.float64)
+        return x0 + self.Z @ (self.Epinv @ (self.Z.T @ (b - self.prob.apply_A(x0))))
 
 
 # --------------------------------------------------------------------------

@@ -245,6 +245,39 @@ def test_solution_independent_of_preconditioner():
     assert np.linalg.norm(x1 - x2) / np.linalg.norm(x1) < 1e-10
 
 
+def test_adef2_spectrum_and_start():
+    """App. B: M_alt A and M_2lvl A share their spectrum (the theorem the paper cites for
+    the two deflation variants); from its special initial guess the A-DEF2 PCG reaches
+    the dense solution, starting with Z^T r_0 = 0, in about as many iterations as
+    A-DEF1."""
+    sc = tiny_iqu(interval_len=256)
+    pr = O.Problem.from_scan(sc)
+    A, _, _ = O.dense_system(pr)
+    C = O.Coarse(pr, O.coarse_zs(pr))
+    n = A.shape[0]
+    eye = np.eye(n)
+    M1 = np.stack([C.apply(eye[:, j]) for j in range(n)], axis=1)
+    M2 = np.stack([C.apply_adef2(eye[:, j]) for j in range(n)], axis=1)
+    assert np.max(np.abs(M1 - M2)) > 1e-2 * np.max(np.abs(M1))  # different operators
+    ev1 = np.linalg.eigvals(M1 @ A)
+    ev2 = np.linalg.eigvals(M2 @ A)
+    assert np.max(np.abs(ev1.imag)) <= 1e-8 and np.max(np.abs(ev2.imag)) <= 1e-8
+    e1, e2 = np.sort(ev1.real), np.sort(ev2.real)
+    assert np.max(np.abs(e1 - e2)) <= 1e-8 * e1.max()
+    # the deflated directions sit at 1: rank(Z) eigenvalues equal to 1
+    assert np.sum(np.abs(e1 - 1.0) <= 1e-8) >= C.rank
+    b = pr.rhs(pr.signal(sc.sky) + sc.noise)
+    x0 = C.adef2_start(b)
+    r0 = b - pr.apply_A(x0)
+    assert np.max(np.abs(C.Z.T @ r0)) <= 1e-10 * np.max(np.abs(C.Z.T @ b))
+    xd = np.linalg.solve(A, b)
+    x2, it2, s2 = O.pcg(pr.apply_A, b, C.apply_adef2, tol=1e-12, maxit=1000, x0=x0)
+    _, it1, s1 = O.pcg(pr.apply_A, b, C.apply, tol=1e-12, maxit=1000)
+    assert s1 == 0 and s2 == 0
+    assert np.linalg.norm(x2 - xd) / np.linalg.norm(xd) <= 1e-10
+    assert abs(it2 - it1) <= 2, (it1, it2)
+
+
 # ------------------------------------------------------- P11: near-null mode
 
 def test_ones_in_near_null_space_with_1f_noise():
