@@ -63,7 +63,7 @@ enum { MM_F32 = 0, MM_F64 = 1 };                               /* element types 
 enum { MM_WIN_GAUSS = 0, MM_WIN_GAUSS2 = 1, MM_WIN_RECT = 2 };  /* apodisation windows */
 enum { MM_FP64 = 0, MM_MIXED = 1, MM_MIXED_IR = 2 };          /* arithmetic of the operator */
 enum { MM_COARSE_NONE = 0, MM_COARSE_ZS = 1 };                 /* coarse space built by mm_plan */
-enum { MM_BJ = 0, MM_2LVL = 1 };                               /* preconditioner of mm_pcg_solve */
+enum { MM_BJ = 0, MM_2LVL = 1, MM_ADEF2 = 2 };                 /* preconditioner of mm_pcg_solve */
 
 /* Noise model of one stationary interval: per-sample PSD
  * P(f) = sigma^2 (1 + (f_knee / f)^alpha)  [Sect. 4.1.4, eq. fknee with the
@@ -194,6 +194,12 @@ int mm_precond_bj(mm_plan_t plan, const double* r, double* z);
  * r and z may not alias. */
 int mm_precond_2lvl(mm_plan_t plan, const double* r, double* z);
 
+/* z = M_alt r = R^T M_BD r + Z E^-1 Z^T r, R^T = I - Z E^-1 (AZ)^T [App. B, eq. ADEF2]
+ * (A-DEF2) with the plan's coarse space (none: MM_ERR_STATE).  Same spectrum of M A as
+ * MM_2LVL; PCG with it starts from x0 + Z E^-1 Z^T (b - A x0), for which it is
+ * equivalent to CG with an SPD preconditioner.  r and z may not alias. */
+int mm_precond_adef2(mm_plan_t plan, const double* r, double* z);
+
 /* ----- solver ----- */
 
 typedef struct {
@@ -211,7 +217,8 @@ typedef struct {
 
 /* Solve A x = b by PCG [Sect. 3] from the initial guess in x (pass zeros for x0 = 0);
  * for a batched plan every problem b solves A_b x_b = b_b (its block of the vectors).
- *   precond    MM_BJ or MM_2LVL
+ *   precond    MM_BJ, MM_2LVL (A-DEF1) or MM_ADEF2 (which first replaces x by
+ *              x + Z E^-1 Z^T (b - A x))
  *   precision  MM_FP64: FP64 operator; convergence when the recursive and then the true
  *              relative residual are <= tol (otherwise the recursive residual is replaced
  *              by the true one and the iteration continues).

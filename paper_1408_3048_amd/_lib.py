@@ -22,7 +22,8 @@ MM_F32, MM_F64 = 0, 1
 MM_WIN_GAUSS, MM_WIN_GAUSS2, MM_WIN_RECT = 0, 1, 2
 MM_FP64, MM_MIXED, MM_MIXED_IR = 0, 1, 2
 MM_COARSE_NONE, MM_COARSE_ZS = 0, 1
-MM_BJ, MM_2LVL = 0, 1
+MM_BJ, MM_2LVL, MM_ADEF2 = 0, 1, 2
+_PRECOND = {"bj": MM_BJ, "2lvl": MM_2LVL, "adef2": MM_ADEF2}
 
 STATUS_NAMES = {0: "MM_OK", -1: "MM_ERR_ARG", -2: "MM_ERR_DEVICE", -3: "MM_ERR_RANK",
                 -4: "MM_ERR_NOT_SPD", -5: "MM_ERR_BREAKDOWN", -6: "MM_ERR_NOCONV",
@@ -36,7 +37,7 @@ EXPORTED = [
     "mm_profile", "mm_profile_read", "mm_last_error", "mm_plan_batched", "mm_n_problems",
     "mm_problem_pixels", "mm_coarse_problem_columns", "mm_fft_lengths", "mm_lag_correlations",
     "mm_tap_derivatives", "mm_adjoint", "mm_coarse_from_krylov", "mm_lanczos_ritz",
-    "mm_coarse_kind", "mm_coarse_ritz_values", "mm_coarse_dense_columns",
+    "mm_coarse_kind", "mm_coarse_ritz_values", "mm_coarse_dense_columns", "mm_precond_adef2",
 ]
 
 
@@ -99,6 +100,7 @@ def load():
         "mm_apply_A": (I, [P, P, P, I]),
         "mm_precond_bj": (I, [P, P, P]),
         "mm_precond_2lvl": (I, [P, P, P]),
+        "mm_precond_adef2": (I, [P, P, P]),
         "mm_pcg_solve": (I, [P, P, P, I, I, D, I, ctypes.POINTER(mm_solve_info)]),
         "mm_plan_time_ms": (D, [P]),
         "mm_gemm_tn_f64": (I, [P, P, P, I64, I32, I32, P]),
@@ -380,6 +382,11 @@ class Plan:
         check(self._lib.mm_precond_2lvl(self._h, _ptr(r), _ptr(z)))
         return z
 
+    def precond_adef2(self, r):
+        z = self._vec()
+        check(self._lib.mm_precond_adef2(self._h, _ptr(r), _ptr(z)))
+        return z
+
     # ---- adjoint
     def lag_correlations(self, u, v):
         """c[j, k], k = 0..lambda: lag cross-correlations of FP64 TOD u, v per interval."""
@@ -406,7 +413,7 @@ class Plan:
         infos = (mm_solve_info * self.n_problems)()
         st = self._lib.mm_adjoint(
             self._h, _ptr(m_hat), _ptr(g), _ptr(d), MM_F64 if d.dtype == torch.float64 else MM_F32,
-            MM_2LVL if precond == "2lvl" else MM_BJ,
+            _PRECOND[precond],
             {"fp64": MM_FP64, "mixed": MM_MIXED, "mixed_ir": MM_MIXED_IR}[precision], float(tol),
             int(max_iter), _ptr(mu), _ptr(gd),
             MM_F64 if grad_d_dtype == torch.float64 else MM_F32,
@@ -436,7 +443,7 @@ class Plan:
         x = torch.zeros_like(b) if x0 is None else x0.clone()
         infos, hists = self._infos(max_iter, history)
         st = self._lib.mm_pcg_solve(self._h, _ptr(b), _ptr(x),
-                                    MM_2LVL if precond == "2lvl" else MM_BJ,
+                                    _PRECOND[precond],
                                     {"fp64": MM_FP64, "mixed": MM_MIXED,
                                      "mixed_ir": MM_MIXED_IR}[precision],
                                     float(tol), int(max_iter), infos)

@@ -26,7 +26,7 @@ class GLSMap(torch.autograd.Function):
         max_iter = opts.pop("max_iter", 3000)
         plan = Plan(pix, weights, n_pix, offsets, psd.detach().cpu().numpy().astype(np.float64),
                     precision="mixed" if precision != "fp64" else "fp64",
-                    coarse=precond == "2lvl", **opts)
+                    coarse=precond in ("2lvl", "adef2"), **opts)
         d_det = d.detach().contiguous()
         b = plan.rhs(d_det)
         m, _ = plan.pcg_solve(b, precond=precond, precision=precision, tol=tol,
@@ -52,5 +52,5 @@ def gls_map(d, psd, pix, weights, n_pix, offsets, **options):
     """The GLS map of TOD d (CUDA tensor) with per-interval noise parameters psd
     ([K, 3] tensor of (sigma, f_knee, alpha)), differentiable in both.  options: the
     Plan keyword arguments (n_stokes, lam, f_samp, window, fft lengths, ...) plus
-    precond ("bj" / "2lvl"), precision ("fp64" / "mixed"), tol and max_iter of both solves."""
+    precond ("bj" / "2lvl" / "adef2"), precision ("fp64" / "mixed"), tol and max_iter of both solves."""
     return GLSMap.apply(d, psd, (pix, weights, n_pix, offsets), tuple(sorted(options.items())))

@@ -155,7 +155,9 @@ double ms_since(clk::time_point t0) {
 
 int precond(mm_plan_t pl, int pc, const double* r, double* z, const PcgCtl& ctl, int tag = -1) {
     MM_TRY(prof_begin(pl, MM_K_PRECOND, tag));
-    MM_TRY(pc == MM_2LVL ? twolvl_apply(pl, r, z, ctl) : bj_apply(pl, r, z, ctl));
+    MM_TRY(pc == MM_2LVL    ? twolvl_apply(pl, r, z, ctl)
+           : pc == MM_ADEF2 ? adef2_apply(pl, r, z, ctl)
+                            : bj_apply(pl, r, z, ctl));
     return prof_end(pl, MM_K_PRECOND);
 }
 
@@ -265,6 +267,8 @@ int pcg_engine(mm_plan_t pl, const double* b, double* x, const EngineArgs& ea) {
         MM_TRY(ea.op32 ? apply_A32(pl, xw, q, nullptr) : apply_A64(pl, xw, q, nullptr));
         MM_TRY(vec_residual(pl, b, q, r, all));
     }
+    // A-DEF2 starts from x0 + Z E^-1 Z^T (b - A x0) [App. B]
+    if (ea.pc == MM_ADEF2) MM_TRY(coarse_start(pl, xw, r));
     MM_TRY(vec_dot(pl, b, b, kSlotAux, all));
     MM_TRY(pcg_init(pl, all, ea.tol, 1));
     MM_TRY(vec_zero_flagged(pl, xw, pl->sel.p, all));  // b_b = 0: x_b = 0 exactly
@@ -285,7 +289,7 @@ int pcg_engine(mm_plan_t pl, const double* b, double* x, const EngineArgs& ea) {
     // graph of one iteration for this operator / preconditioner and control arguments
     const bool use_graph = pl->opts.graph != 0 && !pl->prof_on && pl->gstream != nullptr &&
                            pl->stream == pl->gstream;
-    const int gi = ea.op32 ? 1 : 0, gj = ea.pc == MM_2LVL ? 1 : 0;
+    const int gi = ea.op32 ? 1 : 0, gj = ea.pc;
     hipGraphExec_t& gx = pl->gexec[gi][gj];
     auto& key = pl->gkey[gi][gj];
     if (use_graph && gx &&
@@ -773,16 +777,33 @@ int mm_precond_2lvl(mm_plan_t pl, const double* r, double* z) {
     return twolvl_apply(pl, r, z, c);
 }
 
+int mm_precond_adef2(mm_plan_t pl, const double* r, double* z) {
+    clear_error();
+    MM_TRY(check_vec_args(pl, r, z));
+    if (!pl->has_coarse) {
+        set_error("plan without a coarse space (opts.coarse = MM_COARSE_ZS or "
+                  "mm_coarse_from_krylov)");
+        return MM_ERR_STATE;
+    }
+    if (r == z) {
+        set_error("r and z may not alias");
+        return MM_ERR_ARG;
+    }
+    PcgCtl c = batch_ctl(pl);
+    c.part = nullptr;
+    return adef2_apply(pl, r, z, c);
+}
+
 int mm_pcg_solve(mm_plan_t pl, const double* b, double* x, int pc, int precision, double tol,
                  int max_iter, mm_solve_info* info) {
     clear_error();
     MM_TRY(check_vec_args(pl, b, x));
-    if (pc != MM_BJ && pc != MM_2LVL) {
-        set_error("precond must be MM_BJ or MM_2LVL");
+    if (pc != MM_BJ && pc != MM_2LVL && pc != MM_ADEF2) {
+        set_error("precond must be MM_BJ, MM_2LVL or MM_ADEF2");
         return MM_ERR_ARG;
     }
-    if (pc == MM_2LVL && !pl->has_coarse) {
-        set_error("MM_2LVL needs a coarse space (opts.coarse = MM_COARSE_ZS or "
+    if (pc != MM_BJ && !pl->has_coarse) {
+        set_error("MM_2LVL and MM_ADEF2 need a coarse space (opts.coarse = MM_COARSE_ZS or "
                   "mm_coarse_from_krylov)");
         return MM_ERR_STATE;
     }

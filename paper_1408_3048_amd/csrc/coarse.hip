@@ -547,37 +547,50 @@ __global__ __launch_bounds__(256) void k_ztr_chunks(const TA* __restrict__ zd,
         cpart[c * n_ch + g] = ((red[c] + red[r_max + c]) + red[2 * r_max + c]) + red[3 * r_max + c];
 }
 
-// second stage, one block per problem: v_i = sum of the chunk partials of column i (one
-// wave per column, four independent load streams per lane, fixed order) into LDS, then
-// w = E^-1 v
+// sum of n_ch-strided chunk partials ci[g0..g1) over the wave (four independent load
+// streams per lane, fixed order)
+__device__ __forceinline__ double wave_chunk_sum(const double* __restrict__ ci, int64_t g0,
+                                                 int64_t g1, int lane) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int64_t g = g0 + lane;
+    for (; g + 192 < g1; g += 256) {
+        s0 += ci[g];
+        s1 += ci[g + 64];
+        s2 += ci[g + 128];
+        s3 += ci[g + 192];
+    }
+    for (; g < g1; g += 64) s0 += ci[g];
+    double s = (s0 + s1) + (s2 + s3);
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    return s;
+}
+
+// second stage, one block per problem: v_i = Z^T r of column i, from chunk partials cz
+// (Z_D) or from the slice partials vpart / vslice (Z_S), minus (AZ)^T y of column i from
+// chunk partials caz when given (A-DEF2); one wave per column into LDS, then w = E^-1 v
 constexpr int kCsThreads = 1024;
-__global__ __launch_bounds__(kCsThreads) void k_coarse_solve(const double* __restrict__ cpart,
-                                                      const int64_t* __restrict__ ch_off,
-                                                      const int32_t* __restrict__ col_off,
-                                                      const double* __restrict__ Einv,
-                                                      const int64_t* __restrict__ einv_off,
-                                                      int32_t r_max, int64_t n_ch,
-                                                      double* __restrict__ w,
-                                                      const int* __restrict__ mask) {
+__global__ __launch_bounds__(kCsThreads) void k_coarse_solve(
+    const double* __restrict__ cz, const double* __restrict__ vpart,
+    const int32_t* __restrict__ vslice, const double* __restrict__ caz,
+    const int64_t* __restrict__ ch_off, const int32_t* __restrict__ col_off,
+    const double* __restrict__ Einv, const int64_t* __restrict__ einv_off, int32_t r_max,
+    int64_t n_ch, double* __restrict__ w, const int* __restrict__ mask) {
     extern __shared__ double sv[];  // [r_max]
     const int b = blockIdx.x;
     if (mask && !mask[b]) return;
     const int32_t c0 = col_off[b], rb = col_off[b + 1] - c0;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t g1 = ch_off[b + 1];
+    const int64_t g0 = ch_off[b], g1 = ch_off[b + 1];
     for (int32_t i = wv; i < rb; i += kCsThreads / 64) {
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        const double* ci = cpart + (int64_t)i * n_ch;
-        int64_t g = ch_off[b] + lane;
-        for (; g + 192 < g1; g += 256) {
-            s0 += ci[g];
-            s1 += ci[g + 64];
-            s2 += ci[g + 128];
-            s3 += ci[g + 192];
+        double s;
+        if (cz) {
+            s = wave_chunk_sum(cz + (int64_t)i * n_ch, g0, g1, lane);
+        } else {
+            s = 0.0;
+            for (int32_t t = vslice[c0 + i] + lane; t < vslice[c0 + i + 1]; t += 64) s += vpart[t];
+            for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
         }
-        for (; g < g1; g += 64) s0 += ci[g];
-        double s = (s0 + s1) + (s2 + s3);
-        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+        if (caz) s -= wave_chunk_sum(caz + (int64_t)i * n_ch, g0, g1, lane);
         if (lane == 0) sv[i] = s;
     }
     __syncthreads();
@@ -587,6 +600,92 @@ __global__ __launch_bounds__(kCsThreads) void k_coarse_solve(const double* __res
         for (int32_t q = lane; q < rb; q += 64) s += E[(int64_t)a * rb + q] * sv[q];
         for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
         if (lane == 0) w[c0 + a] = s;
+    }
+}
+
+// A-DEF2, last step: z = y + Z w per pixel (y = M_BD r already in z), partials of r^T z.
+// DZ: dense Z blocks (layout of AZ); else the Z_S rows in CSR form.
+template <typename TA, int NS, bool DZ>
+__global__ __launch_bounds__(kVecThreads) void k_adef2_finish(
+    const double* __restrict__ r, double* __restrict__ z, const TA* __restrict__ zd,
+    const int64_t* __restrict__ az_off, const int32_t* __restrict__ col_off,
+    const double* __restrict__ w, const int64_t* __restrict__ zptr,
+    const int32_t* __restrict__ zcol, const double* __restrict__ zval, PcgCtl ctl) {
+    __shared__ double red[kVecThreads];
+    extern __shared__ double sw[];
+    const VecBlock vb = vec_block(ctl, NS, false);
+    if (ctl.mask && !ctl.mask[vb.b]) return;
+    const int32_t c0 = col_off[vb.b], rk = col_off[vb.b + 1] - c0;
+    for (int c = threadIdx.x; c < rk; c += kVecThreads) sw[c] = w[c0 + c];
+    __syncthreads();
+    const int64_t nv = vb.n * NS;
+    double acc = 0.0;
+    for (int64_t q = (int64_t)vb.k * kVecThreads + threadIdx.x; q < vb.n;
+         q += (int64_t)kVecBlocks * kVecThreads) {
+        const int64_t p = vb.base + q;
+        double zz[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) zz[s] = z[p * NS + s];
+        if constexpr (DZ) {
+            const TA* zb = zd + az_off[vb.b] + q * NS;
+            for (int32_t c = 0; c < rk; ++c) {
+                const double wc = sw[c];
+#pragma unroll
+                for (int s = 0; s < NS; ++s) zz[s] += (double)zb[(int64_t)c * nv + s] * wc;
+            }
+        } else {
+            double zw = 0.0;
+            for (int64_t e = zptr[p]; e < zptr[p + 1]; ++e) zw += zval[e] * sw[zcol[e] - c0];
+            zz[0] += zw;
+        }
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            z[p * NS + s] = zz[s];
+            acc += r[p * NS + s] * zz[s];
+        }
+    }
+    if (ctl.part) write_partial_at(acc, slot_part(ctl, kSlotRZ, vb.b), vb.k, red);
+}
+
+// coarse correction of an initial guess: x += Z w, r -= AZ w per pixel
+template <typename TA, int NS, bool DZ>
+__global__ __launch_bounds__(kVecThreads) void k_coarse_correct(
+    double* __restrict__ x, double* __restrict__ r, const TA* __restrict__ az,
+    const TA* __restrict__ zd, const int64_t* __restrict__ az_off,
+    const int32_t* __restrict__ col_off, const double* __restrict__ w,
+    const int64_t* __restrict__ zptr, const int32_t* __restrict__ zcol,
+    const double* __restrict__ zval, PcgCtl ctl) {
+    extern __shared__ double sw[];
+    const VecBlock vb = vec_block(ctl, NS, false);
+    if (ctl.mask && !ctl.mask[vb.b]) return;
+    const int32_t c0 = col_off[vb.b], rk = col_off[vb.b + 1] - c0;
+    for (int c = threadIdx.x; c < rk; c += kVecThreads) sw[c] = w[c0 + c];
+    __syncthreads();
+    const int64_t nv = vb.n * NS;
+    for (int64_t q = (int64_t)vb.k * kVecThreads + threadIdx.x; q < vb.n;
+         q += (int64_t)kVecBlocks * kVecThreads) {
+        const int64_t p = vb.base + q;
+        double dx[NS], dr[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) dx[s] = dr[s] = 0.0;
+        const TA* ab = az + az_off[vb.b] + q * NS;
+        for (int32_t c = 0; c < rk; ++c) {
+            const double wc = sw[c];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) dr[s] += (double)ab[(int64_t)c * nv + s] * wc;
+            if constexpr (DZ) {
+                const TA* zb = zd + az_off[vb.b] + q * NS;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) dx[s] += (double)zb[(int64_t)c * nv + s] * wc;
+            }
+        }
+        if constexpr (!DZ)
+            for (int64_t e = zptr[p]; e < zptr[p + 1]; ++e) dx[0] += zval[e] * sw[zcol[e] - c0];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            x[p * NS + s] += dx[s];
+            r[p * NS + s] -= dr[s];
+        }
     }
 }
 
@@ -1052,6 +1151,16 @@ int build_coarse(mm_plan_t pl) {
     MM_HIP(hipGetLastError());
     MM_TRY(co.w.alloc(keff));
     MM_TRY(co.vpart.alloc(co.n_slices));
+    // chunk tables of the dense (AZ)^T y products (A-DEF2)
+    {
+        std::vector<int64_t> choff(B + 1, 0);
+        for (int b = 0; b < B; ++b)
+            choff[b + 1] = choff[b] + ((oo[b + 1] - oo[b]) * ns + kZtChunk - 1) / kZtChunk;
+        co.n_chunks = choff[B];
+        MM_TRY(co.ch_off.alloc(B + 1));
+        MM_TRY(co.cpart2.alloc((size_t)co.n_chunks * co.r_max));
+        MM_HIP(hipMemcpyAsync(co.ch_off.p, choff.data(), (B + 1) * 8, hipMemcpyHostToDevice, st));
+    }
     MM_HIP(hipStreamSynchronize(st));
     tick("csr");
     co.kind = 1;
@@ -1294,9 +1403,10 @@ int build_coarse_dense(mm_plan_t pl, const double* basis, int64_t basis_stride,
         for (int32_t a = col_off[b]; a < col_off[b + 1]; ++a) cprob[a] = b;
     }
     DBuf<int64_t> d_choff;
-    DBuf<double> d_cpart;
+    DBuf<double> d_cpart, d_cpart2;
     MM_TRY(d_choff.alloc(B + 1));
     MM_TRY(d_cpart.alloc((size_t)choff[B] * keep_max));
+    MM_TRY(d_cpart2.alloc((size_t)choff[B] * keep_max));
     MM_HIP(hipMemcpyAsync(d_choff.p, choff.data(), (B + 1) * 8, hipMemcpyHostToDevice, st));
     DBuf<int32_t> d_cprob, d_coloff;
     DBuf<int64_t> d_azoff, d_einvoff;
@@ -1338,6 +1448,7 @@ int build_coarse_dense(mm_plan_t pl, const double* basis, int64_t basis_stride,
     co.n_slices = 0;
     co.ch_off.swap(d_choff);
     co.cpart.swap(d_cpart);
+    co.cpart2.swap(d_cpart2);
     co.n_chunks = choff[B];
     co.AZ64.swap(faz64);
     co.AZ32.swap(faz32);
@@ -1388,9 +1499,10 @@ int twolvl_apply_dense(mm_plan_t pl, const double* r, double* z, const PcgCtl& c
                            co.az_off.p, co.col_off.p, co.ch_off.p, pl->n_prob, pl->ooff.p, ns,
                            r, co.r_max, co.n_chunks, co.cpart.p, ctl.mask);
     hipLaunchKernelGGL(k_coarse_solve, dim3(pl->n_prob), dim3(kCsThreads),
-                       (size_t)co.r_max * sizeof(double),
-                       st, (const double*)co.cpart.p, co.ch_off.p, co.col_off.p, co.Einv.p,
-                       co.einv_off.p, co.r_max, co.n_chunks, co.w.p, ctl.mask);
+                       (size_t)co.r_max * sizeof(double), st, (const double*)co.cpart.p,
+                       (const double*)nullptr, (const int32_t*)nullptr, (const double*)nullptr,
+                       co.ch_off.p, co.col_off.p, co.Einv.p, co.einv_off.p, co.r_max,
+                       co.n_chunks, co.w.p, ctl.mask);
     const size_t shm = (size_t)co.r_max * sizeof(double);
     const dim3 g(pl->n_pblk), t(kVecThreads);
     const int64_t* np64 = nullptr;
@@ -1454,6 +1566,129 @@ int twolvl_apply(mm_plan_t pl, const double* r, double* z, const PcgCtl& ctl) {
     }
     MM_HIP(hipGetLastError());
     return MM_OK;
+}
+
+namespace {
+
+template <typename TA>
+const TA* az_blocks(const Coarse& co);
+template <>
+const float* az_blocks<float>(const Coarse& co) { return co.AZ32.p; }
+template <>
+const double* az_blocks<double>(const Coarse& co) { return co.AZ64.p; }
+template <typename TA>
+const TA* z_blocks(const Coarse& co);
+template <>
+const float* z_blocks<float>(const Coarse& co) { return co.ZD32.p; }
+template <>
+const double* z_blocks<double>(const Coarse& co) { return co.ZD64.p; }
+
+// chunk partials of X^T v for dense blocks X laid out like AZ
+template <typename TA>
+int chunk_partials(mm_plan_t pl, const TA* X, const double* v, double* out, const int* mask) {
+    const Coarse& co = pl->co;
+    hipLaunchKernelGGL(k_ztr_chunks<TA>, dim3((unsigned)co.n_chunks), dim3(256),
+                       (size_t)4 * co.r_max * sizeof(double), pl->stream, X, co.az_off.p,
+                       co.col_off.p, co.ch_off.p, pl->n_prob, pl->ooff.p, pl->n_s, v, co.r_max,
+                       co.n_chunks, out, mask);
+    MM_HIP(hipGetLastError());
+    return MM_OK;
+}
+
+// w = E^-1 (Z^T r - (AZ)^T y) per masked problem (the second term only when y is given)
+int coarse_w(mm_plan_t pl, const double* r, const double* y, const int* mask) {
+    Coarse& co = pl->co;
+    hipStream_t st = pl->stream;
+    const bool f32 = co.AZ32.p != nullptr;
+    if (co.kind == 2) {
+        MM_TRY(f32 ? chunk_partials<float>(pl, co.ZD32.p, r, co.cpart.p, mask)
+                   : chunk_partials<double>(pl, co.ZD64.p, r, co.cpart.p, mask));
+    } else {
+        hipLaunchKernelGGL(k_ztr, dim3((co.n_slices + 3) / 4), dim3(256), 0, st, co.csc_beg.p,
+                           co.csc_end.p, co.csc_row.p, co.csc_val.p, r, pl->n_s, co.r_eff,
+                           co.vslice.p, co.n_slices, co.col_prob.p, co.vpart.p, mask);
+        MM_HIP(hipGetLastError());
+    }
+    if (y)
+        MM_TRY(f32 ? chunk_partials<float>(pl, co.AZ32.p, y, co.cpart2.p, mask)
+                   : chunk_partials<double>(pl, co.AZ64.p, y, co.cpart2.p, mask));
+    hipLaunchKernelGGL(k_coarse_solve, dim3(pl->n_prob), dim3(kCsThreads),
+                       (size_t)co.r_max * sizeof(double), st,
+                       co.kind == 2 ? (const double*)co.cpart.p : nullptr,
+                       (const double*)co.vpart.p, (const int32_t*)co.vslice.p,
+                       y ? (const double*)co.cpart2.p : nullptr, co.ch_off.p, co.col_off.p,
+                       co.Einv.p, co.einv_off.p, co.r_max, co.n_chunks, co.w.p, mask);
+    MM_HIP(hipGetLastError());
+    return MM_OK;
+}
+
+template <typename TA, int NS, bool DZ>
+int adef2_finish_t(mm_plan_t pl, const double* r, double* z, const PcgCtl& ctl) {
+    const Coarse& co = pl->co;
+    const TA* zd = DZ ? z_blocks<TA>(co) : nullptr;
+    hipLaunchKernelGGL((k_adef2_finish<TA, NS, DZ>), dim3(pl->n_pblk), dim3(kVecThreads),
+                       (size_t)co.r_max * sizeof(double), pl->stream, r, z, zd, co.az_off.p,
+                       co.col_off.p, co.w.p, co.csr_ptr.p, co.csr_col.p, co.csr_val.p, ctl);
+    MM_HIP(hipGetLastError());
+    return MM_OK;
+}
+
+template <typename TA, int NS, bool DZ>
+int coarse_correct_t(mm_plan_t pl, double* x, double* r, const PcgCtl& ctl) {
+    const Coarse& co = pl->co;
+    const TA* zd = DZ ? z_blocks<TA>(co) : nullptr;
+    hipLaunchKernelGGL((k_coarse_correct<TA, NS, DZ>), dim3(pl->n_pblk), dim3(kVecThreads),
+                       (size_t)co.r_max * sizeof(double), pl->stream, x, r, az_blocks<TA>(co), zd,
+                       co.az_off.p, co.col_off.p, co.w.p, co.csr_ptr.p, co.csr_col.p,
+                       co.csr_val.p, ctl);
+    MM_HIP(hipGetLastError());
+    return MM_OK;
+}
+
+// instantiation for the plan's AZ precision, Stokes count and kind of Z
+template <template <typename, int, bool> class K, typename... Args>
+int by_layout(mm_plan_t pl, Args... args) {
+    const bool f = pl->co.AZ32.p != nullptr, d = pl->co.kind == 2;
+    if (pl->n_s == 3) {
+        if (f) return d ? K<float, 3, true>::run(pl, args...) : K<float, 3, false>::run(pl, args...);
+        return d ? K<double, 3, true>::run(pl, args...) : K<double, 3, false>::run(pl, args...);
+    }
+    if (f) return d ? K<float, 1, true>::run(pl, args...) : K<float, 1, false>::run(pl, args...);
+    return d ? K<double, 1, true>::run(pl, args...) : K<double, 1, false>::run(pl, args...);
+}
+template <typename TA, int NS, bool DZ>
+struct Adef2Finish {
+    static int run(mm_plan_t pl, const double* r, double* z, PcgCtl ctl) {
+        return adef2_finish_t<TA, NS, DZ>(pl, r, z, ctl);
+    }
+};
+template <typename TA, int NS, bool DZ>
+struct CoarseCorrect {
+    static int run(mm_plan_t pl, double* x, double* r, PcgCtl ctl) {
+        return coarse_correct_t<TA, NS, DZ>(pl, x, r, ctl);
+    }
+};
+
+}  // namespace
+
+// A-DEF2 [App. B, eq. ADEF2]: z = R^T M_BD r + Z E^-1 Z^T r = y + Z E^-1 (Z^T r - (AZ)^T y),
+// y = M_BD r (R^T = I - Z E^-1 (AZ)^T, A and E symmetric); partials of r^T z as ctl asks
+int adef2_apply(mm_plan_t pl, const double* r, double* z, const PcgCtl& ctl) {
+    PcgCtl c0 = ctl;
+    c0.part = nullptr;
+    MM_TRY(bj_apply(pl, r, z, c0));  // y in z
+    MM_TRY(coarse_w(pl, r, z, ctl.mask));
+    return by_layout<Adef2Finish>(pl, r, z, ctl);
+}
+
+// the A-DEF2 initial guess [App. B]: w = E^-1 Z^T r, x += Z w, r -= AZ w for every problem
+// (r = b - A x on entry), after which Z^T r = 0
+int coarse_start(mm_plan_t pl, double* x, double* r) {
+    PcgCtl c = batch_ctl(pl);
+    c.part = nullptr;
+    c.mask = nullptr;
+    MM_TRY(coarse_w(pl, r, nullptr, nullptr));
+    return by_layout<CoarseCorrect>(pl, x, r, c);
 }
 
 }  // namespace mm

@@ -185,8 +185,9 @@ struct Coarse {
     DBuf<int32_t> vslice;            // [r_eff+1] first Z^T r slice of every kept column
     int64_t n_slices = 0;            // slices of 512 entries over all kept columns
     DBuf<double> vpart;              // [n_slices] partial sums of Z^T r
-    DBuf<int64_t> ch_off;            // Z_D: [B+1] first Z^T r chunk of every problem
-    DBuf<double> cpart;              // Z_D: [n_chunks][r_max] chunk partials of Z^T r
+    DBuf<int64_t> ch_off;            // [B+1] first chunk (kZtChunk vector entries) of every problem
+    DBuf<double> cpart;              // Z_D: [r_max][n_chunks] chunk partials of Z^T r
+    DBuf<double> cpart2;             // [r_max][n_chunks] chunk partials of (AZ)^T y (A-DEF2)
     int64_t n_chunks = 0;
 };
 
@@ -264,14 +265,15 @@ struct mm_plan_s {
         double* alpha = nullptr;        // [B][hstride]
         int cap = 0;
     } krec;
-    // captured PCG iteration (one per operator precision / preconditioner)
+    // captured PCG iteration (one per operator precision / preconditioner MM_BJ, MM_2LVL,
+    // MM_ADEF2)
     hipStream_t gstream = nullptr;      // non-blocking stream the graphs are captured on
-    hipGraphExec_t gexec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    hipGraphExec_t gexec[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
     struct GraphKey {          // control arguments baked into a captured iteration
         int replace = -1;
         double ratio = 0.0;
         int max_iter = 0;
-    } gkey[2][2];
+    } gkey[2][3];
     double plan_ms = 0.0;
     // optional event timing of the hot kernels
     bool prof_on = false;
@@ -342,6 +344,10 @@ int build_coarse_dense(mm_plan_t pl, const double* basis, int64_t basis_stride,
                        const std::vector<std::vector<double>>& G, const std::vector<int>& m,
                        const std::vector<std::vector<double>>& theta);
 int twolvl_apply(mm_plan_t pl, const double* r, double* z, const PcgCtl& ctl);
+// A-DEF2 preconditioner z = R^T M_BD r + Z E^-1 Z^T r (partials of r^T z as ctl asks)
+int adef2_apply(mm_plan_t pl, const double* r, double* z, const PcgCtl& ctl);
+// A-DEF2 initial guess: x += Z E^-1 Z^T r, r -= AZ E^-1 Z^T r (r = b - A x on entry)
+int coarse_start(mm_plan_t pl, double* x, double* r);
 // the kept Z_D blocks, FP64, into out (h_az_off[B] values)
 int coarse_dense_columns(mm_plan_t pl, double* out);
 
