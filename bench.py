@@ -61,12 +61,16 @@ def fft_tile_flops(offsets, lam, n_r):
 # The figures hold only for the kernel source they were taken on (sha256 below); after any
 # change to that file the traffic is reported as null until the counters are taken again.
 TRAFFIC = {
+    # per FP32 tile length n_r (the plan's autotuner picks 8192 or 16384 on this workload)
     "ninv32": dict(source="paper_1408_3048_amd/csrc/toeplitz.hip",
-                   sha256="7acc442ffd2ddd79eeef1f101af789d21f781b0078a6aa8dd923d09a3d7ce73c",
-                   fetch_kib=286084.8125, write_kib=65536.0, fetch_factor=2.0, write_factor=1.0),
+                   sha256="4a2295e4d14a4905262587817345b7d44ec1c2440df236224619242f7b723e75",
+                   by_n_r={8192: dict(fetch_kib=295064.25, write_kib=65536.0),
+                           16384: dict(fetch_kib=202422.9375, write_kib=65578.625)},
+                   fetch_factor=2.0, write_factor=1.0),
     "pt32": dict(source="paper_1408_3048_amd/csrc/pointing.hip",
                  sha256="53f8c7d69fb28776fe71aa5f890c9f8c5c35f447a3b70c724a45cf164829388d",
-                 fetch_kib=152719.8125, write_kib=6798.66, fetch_factor=2.0, write_factor=1.0),
+                 by_n_r={None: dict(fetch_kib=152702.8125, write_kib=6798.71875)},
+                 fetch_factor=2.0, write_factor=1.0),
 }
 
 
@@ -188,16 +192,18 @@ def multi_rhs_leg(pix, w, sc, psd, m, noise, tol, n_rhs, autotune, krylov_dim=25
     return out
 
 
-def kernel_traffic(name):
-    """HBM bytes per launch of a kernel from the stored counter figures, or None when its
-    source has changed since they were taken."""
+def kernel_traffic(name, n_r=None):
+    """HBM bytes per launch of a kernel from the stored counter figures (for FFT tile length
+    n_r where they depend on it), or None when its source has changed since they were taken
+    or no figures exist for that configuration."""
     t = TRAFFIC[name]
-    if t["sha256"] is None:
+    c = t["by_n_r"].get(n_r if n_r in t["by_n_r"] else None)
+    if t["sha256"] is None or c is None:
         return None
     with open(os.path.join(ROOT, t["source"]), "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != t["sha256"]:
             return None
-    return round(1024 * (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"]))
+    return round(1024 * (c["fetch_kib"] * t["fetch_factor"] + c["write_kib"] * t["write_factor"]))
 
 
 def copy_calibration():
@@ -330,11 +336,11 @@ def main():
                    speedup_of_mixed_2lvl=float(np.mean(rtimes)) / t_step,
                    map_rel_diff_mixed_vs_fp64=map_diff, fp64_kernels=ax64)
 
-    # iteration counts of the other two combinations (one untimed run each, for context)
+    # the other combinations, incl. the A-DEF2 variant (one run each, for context)
     legs = {}
     if not args.no_reference:
-        for prec, pc in (("fp64", "2lvl"), ("mixed", "bj")):
-            tt, _, ex, _ = step(prec, pc == "2lvl", pc)
+        for prec, pc in (("fp64", "2lvl"), ("mixed", "bj"), ("mixed", "adef2")):
+            tt, _, ex, _ = step(prec, pc != "bj", pc)
             legs[f"{prec}_{pc}"] = dict(time_s=tt, **ex)
             log(f"{prec} {pc}: {tt * 1e3:.1f} ms {ex}")
 
@@ -348,7 +354,7 @@ def main():
     hbm = {
         "ninv32": dict(GBps=round(BYTES_NINV32 * sc.n_samples / (avg_ninv * 1e-3) / 1e9, 1),
                        algorithmic_bytes_per_launch=BYTES_NINV32 * sc.n_samples,
-                       traffic=kernel_traffic("ninv32"), avg_ms=round(avg_ninv, 5)),
+                       traffic=kernel_traffic("ninv32", n_r32), avg_ms=round(avg_ninv, 5)),
         "pt32": dict(GBps=round(BYTES_PT32 * sc.n_samples / (avg_pt * 1e-3) / 1e9, 1),
                      algorithmic_bytes_per_launch=BYTES_PT32 * sc.n_samples,
                      traffic=kernel_traffic("pt32"), avg_ms=round(avg_pt, 5),
@@ -360,7 +366,7 @@ def main():
         achieved = flops / (avg_ninv * 1e-3) / 1e12
         roof = dict(bound="alu", achieved=round(achieved, 2), peak=FP32_VALU_PEAK_TFLOPS,
                     unit="TFLOP/s", frac=round(achieved / FP32_VALU_PEAK_TFLOPS, 4),
-                    traffic=kernel_traffic("ninv32"),
+                    traffic=kernel_traffic("ninv32", n_r32),
                     kernel="k_toeplitz<float> (gather P + overlap-save N^-1)",
                     avg_launch_ms=round(avg_ninv, 5), launches=n_ninv, tiles=tiles, n_r=n_r32,
                     algorithmic_flops_per_launch=flops)
