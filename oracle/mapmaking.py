@@ -103,14 +103,16 @@ def inverse_psd(n, sigma, fknee, alpha, f_samp):
 
 
 def _window(k, lam, window):
+    """Apodisation window at lags k, |k| <= lam (App. D, eq. apodDef); every window is 1
+    at k = 0, so lam = 0 keeps the diagonal alone."""
     k = np.asarray(k, dtype=np.float64)
+    if window not in ("gauss", "gauss2", "rect"):
+        raise ValueError(window)
+    if lam == 0 or window == "rect":
+        return np.ones_like(k)
     if window == "gauss":
         return np.exp(-(k / lam) ** 2)
-    if window == "gauss2":
-        return np.exp(-2.0 * (k / lam) ** 2)
-    if window == "rect":
-        return np.ones_like(k)
-    raise ValueError(window)
+    return np.exp(-2.0 * (k / lam) ** 2)
 
 
 def toeplitz_taps(n, sigma, fknee, alpha, lam, f_samp, window="gauss"):

@@ -443,3 +443,67 @@ def test_deflation_space_two_level_properties():
     _, it_bj, _ = O.pcg(pr.apply_A, b2, pr.bj_apply, tol=1e-8, maxit=2000)
     x2, it_d, st = O.pcg(pr.apply_A, b2, co.apply, tol=1e-8, maxit=2000)
     assert st == 0 and it_d < it_bj
+
+
+# ------------------------------------------- bandwidth and apodisation (App. D)
+
+def _apodised_over_true(taps, f, fs, sigma, fknee, alpha):
+    k = np.arange(1, taps.shape[0])
+    s = taps[0] + 2.0 * np.sum(taps[1:] * np.cos(2.0 * np.pi * f / fs * k))
+    return s / (1.0 / (sigma ** 2 * (1.0 + (fknee / f) ** alpha)))
+
+
+def test_apodised_inverse_spectrum_deflects_below_f_defl():
+    """App. D / Fig. corrPlot: with the Gaussian window the band-limited inverse spectrum
+    follows 1/P(f) above a few f_defl = 1/(pi lambda t_samp) and is flattened (lifted far
+    above it) below f_defl; a narrower window (exp(-2 (k/lambda)^2)) deflects higher."""
+    fs, n = 200.0, 2 ** 16
+    for lam in (100, 500, 2000):
+        fd = fs / (np.pi * lam)
+        taps = O.toeplitz_taps(n, 1.0, 1.0, 2.0, lam, fs)
+        for m in (4, 8, 16):
+            assert abs(_apodised_over_true(taps, m * fd, fs, 1.0, 1.0, 2.0) - 1.0) <= 0.05
+        assert _apodised_over_true(taps, fd / 4, fs, 1.0, 1.0, 2.0) >= 5.0
+        assert _apodised_over_true(taps, fd / 8, fs, 1.0, 1.0, 2.0) >= 20.0
+        taps2 = O.toeplitz_taps(n, 1.0, 1.0, 2.0, lam, fs, window="gauss2")
+        assert (_apodised_over_true(taps2, fd, fs, 1.0, 1.0, 2.0)
+                > _apodised_over_true(taps, fd, fs, 1.0, 1.0, 2.0))
+
+
+def test_bandwidth_below_knee_scale_is_nearly_uniform_weighting():
+    """App. D: lambda = 1/(pi t_samp f_knee) is the largest bandwidth that is still about
+    as good as uniform (white-noise) weighting: the apodised inverse spectrum varies by
+    less than a factor 4 over all frequencies, while 16 times that bandwidth resolves the
+    1/f fall-off (a factor above 25)."""
+    fs, n = 200.0, 2 ** 16
+    for fk, al in ((1.0, 2.0), (5.0, 2.0), (1.0, 1.0), (0.5, 1.5)):
+        lam0 = fs / (np.pi * fk)
+        narrow = O.taps_symbol(O.toeplitz_taps(n, 1.0, fk, al, int(round(lam0)), fs), 4096)
+        wide = O.taps_symbol(O.toeplitz_taps(n, 1.0, fk, al, int(round(16 * lam0)), fs), 4096)
+        assert narrow.max() / narrow.min() <= 4.0, (fk, al)
+        assert wide.max() / wide.min() >= 25.0, (fk, al)
+
+
+def test_zero_bandwidth_is_white_noise_weighting():
+    """lambda = 0 keeps only t_0 = the mean of the inverse PSD on the interval's grid (the
+    window is 1 at lag 0): N^-1 is diagonal, M_BD = A^-1 (one PCG step), and the map is the
+    per-pixel noise-weighted least-squares co-addition written out directly."""
+    sc = tiny_iqu(fknee=(1.0, 3.0), lam=0)
+    pr = O.Problem.from_scan(sc)
+    for j, t in enumerate(pr.taps):
+        n = int(sc.offsets[j + 1] - sc.offsets[j])
+        q = O.inverse_psd(n, sc.sigma[j], sc.fknee[j], sc.alpha[j], sc.f_samp)
+        full = np.concatenate([q, q[1:(n + 1) // 2][::-1]])  # the n-point spectrum
+        assert t.shape == (1,) and t[0] == pytest.approx(full.mean(), rel=1e-12)
+    d = pr.signal(sc.sky) + sc.noise
+    b = pr.rhs(d)
+    x, it, st = O.pcg(pr.apply_A, b, pr.bj_apply, tol=1e-12, maxit=10)
+    assert st == 0 and it == 1
+    w_t = np.concatenate([np.full(int(sc.offsets[j + 1] - sc.offsets[j]), pr.taps[j][0])
+                          for j in range(len(pr.taps))])
+    ref = np.empty((pr.n_obs, 3))
+    for p in range(pr.n_obs):
+        s = pr.cid == p
+        Wp = pr.W[s]
+        ref[p] = np.linalg.solve(Wp.T @ (w_t[s, None] * Wp), Wp.T @ (w_t[s] * d[s]))
+    assert np.linalg.norm(x - ref.ravel()) / np.linalg.norm(ref) <= 1e-11
