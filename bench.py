@@ -192,6 +192,39 @@ def multi_rhs_leg(pix, w, sc, psd, m, noise, tol, n_rhs, autotune, krylov_dim=25
     return out
 
 
+def bandwidth_leg(pix, w, sc, psd, m, d, tol, lams, autotune):
+    """The bandwidth study on the same data (Sect. 4.2, Fig. conv_lambda; App. D): for
+    every half-bandwidth lambda (0 = white-noise weighting) a mixed plan with Z_S, then the
+    mixed block-Jacobi and two-level solves: iterations, solve time, time per iteration and
+    the map's distance from the input sky; the same at lambda = 2048 for the narrower
+    Gaussian and the rectangular window."""
+    import torch
+    from paper_1408_3048_amd import Plan
+    out = []
+    mn = float(m.norm())
+    cases = [(lam, "gauss") for lam in lams] + [(2048, "gauss2"), (2048, "rect")]
+    for lam, window in cases:
+        plan = Plan(pix, w, sc.n_pix, sc.offsets, psd, n_stokes=3, lam=lam, f_samp=sc.f_samp,
+                    window=window, precision="mixed", coarse=True, autotune=autotune)
+        b = plan.rhs(d)
+        row = dict(lam=lam, window=window, plan_ms=round(plan.plan_ms, 2),
+                   fft_lengths=plan.fft_lengths(), r_eff=plan.coarse_rank())
+        for pc in ("bj", "2lvl"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, info = plan.pcg_solve(b, precond=pc, precision="mixed", tol=tol, max_iter=5000,
+                                     history=False)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0)
+            row[pc] = dict(iterations=info["iterations"], solve_ms=round(ms, 2),
+                           ms_per_iteration=round(ms / max(info["iterations"], 1), 4),
+                           map_err=round(float((x - m).norm()) / mn, 6))
+        log(f"bandwidth: {row}")
+        out.append(row)
+        plan.close()
+    return out
+
+
 def kernel_traffic(name, n_r=None):
     """HBM bytes per launch of a kernel from the stored counter figures (for FFT tile length
     n_r where they depend on it), or None when its source has changed since they were taken
@@ -235,6 +268,8 @@ def main():
     ap.add_argument("--no-reference", action="store_true", help="skip the FP64 block-Jacobi leg")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 256-problem batched Monte Carlo leg")
+    ap.add_argument("--bandwidth", default="0,64,256,1024,2048,4096",
+                    help="half-bandwidths of the bandwidth-study leg ('' skips it)")
     ap.add_argument("--multi-rhs", type=int, default=8,
                     help="right-hand sides of the plan-reuse leg (0 skips it)")
     ap.add_argument("--autotune", type=int, default=1,
@@ -386,6 +421,11 @@ def main():
         multi = multi_rhs_leg(pix, w, sc, psd, m, torch.from_numpy(sc.noise).cuda(), args.tol,
                               args.multi_rhs, bool(args.autotune))
 
+    bandwidth = None
+    if args.bandwidth and not args.no_reference:
+        lams = [int(v) for v in args.bandwidth.split(",")]
+        bandwidth = bandwidth_leg(pix, w, sc, psd, m, d, args.tol, lams, bool(args.autotune))
+
     batched = None
     if not args.no_batched:
         batched = batched_leg(args.tol)
@@ -408,7 +448,8 @@ def main():
                               "lambda=2048, mixed FP32/FP64 two-level PCG to 1e-8 incl. plan"),
                     n_samples=sc.n_samples, unknowns=extras[-1]["unknowns"],
                     tol=args.tol, parallelism="single GPU"),
-        breakdown=extras[-1], reference=ref, other_legs=legs, multi_rhs=multi, batched=batched,
+        breakdown=extras[-1], reference=ref, other_legs=legs, multi_rhs=multi,
+        bandwidth=bandwidth, batched=batched,
         roofline=roof,
         cpu_baseline=cpu,
     )

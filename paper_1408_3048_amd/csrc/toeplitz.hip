@@ -115,6 +115,16 @@ __global__ void k_cos_transform(const double* __restrict__ a, const int64_t* __r
     if (j < J) out[ooff[g] + j] = acc;
 }
 
+// apodisation window at lag k (0 <= k <= lambda) [App. D, eq. apodDef]: 1 at k = 0 for
+// every window, so lambda = 0 keeps t_0 alone (a diagonal N^-1)
+__device__ __forceinline__ double window_at(int64_t k, int lam, int window) {
+    if (k == 0) return 1.0;
+    const double x = (double)k / (double)lam;
+    if (window == MM_WIN_GAUSS) return exp(-x * x);
+    if (window == MM_WIN_GAUSS2) return exp(-2.0 * x * x);
+    return 1.0;
+}
+
 __global__ void k_taps_finish(double* __restrict__ t, const int64_t* __restrict__ toff,
                               const int64_t* __restrict__ tcnt, const int32_t* __restrict__ klen,
                               int lam, int window, int32_t nk) {
@@ -122,11 +132,7 @@ __global__ void k_taps_finish(double* __restrict__ t, const int64_t* __restrict_
     if (g >= nk) return;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < tcnt[g];
          k += (int64_t)gridDim.x * blockDim.x) {
-        double w = 1.0;
-        const double x = (double)k / (double)lam;
-        if (window == MM_WIN_GAUSS) w = exp(-x * x);
-        else if (window == MM_WIN_GAUSS2) w = exp(-2.0 * x * x);
-        t[toff[g] + k] *= w / (double)klen[g];
+        t[toff[g] + k] *= window_at(k, lam, window) / (double)klen[g];
     }
 }
 
@@ -729,11 +735,7 @@ __global__ void k_taps_sum(const int32_t* __restrict__ kid, const int32_t* __res
          k += (int64_t)gridDim.x * blockDim.x) {
         double s = 0.0;
         for (int b = 0; b < R; ++b) s += part[((int64_t)gi * rmax + b) * kstride + k];
-        double w = 1.0;
-        const double x = (double)k / (double)lam;
-        if (window == MM_WIN_GAUSS) w = exp(-x * x);
-        else if (window == MM_WIN_GAUSS2) w = exp(-2.0 * x * x);
-        t[toff[g] + k] = s * w / (double)n;
+        t[toff[g] + k] = s * window_at(k, lam, window) / (double)n;
     }
 }
 
