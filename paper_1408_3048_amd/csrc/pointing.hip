@@ -124,8 +124,19 @@ __device__ __forceinline__ void seg_reduce(int64_t i0, int64_t i1, int64_t p0,
     }
 }
 
-// x[p, s] = sum_{t in p} W[t, s] z_t (P^T), E samples per lane (a multiple of 4): one
-// chunk of 64 E samples keeps E gathers of z per lane in flight
+// LDS exchange among the lanes of one wave: orders the wave's LDS writes before its reads
+// (a wave's LDS instructions execute in order; this keeps the compiler from moving them)
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// x[p, s] = sum_{t in p} W[t, s] z_t (P^T), E samples per lane (a multiple of 4).  The z
+// gather of a chunk of 64 E sorted samples is issued lane-strided (one instruction covers
+// 64 consecutive sorted samples, i.e. a few runs of consecutive time samples, so few cache
+// lines) and handed to the lane layout of the segmented reduction (E consecutive samples
+// per lane) through LDS; the additions are unchanged.
 template <typename T, int NS, int E>
 __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ perm,
                                                  const T* __restrict__ ws, const T* __restrict__ z,
@@ -137,33 +148,40 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ per
                                                  const int* __restrict__ mask,
                                                  const int32_t* __restrict__ wave_prob) {
     static_assert(E % 4 == 0, "E must be a multiple of 4");
+    __shared__ __align__(16) T zx[4][64 * E];
     const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (w >= n_waves) return;
     if (mask && !mask[wave_prob[w]]) return;
     const int32_t p0 = wave_pix[w], p1 = wave_pix[w + 1];
     if (p0 >= p1) return;
+    const int64_t i0 = seg[p0];
     const int64_t i1 = seg[p1 - 1] + hits[p1 - 1];
+    const int lane = threadIdx.x & 63;
+    T* zw = zx[threadIdx.x >> 6];
     auto load = [&](int64_t base, const bool* valid, T (*v)[NS]) {
-        if (base >= i1) {  // whole lane past the range: no loads
+        // every lane takes part in the exchange, also lanes past the range
+        const int64_t c = base - (int64_t)E * lane;
+#pragma unroll
+        for (int g = 0; g < E; ++g) {
+            const int64_t i = c + lane + 64 * g;
+            T zg = (T)0;
+            if (i >= i0 && i < i1) zg = z[perm[i]];
+            zw[lane + 64 * g] = zg;
+        }
+        wave_lds_sync();
+        T zz[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) zz[e] = zw[E * lane + e];
+        wave_lds_sync();  // the next chunk's writes come after these reads
+        if (base >= i1) {  // whole lane past the range
 #pragma unroll
             for (int e = 0; e < E; ++e)
 #pragma unroll
                 for (int q = 0; q < NS; ++q) v[e][q] = (T)0;
             return;
         }
-        // aligned vector loads; perm and ws carry a zeroed tail of 8 samples
-        int tt[E];
 #pragma unroll
-        for (int g = 0; g < E / 4; ++g) {
-            const int4 t4 = *reinterpret_cast<const int4*>(perm + base + 4 * g);
-            tt[4 * g] = t4.x;
-            tt[4 * g + 1] = t4.y;
-            tt[4 * g + 2] = t4.z;
-            tt[4 * g + 3] = t4.w;
-        }
-        T zz[E];
-#pragma unroll
-        for (int e = 0; e < E; ++e) zz[e] = valid[e] ? z[tt[e]] : (T)0;
+        for (int e = 0; e < E; ++e) zz[e] = valid[e] ? zz[e] : (T)0;
         if constexpr (NS == 3) {
             T wv[2 * E];
             if constexpr (sizeof(T) == 4) {
@@ -198,7 +216,7 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ per
 #pragma unroll
         for (int q = 0; q < NS; ++q) out[pix * NS + q] = (double)tot[q];
     };
-    seg_reduce<T, NS, E>(seg[p0], i1, p0, heads, load, emit);
+    seg_reduce<T, NS, E>(i0, i1, p0, heads, load, emit);
 }
 
 // y_t = sum_s W[t, s] x[c(t), s]
