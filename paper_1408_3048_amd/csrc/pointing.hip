@@ -158,16 +158,25 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ per
     const int64_t i1 = seg[p1 - 1] + hits[p1 - 1];
     const int lane = threadIdx.x & 63;
     T* zw = zx[threadIdx.x >> 6];
-    auto load = [&](int64_t base, const bool* valid, T (*v)[NS]) {
-        // every lane takes part in the exchange, also lanes past the range
-        const int64_t c = base - (int64_t)E * lane;
+    // sample indices of the next chunk, loaded one chunk ahead (-1 outside [i0, i1))
+    int32_t pf[E];
+    auto fetch = [&](int64_t c) {
 #pragma unroll
         for (int g = 0; g < E; ++g) {
             const int64_t i = c + lane + 64 * g;
-            T zg = (T)0;
-            if (i >= i0 && i < i1) zg = z[perm[i]];
-            zw[lane + 64 * g] = zg;
+            pf[g] = i >= i0 && i < i1 ? perm[i] : -1;
         }
+    };
+    fetch(i0 & ~(int64_t)(E - 1));
+    auto load = [&](int64_t base, const bool* valid, T (*v)[NS]) {
+        // every lane takes part in the exchange, also lanes past the range
+        const int64_t c = base - (int64_t)E * lane;
+        int32_t tc[E];
+#pragma unroll
+        for (int g = 0; g < E; ++g) tc[g] = pf[g];
+        fetch(c + 64 * E);
+#pragma unroll
+        for (int g = 0; g < E; ++g) zw[lane + 64 * g] = tc[g] >= 0 ? z[tc[g]] : (T)0;
         wave_lds_sync();
         T zz[E];
 #pragma unroll
