@@ -472,6 +472,10 @@ int build_pointing(mm_plan_t pl, const int32_t* pix, const void* weights, int wd
     int64_t n_obs = 0;
     MM_HIP(hipMemcpy(&n_obs, pos.p + pl->n_pix, sizeof(int64_t), hipMemcpyDeviceToHost));
     pl->n_obs = n_obs;
+    if (n_obs >= ((int64_t)1 << 27)) {  // the map gathers use 32-bit byte offsets
+        set_error("%lld observed pixels: at most 2^27 - 1 supported", (long long)n_obs);
+        return MM_ERR_ARG;
+    }
     // compact pixel offsets of the problems: observed pixels below each problem's first id
     pl->h_ooff.assign(B + 1, n_obs);
     for (int b = 0; b < B; ++b)

@@ -536,48 +536,58 @@ __device__ __forceinline__ bool load_window(const ToepArgs<T>& a, const CBuf<T>&
     static_assert(NT % 2 == 0, "even thread count");
     // point (tid + c NT) / 2 = tid / 2 + c NT / 2 with bit-disjoint terms
     const int sbase = swz(threadIdx.x >> 1), part = threadIdx.x & 1;
+    // indices relative to the window start (a block-uniform base): window positions
+    // [i_lo, i_hi) lie inside the interval; others read position i_lo (inside the
+    // interval, since the window ends past it) and are masked.  32-bit unsigned offsets
+    // from uniform bases keep the address arithmetic out of 64-bit vector instructions.
+    const int i_lo = (int)(lo > base ? lo - base : 0);
+    const int i_hi = (int)(hi - base < (int64_t)win ? hi - base : (int64_t)win);
     bool nz = false;
 #pragma unroll
     for (int b0 = 0; b0 < PER; b0 += B) {
-        int32_t tt[B];  // sample indices (n_samples < 2^31)
+        uint32_t rr[B];
         bool ok[B];
 #pragma unroll
         for (int u = 0; u < B; ++u) {
             const int i = threadIdx.x + (b0 + u) * NT;
-            const int64_t t = base + i;
-            ok[u] = i < win && t >= lo && t < hi;
-            tt[u] = (int32_t)(ok[u] ? t : lo);
+            ok[u] = i >= i_lo && i < i_hi;
+            rr[u] = (uint32_t)(ok[u] ? i : i_lo);
         }
         T v[B];
         if constexpr (MODE == 0) {  // map, I/Q/U: one packed-map gather per sample
             typedef typename std::conditional<sizeof(T) == 4, float4, double4>::type T4;
             typedef typename std::conditional<sizeof(T) == 4, float2, double2>::type T2;
-            int32_t cc[B];
+            const int32_t* cb = a.cid + base;
+            const T2* wb = reinterpret_cast<const T2*>(a.w) + base;
+            const char* xpb = reinterpret_cast<const char*>(a.xp);
+            uint32_t cc[B];
             T2 ww[B];
 #pragma unroll
-            for (int u = 0; u < B; ++u) cc[u] = a.cid[tt[u]];
+            for (int u = 0; u < B; ++u) cc[u] = (uint32_t)cb[rr[u]];
 #pragma unroll
-            for (int u = 0; u < B; ++u) ww[u] = reinterpret_cast<const T2*>(a.w)[tt[u]];
-            T4 xx[B];
+            for (int u = 0; u < B; ++u) ww[u] = wb[rr[u]];
+            T4 xx[B];  // byte offsets of the packed map fit 32 bits (n_obs < 2^27)
 #pragma unroll
-            for (int u = 0; u < B; ++u) xx[u] = reinterpret_cast<const T4*>(a.xp)[cc[u]];
+            for (int u = 0; u < B; ++u)
+                xx[u] = *reinterpret_cast<const T4*>(xpb + cc[u] * (uint32_t)sizeof(T4));
 #pragma unroll
             for (int u = 0; u < B; ++u)
                 v[u] = ok[u] ? xx[u].x + ww[u].x * xx[u].y + ww[u].y * xx[u].z : (T)0;
         } else if constexpr (MODE == 1) {  // map, I only
+            const int32_t* cb = a.cid + base;
             int32_t cc[B];
 #pragma unroll
-            for (int u = 0; u < B; ++u) cc[u] = a.cid[tt[u]];
+            for (int u = 0; u < B; ++u) cc[u] = cb[rr[u]];
 #pragma unroll
             for (int u = 0; u < B; ++u) v[u] = ok[u] ? (T)a.x[cc[u]] : (T)0;
         } else if constexpr (MODE == 2) {  // TOD, FP64
-            const double* y = (const double*)a.y;
+            const double* y = (const double*)a.y + base;
 #pragma unroll
-            for (int u = 0; u < B; ++u) v[u] = ok[u] ? (T)y[tt[u]] : (T)0;
+            for (int u = 0; u < B; ++u) v[u] = ok[u] ? (T)y[rr[u]] : (T)0;
         } else {  // TOD, FP32
-            const float* y = (const float*)a.y;
+            const float* y = (const float*)a.y + base;
 #pragma unroll
-            for (int u = 0; u < B; ++u) v[u] = ok[u] ? (T)y[tt[u]] : (T)0;
+            for (int u = 0; u < B; ++u) v[u] = ok[u] ? (T)y[rr[u]] : (T)0;
         }
 #pragma unroll
         for (int u = 0; u < B; ++u) {
@@ -628,7 +638,9 @@ __global__ __launch_bounds__(NT, (tile_waves_per_simd<T, LOGM, NT>())) void k_to
     fwd_passes<T, LOGM, NT, LOGM>(buf, a.tw);
     spectrum_pass<T, LOGM, NT>(buf, a.H + (int64_t)a.int_kern[j] * (M + 1), a.tw);
     inv_passes<T, LOGM, NT, LOGM>(buf, a.tw);
-    for (int i = lam + threadIdx.x; i < lam + L; i += NT) a.z[o + (i - lam)] = buf.get_part(i >> 1, i & 1);
+    T* zo = a.z + o;  // block-uniform base, 32-bit offsets
+    for (int i = lam + threadIdx.x; i < lam + L; i += NT)
+        zo[(uint32_t)(i - lam)] = buf.get_part(i >> 1, i & 1);
 }
 
 // ------------------------------------------------------------------ plan-time FFTs (FP64)
