@@ -9,6 +9,8 @@
   most and least observed ones.
 - The 256-problem batched Monte Carlo plan: A x at sampled pixels of several problems.
 - The 2^22-sample case of the differentiated solve: A x at sampled pixels.
+- The a posteriori coarse space and A-DEF2 on the 2^24-sample raster (properties that hold
+  at any size: the deflation property, iteration counts, residuals).
 """
 
 import functools
@@ -134,4 +136,32 @@ def test_cfg5_fullsize_sampled_operator():
     pixels = rng.choice(pr.n_obs, 24, replace=False)
     e64, e32 = _sampled_A(pl, pr, x, pixels, 3)
     assert e64 <= 1e-11 and e32 <= 5e-5, (e64, e32)
+    pl.close()
+
+
+def test_cfg2_fullsize_a_posteriori_and_adef2():
+    """2^24 samples, mixed plan: Z_D from the FP64 block-Jacobi solve of one right-hand
+    side (M_2lvl,D A z = z for sampled columns, a second right-hand side in fewer
+    iterations than block Jacobi), and A-DEF2 with Z_S in as many iterations as A-DEF1."""
+    sc, pr = cfg2()
+    pl = Plan.from_scan(sc, precision="mixed", coarse=True, autotune=True)
+    noise = torch.from_numpy(sc.noise).cuda()
+    m = torch.from_numpy(pr.sky_to_compact(sc.sky)).cuda()
+    sig = pl.apply_P(m)
+    b2 = pl.rhs(sig + torch.roll(noise, 7919))
+    _, i1 = pl.pcg_solve(b2, precond="2lvl", precision="mixed", tol=1e-8, max_iter=3000)
+    _, i2 = pl.pcg_solve(b2, precond="adef2", precision="mixed", tol=1e-8, max_iter=3000)
+    assert i2["rel_residual"] <= 1e-8 and abs(i1["iterations"] - i2["iterations"]) <= 2
+    _, ib = pl.pcg_solve(b2, precond="bj", precision="mixed", tol=1e-8, max_iter=3000)
+    x, info = pl.coarse_from_krylov(pl.rhs(sig + noise), tol=1e-8, max_iter=3000,
+                                    krylov_dim=256, eps_tol=0.2)
+    assert pl.coarse_kind() == 2 and pl.coarse_rank() >= 5
+    assert info["rel_residual"] <= 1e-8
+    (Z,) = pl.dense_columns()
+    for i in (0, Z.shape[0] - 1):  # FP32 Z_D and AZ_D: deflation property to FP32 accuracy
+        z = Z[i].contiguous()
+        w = pl.precond_2lvl(pl.apply_A(z, precision="mixed"))
+        assert _rel(w.cpu().numpy(), z.cpu().numpy()) <= 1e-4, i
+    xd, idd = pl.pcg_solve(b2, precond="2lvl", precision="mixed", tol=1e-8, max_iter=3000)
+    assert idd["rel_residual"] <= 1e-8 and idd["iterations"] < ib["iterations"]
     pl.close()
