@@ -63,13 +63,13 @@ def fft_tile_flops(offsets, lam, n_r):
 TRAFFIC = {
     # per FP32 tile length n_r (the plan's autotuner picks 8192 or 16384 on this workload)
     "ninv32": dict(source="paper_1408_3048_amd/csrc/toeplitz.hip",
-                   sha256="4a2295e4d14a4905262587817345b7d44ec1c2440df236224619242f7b723e75",
-                   by_n_r={8192: dict(fetch_kib=295064.25, write_kib=65536.0),
-                           16384: dict(fetch_kib=202422.9375, write_kib=65578.625)},
+                   sha256="2f4ffbd6a8abe84708f8aaac60f19ba849da8dbf4b6512fc8c791ee58e88e8ac",
+                   by_n_r={8192: dict(fetch_kib=294641.8125, write_kib=65536.0),
+                           16384: dict(fetch_kib=202661.625, write_kib=65579.46875)},
                    fetch_factor=2.0, write_factor=1.0),
     "pt32": dict(source="paper_1408_3048_amd/csrc/pointing.hip",
-                 sha256="53f8c7d69fb28776fe71aa5f890c9f8c5c35f447a3b70c724a45cf164829388d",
-                 by_n_r={None: dict(fetch_kib=152702.8125, write_kib=6798.71875)},
+                 sha256="a5f64bd660c1d6a112cbfd051a13a9a503f95f66bb552a96563dd814c32aa466",
+                 by_n_r={None: dict(fetch_kib=152901.75, write_kib=6762.59375)},
                  fetch_factor=2.0, write_factor=1.0),
 }
 
