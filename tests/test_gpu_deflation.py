@@ -216,3 +216,38 @@ def test_no_ritz_value_below_threshold_keeps_coarse_space():
     x, info = pl.pcg_solve(dev(b), precond="2lvl", tol=TOL, max_iter=3000)
     assert info["rel_residual"] <= TOL
     pl.close()
+
+
+def test_truncated_basis_cap_and_unconverged_recording():
+    """krylov_dim keeps the first steps only: the Ritz values are those of the leading
+    block of the oracle's Lanczos matrix; max_cols keeps the smallest; a recording solve
+    stopped by max_iter reports MM_ERR_NOCONV and still installs Z_D; bad arguments are
+    rejected before any device work."""
+    from paper_1408_3048_amd import MM_ERR_ARG, MM_ERR_NOCONV
+    sc = scan()
+    pr, b, x_o, m, th_o, Y_o, est = oracle_run()
+    Bk = pr.bj_blocks()
+    _, al, rz, _ = O.pcg_lanczos(pr.apply_A, b, lambda r: pr.bj_apply(r, Bk), TOL, 3000)
+    k = 20
+    T = O.lanczos_tridiagonal(al[:k], rz[:k + 1])
+    ev = np.linalg.eigvalsh(T)
+    ev = ev[ev < EPS_TOL]
+    pl = Plan.from_scan(sc)
+    pl.coarse_from_krylov(dev(b), tol=TOL, max_iter=3000, krylov_dim=k, eps_tol=EPS_TOL)
+    th = pl.ritz_values()
+    assert th.shape == ev.shape and np.max(np.abs(th - ev) / ev) <= 1e-8
+    pl.coarse_from_krylov(dev(b), tol=TOL, max_iter=3000, eps_tol=EPS_TOL, max_cols=5)
+    assert np.max(np.abs(pl.ritz_values() - th_o[:5]) / th_o[:5]) <= 1e-8
+    x, info = pl.coarse_from_krylov(dev(b), tol=TOL, max_iter=k, eps_tol=EPS_TOL,
+                                    raise_on_error=False)
+    assert info["status"] == MM_ERR_NOCONV and info["iterations"] == k
+    assert pl.coarse_kind() == 2 and pl.coarse_rank() == th.shape[0]
+    for bad in (dict(tol=0.0), dict(max_iter=0), dict(eps_tol=-1.0), dict(krylov_dim=-1),
+                dict(max_cols=-2)):
+        kw = dict(tol=TOL, max_iter=100, eps_tol=EPS_TOL)
+        kw.update(bad)
+        with pytest.raises(MMError) as e:
+            pl.coarse_from_krylov(dev(b), **kw)
+        assert e.value.status == MM_ERR_ARG, bad
+    assert pl.coarse_kind() == 2
+    pl.close()
