@@ -440,20 +440,21 @@ __device__ __forceinline__ void dit_pass(const CBuf<T>& buf, const T* __restrict
     __syncthreads();
 }
 
-template <typename T, int LOGM, int NT, int LOGB>
+// STOP = 1: the last radix-2 stage (LOGB == 1) is left to the fused spectrum pass
+template <typename T, int LOGM, int NT, int LOGB, int STOP = 0>
 __device__ __forceinline__ void fwd_passes(const CBuf<T>& buf, const T* tw) {
-    if constexpr (LOGB > 0) {
+    if constexpr (LOGB > STOP) {
         constexpr int LR = LOGB >= 4 ? 4 : LOGB;
         dif_pass<T, LOGM, NT, LR, LOGB>(buf, tw);
-        fwd_passes<T, LOGM, NT, LOGB - LR>(buf, tw);
+        fwd_passes<T, LOGM, NT, LOGB - LR, STOP>(buf, tw);
     }
 }
 
-template <typename T, int LOGM, int NT, int LOGB>
+template <typename T, int LOGM, int NT, int LOGB, int STOP = 0>
 __device__ __forceinline__ void inv_passes(const CBuf<T>& buf, const T* tw) {
-    if constexpr (LOGB > 0) {
+    if constexpr (LOGB > STOP) {
         constexpr int LR = LOGB >= 4 ? 4 : LOGB;
-        inv_passes<T, LOGM, NT, LOGB - LR>(buf, tw);
+        inv_passes<T, LOGM, NT, LOGB - LR, STOP>(buf, tw);
         dit_pass<T, LOGM, NT, LR, LOGB>(buf, tw);
     }
 }
@@ -512,6 +513,105 @@ __device__ __forceinline__ void spectrum_pass(const CBuf<T>& buf, const T* __res
             pim = fr * Di - fi * Dr;
             buf.put(am, Ar - pim, Ai + pr);
         }
+    }
+    __syncthreads();
+}
+
+// For LOGM = 1 mod 4 the forward transform ends and the inverse starts with a radix-2
+// stage on adjacent slots (2j, 2j + 1), which hold the frequencies f and f + M/2 after the
+// stage (f = rev(2j)).  The slots {rev(k), rev(k) ^ 1, rev(M - k), rev(M - k) ^ 1} carry the
+// frequencies k, M/2 + k, M - k and M/2 - k: the two spectrum pairs (k, M - k) and
+// (M/2 + k, M/2 - k).  This pass takes such a group (k = 0 .. M/4) through the forward
+// radix-2 stage, the spectrum product of both pairs and the inverse radix-2 stage, which
+// saves two passes over LDS and two barriers; the arithmetic is that of the three passes.
+template <typename T, int LOGM, int NT>
+__device__ __forceinline__ void spectrum_pass_r2(const CBuf<T>& buf, const T* __restrict__ H,
+                                                 const T* __restrict__ tw) {
+    constexpr int M = 1 << LOGM;
+    // spectrum product of the pair (k, km), k != km, 0 < k < M
+    auto pair = [&](int k, int km, T zkr, T zki, T zmr, T zmi, T& ykr_o, T& yki_o, T& ymr_o,
+                    T& ymi_o) {
+        const T er = tw[2 * k], ei = tw[2 * k + 1];
+        const T fr = tw[2 * km], fi = tw[2 * km + 1];
+        T Ar = zkr + zmr, Ai = zki - zmi, Dr = zkr - zmr, Di = zki + zmi;
+        T pr = er * Dr - ei * Di, pim = er * Di + ei * Dr;
+        const T xkr = Ar + pim, xki = Ai - pr;
+        Ar = zmr + zkr;
+        Ai = zmi - zki;
+        Dr = zmr - zkr;
+        Di = zmi + zki;
+        pr = fr * Dr - fi * Di;
+        pim = fr * Di + fi * Dr;
+        const T xmr = Ar + pim, xmi = Ai - pr;
+        const T hk = H[k], hm = H[km];
+        const T ykr = hk * xkr, yki = hk * xki, ymr = hm * xmr, ymi = hm * xmi;
+        Ar = ykr + ymr;
+        Ai = yki - ymi;
+        Dr = ykr - ymr;
+        Di = yki + ymi;
+        pr = er * Dr + ei * Di;
+        pim = er * Di - ei * Dr;
+        ykr_o = Ar - pim;
+        yki_o = Ai + pr;
+        Ar = ymr + ykr;
+        Ai = ymi - yki;
+        Dr = ymr - ykr;
+        Di = ymi + yki;
+        pr = fr * Dr + fi * Di;
+        pim = fr * Di - fi * Dr;
+        ymr_o = Ar - pim;
+        ymi_o = Ai + pr;
+    };
+    // spectrum product of the self-paired frequency k = M/2
+    auto self = [&](T zr, T zi, T& yr_o, T& yi_o) {
+        constexpr int k = M / 2;
+        const T er = tw[2 * k], ei = tw[2 * k + 1];
+        T Ar = zr + zr, Ai = zi - zi, Dr = zr - zr, Di = zi + zi;
+        T pr = er * Dr - ei * Di, pim = er * Di + ei * Dr;
+        const T xkr = Ar + pim, xki = Ai - pr;
+        const T hk = H[k];
+        const T ykr = hk * xkr, yki = hk * xki;
+        Ar = ykr + ykr;
+        Ai = yki - yki;
+        Dr = ykr - ykr;
+        Di = yki + yki;
+        pr = er * Dr + ei * Di;
+        pim = er * Di - ei * Dr;
+        yr_o = Ar - pim;
+        yi_o = Ai + pr;
+    };
+    for (int k = threadIdx.x; k <= M / 4; k += NT) {
+        const int a = rev_bits<LOGM>(k);  // even: k < M/2
+        T ur, ui, vr, vi;
+        buf.get(a, ur, ui);
+        buf.get(a + 1, vr, vi);
+        // forward radix-2 stage: slot a -> frequency k, slot a + 1 -> k + M/2
+        const T z0r = ur + vr, z0i = ui + vi, z1r = ur - vr, z1i = ui - vi;
+        T y0r, y0i, y1r, y1i;
+        if (k == 0) {  // DC and Nyquist of the real sequence (k = 0), self-paired M/2
+            const T yd = H[0] * ((T)2 * (z0r + z0i));
+            const T yn = H[M] * ((T)2 * (z0r - z0i));
+            y0r = yd + yn;
+            y0i = yd - yn;
+            self(z1r, z1i, y1r, y1i);
+        } else if (k == M / 4) {  // the pair (M/4, 3M/4) is the slot pair itself
+            pair(k, M - k, z0r, z0i, z1r, z1i, y0r, y0i, y1r, y1i);
+        } else {
+            const int b = rev_bits<LOGM>(M - k);  // odd: slot b -> M - k, b - 1 -> M/2 - k
+            T sr, si, tr, ti;
+            buf.get(b - 1, sr, si);
+            buf.get(b, tr, ti);
+            const T w0r = sr + tr, w0i = si + ti, w1r = sr - tr, w1i = si - ti;
+            T q0r, q0i, q1r, q1i;
+            pair(k, M - k, z0r, z0i, w1r, w1i, y0r, y0i, q1r, q1i);
+            pair(M / 2 + k, M / 2 - k, z1r, z1i, w0r, w0i, y1r, y1i, q0r, q0i);
+            // inverse radix-2 stage on the slots (b - 1, b)
+            buf.put(b - 1, q0r + q1r, q0i + q1i);
+            buf.put(b, q0r - q1r, q0i - q1i);
+        }
+        // inverse radix-2 stage on the slots (a, a + 1)
+        buf.put(a, y0r + y1r, y0i + y1i);
+        buf.put(a + 1, y0r - y1r, y0i - y1i);
     }
     __syncthreads();
 }
@@ -635,9 +735,15 @@ __global__ __launch_bounds__(NT, (tile_waves_per_simd<T, LOGM, NT>())) void k_to
         (void)nz;
         __syncthreads();
     }
-    fwd_passes<T, LOGM, NT, LOGM>(buf, a.tw);
-    spectrum_pass<T, LOGM, NT>(buf, a.H + (int64_t)a.int_kern[j] * (M + 1), a.tw);
-    inv_passes<T, LOGM, NT, LOGM>(buf, a.tw);
+    if constexpr (LOGM % 4 == 1) {  // the radix-2 stages go into the spectrum pass
+        fwd_passes<T, LOGM, NT, LOGM, 1>(buf, a.tw);
+        spectrum_pass_r2<T, LOGM, NT>(buf, a.H + (int64_t)a.int_kern[j] * (M + 1), a.tw);
+        inv_passes<T, LOGM, NT, LOGM, 1>(buf, a.tw);
+    } else {
+        fwd_passes<T, LOGM, NT, LOGM>(buf, a.tw);
+        spectrum_pass<T, LOGM, NT>(buf, a.H + (int64_t)a.int_kern[j] * (M + 1), a.tw);
+        inv_passes<T, LOGM, NT, LOGM>(buf, a.tw);
+    }
     T* zo = a.z + o;  // block-uniform base, 32-bit offsets
     for (int i = lam + threadIdx.x; i < lam + L; i += NT)
         zo[(uint32_t)(i - lam)] = buf.get_part(i >> 1, i & 1);
