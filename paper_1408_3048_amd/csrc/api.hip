@@ -267,8 +267,16 @@ int pcg_engine(mm_plan_t pl, const double* b, double* x, const EngineArgs& ea) {
         MM_TRY(ea.op32 ? apply_A32(pl, xw, q, nullptr) : apply_A64(pl, xw, q, nullptr));
         MM_TRY(vec_residual(pl, b, q, r, all));
     }
-    // A-DEF2 starts from x0 + Z E^-1 Z^T (b - A x0) [App. B]
-    if (ea.pc == MM_ADEF2) MM_TRY(coarse_start(pl, xw, r));
+    // A-DEF2 starts from x0 + Z E^-1 Z^T (b - A x0) [App. B].  Its equivalence to an SPD
+    // preconditioner needs Z^T r = 0; where AZ is stored in FP32 (mixed plans) the update
+    // r -= AZ w is off by its rounding, so the FP64 operator recomputes r = b - A x.
+    if (ea.pc == MM_ADEF2) {
+        MM_TRY(coarse_start(pl, xw, r));
+        if (!ea.op32 && pl->co.AZ32.p) {
+            MM_TRY(apply_A64(pl, xw, q, nullptr));
+            MM_TRY(vec_residual(pl, b, q, r, all));
+        }
+    }
     MM_TRY(vec_dot(pl, b, b, kSlotAux, all));
     MM_TRY(pcg_init(pl, all, ea.tol, 1));
     MM_TRY(vec_zero_flagged(pl, xw, pl->sel.p, all));  // b_b = 0: x_b = 0 exactly
@@ -342,6 +350,8 @@ int pcg_engine(mm_plan_t pl, const double* b, double* x, const EngineArgs& ea) {
             MM_TRY(apply_A64(pl, xw, q, pl->sel.p));
             MM_TRY(vec_residual(pl, b, q, r, cs));
             MM_TRY(pcg_decide(pl, cs));
+            // A-DEF2: the replaced residual gets the coarse correction again (Z^T r = 0)
+            if (ea.pc == MM_ADEF2) MM_TRY(coarse_start(pl, xw, r, pl->sel.p));
             MM_TRY(precond(pl, ea.pc, r, z, cs));
             MM_TRY(pcg_update_p(pl, p, z, cs));
             MM_TRY(pcg_resume(pl, all));

@@ -1681,13 +1681,13 @@ int adef2_apply(mm_plan_t pl, const double* r, double* z, const PcgCtl& ctl) {
     return by_layout<Adef2Finish>(pl, r, z, ctl);
 }
 
-// the A-DEF2 initial guess [App. B]: w = E^-1 Z^T r, x += Z w, r -= AZ w for every problem
-// (r = b - A x on entry), after which Z^T r = 0
-int coarse_start(mm_plan_t pl, double* x, double* r) {
+// the A-DEF2 initial guess [App. B]: w = E^-1 Z^T r, x += Z w, r -= AZ w for the problems
+// in mask (nullptr: all; r = b - A x on entry), after which Z^T r = 0
+int coarse_start(mm_plan_t pl, double* x, double* r, const int* mask) {
     PcgCtl c = batch_ctl(pl);
     c.part = nullptr;
-    c.mask = nullptr;
-    MM_TRY(coarse_w(pl, r, nullptr, nullptr));
+    c.mask = mask;
+    MM_TRY(coarse_w(pl, r, nullptr, mask));
     return by_layout<CoarseCorrect>(pl, x, r, c);
 }
 

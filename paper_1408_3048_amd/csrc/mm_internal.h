@@ -346,8 +346,9 @@ int build_coarse_dense(mm_plan_t pl, const double* basis, int64_t basis_stride,
 int twolvl_apply(mm_plan_t pl, const double* r, double* z, const PcgCtl& ctl);
 // A-DEF2 preconditioner z = R^T M_BD r + Z E^-1 Z^T r (partials of r^T z as ctl asks)
 int adef2_apply(mm_plan_t pl, const double* r, double* z, const PcgCtl& ctl);
-// A-DEF2 initial guess: x += Z E^-1 Z^T r, r -= AZ E^-1 Z^T r (r = b - A x on entry)
-int coarse_start(mm_plan_t pl, double* x, double* r);
+// A-DEF2 initial guess: x += Z E^-1 Z^T r, r -= AZ E^-1 Z^T r (r = b - A x on entry) for
+// the problems in mask (nullptr: all)
+int coarse_start(mm_plan_t pl, double* x, double* r, const int* mask = nullptr);
 // the kept Z_D blocks, FP64, into out (h_az_off[B] values)
 int coarse_dense_columns(mm_plan_t pl, double* out);
 

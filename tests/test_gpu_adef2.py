@@ -151,3 +151,22 @@ def test_adef2_graph_replay_equals_plain_launches():
     assert ig["iterations"] == inn["iterations"]
     pg.close()
     pn.close()
+
+
+def test_adef2_fp64_solve_on_a_mixed_plan():
+    """A mixed plan stores AZ in FP32; the FP64 A-DEF2 solve recomputes the residual of
+    its special start with the FP64 operator and re-applies the coarse correction after a
+    residual replacement, so it converges like A-DEF1 to tight tolerances (16x16 IQU, 4
+    co-pointed detectors, a rank-3 coarse space from 16 intervals)."""
+    sc = synth.raster_iqu(side=16, spp=8, n_det=4, interval_len=1024, lam=64,
+                          fknee_range=(0.5, 2.0), alpha_range=(1.0, 2.0), seed_key=99)
+    pr = O.Problem.from_scan(sc)
+    b = dev(pr.rhs(pr.signal(sc.sky) + sc.noise))
+    xo, _, _ = O.pcg(pr.apply_A, b.cpu().numpy(), pr.bj_apply, tol=1e-13, maxit=3000)
+    pl = Plan.from_scan(sc, precision="mixed", coarse=True)
+    for tol in (1e-8, 1e-12):
+        x1, i1 = pl.pcg_solve(b, precond="2lvl", precision="fp64", tol=tol, max_iter=300)
+        x2, i2 = pl.pcg_solve(b, precond="adef2", precision="fp64", tol=tol, max_iter=300)
+        assert i2["rel_residual"] <= tol and abs(i1["iterations"] - i2["iterations"]) <= 1
+    assert rel(x2.cpu().numpy(), xo) <= 1e-10
+    pl.close()
