@@ -561,6 +561,12 @@ int mm_plan_batched(mm_plan_t* out, int32_t n_problems, const int32_t* problem_i
     for (auto& v : pl->vec)
         if ((s = v.alloc(n)) != MM_OK) return fail(s);
     if ((s = pl->part.alloc((size_t)kNumSlots * pl->n_prob * kVecBlocks)) != MM_OK) return fail(s);
+    // slots past a problem's block count are never written and must read as zero
+    if (hipError_t e = hipMemsetAsync(pl->part.p, 0, pl->part.n * sizeof(double), pl->stream);
+        e != hipSuccess) {
+        set_error("hipMemsetAsync failed: %s", hipGetErrorString(e));
+        return fail(MM_ERR_DEVICE);
+    }
     if ((s = pl->sc.alloc(pl->n_prob)) != MM_OK) return fail(s);
     if ((s = pl->act.alloc(pl->n_prob)) != MM_OK) return fail(s);
     if ((s = pl->sel.alloc(pl->n_prob)) != MM_OK) return fail(s);

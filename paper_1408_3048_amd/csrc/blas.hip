@@ -24,7 +24,7 @@ __global__ __launch_bounds__(kVecThreads) void k_dot(const double* __restrict__ 
     if (c.mask && !c.mask[v.b]) return;
     double acc = 0.0;
     for (int64_t i = (int64_t)v.k * kVecThreads + threadIdx.x; i < v.n;
-         i += (int64_t)kVecBlocks * kVecThreads)
+         i += v.stride)
         acc += a[v.base + i] * b[v.base + i];
     write_partial_at(acc, slot_part(c, slot, v.b), v.k, red);
 }
@@ -60,7 +60,7 @@ __global__ __launch_bounds__(kVecThreads) void k_update_xr(double* __restrict__ 
     }
     double acc = 0.0;
     for (int64_t i = (int64_t)v.k * kVecThreads + threadIdx.x; i < v.n;
-         i += (int64_t)kVecBlocks * kVecThreads) {
+         i += v.stride) {
         const int64_t e = v.base + i;
         x[e] += alpha * p[e];
         const double rv = r[e] - alpha * q[e];
@@ -93,7 +93,7 @@ __global__ __launch_bounds__(kVecThreads) void k_update_p(double* __restrict__ p
     // the same iteration, together with rz_hist[it])
     double* kz = c.krylov && it < c.kcap ? c.krylov + (int64_t)it * c.knv : nullptr;
     for (int64_t i = (int64_t)v.k * kVecThreads + threadIdx.x; i < v.n;
-         i += (int64_t)kVecBlocks * kVecThreads) {
+         i += v.stride) {
         const int64_t e = v.base + i;
         const double zv = z[e];
         p[e] = c.first ? zv : zv + beta * p[e];
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(kVecThreads) void k_residual(const double* __restri
     if (c.mask && !c.mask[v.b]) return;
     double acc = 0.0;
     for (int64_t i = (int64_t)v.k * kVecThreads + threadIdx.x; i < v.n;
-         i += (int64_t)kVecBlocks * kVecThreads) {
+         i += v.stride) {
         const int64_t e = v.base + i;
         const double t = b[e] - y[e];
         out[e] = t;
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(kVecThreads) void k_zero_flagged(double* __restrict
     const VecBlock v = vec_block(c, ns, true);
     if (!flag[v.b]) return;
     for (int64_t i = (int64_t)v.k * kVecThreads + threadIdx.x; i < v.n;
-         i += (int64_t)kVecBlocks * kVecThreads)
+         i += v.stride)
         x[v.base + i] = 0.0;
 }
 
@@ -256,12 +256,16 @@ int build_batch_layout(mm_plan_t pl) {
     for (int b = 0; b < B; ++b) {
         const int64_t np = pl->h_ooff[b + 1] - pl->h_ooff[b];
         const int64_t ne = np * pl->n_s;
-        auto blocks = [](int64_t m) {
-            int64_t g = (m + kVecThreads - 1) / kVecThreads;
+        // several items per thread: the prologue reductions of every block (over the
+        // problem's partials) cost as much as a few items, so small problems of a batch
+        // get few blocks; the count depends on the problem alone
+        auto blocks = [](int64_t m, int per_thread) {
+            const int64_t per_block = (int64_t)kVecThreads * per_thread;
+            int64_t g = (m + per_block - 1) / per_block;
             return (int32_t)std::min<int64_t>(kVecBlocks, std::max<int64_t>(1, g));
         };
-        eb[b + 1] = eb[b] + blocks(ne);
-        pb[b + 1] = pb[b] + blocks(np);
+        eb[b + 1] = eb[b] + blocks(ne, kVecPerThreadE);
+        pb[b + 1] = pb[b] + blocks(np, kVecPerThreadP);
     }
     pl->n_eblk = eb[B];
     pl->n_pblk = pb[B];

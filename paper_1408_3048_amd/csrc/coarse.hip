@@ -380,7 +380,7 @@ __global__ __launch_bounds__(kVecThreads) void k_2lvl(
     const TA* azb = az + az_off[vb.b];
     double acc = 0.0;
     for (int64_t q = (int64_t)vb.k * kVecThreads + threadIdx.x; q < vb.n;
-         q += (int64_t)kVecBlocks * kVecThreads) {
+         q += vb.stride) {
         const int64_t p = vb.base + q;
         double u[NS], zw[NS];
 #pragma unroll
@@ -621,7 +621,7 @@ __global__ __launch_bounds__(kVecThreads) void k_adef2_finish(
     const int64_t nv = vb.n * NS;
     double acc = 0.0;
     for (int64_t q = (int64_t)vb.k * kVecThreads + threadIdx.x; q < vb.n;
-         q += (int64_t)kVecBlocks * kVecThreads) {
+         q += vb.stride) {
         const int64_t p = vb.base + q;
         double zz[NS];
 #pragma unroll
@@ -663,7 +663,7 @@ __global__ __launch_bounds__(kVecThreads) void k_coarse_correct(
     __syncthreads();
     const int64_t nv = vb.n * NS;
     for (int64_t q = (int64_t)vb.k * kVecThreads + threadIdx.x; q < vb.n;
-         q += (int64_t)kVecBlocks * kVecThreads) {
+         q += vb.stride) {
         const int64_t p = vb.base + q;
         double dx[NS], dr[NS];
 #pragma unroll

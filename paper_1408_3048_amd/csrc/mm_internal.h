@@ -291,6 +291,8 @@ namespace mm {
 
 constexpr int kVecBlocks = 512;   // fixed grid of the vector kernels (deterministic reductions)
 constexpr int kVecThreads = 256;
+constexpr int kVecPerThreadE = 8;  // elements per thread of a problem's vector grid (sizing)
+constexpr int kVecPerThreadP = 1;  // pixels per thread of the per-pixel kernels (sizing)
 
 // ---- sort.hip
 int build_pointing(mm_plan_t pl, const int32_t* pix, const void* weights, int wdtype);

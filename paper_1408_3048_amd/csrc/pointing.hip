@@ -342,7 +342,7 @@ __global__ __launch_bounds__(kVecThreads) void k_bj_apply(const double* __restri
     if (ctl.mask && !ctl.mask[vb.b]) return;
     double acc = 0.0;
     for (int64_t q = (int64_t)vb.k * kVecThreads + threadIdx.x; q < vb.n;
-         q += (int64_t)kVecBlocks * kVecThreads) {
+         q += vb.stride) {
         const int64_t c = vb.base + q;
         if constexpr (NS == 1) {
             const double rv = r[c];
