@@ -63,13 +63,13 @@ def fft_tile_flops(offsets, lam, n_r):
 TRAFFIC = {
     # per FP32 tile length n_r (the plan's autotuner picks 8192 or 16384 on this workload)
     "ninv32": dict(source="paper_1408_3048_amd/csrc/toeplitz.hip",
-                   sha256="2f4ffbd6a8abe84708f8aaac60f19ba849da8dbf4b6512fc8c791ee58e88e8ac",
-                   by_n_r={8192: dict(fetch_kib=294641.8125, write_kib=65536.0),
-                           16384: dict(fetch_kib=202661.625, write_kib=65579.46875)},
+                   sha256="08bdd3df6287745a495fb7c84fd5408c1a148207ca60526708227809226a62b1",
+                   by_n_r={8192: dict(fetch_kib=294600.125, write_kib=65536.0),
+                           16384: dict(fetch_kib=203174.0625, write_kib=65579.09375)},
                    fetch_factor=2.0, write_factor=1.0),
     "pt32": dict(source="paper_1408_3048_amd/csrc/pointing.hip",
-                 sha256="a5f64bd660c1d6a112cbfd051a13a9a503f95f66bb552a96563dd814c32aa466",
-                 by_n_r={None: dict(fetch_kib=152901.75, write_kib=6762.59375)},
+                 sha256="f4d605beb107d3e922686a78c75d6a3ccbf74dfe33179f9f6c52a5a4fe84c266",
+                 by_n_r={None: dict(fetch_kib=152897.0, write_kib=6764.78125)},
                  fetch_factor=2.0, write_factor=1.0),
 }
 
