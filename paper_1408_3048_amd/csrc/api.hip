@@ -6,6 +6,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
 
 #include "mm_device.h"
 
@@ -28,6 +32,54 @@ static thread_local hipStream_t g_alloc_stream = nullptr;
 void set_alloc_stream(hipStream_t st) { g_alloc_stream = st; }
 hipStream_t alloc_stream() { return g_alloc_stream; }
 
+namespace {
+
+// Freed device blocks are kept for reuse: hipMallocAsync and hipFreeAsync take tens to
+// hundreds of microseconds of host time each, and building a plan makes about fifty of
+// each.  Requests are rounded up to a size class (1/8 of their power of two); a freed block
+// is kept per device and class with an event recorded on the freeing stream, and the
+// allocation that reuses it makes its own stream wait on that event, so reuse is
+// stream-ordered whatever the streams.  At most kCacheCap bytes are kept per device; past
+// that, and when the device runs out of memory, blocks go back to the pool.  No allocation
+// or release happens inside a captured stream region.
+struct CachedBlock {
+    void* p;
+    hipEvent_t ev;
+};
+struct LiveBlock {
+    int dev;
+    size_t cls;
+};
+constexpr size_t kCacheCap = (size_t)16 << 30;
+std::mutex g_cache_mu;
+std::map<std::pair<int, size_t>, std::vector<CachedBlock>> g_cache;
+std::map<int, size_t> g_cached_bytes;
+std::unordered_map<void*, LiveBlock> g_live;
+std::map<int, std::vector<hipEvent_t>> g_events;  // idle events per device
+
+size_t size_class(size_t b) {
+    if (b <= 4096) return 4096;
+    const int l = 63 - __builtin_clzll((unsigned long long)b);
+    const size_t q = (size_t)1 << (l - 3);
+    return (b + q - 1) / q * q;
+}
+
+// hand every cached block of device dev back to the pool (g_cache_mu held)
+void flush_cache(int dev, hipStream_t st) {
+    for (auto& kv : g_cache) {
+        if (kv.first.first != dev) continue;
+        for (const CachedBlock& c : kv.second) {
+            (void)hipStreamWaitEvent(st, c.ev, 0);
+            (void)hipFreeAsync(c.p, st);
+            g_events[dev].push_back(c.ev);
+        }
+        kv.second.clear();
+    }
+    g_cached_bytes[dev] = 0;
+}
+
+}  // namespace
+
 int pool_alloc(void** p, size_t bytes, hipStream_t st) {
     static thread_local int configured_dev = -1;
     int dev = 0;
@@ -40,15 +92,70 @@ int pool_alloc(void** p, size_t bytes, hipStream_t st) {
         }
         configured_dev = dev;
     }
-    hipError_t e = hipMallocAsync(p, bytes, st);
+    const size_t cls = size_class(bytes);
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_cache.find({dev, cls});
+    if (it != g_cache.end() && !it->second.empty()) {
+        const CachedBlock c = it->second.back();
+        it->second.pop_back();
+        g_cached_bytes[dev] -= cls;
+        g_events[dev].push_back(c.ev);
+        const hipError_t e = hipStreamWaitEvent(st, c.ev, 0);
+        if (e != hipSuccess) {
+            (void)hipFreeAsync(c.p, st);
+            set_error("hipStreamWaitEvent failed: %s", hipGetErrorString(e));
+            return MM_ERR_DEVICE;
+        }
+        g_live[c.p] = {dev, cls};
+        *p = c.p;
+        return MM_OK;
+    }
+    hipError_t e = hipMallocAsync(p, cls, st);
+    if (e == hipErrorOutOfMemory && g_cached_bytes[dev] > 0) {
+        (void)hipGetLastError();
+        flush_cache(dev, st);
+        e = hipMallocAsync(p, cls, st);
+    }
     if (e != hipSuccess) {
         set_error("hipMallocAsync(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
         return MM_ERR_DEVICE;
     }
+    g_live[*p] = {dev, cls};
     return MM_OK;
 }
 
-void pool_free(void* p, hipStream_t st) { (void)hipFreeAsync(p, st); }
+void pool_free(void* p, hipStream_t st) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_live.find(p);
+    if (it == g_live.end()) {  // not from pool_alloc
+        (void)hipFreeAsync(p, st);
+        return;
+    }
+    const LiveBlock b = it->second;
+    g_live.erase(it);
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != b.dev || g_cached_bytes[b.dev] + b.cls > kCacheCap) {
+        (void)hipFreeAsync(p, st);
+        return;
+    }
+    hipEvent_t ev = nullptr;
+    auto& idle = g_events[b.dev];
+    if (!idle.empty()) {
+        ev = idle.back();
+        idle.pop_back();
+    } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipFreeAsync(p, st);
+        return;
+    }
+    if (hipEventRecord(ev, st) != hipSuccess) {
+        idle.push_back(ev);
+        (void)hipFreeAsync(p, st);
+        return;
+    }
+    g_cache[{b.dev, b.cls}].push_back({p, ev});
+    g_cached_bytes[b.dev] += b.cls;
+}
 
 // RAII: the stream for allocations made during one API call
 struct AllocStream {
@@ -111,15 +218,15 @@ int apply_A64(mm_plan_t pl, const double* x, double* y, const int* mask) {
     return apply_A64_tag(pl, x, y, mask, -1);
 }
 
-int apply_A64_sparse(mm_plan_t pl, const double* x, double* y) {
+int apply_A64_sparse(mm_plan_t pl, const double* x, double* y, const uint8_t* int_on) {
     MM_TRY(pack_map64(pl, x));
-    MM_TRY(toeplitz_map64(pl, x, pl->tod64a.p, nullptr, true));
+    MM_TRY(toeplitz_map64(pl, x, pl->tod64a.p, nullptr, true, int_on));
     return scatter64(pl, pl->tod64a.p, y, nullptr);
 }
 
-int apply_A32_sparse(mm_plan_t pl, const double* x, double* y) {
+int apply_A32_sparse(mm_plan_t pl, const double* x, double* y, const uint8_t* int_on) {
     MM_TRY(pack_map32(pl, x));
-    MM_TRY(toeplitz_map32(pl, x, pl->tod32a.p, nullptr, true));
+    MM_TRY(toeplitz_map32(pl, x, pl->tod32a.p, nullptr, true, int_on));
     return scatter32(pl, pl->tod32a.p, y, nullptr);
 }
 
@@ -644,10 +751,13 @@ int mm_interval_taps(mm_plan_t pl, int32_t j, double* host_out, int cap) {
         set_error("bad plan or interval index");
         return MM_ERR_ARG;
     }
-    const auto& t = pl->h_taps[pl->h_int_kern[j]];
+    MM_TRY(host_taps(pl));
+    const int32_t g = pl->h_int_kern[j];
+    const double* t = pl->h_taps.data() + pl->h_taps_off[g];
+    const int n = (int)pl->h_taps_cnt[g];
     if (host_out)
-        for (int k = 0; k < cap && k < (int)t.size(); ++k) host_out[k] = t[k];
-    return (int)t.size();
+        for (int k = 0; k < cap && k < n; ++k) host_out[k] = t[k];
+    return n;
 }
 
 int mm_coarse_rank(mm_plan_t pl) {
@@ -691,7 +801,9 @@ int mm_gemm_tn_f64(void* stream, const double* A, const double* B, int64_t n, in
         set_error("mm_gemm_tn_f64: n must be a positive multiple of 4, ra and rb multiples of 16");
         return MM_ERR_ARG;
     }
-    return gemm_tn_f64((hipStream_t)stream, A, B, n, ra, rb, C);
+    MM_TRY(gemm_tn_f64((hipStream_t)stream, A, B, n, ra, rb, C));
+    MM_HIP(hipStreamSynchronize((hipStream_t)stream));
+    return MM_OK;
 }
 
 int mm_apply_P(mm_plan_t pl, const double* x, void* y, int y_dtype) {

@@ -181,6 +181,36 @@ __global__ void k_cols_to_vec(const int32_t* __restrict__ ucol, const int64_t* _
         out[(int64_t)rows[i] * ns] = vals[i];
 }
 
+// on[k * K + j] = 1 when layer k's column of interval j's problem has a pixel hit in
+// interval j, i.e. when P applied to that column does not vanish on the whole interval
+// (an entry of Z_S^T Z_S): row p of Z_S lists the intervals that hit pixel p, and each
+// pair of its entries marks one (layer, interval) pair.  A row longer than kPairCap marks
+// every layer for its intervals instead (more flags than needed, never fewer).
+constexpr int kPairCap = 64;
+__global__ void k_az_int_flags(const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                               int64_t n_obs, const int32_t* __restrict__ layer, int32_t K,
+                               int32_t n_layers, uint8_t* __restrict__ on) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n_obs;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t a0 = ptr[p], a1 = ptr[p + 1];
+        if (a1 - a0 <= kPairCap) {
+            for (int64_t a = a0; a < a1; ++a) {
+                uint8_t* row = on + (int64_t)layer[col[a]] * K;
+                for (int64_t c = a0; c < a1; ++c) {
+                    const int32_t j = col[c];
+                    if (!row[j]) row[j] = 1;
+                }
+            }
+        } else {
+            for (int64_t c = a0; c < a1; ++c) {
+                const int32_t j = col[c];
+                for (int32_t k = 0; k < n_layers; ++k)
+                    if (!on[(int64_t)k * K + j]) on[(int64_t)k * K + j] = 1;
+            }
+        }
+    }
+}
+
 // copy problem lp[y]'s slice of the map vector y into column `col` of its AZ block
 template <typename TA>
 __global__ void k_store_az(const int32_t* __restrict__ lp, const double* __restrict__ y,
@@ -771,7 +801,8 @@ bool spd_inverse(const std::vector<double>& A, int k, std::vector<double>& out) 
 
 }  // namespace
 
-// C[ra][rb] (host, row-major) = A^T B for device row-major A [n][ra], B [n][rb]
+// C[ra][rb] (device, row-major) = A^T B for device row-major A [n][ra], B [n][rb], enqueued
+// on st (no synchronisation: its scratch is released in stream order)
 int gemm_tn_f64(hipStream_t st, const double* A, const double* B, int64_t n, int32_t ra,
                 int32_t rb, double* dev_C) {
     const int32_t ntile = (ra / 16) * (rb / 16);
@@ -785,7 +816,6 @@ int gemm_tn_f64(hipStream_t st, const double* A, const double* B, int64_t n, int
     const int64_t m = (int64_t)ra * rb;
     hipLaunchKernelGGL(k_sum_parts, dim3(grid_for(m)), dim3(256), 0, st, part.p, m, ksplit, dev_C);
     MM_HIP(hipGetLastError());
-    MM_HIP(hipStreamSynchronize(st));
     return MM_OK;
 }
 
@@ -873,6 +903,8 @@ int build_coarse(mm_plan_t pl) {
         }
     }
     std::vector<char> dup(K, 0);
+    std::vector<int32_t> rep(K);  // interval whose column represents interval j's column
+    for (int32_t j = 0; j < K; ++j) rep[j] = j;
     if (!cand_a.empty()) {
         const int nc = (int)cand_a.size();
         DBuf<int32_t> da, db;
@@ -890,7 +922,10 @@ int build_coarse(mm_plan_t pl) {
         MM_HIP(hipMemcpyAsync(hn.data(), neq.p, nc * sizeof(int), hipMemcpyDeviceToHost, st));
         MM_HIP(hipStreamSynchronize(st));
         for (int i = 0; i < nc; ++i)
-            if (!hn[i]) dup[cand_a[i]] = 1;
+            if (!hn[i]) {
+                dup[cand_a[i]] = 1;
+                rep[cand_a[i]] = cand_b[i];
+            }
     }
     std::vector<int32_t> uniq;  // representative interval of every distinct column
     for (int32_t j = 0; j < K; ++j)
@@ -932,18 +967,41 @@ int build_coarse(mm_plan_t pl) {
     MM_HIP(hipMemcpyAsync(dub.p, ub.data(), rd * 8, hipMemcpyHostToDevice, st));
     MM_HIP(hipMemcpyAsync(due.p, ue.data(), rd * 8, hipMemcpyHostToDevice, st));
     // AZ of the distinct columns, block per problem: A is block diagonal over the problems,
-    // so one application to the sum of every problem's k-th column gives all k-th columns
+    // so one application to the sum of every problem's k-th column (layer k) gives all k-th
+    // columns.  Layer k's columns reach only the intervals flagged in on[k]; the tiles of the
+    // others write zeros without loading.
     const bool mixed = pl->opts.precision == MM_MIXED;
     DBuf<double> azd;
     DBuf<float> azf;
     if (mixed) MM_TRY(azf.alloc((size_t)azd_off[B]));
     else MM_TRY(azd.alloc((size_t)azd_off[B]));
-    DBuf<double> zc, tmp;
-    MM_TRY(zc.alloc(nv));
-    MM_TRY(tmp.alloc(nv));
     DBuf<int64_t> d_azd_off;
     MM_TRY(d_azd_off.alloc(B + 1));
     MM_HIP(hipMemcpyAsync(d_azd_off.p, azd_off.data(), (B + 1) * 8, hipMemcpyHostToDevice, st));
+    // layer of every interval's column within its problem, and the (layer, interval) flags
+    std::vector<int32_t> u_of(K, -1), h_layer(K);
+    for (int32_t u = 0; u < rd; ++u) u_of[uniq[u]] = u;
+    for (int b = 0; b < B; ++b)
+        for (int32_t j = pl->h_pint[b]; j < pl->h_pint[b + 1]; ++j) {
+            h_layer[j] = u_of[rep[j]] - ud_off[b];
+            if (h_layer[j] < 0 || h_layer[j] >= ud_off[b + 1] - ud_off[b]) {  // flags index
+                set_error("interval %d: column layer %d outside [0, %d)", j, h_layer[j],
+                          ud_off[b + 1] - ud_off[b]);
+                return MM_ERR_ARG;
+            }
+        }
+    DBuf<int32_t> d_layer;
+    DBuf<uint8_t> on;
+    MM_TRY(d_layer.alloc(K));
+    MM_TRY(on.alloc((size_t)rd_max * K));
+    MM_HIP(hipMemcpyAsync(d_layer.p, h_layer.data(), (size_t)K * 4, hipMemcpyHostToDevice, st));
+    MM_HIP(hipMemsetAsync(on.p, 0, (size_t)rd_max * K, st));
+    hipLaunchKernelGGL(k_az_int_flags, dim3(grid_for(n_obs)), dim3(256), 0, st, ptr.p, col.p,
+                       n_obs, d_layer.p, K, rd_max, on.p);
+    MM_HIP(hipGetLastError());
+    DBuf<double> zc, tmp;
+    MM_TRY(zc.alloc(nv));
+    MM_TRY(tmp.alloc(nv));
     DBuf<int32_t> lcols, lprob;
     MM_TRY(lcols.alloc((size_t)rd_max * B));
     MM_TRY(lprob.alloc((size_t)rd_max * B));
@@ -965,17 +1023,18 @@ int build_coarse(mm_plan_t pl) {
         int64_t lo = 0;
         for (int32_t k = 0; k < rd_max; ++k) {
             const int nl = lcnt[k];
+            const uint8_t* on_k = on.p + (int64_t)k * K;
             MM_HIP(hipMemsetAsync(zc.p, 0, nv * 8, st));
             hipLaunchKernelGGL(k_cols_to_vec, dim3(16, nl), dim3(256), 0, st, lcols.p + lo, dub.p,
                                due.p, crow.p, cval.p, (int)ns, zc.p);
             MM_HIP(hipGetLastError());
             if (mixed) {
-                MM_TRY(apply_A32_sparse(pl, zc.p, tmp.p));
+                MM_TRY(apply_A32_sparse(pl, zc.p, tmp.p, on_k));
                 hipLaunchKernelGGL(k_store_az<float>, dim3(sgx, nl), dim3(256), 0, st, lprob.p + lo,
                                    (const double*)tmp.p, pl->ooff.p, (int)ns,
                                    (const int64_t*)d_azd_off.p, k, azf.p);
             } else {
-                MM_TRY(apply_A64_sparse(pl, zc.p, tmp.p));
+                MM_TRY(apply_A64_sparse(pl, zc.p, tmp.p, on_k));
                 hipLaunchKernelGGL(k_store_az<double>, dim3(sgx, nl), dim3(256), 0, st, lprob.p + lo,
                                    (const double*)tmp.p, pl->ooff.p, (int)ns,
                                    (const int64_t*)d_azd_off.p, k, azd.p);
@@ -986,22 +1045,22 @@ int build_coarse(mm_plan_t pl) {
     }
     zc.release();
     tmp.release();
+    on.release();
     tick("AZ");
     // per problem: E_b = Z_b^T (AZ)_b on the matrix cores, independent subset, E_b^-1
     int64_t npad_max = 0;
     for (int b = 0; b < B; ++b) npad_max = std::max<int64_t>(npad_max, (oo[b + 1] - oo[b] + 3) / 4 * 4);
     const int32_t rp_max = (rd_max + 15) / 16 * 16;
+    // every problem's E_b into one device array (offsets eoff), read back once
+    std::vector<int64_t> eoff(B + 1, 0);
+    for (int b = 0; b < B; ++b) {
+        const int64_t rp = (ud_off[b + 1] - ud_off[b] + 15) / 16 * 16;
+        eoff[b + 1] = eoff[b] + rp * rp;
+    }
     DBuf<double> zd, azr, dE;
     MM_TRY(zd.alloc((size_t)npad_max * rp_max));
     MM_TRY(azr.alloc((size_t)npad_max * rp_max));
-    MM_TRY(dE.alloc((size_t)rp_max * rp_max));
-    std::vector<std::vector<int>> sels(B);
-    std::vector<double> Eall, Einv_all;
-    co.h_col_off.assign(B + 1, 0);
-    co.h_einv_off.assign(B + 1, 0);
-    co.h_az_off.assign(B + 1, 0);
-    co.cols.clear();
-    co.r_max = 0;
+    MM_TRY(dE.alloc((size_t)eoff[B]));
     for (int b = 0; b < B; ++b) {
         const int32_t rb = ud_off[b + 1] - ud_off[b];
         const int64_t nob = oo[b + 1] - oo[b];
@@ -1018,9 +1077,23 @@ int build_coarse(mm_plan_t pl) {
             hipLaunchKernelGGL(k_az_rows<double>, dim3(grid_for(nob, 256, 4096), rb), dim3(256), 0,
                                st, azd.p + azd_off[b], nob * ns, nob, (int)ns, rb, rp, azr.p);
         MM_HIP(hipGetLastError());
-        MM_TRY(gemm_tn_f64(st, zd.p, azr.p, npad, rp, rp, dE.p));
-        std::vector<double> Ep((size_t)rp * rp);
-        MM_HIP(hipMemcpy(Ep.data(), dE.p, Ep.size() * 8, hipMemcpyDeviceToHost));
+        MM_TRY(gemm_tn_f64(st, zd.p, azr.p, npad, rp, rp, dE.p + eoff[b]));
+    }
+    std::vector<double> Eh((size_t)eoff[B]);
+    MM_HIP(hipMemcpyAsync(Eh.data(), dE.p, Eh.size() * 8, hipMemcpyDeviceToHost, st));
+    MM_HIP(hipStreamSynchronize(st));
+    std::vector<std::vector<int>> sels(B);
+    std::vector<double> Eall, Einv_all;
+    co.h_col_off.assign(B + 1, 0);
+    co.h_einv_off.assign(B + 1, 0);
+    co.h_az_off.assign(B + 1, 0);
+    co.cols.clear();
+    co.r_max = 0;
+    for (int b = 0; b < B; ++b) {
+        const int32_t rb = ud_off[b + 1] - ud_off[b];
+        const int64_t nob = oo[b + 1] - oo[b];
+        const int32_t rp = (rb + 15) / 16 * 16;
+        const double* Ep = Eh.data() + eoff[b];
         std::vector<double> E((size_t)rb * rb);
         for (int32_t i = 0; i < rb; ++i)
             for (int32_t j = 0; j < rb; ++j)
@@ -1142,7 +1215,8 @@ int build_coarse(mm_plan_t pl) {
     MM_TRY(co.csr_ptr.alloc(n_obs + 1));
     MM_TRY(scan_exclusive_i64(kcnt.p, co.csr_ptr.p, n_obs, st));
     int64_t kn = 0;
-    MM_HIP(hipMemcpy(&kn, co.csr_ptr.p + n_obs, 8, hipMemcpyDeviceToHost));
+    MM_HIP(hipMemcpyAsync(&kn, co.csr_ptr.p + n_obs, 8, hipMemcpyDeviceToHost, st));
+    MM_HIP(hipStreamSynchronize(st));
     MM_TRY(co.csr_col.alloc(std::max<int64_t>(1, kn)));
     MM_TRY(co.csr_val.alloc(std::max<int64_t>(1, kn)));
     hipLaunchKernelGGL(k_csr_filter, dim3(grid_for(n_obs)), dim3(256), 0, st, ptr.p, col.p, val.p,
@@ -1315,7 +1389,8 @@ int build_coarse_dense(mm_plan_t pl, const double* basis, int64_t basis_stride,
                 MM_HIP(hipGetLastError());
                 MM_TRY(gemm_tn_f64(st, zr.p, azr.p, npad, rp, rp, dE.p));
                 std::vector<double> Ep((size_t)rp * rp);
-                MM_HIP(hipMemcpy(Ep.data(), dE.p, Ep.size() * 8, hipMemcpyDeviceToHost));
+                MM_HIP(hipMemcpyAsync(Ep.data(), dE.p, Ep.size() * 8, hipMemcpyDeviceToHost, st));
+                MM_HIP(hipStreamSynchronize(st));
                 std::vector<double> E((size_t)r * r);
                 for (int32_t i = 0; i < r; ++i)
                     for (int32_t j = 0; j < r; ++j)

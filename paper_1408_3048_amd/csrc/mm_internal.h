@@ -217,7 +217,10 @@ struct mm_plan_s {
     std::vector<int32_t> h_int_kern;    // interval -> distinct kernel
     std::vector<int32_t> h_kern_len;    // kernel -> interval length n_j
     std::vector<mm_psd> h_kern_psd;
-    std::vector<std::vector<double>> h_taps;  // per kernel, t_0..t_K (FP64)
+    mm::DBuf<double> taps;              // t_0..t_K of every kernel, flat (FP64)
+    mm::DBuf<int64_t> taps_off, taps_cnt;  // [n_kern] offset and count of its taps
+    std::vector<int64_t> h_taps_off, h_taps_cnt;
+    std::vector<double> h_taps;         // host copy of taps, fetched on first use (host_taps)
     int32_t n_kern = 0;
 
     // time-ordered data
@@ -296,7 +299,7 @@ constexpr int kVecPerThreadP = 1;  // pixels per thread of the per-pixel kernels
 
 // ---- sort.hip
 int build_pointing(mm_plan_t pl, const int32_t* pix, const void* weights, int wdtype);
-// out[0..n] = exclusive scan of in[0..n-1] (int64), out[n] = total; synchronises st
+// out[0..n] = exclusive scan of in[0..n-1] (int64), out[n] = total, enqueued on st
 int scan_exclusive_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t st);
 // stable LSD radix sort of (key, value) pairs, keys in [0, key_max]; synchronises st
 int radix_sort_pairs(const int32_t* keys, const int32_t* vals, int64_t n, int32_t key_max,
@@ -309,6 +312,8 @@ int build_tiling(mm_plan_t pl, FftTiling& ft, bool fp64, int n_r_request);
 int autotune_tiling(mm_plan_t pl, FftTiling& ft, bool fp64);
 // windowed taps of every distinct kernel (what 0) or of the inverse-PSD derivative with
 // respect to sigma / f_knee / alpha (what 1 / 2 / 3), host, flat with offsets and counts
+// host copy of the plan's taps (pl->h_taps), fetched once
+int host_taps(mm_plan_t pl);
 int kernel_taps(mm_plan_t pl, int what, std::vector<double>& taps, std::vector<int64_t>& toff,
                 std::vector<int64_t>& tcnt);
 
@@ -321,13 +326,15 @@ int tap_derivatives(mm_plan_t pl, std::vector<double>& dt);
 int adjoint_tod(mm_plan_t pl, const double* m_hat, const double* mu, const void* d, int d_f64,
                 void* grad_d, int grad_d_f64, double* grad_psd);
 // map-mode N^-1 P x; mask: per-problem flags (nullptr = all problems); the IQU map must
-// have been packed by pack_map64/32 first
+// have been packed by pack_map64/32 first.  skip_zero: tiles whose input window is all
+// zero write zeros without a transform; int_on (with skip_zero, optional): per-interval
+// flags, 0 where P x is known to vanish on the whole interval (no load either)
 int pack_map64(mm_plan_t pl, const double* x);
 int pack_map32(mm_plan_t pl, const double* x);
 int toeplitz_map64(mm_plan_t pl, const double* x, double* z, const int* mask,
-                   bool skip_zero = false);
+                   bool skip_zero = false, const uint8_t* int_on = nullptr);
 int toeplitz_map32(mm_plan_t pl, const double* x, float* z, const int* mask,
-                   bool skip_zero = false);
+                   bool skip_zero = false, const uint8_t* int_on = nullptr);
 int toeplitz_tod64(mm_plan_t pl, const void* y, int y_f64, double* z);
 int toeplitz_tod32(mm_plan_t pl, const void* y, int y_f64, float* z);
 
@@ -392,8 +399,9 @@ int prof_end(mm_plan_t pl, int k);
 void prof_invalidate(mm_plan_t pl, const size_t* mark, int first_skipped);
 int apply_A64(mm_plan_t pl, const double* x, double* y, const int* mask);
 int apply_A32(mm_plan_t pl, const double* x, double* y, const int* mask);
-// A x for mostly-zero x (the coarse-space columns): all-zero tiles skip the transform
-int apply_A64_sparse(mm_plan_t pl, const double* x, double* y);
-int apply_A32_sparse(mm_plan_t pl, const double* x, double* y);
+// A x for mostly-zero x (the coarse-space columns): all-zero tiles skip the transform;
+// int_on (optional): per-interval flags, 0 where P x vanishes on the whole interval
+int apply_A64_sparse(mm_plan_t pl, const double* x, double* y, const uint8_t* int_on = nullptr);
+int apply_A32_sparse(mm_plan_t pl, const double* x, double* y, const uint8_t* int_on = nullptr);
 
 }  // namespace mm

@@ -271,6 +271,10 @@ __global__ __launch_bounds__(256) void k_bj_build(
     if (w >= n_waves) return;
     const int32_t p0 = wave_pix[w], p1 = wave_pix[w + 1];
     if (p0 >= p1) return;
+    // a pixel's sorted samples come in time-ordered runs within one interval: the lane keeps
+    // the interval [jlo, jhi) and t_0 of its last sample and searches only outside it
+    int64_t jlo = 0, jhi = 0;
+    double dj = 0.0;
     auto load = [&](int64_t base, const bool* valid, double (*v)[NV]) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -280,7 +284,13 @@ __global__ __launch_bounds__(256) void k_bj_build(
                 continue;
             }
             const int64_t t = perm[base + e];
-            const double d = t0[int_kern[interval_of(int_lo, n_int, t)]];
+            if (t < jlo || t >= jhi) {
+                const int32_t j = interval_of(int_lo, n_int, t);
+                jlo = int_lo[j];
+                jhi = j + 1 < n_int ? int_lo[j + 1] : INT64_MAX;
+                dj = t0[int_kern[j]];
+            }
+            const double d = dj;
             if constexpr (NV == 6) {
                 const double a = ws[2 * (base + e)], b = ws[2 * (base + e) + 1];
                 v[e][0] = d;

@@ -70,15 +70,13 @@ int scan_exclusive(const TI* in, int64_t* out, int64_t n, hipStream_t st) {
     MM_HIP(hipGetLastError());
     if (nb == 1) {  // one tile: its total is the total
         MM_HIP(hipMemcpyAsync(out + n, sums.p, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
-        MM_HIP(hipStreamSynchronize(st));
         return MM_OK;
     }
     MM_TRY(scan_exclusive<int64_t>(sums.p, soff.p, nb, st));
     hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(kScanThreads), 0, st, out, n, soff.p);
     MM_HIP(hipGetLastError());
     MM_HIP(hipMemcpyAsync(out + n, soff.p + nb, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
-    MM_HIP(hipStreamSynchronize(st));  // scratch buffers are released on return
-    return MM_OK;
+    return MM_OK;  // the scratch buffers are released in stream order
 }
 
 __global__ void k_minmax(const int32_t* __restrict__ pix, int64_t n, int* __restrict__ mm2) {
@@ -238,53 +236,47 @@ __device__ __forceinline__ int find_range(const int64_t* __restrict__ off, int B
     return a;
 }
 
-// per-problem pixel id range (samples of problem b: [samp[b], samp[b+1])): every thread
-// scans 64 consecutive samples keeping a running range per problem; ranges are combined
-// over the wave when all its lanes end in the same problem, so the atomics stay few
+// per-problem pixel id range (samples of problem b: [samp[b], samp[b+1])): every wave reads
+// a chunk of 64 kMinmaxRun consecutive samples with coalesced loads and combines its range by
+// shuffles (one atomic per wave); a chunk that crosses a problem boundary (at most B - 1 of
+// them) takes per-sample atomics instead
+constexpr int kMinmaxRun = 64;
 __global__ void k_prob_minmax(const int32_t* __restrict__ pix, int64_t n,
                               const int64_t* __restrict__ samp, int B, int* __restrict__ lo,
                               int* __restrict__ hi) {
-    constexpr int64_t kRun = 64;
-    const int64_t ng = (n + kRun - 1) / kRun;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    // every lane runs the same number of rounds so the wave reduction below is uniform
-    const int64_t rounds = (ng + stride - 1) / stride;
-    for (int64_t rd = 0; rd < rounds; ++rd) {
-        const int64_t g = g0 + rd * stride;
-        int b = -1, l = INT_MAX, h = INT_MIN;
-        if (g < ng) {
-            const int64_t t0 = g * kRun, t1 = t0 + kRun < n ? t0 + kRun : n;
-            b = find_range(samp, B, t0);
-            int64_t next = samp[b + 1];
-            for (int64_t t = t0; t < t1; ++t) {
-                if (t >= next) {  // problem boundary inside the run
-                    atomicMin(&lo[b], l);
-                    atomicMax(&hi[b], h);
-                    l = INT_MAX;
-                    h = INT_MIN;
-                    b = find_range(samp, B, t);
-                    next = samp[b + 1];
+    constexpr int64_t kChunk = 64 * kMinmaxRun;
+    const int lane = threadIdx.x & 63;
+    const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t c0 = w0 * kChunk; c0 < n; c0 += nw * kChunk) {  // wave-uniform
+        const int64_t c1 = c0 + kChunk < n ? c0 + kChunk : n;
+        const int b = find_range(samp, B, c0);
+        if (c1 <= samp[b + 1]) {
+            int l = INT_MAX, h = INT_MIN;
+#pragma unroll 8
+            for (int r = 0; r < kMinmaxRun; ++r) {
+                const int64_t t = c0 + (int64_t)r * 64 + lane;
+                if (t < c1) {
+                    const int v = pix[t];
+                    l = min(l, v);
+                    h = max(h, v);
                 }
-                const int v = pix[t];
-                l = min(l, v);
-                h = max(h, v);
             }
-        }
-        const int b0 = __shfl(b, 0);
-        const bool same = __all(b == b0);
-        if (same && b0 >= 0) {
             for (int o = 32; o > 0; o >>= 1) {
                 l = min(l, __shfl_xor(l, o));
                 h = max(h, __shfl_xor(h, o));
             }
-            if ((threadIdx.x & 63) == 0) {
-                atomicMin(&lo[b0], l);
-                atomicMax(&hi[b0], h);
+            if (lane == 0) {
+                atomicMin(&lo[b], l);
+                atomicMax(&hi[b], h);
             }
-        } else if (b >= 0) {
-            atomicMin(&lo[b], l);
-            atomicMax(&hi[b], h);
+        } else {
+            for (int64_t t = c0 + lane; t < c1; t += 64) {
+                const int bt = find_range(samp, B, t);
+                const int v = pix[t];
+                atomicMin(&lo[bt], v);
+                atomicMax(&hi[bt], v);
+            }
         }
     }
 }
@@ -415,8 +407,15 @@ int radix_sort_pairs(const int32_t* keys, const int32_t* vals, int64_t n, int32_
     }
     MM_HIP(hipMemcpyAsync(keys_out, kin, n * 4, hipMemcpyDeviceToDevice, st));
     MM_HIP(hipMemcpyAsync(vals_out, vin, n * 4, hipMemcpyDeviceToDevice, st));
-    MM_HIP(hipStreamSynchronize(st));  // scratch is released on return
     return MM_OK;
+}
+
+// out[b] = src[idx[b]], b < n
+template <typename T, typename I>
+__global__ void k_gather(const T* __restrict__ src, const I* __restrict__ idx, int n,
+                         T* __restrict__ out) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < n) out[b] = src[idx[b]];
 }
 
 int build_pointing(mm_plan_t pl, const int32_t* pix, const void* weights, int wdtype) {
@@ -436,7 +435,7 @@ int build_pointing(mm_plan_t pl, const int32_t* pix, const void* weights, int wd
         MM_HIP(hipMemcpyAsync(hi.p, h.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
         MM_HIP(hipMemcpyAsync(samp.p, pl->h_samp.data(), (B + 1) * 8, hipMemcpyHostToDevice, st));
     }
-    hipLaunchKernelGGL(k_prob_minmax, dim3(grid_for((n + 63) / 64, 256, 4096)), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_prob_minmax, dim3(grid_for((n + 4 * 64 * kMinmaxRun - 1) / (4 * 64 * kMinmaxRun), 1, 2048)), dim3(256), 0, st,
                        pix, n, samp.p, B, lo.p, hi.p);
     MM_HIP(hipGetLastError());
     std::vector<int> h_lo(B), h_hi(B);
@@ -470,7 +469,8 @@ int build_pointing(mm_plan_t pl, const int32_t* pix, const void* weights, int wd
     MM_HIP(hipGetLastError());
     MM_TRY(scan_exclusive<int32_t>(flags.p, pos.p, pl->n_pix, st));
     int64_t n_obs = 0;
-    MM_HIP(hipMemcpy(&n_obs, pos.p + pl->n_pix, sizeof(int64_t), hipMemcpyDeviceToHost));
+    MM_HIP(hipMemcpyAsync(&n_obs, pos.p + pl->n_pix, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    MM_HIP(hipStreamSynchronize(st));
     pl->n_obs = n_obs;
     if (n_obs >= ((int64_t)1 << 27)) {  // the map gathers use 32-bit byte offsets
         set_error("%lld observed pixels: at most 2^27 - 1 supported", (long long)n_obs);
@@ -478,9 +478,15 @@ int build_pointing(mm_plan_t pl, const int32_t* pix, const void* weights, int wd
     }
     // compact pixel offsets of the problems: observed pixels below each problem's first id
     pl->h_ooff.assign(B + 1, n_obs);
-    for (int b = 0; b < B; ++b)
-        MM_HIP(hipMemcpyAsync(&pl->h_ooff[b], pos.p + h_lo[b], sizeof(int64_t),
-                              hipMemcpyDeviceToHost, st));
+    {
+        DBuf<int64_t> g;
+        MM_TRY(g.alloc(B));
+        hipLaunchKernelGGL((k_gather<int64_t, int>), dim3((B + 255) / 256), dim3(256), 0, st, pos.p,
+                           lo.p, B, g.p);
+        MM_HIP(hipGetLastError());
+        MM_HIP(hipMemcpyAsync(pl->h_ooff.data(), g.p, B * sizeof(int64_t), hipMemcpyDeviceToHost,
+                              st));
+    }
     MM_TRY(pl->obs.alloc(n_obs));
     MM_TRY(pl->hits.alloc(n_obs));
     hipLaunchKernelGGL(k_compact, dim3(grid_for(pl->n_pix)), dim3(256), 0, st, hfull.p, pos.p,
@@ -531,8 +537,14 @@ int build_pointing(mm_plan_t pl, const int32_t* pix, const void* weights, int wd
     // padded layout: every problem's sorted samples start at a multiple of 8, so the
     // P^T lane and wave structure of a problem does not depend on what precedes it
     std::vector<int64_t> s0(B + 1);
-    for (int b = 0; b < B; ++b)
-        MM_HIP(hipMemcpyAsync(&s0[b], pl->seg.p + pl->h_ooff[b], 8, hipMemcpyDeviceToHost, st));
+    {
+        DBuf<int64_t> g;
+        MM_TRY(g.alloc(B));
+        hipLaunchKernelGGL((k_gather<int64_t, int64_t>), dim3((B + 255) / 256), dim3(256), 0, st,
+                           pl->seg.p, pl->ooff.p, B, g.p);
+        MM_HIP(hipGetLastError());
+        MM_HIP(hipMemcpyAsync(s0.data(), g.p, B * 8, hipMemcpyDeviceToHost, st));
+    }
     MM_HIP(hipStreamSynchronize(st));
     s0[B] = n;
     pl->h_soff.assign(B + 1, 0);
@@ -559,8 +571,7 @@ int build_pointing(mm_plan_t pl, const int32_t* pix, const void* weights, int wd
                            pl->ooff.p, ds0.p, dsoff.p, B, ns_sorted);
         MM_HIP(hipGetLastError());
     }
-    MM_HIP(hipStreamSynchronize(st));
-    k1.release();
+    k1.release();  // released in stream order after the kernels that use them
     k2.release();
     v1.release();
     v2.release();

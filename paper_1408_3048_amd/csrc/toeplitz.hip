@@ -191,6 +191,8 @@ struct ToepArgs {
     const int* mask;          // per-problem flags: tiles of problems with mask 0 are skipped
     const int32_t* int_prob;  // problem of every interval
     int skip_zero;            // map modes: all-zero windows skip the transform
+    const uint8_t* int_on;    // zero-skipping launches: intervals flagged 0 have an all-zero
+                              // input (known beforehand) and write zeros without loading it
 };
 
 // LDS layout of the complex work array (M points).  Element a lives at
@@ -725,6 +727,12 @@ __global__ __launch_bounds__(NT, (tile_waves_per_simd<T, LOGM, NT>())) void k_to
     const int L = a.tile_len[tile];
     const int64_t lo = a.int_lo[j], hi = a.int_hi[j];
     const int lam = a.lam;
+    if constexpr (SKIPZ) {
+        if (a.int_on && !a.int_on[j]) {
+            for (int i = threadIdx.x; i < L; i += NT) a.z[o + i] = (T)0;
+            return;
+        }
+    }
     const bool nz = load_window<T, LOGM, NT, MODE>(a, buf, o - lam, L + 2 * lam, lo, hi);
     if constexpr (SKIPZ) {
         if (!__syncthreads_or(nz)) {  // zero window: the exact result is zero
@@ -950,6 +958,13 @@ ToepArgs<T> base_args(mm_plan_t pl, const FftTiling& ft) {
     return a;
 }
 
+// t0[g] = t_0 of kernel g (the diagonal of its Toeplitz block)
+__global__ void k_gather_t0(const double* __restrict__ taps, const int64_t* __restrict__ toff,
+                            int32_t nk, double* __restrict__ t0) {
+    const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < nk) t0[g] = taps[toff[g]];
+}
+
 constexpr int kMaxLogM64 = 13, kMaxLogM32 = 14, kMinLogM = 10;
 
 int64_t count_tiles(const std::vector<int64_t>& off, int64_t lmax) {
@@ -966,8 +981,8 @@ int64_t count_tiles(const std::vector<int64_t>& off, int64_t lmax) {
 // inverse PSD with respect to sigma, f_knee or alpha (what = 1, 2, 3), on the host, flat
 // with offsets toff and counts tcnt [App. D: the Toeplitz row is the inverse DFT of the
 // inverse PSD on the interval's grid].
-int kernel_taps(mm_plan_t pl, int what, std::vector<double>& taps, std::vector<int64_t>& toff,
-                std::vector<int64_t>& tcnt) {
+int kernel_taps_dev(mm_plan_t pl, int what, DBuf<double>& d_t, std::vector<int64_t>& toff,
+                    std::vector<int64_t>& tcnt) {
     hipStream_t st = pl->stream;
     const int32_t nk = pl->n_kern;
     const int lam = pl->opts.lambda;
@@ -998,7 +1013,7 @@ int kernel_taps(mm_plan_t pl, int what, std::vector<double>& taps, std::vector<i
         kpar[3 * g + 2] = pl->h_kern_psd[g].alpha;
     }
     DBuf<int32_t> d_klen;
-    DBuf<double> d_kpar, d_a, d_t;
+    DBuf<double> d_kpar, d_a;
     DBuf<int64_t> d_aoff, d_acnt, d_nper, d_jcnt, d_toff, d_tcnt;
     MM_TRY(d_klen.alloc(nk));
     MM_TRY(d_kpar.alloc(3 * nk));
@@ -1063,9 +1078,26 @@ int kernel_taps(mm_plan_t pl, int what, std::vector<double>& taps, std::vector<i
                            pl->opts.window, d_t.p, (int)kNs);
         MM_HIP(hipGetLastError());
     }
-    taps.resize(ttot);
-    MM_HIP(hipMemcpyAsync(taps.data(), d_t.p, ttot * 8, hipMemcpyDeviceToHost, st));
-    MM_HIP(hipStreamSynchronize(st));
+    // the temporaries above are released in stream order after the kernels that read them
+    return MM_OK;
+}
+
+int kernel_taps(mm_plan_t pl, int what, std::vector<double>& taps, std::vector<int64_t>& toff,
+                std::vector<int64_t>& tcnt) {
+    DBuf<double> d_t;
+    MM_TRY(kernel_taps_dev(pl, what, d_t, toff, tcnt));
+    taps.resize(d_t.n);
+    MM_HIP(hipMemcpyAsync(taps.data(), d_t.p, d_t.n * 8, hipMemcpyDeviceToHost, pl->stream));
+    MM_HIP(hipStreamSynchronize(pl->stream));
+    return MM_OK;
+}
+
+int host_taps(mm_plan_t pl) {
+    if (!pl->h_taps.empty() || pl->taps.n == 0) return MM_OK;
+    std::vector<double> t(pl->taps.n);
+    MM_HIP(hipMemcpyAsync(t.data(), pl->taps.p, t.size() * 8, hipMemcpyDeviceToHost, pl->stream));
+    MM_HIP(hipStreamSynchronize(pl->stream));
+    pl->h_taps.swap(t);
     return MM_OK;
 }
 
@@ -1093,23 +1125,20 @@ int build_kernels(mm_plan_t pl) {
     }
     const int32_t nk = (int32_t)pl->h_kern_len.size();
     pl->n_kern = nk;
-    std::vector<int64_t> toff, tcnt;
-    std::vector<double> taps;
-    MM_TRY(kernel_taps(pl, 0, taps, toff, tcnt));
-    pl->h_taps.assign(nk, {});
-    std::vector<double> t0(nk);
-    for (int g = 0; g < nk; ++g) {
-        pl->h_taps[g].assign(taps.begin() + toff[g], taps.begin() + toff[g] + tcnt[g]);
-        t0[g] = pl->h_taps[g][0];
-        // t_0 = 0 happens only for a 1-sample interval with 1/f noise (its mean, the
-        // sample itself, is not weighted); a negative or non-finite diagonal is an error
-        if (!(t0[g] >= 0.0) || !std::isfinite(t0[g])) {
-            set_error("kernel of interval length %d has t_0 = %g < 0", pl->h_kern_len[g], t0[g]);
-            return MM_ERR_NOT_SPD;
-        }
-    }
+    // taps stay on the device (the spectra are formed there); the host copy is fetched on
+    // first use
+    pl->h_taps.clear();
+    MM_TRY(kernel_taps_dev(pl, 0, pl->taps, pl->h_taps_off, pl->h_taps_cnt));
+    MM_TRY(pl->taps_off.alloc(nk));
+    MM_TRY(pl->taps_cnt.alloc(nk));
+    MM_HIP(hipMemcpyAsync(pl->taps_off.p, pl->h_taps_off.data(), nk * 8, hipMemcpyHostToDevice, st));
+    MM_HIP(hipMemcpyAsync(pl->taps_cnt.p, pl->h_taps_cnt.data(), nk * 8, hipMemcpyHostToDevice, st));
     MM_TRY(pl->kern_t0.alloc(nk));
-    MM_HIP(hipMemcpyAsync(pl->kern_t0.p, t0.data(), nk * 8, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_gather_t0, dim3((nk + 255) / 256), dim3(256), 0, st, pl->taps.p,
+                       pl->taps_off.p, nk, pl->kern_t0.p);
+    MM_HIP(hipGetLastError());
+    std::vector<double> t0(nk);
+    MM_HIP(hipMemcpyAsync(t0.data(), pl->kern_t0.p, nk * 8, hipMemcpyDeviceToHost, st));
     MM_TRY(pl->int_kern.alloc(pl->n_int));
     MM_HIP(hipMemcpyAsync(pl->int_kern.p, pl->h_int_kern.data(), pl->n_int * 4,
                           hipMemcpyHostToDevice, st));
@@ -1123,6 +1152,14 @@ int build_kernels(mm_plan_t pl) {
     MM_HIP(hipMemcpyAsync(pl->int_lo.p, lo.data(), pl->n_int * 8, hipMemcpyHostToDevice, st));
     MM_HIP(hipMemcpyAsync(pl->int_hi.p, hi.data(), pl->n_int * 8, hipMemcpyHostToDevice, st));
     MM_HIP(hipStreamSynchronize(st));
+    for (int g = 0; g < nk; ++g) {
+        // t_0 = 0 happens only for a 1-sample interval with 1/f noise (its mean, the
+        // sample itself, is not weighted); a negative or non-finite diagonal is an error
+        if (!(t0[g] >= 0.0) || !std::isfinite(t0[g])) {
+            set_error("kernel of interval length %d has t_0 = %g < 0", pl->h_kern_len[g], t0[g]);
+            return MM_ERR_NOT_SPD;
+        }
+    }
     return MM_OK;
 }
 
@@ -1212,53 +1249,41 @@ int build_tiling(mm_plan_t pl, FftTiling& ft, bool fp64, int n_r_request) {
     DBuf<double> d_h, d_min;
     MM_TRY(d_h.alloc((size_t)nk * (M + 1)));
     MM_TRY(d_min.alloc(nk));
-    std::vector<int64_t> toff(nk), tcnt(nk);
-    std::vector<double> flat;
-    for (int g = 0; g < nk; ++g) {
-        toff[g] = (int64_t)flat.size();
-        tcnt[g] = (int64_t)pl->h_taps[g].size();
-        flat.insert(flat.end(), pl->h_taps[g].begin(), pl->h_taps[g].end());
-    }
-    DBuf<double> d_taps;
-    DBuf<int64_t> d_toff, d_tcnt;
-    MM_TRY(d_taps.alloc(flat.size()));
-    MM_TRY(d_toff.alloc(nk));
-    MM_TRY(d_tcnt.alloc(nk));
-    MM_HIP(hipMemcpyAsync(d_taps.p, flat.data(), flat.size() * 8, hipMemcpyHostToDevice, st));
-    MM_HIP(hipMemcpyAsync(d_toff.p, toff.data(), nk * 8, hipMemcpyHostToDevice, st));
-    MM_HIP(hipMemcpyAsync(d_tcnt.p, tcnt.data(), nk * 8, hipMemcpyHostToDevice, st));
+    const double* d_taps = pl->taps.p;
+    const int64_t* d_toff = pl->taps_off.p;
+    const int64_t* d_tcnt = pl->taps_cnt.p;
     if (logm <= kPlanLogM) {  // FP64 FFT of the even kernel on the tile grid
         DBuf<double> d_tw;
         MM_TRY(d_tw.alloc(2 * M));
         MM_HIP(hipMemcpyAsync(d_tw.p, tw.data(), 2 * M * 8, hipMemcpyHostToDevice, st));
         switch (logm) {
             case 10:
-                hipLaunchKernelGGL((k_spec_fft<10, 256>), dim3(nk), dim3(256), 0, st, d_taps.p,
-                                   d_toff.p, d_tcnt.p, d_tw.p, d_h.p);
+                hipLaunchKernelGGL((k_spec_fft<10, 256>), dim3(nk), dim3(256), 0, st, d_taps,
+                                   d_toff, d_tcnt, d_tw.p, d_h.p);
                 break;
             case 11:
-                hipLaunchKernelGGL((k_spec_fft<11, 256>), dim3(nk), dim3(256), 0, st, d_taps.p,
-                                   d_toff.p, d_tcnt.p, d_tw.p, d_h.p);
+                hipLaunchKernelGGL((k_spec_fft<11, 256>), dim3(nk), dim3(256), 0, st, d_taps,
+                                   d_toff, d_tcnt, d_tw.p, d_h.p);
                 break;
             case 12:
-                hipLaunchKernelGGL((k_spec_fft<12, 256>), dim3(nk), dim3(256), 0, st, d_taps.p,
-                                   d_toff.p, d_tcnt.p, d_tw.p, d_h.p);
+                hipLaunchKernelGGL((k_spec_fft<12, 256>), dim3(nk), dim3(256), 0, st, d_taps,
+                                   d_toff, d_tcnt, d_tw.p, d_h.p);
                 break;
             default:
                 hipLaunchKernelGGL((k_spec_fft<kPlanLogM, kPlanNT>), dim3(nk), dim3(kPlanNT), 0, st,
-                                   d_taps.p, d_toff.p, d_tcnt.p, d_tw.p, d_h.p);
+                                   d_taps, d_toff, d_tcnt, d_tw.p, d_h.p);
                 break;
         }
         MM_HIP(hipGetLastError());
-        MM_HIP(hipStreamSynchronize(st));
     } else {  // 2^15-point tiles (FP32 only): direct cosine sums
+        MM_TRY(host_taps(pl));
         std::vector<int64_t> boff(nk), bcnt(nk), nper(nk, ft.n_r), jcnt(nk, M + 1), ooff(nk);
         std::vector<double> b;
         for (int g = 0; g < nk; ++g) {
             boff[g] = (int64_t)b.size();
-            bcnt[g] = (int64_t)pl->h_taps[g].size();
-            for (size_t k = 0; k < pl->h_taps[g].size(); ++k)
-                b.push_back((k == 0 ? 1.0 : 2.0) * pl->h_taps[g][k]);
+            bcnt[g] = pl->h_taps_cnt[g];
+            const double* t = pl->h_taps.data() + pl->h_taps_off[g];
+            for (int64_t k = 0; k < bcnt[g]; ++k) b.push_back((k == 0 ? 1.0 : 2.0) * t[k]);
             ooff[g] = (int64_t)g * (M + 1);
         }
         DBuf<double> d_b;
@@ -1279,7 +1304,6 @@ int build_tiling(mm_plan_t pl, FftTiling& ft, bool fp64, int n_r_request) {
                            dim3(kCtThreads), 0, st, d_b.p, d_boff.p, d_bcnt.p, d_nper.p, d_jcnt.p,
                            d_ooff.p, d_h.p, nk);
         MM_HIP(hipGetLastError());
-        MM_HIP(hipStreamSynchronize(st));
     }
     const double scale = 1.0 / (2.0 * (double)ft.n_r);
     if (fp64) {
@@ -1320,9 +1344,11 @@ int pack_map32(mm_plan_t pl, const double* x) {
     return pl->n_s == 3 ? pack_map<float>(pl, x, pl->xp32.p) : MM_OK;
 }
 
-int toeplitz_map64(mm_plan_t pl, const double* x, double* z, const int* mask, bool skip_zero) {
+int toeplitz_map64(mm_plan_t pl, const double* x, double* z, const int* mask, bool skip_zero,
+                   const uint8_t* int_on) {
     auto a = base_args<double>(pl, pl->fft64);
     a.skip_zero = skip_zero;
+    a.int_on = skip_zero ? int_on : nullptr;
     a.x = x;
     if (pl->n_s == 3) a.xp = pl->xp64.p;
     a.mode = pl->n_s == 3 ? 0 : 1;
@@ -1331,9 +1357,11 @@ int toeplitz_map64(mm_plan_t pl, const double* x, double* z, const int* mask, bo
     return launch<double>(a, pl->fft64.logm, pl->fft64.n_tiles, pl->stream);
 }
 
-int toeplitz_map32(mm_plan_t pl, const double* x, float* z, const int* mask, bool skip_zero) {
+int toeplitz_map32(mm_plan_t pl, const double* x, float* z, const int* mask, bool skip_zero,
+                   const uint8_t* int_on) {
     auto a = base_args<float>(pl, pl->fft32);
     a.skip_zero = skip_zero;
+    a.int_on = skip_zero ? int_on : nullptr;
     a.x = x;
     if (pl->n_s == 3) a.xp = pl->xp32.p;
     a.mode = pl->n_s == 3 ? 0 : 1;
