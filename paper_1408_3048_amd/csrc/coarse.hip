@@ -289,12 +289,12 @@ __global__ void k_az_rows(const TA* __restrict__ az, int64_t n_vec, int64_t n_ob
 // and holds D(i = l/16 + 4 v, j = l%16) in accumulator register v (v = 0..3).
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void k_gemm_tn_f64(const double* __restrict__ A,
-                                                     const double* __restrict__ B, int64_t n,
-                                                     int32_t ra, int32_t rb, int32_t ksplit,
-                                                     double* __restrict__ part) {
+// one wave's share of C = A^T B: output tile (ta, tb) of the slab ks of the n dimension
+__device__ __forceinline__ void gemm_tn_wave(const double* __restrict__ A,
+                                             const double* __restrict__ B, int64_t n, int32_t ra,
+                                             int32_t rb, int32_t ksplit, int64_t wid,
+                                             double* __restrict__ part) {
     const int lane = threadIdx.x & 63;
-    const int64_t wid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int32_t ta_n = ra / 16, tb_n = rb / 16;
     const int64_t ntile = (int64_t)ta_n * tb_n;
     if (wid >= ntile * ksplit) return;
@@ -322,6 +322,13 @@ __global__ __launch_bounds__(256) void k_gemm_tn_f64(const double* __restrict__ 
     }
 }
 
+__global__ __launch_bounds__(256) void k_gemm_tn_f64(const double* __restrict__ A,
+                                                     const double* __restrict__ B, int64_t n,
+                                                     int32_t ra, int32_t rb, int32_t ksplit,
+                                                     double* __restrict__ part) {
+    gemm_tn_wave(A, B, n, ra, rb, ksplit, (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6), part);
+}
+
 __global__ void k_sum_parts(const double* __restrict__ part, int64_t m, int32_t ksplit,
                             double* __restrict__ out) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
@@ -330,6 +337,87 @@ __global__ void k_sum_parts(const double* __restrict__ part, int64_t m, int32_t 
         for (int32_t k = 0; k < ksplit; ++k) s += part[(int64_t)k * m + e];
         out[e] = s;
     }
+}
+
+// Gram products E_b = Z_b^T (AZ)_b of several problems in one launch: problem b's row
+// blocks start at a_off in A and B (row-major [n][rp], rp a multiple of 16), its partials
+// at part_off, its E at c_off; its waves are [woff[b], woff[b+1]) and the slab split
+// ksplit is the one the single-problem product takes, so every E_b is bitwise the same.
+struct GramDesc {
+    int64_t a_off, n, part_off, c_off;
+    int32_t rp, ksplit;
+};
+
+__device__ __forceinline__ int find_off(const int64_t* __restrict__ off, int nb, int64_t v) {
+    int a = 0, b = nb - 1;
+    while (a < b) {
+        const int m = (a + b + 1) >> 1;
+        if (off[m] <= v) a = m; else b = m - 1;
+    }
+    return a;
+}
+
+__global__ __launch_bounds__(256) void k_gemm_tn_f64_batch(const double* __restrict__ A,
+                                                           const double* __restrict__ B,
+                                                           const GramDesc* __restrict__ d,
+                                                           const int64_t* __restrict__ woff,
+                                                           int nb, double* __restrict__ part) {
+    const int64_t wid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wid >= woff[nb]) return;
+    const int b = find_off(woff, nb, wid);
+    const GramDesc g = d[b];
+    gemm_tn_wave(A + g.a_off, B + g.a_off, g.n, g.rp, g.rp, g.ksplit, wid - woff[b],
+                 part + g.part_off);
+}
+
+// E entries of the problems: [eoff[b], eoff[b+1]) is problem b's rp x rp block
+__global__ void k_sum_parts_batch(const double* __restrict__ part, const GramDesc* __restrict__ d,
+                                  const int64_t* __restrict__ eoff, int nb,
+                                  double* __restrict__ out) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < eoff[nb];
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int b = find_off(eoff, nb, e);
+        const GramDesc g = d[b];
+        const int64_t m = (int64_t)g.rp * g.rp, loc = e - eoff[b];
+        double s = 0.0;
+        for (int32_t k = 0; k < g.ksplit; ++k) s += part[g.part_off + (int64_t)k * m + loc];
+        out[g.c_off + loc] = s;
+    }
+}
+
+// dense I rows of the distinct Z_S columns of problems b0 + z (z = blockIdx.z) in the row
+// blocks of the Gram products (row p - ooff[b], column c)
+__global__ void k_dense_z_batch(const int64_t* __restrict__ cb, const int64_t* __restrict__ ce,
+                                const int32_t* __restrict__ rows, const double* __restrict__ vals,
+                                const int32_t* __restrict__ ud_off,
+                                const int64_t* __restrict__ ooff, const GramDesc* __restrict__ d,
+                                int b0, double* __restrict__ zd) {
+    const int b = b0 + (int)blockIdx.z;
+    const int32_t c = blockIdx.y;
+    if (c >= ud_off[b + 1] - ud_off[b]) return;
+    const GramDesc g = d[blockIdx.z];
+    const int32_t u = ud_off[b] + c;
+    for (int64_t i = cb[u] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ce[u];
+         i += (int64_t)gridDim.x * blockDim.x)
+        zd[g.a_off + ((int64_t)rows[i] - ooff[b]) * g.rp + c] = vals[i];
+}
+
+// I rows of problem b0 + z's AZ block (column-major [r_b][n_vec_b] at az_off[b]) in the row
+// blocks of the Gram products
+template <typename TA>
+__global__ void k_az_rows_batch(const TA* __restrict__ az, const int64_t* __restrict__ az_off,
+                                const int32_t* __restrict__ ud_off,
+                                const int64_t* __restrict__ ooff, int ns,
+                                const GramDesc* __restrict__ d, int b0, double* __restrict__ out) {
+    const int b = b0 + (int)blockIdx.z;
+    const int32_t c = blockIdx.y;
+    if (c >= ud_off[b + 1] - ud_off[b]) return;
+    const GramDesc g = d[blockIdx.z];
+    const int64_t nob = ooff[b + 1] - ooff[b], n_vec = nob * ns;
+    const TA* src = az + az_off[b] + (int64_t)c * n_vec;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nob;
+         p += (int64_t)gridDim.x * blockDim.x)
+        out[g.a_off + p * g.rp + c] = (double)src[p * ns];
 }
 
 // v = Z^T r: kept column c owns the slices [vslice[c], vslice[c+1]) of 512 entries; one
@@ -803,10 +891,19 @@ bool spd_inverse(const std::vector<double>& A, int k, std::vector<double>& out) 
 
 // C[ra][rb] (device, row-major) = A^T B for device row-major A [n][ra], B [n][rb], enqueued
 // on st (no synchronisation: its scratch is released in stream order)
+// slabs of the n dimension: about 64 MFMA steps per wave, at most 4096 waves in all
+int32_t gram_ksplit(int64_t n, int32_t ra, int32_t rb) {
+    const int32_t ntile = (ra / 16) * (rb / 16);
+    return (int32_t)std::max<int64_t>(1, std::min<int64_t>(n / 4 / 64, 4096 / std::max(1, ntile)));
+}
+
+// dense row blocks of the batched Gram products, zd and azr together (bytes)
+constexpr int64_t kGramBudget = (int64_t)1 << 30;
+
 int gemm_tn_f64(hipStream_t st, const double* A, const double* B, int64_t n, int32_t ra,
                 int32_t rb, double* dev_C) {
     const int32_t ntile = (ra / 16) * (rb / 16);
-    int32_t ksplit = (int32_t)std::max<int64_t>(1, std::min<int64_t>(n / 4 / 64, 4096 / std::max(1, ntile)));
+    const int32_t ksplit = gram_ksplit(n, ra, rb);
     DBuf<double> part;
     MM_TRY(part.alloc((size_t)ksplit * ra * rb));
     const int64_t waves = (int64_t)ntile * ksplit;
@@ -1048,36 +1145,78 @@ int build_coarse(mm_plan_t pl) {
     on.release();
     tick("AZ");
     // per problem: E_b = Z_b^T (AZ)_b on the matrix cores, independent subset, E_b^-1
-    int64_t npad_max = 0;
-    for (int b = 0; b < B; ++b) npad_max = std::max<int64_t>(npad_max, (oo[b + 1] - oo[b] + 3) / 4 * 4);
-    const int32_t rp_max = (rd_max + 15) / 16 * 16;
-    // every problem's E_b into one device array (offsets eoff), read back once
+    // every problem's E_b = Z_b^T (AZ)_b on the matrix cores into one device array
+    // (offsets eoff), in batched launches over groups of problems whose dense row blocks
+    // fit kGramBudget bytes, read back once
     std::vector<int64_t> eoff(B + 1, 0);
     for (int b = 0; b < B; ++b) {
         const int64_t rp = (ud_off[b + 1] - ud_off[b] + 15) / 16 * 16;
         eoff[b + 1] = eoff[b] + rp * rp;
     }
-    DBuf<double> zd, azr, dE;
-    MM_TRY(zd.alloc((size_t)npad_max * rp_max));
-    MM_TRY(azr.alloc((size_t)npad_max * rp_max));
+    DBuf<double> dE;
+    DBuf<int32_t> d_ud_off;
     MM_TRY(dE.alloc((size_t)eoff[B]));
-    for (int b = 0; b < B; ++b) {
-        const int32_t rb = ud_off[b + 1] - ud_off[b];
-        const int64_t nob = oo[b + 1] - oo[b];
-        const int32_t rp = (rb + 15) / 16 * 16;
-        const int64_t npad = (nob + 3) / 4 * 4;
-        MM_HIP(hipMemsetAsync(zd.p, 0, (size_t)npad * rp * 8, st));
-        MM_HIP(hipMemsetAsync(azr.p, 0, (size_t)npad * rp * 8, st));
-        hipLaunchKernelGGL(k_dense_z, dim3(64, rb), dim3(256), 0, st, dub.p + ud_off[b],
-                           due.p + ud_off[b], crow.p, cval.p, rb, rp, oo[b], zd.p);
+    MM_TRY(d_ud_off.alloc(B + 1));
+    MM_HIP(hipMemcpyAsync(d_ud_off.p, ud_off.data(), (B + 1) * 4, hipMemcpyHostToDevice, st));
+    for (int b0 = 0; b0 < B;) {
+        std::vector<GramDesc> gd;
+        std::vector<int64_t> woff(1, 0), leoff(1, 0);
+        int64_t rows = 0, parts = 0;
+        int32_t rmax = 1;
+        int64_t nob_max = 1;
+        int b1 = b0;
+        for (; b1 < B; ++b1) {
+            const int32_t rb = ud_off[b1 + 1] - ud_off[b1];
+            const int32_t rp = (rb + 15) / 16 * 16;
+            const int64_t nob = oo[b1 + 1] - oo[b1];
+            const int64_t npad = (nob + 3) / 4 * 4;
+            if (b1 > b0 && ((rows + npad * rp) * 16 > kGramBudget || b1 - b0 == 65535)) break;
+            GramDesc g;
+            g.a_off = rows;
+            g.n = npad;
+            g.rp = rp;
+            g.ksplit = gram_ksplit(npad, rp, rp);
+            g.part_off = parts;
+            g.c_off = eoff[b1];
+            gd.push_back(g);
+            rows += npad * rp;
+            parts += (int64_t)g.ksplit * rp * rp;
+            woff.push_back(woff.back() + (int64_t)(rp / 16) * (rp / 16) * g.ksplit);
+            leoff.push_back(leoff.back() + (int64_t)rp * rp);
+            rmax = std::max(rmax, rb);
+            nob_max = std::max(nob_max, nob);
+        }
+        const int nbc = b1 - b0;
+        DBuf<GramDesc> d_gd;
+        DBuf<int64_t> d_woff, d_leoff;
+        DBuf<double> zd, azr, part;
+        MM_TRY(d_gd.alloc(nbc));
+        MM_TRY(d_woff.alloc(nbc + 1));
+        MM_TRY(d_leoff.alloc(nbc + 1));
+        MM_TRY(zd.alloc((size_t)rows));
+        MM_TRY(azr.alloc((size_t)rows));
+        MM_TRY(part.alloc((size_t)parts));
+        MM_HIP(hipMemcpyAsync(d_gd.p, gd.data(), nbc * sizeof(GramDesc), hipMemcpyHostToDevice, st));
+        MM_HIP(hipMemcpyAsync(d_woff.p, woff.data(), (nbc + 1) * 8, hipMemcpyHostToDevice, st));
+        MM_HIP(hipMemcpyAsync(d_leoff.p, leoff.data(), (nbc + 1) * 8, hipMemcpyHostToDevice, st));
+        MM_HIP(hipMemsetAsync(zd.p, 0, (size_t)rows * 8, st));
+        MM_HIP(hipMemsetAsync(azr.p, 0, (size_t)rows * 8, st));
+        hipLaunchKernelGGL(k_dense_z_batch, dim3(64, rmax, nbc), dim3(256), 0, st, dub.p, due.p,
+                           crow.p, cval.p, d_ud_off.p, pl->ooff.p, d_gd.p, b0, zd.p);
         if (mixed)
-            hipLaunchKernelGGL(k_az_rows<float>, dim3(grid_for(nob, 256, 4096), rb), dim3(256), 0,
-                               st, azf.p + azd_off[b], nob * ns, nob, (int)ns, rb, rp, azr.p);
+            hipLaunchKernelGGL(k_az_rows_batch<float>, dim3(grid_for(nob_max, 256, 4096), rmax, nbc),
+                               dim3(256), 0, st, azf.p, d_azd_off.p, d_ud_off.p, pl->ooff.p,
+                               (int)ns, d_gd.p, b0, azr.p);
         else
-            hipLaunchKernelGGL(k_az_rows<double>, dim3(grid_for(nob, 256, 4096), rb), dim3(256), 0,
-                               st, azd.p + azd_off[b], nob * ns, nob, (int)ns, rb, rp, azr.p);
+            hipLaunchKernelGGL(k_az_rows_batch<double>, dim3(grid_for(nob_max, 256, 4096), rmax, nbc),
+                               dim3(256), 0, st, azd.p, d_azd_off.p, d_ud_off.p, pl->ooff.p,
+                               (int)ns, d_gd.p, b0, azr.p);
+        hipLaunchKernelGGL(k_gemm_tn_f64_batch, dim3((woff[nbc] + 3) / 4), dim3(256), 0, st, zd.p,
+                           azr.p, d_gd.p, d_woff.p, nbc, part.p);
+        hipLaunchKernelGGL(k_sum_parts_batch, dim3(grid_for(leoff[nbc])), dim3(256), 0, st, part.p,
+                           d_gd.p, d_leoff.p, nbc, dE.p);
         MM_HIP(hipGetLastError());
-        MM_TRY(gemm_tn_f64(st, zd.p, azr.p, npad, rp, rp, dE.p + eoff[b]));
+        b0 = b1;
     }
     std::vector<double> Eh((size_t)eoff[B]);
     MM_HIP(hipMemcpyAsync(Eh.data(), dE.p, Eh.size() * 8, hipMemcpyDeviceToHost, st));
@@ -1121,8 +1260,6 @@ int build_coarse(mm_plan_t pl) {
         co.r_max = std::max(co.r_max, k);
         sels[b] = std::move(sel);
     }
-    zd.release();
-    azr.release();
     dE.release();
     const int32_t keff = co.h_col_off[B];
     co.r_eff = keff;
