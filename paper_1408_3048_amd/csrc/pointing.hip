@@ -35,13 +35,18 @@ __device__ __forceinline__ void seg_reduce(int64_t i0, int64_t i1, int64_t p0,
         bool valid[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) valid[e] = base + e >= i0 && base + e < i1;
-        uint32_t hb = 0;
-        if (base < i1) hb = (uint32_t)(heads[base >> 6] >> (base & 63)) & ((1u << E) - 1u);
+        // segment-start words of the lane's samples and of the sample after them, loaded
+        // unconditionally (a valid word for lanes past the range) ahead of the samples, so
+        // that a chunk's loads are in flight together; their bits are read after load()
+        const int64_t inext = base + E;
+        const unsigned long long hw = heads[(base < i1 ? base : i0) >> 6];
+        const unsigned long long hn = heads[(inext < i1 ? inext : i0) >> 6];
+        T v[E][NV];
+        load(base, valid, v);
+        uint32_t hb = base < i1 ? (uint32_t)(hw >> (base & 63)) & ((1u << E) - 1u) : 0u;
 #pragma unroll
         for (int e = 0; e < E; ++e)
             if (!valid[e]) hb &= ~(1u << e);
-        T v[E][NV];
-        load(base, valid, v);
         // lane-local segmented prefix sums
         T sl[E][NV];
         T run[NV];
@@ -94,9 +99,8 @@ __device__ __forceinline__ void seg_reduce(int64_t i0, int64_t i1, int64_t p0,
             for (int q = 0; q < NV; ++q) pre[q] += carry[q];
         }
         // segment ends and totals
-        bool next_head_last = false;
-        const int64_t il = base + E;
-        if (valid[E - 1] && il < i1) next_head_last = (heads[il >> 6] >> (il & 63)) & 1ull;
+        const bool next_head_last =
+            valid[E - 1] && inext < i1 && ((hn >> (inext & 63)) & 1ull) != 0;
         int64_t pix = pprev + (hcs - hc);
         T last[NV];
 #pragma unroll
@@ -158,25 +162,61 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ per
     const int64_t i1 = seg[p1 - 1] + hits[p1 - 1];
     const int lane = threadIdx.x & 63;
     T* zw = zx[threadIdx.x >> 6];
-    // sample indices of the next chunk, loaded one chunk ahead (-1 outside [i0, i1))
+    // sample indices of the next chunk, loaded one chunk ahead (-1 outside [i0, i1)).  The
+    // loads here and the z gathers below are unconditional, from a valid address for lanes
+    // outside the range (sorted position i0, sample 0), with the value selected afterwards:
+    // guarded loads become one branch each, and the compiler then waits for every load
+    // before issuing the next.
     int32_t pf[E];
     auto fetch = [&](int64_t c) {
 #pragma unroll
         for (int g = 0; g < E; ++g) {
             const int64_t i = c + lane + 64 * g;
-            pf[g] = i >= i0 && i < i1 ? perm[i] : -1;
+            const bool in = i >= i0 && i < i1;
+            const int32_t t = perm[in ? i : i0];
+            pf[g] = in ? t : -1;
         }
     };
     fetch(i0 & ~(int64_t)(E - 1));
     auto load = [&](int64_t base, const bool* valid, T (*v)[NS]) {
+        // the sorted weights are loaded first, so their latency overlaps the z gather's
+        // (loads after the exchange below would wait for it); lanes past the range skip them
+        T wv[2 * E];
+        if constexpr (NS == 3) {
+            if (base < i1) {
+                if constexpr (sizeof(T) == 4) {
+#pragma unroll
+                    for (int g = 0; g < E / 2; ++g) {
+                        const float4 a = *reinterpret_cast<const float4*>(ws + 2 * base + 4 * g);
+                        wv[4 * g] = a.x;
+                        wv[4 * g + 1] = a.y;
+                        wv[4 * g + 2] = a.z;
+                        wv[4 * g + 3] = a.w;
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < E; ++e) {
+                        const double2 a = *reinterpret_cast<const double2*>(ws + 2 * (base + e));
+                        wv[2 * e] = a.x;
+                        wv[2 * e + 1] = a.y;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < 2 * E; ++e) wv[e] = (T)0;
+            }
+        }
         // every lane takes part in the exchange, also lanes past the range
         const int64_t c = base - (int64_t)E * lane;
         int32_t tc[E];
 #pragma unroll
         for (int g = 0; g < E; ++g) tc[g] = pf[g];
         fetch(c + 64 * E);
+        T zg[E];
 #pragma unroll
-        for (int g = 0; g < E; ++g) zw[lane + 64 * g] = tc[g] >= 0 ? z[tc[g]] : (T)0;
+        for (int g = 0; g < E; ++g) zg[g] = z[tc[g] >= 0 ? tc[g] : 0];
+#pragma unroll
+        for (int g = 0; g < E; ++g) zw[lane + 64 * g] = tc[g] >= 0 ? zg[g] : (T)0;
         wave_lds_sync();
         T zz[E];
 #pragma unroll
@@ -192,24 +232,6 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ per
 #pragma unroll
         for (int e = 0; e < E; ++e) zz[e] = valid[e] ? zz[e] : (T)0;
         if constexpr (NS == 3) {
-            T wv[2 * E];
-            if constexpr (sizeof(T) == 4) {
-#pragma unroll
-                for (int g = 0; g < E / 2; ++g) {
-                    const float4 a = *reinterpret_cast<const float4*>(ws + 2 * base + 4 * g);
-                    wv[4 * g] = a.x;
-                    wv[4 * g + 1] = a.y;
-                    wv[4 * g + 2] = a.z;
-                    wv[4 * g + 3] = a.w;
-                }
-            } else {
-#pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    const double2 a = *reinterpret_cast<const double2*>(ws + 2 * (base + e));
-                    wv[2 * e] = a.x;
-                    wv[2 * e + 1] = a.y;
-                }
-            }
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 v[e][0] = zz[e];
