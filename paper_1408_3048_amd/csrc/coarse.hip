@@ -420,31 +420,48 @@ __global__ void k_az_rows_batch(const TA* __restrict__ az, const int64_t* __rest
         out[g.a_off + p * g.rp + c] = (double)src[p * ns];
 }
 
-// v = Z^T r: kept column c owns the slices [vslice[c], vslice[c+1]) of 512 entries; one
-// wave per slice writes its partial sum to vpart[slice]
+// v = Z^T r: kept column c owns the slices [vslice[c], vslice[c+1]) of 512 entries
+// (slice_col: the column of every slice); one wave per slice writes its partial sum to
+// vpart[slice].  A lane's entries a + lane + 64 k are loaded together (from entry a where
+// past the slice end: guarded loads would be waited for one by one) and summed in order.
 __global__ __launch_bounds__(256) void k_ztr(const int64_t* __restrict__ cbeg,
                                              const int64_t* __restrict__ cend,
                                              const int32_t* __restrict__ rows,
                                              const double* __restrict__ vals,
-                                             const double* __restrict__ r, int ns, int32_t rk,
-                                             const int32_t* __restrict__ vslice, int64_t n_slices,
+                                             const double* __restrict__ r, int ns,
+                                             const int32_t* __restrict__ vslice,
+                                             const int32_t* __restrict__ slice_col,
+                                             int64_t n_slices,
                                              const int32_t* __restrict__ col_prob,
                                              double* __restrict__ vpart,
                                              const int* __restrict__ mask) {
+    constexpr int K = 512 / 64;
     const int lane = threadIdx.x & 63;
     const int64_t wv = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (wv >= n_slices) return;
-    int32_t lo = 0, hi = rk - 1;  // column: largest c with vslice[c] <= wv
-    while (lo < hi) {
-        const int32_t m = (lo + hi + 1) >> 1;
-        if (vslice[m] <= wv) lo = m; else hi = m - 1;
-    }
-    const int32_t c = lo;
+    const int32_t c = slice_col[wv];
     if (mask && !mask[col_prob[c]]) return;
     const int64_t a = cbeg[c] + (wv - vslice[c]) * 512;
     const int64_t b = a + 512 < cend[c] ? a + 512 : cend[c];
+    if (a >= b) {  // empty column
+        if (lane == 0) vpart[wv] = 0.0;
+        return;
+    }
+    int32_t rw[K];
+    double vv[K], rr[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t e = a + lane + 64 * k;
+        const int64_t ec = e < b ? e : a;
+        rw[k] = rows[ec];
+        vv[k] = vals[ec];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) rr[k] = r[(int64_t)rw[k] * ns];
     double s = 0.0;
-    for (int64_t e = a + lane; e < b; e += 64) s += vals[e] * r[(int64_t)rows[e] * ns];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if (a + lane + 64 * k < b) s += vv[k] * rr[k];
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
     if (lane == 0) vpart[wv] = s;
 }
@@ -1319,6 +1336,11 @@ int build_coarse(mm_plan_t pl) {
     for (int32_t a = 0; a < keff; ++a)
         vs[a + 1] = vs[a] + (int32_t)std::max<int64_t>(1, (ke[a] - kb[a] + 511) / 512);
     co.n_slices = vs[keff];
+    std::vector<int32_t> scol((size_t)co.n_slices);
+    for (int32_t a = 0; a < keff; ++a)
+        for (int32_t t = vs[a]; t < vs[a + 1]; ++t) scol[t] = a;
+    MM_TRY(co.slice_col.alloc(co.n_slices));
+    MM_HIP(hipMemcpyAsync(co.slice_col.p, scol.data(), co.n_slices * 4, hipMemcpyHostToDevice, st));
     co.csc_row.swap(crow);
     co.csc_val.swap(cval);
     MM_TRY(co.csc_beg.alloc(keff));
@@ -1656,6 +1678,7 @@ int build_coarse_dense(mm_plan_t pl, const double* basis, int64_t basis_stride,
     co.Einv.swap(d_einv);
     co.w.swap(d_w);
     co.vslice.release();
+    co.slice_col.release();
     co.vpart.release();
     co.n_slices = 0;
     co.ch_off.swap(d_choff);
@@ -1751,8 +1774,8 @@ int twolvl_apply(mm_plan_t pl, const double* r, double* z, const PcgCtl& ctl) {
     hipStream_t st = pl->stream;
     const int32_t k = co.r_eff;
     hipLaunchKernelGGL(k_ztr, dim3((co.n_slices + 3) / 4), dim3(256), 0, st, co.csc_beg.p,
-                       co.csc_end.p, co.csc_row.p, co.csc_val.p, r, pl->n_s, k, co.vslice.p,
-                       co.n_slices, co.col_prob.p, co.vpart.p, ctl.mask);
+                       co.csc_end.p, co.csc_row.p, co.csc_val.p, r, pl->n_s, co.vslice.p,
+                       co.slice_col.p, co.n_slices, co.col_prob.p, co.vpart.p, ctl.mask);
     hipLaunchKernelGGL(k_einv, dim3((k + 3) / 4), dim3(256), 0, st, co.Einv.p, co.einv_off.p,
                        co.col_off.p, co.col_prob.p, co.vpart.p, co.vslice.p, k, co.w.p, ctl.mask);
     const size_t shm = (size_t)co.r_max * sizeof(double);
@@ -1817,8 +1840,8 @@ int coarse_w(mm_plan_t pl, const double* r, const double* y, const int* mask) {
                    : chunk_partials<double>(pl, co.ZD64.p, r, co.cpart.p, mask));
     } else {
         hipLaunchKernelGGL(k_ztr, dim3((co.n_slices + 3) / 4), dim3(256), 0, st, co.csc_beg.p,
-                           co.csc_end.p, co.csc_row.p, co.csc_val.p, r, pl->n_s, co.r_eff,
-                           co.vslice.p, co.n_slices, co.col_prob.p, co.vpart.p, mask);
+                           co.csc_end.p, co.csc_row.p, co.csc_val.p, r, pl->n_s, co.vslice.p,
+                           co.slice_col.p, co.n_slices, co.col_prob.p, co.vpart.p, mask);
         MM_HIP(hipGetLastError());
     }
     if (y)

@@ -183,6 +183,7 @@ struct Coarse {
     DBuf<double> Einv;               // E^-1 blocks
     DBuf<double> w;                  // coarse solution [r_eff]
     DBuf<int32_t> vslice;            // [r_eff+1] first Z^T r slice of every kept column
+    DBuf<int32_t> slice_col;         // [n_slices] kept column of every slice
     int64_t n_slices = 0;            // slices of 512 entries over all kept columns
     DBuf<double> vpart;              // [n_slices] partial sums of Z^T r
     DBuf<int64_t> ch_off;            // [B+1] first chunk (kZtChunk vector entries) of every problem

@@ -297,7 +297,19 @@ __global__ __launch_bounds__(256) void k_bj_build(
     // the interval [jlo, jhi) and t_0 of its last sample and searches only outside it
     int64_t jlo = 0, jhi = 0;
     double dj = 0.0;
+    const int64_t s0 = seg[p0];  // a valid sorted position for the unconditional loads
     auto load = [&](int64_t base, const bool* valid, double (*v)[NV]) {
+        int64_t tt[E];
+        double wa[E], wb[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int64_t ic = valid[e] ? base + e : s0;
+            tt[e] = perm[ic];
+            if constexpr (NV == 6) {
+                wa[e] = ws[2 * ic];
+                wb[e] = ws[2 * ic + 1];
+            }
+        }
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             if (!valid[e]) {
@@ -305,7 +317,7 @@ __global__ __launch_bounds__(256) void k_bj_build(
                 for (int q = 0; q < NV; ++q) v[e][q] = 0.0;
                 continue;
             }
-            const int64_t t = perm[base + e];
+            const int64_t t = tt[e];
             if (t < jlo || t >= jhi) {
                 const int32_t j = interval_of(int_lo, n_int, t);
                 jlo = int_lo[j];
@@ -314,7 +326,7 @@ __global__ __launch_bounds__(256) void k_bj_build(
             }
             const double d = dj;
             if constexpr (NV == 6) {
-                const double a = ws[2 * (base + e)], b = ws[2 * (base + e) + 1];
+                const double a = wa[e], b = wb[e];
                 v[e][0] = d;
                 v[e][1] = d * a;
                 v[e][2] = d * b;
