@@ -645,6 +645,53 @@ __device__ __forceinline__ bool load_window(const ToepArgs<T>& a, const CBuf<T>&
     const int i_lo = (int)(lo > base ? lo - base : 0);
     const int i_hi = (int)(hi - base < (int64_t)win ? hi - base : (int64_t)win);
     bool nz = false;
+    if constexpr (MODE == 0 && sizeof(T) == 4) {
+        // FP32 IQU map gather, software-pipelined: the indices and weights of batch k + 1
+        // are loaded while the map gathers of batch k are in flight, so a batch waits for
+        // one memory latency instead of two (the values are those of the plain loop below)
+        const int32_t* cb = a.cid + base;
+        const float2* wb = reinterpret_cast<const float2*>(a.w) + base;
+        const char* xpb = reinterpret_cast<const char*>(a.xp);
+        auto pos = [&](int k) -> uint32_t {
+            const int i = threadIdx.x + k * NT;
+            return (uint32_t)(i >= i_lo && i < i_hi ? i : i_lo);
+        };
+        uint32_t cc[B];
+        float2 ww[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const uint32_t r = pos(u);
+            cc[u] = (uint32_t)cb[r];
+            ww[u] = wb[r];
+        }
+#pragma unroll
+        for (int b0 = 0; b0 < PER; b0 += B) {
+            float4 xx[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u)
+                xx[u] = *reinterpret_cast<const float4*>(xpb + cc[u] * (uint32_t)sizeof(float4));
+            float2 wcur[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) wcur[u] = ww[u];
+            if (b0 + B < PER) {
+#pragma unroll
+                for (int u = 0; u < B; ++u) {
+                    const uint32_t r = pos(b0 + B + u);
+                    cc[u] = (uint32_t)cb[r];
+                    ww[u] = wb[r];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const int i = threadIdx.x + (b0 + u) * NT;
+                const bool ok = i >= i_lo && i < i_hi;
+                const T v = ok ? xx[u].x + wcur[u].x * xx[u].y + wcur[u].y * xx[u].z : (T)0;
+                buf.put_part_sw(sbase ^ swz((b0 + u) * (NT / 2)), part, v);
+                nz = nz || v != (T)0;
+            }
+        }
+        return nz;
+    }
 #pragma unroll
     for (int b0 = 0; b0 < PER; b0 += B) {
         uint32_t rr[B];
