@@ -1113,9 +1113,16 @@ int build_coarse(mm_plan_t pl) {
     hipLaunchKernelGGL(k_az_int_flags, dim3(grid_for(n_obs)), dim3(256), 0, st, ptr.p, col.p,
                        n_obs, d_layer.p, K, rd_max, on.p);
     MM_HIP(hipGetLastError());
+    std::vector<int32_t> h_rb(B);
+    for (int b = 0; b < B; ++b) h_rb[b] = ud_off[b + 1] - ud_off[b];
+    DBuf<int32_t> d_rb;
+    MM_TRY(d_rb.alloc(B));
+    MM_HIP(hipMemcpyAsync(d_rb.p, h_rb.data(), B * 4, hipMemcpyHostToDevice, st));
     DBuf<double> zc, tmp;
     MM_TRY(zc.alloc(nv));
-    MM_TRY(tmp.alloc(nv));
+    if (!mixed) MM_TRY(tmp.alloc(nv));
+    DBuf<float> tod2;  // mixed: the time streams of two layers, interleaved
+    if (mixed) MM_TRY(tod2.alloc((size_t)2 * pl->n_t));
     DBuf<int32_t> lcols, lprob;
     MM_TRY(lcols.alloc((size_t)rd_max * B));
     MM_TRY(lprob.alloc((size_t)rd_max * B));
@@ -1135,30 +1142,44 @@ int build_coarse(mm_plan_t pl) {
         for (int b = 0; b < B; ++b) nb_max = std::max<int64_t>(nb_max, (oo[b + 1] - oo[b]) * ns);
         const int sgx = (int)std::min<int64_t>(1024, (nb_max + 255) / 256);
         int64_t lo = 0;
-        for (int32_t k = 0; k < rd_max; ++k) {
-            const int nl = lcnt[k];
-            const uint8_t* on_k = on.p + (int64_t)k * K;
+        // the sum of every problem's layer-k column into zc
+        auto layer_vec = [&](int32_t k) -> int {
             MM_HIP(hipMemsetAsync(zc.p, 0, nv * 8, st));
-            hipLaunchKernelGGL(k_cols_to_vec, dim3(16, nl), dim3(256), 0, st, lcols.p + lo, dub.p,
-                               due.p, crow.p, cval.p, (int)ns, zc.p);
+            hipLaunchKernelGGL(k_cols_to_vec, dim3(16, lcnt[k]), dim3(256), 0, st, lcols.p + lo,
+                               dub.p, due.p, crow.p, cval.p, (int)ns, zc.p);
             MM_HIP(hipGetLastError());
-            if (mixed) {
-                MM_TRY(apply_A32_sparse(pl, zc.p, tmp.p, on_k));
-                hipLaunchKernelGGL(k_store_az<float>, dim3(sgx, nl), dim3(256), 0, st, lprob.p + lo,
-                                   (const double*)tmp.p, pl->ooff.p, (int)ns,
-                                   (const int64_t*)d_azd_off.p, k, azf.p);
-            } else {
-                MM_TRY(apply_A64_sparse(pl, zc.p, tmp.p, on_k));
+            return MM_OK;
+        };
+        if (mixed) {
+            // two layers per P^T pass: their N^-1 P outputs interleaved, one gather for both
+            for (int32_t k0 = 0; k0 < rd_max; k0 += 2) {
+                const int nc = std::min<int32_t>(2, rd_max - k0);
+                for (int c = 0; c < nc; ++c) {
+                    const int32_t k = k0 + c;
+                    MM_TRY(layer_vec(k));
+                    MM_TRY(pack_map32(pl, zc.p));
+                    MM_TRY(toeplitz_map32(pl, zc.p, tod2.p + c, nullptr, true,
+                                          on.p + (int64_t)k * K, 2));
+                    lo += lcnt[k];
+                }
+                MM_TRY(scatter_pair32(pl, tod2.p, k0, d_rb.p, d_azd_off.p, azf.p));
+            }
+        } else {
+            for (int32_t k = 0; k < rd_max; ++k) {
+                const int nl = lcnt[k];
+                MM_TRY(layer_vec(k));
+                MM_TRY(apply_A64_sparse(pl, zc.p, tmp.p, on.p + (int64_t)k * K));
                 hipLaunchKernelGGL(k_store_az<double>, dim3(sgx, nl), dim3(256), 0, st, lprob.p + lo,
                                    (const double*)tmp.p, pl->ooff.p, (int)ns,
                                    (const int64_t*)d_azd_off.p, k, azd.p);
+                MM_HIP(hipGetLastError());
+                lo += nl;
             }
-            MM_HIP(hipGetLastError());
-            lo += nl;
         }
     }
     zc.release();
     tmp.release();
+    tod2.release();
     on.release();
     tick("AZ");
     // per problem: E_b = Z_b^T (AZ)_b on the matrix cores, independent subset, E_b^-1

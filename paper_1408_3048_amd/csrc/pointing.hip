@@ -250,6 +250,113 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ per
     seg_reduce<T, NS, E>(i0, i1, p0, heads, load, emit);
 }
 
+// P^T of two FP32 time streams stored interleaved (z2[t] = streams 0 and 1 at sample t),
+// the A Z columns of the coarse space two layers at a time: one 8-byte gather per sample
+// serves both, the loads and the segmented reduction are those of k_scatter (the same
+// additions in the same order for each stream), and the pixel sums go to columns k0 and
+// k0 + 1 of the pixel's problem block in az (where the problem has them).
+template <int NS, int E>
+__global__ __launch_bounds__(256) void k_scatter_pair(
+    const int32_t* __restrict__ perm, const float* __restrict__ ws,
+    const float2* __restrict__ z2, const unsigned long long* __restrict__ heads,
+    const int32_t* __restrict__ wave_pix, const int64_t* __restrict__ seg,
+    const int32_t* __restrict__ hits, int64_t n_waves, const int32_t* __restrict__ wave_prob,
+    const int64_t* __restrict__ ooff, const int32_t* __restrict__ ncols,
+    const int64_t* __restrict__ blk_off, int k0, float* __restrict__ az) {
+    static_assert(E % 4 == 0, "E must be a multiple of 4");
+    constexpr int NV = 2 * NS;
+    __shared__ __align__(16) float2 zx[4][64 * E];
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= n_waves) return;
+    const int b = wave_prob[w];
+    const int ncb = ncols[b] - k0 < 2 ? ncols[b] - k0 : 2;  // columns this problem has
+    if (ncb <= 0) return;
+    const int32_t p0 = wave_pix[w], p1 = wave_pix[w + 1];
+    if (p0 >= p1) return;
+    const int64_t q0 = ooff[b], n_vec = (ooff[b + 1] - q0) * NS;
+    const int64_t i0 = seg[p0];
+    const int64_t i1 = seg[p1 - 1] + hits[p1 - 1];
+    const int lane = threadIdx.x & 63;
+    float2* zw = zx[threadIdx.x >> 6];
+    int32_t pf[E];
+    auto fetch = [&](int64_t c) {
+#pragma unroll
+        for (int g = 0; g < E; ++g) {
+            const int64_t i = c + lane + 64 * g;
+            const bool in = i >= i0 && i < i1;
+            const int32_t t = perm[in ? i : i0];
+            pf[g] = in ? t : -1;
+        }
+    };
+    fetch(i0 & ~(int64_t)(E - 1));
+    auto load = [&](int64_t base, const bool* valid, float (*v)[NV]) {
+        float wv[2 * E];
+        if constexpr (NS == 3) {
+            if (base < i1) {
+#pragma unroll
+                for (int g = 0; g < E / 2; ++g) {
+                    const float4 a = *reinterpret_cast<const float4*>(ws + 2 * base + 4 * g);
+                    wv[4 * g] = a.x;
+                    wv[4 * g + 1] = a.y;
+                    wv[4 * g + 2] = a.z;
+                    wv[4 * g + 3] = a.w;
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < 2 * E; ++e) wv[e] = 0.0f;
+            }
+        }
+        const int64_t c = base - (int64_t)E * lane;
+        int32_t tc[E];
+#pragma unroll
+        for (int g = 0; g < E; ++g) tc[g] = pf[g];
+        fetch(c + 64 * E);
+        float2 zg[E];
+#pragma unroll
+        for (int g = 0; g < E; ++g) zg[g] = z2[tc[g] >= 0 ? tc[g] : 0];
+#pragma unroll
+        for (int g = 0; g < E; ++g) zw[lane + 64 * g] = tc[g] >= 0 ? zg[g] : make_float2(0.0f, 0.0f);
+        wave_lds_sync();
+        float2 zz[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) zz[e] = zw[E * lane + e];
+        wave_lds_sync();
+        if (base >= i1) {
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+#pragma unroll
+                for (int q = 0; q < NV; ++q) v[e][q] = 0.0f;
+            return;
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) zz[e] = valid[e] ? zz[e] : make_float2(0.0f, 0.0f);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if constexpr (NS == 3) {
+                v[e][0] = zz[e].x;
+                v[e][1] = wv[2 * e] * zz[e].x;
+                v[e][2] = wv[2 * e + 1] * zz[e].x;
+                v[e][3] = zz[e].y;
+                v[e][4] = wv[2 * e] * zz[e].y;
+                v[e][5] = wv[2 * e + 1] * zz[e].y;
+            } else {
+                v[e][0] = zz[e].x;
+                v[e][1] = zz[e].y;
+            }
+        }
+    };
+    auto emit = [&](int64_t pix, const float* tot) {
+        float* dst = az + blk_off[b] + (int64_t)k0 * n_vec + (pix - q0) * NS;
+#pragma unroll
+        for (int q = 0; q < NS; ++q) dst[q] = tot[q];
+        if (ncb > 1) {
+#pragma unroll
+            for (int q = 0; q < NS; ++q) dst[n_vec + q] = tot[NS + q];
+        }
+    };
+    seg_reduce<float, NV, E>(i0, i1, p0, heads, load, emit);
+}
+
 // y_t = sum_s W[t, s] x[c(t), s]
 template <typename TO>
 __global__ void k_depoint(const int32_t* __restrict__ cid, const double* __restrict__ w,
@@ -434,6 +541,26 @@ int scatter_t(mm_plan_t pl, const T* z, const T* ws, double* x, const int* mask)
 }
 
 }  // namespace
+
+int scatter_pair32(mm_plan_t pl, const float* z2, int k0, const int32_t* ncols,
+                   const int64_t* blk_off, float* az) {
+    const int64_t nb = (pl->n_waves + 3) / 4;
+    if (nb == 0) return MM_OK;
+    constexpr int E = 4;  // the lane layout of scatter32: the same additions
+    const float2* zp = reinterpret_cast<const float2*>(z2);
+    if (pl->n_s == 3)
+        hipLaunchKernelGGL((k_scatter_pair<3, E>), dim3(nb), dim3(256), 0, pl->stream, pl->perm.p,
+                           pl->ws32.p, zp, (const unsigned long long*)pl->heads.p, pl->wave_pix.p,
+                           pl->seg.p, pl->hits.p, pl->n_waves, pl->wave_prob.p, pl->ooff.p, ncols,
+                           blk_off, k0, az);
+    else
+        hipLaunchKernelGGL((k_scatter_pair<1, E>), dim3(nb), dim3(256), 0, pl->stream, pl->perm.p,
+                           pl->ws32.p, zp, (const unsigned long long*)pl->heads.p, pl->wave_pix.p,
+                           pl->seg.p, pl->hits.p, pl->n_waves, pl->wave_prob.p, pl->ooff.p, ncols,
+                           blk_off, k0, az);
+    MM_HIP(hipGetLastError());
+    return MM_OK;
+}
 
 int scatter64(mm_plan_t pl, const double* z, double* x, const int* mask) {
     return scatter_t<double>(pl, z, pl->ws64.p, x, mask);
