@@ -1121,7 +1121,7 @@ int build_coarse(mm_plan_t pl) {
     DBuf<double> zc, tmp;
     MM_TRY(zc.alloc(nv));
     if (!mixed) MM_TRY(tmp.alloc(nv));
-    DBuf<float> tod2;  // mixed: the time streams of two layers, interleaved
+    DBuf<float> tod2;  // mixed: the time streams of two layers
     if (mixed) MM_TRY(tod2.alloc((size_t)2 * pl->n_t));
     DBuf<int32_t> lcols, lprob;
     MM_TRY(lcols.alloc((size_t)rd_max * B));
@@ -1151,18 +1151,19 @@ int build_coarse(mm_plan_t pl) {
             return MM_OK;
         };
         if (mixed) {
-            // two layers per P^T pass: their N^-1 P outputs interleaved, one gather for both
+            // two layers per P^T pass
             for (int32_t k0 = 0; k0 < rd_max; k0 += 2) {
                 const int nc = std::min<int32_t>(2, rd_max - k0);
                 for (int c = 0; c < nc; ++c) {
                     const int32_t k = k0 + c;
                     MM_TRY(layer_vec(k));
                     MM_TRY(pack_map32(pl, zc.p));
-                    MM_TRY(toeplitz_map32(pl, zc.p, tod2.p + c, nullptr, true,
-                                          on.p + (int64_t)k * K, 2));
+                    MM_TRY(toeplitz_map32(pl, zc.p, tod2.p + c * pl->n_t, nullptr, true,
+                                          on.p + (int64_t)k * K));
                     lo += lcnt[k];
                 }
-                MM_TRY(scatter_pair32(pl, tod2.p, k0, d_rb.p, d_azd_off.p, azf.p));
+                MM_TRY(scatter_pair32(pl, tod2.p, tod2.p + pl->n_t, k0, d_rb.p, d_azd_off.p,
+                                      azf.p));
             }
         } else {
             for (int32_t k = 0; k < rd_max; ++k) {

@@ -329,26 +329,24 @@ int adjoint_tod(mm_plan_t pl, const double* m_hat, const double* mu, const void*
 // map-mode N^-1 P x; mask: per-problem flags (nullptr = all problems); the IQU map must
 // have been packed by pack_map64/32 first.  skip_zero: tiles whose input window is all
 // zero write zeros without a transform; int_on (with skip_zero, optional): per-interval
-// flags, 0 where P x is known to vanish on the whole interval (no load either); zstride
-// (with skip_zero): sample t's output goes to z[t zstride]
+// flags, 0 where P x is known to vanish on the whole interval (no load either)
 int pack_map64(mm_plan_t pl, const double* x);
 int pack_map32(mm_plan_t pl, const double* x);
 int toeplitz_map64(mm_plan_t pl, const double* x, double* z, const int* mask,
-                   bool skip_zero = false, const uint8_t* int_on = nullptr, int zstride = 1);
+                   bool skip_zero = false, const uint8_t* int_on = nullptr);
 int toeplitz_map32(mm_plan_t pl, const double* x, float* z, const int* mask,
-                   bool skip_zero = false, const uint8_t* int_on = nullptr, int zstride = 1);
+                   bool skip_zero = false, const uint8_t* int_on = nullptr);
 int toeplitz_tod64(mm_plan_t pl, const void* y, int y_f64, double* z);
 int toeplitz_tod32(mm_plan_t pl, const void* y, int y_f64, float* z);
 
 // ---- pointing.hip
 int scatter64(mm_plan_t pl, const double* z, double* x, const int* mask);
 int scatter32(mm_plan_t pl, const float* z, double* x, const int* mask);
-// P^T of two FP32 time streams stored interleaved (z2[2 t + c], c = 0, 1) into columns
-// k0 + c of the per-problem FP32 blocks of az (block b at blk_off[b], column-major
-// [ncols[b]][n_vec_b]); columns at or past ncols[b] are not written.  Each stream's sums are
-// those of scatter32.
-int scatter_pair32(mm_plan_t pl, const float* z2, int k0, const int32_t* ncols,
-                   const int64_t* blk_off, float* az);
+// P^T of two FP32 time streams z0, z1 into columns k0, k0 + 1 of the per-problem FP32
+// blocks of az (block b at blk_off[b], column-major [ncols[b]][n_vec_b]); columns at or
+// past ncols[b] are not written.  Each stream's sums are those of scatter32.
+int scatter_pair32(mm_plan_t pl, const float* z0, const float* z1, int k0,
+                   const int32_t* ncols, const int64_t* blk_off, float* az);
 int depoint(mm_plan_t pl, const double* x, void* y, int y_f64);
 int build_bj(mm_plan_t pl);
 int bj_apply(mm_plan_t pl, const double* r, double* z, const PcgCtl& ctl);

@@ -250,15 +250,16 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ per
     seg_reduce<T, NS, E>(i0, i1, p0, heads, load, emit);
 }
 
-// P^T of two FP32 time streams stored interleaved (z2[t] = streams 0 and 1 at sample t),
-// the A Z columns of the coarse space two layers at a time: one 8-byte gather per sample
-// serves both, the loads and the segmented reduction are those of k_scatter (the same
-// additions in the same order for each stream), and the pixel sums go to columns k0 and
-// k0 + 1 of the pixel's problem block in az (where the problem has them).
+// P^T of two FP32 time streams z0, z1, the A Z columns of the coarse space two layers at a
+// time: the sorted indices, weights and segment heads of a chunk are loaded once for both,
+// the two gathers of a sample are issued together, the segmented reduction is that of
+// k_scatter (the same additions in the same order for each stream), and the pixel sums go
+// to columns k0 and k0 + 1 of the pixel's problem block in az (where the problem has them).
 template <int NS, int E>
 __global__ __launch_bounds__(256) void k_scatter_pair(
     const int32_t* __restrict__ perm, const float* __restrict__ ws,
-    const float2* __restrict__ z2, const unsigned long long* __restrict__ heads,
+    const float* __restrict__ z0, const float* __restrict__ z1,
+    const unsigned long long* __restrict__ heads,
     const int32_t* __restrict__ wave_pix, const int64_t* __restrict__ seg,
     const int32_t* __restrict__ hits, int64_t n_waves, const int32_t* __restrict__ wave_prob,
     const int64_t* __restrict__ ooff, const int32_t* __restrict__ ncols,
@@ -313,7 +314,10 @@ __global__ __launch_bounds__(256) void k_scatter_pair(
         fetch(c + 64 * E);
         float2 zg[E];
 #pragma unroll
-        for (int g = 0; g < E; ++g) zg[g] = z2[tc[g] >= 0 ? tc[g] : 0];
+        for (int g = 0; g < E; ++g) {
+            const int32_t t = tc[g] >= 0 ? tc[g] : 0;
+            zg[g] = make_float2(z0[t], z1[t]);
+        }
 #pragma unroll
         for (int g = 0; g < E; ++g) zw[lane + 64 * g] = tc[g] >= 0 ? zg[g] : make_float2(0.0f, 0.0f);
         wave_lds_sync();
@@ -542,20 +546,19 @@ int scatter_t(mm_plan_t pl, const T* z, const T* ws, double* x, const int* mask)
 
 }  // namespace
 
-int scatter_pair32(mm_plan_t pl, const float* z2, int k0, const int32_t* ncols,
-                   const int64_t* blk_off, float* az) {
+int scatter_pair32(mm_plan_t pl, const float* z0, const float* z1, int k0,
+                   const int32_t* ncols, const int64_t* blk_off, float* az) {
     const int64_t nb = (pl->n_waves + 3) / 4;
     if (nb == 0) return MM_OK;
     constexpr int E = 4;  // the lane layout of scatter32: the same additions
-    const float2* zp = reinterpret_cast<const float2*>(z2);
     if (pl->n_s == 3)
         hipLaunchKernelGGL((k_scatter_pair<3, E>), dim3(nb), dim3(256), 0, pl->stream, pl->perm.p,
-                           pl->ws32.p, zp, (const unsigned long long*)pl->heads.p, pl->wave_pix.p,
+                           pl->ws32.p, z0, z1, (const unsigned long long*)pl->heads.p, pl->wave_pix.p,
                            pl->seg.p, pl->hits.p, pl->n_waves, pl->wave_prob.p, pl->ooff.p, ncols,
                            blk_off, k0, az);
     else
         hipLaunchKernelGGL((k_scatter_pair<1, E>), dim3(nb), dim3(256), 0, pl->stream, pl->perm.p,
-                           pl->ws32.p, zp, (const unsigned long long*)pl->heads.p, pl->wave_pix.p,
+                           pl->ws32.p, z0, z1, (const unsigned long long*)pl->heads.p, pl->wave_pix.p,
                            pl->seg.p, pl->hits.p, pl->n_waves, pl->wave_prob.p, pl->ooff.p, ncols,
                            blk_off, k0, az);
     MM_HIP(hipGetLastError());

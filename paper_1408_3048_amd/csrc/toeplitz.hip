@@ -193,7 +193,6 @@ struct ToepArgs {
     int skip_zero;            // map modes: all-zero windows skip the transform
     const uint8_t* int_on;    // zero-skipping launches: intervals flagged 0 have an all-zero
                               // input (known beforehand) and write zeros without loading it
-    int zstride;              // zero-skipping launches: output of sample t at z[t zstride]
 };
 
 // LDS layout of the complex work array (M points).  Element a lives at
@@ -777,14 +776,14 @@ __global__ __launch_bounds__(NT, (tile_waves_per_simd<T, LOGM, NT>())) void k_to
     const int lam = a.lam;
     if constexpr (SKIPZ) {
         if (a.int_on && !a.int_on[j]) {
-            for (int i = threadIdx.x; i < L; i += NT) a.z[(o + i) * a.zstride] = (T)0;
+            for (int i = threadIdx.x; i < L; i += NT) a.z[o + i] = (T)0;
             return;
         }
     }
     const bool nz = load_window<T, LOGM, NT, MODE>(a, buf, o - lam, L + 2 * lam, lo, hi);
     if constexpr (SKIPZ) {
         if (!__syncthreads_or(nz)) {  // zero window: the exact result is zero
-            for (int i = threadIdx.x; i < L; i += NT) a.z[(o + i) * a.zstride] = (T)0;
+            for (int i = threadIdx.x; i < L; i += NT) a.z[o + i] = (T)0;
             return;
         }
     } else {
@@ -800,15 +799,9 @@ __global__ __launch_bounds__(NT, (tile_waves_per_simd<T, LOGM, NT>())) void k_to
         spectrum_pass<T, LOGM, NT>(buf, a.H + (int64_t)a.int_kern[j] * (M + 1), a.tw);
         inv_passes<T, LOGM, NT, LOGM>(buf, a.tw);
     }
-    if constexpr (SKIPZ) {
-        T* zo = a.z + o * a.zstride;
-        for (int i = lam + threadIdx.x; i < lam + L; i += NT)
-            zo[(uint32_t)(i - lam) * (uint32_t)a.zstride] = buf.get_part(i >> 1, i & 1);
-    } else {
-        T* zo = a.z + o;  // block-uniform base, 32-bit offsets
-        for (int i = lam + threadIdx.x; i < lam + L; i += NT)
-            zo[(uint32_t)(i - lam)] = buf.get_part(i >> 1, i & 1);
-    }
+    T* zo = a.z + o;  // block-uniform base, 32-bit offsets
+    for (int i = lam + threadIdx.x; i < lam + L; i += NT)
+        zo[(uint32_t)(i - lam)] = buf.get_part(i >> 1, i & 1);
 }
 
 // ------------------------------------------------------------------ plan-time FFTs (FP64)
@@ -991,7 +984,6 @@ int pack_map(mm_plan_t pl, const double* x, T* xp) {
 template <typename T>
 ToepArgs<T> base_args(mm_plan_t pl, const FftTiling& ft) {
     ToepArgs<T> a{};
-    a.zstride = 1;
     a.cid = pl->cid.p;
     a.tile_out = ft.tile_out.p;
     a.tile_len = ft.tile_len.p;
@@ -1400,15 +1392,10 @@ int pack_map32(mm_plan_t pl, const double* x) {
 }
 
 int toeplitz_map64(mm_plan_t pl, const double* x, double* z, const int* mask, bool skip_zero,
-                   const uint8_t* int_on, int zstride) {
-    if (zstride < 1 || (zstride > 1 && !skip_zero)) {
-        set_error("toeplitz_map: output stride %d needs a zero-skipping launch", zstride);
-        return MM_ERR_ARG;
-    }
+                   const uint8_t* int_on) {
     auto a = base_args<double>(pl, pl->fft64);
     a.skip_zero = skip_zero;
     a.int_on = skip_zero ? int_on : nullptr;
-    a.zstride = zstride;
     a.x = x;
     if (pl->n_s == 3) a.xp = pl->xp64.p;
     a.mode = pl->n_s == 3 ? 0 : 1;
@@ -1418,15 +1405,10 @@ int toeplitz_map64(mm_plan_t pl, const double* x, double* z, const int* mask, bo
 }
 
 int toeplitz_map32(mm_plan_t pl, const double* x, float* z, const int* mask, bool skip_zero,
-                   const uint8_t* int_on, int zstride) {
-    if (zstride < 1 || (zstride > 1 && !skip_zero)) {
-        set_error("toeplitz_map: output stride %d needs a zero-skipping launch", zstride);
-        return MM_ERR_ARG;
-    }
+                   const uint8_t* int_on) {
     auto a = base_args<float>(pl, pl->fft32);
     a.skip_zero = skip_zero;
     a.int_on = skip_zero ? int_on : nullptr;
-    a.zstride = zstride;
     a.x = x;
     if (pl->n_s == 3) a.xp = pl->xp32.p;
     a.mode = pl->n_s == 3 ? 0 : 1;
