@@ -63,13 +63,13 @@ def fft_tile_flops(offsets, lam, n_r):
 TRAFFIC = {
     # per FP32 tile length n_r (the plan's autotuner picks 8192 or 16384 on this workload)
     "ninv32": dict(source="paper_1408_3048_amd/csrc/toeplitz.hip",
-                   sha256="08bdd3df6287745a495fb7c84fd5408c1a148207ca60526708227809226a62b1",
-                   by_n_r={8192: dict(fetch_kib=294600.125, write_kib=65536.0),
-                           16384: dict(fetch_kib=203174.0625, write_kib=65579.09375)},
+                   sha256="b9e30649704484fbfba74bf514b9ded3d85fdf0510da3f446a815bd69b0a5cd4",
+                   by_n_r={8192: dict(fetch_kib=289322.8125, write_kib=65536.0),
+                           16384: dict(fetch_kib=201825.6875, write_kib=65577.75)},
                    fetch_factor=2.0, write_factor=1.0),
     "pt32": dict(source="paper_1408_3048_amd/csrc/pointing.hip",
-                 sha256="f4d605beb107d3e922686a78c75d6a3ccbf74dfe33179f9f6c52a5a4fe84c266",
-                 by_n_r={None: dict(fetch_kib=152897.0, write_kib=6764.78125)},
+                 sha256="2b1744f07693d585aecec123ad0204a71981294b8b460cfae4865d0621057753",
+                 by_n_r={None: dict(fetch_kib=153762.375, write_kib=7791.65625)},
                  fetch_factor=2.0, write_factor=1.0),
 }
 
