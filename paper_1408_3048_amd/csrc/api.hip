@@ -401,7 +401,8 @@ int pcg_engine(mm_plan_t pl, const double* b, double* x, const EngineArgs& ea) {
         for (int i = 0; i < B; ++i) k += pl->h_sc[i].state == state;
         return k;
     };
-    // graph of one iteration for this operator / preconditioner and control arguments
+    // graph of one chunk of kChunk iterations for this operator / preconditioner and control
+    // arguments (one launch per chunk: the gaps between graph launches are paid once)
     const bool use_graph = pl->opts.graph != 0 && !pl->prof_on && pl->gstream != nullptr &&
                            pl->stream == pl->gstream;
     const int gi = ea.op32 ? 1 : 0, gj = ea.pc;
@@ -416,7 +417,9 @@ int pcg_engine(mm_plan_t pl, const double* b, double* x, const EngineArgs& ea) {
     if (use_graph && !gx) {
         hipGraph_t g = nullptr;
         MM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        const int s1 = full_iteration(pl, ea, xw, r, z, p, q, -1);
+        int s1 = MM_OK;
+        for (int c = 0; c < kChunk && s1 == MM_OK; ++c)
+            s1 = full_iteration(pl, ea, xw, r, z, p, q, -1);
         const hipError_t e1 = hipStreamEndCapture(st, &g);
         if (s1 != MM_OK) {
             if (g) (void)hipGraphDestroy(g);
@@ -443,9 +446,12 @@ int pcg_engine(mm_plan_t pl, const double* b, double* x, const EngineArgs& ea) {
         for (int k = 0; k < MM_K_COUNT; ++k) mark[k] = pl->prof_used[k];
         const int it0 = B == 1 ? pl->h_sc[0].iter : 0;
         const int chunk_start = host_it;
-        for (int c = 0; c < kChunk; ++c, ++host_it) {
-            if (graph_ok) MM_HIP(hipGraphLaunch(gx, st));
-            else MM_TRY(full_iteration(pl, ea, xw, r, z, p, q, host_it));
+        if (graph_ok) {
+            MM_HIP(hipGraphLaunch(gx, st));
+            host_it += kChunk;
+        } else {
+            for (int c = 0; c < kChunk; ++c, ++host_it)
+                MM_TRY(full_iteration(pl, ea, xw, r, z, p, q, host_it));
         }
         MM_TRY(read_scalars(pl));
         if (B == 1) prof_invalidate(pl, mark, chunk_start + (pl->h_sc[0].iter - it0));
