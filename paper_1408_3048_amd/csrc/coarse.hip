@@ -211,6 +211,17 @@ __global__ void k_az_int_flags(const int64_t* __restrict__ ptr, const int32_t* _
     }
 }
 
+// the I entries of the columns ucol[0..gridDim.y) into a zeroed packed FP32 map
+// ([n_obs][4] = (I, Q, U, 0)): the values the packing of the expanded vector would give
+__global__ void k_cols_to_packed(const int32_t* __restrict__ ucol, const int64_t* __restrict__ ub,
+                                 const int64_t* __restrict__ ue, const int32_t* __restrict__ rows,
+                                 const double* __restrict__ vals, float* __restrict__ xp) {
+    const int32_t u = ucol[blockIdx.y];
+    for (int64_t i = ub[u] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ue[u];
+         i += (int64_t)gridDim.x * blockDim.x)
+        xp[4 * (int64_t)rows[i]] = (float)vals[i];
+}
+
 // copy problem lp[y]'s slice of the map vector y into column `col` of its AZ block
 template <typename TA>
 __global__ void k_store_az(const int32_t* __restrict__ lp, const double* __restrict__ y,
@@ -1119,10 +1130,11 @@ int build_coarse(mm_plan_t pl) {
     MM_TRY(d_rb.alloc(B));
     MM_HIP(hipMemcpyAsync(d_rb.p, h_rb.data(), B * 4, hipMemcpyHostToDevice, st));
     DBuf<double> zc, tmp;
-    MM_TRY(zc.alloc(nv));
+    MM_TRY(zc.alloc(mixed ? 2 * nv : nv));  // mixed: the maps of two layers (I only)
     if (!mixed) MM_TRY(tmp.alloc(nv));
-    DBuf<float> tod2;  // mixed: the time streams of two layers
+    DBuf<float> tod2, xp2;  // mixed: the time streams and packed maps (IQU) of two layers
     if (mixed) MM_TRY(tod2.alloc((size_t)2 * pl->n_t));
+    if (mixed && ns == 3) MM_TRY(xp2.alloc((size_t)2 * 4 * n_obs));
     DBuf<int32_t> lcols, lprob;
     MM_TRY(lcols.alloc((size_t)rd_max * B));
     MM_TRY(lprob.alloc((size_t)rd_max * B));
@@ -1151,17 +1163,33 @@ int build_coarse(mm_plan_t pl) {
             return MM_OK;
         };
         if (mixed) {
-            // two layers per P^T pass
+            // two layers per pass: their maps (packed FP32 for IQU, FP64 for I only) side by
+            // side, one N^-1 P launch over both, one P^T pass over both
             for (int32_t k0 = 0; k0 < rd_max; k0 += 2) {
                 const int nc = std::min<int32_t>(2, rd_max - k0);
+                if (ns == 3)
+                    MM_HIP(hipMemsetAsync(xp2.p, 0, (size_t)nc * 4 * n_obs * sizeof(float), st));
+                else
+                    MM_HIP(hipMemsetAsync(zc.p, 0, (size_t)nc * nv * 8, st));
                 for (int c = 0; c < nc; ++c) {
                     const int32_t k = k0 + c;
-                    MM_TRY(layer_vec(k));
-                    MM_TRY(pack_map32(pl, zc.p));
-                    MM_TRY(toeplitz_map32(pl, zc.p, tod2.p + c * pl->n_t, nullptr, true,
-                                          on.p + (int64_t)k * K));
+                    if (ns == 3)
+                        hipLaunchKernelGGL(k_cols_to_packed, dim3(16, lcnt[k]), dim3(256), 0, st,
+                                           lcols.p + lo, dub.p, due.p, crow.p, cval.p,
+                                           xp2.p + (int64_t)c * 4 * n_obs);
+                    else
+                        hipLaunchKernelGGL(k_cols_to_vec, dim3(16, lcnt[k]), dim3(256), 0, st,
+                                           lcols.p + lo, dub.p, due.p, crow.p, cval.p, (int)ns,
+                                           zc.p + (int64_t)c * nv);
+                    MM_HIP(hipGetLastError());
                     lo += lcnt[k];
                 }
+                if (ns == 3)
+                    MM_TRY(toeplitz_map32_layers(pl, nullptr, 0, xp2.p, 4 * n_obs, tod2.p, pl->n_t,
+                                                 on.p + (int64_t)k0 * K, K, nc));
+                else
+                    MM_TRY(toeplitz_map32_layers(pl, zc.p, nv, nullptr, 0, tod2.p, pl->n_t,
+                                                 on.p + (int64_t)k0 * K, K, nc));
                 MM_TRY(scatter_pair32(pl, tod2.p, tod2.p + pl->n_t, k0, d_rb.p, d_azd_off.p,
                                       azf.p));
             }
@@ -1181,6 +1209,7 @@ int build_coarse(mm_plan_t pl) {
     zc.release();
     tmp.release();
     tod2.release();
+    xp2.release();
     on.release();
     tick("AZ");
     // per problem: E_b = Z_b^T (AZ)_b on the matrix cores, independent subset, E_b^-1

@@ -336,6 +336,12 @@ int toeplitz_map64(mm_plan_t pl, const double* x, double* z, const int* mask,
                    bool skip_zero = false, const uint8_t* int_on = nullptr);
 int toeplitz_map32(mm_plan_t pl, const double* x, float* z, const int* mask,
                    bool skip_zero = false, const uint8_t* int_on = nullptr);
+// zero-skipping FP32 N^-1 P of `layers` maps at once (blockIdx.y = layer y): layer y
+// reads the FP64 map x + y x_step (I only) or the packed FP32 map xp + y xp_step (IQU) and
+// the interval flags int_on + y on_step (or none), and writes z + y z_step
+int toeplitz_map32_layers(mm_plan_t pl, const double* x, int64_t x_step, const float* xp,
+                          int64_t xp_step, float* z, int64_t z_step, const uint8_t* int_on,
+                          int64_t on_step, int layers);
 int toeplitz_tod64(mm_plan_t pl, const void* y, int y_f64, double* z);
 int toeplitz_tod32(mm_plan_t pl, const void* y, int y_f64, float* z);
 

@@ -193,6 +193,10 @@ struct ToepArgs {
     int skip_zero;            // map modes: all-zero windows skip the transform
     const uint8_t* int_on;    // zero-skipping launches: intervals flagged 0 have an all-zero
                               // input (known beforehand) and write zeros without loading it
+    // zero-skipping launches over several maps (blockIdx.y = layer y < layers): layer y
+    // reads x + y x_step, xp + y xp_step and int_on + y on_step and writes z + y z_step
+    int layers;
+    int64_t x_step, xp_step, z_step, on_step;
 };
 
 // LDS layout of the complex work array (M points).  Element a lives at
@@ -767,6 +771,15 @@ __global__ __launch_bounds__(NT, (tile_waves_per_simd<T, LOGM, NT>())) void k_to
     constexpr int M = 1 << LOGM;
     __shared__ __align__(16) unsigned char smem[2 * M * sizeof(T)];
     const CBuf<T> buf = make_cbuf<T>(smem, M);
+    if constexpr (SKIPZ) {
+        if (blockIdx.y) {
+            const int64_t y = blockIdx.y;
+            a.x += y * a.x_step;
+            a.xp += y * a.xp_step;
+            a.z += y * a.z_step;
+            if (a.int_on) a.int_on += y * a.on_step;
+        }
+    }
     const int64_t tile = blockIdx.x;
     const int j = a.tile_int[tile];
     if (a.mask && !a.mask[a.int_prob[j]]) return;
@@ -920,10 +933,11 @@ int launch_logm(const ToepArgs<T>& a, int64_t n_tiles, hipStream_t st) {
     constexpr int M = 1 << LOGM;
     constexpr int NT = (M / 16) > 1024 ? 1024 : ((M / 16) < 256 ? 256 : (M / 16));
     if (a.skip_zero) {
+        const dim3 grid((unsigned)n_tiles, a.layers > 1 ? (unsigned)a.layers : 1u);
         if (a.mode == 0)
-            hipLaunchKernelGGL((k_toeplitz<T, LOGM, NT, 0, true>), dim3(n_tiles), dim3(NT), 0, st, a);
+            hipLaunchKernelGGL((k_toeplitz<T, LOGM, NT, 0, true>), grid, dim3(NT), 0, st, a);
         else
-            hipLaunchKernelGGL((k_toeplitz<T, LOGM, NT, 1, true>), dim3(n_tiles), dim3(NT), 0, st, a);
+            hipLaunchKernelGGL((k_toeplitz<T, LOGM, NT, 1, true>), grid, dim3(NT), 0, st, a);
     } else {
         switch (a.mode) {
             case 0: hipLaunchKernelGGL((k_toeplitz<T, LOGM, NT, 0, false>), dim3(n_tiles), dim3(NT), 0, st, a); break;
@@ -1414,6 +1428,28 @@ int toeplitz_map32(mm_plan_t pl, const double* x, float* z, const int* mask, boo
     a.mode = pl->n_s == 3 ? 0 : 1;
     a.z = z;
     a.mask = mask;
+    return launch<float>(a, pl->fft32.logm, pl->fft32.n_tiles, pl->stream);
+}
+
+int toeplitz_map32_layers(mm_plan_t pl, const double* x, int64_t x_step, const float* xp,
+                          int64_t xp_step, float* z, int64_t z_step, const uint8_t* int_on,
+                          int64_t on_step, int layers) {
+    if (layers < 1 || layers > 65535) {
+        set_error("toeplitz_map32_layers: %d layers", layers);
+        return MM_ERR_ARG;
+    }
+    auto a = base_args<float>(pl, pl->fft32);
+    a.skip_zero = 1;
+    a.x = x;
+    a.xp = xp;
+    a.mode = pl->n_s == 3 ? 0 : 1;
+    a.z = z;
+    a.int_on = int_on;
+    a.layers = layers;
+    a.x_step = x_step;
+    a.xp_step = xp_step;
+    a.z_step = z_step;
+    a.on_step = on_step;
     return launch<float>(a, pl->fft32.logm, pl->fft32.n_tiles, pl->stream);
 }
 
