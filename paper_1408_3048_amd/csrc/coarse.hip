@@ -925,6 +925,9 @@ int32_t gram_ksplit(int64_t n, int32_t ra, int32_t rb) {
     return (int32_t)std::max<int64_t>(1, std::min<int64_t>(n / 4 / 64, 4096 / std::max(1, ntile)));
 }
 
+// layers of the A Z columns per zero-skipping N^-1 launch (mixed plans; even)
+constexpr int kAzGroup = 8;
+
 // dense row blocks of the batched Gram products, zd and azr together (bytes)
 constexpr int64_t kGramBudget = (int64_t)1 << 30;
 
@@ -1130,11 +1133,13 @@ int build_coarse(mm_plan_t pl) {
     MM_TRY(d_rb.alloc(B));
     MM_HIP(hipMemcpyAsync(d_rb.p, h_rb.data(), B * 4, hipMemcpyHostToDevice, st));
     DBuf<double> zc, tmp;
-    MM_TRY(zc.alloc(mixed ? 2 * nv : nv));  // mixed: the maps of two layers (I only)
+    MM_TRY(zc.alloc(mixed ? kAzGroup * nv : nv));  // mixed: the maps of a group (I only)
     if (!mixed) MM_TRY(tmp.alloc(nv));
-    DBuf<float> tod2, xp2;  // mixed: the time streams and packed maps (IQU) of two layers
-    if (mixed) MM_TRY(tod2.alloc((size_t)2 * pl->n_t));
-    if (mixed && ns == 3) MM_TRY(xp2.alloc((size_t)2 * 4 * n_obs));
+    // mixed: the time streams and packed maps (IQU) of a group of layers (the pair P^T of
+    // an odd last layer reads a stream it does not write out)
+    DBuf<float> todg, xpg;
+    if (mixed) MM_TRY(todg.alloc((size_t)kAzGroup * pl->n_t));
+    if (mixed && ns == 3) MM_TRY(xpg.alloc((size_t)kAzGroup * 4 * n_obs));
     DBuf<int32_t> lcols, lprob;
     MM_TRY(lcols.alloc((size_t)rd_max * B));
     MM_TRY(lprob.alloc((size_t)rd_max * B));
@@ -1163,12 +1168,12 @@ int build_coarse(mm_plan_t pl) {
             return MM_OK;
         };
         if (mixed) {
-            // two layers per pass: their maps (packed FP32 for IQU, FP64 for I only) side by
-            // side, one N^-1 P launch over both, one P^T pass over both
-            for (int32_t k0 = 0; k0 < rd_max; k0 += 2) {
-                const int nc = std::min<int32_t>(2, rd_max - k0);
+            // kAzGroup layers at a time: their maps (packed FP32 for IQU, FP64 for I only)
+            // side by side, one N^-1 P launch over all of them, P^T two layers per pass
+            for (int32_t k0 = 0; k0 < rd_max; k0 += kAzGroup) {
+                const int nc = std::min<int32_t>(kAzGroup, rd_max - k0);
                 if (ns == 3)
-                    MM_HIP(hipMemsetAsync(xp2.p, 0, (size_t)nc * 4 * n_obs * sizeof(float), st));
+                    MM_HIP(hipMemsetAsync(xpg.p, 0, (size_t)nc * 4 * n_obs * sizeof(float), st));
                 else
                     MM_HIP(hipMemsetAsync(zc.p, 0, (size_t)nc * nv * 8, st));
                 for (int c = 0; c < nc; ++c) {
@@ -1176,7 +1181,7 @@ int build_coarse(mm_plan_t pl) {
                     if (ns == 3)
                         hipLaunchKernelGGL(k_cols_to_packed, dim3(16, lcnt[k]), dim3(256), 0, st,
                                            lcols.p + lo, dub.p, due.p, crow.p, cval.p,
-                                           xp2.p + (int64_t)c * 4 * n_obs);
+                                           xpg.p + (int64_t)c * 4 * n_obs);
                     else
                         hipLaunchKernelGGL(k_cols_to_vec, dim3(16, lcnt[k]), dim3(256), 0, st,
                                            lcols.p + lo, dub.p, due.p, crow.p, cval.p, (int)ns,
@@ -1185,13 +1190,14 @@ int build_coarse(mm_plan_t pl) {
                     lo += lcnt[k];
                 }
                 if (ns == 3)
-                    MM_TRY(toeplitz_map32_layers(pl, nullptr, 0, xp2.p, 4 * n_obs, tod2.p, pl->n_t,
+                    MM_TRY(toeplitz_map32_layers(pl, nullptr, 0, xpg.p, 4 * n_obs, todg.p, pl->n_t,
                                                  on.p + (int64_t)k0 * K, K, nc));
                 else
-                    MM_TRY(toeplitz_map32_layers(pl, zc.p, nv, nullptr, 0, tod2.p, pl->n_t,
+                    MM_TRY(toeplitz_map32_layers(pl, zc.p, nv, nullptr, 0, todg.p, pl->n_t,
                                                  on.p + (int64_t)k0 * K, K, nc));
-                MM_TRY(scatter_pair32(pl, tod2.p, tod2.p + pl->n_t, k0, d_rb.p, d_azd_off.p,
-                                      azf.p));
+                for (int c = 0; c < nc; c += 2)
+                    MM_TRY(scatter_pair32(pl, todg.p + c * pl->n_t, todg.p + (c + 1) * pl->n_t,
+                                          k0 + c, d_rb.p, d_azd_off.p, azf.p));
             }
         } else {
             for (int32_t k = 0; k < rd_max; ++k) {
@@ -1208,8 +1214,8 @@ int build_coarse(mm_plan_t pl) {
     }
     zc.release();
     tmp.release();
-    tod2.release();
-    xp2.release();
+    todg.release();
+    xpg.release();
     on.release();
     tick("AZ");
     // per problem: E_b = Z_b^T (AZ)_b on the matrix cores, independent subset, E_b^-1
