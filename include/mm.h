@@ -224,7 +224,7 @@ typedef struct {
  *              by the true one and the iteration continues).
  *              MM_MIXED: PCG with the FP32 operator (FP64 vectors, scalars and coarse
  *              solve) whose recursive residual is replaced by the FP64 true residual
- *              b - A x each time it has dropped by 1000x since the last replacement and
+ *              b - A x each time it has dropped by 10^4 since the last replacement and
  *              when it reaches tol (the search direction is kept); stops when the true
  *              relative residual is <= tol.
  *              MM_MIXED_IR: classic iterative refinement; each step solves A d = r with

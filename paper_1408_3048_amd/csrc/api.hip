@@ -252,7 +252,7 @@ using clk = std::chrono::steady_clock;
 
 // mixed precision: evaluate the true residual each time the recursive one has dropped
 // by this factor since the last evaluation
-constexpr double kReplaceRatio = 1e-3;
+constexpr double kReplaceRatio = 1e-4;
 // iterations launched between two reads of the problem states
 constexpr int kChunk = 4;
 
