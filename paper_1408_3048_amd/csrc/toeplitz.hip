@@ -649,44 +649,49 @@ __device__ __forceinline__ bool load_window(const ToepArgs<T>& a, const CBuf<T>&
     const int i_lo = (int)(lo > base ? lo - base : 0);
     const int i_hi = (int)(hi - base < (int64_t)win ? hi - base : (int64_t)win);
     bool nz = false;
-    if constexpr (MODE == 0 && sizeof(T) == 4) {
-        // FP32 IQU map gather, software-pipelined: the indices and weights of batch k + 1
-        // are loaded while the map gathers of batch k are in flight, so a batch waits for
-        // one memory latency instead of two (the values are those of the plain loop below)
+    if constexpr (MODE == 0) {
+        // IQU map gather, software-pipelined: the indices and weights of batch k + 1 are
+        // loaded while the map gathers of batch k are in flight, so a batch waits for one
+        // memory latency instead of two (the values are those of the plain loop below);
+        // batches of 8 samples in FP32, 4 in FP64 (registers)
+        typedef typename std::conditional<sizeof(T) == 4, float4, double4>::type T4;
+        typedef typename std::conditional<sizeof(T) == 4, float2, double2>::type T2;
+        constexpr int BP = sizeof(T) == 4 ? (PER < 8 ? PER : 8) : (PER < 4 ? PER : 4);
+        static_assert(PER % BP == 0, "tile must split into batches");
         const int32_t* cb = a.cid + base;
-        const float2* wb = reinterpret_cast<const float2*>(a.w) + base;
+        const T2* wb = reinterpret_cast<const T2*>(a.w) + base;
         const char* xpb = reinterpret_cast<const char*>(a.xp);
         auto pos = [&](int k) -> uint32_t {
             const int i = threadIdx.x + k * NT;
             return (uint32_t)(i >= i_lo && i < i_hi ? i : i_lo);
         };
-        uint32_t cc[B];
-        float2 ww[B];
+        uint32_t cc[BP];
+        T2 ww[BP];
 #pragma unroll
-        for (int u = 0; u < B; ++u) {
+        for (int u = 0; u < BP; ++u) {
             const uint32_t r = pos(u);
             cc[u] = (uint32_t)cb[r];
             ww[u] = wb[r];
         }
 #pragma unroll
-        for (int b0 = 0; b0 < PER; b0 += B) {
-            float4 xx[B];
+        for (int b0 = 0; b0 < PER; b0 += BP) {
+            T4 xx[BP];
 #pragma unroll
-            for (int u = 0; u < B; ++u)
-                xx[u] = *reinterpret_cast<const float4*>(xpb + cc[u] * (uint32_t)sizeof(float4));
-            float2 wcur[B];
+            for (int u = 0; u < BP; ++u)
+                xx[u] = *reinterpret_cast<const T4*>(xpb + cc[u] * (uint32_t)sizeof(T4));
+            T2 wcur[BP];
 #pragma unroll
-            for (int u = 0; u < B; ++u) wcur[u] = ww[u];
-            if (b0 + B < PER) {
+            for (int u = 0; u < BP; ++u) wcur[u] = ww[u];
+            if (b0 + BP < PER) {
 #pragma unroll
-                for (int u = 0; u < B; ++u) {
-                    const uint32_t r = pos(b0 + B + u);
+                for (int u = 0; u < BP; ++u) {
+                    const uint32_t r = pos(b0 + BP + u);
                     cc[u] = (uint32_t)cb[r];
                     ww[u] = wb[r];
                 }
             }
 #pragma unroll
-            for (int u = 0; u < B; ++u) {
+            for (int u = 0; u < BP; ++u) {
                 const int i = threadIdx.x + (b0 + u) * NT;
                 const bool ok = i >= i_lo && i < i_hi;
                 const T v = ok ? xx[u].x + wcur[u].x * xx[u].y + wcur[u].y * xx[u].z : (T)0;
