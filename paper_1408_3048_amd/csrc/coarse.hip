@@ -1135,8 +1135,7 @@ int build_coarse(mm_plan_t pl) {
     DBuf<double> zc, tmp;
     MM_TRY(zc.alloc(mixed ? kAzGroup * nv : nv));  // mixed: the maps of a group (I only)
     if (!mixed) MM_TRY(tmp.alloc(nv));
-    // mixed: the time streams and packed maps (IQU) of a group of layers (the pair P^T of
-    // an odd last layer reads a stream it does not write out)
+    // mixed: the time streams and packed maps (IQU) of a group of layers
     DBuf<float> todg, xpg;
     if (mixed) MM_TRY(todg.alloc((size_t)kAzGroup * pl->n_t));
     if (mixed && ns == 3) MM_TRY(xpg.alloc((size_t)kAzGroup * 4 * n_obs));
@@ -1169,7 +1168,7 @@ int build_coarse(mm_plan_t pl) {
         };
         if (mixed) {
             // kAzGroup layers at a time: their maps (packed FP32 for IQU, FP64 for I only)
-            // side by side, one N^-1 P launch over all of them, P^T two layers per pass
+            // side by side, one N^-1 P launch over all of them, P^T kScatterCols per pass
             for (int32_t k0 = 0; k0 < rd_max; k0 += kAzGroup) {
                 const int nc = std::min<int32_t>(kAzGroup, rd_max - k0);
                 if (ns == 3)
@@ -1195,9 +1194,10 @@ int build_coarse(mm_plan_t pl) {
                 else
                     MM_TRY(toeplitz_map32_layers(pl, zc.p, nv, nullptr, 0, todg.p, pl->n_t,
                                                  on.p + (int64_t)k0 * K, K, nc));
-                for (int c = 0; c < nc; c += 2)
-                    MM_TRY(scatter_pair32(pl, todg.p + c * pl->n_t, todg.p + (c + 1) * pl->n_t,
-                                          k0 + c, d_rb.p, d_azd_off.p, azf.p));
+                for (int c = 0; c < nc; c += kScatterCols)
+                    MM_TRY(scatter_cols32(pl, todg.p + c * pl->n_t, pl->n_t,
+                                          std::min(kScatterCols, nc - c), k0 + c, d_rb.p,
+                                          d_azd_off.p, azf.p));
             }
         } else {
             for (int32_t k = 0; k < rd_max; ++k) {

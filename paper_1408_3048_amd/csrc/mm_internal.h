@@ -348,10 +348,11 @@ int toeplitz_tod32(mm_plan_t pl, const void* y, int y_f64, float* z);
 // ---- pointing.hip
 int scatter64(mm_plan_t pl, const double* z, double* x, const int* mask);
 int scatter32(mm_plan_t pl, const float* z, double* x, const int* mask);
-// P^T of two FP32 time streams z0, z1 into columns k0, k0 + 1 of the per-problem FP32
-// blocks of az (block b at blk_off[b], column-major [ncols[b]][n_vec_b]); columns at or
-// past ncols[b] are not written.  Each stream's sums are those of scatter32.
-int scatter_pair32(mm_plan_t pl, const float* z0, const float* z1, int k0,
+// P^T of nc <= kScatterCols FP32 time streams z + k zstride into columns k0 + k of the
+// per-problem FP32 blocks of az (block b at blk_off[b], column-major [ncols[b]][n_vec_b]);
+// columns at or past ncols[b] are not written.  Each stream's sums are those of scatter32.
+constexpr int kScatterCols = 4;
+int scatter_cols32(mm_plan_t pl, const float* z, int64_t zstride, int nc, int k0,
                    const int32_t* ncols, const int64_t* blk_off, float* az);
 int depoint(mm_plan_t pl, const double* x, void* y, int y_f64);
 int build_bj(mm_plan_t pl);

@@ -250,35 +250,37 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ per
     seg_reduce<T, NS, E>(i0, i1, p0, heads, load, emit);
 }
 
-// P^T of two FP32 time streams z0, z1, the A Z columns of the coarse space two layers at a
-// time: the sorted indices, weights and segment heads of a chunk are loaded once for both,
-// the two gathers of a sample are issued together, the segmented reduction is that of
-// k_scatter (the same additions in the same order for each stream), and the pixel sums go
-// to columns k0 and k0 + 1 of the pixel's problem block in az (where the problem has them).
-template <int NS, int E>
-__global__ __launch_bounds__(256) void k_scatter_pair(
-    const int32_t* __restrict__ perm, const float* __restrict__ ws,
-    const float* __restrict__ z0, const float* __restrict__ z1,
-    const unsigned long long* __restrict__ heads,
+// P^T of NC FP32 time streams z + k zstride (k < NC), the A Z columns of the coarse space
+// several layers at a time: the sorted indices, weights and segment heads of a chunk are
+// loaded once for all, the gathers of a sample are issued together, the segmented
+// reduction is that of k_scatter (the same additions in the same order for each stream),
+// and the pixel sums go to columns k0 + k of the pixel's problem block in az (where the
+// problem has them; streams past nc are not read).
+template <int NS, int E, int NC>
+__global__ __launch_bounds__(256) void k_scatter_cols(
+    const int32_t* __restrict__ perm, const float* __restrict__ ws, const float* __restrict__ z,
+    int64_t zstride, int nc, const unsigned long long* __restrict__ heads,
     const int32_t* __restrict__ wave_pix, const int64_t* __restrict__ seg,
     const int32_t* __restrict__ hits, int64_t n_waves, const int32_t* __restrict__ wave_prob,
     const int64_t* __restrict__ ooff, const int32_t* __restrict__ ncols,
     const int64_t* __restrict__ blk_off, int k0, float* __restrict__ az) {
     static_assert(E % 4 == 0, "E must be a multiple of 4");
-    constexpr int NV = 2 * NS;
-    __shared__ __align__(16) float2 zx[4][64 * E];
+    constexpr int NV = NC * NS;
+    __shared__ __align__(16) float zx[4][NC][64 * E];
     const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (w >= n_waves) return;
     const int b = wave_prob[w];
-    const int ncb = ncols[b] - k0 < 2 ? ncols[b] - k0 : 2;  // columns this problem has
+    int ncb = ncols[b] - k0;  // columns this problem has in the group
+    ncb = ncb < nc ? ncb : nc;
     if (ncb <= 0) return;
     const int32_t p0 = wave_pix[w], p1 = wave_pix[w + 1];
     if (p0 >= p1) return;
     const int64_t q0 = ooff[b], n_vec = (ooff[b + 1] - q0) * NS;
+    float* const azb = az + blk_off[b] + (int64_t)k0 * n_vec - q0 * NS;  // pixel q0 at 0
     const int64_t i0 = seg[p0];
     const int64_t i1 = seg[p1 - 1] + hits[p1 - 1];
     const int lane = threadIdx.x & 63;
-    float2* zw = zx[threadIdx.x >> 6];
+    float (*zw)[64 * E] = zx[threadIdx.x >> 6];
     int32_t pf[E];
     auto fetch = [&](int64_t c) {
 #pragma unroll
@@ -312,18 +314,23 @@ __global__ __launch_bounds__(256) void k_scatter_pair(
 #pragma unroll
         for (int g = 0; g < E; ++g) tc[g] = pf[g];
         fetch(c + 64 * E);
-        float2 zg[E];
+        // streams past nc load stream 0 (unconditional loads; never written out)
+        float zg[NC][E];
 #pragma unroll
-        for (int g = 0; g < E; ++g) {
-            const int32_t t = tc[g] >= 0 ? tc[g] : 0;
-            zg[g] = make_float2(z0[t], z1[t]);
-        }
+        for (int k = 0; k < NC; ++k)
 #pragma unroll
-        for (int g = 0; g < E; ++g) zw[lane + 64 * g] = tc[g] >= 0 ? zg[g] : make_float2(0.0f, 0.0f);
+            for (int g = 0; g < E; ++g)
+                zg[k][g] = z[(k < nc ? k : 0) * zstride + (tc[g] >= 0 ? tc[g] : 0)];
+#pragma unroll
+        for (int k = 0; k < NC; ++k)
+#pragma unroll
+            for (int g = 0; g < E; ++g) zw[k][lane + 64 * g] = tc[g] >= 0 ? zg[k][g] : 0.0f;
         wave_lds_sync();
-        float2 zz[E];
+        float zz[NC][E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) zz[e] = zw[E * lane + e];
+        for (int k = 0; k < NC; ++k)
+#pragma unroll
+            for (int e = 0; e < E; ++e) zz[k][e] = zw[k][E * lane + e];
         wave_lds_sync();
         if (base >= i1) {
 #pragma unroll
@@ -333,30 +340,27 @@ __global__ __launch_bounds__(256) void k_scatter_pair(
             return;
         }
 #pragma unroll
-        for (int e = 0; e < E; ++e) zz[e] = valid[e] ? zz[e] : make_float2(0.0f, 0.0f);
+        for (int e = 0; e < E; ++e)
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            if constexpr (NS == 3) {
-                v[e][0] = zz[e].x;
-                v[e][1] = wv[2 * e] * zz[e].x;
-                v[e][2] = wv[2 * e + 1] * zz[e].x;
-                v[e][3] = zz[e].y;
-                v[e][4] = wv[2 * e] * zz[e].y;
-                v[e][5] = wv[2 * e + 1] * zz[e].y;
-            } else {
-                v[e][0] = zz[e].x;
-                v[e][1] = zz[e].y;
+            for (int k = 0; k < NC; ++k) {
+                const float zk = valid[e] ? zz[k][e] : 0.0f;
+                if constexpr (NS == 3) {
+                    v[e][3 * k] = zk;
+                    v[e][3 * k + 1] = wv[2 * e] * zk;
+                    v[e][3 * k + 2] = wv[2 * e + 1] * zk;
+                } else {
+                    v[e][k] = zk;
+                }
             }
-        }
     };
     auto emit = [&](int64_t pix, const float* tot) {
-        float* dst = az + blk_off[b] + (int64_t)k0 * n_vec + (pix - q0) * NS;
+        float* dst = azb + pix * NS;
 #pragma unroll
-        for (int q = 0; q < NS; ++q) dst[q] = tot[q];
-        if (ncb > 1) {
+        for (int k = 0; k < NC; ++k)
+            if (k < ncb) {
 #pragma unroll
-            for (int q = 0; q < NS; ++q) dst[n_vec + q] = tot[NS + q];
-        }
+                for (int q = 0; q < NS; ++q) dst[k * n_vec + q] = tot[NS * k + q];
+            }
     };
     seg_reduce<float, NV, E>(i0, i1, p0, heads, load, emit);
 }
@@ -546,21 +550,27 @@ int scatter_t(mm_plan_t pl, const T* z, const T* ws, double* x, const int* mask)
 
 }  // namespace
 
-int scatter_pair32(mm_plan_t pl, const float* z0, const float* z1, int k0,
+int scatter_cols32(mm_plan_t pl, const float* z, int64_t zstride, int nc, int k0,
                    const int32_t* ncols, const int64_t* blk_off, float* az) {
+    if (nc < 1 || nc > kScatterCols) {
+        set_error("scatter_cols32: %d streams (1..%d)", nc, kScatterCols);
+        return MM_ERR_ARG;
+    }
     const int64_t nb = (pl->n_waves + 3) / 4;
     if (nb == 0) return MM_OK;
     constexpr int E = 4;  // the lane layout of scatter32: the same additions
     if (pl->n_s == 3)
-        hipLaunchKernelGGL((k_scatter_pair<3, E>), dim3(nb), dim3(256), 0, pl->stream, pl->perm.p,
-                           pl->ws32.p, z0, z1, (const unsigned long long*)pl->heads.p, pl->wave_pix.p,
-                           pl->seg.p, pl->hits.p, pl->n_waves, pl->wave_prob.p, pl->ooff.p, ncols,
-                           blk_off, k0, az);
+        hipLaunchKernelGGL((k_scatter_cols<3, E, kScatterCols>), dim3(nb), dim3(256), 0,
+                           pl->stream, pl->perm.p, pl->ws32.p, z, zstride, nc,
+                           (const unsigned long long*)pl->heads.p, pl->wave_pix.p, pl->seg.p,
+                           pl->hits.p, pl->n_waves, pl->wave_prob.p, pl->ooff.p, ncols, blk_off,
+                           k0, az);
     else
-        hipLaunchKernelGGL((k_scatter_pair<1, E>), dim3(nb), dim3(256), 0, pl->stream, pl->perm.p,
-                           pl->ws32.p, z0, z1, (const unsigned long long*)pl->heads.p, pl->wave_pix.p,
-                           pl->seg.p, pl->hits.p, pl->n_waves, pl->wave_prob.p, pl->ooff.p, ncols,
-                           blk_off, k0, az);
+        hipLaunchKernelGGL((k_scatter_cols<1, E, kScatterCols>), dim3(nb), dim3(256), 0,
+                           pl->stream, pl->perm.p, pl->ws32.p, z, zstride, nc,
+                           (const unsigned long long*)pl->heads.p, pl->wave_pix.p, pl->seg.p,
+                           pl->hits.p, pl->n_waves, pl->wave_prob.p, pl->ooff.p, ncols, blk_off,
+                           k0, az);
     MM_HIP(hipGetLastError());
     return MM_OK;
 }
