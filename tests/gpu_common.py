@@ -45,11 +45,18 @@ def long_iqu(seed=35):
     return sc
 
 
+def strips_i(seed=37):
+    # I only, 24x24 patch, two identical passes cut into 9 intervals each: 9 distinct Z_S
+    # columns (strips of about 2.7 rows), more than one group of layers in the A Z build
+    return synth.raster_i(side=24, spp=4, n_pass=2, interval_len=256, lam=64, seed_key=seed)
+
+
 SCANS = {
     "long_iqu": long_iqu,
     "small_iqu": small_iqu,
     "ragged_iqu": ragged_iqu,
     "cfg1": synth.cfg1_raster_i,
+    "strips_i": strips_i,
 }
 
 
