@@ -51,12 +51,19 @@ def strips_i(seed=37):
     return synth.raster_i(side=24, spp=4, n_pass=2, interval_len=256, lam=64, seed_key=seed)
 
 
+def hot_i(seed=39):
+    # I only, 8x8 patch, 72 passes cut into halves: every pixel is hit by 72 intervals
+    # (rows of Z_S longer than 64 entries), 2 distinct Z_S columns
+    return synth.raster_i(side=8, spp=4, n_pass=72, interval_len=128, lam=16, seed_key=seed)
+
+
 SCANS = {
     "long_iqu": long_iqu,
     "small_iqu": small_iqu,
     "ragged_iqu": ragged_iqu,
     "cfg1": synth.cfg1_raster_i,
     "strips_i": strips_i,
+    "hot_i": hot_i,
 }
 
 
