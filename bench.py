@@ -192,6 +192,62 @@ def multi_rhs_leg(pix, w, sc, psd, m, noise, tol, n_rhs, autotune, krylov_dim=25
     return out
 
 
+def knee_leg(tol, knees, autotune, krylov_dim=2048):
+    """Solvers against the knee frequency of the 1/f noise (Sect. 4.2, Fig.
+    deflation_iterations; Sect. 4.3, Fig. overall_time): the 2^22-sample IQU raster (4
+    co-pointed detectors + 2 Hz HWP, 256x256 patch, 32 intervals of 2^17, lambda = 2048)
+    with every interval's f_knee set to each value (alpha = 2).  For each, the mixed
+    block-Jacobi solve; the mixed two-level solve with Z_S, whose construction (the plan's
+    coarse build) is reported apart; and the mixed two-level solve with Z_D, whose
+    construction is a recording block-Jacobi solve plus the Ritz extraction and A Z_D, E_D.
+    Iterations and solve times are per right-hand side once the preconditioner exists."""
+    import torch
+    import synth
+    from paper_1408_3048_amd import Plan
+    out = []
+    for fk in knees:
+        sc = synth.raster_iqu(256, 8, 4, 2 ** 17, 2048, (fk, fk), (2.0, 2.0), seed_key=5000,
+                              name=f"raster_iqu_2^22_fknee{fk}")
+        pix = torch.from_numpy(sc.pix).cuda()
+        w = torch.from_numpy(sc.weights).cuda()
+        d = torch.from_numpy(sc.noise).cuda()
+        psd = np.stack([sc.sigma, sc.fknee, sc.alpha], axis=1)
+        kw = dict(n_stokes=3, lam=sc.lam, f_samp=sc.f_samp, precision="mixed", autotune=autotune)
+        row = dict(f_knee=fk)
+
+        def solve(plan, b, pc):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info = plan.pcg_solve(b, precond=pc, precision="mixed", tol=tol, max_iter=5000,
+                                     history=False)
+            torch.cuda.synchronize()
+            return info["iterations"], round(1e3 * (time.perf_counter() - t0), 2)
+
+        plan = Plan(pix, w, sc.n_pix, sc.offsets, psd, coarse=False, **kw)
+        b = plan.rhs(d)
+        it, ms = solve(plan, b, "bj")
+        row["bj"] = dict(plan_ms=round(plan.plan_ms, 2), iterations=it, solve_ms=ms)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.coarse_from_krylov(b, tol=tol, max_iter=5000, krylov_dim=krylov_dim, eps_tol=0.2,
+                                history=False)
+        torch.cuda.synchronize()
+        build = round(1e3 * (time.perf_counter() - t0), 2)
+        it, ms = solve(plan, b, "2lvl")
+        row["zd"] = dict(construction_ms=build, rank=plan.coarse_rank(), iterations=it,
+                         solve_ms=ms)
+        plan.close()
+        plan = Plan(pix, w, sc.n_pix, sc.offsets, psd, coarse=True, **kw)
+        b = plan.rhs(d)
+        it, ms = solve(plan, b, "2lvl")
+        row["zs"] = dict(plan_ms=round(plan.plan_ms, 2), rank=plan.coarse_rank(), iterations=it,
+                         solve_ms=ms)
+        plan.close()
+        log(f"knee sweep: {row}")
+        out.append(row)
+    return out
+
+
 def bandwidth_leg(pix, w, sc, psd, m, d, tol, lams, autotune):
     """The bandwidth study on the same data (Sect. 4.2, Fig. conv_lambda; App. D): for
     every half-bandwidth lambda (0 = white-noise weighting) a mixed plan with Z_S, then the
@@ -270,6 +326,8 @@ def main():
                     help="skip the 256-problem batched Monte Carlo leg")
     ap.add_argument("--bandwidth", default="0,64,256,1024,2048,4096",
                     help="half-bandwidths of the bandwidth-study leg ('' skips it)")
+    ap.add_argument("--knees", default="0.5,2,8",
+                    help="f_knee values (Hz) of the knee-frequency leg ('' skips it)")
     ap.add_argument("--multi-rhs", type=int, default=8,
                     help="right-hand sides of the plan-reuse leg (0 skips it)")
     ap.add_argument("--autotune", type=int, default=1,
@@ -426,6 +484,10 @@ def main():
         lams = [int(v) for v in args.bandwidth.split(",")]
         bandwidth = bandwidth_leg(pix, w, sc, psd, m, d, args.tol, lams, bool(args.autotune))
 
+    knee = None
+    if args.knees and not args.no_reference:
+        knee = knee_leg(args.tol, [float(v) for v in args.knees.split(",")], bool(args.autotune))
+
     batched = None
     if not args.no_batched:
         batched = batched_leg(args.tol)
@@ -449,7 +511,7 @@ def main():
                     n_samples=sc.n_samples, unknowns=extras[-1]["unknowns"],
                     tol=args.tol, parallelism="single GPU"),
         breakdown=extras[-1], reference=ref, other_legs=legs, multi_rhs=multi,
-        bandwidth=bandwidth, batched=batched,
+        bandwidth=bandwidth, knee_sweep=knee, batched=batched,
         roofline=roof,
         cpu_baseline=cpu,
     )
