@@ -36,6 +36,12 @@
  *   - Caller-owned buffers stay caller-owned; a plan owns deep copies of
  *     everything it needs, so the inputs of mm_plan may be freed after it
  *     returns.  Calls that overlap on one plan from several host threads race.
+ *   - Device memory comes from the device's stream-ordered pool.  Blocks the
+ *     library frees (mm_destroy, plan-time scratch) are kept for its own later
+ *     allocations, up to 16 GiB per device, until the process ends; a block is
+ *     reused only after the reusing stream has waited for the work enqueued
+ *     before its release, and an allocation the device cannot serve first hands
+ *     the kept blocks back to the pool.
  */
 #ifndef MM_H
 #define MM_H
@@ -141,7 +147,8 @@ int mm_n_problems(mm_plan_t plan);
  * problem b: [n_stokes * off_b, n_stokes * off_{b+1})). */
 int mm_problem_pixels(mm_plan_t plan, int64_t* host_out);
 
-/* Release a plan and all its device memory (NULL is a no-op). */
+/* Release a plan and all its device memory (NULL is a no-op; the memory stays with the
+ * library for reuse, see above). */
 void mm_destroy(mm_plan_t plan);
 
 /* Number of observed pixels n_obs (map vectors hold n_obs * n_stokes doubles); -1 on NULL. */
