@@ -304,8 +304,8 @@ int prob_sq_norms(mm_plan_t pl, const double* v, std::vector<double>& out) {
 // One PCG iteration for every iterating problem (mask act): q = A p, alpha, x and r,
 // convergence test, z = M r, beta and p.  Launch arguments do not change between
 // iterations, so the sequence can be captured once and replayed.
-int pcg_iteration(mm_plan_t pl, int pc, bool op32, double* x, double* r, double* z, double* p,
-                  double* q, int tag) {
+int pcg_iteration(mm_plan_t pl, bool op32, double* x, double* r, double* p, double* q,
+                  int tag) {
     PcgCtl c = batch_ctl(pl);
     c.mask = pl->act.p;
     MM_TRY(op32 ? apply_A32_tag(pl, p, q, c.mask, tag) : apply_A64_tag(pl, p, q, c.mask, tag));
@@ -343,7 +343,7 @@ int pcg_iteration_tail(mm_plan_t pl, const EngineArgs& ea, double* r, double* z,
 
 int full_iteration(mm_plan_t pl, const EngineArgs& ea, double* x, double* r, double* z, double* p,
                    double* q, int tag) {
-    MM_TRY(pcg_iteration(pl, ea.pc, ea.op32, x, r, z, p, q, tag));
+    MM_TRY(pcg_iteration(pl, ea.op32, x, r, p, q, tag));
     return pcg_iteration_tail(pl, ea, r, z, p, tag);
 }
 
@@ -1022,7 +1022,6 @@ int mm_pcg_solve(mm_plan_t pl, const double* b, double* x, int pc, int precision
         }
     } else {
         // iterative refinement: r = b - A64 x; solve A32 d = r by PCG from d = 0; x += d
-        const int64_t n = nvec(pl);
         std::vector<double> bb;
         MM_TRY(prob_sq_norms(pl, b, bb));
         const double bn = std::sqrt(bb[0]);

@@ -270,29 +270,6 @@ __global__ void k_csr_filter(const int64_t* __restrict__ ptr, const int32_t* __r
     }
 }
 
-// dense Z_I of one problem, row-major [n_obs_pad][rp] from per-column entry lists (rows
-// relative to the problem's first pixel row0)
-__global__ void k_dense_z(const int64_t* __restrict__ cb, const int64_t* __restrict__ ce,
-                          const int32_t* __restrict__ rows, const double* __restrict__ vals,
-                          int32_t r, int32_t rp, int64_t row0, double* __restrict__ zd) {
-    const int32_t c = blockIdx.y;
-    if (c >= r) return;
-    for (int64_t i = cb[c] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ce[c];
-         i += (int64_t)gridDim.x * blockDim.x)
-        zd[((int64_t)rows[i] - row0) * rp + c] = vals[i];
-}
-
-// AZ_I row-major [n_obs_pad][rp] from one problem's column-major AZ block [r][n_vec] (I rows)
-template <typename TA>
-__global__ void k_az_rows(const TA* __restrict__ az, int64_t n_vec, int64_t n_obs, int ns,
-                          int32_t r, int32_t rp, double* __restrict__ out) {
-    const int32_t c = blockIdx.y;
-    if (c >= r) return;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n_obs;
-         p += (int64_t)gridDim.x * blockDim.x)
-        out[p * rp + c] = (double)az[(int64_t)c * n_vec + p * ns];
-}
-
 // ---------------------------------------------------------------- FP64 MFMA: C = A^T B
 // A: row-major [n][ra], B: row-major [n][rb] (n a multiple of 4, ra and rb multiples of
 // 16), C partials [ksplit][ra][rb].  One wave per 16x16 output tile and pixel slab;
@@ -719,9 +696,9 @@ __global__ __launch_bounds__(kCsThreads) void k_coarse_solve(
     const double* __restrict__ cz, const double* __restrict__ vpart,
     const int32_t* __restrict__ vslice, const double* __restrict__ caz,
     const int64_t* __restrict__ ch_off, const int32_t* __restrict__ col_off,
-    const double* __restrict__ Einv, const int64_t* __restrict__ einv_off, int32_t r_max,
+    const double* __restrict__ Einv, const int64_t* __restrict__ einv_off,
     int64_t n_ch, double* __restrict__ w, const int* __restrict__ mask) {
-    extern __shared__ double sv[];  // [r_max]
+    extern __shared__ double sv[];  // [largest r_b]
     const int b = blockIdx.x;
     if (mask && !mask[b]) return;
     const int32_t c0 = col_off[b], rb = col_off[b + 1] - c0;
@@ -1778,7 +1755,6 @@ namespace {
 int twolvl_apply_dense(mm_plan_t pl, const double* r, double* z, const PcgCtl& ctl) {
     Coarse& co = pl->co;
     hipStream_t st = pl->stream;
-    const int32_t k = co.r_eff;
     const int ns = pl->n_s;
     const dim3 gc((unsigned)co.n_chunks), t256(256);
     const size_t zsh = (size_t)4 * co.r_max * sizeof(double);
@@ -1793,8 +1769,8 @@ int twolvl_apply_dense(mm_plan_t pl, const double* r, double* z, const PcgCtl& c
     hipLaunchKernelGGL(k_coarse_solve, dim3(pl->n_prob), dim3(kCsThreads),
                        (size_t)co.r_max * sizeof(double), st, (const double*)co.cpart.p,
                        (const double*)nullptr, (const int32_t*)nullptr, (const double*)nullptr,
-                       co.ch_off.p, co.col_off.p, co.Einv.p, co.einv_off.p, co.r_max,
-                       co.n_chunks, co.w.p, ctl.mask);
+                       co.ch_off.p, co.col_off.p, co.Einv.p, co.einv_off.p, co.n_chunks, co.w.p,
+                       ctl.mask);
     const size_t shm = (size_t)co.r_max * sizeof(double);
     const dim3 g(pl->n_pblk), t(kVecThreads);
     const int64_t* np64 = nullptr;
@@ -1909,7 +1885,7 @@ int coarse_w(mm_plan_t pl, const double* r, const double* y, const int* mask) {
                        co.kind == 2 ? (const double*)co.cpart.p : nullptr,
                        (const double*)co.vpart.p, (const int32_t*)co.vslice.p,
                        y ? (const double*)co.cpart2.p : nullptr, co.ch_off.p, co.col_off.p,
-                       co.Einv.p, co.einv_off.p, co.r_max, co.n_chunks, co.w.p, mask);
+                       co.Einv.p, co.einv_off.p, co.n_chunks, co.w.p, mask);
     MM_HIP(hipGetLastError());
     return MM_OK;
 }

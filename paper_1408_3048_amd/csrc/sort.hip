@@ -31,7 +31,7 @@ __global__ void k_scan_tile(const TI* __restrict__ in, int64_t* __restrict__ out
     s[threadIdx.x] = acc;
     __syncthreads();
     for (int d = 1; d < kScanThreads; d <<= 1) {
-        int64_t t = threadIdx.x >= d ? s[threadIdx.x - d] : 0;
+        int64_t t = (int)threadIdx.x >= d ? s[threadIdx.x - d] : 0;
         __syncthreads();
         s[threadIdx.x] += t;
         __syncthreads();
@@ -77,34 +77,6 @@ int scan_exclusive(const TI* in, int64_t* out, int64_t n, hipStream_t st) {
     MM_HIP(hipGetLastError());
     MM_HIP(hipMemcpyAsync(out + n, soff.p + nb, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
     return MM_OK;  // the scratch buffers are released in stream order
-}
-
-__global__ void k_minmax(const int32_t* __restrict__ pix, int64_t n, int* __restrict__ mm2) {
-    __shared__ int slo[4], shi[4];
-    int lo = INT_MAX, hi = INT_MIN;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const int v = pix[t];
-        lo = min(lo, v);
-        hi = max(hi, v);
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        lo = min(lo, __shfl_xor(lo, o));
-        hi = max(hi, __shfl_xor(hi, o));
-    }
-    if ((threadIdx.x & 63) == 0) {
-        slo[threadIdx.x >> 6] = lo;
-        shi[threadIdx.x >> 6] = hi;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
-            lo = min(lo, slo[w]);
-            hi = max(hi, shi[w]);
-        }
-        atomicMin(&mm2[0], lo);
-        atomicMax(&mm2[1], hi);
-    }
 }
 
 // hit counts: every thread counts runs of equal pixel ids in 8 consecutive samples and

@@ -136,19 +136,9 @@ __global__ void k_taps_finish(double* __restrict__ t, const int64_t* __restrict_
     }
 }
 
-// spectrum coefficients b_0 = t_0, b_k = 2 t_k
-__global__ void k_spec_coef(const double* __restrict__ t, const int64_t* __restrict__ toff,
-                            const int64_t* __restrict__ tcnt, double* __restrict__ b, int32_t nk) {
-    const int g = blockIdx.y;
-    if (g >= nk) return;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < tcnt[g];
-         k += (int64_t)gridDim.x * blockDim.x)
-        b[toff[g] + k] = (k == 0 ? 1.0 : 2.0) * t[toff[g] + k];
-}
-
 __global__ void k_spec_finish(const double* __restrict__ Hraw, int64_t stride, int64_t cnt,
                               double scale, double* __restrict__ H64, float* __restrict__ H32,
-                              double* __restrict__ hmin, int32_t nk) {
+                              double* __restrict__ hmin) {
     const int g = blockIdx.x;
     double m = INFINITY;
     for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) {
@@ -1379,7 +1369,7 @@ int build_tiling(mm_plan_t pl, FftTiling& ft, bool fp64, int n_r_request) {
     }
     hipLaunchKernelGGL(k_spec_finish, dim3(nk), dim3(256), 0, st, d_h.p, (int64_t)(M + 1),
                        (int64_t)(M + 1), scale, fp64 ? ft.H64.p : nullptr,
-                       fp64 ? nullptr : ft.H32.p, d_min.p, nk);
+                       fp64 ? nullptr : ft.H32.p, d_min.p);
     MM_HIP(hipGetLastError());
     std::vector<double> hmin(nk);
     MM_HIP(hipMemcpyAsync(hmin.data(), d_min.p, nk * 8, hipMemcpyDeviceToHost, st));
