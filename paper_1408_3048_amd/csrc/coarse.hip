@@ -613,16 +613,17 @@ __global__ void k_cols_to_rows(const TA* __restrict__ src, int64_t n, int32_t r,
 // column i of the problem to cpart[i * n_ch + g] (r and every column read once,
 // coalesced; fixed reduction order)
 constexpr int kZtChunk = 1024;
+constexpr int kZtCols = 32;  // columns per block of the chunk partials (grid y)
 template <typename TA>
 __global__ __launch_bounds__(256) void k_ztr_chunks(const TA* __restrict__ zd,
                                                     const int64_t* __restrict__ blk_off,
                                                     const int32_t* __restrict__ col_off,
                                                     const int64_t* __restrict__ ch_off, int B,
                                                     const int64_t* __restrict__ ooff, int ns,
-                                                    const double* __restrict__ r, int32_t r_max,
+                                                    const double* __restrict__ r,
                                                     int64_t n_ch, double* __restrict__ cpart,
                                                     const int* __restrict__ mask) {
-    extern __shared__ double red[];  // [4][r_max]
+    __shared__ double red[4 * kZtCols];
     const int64_t g = blockIdx.x;
     int lo = 0, hi = B - 1;  // problem: largest b with ch_off[b] <= g
     while (lo < hi) {
@@ -632,6 +633,9 @@ __global__ __launch_bounds__(256) void k_ztr_chunks(const TA* __restrict__ zd,
     const int b = lo;
     if (mask && !mask[b]) return;
     const int32_t rb = col_off[b + 1] - col_off[b];
+    const int32_t cg0 = (int32_t)blockIdx.y * kZtCols;  // this block's group of columns
+    if (cg0 >= rb) return;
+    const int32_t cg1 = cg0 + kZtCols < rb ? cg0 + kZtCols : rb;
     const int64_t v0 = ooff[b] * ns, n = (ooff[b + 1] - ooff[b]) * ns;
     const int64_t e0 = (g - ch_off[b]) * kZtChunk;
     constexpr int E = kZtChunk / 256;
@@ -648,7 +652,7 @@ __global__ __launch_bounds__(256) void k_ztr_chunks(const TA* __restrict__ zd,
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const TA* zb = zd + blk_off[b];
-    for (int32_t c0 = 0; c0 < rb; c0 += 8) {
+    for (int32_t c0 = cg0; c0 < cg1; c0 += 8) {
         double acc[8];
 #pragma unroll
         for (int cc = 0; cc < 8; ++cc) {
@@ -662,12 +666,13 @@ __global__ __launch_bounds__(256) void k_ztr_chunks(const TA* __restrict__ zd,
         for (int cc = 0; cc < 8; ++cc) {
             double a = acc[cc];
             for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
-            if (lane == 0 && c0 + cc < rb) red[wv * r_max + c0 + cc] = a;
+            if (lane == 0 && c0 + cc < cg1) red[wv * kZtCols + c0 + cc - cg0] = a;
         }
     }
     __syncthreads();
-    for (int32_t c = threadIdx.x; c < rb; c += 256)
-        cpart[c * n_ch + g] = ((red[c] + red[r_max + c]) + red[2 * r_max + c]) + red[3 * r_max + c];
+    for (int32_t c = threadIdx.x; c < cg1 - cg0; c += 256)
+        cpart[(cg0 + c) * n_ch + g] =
+            ((red[c] + red[kZtCols + c]) + red[2 * kZtCols + c]) + red[3 * kZtCols + c];
 }
 
 // sum of n_ch-strided chunk partials ci[g0..g1) over the wave (four independent load
@@ -688,42 +693,50 @@ __device__ __forceinline__ double wave_chunk_sum(const double* __restrict__ ci, 
     return s;
 }
 
-// second stage, one block per problem: v_i = Z^T r of column i, from chunk partials cz
-// (Z_D) or from the slice partials vpart / vslice (Z_S), minus (AZ)^T y of column i from
-// chunk partials caz when given (A-DEF2); one wave per column into LDS, then w = E^-1 v
-constexpr int kCsThreads = 1024;
-__global__ __launch_bounds__(kCsThreads) void k_coarse_solve(
+// v_a = the sum of the chunk partials of column a of Z^T r (Z_D: cz), or of its slice
+// partials (Z_S: vpart, vslice), minus that of (AZ)^T y (caz) where given, for every kept
+// column a of the masked problems: one wave per column over all problems
+__global__ __launch_bounds__(256) void k_coarse_sums(
     const double* __restrict__ cz, const double* __restrict__ vpart,
     const int32_t* __restrict__ vslice, const double* __restrict__ caz,
     const int64_t* __restrict__ ch_off, const int32_t* __restrict__ col_off,
-    const double* __restrict__ Einv, const int64_t* __restrict__ einv_off,
-    int64_t n_ch, double* __restrict__ w, const int* __restrict__ mask) {
-    extern __shared__ double sv[];  // [largest r_b]
-    const int b = blockIdx.x;
+    const int32_t* __restrict__ col_prob, int64_t n_ch, int32_t r_eff,
+    double* __restrict__ v, const int* __restrict__ mask) {
+    const int lane = threadIdx.x & 63;
+    const int32_t a = (int32_t)blockIdx.x * 4 + (int32_t)(threadIdx.x >> 6);
+    if (a >= r_eff) return;
+    const int b = col_prob[a];
     if (mask && !mask[b]) return;
-    const int32_t c0 = col_off[b], rb = col_off[b + 1] - c0;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int32_t i = a - col_off[b];
     const int64_t g0 = ch_off[b], g1 = ch_off[b + 1];
-    for (int32_t i = wv; i < rb; i += kCsThreads / 64) {
-        double s;
-        if (cz) {
-            s = wave_chunk_sum(cz + (int64_t)i * n_ch, g0, g1, lane);
-        } else {
-            s = 0.0;
-            for (int32_t t = vslice[c0 + i] + lane; t < vslice[c0 + i + 1]; t += 64) s += vpart[t];
-            for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-        }
-        if (caz) s -= wave_chunk_sum(caz + (int64_t)i * n_ch, g0, g1, lane);
-        if (lane == 0) sv[i] = s;
-    }
-    __syncthreads();
-    const double* E = Einv + einv_off[b];
-    for (int32_t a = wv; a < rb; a += kCsThreads / 64) {  // one wave per row of E^-1
-        double s = 0.0;
-        for (int32_t q = lane; q < rb; q += 64) s += E[(int64_t)a * rb + q] * sv[q];
+    double s;
+    if (cz) {
+        s = wave_chunk_sum(cz + (int64_t)i * n_ch, g0, g1, lane);
+    } else {
+        s = 0.0;
+        for (int32_t t = vslice[a] + lane; t < vslice[a + 1]; t += 64) s += vpart[t];
         for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-        if (lane == 0) w[c0 + a] = s;
     }
+    if (caz) s -= wave_chunk_sum(caz + (int64_t)i * n_ch, g0, g1, lane);
+    if (lane == 0) v[a] = s;
+}
+
+// w = E_b^-1 v_b per masked problem b: one wave per kept column (a row of E_b^-1)
+__global__ __launch_bounds__(256) void k_coarse_einv(
+    const double* __restrict__ Einv, const int64_t* __restrict__ einv_off,
+    const int32_t* __restrict__ col_off, const int32_t* __restrict__ col_prob, int32_t r_eff,
+    const double* __restrict__ v, double* __restrict__ w, const int* __restrict__ mask) {
+    const int lane = threadIdx.x & 63;
+    const int32_t a = (int32_t)blockIdx.x * 4 + (int32_t)(threadIdx.x >> 6);
+    if (a >= r_eff) return;
+    const int b = col_prob[a];
+    if (mask && !mask[b]) return;
+    const int32_t c0 = col_off[b], rb = col_off[b + 1] - c0, i = a - c0;
+    const double* E = Einv + einv_off[b] + (int64_t)i * rb;
+    double s = 0.0;
+    for (int32_t q = lane; q < rb; q += 64) s += E[q] * v[c0 + q];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) w[a] = s;
 }
 
 // A-DEF2, last step: z = y + Z w per pixel (y = M_BD r already in z), partials of r^T z.
@@ -1417,6 +1430,7 @@ int build_coarse(mm_plan_t pl) {
                        co.csr_col.p, co.csr_val.p);
     MM_HIP(hipGetLastError());
     MM_TRY(co.w.alloc(keff));
+    MM_TRY(co.v.alloc(keff));
     MM_TRY(co.vpart.alloc(co.n_slices));
     // chunk tables of the dense (AZ)^T y products (A-DEF2)
     {
@@ -1678,13 +1692,14 @@ int build_coarse_dense(mm_plan_t pl, const double* basis, int64_t basis_stride,
     MM_HIP(hipMemcpyAsync(d_choff.p, choff.data(), (B + 1) * 8, hipMemcpyHostToDevice, st));
     DBuf<int32_t> d_cprob, d_coloff;
     DBuf<int64_t> d_azoff, d_einvoff;
-    DBuf<double> d_einv, d_w;
+    DBuf<double> d_einv, d_w, d_v;
     MM_TRY(d_cprob.alloc(keff));
     MM_TRY(d_coloff.alloc(B + 1));
     MM_TRY(d_azoff.alloc(B + 1));
     MM_TRY(d_einvoff.alloc(B + 1));
     MM_TRY(d_einv.alloc(Einv_all.size()));
     MM_TRY(d_w.alloc(keff));
+    MM_TRY(d_v.alloc(keff));
     MM_HIP(hipMemcpyAsync(d_cprob.p, cprob.data(), keff * 4, hipMemcpyHostToDevice, st));
     MM_HIP(hipMemcpyAsync(d_coloff.p, col_off.data(), (B + 1) * 4, hipMemcpyHostToDevice, st));
     MM_HIP(hipMemcpyAsync(d_azoff.p, az_off.data(), (B + 1) * 8, hipMemcpyHostToDevice, st));
@@ -1711,6 +1726,7 @@ int build_coarse_dense(mm_plan_t pl, const double* basis, int64_t basis_stride,
     co.einv_off.swap(d_einvoff);
     co.Einv.swap(d_einv);
     co.w.swap(d_w);
+    co.v.swap(d_v);
     co.vslice.release();
     co.slice_col.release();
     co.vpart.release();
@@ -1752,25 +1768,37 @@ int coarse_dense_columns(mm_plan_t pl, double* out) {
 
 namespace {
 
+// w = E^-1 (Z^T r - (AZ)^T y) of the masked problems from the partials of the first
+// stage: cz (Z_D chunk partials) or the Z_S slice partials, and caz ((AZ)^T y chunk
+// partials) or none
+int coarse_solve(mm_plan_t pl, const double* cz, const double* caz, const int* mask) {
+    Coarse& co = pl->co;
+    const int32_t k = co.r_eff;
+    const dim3 g((unsigned)((k + 3) / 4)), t(256);
+    hipLaunchKernelGGL(k_coarse_sums, g, t, 0, pl->stream, cz, (const double*)co.vpart.p,
+                       (const int32_t*)co.vslice.p, caz, co.ch_off.p, co.col_off.p,
+                       co.col_prob.p, co.n_chunks, k, co.v.p, mask);
+    hipLaunchKernelGGL(k_coarse_einv, g, t, 0, pl->stream, co.Einv.p, co.einv_off.p,
+                       co.col_off.p, co.col_prob.p, k, (const double*)co.v.p, co.w.p, mask);
+    MM_HIP(hipGetLastError());
+    return MM_OK;
+}
+
 int twolvl_apply_dense(mm_plan_t pl, const double* r, double* z, const PcgCtl& ctl) {
     Coarse& co = pl->co;
     hipStream_t st = pl->stream;
     const int ns = pl->n_s;
-    const dim3 gc((unsigned)co.n_chunks), t256(256);
-    const size_t zsh = (size_t)4 * co.r_max * sizeof(double);
+    const dim3 gc((unsigned)co.n_chunks, (unsigned)((co.r_max + kZtCols - 1) / kZtCols)),
+        t256(256);
     if (co.ZD32.p)
-        hipLaunchKernelGGL(k_ztr_chunks<float>, gc, t256, zsh, st, (const float*)co.ZD32.p,
+        hipLaunchKernelGGL(k_ztr_chunks<float>, gc, t256, 0, st, (const float*)co.ZD32.p,
                            co.az_off.p, co.col_off.p, co.ch_off.p, pl->n_prob, pl->ooff.p, ns,
-                           r, co.r_max, co.n_chunks, co.cpart.p, ctl.mask);
+                           r, co.n_chunks, co.cpart.p, ctl.mask);
     else
-        hipLaunchKernelGGL(k_ztr_chunks<double>, gc, t256, zsh, st, (const double*)co.ZD64.p,
+        hipLaunchKernelGGL(k_ztr_chunks<double>, gc, t256, 0, st, (const double*)co.ZD64.p,
                            co.az_off.p, co.col_off.p, co.ch_off.p, pl->n_prob, pl->ooff.p, ns,
-                           r, co.r_max, co.n_chunks, co.cpart.p, ctl.mask);
-    hipLaunchKernelGGL(k_coarse_solve, dim3(pl->n_prob), dim3(kCsThreads),
-                       (size_t)co.r_max * sizeof(double), st, (const double*)co.cpart.p,
-                       (const double*)nullptr, (const int32_t*)nullptr, (const double*)nullptr,
-                       co.ch_off.p, co.col_off.p, co.Einv.p, co.einv_off.p, co.n_chunks, co.w.p,
-                       ctl.mask);
+                           r, co.n_chunks, co.cpart.p, ctl.mask);
+    MM_TRY(coarse_solve(pl, (const double*)co.cpart.p, nullptr, ctl.mask));
     const size_t shm = (size_t)co.r_max * sizeof(double);
     const dim3 g(pl->n_pblk), t(kVecThreads);
     const int64_t* np64 = nullptr;
@@ -1855,10 +1883,10 @@ const double* z_blocks<double>(const Coarse& co) { return co.ZD64.p; }
 template <typename TA>
 int chunk_partials(mm_plan_t pl, const TA* X, const double* v, double* out, const int* mask) {
     const Coarse& co = pl->co;
-    hipLaunchKernelGGL(k_ztr_chunks<TA>, dim3((unsigned)co.n_chunks), dim3(256),
-                       (size_t)4 * co.r_max * sizeof(double), pl->stream, X, co.az_off.p,
-                       co.col_off.p, co.ch_off.p, pl->n_prob, pl->ooff.p, pl->n_s, v, co.r_max,
-                       co.n_chunks, out, mask);
+    hipLaunchKernelGGL(k_ztr_chunks<TA>,
+                       dim3((unsigned)co.n_chunks, (unsigned)((co.r_max + kZtCols - 1) / kZtCols)),
+                       dim3(256), 0, pl->stream, X, co.az_off.p, co.col_off.p, co.ch_off.p,
+                       pl->n_prob, pl->ooff.p, pl->n_s, v, co.n_chunks, out, mask);
     MM_HIP(hipGetLastError());
     return MM_OK;
 }
@@ -1880,12 +1908,8 @@ int coarse_w(mm_plan_t pl, const double* r, const double* y, const int* mask) {
     if (y)
         MM_TRY(f32 ? chunk_partials<float>(pl, co.AZ32.p, y, co.cpart2.p, mask)
                    : chunk_partials<double>(pl, co.AZ64.p, y, co.cpart2.p, mask));
-    hipLaunchKernelGGL(k_coarse_solve, dim3(pl->n_prob), dim3(kCsThreads),
-                       (size_t)co.r_max * sizeof(double), st,
-                       co.kind == 2 ? (const double*)co.cpart.p : nullptr,
-                       (const double*)co.vpart.p, (const int32_t*)co.vslice.p,
-                       y ? (const double*)co.cpart2.p : nullptr, co.ch_off.p, co.col_off.p,
-                       co.Einv.p, co.einv_off.p, co.n_chunks, co.w.p, mask);
+    MM_TRY(coarse_solve(pl, co.kind == 2 ? (const double*)co.cpart.p : nullptr,
+                        y ? (const double*)co.cpart2.p : nullptr, mask));
     MM_HIP(hipGetLastError());
     return MM_OK;
 }

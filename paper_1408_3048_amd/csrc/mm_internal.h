@@ -182,6 +182,7 @@ struct Coarse {
     DBuf<float> ZD32;                // same (mixed plans)
     DBuf<double> Einv;               // E^-1 blocks
     DBuf<double> w;                  // coarse solution [r_eff]
+    DBuf<double> v;                  // coarse right-hand side Z^T r (- (AZ)^T y) [r_eff]
     DBuf<int32_t> vslice;            // [r_eff+1] first Z^T r slice of every kept column
     DBuf<int32_t> slice_col;         // [n_slices] kept column of every slice
     int64_t n_slices = 0;            // slices of 512 entries over all kept columns
