@@ -502,46 +502,63 @@ __global__ __launch_bounds__(kVecThreads) void k_2lvl(
     const int64_t nv = vb.n * NS;
     const TA* azb = az + az_off[vb.b];
     double acc = 0.0;
+    // a thread's pixels q and q + stride go through the column loop together (twice the
+    // loads in flight per column); a missing second pixel reads the first again and is
+    // not stored.  Every per-pixel sum and the order of acc are those of one pixel at a
+    // time.
     for (int64_t q = (int64_t)vb.k * kVecThreads + threadIdx.x; q < vb.n;
-         q += vb.stride) {
-        const int64_t p = vb.base + q;
-        double u[NS], zw[NS];
+         q += 2 * vb.stride) {
+        const int64_t q1 = q + vb.stride < vb.n ? q + vb.stride : q;
+        const int64_t qq[2] = {q, q1};
+        double u[2][NS], zw[2][NS];
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            u[s] = r[p * NS + s];
-            zw[s] = 0.0;
-        }
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                u[j][s] = r[(vb.base + qq[j]) * NS + s];
+                zw[j][s] = 0.0;
+            }
         for (int32_t c = 0; c < rk; ++c) {
             const double wc = sw[c];
-            const TA* col = azb + (int64_t)c * nv + q * NS;
+            const TA* col = azb + (int64_t)c * nv;
 #pragma unroll
-            for (int s = 0; s < NS; ++s) u[s] -= (double)col[s] * wc;
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int s = 0; s < NS; ++s) u[j][s] -= (double)col[qq[j] * NS + s] * wc;
             if constexpr (DZ) {
-                const TA* zc = zd + az_off[vb.b] + (int64_t)c * nv + q * NS;
+                const TA* zc = zd + az_off[vb.b] + (int64_t)c * nv;
 #pragma unroll
-                for (int s = 0; s < NS; ++s) zw[s] += (double)zc[s] * wc;
+                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) zw[j][s] += (double)zc[qq[j] * NS + s] * wc;
             }
         }
-        double zz[NS];
-        if constexpr (NS == 1) {
-            zz[0] = bj[p] * u[0];
-        } else {
-            const double* m = bj + 6 * p;
-            zz[0] = m[0] * u[0] + m[1] * u[1] + m[2] * u[2];
-            zz[1] = m[1] * u[0] + m[3] * u[1] + m[4] * u[2];
-            zz[2] = m[2] * u[0] + m[4] * u[1] + m[5] * u[2];
-        }
-        if constexpr (DZ) {
 #pragma unroll
-            for (int s = 0; s < NS; ++s) zz[s] += zw[s];
-        } else {
-            for (int64_t e = zptr[p]; e < zptr[p + 1]; ++e) zw[0] += zval[e] * sw[zcol[e] - c0];
-            zz[0] += zw[0];
-        }
+        for (int j = 0; j < 2; ++j) {
+            if (j == 1 && q1 == q) break;
+            const int64_t p = vb.base + qq[j];
+            double zz[NS];
+            if constexpr (NS == 1) {
+                zz[0] = bj[p] * u[j][0];
+            } else {
+                const double* m = bj + 6 * p;
+                zz[0] = m[0] * u[j][0] + m[1] * u[j][1] + m[2] * u[j][2];
+                zz[1] = m[1] * u[j][0] + m[3] * u[j][1] + m[4] * u[j][2];
+                zz[2] = m[2] * u[j][0] + m[4] * u[j][1] + m[5] * u[j][2];
+            }
+            if constexpr (DZ) {
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            z[p * NS + s] = zz[s];
-            acc += r[p * NS + s] * zz[s];
+                for (int s = 0; s < NS; ++s) zz[s] += zw[j][s];
+            } else {
+                double zs = zw[j][0];
+                for (int64_t e = zptr[p]; e < zptr[p + 1]; ++e) zs += zval[e] * sw[zcol[e] - c0];
+                zz[0] += zs;
+            }
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                z[p * NS + s] = zz[s];
+                acc += r[p * NS + s] * zz[s];
+            }
         }
     }
     if (ctl.part) write_partial_at(acc, slot_part(ctl, kSlotRZ, vb.b), vb.k, red);
