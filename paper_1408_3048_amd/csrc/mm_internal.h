@@ -352,7 +352,7 @@ int scatter32(mm_plan_t pl, const float* z, double* x, const int* mask);
 // P^T of nc <= kScatterCols FP32 time streams z + k zstride into columns k0 + k of the
 // per-problem FP32 blocks of az (block b at blk_off[b], column-major [ncols[b]][n_vec_b]);
 // columns at or past ncols[b] are not written.  Each stream's sums are those of scatter32.
-constexpr int kScatterCols = 4;
+constexpr int kScatterCols = 8;
 int scatter_cols32(mm_plan_t pl, const float* z, int64_t zstride, int nc, int k0,
                    const int32_t* ncols, const int64_t* blk_off, float* az);
 int depoint(mm_plan_t pl, const double* x, void* y, int y_f64);
