@@ -368,6 +368,8 @@ __global__ void k_sum_parts_batch(const double* __restrict__ part, const GramDes
         const GramDesc g = d[b];
         const int64_t m = (int64_t)g.rp * g.rp, loc = e - eoff[b];
         double s = 0.0;
+        // in slab order; eight loads in flight
+#pragma unroll 8
         for (int32_t k = 0; k < g.ksplit; ++k) s += part[g.part_off + (int64_t)k * m + loc];
         out[g.c_off + loc] = s;
     }
@@ -391,21 +393,35 @@ __global__ void k_dense_z_batch(const int64_t* __restrict__ cb, const int64_t* _
 }
 
 // I rows of problem b0 + z's AZ block (column-major [r_b][n_vec_b] at az_off[b]) in the row
-// blocks of the Gram products
+// blocks of the Gram products.  A block moves tiles of 64 pixels x 64 columns (columns
+// 64 blockIdx.y + ...) through LDS, so that both the column reads and the row writes are
+// coalesced.
 template <typename TA>
-__global__ void k_az_rows_batch(const TA* __restrict__ az, const int64_t* __restrict__ az_off,
-                                const int32_t* __restrict__ ud_off,
-                                const int64_t* __restrict__ ooff, int ns,
-                                const GramDesc* __restrict__ d, int b0, double* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_az_rows_batch(const TA* __restrict__ az,
+                                                       const int64_t* __restrict__ az_off,
+                                                       const int32_t* __restrict__ ud_off,
+                                                       const int64_t* __restrict__ ooff, int ns,
+                                                       const GramDesc* __restrict__ d, int b0,
+                                                       double* __restrict__ out) {
+    __shared__ double tile[64][65];
     const int b = b0 + (int)blockIdx.z;
-    const int32_t c = blockIdx.y;
-    if (c >= ud_off[b + 1] - ud_off[b]) return;
+    const int32_t rb = ud_off[b + 1] - ud_off[b];
+    const int32_t c0 = (int32_t)blockIdx.y * 64;
+    if (c0 >= rb) return;
+    const int32_t nc = rb - c0 < 64 ? rb - c0 : 64;
     const GramDesc g = d[blockIdx.z];
     const int64_t nob = ooff[b + 1] - ooff[b], n_vec = nob * ns;
-    const TA* src = az + az_off[b] + (int64_t)c * n_vec;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nob;
-         p += (int64_t)gridDim.x * blockDim.x)
-        out[g.a_off + p * g.rp + c] = (double)src[p * ns];
+    const TA* src = az + az_off[b] + (int64_t)c0 * n_vec;
+    const int lo = threadIdx.x & 63, hi = threadIdx.x >> 6;
+    for (int64_t p0 = (int64_t)blockIdx.x * 64; p0 < nob; p0 += (int64_t)gridDim.x * 64) {
+        const int64_t p = p0 + lo;
+        for (int c = hi; c < nc; c += 4)
+            if (p < nob) tile[c][lo] = (double)src[(int64_t)c * n_vec + p * ns];
+        __syncthreads();
+        for (int i = hi; i < 64; i += 4)
+            if (p0 + i < nob && lo < nc) out[g.a_off + (p0 + i) * g.rp + c0 + lo] = tile[lo][i];
+        __syncthreads();
+    }
 }
 
 // v = Z^T r: kept column c owns the slices [vslice[c], vslice[c+1]) of 512 entries
@@ -614,15 +630,27 @@ __global__ void k_zd_to_vec(const int32_t* __restrict__ lp, const TA* __restrict
 }
 
 // column-major [r][n] block -> row-major [npad][rp] FP64 (rows past n and columns past r
-// are left as they are: zeroed by the caller)
+// are left as they are: zeroed by the caller); tiles of 64 entries x 64 columns (columns
+// 64 blockIdx.y + ...) go through LDS, so that reads and writes are both coalesced
 template <typename TA>
-__global__ void k_cols_to_rows(const TA* __restrict__ src, int64_t n, int32_t r, int32_t rp,
-                               double* __restrict__ dst) {
-    const int32_t c = blockIdx.y;
-    if (c >= r) return;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-         e += (int64_t)gridDim.x * blockDim.x)
-        dst[e * rp + c] = (double)src[(int64_t)c * n + e];
+__global__ __launch_bounds__(256) void k_cols_to_rows(const TA* __restrict__ src, int64_t n,
+                                                      int32_t r, int32_t rp,
+                                                      double* __restrict__ dst) {
+    __shared__ double tile[64][65];
+    const int32_t c0 = (int32_t)blockIdx.y * 64;
+    if (c0 >= r) return;
+    const int32_t nc = r - c0 < 64 ? r - c0 : 64;
+    const TA* s = src + (int64_t)c0 * n;
+    const int lo = threadIdx.x & 63, hi = threadIdx.x >> 6;
+    for (int64_t e0 = (int64_t)blockIdx.x * 64; e0 < n; e0 += (int64_t)gridDim.x * 64) {
+        const int64_t e = e0 + lo;
+        for (int c = hi; c < nc; c += 4)
+            if (e < n) tile[c][lo] = (double)s[(int64_t)c * n + e];
+        __syncthreads();
+        for (int i = hi; i < 64; i += 4)
+            if (e0 + i < n && lo < nc) dst[(e0 + i) * rp + c0 + lo] = tile[lo][i];
+        __syncthreads();
+    }
 }
 
 // v = Z_D^T r, first stage: block g takes the chunk [ch*kZtChunk, +kZtChunk) of its
@@ -1285,11 +1313,11 @@ int build_coarse(mm_plan_t pl) {
         hipLaunchKernelGGL(k_dense_z_batch, dim3(64, rmax, nbc), dim3(256), 0, st, dub.p, due.p,
                            crow.p, cval.p, d_ud_off.p, pl->ooff.p, d_gd.p, b0, zd.p);
         if (mixed)
-            hipLaunchKernelGGL(k_az_rows_batch<float>, dim3(grid_for(nob_max, 256, 4096), rmax, nbc),
+            hipLaunchKernelGGL(k_az_rows_batch<float>, dim3(grid_for(nob_max, 64, 2048), (rmax + 63) / 64, nbc),
                                dim3(256), 0, st, azf.p, d_azd_off.p, d_ud_off.p, pl->ooff.p,
                                (int)ns, d_gd.p, b0, azr.p);
         else
-            hipLaunchKernelGGL(k_az_rows_batch<double>, dim3(grid_for(nob_max, 256, 4096), rmax, nbc),
+            hipLaunchKernelGGL(k_az_rows_batch<double>, dim3(grid_for(nob_max, 64, 2048), (rmax + 63) / 64, nbc),
                                dim3(256), 0, st, azd.p, d_azd_off.p, d_ud_off.p, pl->ooff.p,
                                (int)ns, d_gd.p, b0, azr.p);
         hipLaunchKernelGGL(k_gemm_tn_f64_batch, dim3((woff[nbc] + 3) / 4), dim3(256), 0, st, zd.p,
@@ -1598,7 +1626,7 @@ int build_coarse_dense(mm_plan_t pl, const double* basis, int64_t basis_stride,
                 const int64_t npad = (nb + 3) / 4 * 4;
                 MM_HIP(hipMemsetAsync(zr.p, 0, (size_t)npad * rp * 8, st));
                 MM_HIP(hipMemsetAsync(azr.p, 0, (size_t)npad * rp * 8, st));
-                const dim3 g(grid_for(nb, 256, 4096), r);
+                const dim3 g(grid_for(nb, 64, 2048), (r + 63) / 64);
                 if (mixed) {
                     hipLaunchKernelGGL(k_cols_to_rows<float>, g, dim3(256), 0, st,
                                        (const float*)zd32.p + zoff[b], nb, r, rp, zr.p);
