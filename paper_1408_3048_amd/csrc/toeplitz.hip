@@ -73,6 +73,23 @@ __global__ void k_inv_psd(const int32_t* __restrict__ klen, const double* __rest
     }
 }
 
+// the FFT twiddles exp(-2 pi i q / n), q < count, as (re, im) pairs in FP64 and, where
+// tw32 is given, rounded to FP32 (2q/n is exact for the power-of-two lengths used here)
+__global__ void k_twiddles(int64_t count, int64_t n, double* __restrict__ tw64,
+                           float* __restrict__ tw32) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        double s, c;
+        sincospi(-2.0 * (double)q / (double)n, &s, &c);
+        tw64[2 * q] = c;
+        tw64[2 * q + 1] = s;
+        if (tw32) {
+            tw32[2 * q] = (float)c;
+            tw32[2 * q + 1] = (float)s;
+        }
+    }
+}
+
 // out[g][j] = sum_{i < cnt[g]} a[g][i] cos(2 pi i j / n[g]) for j < J[g].
 // The cosine of every term comes from a rotation recurrence re-anchored by
 // sincospi every 32 terms (bounded rounding growth).
@@ -1112,18 +1129,13 @@ int kernel_taps_dev(mm_plan_t pl, int what, DBuf<double>& d_t, std::vector<int64
             rmax = std::max<int>(rmax, (int)(pl->h_kern_len[g] / kNs));
             kmax = std::max<int>(kmax, (int)tcnt[g]);
         }
-        std::vector<double> tw(kNs);
-        for (int64_t q = 0; q < kNs / 2; ++q) {
-            const double ang = -2.0 * M_PI * (double)q / (double)kNs;
-            tw[2 * q] = std::cos(ang);
-            tw[2 * q + 1] = std::sin(ang);
-        }
         DBuf<double> d_tw, d_part;
         DBuf<int32_t> d_kid;
         MM_TRY(d_tw.alloc(kNs));
         MM_TRY(d_kid.alloc(nf));
         MM_TRY(d_part.alloc((size_t)nf * rmax * kmax));
-        MM_HIP(hipMemcpyAsync(d_tw.p, tw.data(), kNs * 8, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_twiddles, dim3((kNs / 2 + 255) / 256), dim3(256), 0, st, kNs / 2,
+                           kNs, d_tw.p, (float*)nullptr);
         MM_HIP(hipMemcpyAsync(d_kid.p, fft_ids.data(), nf * 4, hipMemcpyHostToDevice, st));
         hipLaunchKernelGGL((k_taps_fft<kPlanLogM, kPlanNT>), dim3(rmax, nf), dim3(kPlanNT), 0, st,
                            d_kid.p, d_klen.p, d_kpar.p, d_tcnt.p, pl->opts.f_samp, d_tw.p, kmax,
@@ -1285,21 +1297,21 @@ int build_tiling(mm_plan_t pl, FftTiling& ft, bool fp64, int n_r_request) {
     MM_HIP(hipMemcpyAsync(ft.tile_out.p, tout.data(), ft.n_tiles * 8, hipMemcpyHostToDevice, st));
     MM_HIP(hipMemcpyAsync(ft.tile_len.p, tlen.data(), ft.n_tiles * 4, hipMemcpyHostToDevice, st));
     MM_HIP(hipMemcpyAsync(ft.tile_int.p, tint.data(), ft.n_tiles * 4, hipMemcpyHostToDevice, st));
-    // twiddles exp(-2 pi i q / n_r), q < M
-    std::vector<double> tw(2 * (size_t)M);
-    for (int q = 0; q < M; ++q) {
-        const double ang = -2.0 * M_PI * (double)q / (double)ft.n_r;
-        tw[2 * q] = std::cos(ang);
-        tw[2 * q + 1] = std::sin(ang);
-    }
+    // twiddles exp(-2 pi i q / n_r), q < M, in FP64 (the spectra below and FP64 tiles) and
+    // FP32 for FP32 tiles
+    DBuf<double> d_tw;
+    double* tw64 = nullptr;
     if (fp64) {
         MM_TRY(ft.tw64.alloc(2 * M));
-        MM_HIP(hipMemcpyAsync(ft.tw64.p, tw.data(), 2 * M * 8, hipMemcpyHostToDevice, st));
+        tw64 = ft.tw64.p;
     } else {
-        std::vector<float> twf(tw.begin(), tw.end());
+        MM_TRY(d_tw.alloc(2 * M));
         MM_TRY(ft.tw32.alloc(2 * M));
-        MM_HIP(hipMemcpyAsync(ft.tw32.p, twf.data(), 2 * M * 4, hipMemcpyHostToDevice, st));
+        tw64 = d_tw.p;
     }
+    hipLaunchKernelGGL(k_twiddles, dim3((M + 255) / 256), dim3(256), 0, st, (int64_t)M,
+                       (int64_t)ft.n_r, tw64, fp64 ? (float*)nullptr : ft.tw32.p);
+    MM_HIP(hipGetLastError());
     // spectra H(m), m = 0..M, of every kernel on this grid
     const int32_t nk = pl->n_kern;
     DBuf<double> d_h, d_min;
@@ -1309,25 +1321,22 @@ int build_tiling(mm_plan_t pl, FftTiling& ft, bool fp64, int n_r_request) {
     const int64_t* d_toff = pl->taps_off.p;
     const int64_t* d_tcnt = pl->taps_cnt.p;
     if (logm <= kPlanLogM) {  // FP64 FFT of the even kernel on the tile grid
-        DBuf<double> d_tw;
-        MM_TRY(d_tw.alloc(2 * M));
-        MM_HIP(hipMemcpyAsync(d_tw.p, tw.data(), 2 * M * 8, hipMemcpyHostToDevice, st));
         switch (logm) {
             case 10:
                 hipLaunchKernelGGL((k_spec_fft<10, 256>), dim3(nk), dim3(256), 0, st, d_taps,
-                                   d_toff, d_tcnt, d_tw.p, d_h.p);
+                                   d_toff, d_tcnt, tw64, d_h.p);
                 break;
             case 11:
                 hipLaunchKernelGGL((k_spec_fft<11, 256>), dim3(nk), dim3(256), 0, st, d_taps,
-                                   d_toff, d_tcnt, d_tw.p, d_h.p);
+                                   d_toff, d_tcnt, tw64, d_h.p);
                 break;
             case 12:
                 hipLaunchKernelGGL((k_spec_fft<12, 256>), dim3(nk), dim3(256), 0, st, d_taps,
-                                   d_toff, d_tcnt, d_tw.p, d_h.p);
+                                   d_toff, d_tcnt, tw64, d_h.p);
                 break;
             default:
                 hipLaunchKernelGGL((k_spec_fft<kPlanLogM, kPlanNT>), dim3(nk), dim3(kPlanNT), 0, st,
-                                   d_taps, d_toff, d_tcnt, d_tw.p, d_h.p);
+                                   d_taps, d_toff, d_tcnt, tw64, d_h.p);
                 break;
         }
         MM_HIP(hipGetLastError());
