@@ -44,6 +44,22 @@ __device__ __forceinline__ int32_t interval_of(const int64_t* __restrict__ lo, i
     return a;
 }
 
+// interval of sample t, searched only when t leaves the last interval found ([lo, hi), kept
+// by the caller): a pixel's samples ascend in t, so most lookups cost one comparison
+struct IntervalCache {
+    int64_t lo = 0, hi = 0;
+    int32_t j = 0;
+    __device__ __forceinline__ int32_t of(const int64_t* __restrict__ int_lo, int32_t n_int,
+                                          int64_t t) {
+        if (t < lo || t >= hi) {
+            j = interval_of(int_lo, n_int, t);
+            lo = int_lo[j];
+            hi = j + 1 < n_int ? int_lo[j + 1] : INT64_MAX;
+        }
+        return j;
+    }
+};
+
 // number of distinct intervals among each pixel's samples (ascending in t)
 __global__ void k_zs_count(const int32_t* __restrict__ perm, const int64_t* __restrict__ seg,
                            const int32_t* __restrict__ hits, int64_t n_obs,
@@ -53,8 +69,9 @@ __global__ void k_zs_count(const int32_t* __restrict__ perm, const int64_t* __re
          c += (int64_t)gridDim.x * blockDim.x) {
         int64_t cnt = 0;
         int32_t last = -1;
+        IntervalCache ic;
         for (int64_t i = seg[c]; i < seg[c] + hits[c]; ++i) {
-            const int32_t j = interval_of(int_lo, n_int, perm[i]);
+            const int32_t j = ic.of(int_lo, n_int, perm[i]);
             if (j != last) {
                 ++cnt;
                 last = j;
@@ -75,8 +92,9 @@ __global__ void k_zs_fill(const int32_t* __restrict__ perm, const int64_t* __res
         int64_t o = ptr[c];
         int32_t last = -1;
         int64_t run = 0;
+        IntervalCache ic;
         for (int64_t i = seg[c]; i < seg[c] + s; ++i) {
-            const int32_t j = interval_of(int_lo, n_int, perm[i]);
+            const int32_t j = ic.of(int_lo, n_int, perm[i]);
             if (j != last) {
                 if (last >= 0) {
                     col[o] = last;
