@@ -63,13 +63,13 @@ def fft_tile_flops(offsets, lam, n_r):
 TRAFFIC = {
     # per FP32 tile length n_r (the plan's autotuner picks 8192 or 16384 on this workload)
     "ninv32": dict(source="paper_1408_3048_amd/csrc/toeplitz.hip",
-                   sha256="87ac356097d1d65fdc2655e26c7a623817320722d72e8b175d1baa1589597f48",
-                   by_n_r={8192: dict(fetch_kib=289268.0625, write_kib=65536.0),
-                           16384: dict(fetch_kib=201650.5625, write_kib=65576.5625)},
+                   sha256="9ab08173f4dc73ec1fa3d16f2b82f2e2f56e4022844122e2453dff151f12ec49",
+                   by_n_r={8192: dict(fetch_kib=289529.4375, write_kib=65536.0),
+                           16384: dict(fetch_kib=201937.75, write_kib=65578.5625)},
                    fetch_factor=2.0, write_factor=1.0),
     "pt32": dict(source="paper_1408_3048_amd/csrc/pointing.hip",
                  sha256="e0f93caae0ebdb34ce2935e6498a28231613cee1e45c1a124fab3f6c34a04440",
-                 by_n_r={None: dict(fetch_kib=153646.3125, write_kib=7801.0)},
+                 by_n_r={None: dict(fetch_kib=153637.4375, write_kib=7799.78125)},
                  fetch_factor=2.0, write_factor=1.0),
 }
 

@@ -536,17 +536,18 @@ __global__ __launch_bounds__(kVecThreads) void k_2lvl(
     const int64_t nv = vb.n * NS;
     const TA* azb = az + az_off[vb.b];
     double acc = 0.0;
-    // a thread's pixels q and q + stride go through the column loop together (twice the
-    // loads in flight per column); a missing second pixel reads the first again and is
-    // not stored.  Every per-pixel sum and the order of acc are those of one pixel at a
-    // time.
+    // sparse Z: a thread's pixels q and q + stride go through the column loop together
+    // (twice the loads in flight per column); a missing second pixel reads the first again
+    // and is not stored.  Every per-pixel sum and the order of acc are those of one pixel
+    // at a time.  Dense Z already streams two blocks per column and takes one pixel.
+    constexpr int PX = DZ ? 1 : 2;
     for (int64_t q = (int64_t)vb.k * kVecThreads + threadIdx.x; q < vb.n;
-         q += 2 * vb.stride) {
-        const int64_t q1 = q + vb.stride < vb.n ? q + vb.stride : q;
+         q += PX * vb.stride) {
+        const int64_t q1 = PX == 2 && q + vb.stride < vb.n ? q + vb.stride : q;
         const int64_t qq[2] = {q, q1};
-        double u[2][NS], zw[2][NS];
+        double u[PX][NS], zw[PX][NS];
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < PX; ++j)
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
                 u[j][s] = r[(vb.base + qq[j]) * NS + s];
@@ -556,19 +557,19 @@ __global__ __launch_bounds__(kVecThreads) void k_2lvl(
             const double wc = sw[c];
             const TA* col = azb + (int64_t)c * nv;
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < PX; ++j)
 #pragma unroll
                 for (int s = 0; s < NS; ++s) u[j][s] -= (double)col[qq[j] * NS + s] * wc;
             if constexpr (DZ) {
                 const TA* zc = zd + az_off[vb.b] + (int64_t)c * nv;
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
+                for (int j = 0; j < PX; ++j)
 #pragma unroll
                     for (int s = 0; s < NS; ++s) zw[j][s] += (double)zc[qq[j] * NS + s] * wc;
             }
         }
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < PX; ++j) {
             if (j == 1 && q1 == q) break;
             const int64_t p = vb.base + qq[j];
             double zz[NS];
