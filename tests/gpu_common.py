@@ -57,6 +57,13 @@ def hot_i(seed=39):
     return synth.raster_i(side=8, spp=4, n_pass=72, interval_len=128, lam=16, seed_key=seed)
 
 
+def many_i(seed=43):
+    # I only, 48x48 patch, two identical passes cut into intervals of 16 pixels: 144
+    # distinct Z_S columns, more than the 64 of one tile of the coarse-build transposes
+    # and nine 16-column MFMA tiles per side of E
+    return synth.raster_i(side=48, spp=4, n_pass=2, interval_len=64, lam=16, seed_key=seed)
+
+
 SCANS = {
     "long_iqu": long_iqu,
     "small_iqu": small_iqu,
@@ -64,6 +71,7 @@ SCANS = {
     "cfg1": synth.cfg1_raster_i,
     "strips_i": strips_i,
     "hot_i": hot_i,
+    "many_i": many_i,
 }
 
 

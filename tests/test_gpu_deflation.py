@@ -102,6 +102,34 @@ def test_deflation_property_and_coarse_matrix():
     assert rel(pl.coarse_matrix(), E) <= 1e-11
 
 
+def test_rank_past_one_transpose_tile():
+    """eps_tol above every Ritz value of the recorded run: all 65 Ritz pairs become Z_D,
+    one column more than a tile of the column-to-row transposes feeding the Gram product.
+    The Ritz values follow the oracle's, E_D = Z_D^T A Z_D, and M_2lvl,D A z = z holds for
+    the columns of the second tile."""
+    sc = scan()
+    pr, b = oracle_run()[:2]
+    Bk = pr.bj_blocks()
+    _, al, rz, Zk = O.pcg_lanczos(pr.apply_A, b, lambda r: pr.bj_apply(r, Bk), TOL, 3000)
+    theta, _, _ = O.ritz_pairs(al, rz, Zk)
+    assert theta.shape[0] == 65 and np.max(theta) < 1.5
+    pl = Plan.from_scan(sc)
+    pl.coarse_from_krylov(dev(b), tol=TOL, max_iter=3000, eps_tol=1.5)
+    th = pl.ritz_values()
+    assert th.shape == theta.shape
+    assert np.max(np.abs(th - theta) / theta) <= 1e-8
+    assert pl.coarse_kind() == 2 and pl.coarse_rank() == 65
+    (Z,) = pl.dense_columns()
+    Zn = Z.cpu().numpy().T
+    E = Zn.T @ np.stack([pr.apply_A(Zn[:, i]) for i in range(Zn.shape[1])], axis=1)
+    assert rel(pl.coarse_matrix(), E) <= 1e-11
+    for i in range(60, 65):
+        z = Z[i].contiguous()
+        w = pl.precond_2lvl(pl.apply_A(z))
+        assert rel(w.cpu().numpy(), z.cpu().numpy()) <= 1e-9, i
+    pl.close()
+
+
 def test_second_system_solve_matches_oracle_with_fewer_iterations():
     sc = scan()
     pr, b, x_o, m, th_o, Y_o, est = oracle_run()

@@ -141,7 +141,8 @@ def test_mfma_gemm_layout():
 @pytest.mark.parametrize("name,prec", [("small_iqu", "fp64"), ("small_iqu", "mixed"),
                                        ("ragged_iqu", "mixed"), ("cfg1", "fp64"),
                                        ("strips_i", "fp64"), ("strips_i", "mixed"),
-                                       ("hot_i", "fp64"), ("hot_i", "mixed")])
+                                       ("hot_i", "fp64"), ("hot_i", "mixed"),
+                                       ("many_i", "fp64"), ("many_i", "mixed")])
 def test_two_level_operator(plans, name, prec):
     sc, pr = problem(name)
     pl = plans(name, precision=prec, coarse=True)
