@@ -313,7 +313,21 @@ __device__ __forceinline__ void gemm_tn_wave(const double* __restrict__ A,
     dbl4 acc = {0.0, 0.0, 0.0, 0.0};
     const double* Ap = A + (int64_t)16 * ta + i;
     const double* Bp = B + (int64_t)16 * tb + i;
-    for (int64_t q = q0; q < q1; ++q) {
+    // eight steps' loads in flight before their products (one step at a time, every step
+    // waited for the memory latency); the products keep the order of q
+    int64_t q = q0;
+    for (; q + 8 <= q1; q += 8) {
+        double a[8], b[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t row = 4 * (q + u) + k;
+            a[u] = Ap[row * ra];
+            b[u] = Bp[row * rb];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
+    }
+    for (; q < q1; ++q) {
         const int64_t row = 4 * q + k;
         const double a = Ap[row * ra];
         const double b = Bp[row * rb];
