@@ -229,15 +229,18 @@ __global__ void k_az_int_flags(const int64_t* __restrict__ ptr, const int32_t* _
     }
 }
 
-// the I entries of the columns ucol[0..gridDim.y) into a zeroed packed FP32 map
-// ([n_obs][4] = (I, Q, U, 0)): the values the packing of the expanded vector would give
-__global__ void k_cols_to_packed(const int32_t* __restrict__ ucol, const int64_t* __restrict__ ub,
+// the I entries of the columns ucol[0..gridDim.y) into zeroed packed FP32 maps
+// ([n_obs][4] = (I, Q, U, 0)), column y into map lay[y] - k0 (xp + (lay[y] - k0) xstride):
+// the values the packing of the expanded vector would give
+__global__ void k_cols_to_packed(const int32_t* __restrict__ ucol, const int32_t* __restrict__ lay,
+                                 int32_t k0, int64_t xstride, const int64_t* __restrict__ ub,
                                  const int64_t* __restrict__ ue, const int32_t* __restrict__ rows,
                                  const double* __restrict__ vals, float* __restrict__ xp) {
     const int32_t u = ucol[blockIdx.y];
+    float* x = xp + (int64_t)(lay[blockIdx.y] - k0) * xstride;
     for (int64_t i = ub[u] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ue[u];
          i += (int64_t)gridDim.x * blockDim.x)
-        xp[4 * (int64_t)rows[i]] = (float)vals[i];
+        x[4 * (int64_t)rows[i]] = (float)vals[i];
 }
 
 // copy problem lp[y]'s slice of the map vector y into column `col` of its AZ block
@@ -1207,21 +1210,26 @@ int build_coarse(mm_plan_t pl) {
     DBuf<float> todg, xpg;
     if (mixed) MM_TRY(todg.alloc((size_t)kAzGroup * pl->n_t));
     if (mixed && ns == 3) MM_TRY(xpg.alloc((size_t)kAzGroup * 4 * n_obs));
-    DBuf<int32_t> lcols, lprob;
+    DBuf<int32_t> lcols, lprob, llay;
     MM_TRY(lcols.alloc((size_t)rd_max * B));
     MM_TRY(lprob.alloc((size_t)rd_max * B));
+    MM_TRY(llay.alloc((size_t)rd_max * B));
     {
-        std::vector<int32_t> hc, hp;
+        // the columns by layer: layer k's are [lo_k, lo_k + lcnt[k]) of lcols (problem in
+        // lprob, layer in llay)
+        std::vector<int32_t> hc, hp, hl;
         std::vector<int32_t> lcnt(rd_max, 0);
         for (int32_t k = 0; k < rd_max; ++k)
             for (int b = 0; b < B; ++b)
                 if (ud_off[b] + k < ud_off[b + 1]) {
                     hc.push_back(ud_off[b] + k);
                     hp.push_back(b);
+                    hl.push_back(k);
                     lcnt[k]++;
                 }
         MM_HIP(hipMemcpyAsync(lcols.p, hc.data(), hc.size() * 4, hipMemcpyHostToDevice, st));
         MM_HIP(hipMemcpyAsync(lprob.p, hp.data(), hp.size() * 4, hipMemcpyHostToDevice, st));
+        MM_HIP(hipMemcpyAsync(llay.p, hl.data(), hl.size() * 4, hipMemcpyHostToDevice, st));
         int64_t nb_max = 1;  // largest problem vector
         for (int b = 0; b < B; ++b) nb_max = std::max<int64_t>(nb_max, (oo[b + 1] - oo[b]) * ns);
         const int sgx = (int)std::min<int64_t>(1024, (nb_max + 255) / 256);
@@ -1243,18 +1251,29 @@ int build_coarse(mm_plan_t pl) {
                     MM_HIP(hipMemsetAsync(xpg.p, 0, (size_t)nc * 4 * n_obs * sizeof(float), st));
                 else
                     MM_HIP(hipMemsetAsync(zc.p, 0, (size_t)nc * nv * 8, st));
-                for (int c = 0; c < nc; ++c) {
-                    const int32_t k = k0 + c;
-                    if (ns == 3)
-                        hipLaunchKernelGGL(k_cols_to_packed, dim3(16, lcnt[k]), dim3(256), 0, st,
-                                           lcols.p + lo, dub.p, due.p, crow.p, cval.p,
-                                           xpg.p + (int64_t)c * 4 * n_obs);
-                    else
-                        hipLaunchKernelGGL(k_cols_to_vec, dim3(16, lcnt[k]), dim3(256), 0, st,
-                                           lcols.p + lo, dub.p, due.p, crow.p, cval.p, (int)ns,
-                                           zc.p + (int64_t)c * nv);
+                int64_t gcnt = 0;  // columns of the group's layers
+                for (int c = 0; c < nc; ++c) gcnt += lcnt[k0 + c];
+                if (ns == 3 && gcnt <= 65535) {  // the group's maps in one launch
+                    hipLaunchKernelGGL(k_cols_to_packed, dim3(16, (unsigned)gcnt), dim3(256), 0,
+                                       st, lcols.p + lo, llay.p + lo, k0, (int64_t)4 * n_obs,
+                                       dub.p, due.p, crow.p, cval.p, xpg.p);
                     MM_HIP(hipGetLastError());
-                    lo += lcnt[k];
+                    lo += gcnt;
+                } else {
+                    for (int c = 0; c < nc; ++c) {
+                        const int32_t k = k0 + c;
+                        if (ns == 3)
+                            hipLaunchKernelGGL(k_cols_to_packed, dim3(16, lcnt[k]), dim3(256), 0,
+                                               st, lcols.p + lo, llay.p + lo, k0,
+                                               (int64_t)4 * n_obs, dub.p, due.p, crow.p, cval.p,
+                                               xpg.p);
+                        else
+                            hipLaunchKernelGGL(k_cols_to_vec, dim3(16, lcnt[k]), dim3(256), 0, st,
+                                               lcols.p + lo, dub.p, due.p, crow.p, cval.p,
+                                               (int)ns, zc.p + (int64_t)c * nv);
+                        MM_HIP(hipGetLastError());
+                        lo += lcnt[k];
+                    }
                 }
                 if (ns == 3)
                     MM_TRY(toeplitz_map32_layers(pl, nullptr, 0, xpg.p, 4 * n_obs, todg.p, pl->n_t,
