@@ -129,11 +129,16 @@ def batched_leg(tol, warmup=1):
         t0 = time.perf_counter()
         plan = Plan(pix, w, sc.n_pix, sc.offsets, psd, n_stokes=3, lam=sc.lam, f_samp=sc.f_samp,
                     precision="mixed", coarse=True, problem_intervals=sc.problem_offsets)
+        t1 = time.perf_counter()
         b = plan.rhs(d)
+        t2 = time.perf_counter()
         x, info = plan.pcg_solve(b, precond="2lvl", precision="mixed", tol=tol, max_iter=5000,
                                  history=False)
         torch.cuda.synchronize()
-        tt = time.perf_counter() - t0
+        t3 = time.perf_counter()
+        tt = t3 - t0
+        log(f"batched walls: plan {1e3 * (t1 - t0):.1f} ms, rhs {1e3 * (t2 - t1):.1f} ms, "
+            f"solve {1e3 * (t3 - t2):.1f} ms")
         its = [p["iterations"] for p in info["problems"]]
         res = dict(problems=plan.n_problems, n_samples=sc.n_samples, unknowns=plan.n_vec,
                    time_s=tt, plan_ms=plan.plan_ms, solve_ms=info["solve_ms"],
@@ -143,6 +148,9 @@ def batched_leg(tol, warmup=1):
                    method="mixed two-level PCG, one batched plan, graph-captured iterations")
         log(f"batched {'warmup' if i < warmup else 'timed'}: {tt * 1e3:.1f} ms {res}")
         plan.close()
+        # the outputs are consumed here, so the next iteration's allocations reuse them
+        del plan, b, x, info
+        torch.cuda.synchronize()
     return res
 
 
