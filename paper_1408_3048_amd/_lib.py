@@ -144,6 +144,42 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
+def _validate(*specs):
+    """Raise before any library call unless every (tensor, name, dtypes, numel) in specs is
+    a contiguous tensor of one of dtypes with numel elements (None: any) on a GPU: the
+    library dereferences the raw pointers in its kernels, so a host tensor, a wrong element
+    type or a short buffer would be read or written out of bounds on the device.  Types,
+    lengths and layouts of every argument are checked before their devices."""
+    import torch
+    for t, name, dtypes, numel in specs:
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+        if t.dtype not in dtypes:
+            raise TypeError(f"{name}: dtype {t.dtype} not in {tuple(str(d) for d in dtypes)}")
+        if numel is not None and t.numel() != numel:
+            raise ValueError(f"{name}: {t.numel()} elements, expected {numel}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name}: tensor must be contiguous")
+    for t, name, _, _ in specs:
+        if not t.is_cuda:
+            raise ValueError(f"{name}: tensor must be on the GPU (got device {t.device})")
+
+
+def _check(t, name, dtypes, numel=None):
+    _validate((t, name, dtypes, numel))
+    return t
+
+
+def _f64():
+    import torch
+    return (torch.float64,)
+
+
+def _f32_or_f64():
+    import torch
+    return (torch.float32, torch.float64)
+
+
 def _stream():
     import torch
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
@@ -162,9 +198,23 @@ class Plan:
                  fft_len_f64=0, fft_len_f32=0, problem_intervals=None, graph=True,
                  autotune=False):
         import torch
+        self._h = ctypes.c_void_p()
+        if not isinstance(pix, torch.Tensor) or pix.dim() != 1:
+            raise ValueError("pix: expected a 1-D tensor")
+        specs = [(pix, "pix", (torch.int32,), None)]
+        wdt = MM_F64
+        if weights is not None:
+            specs.append((weights, "weights", _f32_or_f64(), 2 * pix.shape[0]))
+            if isinstance(weights, torch.Tensor) and tuple(weights.shape) != (pix.shape[0], 2):
+                raise ValueError(f"weights: shape {tuple(weights.shape)}, expected "
+                                 f"({pix.shape[0]}, 2)")
+        elif n_stokes != 1:
+            raise ValueError("weights: required for n_stokes = 3")
+        _validate(*specs)
+        if weights is not None:
+            wdt = MM_F64 if weights.dtype == torch.float64 else MM_F32
         L = load()
         self._lib = L
-        self._h = ctypes.c_void_p()
         opts = mm_opts()
         L.mm_default_opts(ctypes.byref(opts))
         opts.n_stokes = n_stokes
@@ -180,12 +230,6 @@ class Plan:
         opts.stream = _stream()
         opts.graph = 1 if graph else 0
         opts.autotune = 1 if autotune else 0
-        assert pix.is_cuda and pix.dtype == torch.int32 and pix.is_contiguous()
-        wdt = MM_F64
-        if weights is not None:
-            assert weights.is_cuda and weights.is_contiguous() and weights.shape == (pix.shape[0], 2)
-            wdt = MM_F64 if weights.dtype == torch.float64 else MM_F32
-            assert weights.dtype in (torch.float32, torch.float64)
         off = np.ascontiguousarray(offsets, dtype=np.int64)
         ps = np.ascontiguousarray(psd, dtype=np.float64).reshape(-1, 3)
         self.n_samples = int(pix.shape[0])
@@ -335,9 +379,18 @@ class Plan:
         import torch
         return torch.empty(self.n_vec, dtype=torch.float64, device="cuda")
 
+    def _map(self, t, name):
+        return (t, name, _f64(), self.n_vec)
+
+    def _tod(self, t, name, dtypes=None):
+        return (t, name, dtypes or _f32_or_f64(), self.n_samples)
+
     def apply_P(self, x, dtype=None):
         import torch
         dtype = dtype or torch.float64
+        _validate(self._map(x, "x"))
+        if dtype not in _f32_or_f64():
+            raise TypeError(f"dtype {dtype} not in (torch.float32, torch.float64)")
         y = torch.empty(self.n_samples, dtype=dtype, device="cuda")
         check(self._lib.mm_apply_P(self._h, _ptr(x), _ptr(y),
                                    MM_F64 if dtype == torch.float64 else MM_F32))
@@ -345,15 +398,16 @@ class Plan:
 
     def apply_Ninv(self, y, precision="fp64"):
         import torch
-        z = torch.empty_like(y)
         p = MM_FP64 if precision == "fp64" else MM_MIXED
         want = torch.float64 if p == MM_FP64 else torch.float32
-        assert y.dtype == want and y.is_contiguous()
+        _validate(self._tod(y, "y", (want,)))
+        z = torch.empty_like(y)
         check(self._lib.mm_apply_Ninv(self._h, _ptr(y), _ptr(z), p))
         return z
 
     def apply_PT(self, z):
         import torch
+        _validate(self._tod(z, "z"))
         x = self._vec()
         check(self._lib.mm_apply_PT(self._h, _ptr(z), MM_F64 if z.dtype == torch.float64 else MM_F32,
                                     _ptr(x)))
@@ -361,28 +415,36 @@ class Plan:
 
     def rhs(self, d):
         import torch
+        _validate(self._tod(d, "d"))
         b = self._vec()
         check(self._lib.mm_rhs(self._h, _ptr(d), MM_F64 if d.dtype == torch.float64 else MM_F32,
                                _ptr(b)))
         return b
 
     def apply_A(self, x, precision="fp64", out=None):
+        _validate(self._map(x, "x"), *([self._map(out, "out")] if out is not None else []))
+        if out is not None:
+            if out.data_ptr() == x.data_ptr():
+                raise ValueError("apply_A: x and out may not alias")
         y = self._vec() if out is None else out
         check(self._lib.mm_apply_A(self._h, _ptr(x), _ptr(y),
                                    MM_FP64 if precision == "fp64" else MM_MIXED))
         return y
 
     def precond_bj(self, r):
+        _validate(self._map(r, "r"))
         z = self._vec()
         check(self._lib.mm_precond_bj(self._h, _ptr(r), _ptr(z)))
         return z
 
     def precond_2lvl(self, r):
+        _validate(self._map(r, "r"))
         z = self._vec()
         check(self._lib.mm_precond_2lvl(self._h, _ptr(r), _ptr(z)))
         return z
 
     def precond_adef2(self, r):
+        _validate(self._map(r, "r"))
         z = self._vec()
         check(self._lib.mm_precond_adef2(self._h, _ptr(r), _ptr(z)))
         return z
@@ -391,6 +453,7 @@ class Plan:
     def lag_correlations(self, u, v):
         """c[j, k], k = 0..lambda: lag cross-correlations of FP64 TOD u, v per interval."""
         import torch
+        _validate(self._tod(u, "u", _f64()), self._tod(v, "v", _f64()))
         c = torch.empty((self.n_intervals, self.lam + 1), dtype=torch.float64, device="cuda")
         check(self._lib.mm_lag_correlations(self._h, _ptr(u), _ptr(v), _ptr(c)))
         return c
@@ -406,7 +469,10 @@ class Plan:
                 grad_d_dtype=None, want_psd=True):
         """(dL/dd, dL/dpsd [K, 3] numpy, mu, info) for g = dL/dm_hat."""
         import torch
+        _validate(self._map(m_hat, "m_hat"), self._map(g, "g"), self._tod(d, "d"))
         grad_d_dtype = grad_d_dtype or d.dtype
+        if grad_d_dtype not in _f32_or_f64():
+            raise TypeError(f"grad_d_dtype {grad_d_dtype} not in (torch.float32, torch.float64)")
         gd = torch.empty(self.n_samples, dtype=grad_d_dtype, device="cuda")
         gp = np.zeros((self.n_intervals, 3), dtype=np.float64)
         mu = torch.empty(self.n_vec, dtype=torch.float64, device="cuda")
@@ -440,6 +506,7 @@ class Plan:
         """Returns (x, info dict); for a batched plan info["problems"] lists the info of
         every problem and the top-level fields are those of problem 0 plus totals."""
         import torch
+        _validate(self._map(b, "b"), *([self._map(x0, "x0")] if x0 is not None else []))
         x = torch.zeros_like(b) if x0 is None else x0.clone()
         infos, hists = self._infos(max_iter, history)
         st = self._lib.mm_pcg_solve(self._h, _ptr(b), _ptr(x),
@@ -474,6 +541,7 @@ class Plan:
         replaces the plan's coarse space with Z_D (Ritz vectors of M_BD A with Ritz value
         below eps_tol).  Returns (x, info dict) like pcg_solve."""
         import torch
+        _validate(self._map(b, "b"))
         x = torch.zeros_like(b)
         infos, hists = self._infos(max_iter, history)
         st = self._lib.mm_coarse_from_krylov(self._h, _ptr(b), _ptr(x), float(tol),
@@ -530,9 +598,18 @@ def lanczos_ritz(alpha, rz, eps_tol=0.2, max_cols=None):
     return theta[:r].copy(), S[:m * r].reshape(m, r).copy()
 
 
+def _validate_gemm(A, B):
+    import torch
+    if (not isinstance(A, torch.Tensor) or not isinstance(B, torch.Tensor) or A.dim() != 2
+            or B.dim() != 2 or A.shape[0] != B.shape[0]):
+        raise ValueError("A and B: expected 2-D tensors [n, ra] and [n, rb]")
+    _validate((A, "A", _f64(), None), (B, "B", _f64(), None))
+
+
 def gemm_tn_f64(A, B):
     """C = A^T B (FP64 matrix cores) for CUDA row-major A [n, ra], B [n, rb]."""
     import torch
+    _validate_gemm(A, B)
     C = torch.empty((A.shape[1], B.shape[1]), dtype=torch.float64, device="cuda")
     check(load().mm_gemm_tn_f64(_stream(), _ptr(A), _ptr(B), A.shape[0], A.shape[1], B.shape[1],
                                 _ptr(C)))

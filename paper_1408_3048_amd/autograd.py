@@ -12,13 +12,15 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from ._lib import Plan
+from ._lib import Plan, _check
 
 
 class GLSMap(torch.autograd.Function):
     @staticmethod
     def forward(ctx, d, psd, geometry, options):
         pix, weights, n_pix, offsets = geometry
+        # checked before the plan is built: the library reads d through its raw pointer
+        _check(d, "d", (torch.float32, torch.float64), int(pix.shape[0]))
         opts = dict(options)
         precond = opts.pop("precond", "bj")
         precision = opts.pop("precision", "fp64")

@@ -370,8 +370,10 @@ int pcg_engine(mm_plan_t pl, const double* b, double* x, const EngineArgs& ea) {
         MM_HIP(hipMemsetAsync(xw, 0, n * 8, st));
         MM_HIP(hipMemcpyAsync(r, b, n * 8, hipMemcpyDeviceToDevice, st));
     } else {
+        // the initial residual of a given x0 is a true residual: FP64 operator for every
+        // precision, so that a start already within tol is judged as the final test would
         MM_HIP(hipMemcpyAsync(xw, x, n * 8, hipMemcpyDeviceToDevice, st));
-        MM_TRY(ea.op32 ? apply_A32(pl, xw, q, nullptr) : apply_A64(pl, xw, q, nullptr));
+        MM_TRY(apply_A64(pl, xw, q, nullptr));
         MM_TRY(vec_residual(pl, b, q, r, all));
     }
     // A-DEF2 starts from x0 + Z E^-1 Z^T (b - A x0) [App. B].  Its equivalence to an SPD
@@ -1079,6 +1081,9 @@ int mm_pcg_solve(mm_plan_t pl, const double* b, double* x, int pc, int precision
     for (int i = 0; i < B; ++i) {
         inf[i].rel_residual = pl->h_sc[i].rel;
         if (status[i] == MM_ERR_NOCONV && inf[i].rel_residual <= tol) status[i] = MM_OK;
+        // the status follows the final FP64 true residual: a problem the engine stopped
+        // on a residual that the FP64 operator does not confirm has not converged
+        if (status[i] == MM_OK && !(inf[i].rel_residual <= tol)) status[i] = MM_ERR_NOCONV;
         if (inf[i].history && inf[i].history_cap > 0) {
             const int m = std::min<int>(inf[i].history_cap, (int)hist_all[i].size());
             for (int k = 0; k < m; ++k) inf[i].history[k] = hist_all[i][k];
