@@ -201,8 +201,8 @@ def multi_rhs_leg(pix, w, sc, psd, m, noise, tol, n_rhs, autotune, krylov_dim=25
 
 
 def knee_leg(tol, knees, autotune, krylov_dim=2048):
-    """Solvers against the knee frequency of the 1/f noise (Sect. 4.2, Fig.
-    deflation_iterations; Sect. 4.3, Fig. overall_time): the 2^22-sample IQU raster (4
+    """Solvers against the knee frequency of the 1/f noise (Sect. 5.1, Fig.
+    deflation_iterations; Sect. 5.2, Fig. overall_time): the 2^22-sample IQU raster (4
     co-pointed detectors + 2 Hz HWP, 256x256 patch, 32 intervals of 2^17, lambda = 2048)
     with every interval's f_knee set to each value (alpha = 2).  For each, the mixed
     block-Jacobi solve; the mixed two-level solve with Z_S, whose construction (the plan's
@@ -257,7 +257,7 @@ def knee_leg(tol, knees, autotune, krylov_dim=2048):
 
 
 def bandwidth_leg(pix, w, sc, psd, m, d, tol, lams, autotune):
-    """The bandwidth study on the same data (Sect. 4.2, Fig. conv_lambda; App. D): for
+    """The bandwidth study on the same data (Sect. 5.1.3, Fig. conv_lambda; App. D): for
     every half-bandwidth lambda (0 = white-noise weighting) a mixed plan with Z_S, then the
     mixed block-Jacobi and two-level solves: iterations, solve time, time per iteration and
     the map's distance from the input sky; the same at lambda = 2048 for the narrower

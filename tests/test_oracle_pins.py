@@ -507,3 +507,74 @@ def test_zero_bandwidth_is_white_noise_weighting():
         Wp = pr.W[s]
         ref[p] = np.linalg.solve(Wp.T @ (w_t[s, None] * Wp), Wp.T @ (w_t[s] * d[s]))
     assert np.linalg.norm(x - ref.ravel()) / np.linalg.norm(ref) <= 1e-11
+
+
+# ------------------------------------------- block conditioning and the symbol bound
+
+def test_bj_rcond_closed_forms():
+    """rcond_1(B) = 1 / (||B||_1 ||B^-1||_1) on blocks whose inverse is known in closed
+    form: diagonal blocks (min/max of the diagonal), and [[a, b, 0], [b, a, 0], [0, 0, a]]
+    with a > b > 0, whose inverse has the 2x2 part [[a, -b], [-b, a]] / (a^2 - b^2), so
+    ||B||_1 = a + b, ||B^-1||_1 = 1 / (a - b) and rcond = (a - b) / (a + b)."""
+    pr = O.Problem.from_scan(tiny_iqu())
+    B = np.zeros((4, 3, 3))
+    B[0] = np.diag([4.0, 2.0, 1.0])
+    B[1] = np.diag([3.0, 3.0, 3.0])
+    a, b = 5.0, 3.0
+    B[2] = [[a, b, 0], [b, a, 0], [0, 0, a]]
+    a2, b2 = 1.0, 1.0 - 1e-6
+    B[3] = [[a2, b2, 0], [b2, a2, 0], [0, 0, a2]]
+    rc = pr.bj_rcond(B)
+    assert rc[0] == pytest.approx(0.25, rel=1e-15)
+    assert rc[1] == pytest.approx(1.0, rel=1e-15)
+    assert rc[2] == pytest.approx((a - b) / (a + b), rel=1e-14)
+    assert rc[3] == pytest.approx((a2 - b2) / (a2 + b2), rel=1e-8)
+
+
+def test_bj_rcond_of_a_pixel_seen_at_four_angles():
+    """A pixel seen once at each of the polariser angles 0, 45, 90, 135 deg (2 phi = 0, 90,
+    180, 270 deg) in an interval with diagonal tap t_0: B_p = t_0 sum_t W_t W_t^T =
+    t_0 diag(4, 2, 2) (eq. stdPrec), so rcond = 1/2 whatever t_0 is."""
+    phi = np.deg2rad([0.0, 45.0, 90.0, 135.0])
+    w = np.stack([np.cos(2 * phi), np.sin(2 * phi)], axis=1)
+    pr = O.Problem(np.zeros(4, dtype=np.int32), w, 3, np.array([0, 4]), [1.3], [0.0], [1.0],
+                   2, 200.0)
+    B = pr.bj_blocks()
+    t0 = pr.taps[0][0]
+    assert t0 == pytest.approx(1.0 / 1.3 ** 2, rel=1e-14)
+    assert np.max(np.abs(B[0] - t0 * np.diag([4.0, 2.0, 2.0]))) <= 1e-15 * t0
+    assert pr.bj_rcond()[0] == pytest.approx(0.5, rel=1e-14)
+
+
+@pytest.mark.parametrize("window,fk,al", [("gauss", 2.0, 2.0), ("rect", 1.0, 1.0),
+                                          ("gauss2", 5.0, 1.5)])
+def test_symbol_bounds_the_spectrum_of_toeplitz_sections(window, fk, al):
+    """taps_symbol against the eigenvalues of an explicit n x n section of the band
+    Toeplitz matrix (not a restatement of its formula): every eigenvalue lies in
+    [min S, max S] and, as n grows, the extreme eigenvalues approach min S and max S
+    (Szego); with n = 4096 >> lambda = 32 they are within 1e-3 of the range.  A symbol
+    with t_0 + sum t_k cos(k theta) (a lost factor 2) fails both bounds; the pointwise
+    values are pinned on the FFT grid by the next test."""
+    lam, n = 32, 4096
+    t = O.toeplitz_taps(2 ** 14, 1.0, fk, al, lam, 200.0, window)
+    s = O.taps_symbol(t, 1 << 16)
+    ev = np.linalg.eigvalsh(O.toeplitz_dense(t, n))
+    span = s.max() - s.min()
+    assert ev.min() >= s.min() - 1e-12 * span
+    assert ev.max() <= s.max() + 1e-12 * span
+    assert ev.min() - s.min() <= 1e-3 * span
+    assert s.max() - ev.max() <= 1e-3 * span
+
+
+def test_symbol_on_the_fft_grid_is_the_dft_of_the_even_row():
+    """On the grid theta_m = 2 pi m / n_r (n_theta = n_r / 2 + 1), taps_symbol equals the
+    real DFT of the even sequence h_0 = t_0, h_k = h_{n_r - k} = t_k: the spectrum an
+    overlap-save convolution of length n_r multiplies by."""
+    t = O.toeplitz_taps(3000, 1.0, 1.5, 1.2, 100, 200.0)
+    nr = 1024
+    h = np.zeros(nr)
+    h[:t.shape[0]] = t
+    h[nr - t.shape[0] + 1:] = t[1:][::-1]
+    H = np.fft.rfft(h).real
+    s = O.taps_symbol(t, nr // 2 + 1)
+    assert np.max(np.abs(s - H)) <= 1e-13 * np.max(np.abs(H))
