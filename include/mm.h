@@ -342,6 +342,23 @@ double mm_plan_time_ms(mm_plan_t plan);
 int mm_gemm_tn_f64(void* stream, const double* A, const double* B, int64_t n, int32_t ra,
                    int32_t rb, double* C);
 
+/* mm_gemm_tn_f64 for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same product with
+ * the same kernels and the same fixed-order sums (bitwise the result of mm_gemm_tn_f64),
+ * with its slab partials in a fixed array of 2^20 FP64 values (8 MiB) that the library
+ * holds on every device it runs on until the process ends, instead of a buffer allocated
+ * per call.  Calls no hipMalloc, hipFree or allocating library routine.
+ *   stream  a hipStream_t of the current device (NULL = default stream); the work is
+ *           enqueued on it and the call returns without synchronising
+ *   A, B, C, n, ra, rb   as mm_gemm_tn_f64
+ * Limit: the partials, ksplit * ra * rb values with ksplit = max(1, min(n / 256,
+ * 4096 / (ra/16 * rb/16))), must fit the array; every product with ra * rb <= 2^20 does.
+ * Calls that overlap on one device share its array and race: order them on one stream.
+ * Returns MM_OK, MM_ERR_ARG (shapes as mm_gemm_tn_f64, partials beyond the limit, a
+ * stream of another device) or MM_ERR_DEVICE. */
+int mm_gemm_tn_f64_noalloc(void* stream, const double* A, const double* B, int64_t n,
+                           int32_t ra, int32_t rb, double* C);
+
 /* Kernel timing with HIP events recorded on the plan's stream around every launch of the
  * hot-path kernels (for measurements; off by default).  enable = 1 starts a fresh window,
  * 0 stops recording.  Kernel ids: MM_K_NINV32 / MM_K_NINV64 (overlap-save N^-1 with the

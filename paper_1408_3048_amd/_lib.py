@@ -38,6 +38,7 @@ EXPORTED = [
     "mm_problem_pixels", "mm_coarse_problem_columns", "mm_fft_lengths", "mm_lag_correlations",
     "mm_tap_derivatives", "mm_adjoint", "mm_coarse_from_krylov", "mm_lanczos_ritz",
     "mm_coarse_kind", "mm_coarse_ritz_values", "mm_coarse_dense_columns", "mm_precond_adef2",
+    "mm_gemm_tn_f64_noalloc",
 ]
 
 
@@ -104,6 +105,7 @@ def load():
         "mm_pcg_solve": (I, [P, P, P, I, I, D, I, ctypes.POINTER(mm_solve_info)]),
         "mm_plan_time_ms": (D, [P]),
         "mm_gemm_tn_f64": (I, [P, P, P, I64, I32, I32, P]),
+        "mm_gemm_tn_f64_noalloc": (I, [P, P, P, I64, I32, I32, P]),
         "mm_profile": (I, [P, I]),
         "mm_profile_read": (I, [P, I, ctypes.POINTER(I64), ctypes.POINTER(D)]),
         "mm_last_error": (ctypes.c_char_p, []),
@@ -613,4 +615,14 @@ def gemm_tn_f64(A, B):
     C = torch.empty((A.shape[1], B.shape[1]), dtype=torch.float64, device="cuda")
     check(load().mm_gemm_tn_f64(_stream(), _ptr(A), _ptr(B), A.shape[0], A.shape[1], B.shape[1],
                                 _ptr(C)))
+    return C
+
+
+def gemm_tn_f64_noalloc(A, B, C):
+    """C = A^T B like gemm_tn_f64 through the allocation-free entry point: C is a
+    caller-owned CUDA FP64 [ra, rb] tensor; the work is enqueued on the current stream."""
+    _validate_gemm(A, B)
+    _validate((C, "C", _f64(), A.shape[1] * B.shape[1]))
+    check(load().mm_gemm_tn_f64_noalloc(_stream(), _ptr(A), _ptr(B), A.shape[0], A.shape[1],
+                                        B.shape[1], _ptr(C)))
     return C

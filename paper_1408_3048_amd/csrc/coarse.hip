@@ -20,6 +20,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <unordered_map>
 
 #include "mm_device.h"
@@ -1014,6 +1015,80 @@ int gemm_tn_f64(hipStream_t st, const double* A, const double* B, int64_t n, int
     MM_HIP(hipGetLastError());
     const int64_t m = (int64_t)ra * rb;
     hipLaunchKernelGGL(k_sum_parts, dim3(grid_for(m)), dim3(256), 0, st, part.p, m, ksplit, dev_C);
+    MM_HIP(hipGetLastError());
+    return MM_OK;
+}
+
+// ---- the E product without allocation: its slab partials live in a fixed device array.
+//
+// The array holds kNoAllocDoubles FP64 values (8 MiB) on every device the library runs
+// on, until the process ends.  Host code never passes the array's name to a kernel (on
+// the host it only stands in for the symbol): the device address comes from
+// hipGetSymbolAddress, taken once per device with that device current and kept per
+// device.  Every call on a device shares that device's array, so calls that overlap on
+// one device race.
+constexpr int64_t kNoAllocDoubles = (int64_t)1 << 20;
+constexpr int kNoAllocMaxDevices = 64;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+namespace {
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kNoAllocMaxDevices] = {};
+}  // namespace
+
+// the device address of the calling thread's current device's array
+int scratch_address(double** out) {
+    int dev = -1;
+    MM_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNoAllocMaxDevices) {
+        set_error("device %d outside the %d devices the fixed scratch supports", dev,
+                  kNoAllocMaxDevices);
+        return MM_ERR_DEVICE;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error("hipGetSymbolAddress of the fixed scratch failed on device %d: %s", dev,
+                      hipGetErrorString(e));
+            return MM_ERR_DEVICE;
+        }
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return MM_OK;
+}
+
+int gemm_tn_f64_noalloc(hipStream_t st, const double* A, const double* B, int64_t n,
+                        int32_t ra, int32_t rb, double* dev_C) {
+    const int32_t ntile = (ra / 16) * (rb / 16);
+    const int32_t ksplit = gram_ksplit(n, ra, rb);
+    const int64_t need = (int64_t)ksplit * ra * rb;
+    if (need > kNoAllocDoubles) {
+        set_error("mm_gemm_tn_f64_noalloc: %lld partial values (ra %d, rb %d, %d slabs) exceed "
+                  "the fixed scratch of %lld FP64 values (ra * rb <= 2^20 always fits)",
+                  (long long)need, ra, rb, ksplit, (long long)kNoAllocDoubles);
+        return MM_ERR_ARG;
+    }
+    if (st) {
+        int sdev = -1, dev = -1;
+        MM_HIP(hipStreamGetDevice(st, &sdev));
+        MM_HIP(hipGetDevice(&dev));
+        if (sdev != dev) {
+            set_error("mm_gemm_tn_f64_noalloc: the stream belongs to device %d, the current "
+                      "device is %d", sdev, dev);
+            return MM_ERR_ARG;
+        }
+    }
+    double* part = nullptr;
+    MM_TRY(scratch_address(&part));
+    const int64_t waves = (int64_t)ntile * ksplit;
+    hipLaunchKernelGGL(k_gemm_tn_f64, dim3((waves + 3) / 4), dim3(256), 0, st, A, B, n, ra, rb,
+                       ksplit, part);
+    MM_HIP(hipGetLastError());
+    const int64_t m = (int64_t)ra * rb;
+    hipLaunchKernelGGL(k_sum_parts, dim3(grid_for(m)), dim3(256), 0, st, part, m, ksplit, dev_C);
     MM_HIP(hipGetLastError());
     return MM_OK;
 }
@@ -2081,3 +2156,14 @@ int coarse_start(mm_plan_t pl, double* x, double* r, const int* mask) {
 }
 
 }  // namespace mm
+
+extern "C" int mm_gemm_tn_f64_noalloc(void* stream, const double* A, const double* B, int64_t n,
+                                      int32_t ra, int32_t rb, double* C) {
+    mm::clear_error();
+    if (!A || !B || !C || n < 4 || n % 4 || ra < 16 || rb < 16 || ra % 16 || rb % 16) {
+        mm::set_error("mm_gemm_tn_f64_noalloc: n must be a positive multiple of 4, ra and rb "
+                      "multiples of 16");
+        return MM_ERR_ARG;
+    }
+    return mm::gemm_tn_f64_noalloc((hipStream_t)stream, A, B, n, ra, rb, C);
+}
