@@ -79,3 +79,48 @@ def rel(a, b):
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def relmax(a, b):
+    """Element-wise error: max |a - b| / max |b|."""
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return np.max(np.abs(a - b)) / np.max(np.abs(b))
+
+
+def check(a, b, bar, what=""):
+    """Both the normwise and the element-wise relative error of a against b within bar."""
+    e_norm, e_max = rel(a, b), relmax(a, b)
+    assert e_norm <= bar and e_max <= bar, (what, e_norm, e_max, bar)
+    return e_norm, e_max
+
+
+def tile_edges(offsets, lam, n_r):
+    """First and last output sample of every overlap-save tile of length n_r: each interval
+    of n samples is cut into ceil(n / (n_r - 2 lam)) tiles of equal length (the last one
+    shorter), as the library's plan lays them out."""
+    out = []
+    lmax = n_r - 2 * lam
+    for a, b in zip(offsets[:-1], offsets[1:]):
+        n = int(b - a)
+        nt = -(-n // lmax)
+        ln = -(-n // nt)
+        for i in range(nt):
+            s, e = int(a) + i * ln, min(int(b), int(a) + (i + 1) * ln)
+            if e > s:
+                out += [s, e - 1]
+    return np.unique(np.asarray(out, dtype=np.int64))
+
+
+def interval_edge_samples(offsets, lam):
+    """Samples next to the hard boundaries of every interval: its first and last sample and
+    the samples lam - 1, lam and lam + 1 away from either end (where the band first reaches
+    past the edge), clipped to the interval."""
+    out = []
+    for a, b in zip(offsets[:-1], offsets[1:]):
+        a, b = int(a), int(b)
+        for d in (0, 1, lam - 1, lam, lam + 1):
+            for t in (a + d, b - 1 - d):
+                if a <= t < b:
+                    out.append(t)
+    return np.unique(np.asarray(out, dtype=np.int64))

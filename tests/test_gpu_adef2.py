@@ -22,7 +22,7 @@ import oracle as O  # noqa: E402
 import synth  # noqa: E402
 from paper_1408_3048_amd import Plan  # noqa: E402
 
-from gpu_common import problem, rel  # noqa: E402
+from gpu_common import check, problem, rel  # noqa: E402
 
 
 def dev(a):
@@ -46,13 +46,14 @@ def test_adef2_operator_zs(name, prec):
     tol = 1e-9 if prec == "fp64" else 1e-4
     for _ in range(2):
         r = rng.standard_normal(pr.n_obs * pr.n_s)
-        assert rel(pl.precond_adef2(dev(r)).cpu().numpy(), C.apply_adef2(r)) <= tol
+        check(pl.precond_adef2(dev(r)).cpu().numpy(), C.apply_adef2(r), tol, "M_alt")
     # on A z for a column z of Z_S: A-DEF2 against the oracle, while A-DEF1 returns z
     j = int(pl.coarse_columns()[0])
     az = pl.apply_A(dev(C.Z[:, j]))
     a2 = pl.precond_adef2(az).cpu().numpy()
-    assert rel(a2, C.apply_adef2(az.cpu().numpy())) <= tol
-    assert rel(pl.precond_2lvl(az).cpu().numpy(), C.Z[:, j]) <= (1e-9 if prec == "fp64" else 1e-4)
+    check(a2, C.apply_adef2(az.cpu().numpy()), tol, "M_alt A z")
+    check(pl.precond_2lvl(az).cpu().numpy(), C.Z[:, j], 1e-9 if prec == "fp64" else 1e-4,
+          "M_2lvl A z")
     pl.close()
 
 
@@ -104,7 +105,7 @@ def test_adef2_with_krylov_coarse_space():
     (Z,) = pl.dense_columns()
     C = O.Coarse(pr, Z.cpu().numpy().T)
     r = np.random.default_rng(8).standard_normal(pr.n_obs * 3)
-    assert rel(pl.precond_adef2(dev(r)).cpu().numpy(), C.apply_adef2(r)) <= 1e-9
+    check(pl.precond_adef2(dev(r)).cpu().numpy(), C.apply_adef2(r), 1e-9, "M_alt Z_D")
     b2 = pr.rhs(np.roll(sc.noise, 12345) + pr.signal(sc.sky))
     xo, ito, st = O.pcg(pr.apply_A, b2, C.apply_adef2, tol=1e-12, maxit=3000,
                         x0=C.adef2_start(b2))

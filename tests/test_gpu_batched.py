@@ -22,7 +22,7 @@ import oracle as O  # noqa: E402
 import synth  # noqa: E402
 from paper_1408_3048_amd import Plan  # noqa: E402
 
-from gpu_common import rel  # noqa: E402
+from gpu_common import check, rel  # noqa: E402
 
 N_PROB = 6
 GEN = dict(n_problems=N_PROB, side=32, n_min=2 ** 13, n_max=2 ** 16, interval_len=2 ** 12,
@@ -94,7 +94,7 @@ def test_batched_operator_vs_oracle():
         xb = torch.zeros(pb.n_vec, dtype=torch.float64, device="cuda")
         xb[off3[b]:off3[b + 1]] = torch.from_numpy(x).cuda()
         y = pb.apply_A(xb).cpu().numpy()
-        assert rel(y[off3[b]:off3[b + 1]], pr.apply_A(x)) <= 1e-12
+        check(y[off3[b]:off3[b + 1]], pr.apply_A(x), 1e-12, f"A problem {b}")
         # other problems' blocks of A x stay zero
         mask = np.ones(y.shape[0], bool)
         mask[off3[b]:off3[b + 1]] = False
@@ -169,7 +169,7 @@ def test_batched_solution_vs_oracle_one_problem():
     pr = O.Problem.from_scan(s1)
     bo = pr.rhs(s1.noise)
     off3 = pb.problem_pixels() * 3
-    assert rel(b_all[off3[k]:off3[k + 1]].cpu().numpy(), bo) <= 1e-12
+    check(b_all[off3[k]:off3[k + 1]].cpu().numpy(), bo, 1e-12, "b")
     xo, _, st = O.pcg(pr.apply_A, bo, pr.bj_apply, tol=1e-13, maxit=5000)
     assert rel(x_all[off3[k]:off3[k + 1]].cpu().numpy(), xo) <= 1e-10
     pb.close()

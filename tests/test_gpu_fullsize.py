@@ -28,6 +28,8 @@ import oracle as O  # noqa: E402
 import synth  # noqa: E402
 from paper_1408_3048_amd import Plan  # noqa: E402
 
+from gpu_common import check, interval_edge_samples, tile_edges  # noqa: E402
+
 
 def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
@@ -39,11 +41,43 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-def _sampled_A(pl, pr, x, pixels, ns):
+def _sampled_A(pl, pr, x, pixels, ns, what):
+    """A x at some pixels, FP64 and FP32 operators, normwise and element by element."""
     ref = pr.apply_A_at(x, pixels)
     y64 = pl.apply_A(dev(x)).cpu().numpy().reshape(-1, ns)[pixels]
     y32 = pl.apply_A(dev(x), precision="mixed").cpu().numpy().reshape(-1, ns)[pixels]
-    return _rel(y64, ref), _rel(y32, ref)
+    e64 = check(y64, ref, 1e-12, f"{what} A fp64")
+    e32 = check(y32, ref, 5e-5, f"{what} A fp32")
+    print(f"[fullsize] {what}: A at {len(pixels)} pixels, fp64 {e64}, fp32 {e32}", flush=True)
+
+
+def _edge_samples(pl, pr, rng, n_random=200):
+    """Sample indices where N^-1 is most likely to go wrong: the first and last output of
+    every overlap-save tile of both operators (tile seams), the samples next to every
+    interval edge (hard zero boundaries), plus random ones."""
+    n64, n32 = pl.fft_lengths()
+    ts = [rng.choice(pr.n_t, n_random, replace=False), interval_edge_samples(pr.offsets, pr.lam)]
+    for n_r in (n64, n32):
+        if n_r:
+            ts.append(tile_edges(pr.offsets, pr.lam, n_r))
+    return np.unique(np.concatenate(ts))
+
+
+def _sampled_ninv(pl, pr, y, ts, what):
+    """N^-1 y at the samples ts, FP64 and FP32 operators, element by element."""
+    z64 = pl.apply_Ninv(dev(y)).cpu().numpy()[ts]
+    e64 = check(z64, O.toeplitz_apply_at(y, pr.offsets, pr.taps, ts), 1e-12, f"{what} N^-1 fp64")
+    y32 = y.astype(np.float32)
+    z32 = pl.apply_Ninv(dev(y32), precision="mixed").cpu().numpy()[ts]
+    ref32 = O.toeplitz_apply_at(y32.astype(np.float64), pr.offsets, pr.taps, ts)
+    e32 = check(z32, ref32, 5e-5, f"{what} N^-1 fp32")
+    print(f"[fullsize] {what}: N^-1 at {len(ts)} samples, fp64 {e64}, fp32 {e32}", flush=True)
+
+
+def _seam_pixels(pr, ts, rng, k):
+    """k pixels observed at some of the samples ts (so that A x there sums tile seams)."""
+    cand = np.unique(pr.cid[ts])
+    return rng.choice(cand, min(k, cand.shape[0]), replace=False)
 
 
 @functools.lru_cache(maxsize=None)
@@ -61,22 +95,19 @@ def test_cfg2_fullsize_layout_operators_and_solution():
     assert np.array_equal(pl.sorted_samples().cpu().numpy(), np.argsort(pr.cid, kind="stable"))
     rng = np.random.default_rng(40)
     x = rng.standard_normal(pr.n_obs * pr.n_s)
-    pixels = np.concatenate([rng.choice(pr.n_obs, 30, replace=False), [0, pr.n_obs - 1]])
-    e64, e32 = _sampled_A(pl, pr, x, pixels, 3)
-    assert e64 <= 1e-11 and e32 <= 5e-5, (e64, e32)
-    # N^-1 (FP64, FP32) at sampled samples, b = P^T N^-1 d at sampled pixels
     d = sc.noise
-    ts = np.sort(rng.choice(pr.n_t, 200, replace=False))
-    zr = O.toeplitz_apply_at(d, pr.offsets, pr.taps, ts)
-    assert _rel(pl.apply_Ninv(dev(d)).cpu().numpy()[ts], zr) <= 1e-11
-    d32 = d.astype(np.float32)
-    z32 = pl.apply_Ninv(dev(d32), precision="mixed").cpu().numpy()[ts]
-    assert _rel(z32, O.toeplitz_apply_at(d32.astype(np.float64), pr.offsets, pr.taps, ts)) <= 5e-5
+    ts = _edge_samples(pl, pr, rng)
+    pixels = np.unique(np.concatenate([rng.choice(pr.n_obs, 30, replace=False),
+                                       [0, pr.n_obs - 1], _seam_pixels(pr, ts, rng, 48)]))
+    _sampled_A(pl, pr, x, pixels, 3, "2^24 raster")
+    # N^-1 (FP64, FP32) at tile seams, interval edges and random samples
+    _sampled_ninv(pl, pr, d, ts, "2^24 raster")
+    # b = P^T N^-1 d at sampled pixels
     b = pl.rhs(dev(d)).cpu().numpy().reshape(-1, 3)
     bref = np.stack([pr.W[np.nonzero(pr.cid == p)[0]].T @
                      O.toeplitz_apply_at(d, pr.offsets, pr.taps, np.nonzero(pr.cid == p)[0])
                      for p in pixels])
-    assert _rel(b[pixels], bref) <= 1e-11
+    check(b[pixels], bref, 1e-12, "2^24 raster b")
     # noiseless data: the FP64 two-level solve and the mixed solve return the input map
     m = pr.sky_to_compact(sc.sky)
     dn = pl.apply_P(dev(m))
@@ -98,10 +129,12 @@ def test_ring_share_fullsize_sampled_operator():
     assert np.array_equal(pl.hits().cpu().numpy(), pr.s)
     rng = np.random.default_rng(41)
     x = rng.standard_normal(pr.n_obs * pr.n_s)
-    pixels = np.concatenate([rng.choice(pr.n_obs, 24, replace=False),
-                             [int(np.argmax(pr.s)), int(np.argmin(pr.s))]])
-    e64, e32 = _sampled_A(pl, pr, x, pixels, 3)
-    assert e64 <= 1e-11 and e32 <= 5e-5, (e64, e32)
+    ts = _edge_samples(pl, pr, rng)
+    pixels = np.unique(np.concatenate([rng.choice(pr.n_obs, 24, replace=False),
+                                       [int(np.argmax(pr.s)), int(np.argmin(pr.s))],
+                                       _seam_pixels(pr, ts, rng, 24)]))
+    _sampled_A(pl, pr, x, pixels, 3, "ring share")
+    _sampled_ninv(pl, pr, rng.standard_normal(pr.n_t), ts, "ring share")
     pl.close()
 
 
@@ -122,8 +155,8 @@ def test_batched_fullsize_sampled_operator():
         xb = x[off3[b]:off3[b + 1]]
         pixels = rng.choice(pr.n_obs, 12, replace=False)
         ref = pr.apply_A_at(xb, pixels)
-        assert _rel(y64[off3[b]:off3[b + 1]].reshape(-1, 3)[pixels], ref) <= 1e-11, b
-        assert _rel(y32[off3[b]:off3[b + 1]].reshape(-1, 3)[pixels], ref) <= 5e-5, b
+        check(y64[off3[b]:off3[b + 1]].reshape(-1, 3)[pixels], ref, 1e-12, f"problem {b} fp64")
+        check(y32[off3[b]:off3[b + 1]].reshape(-1, 3)[pixels], ref, 5e-5, f"problem {b} fp32")
     pl.close()
 
 
@@ -133,9 +166,11 @@ def test_cfg5_fullsize_sampled_operator():
     pl = Plan.from_scan(sc, precision="mixed", coarse=True, autotune=True)
     rng = np.random.default_rng(43)
     x = rng.standard_normal(pr.n_obs * pr.n_s)
-    pixels = rng.choice(pr.n_obs, 24, replace=False)
-    e64, e32 = _sampled_A(pl, pr, x, pixels, 3)
-    assert e64 <= 1e-11 and e32 <= 5e-5, (e64, e32)
+    ts = _edge_samples(pl, pr, rng)
+    pixels = np.unique(np.concatenate([rng.choice(pr.n_obs, 24, replace=False),
+                                       _seam_pixels(pr, ts, rng, 24)]))
+    _sampled_A(pl, pr, x, pixels, 3, "2^22 raster")
+    _sampled_ninv(pl, pr, rng.standard_normal(pr.n_t), ts, "2^22 raster")
     pl.close()
 
 
