@@ -98,9 +98,19 @@ typedef struct {
                           launches on the caller's stream */
     int autotune;      /* 1: mm_plan times the candidate FFT lengths on the plan's own data
                           and keeps the fastest (when fft_len_* is 0); 0 (default): cost model */
+    int az_fp16;       /* mixed plans with Z_S: 1 (default) the two-level (A-DEF1) apply reads
+                          AZ in FP16 with a power-of-two scale per column (half the bytes of
+                          FP32; each entry rounded once, relative error <= 2^-11); 0: FP32.
+                          E, A-DEF2 and the coarse start keep the FP32 AZ */
+    int pt_range;      /* samples per work range of the P^T segmented reduction (a wave takes
+                          the whole pixels starting in its range), a power of two in
+                          [256, 65536]; 0 = automatic: 2048, or with autotune the fastest of
+                          1024 / 2048 / 4096 timed on the plan's own data.  Results depend on
+                          it at rounding level (the order of additions within a pixel) */
 } mm_opts;
 
-/* Fill *opts with the defaults above (n_stokes 3, lambda 1024, f_samp 200, graph 1). */
+/* Fill *opts with the defaults above (n_stokes 3, lambda 1024, f_samp 200, graph 1,
+ * az_fp16 1). */
 void mm_default_opts(mm_opts* opts);
 
 /* Build a plan for one problem [Sect. 2, Sect. 3, App. C]; the same as mm_plan_batched
@@ -296,6 +306,10 @@ int64_t mm_coarse_dense_columns(mm_plan_t plan, double* dev_out);
 /* FFT lengths (real samples per overlap-save tile) the plan uses for the FP64 and the
  * FP32 operator (0 for an operator the plan does not have). */
 int mm_fft_lengths(mm_plan_t plan, int* n_r_f64, int* n_r_f32);
+
+/* Samples per P^T work range the plan uses (opts.pt_range, or the autotuned / default
+ * value), or a negative status. */
+int mm_pt_range(mm_plan_t plan);
 
 /* ----- adjoint (gradients of a loss of the map) ----- */
 

@@ -38,7 +38,7 @@ EXPORTED = [
     "mm_problem_pixels", "mm_coarse_problem_columns", "mm_fft_lengths", "mm_lag_correlations",
     "mm_tap_derivatives", "mm_adjoint", "mm_coarse_from_krylov", "mm_lanczos_ritz",
     "mm_coarse_kind", "mm_coarse_ritz_values", "mm_coarse_dense_columns", "mm_precond_adef2",
-    "mm_gemm_tn_f64_noalloc",
+    "mm_gemm_tn_f64_noalloc", "mm_pt_range",
 ]
 
 
@@ -57,7 +57,8 @@ class mm_opts(ctypes.Structure):
                 ("window", ctypes.c_int), ("precision", ctypes.c_int), ("coarse", ctypes.c_int),
                 ("rank_tol", ctypes.c_double), ("rcond_min", ctypes.c_double),
                 ("fft_len_f64", ctypes.c_int), ("fft_len_f32", ctypes.c_int),
-                ("stream", ctypes.c_void_p), ("graph", ctypes.c_int), ("autotune", ctypes.c_int)]
+                ("stream", ctypes.c_void_p), ("graph", ctypes.c_int), ("autotune", ctypes.c_int),
+                ("az_fp16", ctypes.c_int), ("pt_range", ctypes.c_int)]
 
 
 class mm_solve_info(ctypes.Structure):
@@ -106,6 +107,7 @@ def load():
         "mm_plan_time_ms": (D, [P]),
         "mm_gemm_tn_f64": (I, [P, P, P, I64, I32, I32, P]),
         "mm_gemm_tn_f64_noalloc": (I, [P, P, P, I64, I32, I32, P]),
+        "mm_pt_range": (I, [P]),
         "mm_profile": (I, [P, I]),
         "mm_profile_read": (I, [P, I, ctypes.POINTER(I64), ctypes.POINTER(D)]),
         "mm_last_error": (ctypes.c_char_p, []),
@@ -198,7 +200,7 @@ class Plan:
     def __init__(self, pix, weights, n_pix, offsets, psd, *, n_stokes=3, lam=1024, f_samp=200.0,
                  window="gauss", precision="fp64", coarse=False, rank_tol=1e-10, rcond_min=1e-8,
                  fft_len_f64=0, fft_len_f32=0, problem_intervals=None, graph=True,
-                 autotune=False):
+                 autotune=False, az_fp16=True, pt_range=0):
         import torch
         self._h = ctypes.c_void_p()
         if not isinstance(pix, torch.Tensor) or pix.dim() != 1:
@@ -232,6 +234,8 @@ class Plan:
         opts.stream = _stream()
         opts.graph = 1 if graph else 0
         opts.autotune = 1 if autotune else 0
+        opts.az_fp16 = 1 if az_fp16 else 0
+        opts.pt_range = int(pt_range)
         off = np.ascontiguousarray(offsets, dtype=np.int64)
         ps = np.ascontiguousarray(psd, dtype=np.float64).reshape(-1, 3)
         self.n_samples = int(pix.shape[0])
@@ -329,6 +333,12 @@ class Plan:
         a, b = ctypes.c_int(), ctypes.c_int()
         check(self._lib.mm_fft_lengths(self._h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
+
+    def pt_range(self):
+        """Samples per P^T work range of the plan."""
+        v = self._lib.mm_pt_range(self._h)
+        check(min(v, 0))
+        return v
 
     def problem_pixels(self):
         """Host int64 [B+1]: first compact pixel of every problem."""

@@ -530,6 +530,7 @@ void mm_default_opts(mm_opts* o) {
     o->stream = nullptr;
     o->graph = 1;
     o->autotune = 0;
+    o->az_fp16 = 1;
 }
 
 int mm_plan(mm_plan_t* out, int64_t n_samples, const int32_t* pix, const void* weights,
@@ -616,9 +617,13 @@ int mm_plan_batched(mm_plan_t* out, int32_t n_problems, const int32_t* problem_i
     if (opts->lambda < 0 || !(opts->f_samp > 0.0) || opts->window < 0 || opts->window > 2 ||
         (opts->precision != MM_FP64 && opts->precision != MM_MIXED) ||
         (opts->coarse != MM_COARSE_NONE && opts->coarse != MM_COARSE_ZS) ||
-        !(opts->rank_tol > 0.0) || !(opts->rcond_min >= 0.0)) {
+        !(opts->rank_tol > 0.0) || !(opts->rcond_min >= 0.0) ||
+        (opts->az_fp16 != 0 && opts->az_fp16 != 1) ||
+        (opts->pt_range != 0 && (opts->pt_range < 256 || opts->pt_range > 65536 ||
+                                 (opts->pt_range & (opts->pt_range - 1))))) {
         set_error("invalid mm_opts (lambda >= 0, f_samp > 0, window/precision/coarse enums, "
-                  "rank_tol > 0, rcond_min >= 0)");
+                  "rank_tol > 0, rcond_min >= 0, az_fp16 0 or 1, pt_range 0 or a power of two "
+                  "in [256, 65536])");
         return MM_ERR_ARG;
     }
     mm_plan_s* pl = new mm_plan_s();
@@ -666,6 +671,10 @@ int mm_plan_batched(mm_plan_t* out, int32_t n_problems, const int32_t* problem_i
                              : build_tiling(pl, pl->fft32, false, opts->fft_len_f32)) != MM_OK)
         return fail(s);
     tick("tiling32");
+    // the P^T work ranges before anything that sums over them (block-Jacobi blocks, A Z)
+    if (opts->autotune && opts->pt_range == 0 && (s = tune_pt_range(pl)) != MM_OK)
+        return fail(s);
+    tick("pt_range");
     if ((s = build_bj(pl)) != MM_OK) return fail(s);
     tick("bj");
     const int64_t n = pl->n_obs * pl->n_s;
@@ -1285,6 +1294,15 @@ int mm_fft_lengths(mm_plan_t pl, int* n64, int* n32) {
     *n64 = pl->fft64.n_r;
     *n32 = pl->opts.precision == MM_MIXED ? pl->fft32.n_r : 0;
     return MM_OK;
+}
+
+int mm_pt_range(mm_plan_t pl) {
+    clear_error();
+    if (!pl) {
+        set_error("plan is NULL");
+        return MM_ERR_ARG;
+    }
+    return (int)pl->pt_range;
 }
 
 int mm_profile(mm_plan_t pl, int enable) {

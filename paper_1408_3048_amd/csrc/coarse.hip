@@ -23,6 +23,8 @@
 #include <mutex>
 #include <unordered_map>
 
+#include <hip/hip_fp16.h>
+
 #include "mm_device.h"
 
 namespace mm {
@@ -258,16 +260,35 @@ __global__ void k_store_az(const int32_t* __restrict__ lp, const double* __restr
         dst[i] = (TA)y[v0 + i];
 }
 
-// copy n[c] values from src + so[c] to dst + d_o[c] for every column c = blockIdx.y
+// copy n[c] values from src + so[c] to dst + d_o[c] for every column c = blockIdx.y; with
+// mx != nullptr also the column's largest |value| into mx[c] as FP32 bits (non-negative
+// floats order like their bit patterns; mx starts at zero): one atomic max per block
 template <typename TA>
-__global__ void k_copy_cols(const TA* __restrict__ src, TA* __restrict__ dst,
-                            const int64_t* __restrict__ so, const int64_t* __restrict__ d_o,
-                            const int64_t* __restrict__ n) {
+__global__ __launch_bounds__(256) void k_copy_cols(const TA* __restrict__ src,
+                                                   TA* __restrict__ dst,
+                                                   const int64_t* __restrict__ so,
+                                                   const int64_t* __restrict__ d_o,
+                                                   const int64_t* __restrict__ n,
+                                                   unsigned* __restrict__ mx) {
+    __shared__ float red[4];
     const int32_t c = blockIdx.y;
     const int64_t a = so[c], d = d_o[c], m = n[c];
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
-         i += (int64_t)gridDim.x * blockDim.x)
-        dst[d + i] = src[a + i];
+    float am = 0.0f;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * 256) {
+        const TA v = src[a + i];
+        dst[d + i] = v;
+        am = fmaxf(am, fabsf((float)v));
+    }
+    if (!mx) return;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) am = fmaxf(am, __shfl_xor(am, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = am;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        am = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+        if (am > 0.0f) atomicMax(mx + c, __float_as_uint(am));
+    }
 }
 
 // Z_S rows restricted to the kept columns: count pass (out == nullptr) or fill pass
@@ -534,6 +555,34 @@ __global__ __launch_bounds__(256) void k_einv(const double* __restrict__ Einv,
     if (lane == 0) w[a] = s;
 }
 
+// FP16 copy of the kept AZ columns for the A-DEF1 apply.  Column a (blockIdx.y) as
+// entry / scale[a], scale[a] = 2^(e - 14) for the column's largest |entry| mx[a] < 2^e (1 for
+// a zero column): scaled entries stay below 2^14, far from FP16's 65504 limit, the
+// power-of-two scaling is exact, and every entry is rounded once.  Entries [len[a], ld[a])
+// of the column (the pixel-pair padding) are zero.
+__global__ __launch_bounds__(256) void k_az_to_half(const float* __restrict__ az,
+                                                    const int64_t* __restrict__ src_off,
+                                                    const int64_t* __restrict__ len,
+                                                    const int64_t* __restrict__ dst_off,
+                                                    const int64_t* __restrict__ ld,
+                                                    const unsigned* __restrict__ mx,
+                                                    double* __restrict__ scale,
+                                                    uint16_t* __restrict__ out) {
+    const int a = blockIdx.y;
+    const float* col = az + src_off[a];
+    uint16_t* dst = out + dst_off[a];
+    const float m = __uint_as_float(mx[a]);
+    int e = 0;
+    if (m > 0.0f) (void)frexpf(m, &e);  // m < 2^e
+    const float inv = m > 0.0f ? ldexpf(1.0f, 14 - e) : 1.0f;  // a power of two: exact
+    if (blockIdx.x == 0 && threadIdx.x == 0) scale[a] = m > 0.0f ? ldexp(1.0, e - 14) : 1.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < ld[a];
+         i += (int64_t)gridDim.x * 256) {
+        const float v = i < len[a] ? col[i] * inv : 0.0f;
+        dst[i] = __half_as_ushort(__float2half_rn(v));
+    }
+}
+
 // z = M_BD (r - AZ w) + Z w per pixel of every masked problem, partials of r^T z.
 // DZ: Z is dense (Z_D blocks laid out like AZ, every Stokes row); else the sparse Z_S rows
 // (I rows only) in CSR form.
@@ -607,6 +656,92 @@ __global__ __launch_bounds__(kVecThreads) void k_2lvl(
                 for (int64_t e = zptr[p]; e < zptr[p + 1]; ++e) zs += zval[e] * sw[zcol[e] - c0];
                 zz[0] += zs;
             }
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                z[p * NS + s] = zz[s];
+                acc += r[p * NS + s] * zz[s];
+            }
+        }
+    }
+    if (ctl.part) write_partial_at(acc, slot_part(ctl, kSlotRZ, vb.b), vb.k, red);
+}
+
+// k_2lvl for sparse Z_S with AZ in FP16 (the az_fp16 layout): z = M_BD (r - AZ w) + Z w.
+// A thread takes two adjacent pixels, whose 2 n_s FP16 entries of a column are one aligned
+// 4- or 12-byte load; the column scales are folded into w (exact: powers of two).  Per
+// pixel the sums run over the columns in order, in FP64, as in k_2lvl.
+template <int NS>
+__global__ __launch_bounds__(kVecThreads) void k_2lvl16(
+    const double* __restrict__ r, double* __restrict__ z, const double* __restrict__ bj,
+    const uint16_t* __restrict__ az16, const int64_t* __restrict__ az16_off,
+    const double* __restrict__ az_scale, const int32_t* __restrict__ col_off,
+    const double* __restrict__ w, const int64_t* __restrict__ zptr,
+    const int32_t* __restrict__ zcol, const double* __restrict__ zval, PcgCtl ctl) {
+    __shared__ double red[kVecThreads];
+    extern __shared__ double sw[];  // [2 r_max]: w, and w times the column scales
+    const VecBlock vb = vec_block(ctl, NS, false);
+    if (ctl.mask && !ctl.mask[vb.b]) return;
+    const int32_t c0 = col_off[vb.b], rk = col_off[vb.b + 1] - c0;
+    double* swa = sw + rk;
+    for (int c = threadIdx.x; c < rk; c += kVecThreads) {
+        const double wc = w[c0 + c];
+        sw[c] = wc;
+        swa[c] = wc * az_scale[c0 + c];
+    }
+    __syncthreads();
+    const int64_t ld = rk > 0 ? (az16_off[vb.b + 1] - az16_off[vb.b]) / rk : 0;
+    const uint16_t* azb = az16 + az16_off[vb.b];
+    const int64_t npair = (vb.n + 1) / 2;
+    double acc = 0.0;
+    for (int64_t jp = (int64_t)vb.k * kVecThreads + threadIdx.x; jp < npair; jp += vb.stride) {
+        const int64_t q0 = 2 * jp;
+        const bool two = q0 + 1 < vb.n;
+        const int64_t qq[2] = {q0, two ? q0 + 1 : q0};
+        double u[2][NS];
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int s = 0; s < NS; ++s) u[j][s] = r[(vb.base + qq[j]) * NS + s];
+        const uint16_t* pe = azb + 2 * NS * jp;
+        for (int32_t c = 0; c < rk; ++c) {
+            const double wc = swa[c];
+            float f[2 * NS];
+            if constexpr (NS == 3) {
+                const uint3 raw = *reinterpret_cast<const uint3*>(pe + (int64_t)c * ld);
+                const uint32_t wd[3] = {raw.x, raw.y, raw.z};
+#pragma unroll
+                for (int h = 0; h < 3; ++h) {
+                    const float2 v = __half22float2(__builtin_bit_cast(__half2, wd[h]));
+                    f[2 * h] = v.x;
+                    f[2 * h + 1] = v.y;
+                }
+            } else {
+                const uint32_t raw = *reinterpret_cast<const uint32_t*>(pe + (int64_t)c * ld);
+                const float2 v = __half22float2(__builtin_bit_cast(__half2, raw));
+                f[0] = v.x;
+                f[1] = v.y;
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int s = 0; s < NS; ++s) u[j][s] -= (double)f[NS * j + s] * wc;
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            if (j == 1 && !two) break;
+            const int64_t p = vb.base + qq[j];
+            double zz[NS];
+            if constexpr (NS == 1) {
+                zz[0] = bj[p] * u[j][0];
+            } else {
+                const double* m = bj + 6 * p;
+                zz[0] = m[0] * u[j][0] + m[1] * u[j][1] + m[2] * u[j][2];
+                zz[1] = m[1] * u[j][0] + m[3] * u[j][1] + m[4] * u[j][2];
+                zz[2] = m[2] * u[j][0] + m[4] * u[j][1] + m[5] * u[j][2];
+            }
+            double zs = 0.0;
+            for (int64_t e = zptr[p]; e < zptr[p + 1]; ++e) zs += zval[e] * sw[zcol[e] - c0];
+            zz[0] += zs;
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
                 z[p * NS + s] = zz[s];
@@ -1524,18 +1659,61 @@ int build_coarse(mm_plan_t pl) {
         MM_HIP(hipMemcpyAsync(dso.p, so.data(), keff * 8, hipMemcpyHostToDevice, st));
         MM_HIP(hipMemcpyAsync(ddo.p, d_o.data(), keff * 8, hipMemcpyHostToDevice, st));
         MM_HIP(hipMemcpyAsync(dcn.p, cn.data(), keff * 8, hipMemcpyHostToDevice, st));
+        // the FP16 copy of AZ for the A-DEF1 apply of mixed plans (column maxima taken by the
+        // copy into AZ32)
+        const bool fp16 = mixed && pl->opts.az_fp16 && keff > 0;
+        DBuf<unsigned> dmx;
+        if (fp16) {
+            MM_TRY(dmx.alloc(keff));
+            MM_HIP(hipMemsetAsync(dmx.p, 0, keff * sizeof(unsigned), st));
+        }
         if (mixed) {
             MM_TRY(co.AZ32.alloc((size_t)co.h_az_off[B]));
             hipLaunchKernelGGL(k_copy_cols<float>, dim3(64, keff), dim3(256), 0, st,
                                (const float*)azf.p, co.AZ32.p, (const int64_t*)dso.p,
-                               (const int64_t*)ddo.p, (const int64_t*)dcn.p);
+                               (const int64_t*)ddo.p, (const int64_t*)dcn.p, dmx.p);
         } else {
             MM_TRY(co.AZ64.alloc((size_t)co.h_az_off[B]));
             hipLaunchKernelGGL(k_copy_cols<double>, dim3(64, keff), dim3(256), 0, st,
                                (const double*)azd.p, co.AZ64.p, (const int64_t*)dso.p,
-                               (const int64_t*)ddo.p, (const int64_t*)dcn.p);
+                               (const int64_t*)ddo.p, (const int64_t*)dcn.p, nullptr);
         }
         MM_HIP(hipGetLastError());
+        if (fp16) {
+            // FP16 copy for the A-DEF1 apply: pixel pairs, columns padded to 8 entries
+            std::vector<int64_t> h16(B + 1, 0), lenv(keff), dof(keff), ldv(keff);
+            for (int b = 0; b < B; ++b) {
+                const int64_t pix_b = oo[b + 1] - oo[b];
+                const int64_t ld = (ns * 2 * ((pix_b + 1) / 2) + 7) / 8 * 8;
+                const int32_t r_b = co.h_col_off[b + 1] - co.h_col_off[b];
+                for (int32_t i = 0; i < r_b; ++i) {
+                    const int32_t a = co.h_col_off[b] + i;
+                    lenv[a] = pix_b * ns;
+                    dof[a] = h16[b] + (int64_t)i * ld;
+                    ldv[a] = ld;
+                }
+                h16[b + 1] = h16[b] + (int64_t)r_b * ld;
+            }
+            DBuf<int64_t> dlen, ddof, dld;
+            MM_TRY(dlen.alloc(keff));
+            MM_TRY(ddof.alloc(keff));
+            MM_TRY(dld.alloc(keff));
+            MM_TRY(co.AZ16.alloc((size_t)h16[B]));
+            MM_TRY(co.az16_off.alloc(B + 1));
+            MM_TRY(co.az16_scale.alloc(keff));
+            MM_HIP(hipMemcpyAsync(dlen.p, lenv.data(), keff * 8, hipMemcpyHostToDevice, st));
+            MM_HIP(hipMemcpyAsync(ddof.p, dof.data(), keff * 8, hipMemcpyHostToDevice, st));
+            MM_HIP(hipMemcpyAsync(dld.p, ldv.data(), keff * 8, hipMemcpyHostToDevice, st));
+            MM_HIP(hipMemcpyAsync(co.az16_off.p, h16.data(), (B + 1) * 8, hipMemcpyHostToDevice,
+                                  st));
+            hipLaunchKernelGGL(k_az_to_half, dim3(64, keff), dim3(256), 0, st,
+                               (const float*)co.AZ32.p, (const int64_t*)ddo.p,
+                               (const int64_t*)dlen.p, (const int64_t*)ddof.p,
+                               (const int64_t*)dld.p, (const unsigned*)dmx.p, co.az16_scale.p,
+                               co.AZ16.p);
+            MM_HIP(hipGetLastError());
+            MM_HIP(hipStreamSynchronize(st));
+        }
         MM_HIP(hipStreamSynchronize(st));
     }
     azf.release();
@@ -1831,19 +2009,19 @@ int build_coarse_dense(mm_plan_t pl, const double* basis, int64_t basis_stride,
             MM_TRY(faz32.alloc((size_t)az_off[B]));
             hipLaunchKernelGGL(k_copy_cols<float>, g, dim3(256), 0, st, (const float*)zd32.p,
                                fz32.p, (const int64_t*)dso.p, (const int64_t*)ddo.p,
-                               (const int64_t*)dcn.p);
+                               (const int64_t*)dcn.p, nullptr);
             hipLaunchKernelGGL(k_copy_cols<float>, g, dim3(256), 0, st, (const float*)az32.p,
                                faz32.p, (const int64_t*)dso.p, (const int64_t*)ddo.p,
-                               (const int64_t*)dcn.p);
+                               (const int64_t*)dcn.p, nullptr);
         } else {
             MM_TRY(fz64.alloc((size_t)az_off[B]));
             MM_TRY(faz64.alloc((size_t)az_off[B]));
             hipLaunchKernelGGL(k_copy_cols<double>, g, dim3(256), 0, st, (const double*)zd64.p,
                                fz64.p, (const int64_t*)dso.p, (const int64_t*)ddo.p,
-                               (const int64_t*)dcn.p);
+                               (const int64_t*)dcn.p, nullptr);
             hipLaunchKernelGGL(k_copy_cols<double>, g, dim3(256), 0, st, (const double*)az64.p,
                                faz64.p, (const int64_t*)dso.p, (const int64_t*)ddo.p,
-                               (const int64_t*)dcn.p);
+                               (const int64_t*)dcn.p, nullptr);
         }
         MM_HIP(hipGetLastError());
         MM_HIP(hipStreamSynchronize(st));
@@ -1909,6 +2087,9 @@ int build_coarse_dense(mm_plan_t pl, const double* basis, int64_t basis_stride,
     co.n_chunks = choff[B];
     co.AZ64.swap(faz64);
     co.AZ32.swap(faz32);
+    co.AZ16.release();
+    co.az16_off.release();
+    co.az16_scale.release();
     co.ZD64.swap(fz64);
     co.ZD32.swap(fz32);
     co.csr_ptr.release();
@@ -2013,6 +2194,18 @@ int twolvl_apply(mm_plan_t pl, const double* r, double* z, const PcgCtl& ctl) {
                        co.col_off.p, co.col_prob.p, co.vpart.p, co.vslice.p, k, co.w.p, ctl.mask);
     const size_t shm = (size_t)co.r_max * sizeof(double);
     const dim3 g(pl->n_pblk), t(kVecThreads);
+    if (co.AZ16.p) {
+        if (pl->n_s == 3)
+            hipLaunchKernelGGL((k_2lvl16<3>), g, t, 2 * shm, st, r, z, pl->bj.p, co.AZ16.p,
+                               co.az16_off.p, co.az16_scale.p, co.col_off.p, co.w.p,
+                               co.csr_ptr.p, co.csr_col.p, co.csr_val.p, ctl);
+        else
+            hipLaunchKernelGGL((k_2lvl16<1>), g, t, 2 * shm, st, r, z, pl->bj.p, co.AZ16.p,
+                               co.az16_off.p, co.az16_scale.p, co.col_off.p, co.w.p,
+                               co.csr_ptr.p, co.csr_col.p, co.csr_val.p, ctl);
+        MM_HIP(hipGetLastError());
+        return MM_OK;
+    }
     if (pl->n_s == 3) {
         if (co.AZ32.p)
             hipLaunchKernelGGL((k_2lvl<float, 3, false>), g, t, shm, st, r, z, pl->bj.p, co.AZ32.p,

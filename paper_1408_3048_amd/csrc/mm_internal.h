@@ -78,6 +78,20 @@ struct DBuf {
 // ---------------------------------------------------------------- overlap-save tiling
 // One FFT configuration (per precision): tiles of L_max outputs read a window of
 // L + 2 lambda samples into a real buffer of n_r = 2^(logm+1) points.
+// Workgroups of a launch are dispatched to the chip's kXcds XCDs round-robin by their
+// linear index, and each XCD has its own L2.  A launch of n work items (tiles, wave groups)
+// over xcd_grid(n) blocks maps block b to item xcd_item(b, n): XCD x (= b mod kXcds) takes
+// the contiguous items [x n / kXcds, (x + 1) n / kXcds) (balanced to within one), in order,
+// so neighbouring items, which share pointing, map and kernel data, meet in one L2.
+// Returns -1 for the blocks of an XCD past its share.
+constexpr int kXcds = 8;
+__host__ __device__ inline int64_t xcd_grid(int64_t n) { return (n + kXcds - 1) / kXcds * kXcds; }
+__host__ __device__ inline int64_t xcd_item(int64_t b, int64_t n) {
+    const int64_t x = b % kXcds, j = b / kXcds, q = n / kXcds, r = n % kXcds;
+    const int64_t cnt = q + (x < r ? 1 : 0);
+    return j < cnt ? x * q + (x < r ? x : r) + j : -1;
+}
+
 struct FftTiling {
     int logm = 0;            // complex half-length M = 2^logm, real length n_r = 2M
     int n_r = 0;
@@ -85,7 +99,7 @@ struct FftTiling {
     DBuf<int64_t> tile_out;  // first output sample of every tile
     DBuf<int32_t> tile_len;  // outputs of every tile
     DBuf<int32_t> tile_int;  // interval of every tile
-    DBuf<double> H64;        // [n_kern][M+1] kernel spectrum / (2 n_r), FP64 operator
+    DBuf<double> H64;        // [n_kern][M+1] kernel spectrum / n_r, FP64 operator
     DBuf<float> H32;         // same, FP32 operator
     DBuf<double> tw64;       // [n_r/2][2] exp(-2 pi i q / n_r)
     DBuf<float> tw32;
@@ -178,6 +192,13 @@ struct Coarse {
     DBuf<double> csc_val;
     DBuf<double> AZ64;               // AZ blocks (FP64 plans)
     DBuf<float> AZ32;                // same (mixed plans)
+    // mixed plans with Z_S (opts.az_fp16): AZ for the A-DEF1 apply in FP16 (raw bits), column
+    // c of problem b at az16_off[b] + c * ld_b with ld_b = (az16_off[b+1] - az16_off[b]) / r_b
+    // a multiple of 8 covering an even number of pixels (the entries past the problem's
+    // pixels are 0); entry value times az16_scale[column] is the FP32 AZ entry rounded
+    DBuf<uint16_t> AZ16;
+    DBuf<int64_t> az16_off;          // [B+1]
+    DBuf<double> az16_scale;         // [r_eff] power of two
     DBuf<double> ZD64;               // Z_D blocks, same layout as AZ (FP64 plans)
     DBuf<float> ZD32;                // same (mixed plans)
     DBuf<double> Einv;               // E^-1 blocks
@@ -209,6 +230,8 @@ struct mm_plan_s {
     std::vector<int32_t> h_pint;
     std::vector<int64_t> h_samp, h_ooff;
     std::vector<int64_t> h_soff;        // [B+1] first padded sorted position of every problem
+    std::vector<int64_t> h_pn;          // [B] samples of every problem
+    int64_t pt_range = 2048;            // samples per P^T work range
     int64_t n_sorted = 0;               // padded sorted length (problems start 8-aligned)
     mm::DBuf<int32_t> int_prob;         // [n_int] problem of every interval
     mm::DBuf<int64_t> ooff;             // [B+1] compact pixel offsets
@@ -238,6 +261,8 @@ struct mm_plan_s {
     mm::DBuf<uint64_t> heads;           // segment-start bit per sorted sample
     mm::DBuf<int32_t> wave_pix;         // [n_waves+1] pixel ranges of the P^T waves
     mm::DBuf<int32_t> wave_prob;        // [n_waves] problem of every wave
+    mm::DBuf<int64_t> wave_off;         // [B+1] first P^T wave of every problem
+    mm::DBuf<int64_t> soff;             // [B+1] h_soff on the device
     int64_t n_waves = 0;
     mm::DBuf<int32_t> obs;              // compact -> original id
     mm::DBuf<int32_t> hits;             // s_p
@@ -347,6 +372,11 @@ int toeplitz_tod64(mm_plan_t pl, const void* y, int y_f64, double* z);
 int toeplitz_tod32(mm_plan_t pl, const void* y, int y_f64, float* z);
 
 // ---- pointing.hip
+// P^T work ranges (wave_pix, wave_prob, wave_off) for per_wave samples per range
+int build_wave_ranges(mm_plan_t pl, int64_t per_wave);
+// the P^T range: opts.pt_range, else the fastest candidate (autotune) or the default
+int tune_pt_range(mm_plan_t pl);
+// x = P^T z for the problems in mask
 int scatter64(mm_plan_t pl, const double* z, double* x, const int* mask);
 int scatter32(mm_plan_t pl, const float* z, double* x, const int* mask);
 // P^T of nc <= kScatterCols FP32 time streams z + k zstride into columns k0 + k of the

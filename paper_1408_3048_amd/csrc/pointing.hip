@@ -2,6 +2,9 @@
 // de-pointing P (time-ordered gather), and the block-Jacobi preconditioner
 // M_BD = (P^T diag(N^-1) P)^-1 [Sect. 3.1, eq. stdPrec].
 #include <cfloat>
+#include <map>
+#include <mutex>
+#include <vector>
 
 #include "mm_device.h"
 
@@ -153,7 +156,11 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ per
                                                  const int32_t* __restrict__ wave_prob) {
     static_assert(E % 4 == 0, "E must be a multiple of 4");
     __shared__ __align__(16) T zx[4][64 * E];
-    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    // the blocks of one XCD take a contiguous range of waves (neighbouring pixels share the
+    // time samples whose z they gather)
+    const int64_t blk = xcd_item(blockIdx.x, (n_waves + 3) / 4);
+    if (blk < 0) return;
+    const int64_t w = blk * 4 + (threadIdx.x >> 6);
     if (w >= n_waves) return;
     if (mask && !mask[wave_prob[w]]) return;
     const int32_t p0 = wave_pix[w], p1 = wave_pix[w + 1];
@@ -267,7 +274,9 @@ __global__ __launch_bounds__(256) void k_scatter_cols(
     static_assert(E % 4 == 0, "E must be a multiple of 4");
     constexpr int NV = NC * NS;
     __shared__ __align__(16) float zx[4][NC][64 * E];
-    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t blk = xcd_item(blockIdx.x, (n_waves + 3) / 4);
+    if (blk < 0) return;
+    const int64_t w = blk * 4 + (threadIdx.x >> 6);
     if (w >= n_waves) return;
     const int b = wave_prob[w];
     int ncb = ncols[b] - k0;  // columns this problem has in the group
@@ -537,11 +546,11 @@ int scatter_t(mm_plan_t pl, const T* z, const T* ws, double* x, const int* mask)
     // 4 samples per lane: 8 gathers more per lane cost the residency they would add
     constexpr int E = 4;
     if (pl->n_s == 3)
-        hipLaunchKernelGGL((k_scatter<T, 3, E>), dim3(nb), dim3(256), 0, pl->stream, pl->perm.p, ws,
+        hipLaunchKernelGGL((k_scatter<T, 3, E>), dim3(xcd_grid(nb)), dim3(256), 0, pl->stream, pl->perm.p, ws,
                            z, (const unsigned long long*)pl->heads.p, pl->wave_pix.p, pl->seg.p,
                            pl->hits.p, pl->n_waves, x, mask, pl->wave_prob.p);
     else
-        hipLaunchKernelGGL((k_scatter<T, 1, E>), dim3(nb), dim3(256), 0, pl->stream, pl->perm.p, ws,
+        hipLaunchKernelGGL((k_scatter<T, 1, E>), dim3(xcd_grid(nb)), dim3(256), 0, pl->stream, pl->perm.p, ws,
                            z, (const unsigned long long*)pl->heads.p, pl->wave_pix.p, pl->seg.p,
                            pl->hits.p, pl->n_waves, x, mask, pl->wave_prob.p);
     MM_HIP(hipGetLastError());
@@ -560,13 +569,13 @@ int scatter_cols32(mm_plan_t pl, const float* z, int64_t zstride, int nc, int k0
     if (nb == 0) return MM_OK;
     constexpr int E = 4;  // the lane layout of scatter32: the same additions
     if (pl->n_s == 3)
-        hipLaunchKernelGGL((k_scatter_cols<3, E, kScatterCols>), dim3(nb), dim3(256), 0,
+        hipLaunchKernelGGL((k_scatter_cols<3, E, kScatterCols>), dim3(xcd_grid(nb)), dim3(256), 0,
                            pl->stream, pl->perm.p, pl->ws32.p, z, zstride, nc,
                            (const unsigned long long*)pl->heads.p, pl->wave_pix.p, pl->seg.p,
                            pl->hits.p, pl->n_waves, pl->wave_prob.p, pl->ooff.p, ncols, blk_off,
                            k0, az);
     else
-        hipLaunchKernelGGL((k_scatter_cols<1, E, kScatterCols>), dim3(nb), dim3(256), 0,
+        hipLaunchKernelGGL((k_scatter_cols<1, E, kScatterCols>), dim3(xcd_grid(nb)), dim3(256), 0,
                            pl->stream, pl->perm.p, pl->ws32.p, z, zstride, nc,
                            (const unsigned long long*)pl->heads.p, pl->wave_pix.p, pl->seg.p,
                            pl->hits.p, pl->n_waves, pl->wave_prob.p, pl->ooff.p, ncols, blk_off,
@@ -641,6 +650,69 @@ int bj_apply(mm_plan_t pl, const double* r, double* z, const PcgCtl& ctl) {
         hipLaunchKernelGGL(k_bj_apply<1>, dim3(pl->n_pblk), dim3(kVecThreads), 0, pl->stream, r, z,
                            pl->bj.p, ctl);
     MM_HIP(hipGetLastError());
+    return MM_OK;
+}
+
+namespace {
+std::mutex g_pt_mu;
+std::map<std::vector<int64_t>, int64_t> g_pt_cache;
+}  // namespace
+
+// The P^T work range of the plan's operator (FP32 for mixed plans, else FP64): each of
+// 1024, 2048 and 4096 samples per range timed over three launches on a nonzero TOD (after
+// one untimed launch), the fastest kept; cached per process for the same scan shape.
+int tune_pt_range(mm_plan_t pl) {
+    const bool f32 = pl->opts.precision == MM_MIXED;
+    std::vector<int64_t> key = {pl->n_t, pl->n_obs, pl->n_s, pl->n_prob, f32 ? 1 : 0};
+    for (int32_t j = 0; j < pl->n_int; ++j) key.push_back(pl->h_off[j + 1] - pl->h_off[j]);
+    {
+        std::lock_guard<std::mutex> lk(g_pt_mu);
+        auto it = g_pt_cache.find(key);
+        if (it != g_pt_cache.end()) return build_wave_ranges(pl, it->second);
+    }
+    hipStream_t st = pl->stream;
+    DBuf<unsigned char> z;
+    DBuf<double> x;
+    MM_TRY(z.alloc((size_t)pl->n_t * (f32 ? 4 : 8)));
+    MM_TRY(x.alloc((size_t)pl->n_obs * pl->n_s));
+    MM_HIP(hipMemsetAsync(z.p, 0x3f, z.n, st));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    MM_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        set_error("hipEventCreate failed");
+        return MM_ERR_DEVICE;
+    }
+    struct Ev {
+        hipEvent_t a, b;
+        ~Ev() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } ev{e0, e1};
+    auto run = [&]() {
+        return f32 ? scatter32(pl, (const float*)z.p, x.p, nullptr)
+                   : scatter64(pl, (const double*)z.p, x.p, nullptr);
+    };
+    int64_t best = 0;
+    float best_ms = 0.0f;
+    for (const int64_t cand : {1024, 2048, 4096}) {
+        MM_TRY(build_wave_ranges(pl, cand));
+        MM_TRY(run());
+        MM_HIP(hipEventRecord(e0, st));
+        for (int k = 0; k < 3; ++k) MM_TRY(run());
+        MM_HIP(hipEventRecord(e1, st));
+        MM_HIP(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        MM_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (best == 0 || ms < best_ms) {
+            best = cand;
+            best_ms = ms;
+        }
+    }
+    MM_TRY(build_wave_ranges(pl, best));
+    std::lock_guard<std::mutex> lk(g_pt_mu);
+    g_pt_cache[key] = best;
     return MM_OK;
 }
 

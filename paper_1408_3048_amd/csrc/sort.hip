@@ -556,19 +556,11 @@ int build_pointing(mm_plan_t pl, const int32_t* pix, const void* weights, int wd
     hipLaunchKernelGGL(k_heads, dim3(grid_for(n_obs)), dim3(256), 0, st, pl->seg.p, n_obs,
                        (unsigned long long*)pl->heads.p);
     MM_HIP(hipGetLastError());
-    const int64_t per_wave = 2048;
-    std::vector<int64_t> woff(B + 1, 0);
-    for (int b = 0; b < B; ++b) woff[b + 1] = woff[b] + (s0[b + 1] - s0[b] + per_wave - 1) / per_wave;
-    pl->n_waves = woff[B];
-    DBuf<int64_t> dwoff;
-    MM_TRY(dwoff.alloc(B + 1));
-    MM_HIP(hipMemcpyAsync(dwoff.p, woff.data(), (B + 1) * 8, hipMemcpyHostToDevice, st));
-    MM_TRY(pl->wave_pix.alloc(pl->n_waves + 1));
-    MM_TRY(pl->wave_prob.alloc(std::max<int64_t>(1, pl->n_waves)));
-    hipLaunchKernelGGL(k_wave_ranges, dim3(grid_for(pl->n_waves + 1)), dim3(256), 0, st, pl->seg.p,
-                       pl->ooff.p, dsoff.p, dwoff.p, B, n_obs, pl->n_waves, per_wave,
-                       pl->wave_pix.p, pl->wave_prob.p);
-    MM_HIP(hipGetLastError());
+    pl->h_pn.assign(B, 0);
+    for (int b = 0; b < B; ++b) pl->h_pn[b] = s0[b + 1] - s0[b];
+    MM_TRY(pl->soff.alloc(B + 1));
+    MM_HIP(hipMemcpyAsync(pl->soff.p, pl->h_soff.data(), (B + 1) * 8, hipMemcpyHostToDevice, st));
+    MM_TRY(build_wave_ranges(pl, pl->opts.pt_range > 0 ? pl->opts.pt_range : 2048));
     // weights, time-ordered and pixel-sorted
     if (pl->n_s == 3) {
         const bool mixed = pl->opts.precision == MM_MIXED;
@@ -591,6 +583,26 @@ int build_pointing(mm_plan_t pl, const int32_t* pix, const void* weights, int wd
         MM_HIP(hipGetLastError());
     }
     MM_HIP(hipStreamSynchronize(st));
+    return MM_OK;
+}
+
+// P^T work ranges: problem b's sorted samples (from its padded start) are cut every
+// per_wave samples; each range's wave takes the whole pixels that start in it
+int build_wave_ranges(mm_plan_t pl, int64_t per_wave) {
+    hipStream_t st = pl->stream;
+    const int B = pl->n_prob;
+    std::vector<int64_t> woff(B + 1, 0);
+    for (int b = 0; b < B; ++b) woff[b + 1] = woff[b] + (pl->h_pn[b] + per_wave - 1) / per_wave;
+    pl->n_waves = woff[B];
+    pl->pt_range = per_wave;
+    MM_TRY(pl->wave_off.alloc(B + 1));
+    MM_HIP(hipMemcpyAsync(pl->wave_off.p, woff.data(), (B + 1) * 8, hipMemcpyHostToDevice, st));
+    MM_TRY(pl->wave_pix.alloc(pl->n_waves + 1));
+    MM_TRY(pl->wave_prob.alloc(std::max<int64_t>(1, pl->n_waves)));
+    hipLaunchKernelGGL(k_wave_ranges, dim3(grid_for(pl->n_waves + 1)), dim3(256), 0, st, pl->seg.p,
+                       pl->ooff.p, pl->soff.p, pl->wave_off.p, B, pl->n_obs, pl->n_waves, per_wave,
+                       pl->wave_pix.p, pl->wave_prob.p);
+    MM_HIP(hipGetLastError());
     return MM_OK;
 }
 

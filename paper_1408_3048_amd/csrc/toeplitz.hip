@@ -195,6 +195,7 @@ struct ToepArgs {
     const int64_t* int_hi;
     const int32_t* int_kern;
     int lam;
+    int64_t n_tiles;          // tiles of the launch (blocks are mapped to tiles XCD-major)
     const int* mask;          // per-problem flags: tiles of problems with mask 0 are skipped
     const int32_t* int_prob;  // problem of every interval
     int skip_zero;            // map modes: all-zero windows skip the transform
@@ -224,14 +225,14 @@ struct CBuf;
 template <>
 struct CBuf<float> {
     float2* c;
-    // at an already swizzled position p
-    __device__ __forceinline__ void get_sw(int p, float& re, float& im) const {
-        const float2 v = c[p];
+    // at byte offset b (8 times an already swizzled position)
+    __device__ __forceinline__ void get_swb(int b, float& re, float& im) const {
+        const float2 v = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(c) + b);
         re = v.x;
         im = v.y;
     }
-    __device__ __forceinline__ void put_sw(int p, float re, float im) const {
-        c[p] = make_float2(re, im);
+    __device__ __forceinline__ void put_swb(int b, float re, float im) const {
+        *reinterpret_cast<float2*>(reinterpret_cast<char*>(c) + b) = make_float2(re, im);
     }
     __device__ __forceinline__ void put_part_sw(int p, int part, float v) const {
         reinterpret_cast<float*>(c)[2 * p + part] = v;
@@ -256,13 +257,13 @@ template <>
 struct CBuf<double> {
     double* re;
     double* im;
-    __device__ __forceinline__ void get_sw(int p, double& r, double& i) const {
-        r = re[p];
-        i = im[p];
+    __device__ __forceinline__ void get_swb(int b, double& r, double& i) const {
+        r = *reinterpret_cast<const double*>(reinterpret_cast<const char*>(re) + b);
+        i = *reinterpret_cast<const double*>(reinterpret_cast<const char*>(im) + b);
     }
-    __device__ __forceinline__ void put_sw(int p, double r, double i) const {
-        re[p] = r;
-        im[p] = i;
+    __device__ __forceinline__ void put_swb(int b, double r, double i) const {
+        *reinterpret_cast<double*>(reinterpret_cast<char*>(re) + b) = r;
+        *reinterpret_cast<double*>(reinterpret_cast<char*>(im) + b) = i;
     }
     __device__ __forceinline__ void put_part_sw(int p, int part, double v) const {
         (part ? im : re)[p] = v;
@@ -397,20 +398,131 @@ __device__ __forceinline__ void powers(T wr, T wi, T* pr, T* pi) {
     }
 }
 
-template <typename T, int LOGM, int NT, int LR, int LOGB>
-__device__ __forceinline__ void dif_pass(const CBuf<T>& buf, const T* __restrict__ tw) {
-    constexpr int R = 1 << LR, B = 1 << LOGB, Q = B / R, M = 1 << LOGM, G = M / R;
+// The passes address LDS by byte offsets: an 8-byte point (FP32 (re, im), or one FP64
+// part) at swizzled position p sits at byte 8 p, and swz is linear over XOR, so the
+// byte offset of point (base + c) is (8 swz(base)) ^ (8 swz(c)) for bit-disjoint base and
+// c: one XOR with a compile-time constant per point.
+// exp(-2 pi i e / 32), e = 0..15: the twiddles of a radix-16 pass of block size 32 for its
+// group k = 1 (cos and sin of multiples of pi/16)
+template <typename T>
+__device__ __forceinline__ void root32(int e, T& c, T& s) {
+    // cos and sin of pi e / 16
+    constexpr double cs[16] = {1.0, 0.98078528040323044913, 0.92387953251128675613,
+                               0.83146961230254523708, 0.70710678118654752440,
+                               0.55557023301960222474, 0.38268343236508977173,
+                               0.19509032201612826785, 0.0, -0.19509032201612826785,
+                               -0.38268343236508977173, -0.55557023301960222474,
+                               -0.70710678118654752440, -0.83146961230254523708,
+                               -0.92387953251128675613, -0.98078528040323044913};
+    constexpr double sn[16] = {0.0, 0.19509032201612826785, 0.38268343236508977173,
+                               0.55557023301960222474, 0.70710678118654752440,
+                               0.83146961230254523708, 0.92387953251128675613,
+                               0.98078528040323044913, 1.0, 0.98078528040323044913,
+                               0.92387953251128675613, 0.83146961230254523708,
+                               0.70710678118654752440, 0.55557023301960222474,
+                               0.38268343236508977173, 0.19509032201612826785};
+    c = (T)cs[e & 15];
+    s = (T)(-sn[e & 15]);
+}
+
+// Twiddles of a pass (block size B = 2^LOGB, Q = B / 2^LR groups per block):
+//  - Q == 2 (B = 32): the groups are mapped so that every wave has one k; k = 0 needs none,
+//    k = 1 the constants root32;
+//  - the passes after the first with Q >= 4 read w^e, e = 1 .. R-1, from an LDS table
+//    filled at the start of the kernel (lt, [e - 1][k] per pass) where the table leaves the
+//    tile's occupancy unchanged;
+//  - otherwise binary powers of w = tw[k TWS] (the first pass, the plan-time transforms).
+// Every source gives the same values: the LDS table holds the powers the last case forms.
+template <typename T, int LOGM, int LOGB>
+constexpr bool first_pass() {
+    return LOGB == LOGM;
+}
+// entries of the LDS twiddle table before the pass of block size 2^LOGB (passes after the
+// first, with Q >= 4), and in all
+__host__ __device__ constexpr int ltw_offset(int logm, int logb) {
+    int off = 0;
+    for (int l = logm; l > logb; l -= (l >= 4 ? 4 : l)) {
+        const int lr = l >= 4 ? 4 : l;
+        const int q = (1 << l) >> lr;
+        if (l != logm && q >= 4) off += ((1 << lr) - 1) * q;
+    }
+    return off;
+}
+__host__ __device__ constexpr int ltw_total(int logm) { return ltw_offset(logm, 0); }
+
+template <typename T, int LOGM, int NT, int LR, int LOGB, bool LTW>
+__device__ __forceinline__ void pass_twiddles(int k, const T* __restrict__ tw,
+                                              const T* __restrict__ lt, T* pr, T* pi) {
+    constexpr int R = 1 << LR, B = 1 << LOGB, Q = B / R, M = 1 << LOGM;
     constexpr int TWS = (2 * M) / B;
+    if constexpr (Q == 2 && R == 16) {
+#pragma unroll
+        for (int e = 1; e < R; ++e) root32<T>(e, pr[e], pi[e]);
+    } else if constexpr (LTW && !first_pass<T, LOGM, LOGB>() && Q >= 4) {
+        const T* tb = lt + 2 * (ltw_offset(LOGM, LOGB) + k);
+#pragma unroll
+        for (int e = 1; e < R; ++e) {
+            pr[e] = tb[2 * (e - 1) * Q];
+            pi[e] = tb[2 * (e - 1) * Q + 1];
+        }
+    } else {
+        powers<T, R>(tw[2 * k * TWS], tw[2 * k * TWS + 1], pr, pi);
+    }
+}
+
+// the LDS twiddle table of the passes after the first (see pass_twiddles), formed by the
+// same binary powers the passes would take; every thread must call
+template <typename T, int LOGM, int NT>
+__device__ __forceinline__ void fill_ltw(const T* __restrict__ tw, T* lt) {
+    constexpr int M = 1 << LOGM;
+    for (int l = LOGM - 4; l > 0; l -= (l >= 4 ? 4 : l)) {
+        const int lr = l >= 4 ? 4 : l;
+        const int q = (1 << l) >> lr;
+        if (q < 4) continue;
+        const int tws = (2 * M) >> l;
+        const int off = ltw_offset(LOGM, l);
+        for (int k = threadIdx.x; k < q; k += NT) {
+            T pr[16], pi[16];
+            const T wr = tw[2 * k * tws], wi = tw[2 * k * tws + 1];
+            if (lr == 4) powers<T, 16>(wr, wi, pr, pi);
+            else if (lr == 3) powers<T, 8>(wr, wi, pr, pi);
+            else powers<T, 4>(wr, wi, pr, pi);
+            for (int e = 1; e < (1 << lr); ++e) {
+                lt[2 * (off + (e - 1) * q + k)] = k ? pr[e] : (T)1;
+                lt[2 * (off + (e - 1) * q + k) + 1] = k ? pi[e] : (T)0;
+            }
+        }
+    }
+}
+
+// group g of a pass -> (block, k); for Q == 2 the first half of the groups has k = 0 and
+// the second k = 1, so that k is uniform over a wave
+template <int Q, int G>
+__device__ __forceinline__ void pass_group(int g, int& blk, int& k) {
+    if constexpr (Q == 2) {
+        k = g >= G / 2 ? 1 : 0;
+        blk = g & (G / 2 - 1);
+    } else {
+        k = g & (Q - 1);
+        blk = g / Q;
+    }
+}
+
+template <typename T, int LOGM, int NT, int LR, int LOGB, bool LTW = false>
+__device__ __forceinline__ void dif_pass(const CBuf<T>& buf, const T* __restrict__ tw,
+                                         const T* __restrict__ lt = nullptr) {
+    constexpr int R = 1 << LR, B = 1 << LOGB, Q = B / R, M = 1 << LOGM, G = M / R;
     for (int g = threadIdx.x; g < G; g += NT) {
-        const int k = g & (Q - 1);
-        const int sb = swz((g / Q) * B + k);  // base and m Q are bit-disjoint
+        int blk, k;
+        pass_group<Q, G>(g, blk, k);
+        const int sbb = swz(blk * B + k) << 3;  // base and m Q are bit-disjoint
         T vr[R], vi[R];
 #pragma unroll
-        for (int m = 0; m < R; ++m) buf.get_sw(sb ^ swz(m * Q), vr[m], vi[m]);
+        for (int m = 0; m < R; ++m) buf.get_swb(sbb ^ (swz(m * Q) << 3), vr[m], vi[m]);
         dif_net<T, R>(vr, vi);
         if (Q > 1 && k != 0) {
             T pr[R], pi[R];
-            powers<T, R>(tw[2 * k * TWS], tw[2 * k * TWS + 1], pr, pi);
+            pass_twiddles<T, LOGM, NT, LR, LOGB, LTW>(k, tw, lt, pr, pi);
 #pragma unroll
             for (int i = 1; i < R; ++i) {
                 const int e = rev_bits<LR>(i);
@@ -420,24 +532,25 @@ __device__ __forceinline__ void dif_pass(const CBuf<T>& buf, const T* __restrict
             }
         }
 #pragma unroll
-        for (int i = 0; i < R; ++i) buf.put_sw(sb ^ swz(i * Q), vr[i], vi[i]);
+        for (int i = 0; i < R; ++i) buf.put_swb(sbb ^ (swz(i * Q) << 3), vr[i], vi[i]);
     }
     __syncthreads();
 }
 
-template <typename T, int LOGM, int NT, int LR, int LOGB>
-__device__ __forceinline__ void dit_pass(const CBuf<T>& buf, const T* __restrict__ tw) {
+template <typename T, int LOGM, int NT, int LR, int LOGB, bool LTW = false>
+__device__ __forceinline__ void dit_pass(const CBuf<T>& buf, const T* __restrict__ tw,
+                                         const T* __restrict__ lt = nullptr) {
     constexpr int R = 1 << LR, B = 1 << LOGB, Q = B / R, M = 1 << LOGM, G = M / R;
-    constexpr int TWS = (2 * M) / B;
     for (int g = threadIdx.x; g < G; g += NT) {
-        const int k = g & (Q - 1);
-        const int sb = swz((g / Q) * B + k);
+        int blk, k;
+        pass_group<Q, G>(g, blk, k);
+        const int sbb = swz(blk * B + k) << 3;
         T vr[R], vi[R];
 #pragma unroll
-        for (int i = 0; i < R; ++i) buf.get_sw(sb ^ swz(i * Q), vr[i], vi[i]);
+        for (int i = 0; i < R; ++i) buf.get_swb(sbb ^ (swz(i * Q) << 3), vr[i], vi[i]);
         if (Q > 1 && k != 0) {
             T pr[R], pi[R];
-            powers<T, R>(tw[2 * k * TWS], tw[2 * k * TWS + 1], pr, pi);
+            pass_twiddles<T, LOGM, NT, LR, LOGB, LTW>(k, tw, lt, pr, pi);
 #pragma unroll
             for (int i = 1; i < R; ++i) {
                 const int e = rev_bits<LR>(i);
@@ -448,84 +561,86 @@ __device__ __forceinline__ void dit_pass(const CBuf<T>& buf, const T* __restrict
         }
         dit_net_inv<T, R>(vr, vi);
 #pragma unroll
-        for (int m = 0; m < R; ++m) buf.put_sw(sb ^ swz(m * Q), vr[m], vi[m]);
+        for (int m = 0; m < R; ++m) buf.put_swb(sbb ^ (swz(m * Q) << 3), vr[m], vi[m]);
     }
     __syncthreads();
 }
 
-// STOP = 1: the last radix-2 stage (LOGB == 1) is left to the fused spectrum pass
-template <typename T, int LOGM, int NT, int LOGB, int STOP = 0>
-__device__ __forceinline__ void fwd_passes(const CBuf<T>& buf, const T* tw) {
+// STOP = 1: the last radix-2 stage (LOGB == 1) is left to the fused spectrum pass.  LTW:
+// the passes after the first read their twiddles from the LDS table lt.
+template <typename T, int LOGM, int NT, int LOGB, int STOP = 0, bool LTW = false>
+__device__ __forceinline__ void fwd_passes(const CBuf<T>& buf, const T* tw,
+                                           const T* lt = nullptr) {
     if constexpr (LOGB > STOP) {
         constexpr int LR = LOGB >= 4 ? 4 : LOGB;
-        dif_pass<T, LOGM, NT, LR, LOGB>(buf, tw);
-        fwd_passes<T, LOGM, NT, LOGB - LR, STOP>(buf, tw);
+        dif_pass<T, LOGM, NT, LR, LOGB, LTW>(buf, tw, lt);
+        fwd_passes<T, LOGM, NT, LOGB - LR, STOP, LTW>(buf, tw, lt);
     }
 }
 
-template <typename T, int LOGM, int NT, int LOGB, int STOP = 0>
-__device__ __forceinline__ void inv_passes(const CBuf<T>& buf, const T* tw) {
+template <typename T, int LOGM, int NT, int LOGB, int STOP = 0, bool LTW = false>
+__device__ __forceinline__ void inv_passes(const CBuf<T>& buf, const T* tw,
+                                           const T* lt = nullptr) {
     if constexpr (LOGB > STOP) {
         constexpr int LR = LOGB >= 4 ? 4 : LOGB;
-        inv_passes<T, LOGM, NT, LOGB - LR, STOP>(buf, tw);
-        dit_pass<T, LOGM, NT, LR, LOGB>(buf, tw);
+        inv_passes<T, LOGM, NT, LOGB - LR, STOP, LTW>(buf, tw, lt);
+        dit_pass<T, LOGM, NT, LR, LOGB, LTW>(buf, tw, lt);
     }
 }
 
-// real-spectrum split, multiplication by the (pre-scaled) real kernel spectrum H,
-// and merge back, on pairs (k, M - k) of the bit-reversed half-length transform
+// The spectrum product of a frequency pair (k, m = M - k) of the packed real transform.
+// With Z the M-point transform of z[n] = y[2n] + i y[2n+1], the real transform of y is
+// X_k = ((Z_k + conj Z_m) - i e (Z_k - conj Z_m)) / 2, e = exp(-i pi k / M); the product
+// Y_k = H_k X_k (H real and even) is packed back into the input of the inverse transform
+// as W_k = (Y_k + conj Y_m) + i conj(e) (Y_k - conj Y_m).  Composed, the three steps are
+// one linear map with real coefficients: with c = cos(pi k / M), s = sin(pi k / M),
+//   W_k = a_k Z_k + i g conj(Z_m),   W_m = a_m Z_m + i g conj(Z_k),
+//   a_k = h_k + h_m - s (h_k - h_m),  a_m = h_k + h_m + s (h_k - h_m),  g = c (h_k - h_m),
+// where h = H / n_r is the spectrum as the plan stores it (the inverse transform's 1/M
+// and the split's factors folded in).  k = 0 (pair with m = M, the Nyquist bin) and the
+// self-paired k = M/2 (c = 0, s = 1) are the same formula.  tw holds e as (c, -s).
+template <typename T>
+__device__ __forceinline__ void spectrum_pair(T hk, T hm, T c, T s, T zkr, T zki, T zmr,
+                                                T zmi, T& wkr, T& wki, T& wmr, T& wmi) {
+    const T u = hk + hm, v = hk - hm;
+    const T ak = u - s * v, am = u + s * v, g = c * v;
+    wkr = ak * zkr + g * zmi;
+    wki = ak * zki + g * zmr;
+    wmr = am * zmr + g * zki;
+    wmi = am * zmi + g * zkr;
+}
+
+// spectrum product on pairs (k, M - k) of the bit-reversed half-length transform.  A
+// thread's kernel-spectrum and twiddle values for all its pairs are loaded before the
+// first product, so their memory latency is paid once, not once per pair.
 template <typename T, int LOGM, int NT>
 __device__ __forceinline__ void spectrum_pass(const CBuf<T>& buf, const T* __restrict__ H,
                                               const T* __restrict__ tw) {
     constexpr int M = 1 << LOGM;
-    for (int k = threadIdx.x; k <= M / 2; k += NT) {
-        if (k == 0) {
-            T zr, zi;
-            buf.get(0, zr, zi);
-            const T y0 = H[0] * ((T)2 * (zr + zi));
-            const T ym = H[M] * ((T)2 * (zr - zi));
-            buf.put(0, y0 + ym, y0 - ym);
-            continue;
-        }
+    constexpr int NI = (M / 2 + NT) / NT;  // pairs k = tid + i NT <= M/2
+    T hk[NI], hm[NI], cc[NI], ss[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int k0 = threadIdx.x + i * NT;
+        const int k = k0 <= M / 2 ? k0 : M / 2;  // valid address; not used past M/2
+        hk[i] = H[k];
+        hm[i] = H[M - k];
+        cc[i] = tw[2 * k];
+        ss[i] = -tw[2 * k + 1];
+    }
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int k = threadIdx.x + i * NT;
+        if (k > M / 2) break;
         const int km = M - k;
         const int ak = rev_bits<LOGM>(k);
-        const int am = rev_bits<LOGM>(km);
-        T zkr, zki, zmr, zmi;
+        const int am = k == 0 ? ak : rev_bits<LOGM>(km);  // bin M is bin 0
+        T zkr, zki, zmr, zmi, wkr, wki, wmr, wmi;
         buf.get(ak, zkr, zki);
         buf.get(am, zmr, zmi);
-        const T er = tw[2 * k], ei = tw[2 * k + 1];
-        const T fr = tw[2 * km], fi = tw[2 * km + 1];
-        // 2 X_k = (Z_k + conj Z_m) - i e (Z_k - conj Z_m)
-        T Ar = zkr + zmr, Ai = zki - zmi, Dr = zkr - zmr, Di = zki + zmi;
-        T pr = er * Dr - ei * Di, pim = er * Di + ei * Dr;
-        const T xkr = Ar + pim, xki = Ai - pr;
-        // 2 X_m = (Z_m + conj Z_k) - i f (Z_m - conj Z_k)
-        Ar = zmr + zkr;
-        Ai = zmi - zki;
-        Dr = zmr - zkr;
-        Di = zmi + zki;
-        pr = fr * Dr - fi * Di;
-        pim = fr * Di + fi * Dr;
-        const T xmr = Ar + pim, xmi = Ai - pr;
-        const T hk = H[k], hm = H[km];
-        const T ykr = hk * xkr, yki = hk * xki, ymr = hm * xmr, ymi = hm * xmi;
-        // W_k = (Y_k + conj Y_m) + i conj(e) (Y_k - conj Y_m)
-        Ar = ykr + ymr;
-        Ai = yki - ymi;
-        Dr = ykr - ymr;
-        Di = yki + ymi;
-        pr = er * Dr + ei * Di;
-        pim = er * Di - ei * Dr;
-        buf.put(ak, Ar - pim, Ai + pr);
-        if (km != k) {
-            Ar = ymr + ykr;
-            Ai = ymi - yki;
-            Dr = ymr - ykr;
-            Di = ymi + yki;
-            pr = fr * Dr + fi * Di;
-            pim = fr * Di - fi * Dr;
-            buf.put(am, Ar - pim, Ai + pr);
-        }
+        spectrum_pair(hk[i], hm[i], cc[i], ss[i], zkr, zki, zmr, zmi, wkr, wki, wmr, wmi);
+        buf.put(ak, wkr, wki);
+        if (k != 0 && km != k) buf.put(am, wmr, wmi);
     }
     __syncthreads();
 }
@@ -541,92 +656,66 @@ template <typename T, int LOGM, int NT>
 __device__ __forceinline__ void spectrum_pass_r2(const CBuf<T>& buf, const T* __restrict__ H,
                                                  const T* __restrict__ tw) {
     constexpr int M = 1 << LOGM;
-    // spectrum product of the pair (k, km), k != km, 0 < k < M
-    auto pair = [&](int k, int km, T zkr, T zki, T zmr, T zmi, T& ykr_o, T& yki_o, T& ymr_o,
-                    T& ymi_o) {
-        const T er = tw[2 * k], ei = tw[2 * k + 1];
-        const T fr = tw[2 * km], fi = tw[2 * km + 1];
-        T Ar = zkr + zmr, Ai = zki - zmi, Dr = zkr - zmr, Di = zki + zmi;
-        T pr = er * Dr - ei * Di, pim = er * Di + ei * Dr;
-        const T xkr = Ar + pim, xki = Ai - pr;
-        Ar = zmr + zkr;
-        Ai = zmi - zki;
-        Dr = zmr - zkr;
-        Di = zmi + zki;
-        pr = fr * Dr - fi * Di;
-        pim = fr * Di + fi * Dr;
-        const T xmr = Ar + pim, xmi = Ai - pr;
-        const T hk = H[k], hm = H[km];
-        const T ykr = hk * xkr, yki = hk * xki, ymr = hm * xmr, ymi = hm * xmi;
-        Ar = ykr + ymr;
-        Ai = yki - ymi;
-        Dr = ykr - ymr;
-        Di = yki + ymi;
-        pr = er * Dr + ei * Di;
-        pim = er * Di - ei * Dr;
-        ykr_o = Ar - pim;
-        yki_o = Ai + pr;
-        Ar = ymr + ykr;
-        Ai = ymi - yki;
-        Dr = ymr - ykr;
-        Di = ymi + yki;
-        pr = fr * Dr + fi * Di;
-        pim = fr * Di - fi * Dr;
-        ymr_o = Ar - pim;
-        ymi_o = Ai + pr;
-    };
-    // spectrum product of the self-paired frequency k = M/2
-    auto self = [&](T zr, T zi, T& yr_o, T& yi_o) {
-        constexpr int k = M / 2;
-        const T er = tw[2 * k], ei = tw[2 * k + 1];
-        T Ar = zr + zr, Ai = zi - zi, Dr = zr - zr, Di = zi + zi;
-        T pr = er * Dr - ei * Di, pim = er * Di + ei * Dr;
-        const T xkr = Ar + pim, xki = Ai - pr;
-        const T hk = H[k];
-        const T ykr = hk * xkr, yki = hk * xki;
-        Ar = ykr + ykr;
-        Ai = yki - yki;
-        Dr = ykr - ykr;
-        Di = yki + yki;
-        pr = er * Dr + ei * Di;
-        pim = er * Di - ei * Dr;
-        yr_o = Ar - pim;
-        yi_o = Ai + pr;
-    };
-    for (int k = threadIdx.x; k <= M / 4; k += NT) {
+    constexpr int NI = (M / 4 + NT) / NT;  // groups k = tid + i NT <= M/4
+    // per group: h at k, M - k, M/2 + k, M/2 - k and the twiddle (c, -s) at k; the pair
+    // (M/2 + k, M/2 - k) has c' = -s, s' = c
+    T h0[NI], h1[NI], h2[NI], h3[NI], cc[NI], ss[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int k0 = threadIdx.x + i * NT;
+        const int k = k0 <= M / 4 ? k0 : M / 4;  // valid address; not used past M/4
+        h0[i] = H[k];
+        h1[i] = H[M - k];
+        h2[i] = H[M / 2 + k];
+        h3[i] = H[M / 2 - k];
+        cc[i] = tw[2 * k];
+        ss[i] = -tw[2 * k + 1];
+    }
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int k = threadIdx.x + i * NT;
+        if (k > M / 4) break;
         const int a = rev_bits<LOGM>(k);  // even: k < M/2
+        // byte offsets: slot a + 1 = a ^ 1 sits at swz(a) ^ 1 (swz is linear over XOR)
+        const int ab = swz(a) << 3;
         T ur, ui, vr, vi;
-        buf.get(a, ur, ui);
-        buf.get(a + 1, vr, vi);
+        buf.get_swb(ab, ur, ui);
+        buf.get_swb(ab ^ 8, vr, vi);
         // forward radix-2 stage: slot a -> frequency k, slot a + 1 -> k + M/2
         const T z0r = ur + vr, z0i = ui + vi, z1r = ur - vr, z1i = ui - vi;
-        T y0r, y0i, y1r, y1i;
-        if (k == 0) {  // DC and Nyquist of the real sequence (k = 0), self-paired M/2
-            const T yd = H[0] * ((T)2 * (z0r + z0i));
-            const T yn = H[M] * ((T)2 * (z0r - z0i));
-            y0r = yd + yn;
-            y0i = yd - yn;
-            self(z1r, z1i, y1r, y1i);
+        T y0r, y0i, y1r, y1i, q0r, q0i, q1r, q1i;
+        if (k == 0) {  // DC with the Nyquist bin (pair (0, M)), and the self-paired M/2
+            // h2 = h3 = H[M/2]; (c, s) at M/2 is (0, 1)
+            spectrum_pair(h0[i], h1[i], (T)1, (T)0, z0r, z0i, z0r, z0i, y0r, y0i, q0r, q0i);
+            spectrum_pair(h2[i], h3[i], (T)0, (T)1, z1r, z1i, z1r, z1i, y1r, y1i, q1r, q1i);
         } else if (k == M / 4) {  // the pair (M/4, 3M/4) is the slot pair itself
-            pair(k, M - k, z0r, z0i, z1r, z1i, y0r, y0i, y1r, y1i);
+            spectrum_pair(h0[i], h1[i], cc[i], ss[i], z0r, z0i, z1r, z1i, y0r, y0i, y1r, y1i);
         } else {
             const int b = rev_bits<LOGM>(M - k);  // odd: slot b -> M - k, b - 1 -> M/2 - k
+            const int bb = swz(b) << 3;           // slot b - 1 = b ^ 1 at bb ^ 8
             T sr, si, tr, ti;
-            buf.get(b - 1, sr, si);
-            buf.get(b, tr, ti);
+            buf.get_swb(bb ^ 8, sr, si);
+            buf.get_swb(bb, tr, ti);
             const T w0r = sr + tr, w0i = si + ti, w1r = sr - tr, w1i = si - ti;
-            T q0r, q0i, q1r, q1i;
-            pair(k, M - k, z0r, z0i, w1r, w1i, y0r, y0i, q1r, q1i);
-            pair(M / 2 + k, M / 2 - k, z1r, z1i, w0r, w0i, y1r, y1i, q0r, q0i);
+            spectrum_pair(h0[i], h1[i], cc[i], ss[i], z0r, z0i, w1r, w1i, y0r, y0i, q1r, q1i);
+            spectrum_pair(h2[i], h3[i], -ss[i], cc[i], z1r, z1i, w0r, w0i, y1r, y1i, q0r, q0i);
             // inverse radix-2 stage on the slots (b - 1, b)
-            buf.put(b - 1, q0r + q1r, q0i + q1i);
-            buf.put(b, q0r - q1r, q0i - q1i);
+            buf.put_swb(bb ^ 8, q0r + q1r, q0i + q1i);
+            buf.put_swb(bb, q0r - q1r, q0i - q1i);
         }
         // inverse radix-2 stage on the slots (a, a + 1)
-        buf.put(a, y0r + y1r, y0i + y1i);
-        buf.put(a + 1, y0r - y1r, y0i - y1i);
+        buf.put_swb(ab, y0r + y1r, y0i + y1i);
+        buf.put_swb(ab ^ 8, y0r - y1r, y0i - y1i);
     }
     __syncthreads();
+}
+
+// element i of an array at a block-uniform base, addressed by a 32-bit byte offset (the
+// scalar-base form of the load: no 64-bit vector address arithmetic per element)
+template <typename E>
+__device__ __forceinline__ E at_u32(const E* base, uint32_t i) {
+    return *reinterpret_cast<const E*>(reinterpret_cast<const char*>(base) +
+                                       i * (uint32_t)sizeof(E));
 }
 
 // Load phase: the tile's window [o - lambda, o + L + lambda) of the interval, zero
@@ -677,8 +766,8 @@ __device__ __forceinline__ bool load_window(const ToepArgs<T>& a, const CBuf<T>&
 #pragma unroll
         for (int u = 0; u < BP; ++u) {
             const uint32_t r = pos(u);
-            cc[u] = (uint32_t)cb[r];
-            ww[u] = wb[r];
+            cc[u] = (uint32_t)at_u32(cb, r);
+            ww[u] = at_u32(wb, r);
         }
 #pragma unroll
         for (int b0 = 0; b0 < PER; b0 += BP) {
@@ -693,8 +782,8 @@ __device__ __forceinline__ bool load_window(const ToepArgs<T>& a, const CBuf<T>&
 #pragma unroll
                 for (int u = 0; u < BP; ++u) {
                     const uint32_t r = pos(b0 + BP + u);
-                    cc[u] = (uint32_t)cb[r];
-                    ww[u] = wb[r];
+                    cc[u] = (uint32_t)at_u32(cb, r);
+                    ww[u] = at_u32(wb, r);
                 }
             }
 #pragma unroll
@@ -728,9 +817,9 @@ __device__ __forceinline__ bool load_window(const ToepArgs<T>& a, const CBuf<T>&
             uint32_t cc[B];
             T2 ww[B];
 #pragma unroll
-            for (int u = 0; u < B; ++u) cc[u] = (uint32_t)cb[rr[u]];
+            for (int u = 0; u < B; ++u) cc[u] = (uint32_t)at_u32(cb, rr[u]);
 #pragma unroll
-            for (int u = 0; u < B; ++u) ww[u] = wb[rr[u]];
+            for (int u = 0; u < B; ++u) ww[u] = at_u32(wb, rr[u]);
             T4 xx[B];  // byte offsets of the packed map fit 32 bits (n_obs < 2^27)
 #pragma unroll
             for (int u = 0; u < B; ++u)
@@ -742,17 +831,17 @@ __device__ __forceinline__ bool load_window(const ToepArgs<T>& a, const CBuf<T>&
             const int32_t* cb = a.cid + base;
             int32_t cc[B];
 #pragma unroll
-            for (int u = 0; u < B; ++u) cc[u] = cb[rr[u]];
+            for (int u = 0; u < B; ++u) cc[u] = at_u32(cb, rr[u]);
 #pragma unroll
             for (int u = 0; u < B; ++u) v[u] = ok[u] ? (T)a.x[cc[u]] : (T)0;
         } else if constexpr (MODE == 2) {  // TOD, FP64
             const double* y = (const double*)a.y + base;
 #pragma unroll
-            for (int u = 0; u < B; ++u) v[u] = ok[u] ? (T)y[rr[u]] : (T)0;
+            for (int u = 0; u < B; ++u) v[u] = ok[u] ? (T)at_u32(y, rr[u]) : (T)0;
         } else {  // TOD, FP32
             const float* y = (const float*)a.y + base;
 #pragma unroll
-            for (int u = 0; u < B; ++u) v[u] = ok[u] ? (T)y[rr[u]] : (T)0;
+            for (int u = 0; u < B; ++u) v[u] = ok[u] ? (T)at_u32(y, rr[u]) : (T)0;
         }
 #pragma unroll
         for (int u = 0; u < B; ++u) {
@@ -766,6 +855,19 @@ __device__ __forceinline__ bool load_window(const ToepArgs<T>& a, const CBuf<T>&
 // waves per SIMD that the tile's LDS allows (160 KB per CU, 4 SIMDs per CU), capped where
 // the butterflies and gathers would spill (4 waves = 128 VGPRs for FP32, 3 = 170
 // for FP64): the register budget the compiler must meet so that LDS bounds occupancy
+// the LDS twiddle table of the passes after the first is used where it leaves the tile's
+// occupancy (blocks per CU, by LDS and by the 32 waves a CU holds) unchanged
+template <typename T, int LOGM, int NT>
+constexpr bool ltw_enabled() {
+    constexpr int bytes = 2 * (1 << LOGM) * (int)sizeof(T);
+    constexpr int tbytes = 2 * ltw_total(LOGM) * (int)sizeof(T);
+    constexpr int wmax = 32 / (NT / 64);
+    constexpr int b0 = (160 * 1024) / bytes < wmax ? (160 * 1024) / bytes : wmax;
+    constexpr int b1 = (160 * 1024) / (bytes + tbytes) < wmax ? (160 * 1024) / (bytes + tbytes)
+                                                              : wmax;
+    return ltw_total(LOGM) > 0 && b0 == b1;
+}
+
 template <typename T, int LOGM, int NT>
 constexpr int tile_waves_per_simd() {
     constexpr int bytes = 2 * (1 << LOGM) * (int)sizeof(T);
@@ -775,14 +877,24 @@ constexpr int tile_waves_per_simd() {
     return w < 1 ? 1 : (w > cap ? cap : w);
 }
 
+// threads of a tile: one radix-16 group per thread and pass
+template <int LOGM>
+constexpr int tile_threads() {
+    constexpr int nt = (1 << LOGM) / 16;
+    return nt > 1024 ? 1024 : (nt < 256 ? 256 : nt);
+}
+
 // SKIPZ: a tile whose input window is all zero writes zeros and skips the transform (the
 // exact result; used for the sparse A Z columns; costs a block vote in LDS)
 template <typename T, int LOGM, int NT, int MODE, bool SKIPZ>
 __global__ __launch_bounds__(NT, (tile_waves_per_simd<T, LOGM, NT>())) void k_toeplitz(
     ToepArgs<T> a) {
     constexpr int M = 1 << LOGM;
-    __shared__ __align__(16) unsigned char smem[2 * M * sizeof(T)];
+    constexpr bool LTW = ltw_enabled<T, LOGM, NT>();
+    __shared__ __align__(16) unsigned char
+        smem[2 * M * sizeof(T) + (LTW ? 2 * ltw_total(LOGM) * sizeof(T) : 0)];
     const CBuf<T> buf = make_cbuf<T>(smem, M);
+    T* const lt = reinterpret_cast<T*>(smem + 2 * M * sizeof(T));
     if constexpr (SKIPZ) {
         if (blockIdx.y) {
             const int64_t y = blockIdx.y;
@@ -792,7 +904,11 @@ __global__ __launch_bounds__(NT, (tile_waves_per_simd<T, LOGM, NT>())) void k_to
             if (a.int_on) a.int_on += y * a.on_step;
         }
     }
-    const int64_t tile = blockIdx.x;
+    // XCD-major tile order (neighbouring tiles share pointing, map and kernel data in one
+    // L2), except for zero-skipping launches: there the few non-zero tiles of a sparse
+    // column are neighbours and would all land on one XCD
+    const int64_t tile = SKIPZ ? (int64_t)blockIdx.x : xcd_item(blockIdx.x, a.n_tiles);
+    if (tile < 0 || tile >= a.n_tiles) return;
     const int j = a.tile_int[tile];
     if (a.mask && !a.mask[a.int_prob[j]]) return;
     const int64_t o = a.tile_out[tile];
@@ -805,28 +921,36 @@ __global__ __launch_bounds__(NT, (tile_waves_per_simd<T, LOGM, NT>())) void k_to
             return;
         }
     }
+    // the twiddle table is ordered by the barrier after the load (zero-skipping launches:
+    // filled only for non-zero windows, behind a barrier of its own)
+    if constexpr (LTW && !SKIPZ) fill_ltw<T, LOGM, NT>(a.tw, lt);
     const bool nz = load_window<T, LOGM, NT, MODE>(a, buf, o - lam, L + 2 * lam, lo, hi);
     if constexpr (SKIPZ) {
         if (!__syncthreads_or(nz)) {  // zero window: the exact result is zero
             for (int i = threadIdx.x; i < L; i += NT) a.z[o + i] = (T)0;
             return;
         }
+        if constexpr (LTW) {
+            fill_ltw<T, LOGM, NT>(a.tw, lt);
+            __syncthreads();
+        }
     } else {
         (void)nz;
         __syncthreads();
     }
     if constexpr (LOGM % 4 == 1) {  // the radix-2 stages go into the spectrum pass
-        fwd_passes<T, LOGM, NT, LOGM, 1>(buf, a.tw);
+        fwd_passes<T, LOGM, NT, LOGM, 1, LTW>(buf, a.tw, lt);
         spectrum_pass_r2<T, LOGM, NT>(buf, a.H + (int64_t)a.int_kern[j] * (M + 1), a.tw);
-        inv_passes<T, LOGM, NT, LOGM, 1>(buf, a.tw);
+        inv_passes<T, LOGM, NT, LOGM, 1, LTW>(buf, a.tw, lt);
     } else {
-        fwd_passes<T, LOGM, NT, LOGM>(buf, a.tw);
+        fwd_passes<T, LOGM, NT, LOGM, 0, LTW>(buf, a.tw, lt);
         spectrum_pass<T, LOGM, NT>(buf, a.H + (int64_t)a.int_kern[j] * (M + 1), a.tw);
-        inv_passes<T, LOGM, NT, LOGM>(buf, a.tw);
+        inv_passes<T, LOGM, NT, LOGM, 0, LTW>(buf, a.tw, lt);
     }
     T* zo = a.z + o;  // block-uniform base, 32-bit offsets
     for (int i = lam + threadIdx.x; i < lam + L; i += NT)
-        zo[(uint32_t)(i - lam)] = buf.get_part(i >> 1, i & 1);
+        *reinterpret_cast<T*>(reinterpret_cast<char*>(zo) + (uint32_t)(i - lam) * (uint32_t)sizeof(T)) =
+            buf.get_part(i >> 1, i & 1);
 }
 
 // ------------------------------------------------------------------ plan-time FFTs (FP64)
@@ -941,9 +1065,11 @@ constexpr int kPlanLogM = 13;  // plan-time FP64 FFTs: n_r = 16384 real points
 constexpr int kPlanNT = 512;
 
 template <typename T, int LOGM>
-int launch_logm(const ToepArgs<T>& a, int64_t n_tiles, hipStream_t st) {
-    constexpr int M = 1 << LOGM;
-    constexpr int NT = (M / 16) > 1024 ? 1024 : ((M / 16) < 256 ? 256 : (M / 16));
+int launch_logm(const ToepArgs<T>& a_in, int64_t n_tiles, hipStream_t st) {
+    constexpr int NT = tile_threads<LOGM>();
+    ToepArgs<T> a = a_in;
+    a.n_tiles = n_tiles;
+    const unsigned gx = (unsigned)xcd_grid(n_tiles);
     if (a.skip_zero) {
         const dim3 grid((unsigned)n_tiles, a.layers > 1 ? (unsigned)a.layers : 1u);
         if (a.mode == 0)
@@ -952,10 +1078,10 @@ int launch_logm(const ToepArgs<T>& a, int64_t n_tiles, hipStream_t st) {
             hipLaunchKernelGGL((k_toeplitz<T, LOGM, NT, 1, true>), grid, dim3(NT), 0, st, a);
     } else {
         switch (a.mode) {
-            case 0: hipLaunchKernelGGL((k_toeplitz<T, LOGM, NT, 0, false>), dim3(n_tiles), dim3(NT), 0, st, a); break;
-            case 1: hipLaunchKernelGGL((k_toeplitz<T, LOGM, NT, 1, false>), dim3(n_tiles), dim3(NT), 0, st, a); break;
-            case 2: hipLaunchKernelGGL((k_toeplitz<T, LOGM, NT, 2, false>), dim3(n_tiles), dim3(NT), 0, st, a); break;
-            default: hipLaunchKernelGGL((k_toeplitz<T, LOGM, NT, 3, false>), dim3(n_tiles), dim3(NT), 0, st, a); break;
+            case 0: hipLaunchKernelGGL((k_toeplitz<T, LOGM, NT, 0, false>), dim3(gx), dim3(NT), 0, st, a); break;
+            case 1: hipLaunchKernelGGL((k_toeplitz<T, LOGM, NT, 1, false>), dim3(gx), dim3(NT), 0, st, a); break;
+            case 2: hipLaunchKernelGGL((k_toeplitz<T, LOGM, NT, 2, false>), dim3(gx), dim3(NT), 0, st, a); break;
+            default: hipLaunchKernelGGL((k_toeplitz<T, LOGM, NT, 3, false>), dim3(gx), dim3(NT), 0, st, a); break;
         }
     }
     MM_HIP(hipGetLastError());
@@ -1370,7 +1496,7 @@ int build_tiling(mm_plan_t pl, FftTiling& ft, bool fp64, int n_r_request) {
                            d_ooff.p, d_h.p, nk);
         MM_HIP(hipGetLastError());
     }
-    const double scale = 1.0 / (2.0 * (double)ft.n_r);
+    const double scale = 1.0 / (double)ft.n_r;
     if (fp64) {
         MM_TRY(ft.H64.alloc((size_t)nk * (M + 1)));
     } else {

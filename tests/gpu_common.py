@@ -81,6 +81,13 @@ def rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
+# two-level preconditioner of a mixed plan whose A-DEF1 apply reads AZ in FP16 (the default
+# az_fp16 layout): every AZ entry is rounded once to FP16 (relative error <= 2^-11 after the
+# exact power-of-two column scaling), so M_2lvl r moves by up to that fraction of the
+# coarse correction M_BD AZ w
+TOL_2LVL_AZ16 = 1e-3
+
+
 def relmax(a, b):
     """Element-wise error: max |a - b| / max |b|."""
     a = np.asarray(a, dtype=np.float64).ravel()

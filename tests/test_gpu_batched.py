@@ -187,3 +187,41 @@ def test_batched_rejects_overlapping_pixel_ranges():
     with pytest.raises(MMError) as e:
         _plan(bad)
     assert "disjoint" in str(e.value)
+
+
+@pytest.mark.parametrize("pt_range", [1024, 4096])
+def test_pt_range_batched_equals_standalone_and_oracle(pt_range):
+    """The P^T work range (opts.pt_range) changes only the order of additions within a
+    pixel: a batched plan and standalone plans with the same range agree bit for bit (A x,
+    the block-Jacobi blocks through M_BD, a mixed two-level solve), and A x stays within the
+    oracle's bars; an autotuned plan reports one of the candidate ranges."""
+    sc = batch_scan()
+    pb = _plan(sc, precision="mixed", coarse=True, pt_range=pt_range)
+    assert pb.pt_range() == pt_range
+    off3 = pb.problem_pixels() * 3
+    d = torch.from_numpy(sc.noise).cuda()
+    xb_sol, _ = pb.pcg_solve(pb.rhs(d), precond="2lvl", precision="mixed", tol=1e-10,
+                             max_iter=3000)
+    for b in (0, N_PROB - 1):
+        s1 = single_scan(b)
+        p1 = _plan(s1, precision="mixed", coarse=True, pt_range=pt_range)
+        x = torch.randn(p1.n_vec, dtype=torch.float64, device="cuda",
+                        generator=torch.Generator("cuda").manual_seed(b))
+        xb = torch.zeros(pb.n_vec, dtype=torch.float64, device="cuda")
+        xb[off3[b]:off3[b + 1]] = x
+        for prec in ("fp64", "mixed"):
+            y1 = p1.apply_A(x, precision=prec)
+            assert torch.equal(y1, pb.apply_A(xb, precision=prec)[off3[b]:off3[b + 1]]), (b, prec)
+        assert torch.equal(p1.precond_bj(x), pb.precond_bj(xb)[off3[b]:off3[b + 1]]), b
+        x1, _ = p1.pcg_solve(p1.rhs(torch.from_numpy(s1.noise).cuda()), precond="2lvl",
+                             precision="mixed", tol=1e-10, max_iter=3000)
+        assert torch.equal(x1, xb_sol[off3[b]:off3[b + 1]]), b
+        pr = O.Problem.from_scan(s1)
+        xn = x.cpu().numpy()
+        check(p1.apply_A(x, precision="mixed").cpu().numpy(), pr.apply_A(xn), 2e-5, "A fp32")
+        check(p1.apply_A(x).cpu().numpy(), pr.apply_A(xn), 1e-12, "A fp64")
+        p1.close()
+    pb.close()
+    pt = _plan(single_scan(0), precision="mixed", autotune=True)
+    assert pt.pt_range() in (1024, 2048, 4096)
+    pt.close()
