@@ -78,33 +78,154 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(sc, n_ax, n_intervals_sample):
-    """The FP64 oracle's A x timed on a few intervals of the same scan (the
-    time-domain part of A x separates by interval), scaled to the whole scan and
-    to the number of A x applications the GPU solve performed."""
+# ---------------------------------------------------------------- the FP64 oracle on the host
+#
+# The oracle's operators are separable by stationary interval in their time-domain part:
+# A x = sum over intervals j of P_j^T N_j^-1 P_j x.  A pool of worker processes (forked
+# before the GPU is touched, so no worker carries a GPU context) each holds the oracle's
+# Problem for a fixed share of the intervals and returns its contribution in the global
+# compact pixel numbering; the parent adds the shares in a fixed order.  The oracle's
+# functions are called unchanged.
+
+_POOL_SCANS = {}     # name -> (scan, shares), inherited by the forked workers
+_POOL_BUFS = {}      # name -> (map buffer, TOD buffer): shared memory written by the parent
+_POOL_PROBS = {}     # (name, share) -> (Problem of the share, global compact index, samples)
+
+
+def _share_problem(name, share):
     import oracle as O
     import synth
-    K = sc.n_intervals
-    idx = np.linspace(0, K - 1, n_intervals_sample).round().astype(np.int64)
-    sub = synth.subset_intervals(sc, idx)
-    pr = O.Problem.from_scan(sub)
-    x = np.random.default_rng(0).standard_normal(pr.n_obs * pr.n_s)
-    pr.apply_A(x)  # warm
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        pr.apply_A(x)
-        reps += 1
-        if time.perf_counter() - t0 > 8.0 or reps >= 3:
-            break
-    t_sub = (time.perf_counter() - t0) / reps
-    scale = sc.n_samples / sub.n_samples
-    t_ax = t_sub * scale
-    return dict(value=t_ax * n_ax, unit="s", cores=1, kind="oracle",
-                sample=(f"oracle A*x on {n_intervals_sample} of {K} intervals "
-                        f"({sub.n_samples} samples, {t_sub:.3f} s per apply), scaled x{scale:.0f} "
-                        f"to {t_ax:.2f} s per full A*x, times the {n_ax} A*x applications of the "
-                        f"timed GPU solve (plan AZ columns + PCG); extrapolated"),
-                t_ax_s=t_ax)
+    key = (name, share)
+    if key not in _POOL_PROBS:
+        sc, n_shares = _POOL_SCANS[name]
+        idx = np.arange(share, sc.n_intervals, n_shares)
+        sub = synth.subset_intervals(sc, idx)
+        pr = O.Problem.from_scan(sub)
+        gobs = np.unique(sc.pix)
+        gidx = np.searchsorted(gobs, pr.obs)
+        samples = np.concatenate([np.arange(sc.offsets[j], sc.offsets[j + 1]) for j in idx])
+        _POOL_PROBS[key] = (pr, gidx, samples)
+    return _POOL_PROBS[key]
+
+
+def _share_apply(task):
+    """One share's part of A x (kind "A", x from the shared map buffer), of b = P^T N^-1 d
+    (kind "rhs", d from the shared TOD buffer) or of the block-Jacobi blocks (kind "bj")."""
+    name, share, kind = task
+    pr, gidx, samples = _share_problem(name, share)
+    xb, db = _POOL_BUFS[name]
+    if kind == "A":
+        y = pr.apply_A(np.frombuffer(xb).reshape(-1, pr.n_s)[gidx].reshape(-1))
+    elif kind == "rhs":
+        y = pr.rhs(np.frombuffer(db)[samples])
+    else:
+        y = pr.bj_blocks().reshape(-1)
+    return gidx, y
+
+
+class OraclePool:
+    """The oracle's A x, b and block-Jacobi blocks of a scan, computed by the worker pool."""
+
+    def __init__(self, pool, name):
+        self.pool, self.name = pool, name
+        sc, self.n_shares = _POOL_SCANS[name]
+        self.n_obs = int(np.unique(sc.pix).shape[0])
+        self.ns = sc.n_stokes
+
+    def _run(self, kind, width):
+        out = np.zeros((self.n_obs, width))
+        tasks = [(self.name, k, kind) for k in range(self.n_shares)]
+        for gidx, y in self.pool.map(_share_apply, tasks):  # shares in order
+            np.add.at(out, gidx, y.reshape(-1, width))
+        return out.reshape(-1)
+
+    def apply_A(self, x):
+        np.frombuffer(_POOL_BUFS[self.name][0])[:] = x
+        return self._run("A", self.ns)
+
+    def rhs(self, d):
+        np.frombuffer(_POOL_BUFS[self.name][1])[:] = d
+        return self._run("rhs", self.ns)
+
+    def bj_apply(self, r):
+        if not hasattr(self, "_B"):
+            self._B = self._run("bj", self.ns * self.ns).reshape(self.n_obs, self.ns, self.ns)
+        R = np.asarray(r).reshape(self.n_obs, self.ns, 1)
+        return np.linalg.solve(self._B, R).reshape(-1)
+
+
+def make_oracle_pool(scans):
+    """Fork the worker pool (before any GPU work) with the scans it serves and shared map and
+    TOD buffers for the vectors it is applied to."""
+    import multiprocessing as mp
+    workers = max(1, min(16, os.cpu_count() or 1))
+    for name, (sc, n_shares) in scans.items():
+        _POOL_SCANS[name] = (sc, n_shares)
+        n_obs = int(np.unique(sc.pix).shape[0])
+        _POOL_BUFS[name] = (mp.RawArray("d", n_obs * sc.n_stokes), mp.RawArray("d", sc.n_samples))
+    return mp.get_context("fork").Pool(workers), workers
+
+
+def cpu_baseline(pool, workers, n_ax, x_gpu, d_gpu, cfg1_gpu, tol):
+    """The FP64 oracle on the host cores (see OraclePool):
+    - one full oracle A x of the 2^24-sample workload, timed; times the number of A x
+      applications of the timed GPU solve (plan A Z columns + PCG) it is the oracle's
+      time to solution at the GPU's iteration count (extrapolated from the measured A x);
+    - the GPU map's relative residual in the oracle's system, ||b - A x|| / ||b|| with the
+      oracle's b and A (the map's error against the FP64 oracle, as a residual);
+    - the 2^18-sample intensity raster solved by the oracle's PCG to tol and to 1e-12
+      (timed), and the GPU map's distance from both."""
+    import oracle as O
+    big = OraclePool(pool, "cfg2")
+    b_or = big.rhs(d_gpu)
+    big.apply_A(x_gpu)  # warm: the workers build their Problems
+    t0 = time.perf_counter()
+    ax = big.apply_A(x_gpu)
+    t_ax = time.perf_counter() - t0
+    relres = float(np.linalg.norm(b_or - ax) / np.linalg.norm(b_or))
+    small = OraclePool(pool, "cfg1")
+    b1 = small.rhs(cfg1_gpu["d"])
+    t0 = time.perf_counter()
+    x1, it1, st1 = O.pcg(small.apply_A, b1, small.bj_apply, tol=tol, maxit=2000)
+    t_solve = time.perf_counter() - t0
+    x1t, it1t, st1t = O.pcg(small.apply_A, b1, small.bj_apply, tol=1e-12, maxit=5000)
+    xg = cfg1_gpu["x"]
+    return dict(
+        value=round(t_ax * n_ax, 3), unit="s", cores=workers, kind="oracle",
+        sample=(f"one full oracle A*x of the 2^24-sample IQU raster (all 256 intervals) on "
+                f"{workers} worker processes ({t_ax:.2f} s), times the {n_ax} A*x applications "
+                f"of the timed GPU solve (plan A Z columns + PCG): extrapolated time to solution"),
+        os_cpu_count=os.cpu_count(), workers=workers, oracle_ax_s=round(t_ax, 3),
+        gpu_map_oracle_relres=relres,
+        small_workload=dict(
+            workload="2^18-sample I raster, 64x64, 16 intervals of 2^14, lambda=1024",
+            oracle_bj_pcg_s=round(t_solve, 3), oracle_iterations=it1, oracle_status=st1,
+            oracle_iterations_tol_1e12=it1t,
+            gpu_iterations=cfg1_gpu["iterations"], gpu_solve_ms=cfg1_gpu["solve_ms"],
+            gpu_map_rel_err_vs_oracle_same_tol=float(np.linalg.norm(xg - x1) / np.linalg.norm(x1)),
+            gpu_map_rel_err_vs_oracle_1e12=float(np.linalg.norm(xg - x1t) / np.linalg.norm(x1t)),
+            tol=tol))
+
+
+def cfg1_gpu_solve(sc, tol):
+    """The 2^18-sample intensity raster on the GPU: d = P m + n formed on the device, mixed
+    two-level PCG to tol.  Returns the host copies the oracle compares with."""
+    import torch
+    from paper_1408_3048_amd import Plan
+    pix = torch.from_numpy(sc.pix).cuda()
+    psd = np.stack([sc.sigma, sc.fknee, sc.alpha], axis=1)
+    plan = Plan(pix, None, sc.n_pix, sc.offsets, psd, n_stokes=1, lam=sc.lam, f_samp=sc.f_samp,
+                precision="mixed", coarse=True)
+    obs = plan.obs_pixels().long()
+    m = torch.from_numpy(sc.sky).cuda()[obs].reshape(-1).contiguous()
+    d = plan.apply_P(m) + torch.from_numpy(sc.noise).cuda()
+    b = plan.rhs(d)
+    x, info = plan.pcg_solve(b, precond="2lvl", precision="mixed", tol=tol, max_iter=5000,
+                             history=False)
+    out = dict(d=d.cpu().numpy(), x=x.cpu().numpy(), iterations=info["iterations"],
+               solve_ms=round(info["solve_ms"], 3))
+    plan.close()
+    return out
 
 
 def batched_leg(tol, warmup=1):
@@ -289,6 +410,97 @@ def bandwidth_leg(pix, w, sc, psd, m, d, tol, lams, autotune):
     return out
 
 
+def ring_share_leg(tol, autotune, reps=10):
+    """One GPU's share of the 2^28-sample ring scan at its real shape (Sect. 4.1.1, Table 1
+    big-circle scan, sharded by detectors): 2 of the 16 detectors, 2^25 samples, 128
+    intervals of 2^18, lambda = 4096, 2048x1024 equirectangular IQU grid.  Reported: the
+    FP32 A x kernels' algorithmic GB/s (16 B/sample each) and a mixed two-level solve to
+    tol (plan + solve).  One detector pair leaves some pixels with too few polariser angles
+    for an IQU solution; their samples are assigned to one extra pixel (a flagged-sample
+    sink, as map-makers do), the pixels with rcond_1 of their block above 1e-6 are solved."""
+    import torch
+    import synth
+    from paper_1408_3048_amd import Plan
+    t = time.perf_counter()
+    sc = synth.cfg3_ring_iqu(det_subset=[0, 1])
+    log(f"ring share generated in {time.perf_counter() - t:.1f}s: {sc.n_samples} samples")
+    pix = torch.from_numpy(sc.pix).cuda().long()
+    w = torch.from_numpy(sc.weights).cuda()
+    # block conditioning of every pixel (input preparation; not part of any timed region)
+    W = torch.cat([torch.ones_like(w[:, :1]), w], 1)
+    Bp = torch.zeros((sc.n_pix, 3, 3), dtype=torch.float64, device="cuda")
+    Bp.view(sc.n_pix, 9).index_add_(0, pix, (W[:, :, None] * W[:, None, :]).reshape(-1, 9))
+    hit = torch.zeros(sc.n_pix, dtype=torch.int64, device="cuda").index_add_(
+        0, pix, torch.ones_like(pix))
+    seen = hit > 0
+    Bs = Bp[seen]
+    det = torch.linalg.det(Bs)
+    okd = det > 1e-12 * Bs.abs().amax(dim=(1, 2)) ** 3
+    Binv = torch.zeros_like(Bs)
+    Binv[okd] = torch.linalg.inv(Bs[okd])
+    rc = torch.where(okd, 1.0 / (Bs.abs().sum(1).amax(1) * Binv.abs().sum(1).amax(1)),
+                     torch.zeros_like(det))
+    bad = torch.zeros(sc.n_pix, dtype=torch.bool, device="cuda")
+    bad[torch.nonzero(seen).squeeze(1)[rc < 1e-6]] = True
+    n_bad = int(bad.sum())
+    pix2 = torch.where(bad[pix], torch.full_like(pix, sc.n_pix), pix).to(torch.int32).contiguous()
+    wf = w.to(torch.float32).contiguous()
+    psd = np.stack([sc.sigma, sc.fknee, sc.alpha], axis=1)
+    kw = dict(n_stokes=3, lam=sc.lam, f_samp=sc.f_samp, autotune=autotune)
+    del W, Bp, Bs, Binv, hit, seen
+    # A x kernels
+    plan = Plan(pix2, wf, sc.n_pix + 1, sc.offsets, psd, precision="mixed", **kw)
+    x = torch.randn(plan.n_vec, dtype=torch.float64, device="cuda",
+                    generator=torch.Generator("cuda").manual_seed(3))
+    for _ in range(2):
+        plan.apply_A(x, precision="mixed")
+    plan.profile(True)
+    for _ in range(reps):
+        plan.apply_A(x, precision="mixed")
+    pr = plan.profile_read()
+    n_ninv, t_ninv = pr["ninv32"]
+    n_pt, t_pt = pr["pt32"]
+    a_ninv, a_pt = t_ninv / n_ninv, t_pt / n_pt
+    res = dict(workload=("one GPU's share of the 2^28-sample ring scan: 2 of 16 detectors, "
+                         "2^25 samples, 128 intervals of 2^18, lambda=4096, 2048x1024 IQU"),
+               n_samples=sc.n_samples, unknowns=plan.n_vec, sink_pixels=n_bad,
+               fft_lengths=plan.fft_lengths(),
+               ninv32=dict(avg_ms=round(a_ninv, 5),
+                           GBps=round(BYTES_NINV32 * sc.n_samples / (a_ninv * 1e-3) / 1e9, 1)),
+               pt32=dict(avg_ms=round(a_pt, 5),
+                         GBps=round(BYTES_PT32 * sc.n_samples / (a_pt * 1e-3) / 1e9, 1)),
+               ax_fp32_GBps=round((BYTES_NINV32 + BYTES_PT32) * sc.n_samples /
+                                  ((a_ninv + a_pt) * 1e-3) / 1e9, 1))
+    res["ax_fp32_frac_of_peak"] = round(res["ax_fp32_GBps"] / HBM_PEAK_GBPS, 4)
+    plan.close()
+    # data and the mixed two-level solve (plan + solve)
+    helper = Plan(pix2, wf, sc.n_pix + 1, sc.offsets, psd, precision="mixed", **kw)
+    obs = helper.obs_pixels().long()
+    sky = torch.cat([torch.from_numpy(sc.sky).cuda(), torch.zeros((1, 3), dtype=torch.float64,
+                                                                  device="cuda")])
+    m = sky[obs].reshape(-1).contiguous()
+    d = helper.apply_P(m) + torch.from_numpy(sc.noise).cuda()
+    helper.close()
+    del helper
+    for name, coarse, pc in (("mixed_2lvl", True, "2lvl"), ("mixed_bj", False, "bj")):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan = Plan(pix2, wf, sc.n_pix + 1, sc.offsets, psd, precision="mixed", coarse=coarse,
+                    **kw)
+        xs, info = plan.pcg_solve(plan.rhs(d), precond=pc, precision="mixed", tol=tol,
+                                  max_iter=5000, history=False, raise_on_error=False)
+        torch.cuda.synchronize()
+        tt = time.perf_counter() - t0
+        res[name] = dict(time_s=round(tt, 4), plan_ms=round(plan.plan_ms, 2),
+                         solve_ms=round(info["solve_ms"], 2), iterations=info["iterations"],
+                         relres=info["rel_residual"], status=info["status"],
+                         r_eff=plan.coarse_rank() if coarse else 0)
+        plan.close()
+        del xs
+    log(f"ring share: {res}")
+    return res
+
+
 def kernel_traffic(name, n_r=None):
     """HBM bytes per launch of a kernel from the stored counter figures (for FFT tile length
     n_r where they depend on it), or None when its source has changed since they were taken
@@ -328,7 +540,6 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-intervals", type=int, default=4)
     ap.add_argument("--no-reference", action="store_true", help="skip the FP64 block-Jacobi leg")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 256-problem batched Monte Carlo leg")
@@ -336,6 +547,8 @@ def main():
                     help="half-bandwidths of the bandwidth-study leg ('' skips it)")
     ap.add_argument("--knees", default="0.5,2,8",
                     help="f_knee values (Hz) of the knee-frequency leg ('' skips it)")
+    ap.add_argument("--no-ring-share", action="store_true",
+                    help="skip the one-GPU share of the 2^28-sample ring scan")
     ap.add_argument("--multi-rhs", type=int, default=8,
                     help="right-hand sides of the plan-reuse leg (0 skips it)")
     ap.add_argument("--autotune", type=int, default=1,
@@ -355,15 +568,23 @@ def main():
         copy_calibration()
         return
 
-    import torch
     import synth
-    from paper_1408_3048_amd import Plan
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
     t = time.perf_counter()
     sc = synth.cfg2_raster_iqu()
     log(f"scan generated in {time.perf_counter() - t:.1f}s: {sc.n_samples} samples, "
         f"{sc.n_intervals} intervals")
+    pool = None
+    if not args.no_cpu_baseline:
+        sc1 = synth.cfg1_raster_i()
+        # the oracle's worker pool is forked before anything touches the GPU
+        pool, workers = make_oracle_pool({"cfg2": (sc, 64), "cfg1": (sc1, 16)})
+        log(f"oracle pool: {workers} workers (os.cpu_count() = {os.cpu_count()})")
+
+    import torch
+    from paper_1408_3048_amd import Plan
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
     pix = torch.from_numpy(sc.pix).cuda()
     w = torch.from_numpy(sc.weights).cuda()
     psd = np.stack([sc.sigma, sc.fknee, sc.alpha], axis=1)
@@ -463,20 +684,27 @@ def main():
         "ax_fp32_GBps": round((BYTES_NINV32 + BYTES_PT32) * sc.n_samples /
                               ((avg_ninv + avg_pt) * 1e-3) / 1e9, 1),
     }
-    if t_ninv >= t_pt:  # the overlap-save FFT kernel: VALU-issue bound
-        achieved = flops / (avg_ninv * 1e-3) / 1e12
-        roof = dict(bound="alu", achieved=round(achieved, 2), peak=FP32_VALU_PEAK_TFLOPS,
-                    unit="TFLOP/s", frac=round(achieved / FP32_VALU_PEAK_TFLOPS, 4),
-                    traffic=kernel_traffic("ninv32", n_r32),
+    # the dominant kernel against the HBM roofline by its algorithmic bytes (16 per sample
+    # for each FP32 A x kernel); the overlap-save kernel's FFT flops against the FP32 vector
+    # peak beside it
+    if t_ninv >= t_pt:
+        achieved = BYTES_NINV32 * sc.n_samples / (avg_ninv * 1e-3) / 1e9
+        alu = flops / (avg_ninv * 1e-3) / 1e12
+        roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBPS, 4), traffic=kernel_traffic("ninv32", n_r32),
                     kernel="k_toeplitz<float> (gather P + overlap-save N^-1)",
                     avg_launch_ms=round(avg_ninv, 5), launches=n_ninv, tiles=tiles, n_r=n_r32,
-                    algorithmic_flops_per_launch=flops)
+                    bytes_per_sample=BYTES_NINV32,
+                    algorithmic_bytes_per_launch=BYTES_NINV32 * sc.n_samples,
+                    alu_view=dict(achieved_TFLOPs=round(alu, 2), peak_TFLOPs=FP32_VALU_PEAK_TFLOPS,
+                                  frac=round(alu / FP32_VALU_PEAK_TFLOPS, 4),
+                                  flops_per_launch=flops))
     else:
         achieved = BYTES_PT32 * sc.n_samples / (avg_pt * 1e-3) / 1e9
         roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBPS, 4), traffic=kernel_traffic("pt32"),
                     kernel="k_scatter<float,3> (P^T segmented reduction)",
-                    avg_launch_ms=round(avg_pt, 5), launches=n_pt,
+                    avg_launch_ms=round(avg_pt, 5), launches=n_pt, bytes_per_sample=BYTES_PT32,
                     algorithmic_bytes_per_launch=BYTES_PT32 * sc.n_samples)
     roof["hbm_view"] = hbm
     roof["other_kernels"] = {k: dict(launches=v[0], avg_ms=v[1] / max(v[0], 1))
@@ -500,14 +728,21 @@ def main():
     if not args.no_batched:
         batched = batched_leg(args.tol)
 
+    ring = None
+    if not args.no_ring_share:
+        ring = ring_share_leg(args.tol, bool(args.autotune))
+
     cpu = None
-    if not args.no_cpu_baseline:
+    if pool is not None:
         ex = extras[-1]
         n_ax = ex["iterations"] + ex["outer"] + 2 + ex["r_eff"]
-        log("timing the oracle on a sample of intervals ...")
-        cpu = cpu_baseline(sc, n_ax, args.cpu_intervals)
-        cpu.pop("t_ax_s", None)
-        log(f"cpu baseline: {cpu}")
+        cfg1 = cfg1_gpu_solve(sc1, args.tol)
+        log("the FP64 oracle on the host cores ...")
+        t0 = time.perf_counter()
+        cpu = cpu_baseline(pool, workers, n_ax, x_mixed.cpu().numpy(), d.cpu().numpy(), cfg1,
+                           args.tol)
+        pool.close()
+        log(f"cpu baseline ({time.perf_counter() - t0:.1f} s): {cpu}")
 
     out = dict(
         metric=METRIC, value=round(t_step, 6), unit="s", n_gpus=1, steps=args.steps,
@@ -519,7 +754,7 @@ def main():
                     n_samples=sc.n_samples, unknowns=extras[-1]["unknowns"],
                     tol=args.tol, parallelism="single GPU"),
         breakdown=extras[-1], reference=ref, other_legs=legs, multi_rhs=multi,
-        bandwidth=bandwidth, knee_sweep=knee, batched=batched,
+        bandwidth=bandwidth, knee_sweep=knee, batched=batched, ring_share=ring,
         roofline=roof,
         cpu_baseline=cpu,
     )
