@@ -620,20 +620,47 @@ __global__ __launch_bounds__(kVecThreads) void k_2lvl(
                 u[j][s] = r[(vb.base + qq[j]) * NS + s];
                 zw[j][s] = 0.0;
             }
-        for (int32_t c = 0; c < rk; ++c) {
-            const double wc = sw[c];
+        // columns in batches of CB: the batch's loads are issued together (CB times the
+        // loads in flight), then added in column order
+        constexpr int CB = 4;
+        auto load_cols = [&](int32_t c, TA (*va)[NS], TA (*vz)[NS]) {
             const TA* col = azb + (int64_t)c * nv;
 #pragma unroll
             for (int j = 0; j < PX; ++j)
 #pragma unroll
-                for (int s = 0; s < NS; ++s) u[j][s] -= (double)col[qq[j] * NS + s] * wc;
+                for (int s = 0; s < NS; ++s) va[j][s] = col[qq[j] * NS + s];
             if constexpr (DZ) {
                 const TA* zc = zd + az_off[vb.b] + (int64_t)c * nv;
 #pragma unroll
                 for (int j = 0; j < PX; ++j)
 #pragma unroll
-                    for (int s = 0; s < NS; ++s) zw[j][s] += (double)zc[qq[j] * NS + s] * wc;
+                    for (int s = 0; s < NS; ++s) vz[j][s] = zc[qq[j] * NS + s];
             }
+        };
+        auto add_cols = [&](double wc, const TA (*va)[NS], const TA (*vz)[NS]) {
+#pragma unroll
+            for (int j = 0; j < PX; ++j)
+#pragma unroll
+                for (int s = 0; s < NS; ++s) u[j][s] -= (double)va[j][s] * wc;
+            if constexpr (DZ) {
+#pragma unroll
+                for (int j = 0; j < PX; ++j)
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) zw[j][s] += (double)vz[j][s] * wc;
+            }
+        };
+        int32_t c = 0;
+        for (; c + CB <= rk; c += CB) {
+            TA va[CB][PX][NS], vz[CB][PX][NS];
+#pragma unroll
+            for (int t = 0; t < CB; ++t) load_cols(c + t, va[t], vz[t]);
+#pragma unroll
+            for (int t = 0; t < CB; ++t) add_cols(sw[c + t], va[t], vz[t]);
+        }
+        for (; c < rk; ++c) {
+            TA va[PX][NS], vz[PX][NS];
+            load_cols(c, va, vz);
+            add_cols(sw[c], va, vz);
         }
 #pragma unroll
         for (int j = 0; j < PX; ++j) {
@@ -697,34 +724,60 @@ __global__ __launch_bounds__(kVecThreads) void k_2lvl16(
         const int64_t q0 = 2 * jp;
         const bool two = q0 + 1 < vb.n;
         const int64_t qq[2] = {q0, two ? q0 + 1 : q0};
-        double u[2][NS];
+        // r, the M_BD blocks and the Z_S row ranges of both pixels are loaded before the
+        // column loop, so that their latency overlaps it
+        double u[2][NS], r0[2][NS], bm[2][NS == 3 ? 6 : 1];
+        int64_t e0[2], e1[2];
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < 2; ++j) {
+            const int64_t p = vb.base + qq[j];
 #pragma unroll
-            for (int s = 0; s < NS; ++s) u[j][s] = r[(vb.base + qq[j]) * NS + s];
+            for (int s = 0; s < NS; ++s) u[j][s] = r0[j][s] = r[p * NS + s];
+#pragma unroll
+            for (int t = 0; t < (NS == 3 ? 6 : 1); ++t) bm[j][t] = bj[(NS == 3 ? 6 : 1) * p + t];
+            e0[j] = zptr[p];
+            e1[j] = zptr[p + 1];
+        }
         const uint16_t* pe = azb + 2 * NS * jp;
-        for (int32_t c = 0; c < rk; ++c) {
-            const double wc = swa[c];
-            float f[2 * NS];
+        // the 2 NS FP16 entries of column c as NS 32-bit words
+        auto load_col = [&](int32_t c, uint32_t* wd) {
             if constexpr (NS == 3) {
                 const uint3 raw = *reinterpret_cast<const uint3*>(pe + (int64_t)c * ld);
-                const uint32_t wd[3] = {raw.x, raw.y, raw.z};
-#pragma unroll
-                for (int h = 0; h < 3; ++h) {
-                    const float2 v = __half22float2(__builtin_bit_cast(__half2, wd[h]));
-                    f[2 * h] = v.x;
-                    f[2 * h + 1] = v.y;
-                }
+                wd[0] = raw.x;
+                wd[1] = raw.y;
+                wd[2] = raw.z;
             } else {
-                const uint32_t raw = *reinterpret_cast<const uint32_t*>(pe + (int64_t)c * ld);
-                const float2 v = __half22float2(__builtin_bit_cast(__half2, raw));
-                f[0] = v.x;
-                f[1] = v.y;
+                wd[0] = *reinterpret_cast<const uint32_t*>(pe + (int64_t)c * ld);
+            }
+        };
+        auto add_col = [&](double wc, const uint32_t* wd) {
+            float f[2 * NS];
+#pragma unroll
+            for (int h = 0; h < NS; ++h) {
+                const float2 v = __half22float2(__builtin_bit_cast(__half2, wd[h]));
+                f[2 * h] = v.x;
+                f[2 * h + 1] = v.y;
             }
 #pragma unroll
             for (int j = 0; j < 2; ++j)
 #pragma unroll
                 for (int s = 0; s < NS; ++s) u[j][s] -= (double)f[NS * j + s] * wc;
+        };
+        // columns in batches of CB: the batch's loads are issued together, then added in
+        // column order
+        constexpr int CB = 8;
+        int32_t c = 0;
+        for (; c + CB <= rk; c += CB) {
+            uint32_t wd[CB][NS];
+#pragma unroll
+            for (int t = 0; t < CB; ++t) load_col(c + t, wd[t]);
+#pragma unroll
+            for (int t = 0; t < CB; ++t) add_col(swa[c + t], wd[t]);
+        }
+        for (; c < rk; ++c) {
+            uint32_t wd[NS];
+            load_col(c, wd);
+            add_col(swa[c], wd);
         }
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
@@ -732,20 +785,20 @@ __global__ __launch_bounds__(kVecThreads) void k_2lvl16(
             const int64_t p = vb.base + qq[j];
             double zz[NS];
             if constexpr (NS == 1) {
-                zz[0] = bj[p] * u[j][0];
+                zz[0] = bm[j][0] * u[j][0];
             } else {
-                const double* m = bj + 6 * p;
+                const double* m = bm[j];
                 zz[0] = m[0] * u[j][0] + m[1] * u[j][1] + m[2] * u[j][2];
                 zz[1] = m[1] * u[j][0] + m[3] * u[j][1] + m[4] * u[j][2];
                 zz[2] = m[2] * u[j][0] + m[4] * u[j][1] + m[5] * u[j][2];
             }
             double zs = 0.0;
-            for (int64_t e = zptr[p]; e < zptr[p + 1]; ++e) zs += zval[e] * sw[zcol[e] - c0];
+            for (int64_t e = e0[j]; e < e1[j]; ++e) zs += zval[e] * sw[zcol[e] - c0];
             zz[0] += zs;
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
                 z[p * NS + s] = zz[s];
-                acc += r[p * NS + s] * zz[s];
+                acc += r0[j][s] * zz[s];
             }
         }
     }
