@@ -228,7 +228,7 @@ def cfg1_gpu_solve(sc, tol):
     return out
 
 
-def batched_leg(tol, warmup=1):
+def batched_leg(tol, warmup=1, graph=True):
     """The batched Monte Carlo workload: 256 independent noise-only problems of uneven
     length (2^16..2^20 samples before dropping out-of-patch samples) over 128x128 IQU
     patches, one batched plan, mixed-precision two-level PCG to tol for all problems at
@@ -249,7 +249,8 @@ def batched_leg(tol, warmup=1):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         plan = Plan(pix, w, sc.n_pix, sc.offsets, psd, n_stokes=3, lam=sc.lam, f_samp=sc.f_samp,
-                    precision="mixed", coarse=True, problem_intervals=sc.problem_offsets)
+                    precision="mixed", coarse=True, problem_intervals=sc.problem_offsets,
+                    graph=graph)
         t1 = time.perf_counter()
         b = plan.rhs(d)
         t2 = time.perf_counter()
@@ -266,7 +267,8 @@ def batched_leg(tol, warmup=1):
                    rhs_per_s=plan.n_problems / tt, samples_per_s=sc.n_samples / tt,
                    iterations_max=max(its), iterations_mean=float(np.mean(its)),
                    rel_residual_max=info["rel_residual_max"], r_eff=plan.coarse_rank(),
-                   method="mixed two-level PCG, one batched plan, graph-captured iterations")
+                   method="mixed two-level PCG, one batched plan, " +
+                   ("graph-captured iterations" if graph else "launches issued one by one"))
         log(f"batched {'warmup' if i < warmup else 'timed'}: {tt * 1e3:.1f} ms {res}")
         plan.close()
         # the outputs are consumed here, so the next iteration's allocations reuse them
@@ -410,7 +412,7 @@ def bandwidth_leg(pix, w, sc, psd, m, d, tol, lams, autotune):
     return out
 
 
-def ring_share_leg(tol, autotune, reps=10):
+def ring_share_leg(tol, autotune, reps=10, fft_len_f32=0, fft_len_f64=0):
     """One GPU's share of the 2^28-sample ring scan at its real shape (Sect. 4.1.1, Table 1
     big-circle scan, sharded by detectors): 2 of the 16 detectors, 2^25 samples, 128
     intervals of 2^18, lambda = 4096, 2048x1024 equirectangular IQU grid.  Reported: the
@@ -446,7 +448,8 @@ def ring_share_leg(tol, autotune, reps=10):
     pix2 = torch.where(bad[pix], torch.full_like(pix, sc.n_pix), pix).to(torch.int32).contiguous()
     wf = w.to(torch.float32).contiguous()
     psd = np.stack([sc.sigma, sc.fknee, sc.alpha], axis=1)
-    kw = dict(n_stokes=3, lam=sc.lam, f_samp=sc.f_samp, autotune=autotune)
+    kw = dict(n_stokes=3, lam=sc.lam, f_samp=sc.f_samp, autotune=autotune,
+              fft_len_f32=fft_len_f32, fft_len_f64=fft_len_f64)
     del W, Bp, Bs, Binv, hit, seen
     # A x kernels
     plan = Plan(pix2, wf, sc.n_pix + 1, sc.offsets, psd, precision="mixed", **kw)
@@ -558,6 +561,14 @@ def main():
     ap.add_argument("--fft-len-f64", type=int, default=0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the 256 MiB copy that calibrates the HBM byte counters")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only run the 256-problem batched leg (profiling runs) and print its "
+                         "record")
+    ap.add_argument("--graph", type=int, default=1,
+                    help="batched leg: 1 captures the PCG iterations in HIP graphs, 0 issues "
+                         "every launch from the host (kernel traces of the iterations)")
+    ap.add_argument("--ring-only", action="store_true",
+                    help="only run the ring-scan share leg (profiling runs) and print its record")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU path "
@@ -566,6 +577,15 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.batched_only:
+        print(json.dumps(dict(batched=batched_leg(args.tol, warmup=args.warmup,
+                                                  graph=bool(args.graph)))), flush=True)
+        return
+    if args.ring_only:
+        print(json.dumps(dict(ring_share=ring_share_leg(
+            args.tol, bool(args.autotune), fft_len_f32=args.fft_len_f32,
+            fft_len_f64=args.fft_len_f64))), flush=True)
         return
 
     import synth

@@ -620,47 +620,22 @@ __global__ __launch_bounds__(kVecThreads) void k_2lvl(
                 u[j][s] = r[(vb.base + qq[j]) * NS + s];
                 zw[j][s] = 0.0;
             }
-        // columns in batches of CB: the batch's loads are issued together (CB times the
-        // loads in flight), then added in column order
-        constexpr int CB = 4;
-        auto load_cols = [&](int32_t c, TA (*va)[NS], TA (*vz)[NS]) {
+        // one column at a time: batches of columns with their loads issued together were
+        // slower here (more pages open per wave), unlike the FP16 layout of k_2lvl16
+        for (int32_t c = 0; c < rk; ++c) {
+            const double wc = sw[c];
             const TA* col = azb + (int64_t)c * nv;
 #pragma unroll
             for (int j = 0; j < PX; ++j)
 #pragma unroll
-                for (int s = 0; s < NS; ++s) va[j][s] = col[qq[j] * NS + s];
+                for (int s = 0; s < NS; ++s) u[j][s] -= (double)col[qq[j] * NS + s] * wc;
             if constexpr (DZ) {
                 const TA* zc = zd + az_off[vb.b] + (int64_t)c * nv;
 #pragma unroll
                 for (int j = 0; j < PX; ++j)
 #pragma unroll
-                    for (int s = 0; s < NS; ++s) vz[j][s] = zc[qq[j] * NS + s];
+                    for (int s = 0; s < NS; ++s) zw[j][s] += (double)zc[qq[j] * NS + s] * wc;
             }
-        };
-        auto add_cols = [&](double wc, const TA (*va)[NS], const TA (*vz)[NS]) {
-#pragma unroll
-            for (int j = 0; j < PX; ++j)
-#pragma unroll
-                for (int s = 0; s < NS; ++s) u[j][s] -= (double)va[j][s] * wc;
-            if constexpr (DZ) {
-#pragma unroll
-                for (int j = 0; j < PX; ++j)
-#pragma unroll
-                    for (int s = 0; s < NS; ++s) zw[j][s] += (double)vz[j][s] * wc;
-            }
-        };
-        int32_t c = 0;
-        for (; c + CB <= rk; c += CB) {
-            TA va[CB][PX][NS], vz[CB][PX][NS];
-#pragma unroll
-            for (int t = 0; t < CB; ++t) load_cols(c + t, va[t], vz[t]);
-#pragma unroll
-            for (int t = 0; t < CB; ++t) add_cols(sw[c + t], va[t], vz[t]);
-        }
-        for (; c < rk; ++c) {
-            TA va[PX][NS], vz[PX][NS];
-            load_cols(c, va, vz);
-            add_cols(sw[c], va, vz);
         }
 #pragma unroll
         for (int j = 0; j < PX; ++j) {
