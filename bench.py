@@ -53,7 +53,7 @@ def fft_tile_flops(offsets, lam, n_r):
     return tiles, float(tiles * per_tile)
 
 # HBM traffic of the dominant kernel per launch, from two rocprofv3 --pmc runs of this
-# script (FETCH_SIZE, then WRITE_SIZE, median over the launches of the timed solve), each
+# script (FETCH_SIZE, then WRITE_SIZE, median over the kernel's launches in that run), each
 # scaled by what the same counter reads for a plain 256 MiB device copy (--copy-calibration):
 # FETCH_SIZE reads 128 MiB for the 256 MiB read (factor 2.0), WRITE_SIZE 256 MiB (factor 1.0).
 # The factor 2 is that of 128-byte read requests, which FETCH_SIZE counts as 64 bytes; the
@@ -61,16 +61,24 @@ def fft_tile_flops(offsets, lam, n_r):
 # The figures hold only for the kernel source they were taken on (sha256 below); after any
 # change to that file the traffic is reported as null until the counters are taken again.
 TRAFFIC = {
-    # per FP32 tile length n_r (the plan's autotuner picks 8192 or 16384 on this workload)
+    # 2^24-sample IQU raster, FP32 tile length 16384 (the autotuner's choice on it)
     "ninv32": dict(source="paper_1408_3048_amd/csrc/toeplitz.hip",
-                   sha256="9ab08173f4dc73ec1fa3d16f2b82f2e2f56e4022844122e2453dff151f12ec49",
-                   by_n_r={8192: dict(fetch_kib=289529.4375, write_kib=65536.0),
-                           16384: dict(fetch_kib=201937.75, write_kib=65578.5625)},
+                   sha256="f56727667da3edd9af518216c937a30296f945ffcb1f5cb9b53e8ec7bb178832",
+                   by_n_r={16384: dict(fetch_kib=138176.2, write_kib=65548.3)},
                    fetch_factor=2.0, write_factor=1.0),
     "pt32": dict(source="paper_1408_3048_amd/csrc/pointing.hip",
-                 sha256="e0f93caae0ebdb34ce2935e6498a28231613cee1e45c1a124fab3f6c34a04440",
-                 by_n_r={None: dict(fetch_kib=153637.4375, write_kib=7799.78125)},
+                 sha256="f9b8097701826ba79f4e3364ef3559d1591769b1a335e8df8b04e01b49b9c074",
+                 by_n_r={None: dict(fetch_kib=133753.9, write_kib=7909.7)},
                  fetch_factor=2.0, write_factor=1.0),
+    # one GPU's share of the ring scan (2^25 samples), FP32 tile length 16384
+    "ring_ninv32": dict(source="paper_1408_3048_amd/csrc/toeplitz.hip",
+                        sha256="f56727667da3edd9af518216c937a30296f945ffcb1f5cb9b53e8ec7bb178832",
+                        by_n_r={16384: dict(fetch_kib=247742.8, write_kib=131072.0)},
+                        fetch_factor=2.0, write_factor=1.0),
+    "ring_pt32": dict(source="paper_1408_3048_amd/csrc/pointing.hip",
+                      sha256="f9b8097701826ba79f4e3364ef3559d1591769b1a335e8df8b04e01b49b9c074",
+                      by_n_r={None: dict(fetch_kib=456496.4, write_kib=46107.1)},
+                      fetch_factor=2.0, write_factor=1.0),
 }
 
 
@@ -469,9 +477,11 @@ def ring_share_leg(tol, autotune, reps=10, fft_len_f32=0, fft_len_f64=0):
                n_samples=sc.n_samples, unknowns=plan.n_vec, sink_pixels=n_bad,
                fft_lengths=plan.fft_lengths(),
                ninv32=dict(avg_ms=round(a_ninv, 5),
-                           GBps=round(BYTES_NINV32 * sc.n_samples / (a_ninv * 1e-3) / 1e9, 1)),
+                           GBps=round(BYTES_NINV32 * sc.n_samples / (a_ninv * 1e-3) / 1e9, 1),
+                           traffic=kernel_traffic("ring_ninv32", plan.fft_lengths()[1])),
                pt32=dict(avg_ms=round(a_pt, 5),
-                         GBps=round(BYTES_PT32 * sc.n_samples / (a_pt * 1e-3) / 1e9, 1)),
+                         GBps=round(BYTES_PT32 * sc.n_samples / (a_pt * 1e-3) / 1e9, 1),
+                         traffic=kernel_traffic("ring_pt32")),
                ax_fp32_GBps=round((BYTES_NINV32 + BYTES_PT32) * sc.n_samples /
                                   ((a_ninv + a_pt) * 1e-3) / 1e9, 1))
     res["ax_fp32_frac_of_peak"] = round(res["ax_fp32_GBps"] / HBM_PEAK_GBPS, 4)

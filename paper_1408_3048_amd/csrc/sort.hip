@@ -210,8 +210,8 @@ __device__ __forceinline__ int find_range(const int64_t* __restrict__ off, int B
 
 // per-problem pixel id range (samples of problem b: [samp[b], samp[b+1])): every wave reads
 // a chunk of 64 kMinmaxRun consecutive samples with coalesced loads and combines its range by
-// shuffles (one atomic per wave); a chunk that crosses a problem boundary (at most B - 1 of
-// them) takes per-sample atomics instead
+// shuffles (one atomic per wave); a chunk that crosses problem boundaries (at most B - 1 of
+// them) does the same for its part in each problem it reaches
 constexpr int kMinmaxRun = 64;
 __global__ void k_prob_minmax(const int32_t* __restrict__ pix, int64_t n,
                               const int64_t* __restrict__ samp, int B, int* __restrict__ lo,
@@ -243,11 +243,25 @@ __global__ void k_prob_minmax(const int32_t* __restrict__ pix, int64_t n,
                 atomicMax(&hi[b], h);
             }
         } else {
-            for (int64_t t = c0 + lane; t < c1; t += 64) {
-                const int bt = find_range(samp, B, t);
-                const int v = pix[t];
-                atomicMin(&lo[bt], v);
-                atomicMax(&hi[bt], v);
+            // the chunk's part in each problem it reaches, combined by shuffles as above
+            for (int bt = b;; ++bt) {
+                const int64_t s0 = c0 > samp[bt] ? c0 : samp[bt];
+                const int64_t s1 = c1 < samp[bt + 1] ? c1 : samp[bt + 1];
+                int l = INT_MAX, h = INT_MIN;
+                for (int64_t t = s0 + lane; t < s1; t += 64) {
+                    const int v = pix[t];
+                    l = min(l, v);
+                    h = max(h, v);
+                }
+                for (int o = 32; o > 0; o >>= 1) {
+                    l = min(l, __shfl_xor(l, o));
+                    h = max(h, __shfl_xor(h, o));
+                }
+                if (lane == 0 && s1 > s0) {
+                    atomicMin(&lo[bt], l);
+                    atomicMax(&hi[bt], h);
+                }
+                if (samp[bt + 1] >= c1) break;  // c1 <= samp[B]: ends at bt < B
             }
         }
     }
