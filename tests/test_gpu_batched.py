@@ -194,7 +194,8 @@ def test_pt_range_batched_equals_standalone_and_oracle(pt_range):
     """The P^T work range (opts.pt_range) changes only the order of additions within a
     pixel: a batched plan and standalone plans with the same range agree bit for bit (A x,
     the block-Jacobi blocks through M_BD, a mixed two-level solve), and A x stays within the
-    oracle's bars; an autotuned plan reports one of the candidate ranges."""
+    oracle's bars; an autotuned batch reports one of the candidate ranges, and standalone
+    plans given its range and FFT lengths agree with it bit for bit."""
     sc = batch_scan()
     pb = _plan(sc, precision="mixed", coarse=True, pt_range=pt_range)
     assert pb.pt_range() == pt_range
@@ -222,6 +223,20 @@ def test_pt_range_batched_equals_standalone_and_oracle(pt_range):
         check(p1.apply_A(x).cpu().numpy(), pr.apply_A(xn), 1e-12, "A fp64")
         p1.close()
     pb.close()
-    pt = _plan(single_scan(0), precision="mixed", autotune=True)
+    # an autotuned batch: a standalone plan given the batch's tuned P^T range and FFT
+    # lengths computes the same A x bit for bit
+    pt = _plan(sc, precision="mixed", autotune=True, fft_len_f64=0, fft_len_f32=0)
     assert pt.pt_range() in (1024, 2048, 4096)
+    n64, n32 = pt.fft_lengths()
+    for b in (0, N_PROB - 1):
+        p1 = _plan(single_scan(b), precision="mixed", pt_range=pt.pt_range(), fft_len_f64=n64,
+                   fft_len_f32=n32)
+        x = torch.randn(p1.n_vec, dtype=torch.float64, device="cuda",
+                        generator=torch.Generator("cuda").manual_seed(7 + b))
+        xb = torch.zeros(pt.n_vec, dtype=torch.float64, device="cuda")
+        xb[off3[b]:off3[b + 1]] = x
+        for prec in ("fp64", "mixed"):
+            assert torch.equal(p1.apply_A(x, precision=prec),
+                               pt.apply_A(xb, precision=prec)[off3[b]:off3[b + 1]]), (b, prec)
+        p1.close()
     pt.close()
