@@ -546,6 +546,29 @@ def copy_calibration():
                           avg_ms=ms, GBps=2 * a.numel() * 8 / (ms * 1e-3) / 1e9)), flush=True)
 
 
+def device_copy_rate(gib=2, reps=10):
+    """GB/s of a plain device-to-device copy of gib GiB (bytes read + written per second):
+    the streaming rate the HBM delivers in practice, far from the 8 TB/s peak; arrays of
+    this size do not fit the 256 MB last-level cache."""
+    import torch
+    a = torch.ones(int(gib * 2 ** 30) // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(reps):
+        b.copy_(a)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / reps
+    rate = 2 * a.numel() * 8 / (ms * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return round(rate, 1)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -628,6 +651,8 @@ def main():
     del helper
     torch.cuda.synchronize()
     log("inputs resident in HBM")
+    copy_rate = device_copy_rate()
+    log(f"plain 2 GiB device copy: {copy_rate} GB/s")
 
     def step(precision, coarse, precond, profile=False):
         torch.cuda.synchronize()
@@ -737,6 +762,11 @@ def main():
                     avg_launch_ms=round(avg_pt, 5), launches=n_pt, bytes_per_sample=BYTES_PT32,
                     algorithmic_bytes_per_launch=BYTES_PT32 * sc.n_samples)
     roof["hbm_view"] = hbm
+    # context: what a plain streaming copy reaches on this GPU, and the kernel's measured HBM
+    # traffic over its launch time
+    roof["device_copy_GBps"] = copy_rate
+    if roof.get("traffic"):
+        roof["traffic_GBps"] = round(roof["traffic"] / (roof["avg_launch_ms"] * 1e-3) / 1e9, 1)
     roof["other_kernels"] = {k: dict(launches=v[0], avg_ms=v[1] / max(v[0], 1))
                              for k, v in prof.items() if v[0] > 0}
 
