@@ -58,25 +58,26 @@ def fft_tile_flops(offsets, lam, n_r):
 # FETCH_SIZE reads 128 MiB for the 256 MiB read (factor 2.0), WRITE_SIZE 256 MiB (factor 1.0).
 # The factor 2 is that of 128-byte read requests, which FETCH_SIZE counts as 64 bytes; the
 # TCC_EA0_RDREQ_{32B,64B,128B} counters show both kernels read with 128-byte requests too.
-# The figures hold only for the kernel source they were taken on (sha256 below); after any
-# change to that file the traffic is reported as null until the counters are taken again.
+# The figures hold only for the kernel source they were taken on (sha256 of its code, see
+# source_digest); after any change to that code the traffic is reported as null until the
+# counters are taken again.
 TRAFFIC = {
     # 2^24-sample IQU raster, FP32 tile length 16384 (the autotuner's choice on it)
     "ninv32": dict(source="paper_1408_3048_amd/csrc/toeplitz.hip",
-                   sha256="f56727667da3edd9af518216c937a30296f945ffcb1f5cb9b53e8ec7bb178832",
+                   sha256="0f73886de3d4f3cb1f3e4796e5ae8d22a17da3eeb12c15f44b76d3c7b14130dd",
                    by_n_r={16384: dict(fetch_kib=138176.2, write_kib=65548.3)},
                    fetch_factor=2.0, write_factor=1.0),
     "pt32": dict(source="paper_1408_3048_amd/csrc/pointing.hip",
-                 sha256="f9b8097701826ba79f4e3364ef3559d1591769b1a335e8df8b04e01b49b9c074",
+                 sha256="93ea83af66f929598c5a5b68d0ec27f6b5c59b2822aa403e1b27b596d629e7c2",
                  by_n_r={None: dict(fetch_kib=133753.9, write_kib=7909.7)},
                  fetch_factor=2.0, write_factor=1.0),
     # one GPU's share of the ring scan (2^25 samples), FP32 tile length 16384
     "ring_ninv32": dict(source="paper_1408_3048_amd/csrc/toeplitz.hip",
-                        sha256="f56727667da3edd9af518216c937a30296f945ffcb1f5cb9b53e8ec7bb178832",
+                        sha256="0f73886de3d4f3cb1f3e4796e5ae8d22a17da3eeb12c15f44b76d3c7b14130dd",
                         by_n_r={16384: dict(fetch_kib=247742.8, write_kib=131072.0)},
                         fetch_factor=2.0, write_factor=1.0),
     "ring_pt32": dict(source="paper_1408_3048_amd/csrc/pointing.hip",
-                      sha256="f9b8097701826ba79f4e3364ef3559d1591769b1a335e8df8b04e01b49b9c074",
+                      sha256="93ea83af66f929598c5a5b68d0ec27f6b5c59b2822aa403e1b27b596d629e7c2",
                       by_n_r={None: dict(fetch_kib=456496.4, write_kib=46107.1)},
                       fetch_factor=2.0, write_factor=1.0),
 }
@@ -514,6 +515,21 @@ def ring_share_leg(tol, autotune, reps=10, fft_len_f32=0, fft_len_f64=0):
     return res
 
 
+def source_digest(rel):
+    """sha256 of a source file's code: '//' comments, trailing blanks and empty lines
+    removed, so that editing a comment does not void the counter figures taken on it."""
+    lines = []
+    with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
+        for ln in f:
+            i = ln.find("//")
+            if i >= 0 and '"' not in ln[:i]:
+                ln = ln[:i]
+            ln = ln.rstrip()
+            if ln:
+                lines.append(ln)
+    return hashlib.sha256("\n".join(lines).encode()).hexdigest()
+
+
 def kernel_traffic(name, n_r=None):
     """HBM bytes per launch of a kernel from the stored counter figures (for FFT tile length
     n_r where they depend on it), or None when its source has changed since they were taken
@@ -522,9 +538,8 @@ def kernel_traffic(name, n_r=None):
     c = t["by_n_r"].get(n_r if n_r in t["by_n_r"] else None)
     if t["sha256"] is None or c is None:
         return None
-    with open(os.path.join(ROOT, t["source"]), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != t["sha256"]:
-            return None
+    if source_digest(t["source"]) != t["sha256"]:
+        return None
     return round(1024 * (c["fetch_kib"] * t["fetch_factor"] + c["write_kib"] * t["write_factor"]))
 
 

@@ -209,11 +209,12 @@ struct ToepArgs {
 
 // LDS layout of the complex work array (M points).  Element a lives at
 // swz(a) = a ^ (((a >> 5) ^ (a >> 10)) & 31), a bijection within every block of 32
-// points that keeps the radix-16 passes, the spectrum pass and the load/store phases
-// free of bank conflicts on the 64-bank LDS, except one pass with 2-way conflicts
-// (checked by enumerating every access pattern), with no padding.  FP32 points are
-// stored interleaved (one 8-byte access per point), FP64 as split real and imaginary
-// arrays (two 8-byte accesses).
+// points, with no padding.  With 8-byte accesses served 32 lanes at a time over the 64
+// four-byte banks, enumerating every access pattern gives conflict-free radix-16 passes
+// (the block-size-32 pass with its groups mapped so that k is uniform over a wave) and
+// load/store phases, and a 1.2-way spectrum pass.  FP32 points are stored interleaved
+// (one 8-byte access per point), FP64 as split real and imaginary arrays (two 8-byte
+// accesses).
 // swz is linear over XOR, so for bit-disjoint a and c, swz(a + c) = swz(a) ^ swz(c): the
 // passes swizzle their thread's base index once and reach the other points by XOR with
 // compile-time constants.

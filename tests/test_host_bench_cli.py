@@ -14,3 +14,20 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     assert "one GPU only" in r.stderr
     assert r.stdout == ""
+
+
+def test_traffic_figures_follow_the_kernel_code(tmp_path):
+    """The stored HBM traffic applies to the kernel code it was measured on: a comment edit
+    keeps the code digest, a code edit changes it (and the traffic is then reported as
+    null)."""
+    sys.path.insert(0, ROOT)
+    import bench
+    src = tmp_path / "k.hip"
+    src.write_text("// kernel\n__global__ void k(float* x) {  // one store\n    x[0] = 1.0f;\n}\n")
+    d0 = bench.source_digest(str(src))
+    src.write_text("// the kernel, reworded\n\n__global__ void k(float* x) {\n    x[0] = 1.0f;  // same\n}\n")
+    assert bench.source_digest(str(src)) == d0
+    src.write_text("__global__ void k(float* x) {\n    x[0] = 2.0f;\n}\n")
+    assert bench.source_digest(str(src)) != d0
+    for name, n_r in (("ninv32", 16384), ("pt32", None)):
+        assert bench.kernel_traffic(name, n_r) is not None, name
