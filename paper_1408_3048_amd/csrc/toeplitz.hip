@@ -1379,13 +1379,19 @@ int build_tiling(mm_plan_t pl, FftTiling& ft, bool fp64, int n_r_request) {
         }
         logm = l;
     } else {
-        // smallest modelled work: tiles x n_r x (log2 n_r + 4)
+        // smallest modelled time: tiles x n_r x (log2 n_r + 4), doubled for a tile whose
+        // LDS leaves room for only one resident tile per CU (160 KB): a second tile hides
+        // the other's window load (measured: 32768-point FP32 tiles at lambda = 4096 take
+        // 1.27x the time of 16384-point ones, for 0.72x the modelled work)
         double best = 0.0;
         for (int l = kMinLogM; l <= maxlogm; ++l) {
             const int64_t nr = (int64_t)2 << l;
             const int64_t lmax = nr - 2 * (int64_t)lam;
             if (lmax < nr / 4) continue;
-            const double cost = (double)count_tiles(pl->h_off, lmax) * (double)nr * (l + 5);
+            const int64_t tile_lds = nr * (fp64 ? 8 : 4);
+            const double resident = (160 * 1024) / tile_lds >= 2 ? 1.0 : 2.0;
+            const double cost =
+                (double)count_tiles(pl->h_off, lmax) * (double)nr * (l + 5) * resident;
             if (logm == 0 || cost < best) {
                 best = cost;
                 logm = l;
