@@ -64,7 +64,7 @@ def fft_tile_flops(offsets, lam, n_r):
 TRAFFIC = {
     # 2^24-sample IQU raster, FP32 tile length 16384 (the autotuner's choice on it)
     "ninv32": dict(source="paper_1408_3048_amd/csrc/toeplitz.hip",
-                   sha256="93c010bdc36f23fc4fe5cd4aa4e789d8dd7bb910e5fb6ec18606a30879aa04f5",
+                   sha256="408fad95fc00c24b63e108915c3cbb43e0a643f705bfc51b1553a9e1606836d9",
                    by_n_r={16384: dict(fetch_kib=138176.2, write_kib=65548.3)},
                    fetch_factor=2.0, write_factor=1.0),
     "pt32": dict(source="paper_1408_3048_amd/csrc/pointing.hip",
@@ -73,7 +73,7 @@ TRAFFIC = {
                  fetch_factor=2.0, write_factor=1.0),
     # one GPU's share of the ring scan (2^25 samples), FP32 tile length 16384
     "ring_ninv32": dict(source="paper_1408_3048_amd/csrc/toeplitz.hip",
-                        sha256="93c010bdc36f23fc4fe5cd4aa4e789d8dd7bb910e5fb6ec18606a30879aa04f5",
+                        sha256="408fad95fc00c24b63e108915c3cbb43e0a643f705bfc51b1553a9e1606836d9",
                         by_n_r={16384: dict(fetch_kib=247742.8, write_kib=131072.0)},
                         fetch_factor=2.0, write_factor=1.0),
     "ring_pt32": dict(source="paper_1408_3048_amd/csrc/pointing.hip",

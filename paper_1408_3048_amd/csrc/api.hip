@@ -224,6 +224,11 @@ int apply_A64_sparse(mm_plan_t pl, const double* x, double* y, const uint8_t* in
     return scatter64(pl, pl->tod64a.p, y, nullptr);
 }
 
+int apply_A64_sparse_i(mm_plan_t pl, const double* xi, double* y, const uint8_t* int_on) {
+    MM_TRY(toeplitz_map64_i(pl, xi, pl->tod64a.p, int_on));
+    return scatter64(pl, pl->tod64a.p, y, nullptr);
+}
+
 int apply_A32_sparse(mm_plan_t pl, const double* x, double* y, const uint8_t* int_on) {
     MM_TRY(pack_map32(pl, x));
     MM_TRY(toeplitz_map32(pl, x, pl->tod32a.p, nullptr, true, int_on));

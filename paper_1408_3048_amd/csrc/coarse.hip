@@ -191,17 +191,6 @@ __global__ __launch_bounds__(256) void k_cols_equal(const int32_t* __restrict__ 
             neq[i] = 1;
 }
 
-// scatter the entries (pixel, value) of the columns ucol[0..gridDim.y) into a zeroed map
-// vector (I rows); the columns of one layer belong to different problems
-__global__ void k_cols_to_vec(const int32_t* __restrict__ ucol, const int64_t* __restrict__ ub,
-                              const int64_t* __restrict__ ue, const int32_t* __restrict__ rows,
-                              const double* __restrict__ vals, int ns, double* __restrict__ out) {
-    const int32_t u = ucol[blockIdx.y];
-    for (int64_t i = ub[u] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ue[u];
-         i += (int64_t)gridDim.x * blockDim.x)
-        out[(int64_t)rows[i] * ns] = vals[i];
-}
-
 // on[k * K + j] = 1 when layer k's column of interval j's problem has a pixel hit in
 // interval j, i.e. when P applied to that column does not vanish on the whole interval
 // (an entry of Z_S^T Z_S): row p of Z_S lists the intervals that hit pixel p, and each
@@ -232,18 +221,17 @@ __global__ void k_az_int_flags(const int64_t* __restrict__ ptr, const int32_t* _
     }
 }
 
-// the I entries of the columns ucol[0..gridDim.y) into zeroed packed FP32 maps
-// ([n_obs][4] = (I, Q, U, 0)), column y into map lay[y] - k0 (xp + (lay[y] - k0) xstride):
-// the values the packing of the expanded vector would give
-__global__ void k_cols_to_packed(const int32_t* __restrict__ ucol, const int32_t* __restrict__ lay,
-                                 int32_t k0, int64_t xstride, const int64_t* __restrict__ ub,
-                                 const int64_t* __restrict__ ue, const int32_t* __restrict__ rows,
-                                 const double* __restrict__ vals, float* __restrict__ xp) {
+// the entries of the columns ucol[0..gridDim.y) into zeroed maps of their I rows (the Q
+// and U rows of Z_S are zero), column y into map lay[y] - k0 (x + (lay[y] - k0) xstride)
+__global__ void k_cols_to_maps(const int32_t* __restrict__ ucol, const int32_t* __restrict__ lay,
+                               int32_t k0, int64_t xstride, const int64_t* __restrict__ ub,
+                               const int64_t* __restrict__ ue, const int32_t* __restrict__ rows,
+                               const double* __restrict__ vals, double* __restrict__ xm) {
     const int32_t u = ucol[blockIdx.y];
-    float* x = xp + (int64_t)(lay[blockIdx.y] - k0) * xstride;
+    double* x = xm + (int64_t)(lay[blockIdx.y] - k0) * xstride;
     for (int64_t i = ub[u] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ue[u];
          i += (int64_t)gridDim.x * blockDim.x)
-        x[4 * (int64_t)rows[i]] = (float)vals[i];
+        x[rows[i]] = vals[i];
 }
 
 // copy problem lp[y]'s slice of the map vector y into column `col` of its AZ block
@@ -1441,13 +1429,13 @@ int build_coarse(mm_plan_t pl) {
     DBuf<int32_t> d_rb;
     MM_TRY(d_rb.alloc(B));
     MM_HIP(hipMemcpyAsync(d_rb.p, h_rb.data(), B * 4, hipMemcpyHostToDevice, st));
+    // the I rows of the columns of a layer (mixed: of a group of layers), the Q and U rows
+    // of Z_S being zero: N^-1 P reads no weights
     DBuf<double> zc, tmp;
-    MM_TRY(zc.alloc(mixed ? kAzGroup * nv : nv));  // mixed: the maps of a group (I only)
+    MM_TRY(zc.alloc((size_t)(mixed ? kAzGroup : 1) * n_obs));
     if (!mixed) MM_TRY(tmp.alloc(nv));
-    // mixed: the time streams and packed maps (IQU) of a group of layers
-    DBuf<float> todg, xpg;
+    DBuf<float> todg;  // mixed: the time streams of a group of layers
     if (mixed) MM_TRY(todg.alloc((size_t)kAzGroup * pl->n_t));
-    if (mixed && ns == 3) MM_TRY(xpg.alloc((size_t)kAzGroup * 4 * n_obs));
     DBuf<int32_t> lcols, lprob, llay;
     MM_TRY(lcols.alloc((size_t)rd_max * B));
     MM_TRY(lprob.alloc((size_t)rd_max * B));
@@ -1472,53 +1460,30 @@ int build_coarse(mm_plan_t pl) {
         for (int b = 0; b < B; ++b) nb_max = std::max<int64_t>(nb_max, (oo[b + 1] - oo[b]) * ns);
         const int sgx = (int)std::min<int64_t>(1024, (nb_max + 255) / 256);
         int64_t lo = 0;
-        // the sum of every problem's layer-k column into zc
-        auto layer_vec = [&](int32_t k) -> int {
-            MM_HIP(hipMemsetAsync(zc.p, 0, nv * 8, st));
-            hipLaunchKernelGGL(k_cols_to_vec, dim3(16, lcnt[k]), dim3(256), 0, st, lcols.p + lo,
-                               dub.p, due.p, crow.p, cval.p, (int)ns, zc.p);
-            MM_HIP(hipGetLastError());
+        // the I rows of layers k0 .. k0 + nc (columns lo .. lo + their count) into zeroed
+        // maps of n_obs values side by side, in launches of at most 65535 columns
+        auto layer_maps = [&](int32_t k0, int nc) -> int {
+            MM_HIP(hipMemsetAsync(zc.p, 0, (size_t)nc * n_obs * 8, st));
+            int64_t cnt = 0;
+            for (int c = 0; c < nc; ++c) cnt += lcnt[k0 + c];
+            for (int64_t c0 = 0; c0 < cnt; c0 += 65535) {
+                const unsigned gy = (unsigned)std::min<int64_t>(65535, cnt - c0);
+                hipLaunchKernelGGL(k_cols_to_maps, dim3(16, gy), dim3(256), 0, st,
+                                   lcols.p + lo + c0, llay.p + lo + c0, k0, n_obs, dub.p, due.p,
+                                   crow.p, cval.p, zc.p);
+                MM_HIP(hipGetLastError());
+            }
+            lo += cnt;
             return MM_OK;
         };
         if (mixed) {
-            // kAzGroup layers at a time: their maps (packed FP32 for IQU, FP64 for I only)
-            // side by side, one N^-1 P launch over all of them, P^T kScatterCols per pass
+            // kAzGroup layers at a time: one N^-1 P launch over their maps, P^T
+            // kScatterCols layers per pass
             for (int32_t k0 = 0; k0 < rd_max; k0 += kAzGroup) {
                 const int nc = std::min<int32_t>(kAzGroup, rd_max - k0);
-                if (ns == 3)
-                    MM_HIP(hipMemsetAsync(xpg.p, 0, (size_t)nc * 4 * n_obs * sizeof(float), st));
-                else
-                    MM_HIP(hipMemsetAsync(zc.p, 0, (size_t)nc * nv * 8, st));
-                int64_t gcnt = 0;  // columns of the group's layers
-                for (int c = 0; c < nc; ++c) gcnt += lcnt[k0 + c];
-                if (ns == 3 && gcnt <= 65535) {  // the group's maps in one launch
-                    hipLaunchKernelGGL(k_cols_to_packed, dim3(16, (unsigned)gcnt), dim3(256), 0,
-                                       st, lcols.p + lo, llay.p + lo, k0, (int64_t)4 * n_obs,
-                                       dub.p, due.p, crow.p, cval.p, xpg.p);
-                    MM_HIP(hipGetLastError());
-                    lo += gcnt;
-                } else {
-                    for (int c = 0; c < nc; ++c) {
-                        const int32_t k = k0 + c;
-                        if (ns == 3)
-                            hipLaunchKernelGGL(k_cols_to_packed, dim3(16, lcnt[k]), dim3(256), 0,
-                                               st, lcols.p + lo, llay.p + lo, k0,
-                                               (int64_t)4 * n_obs, dub.p, due.p, crow.p, cval.p,
-                                               xpg.p);
-                        else
-                            hipLaunchKernelGGL(k_cols_to_vec, dim3(16, lcnt[k]), dim3(256), 0, st,
-                                               lcols.p + lo, dub.p, due.p, crow.p, cval.p,
-                                               (int)ns, zc.p + (int64_t)c * nv);
-                        MM_HIP(hipGetLastError());
-                        lo += lcnt[k];
-                    }
-                }
-                if (ns == 3)
-                    MM_TRY(toeplitz_map32_layers(pl, nullptr, 0, xpg.p, 4 * n_obs, todg.p, pl->n_t,
-                                                 on.p + (int64_t)k0 * K, K, nc));
-                else
-                    MM_TRY(toeplitz_map32_layers(pl, zc.p, nv, nullptr, 0, todg.p, pl->n_t,
-                                                 on.p + (int64_t)k0 * K, K, nc));
+                MM_TRY(layer_maps(k0, nc));
+                MM_TRY(toeplitz_map32_layers(pl, zc.p, n_obs, nullptr, 0, todg.p, pl->n_t,
+                                             on.p + (int64_t)k0 * K, K, nc));
                 for (int c = 0; c < nc; c += kScatterCols)
                     MM_TRY(scatter_cols32(pl, todg.p + c * pl->n_t, pl->n_t,
                                           std::min(kScatterCols, nc - c), k0 + c, d_rb.p,
@@ -1527,20 +1492,19 @@ int build_coarse(mm_plan_t pl) {
         } else {
             for (int32_t k = 0; k < rd_max; ++k) {
                 const int nl = lcnt[k];
-                MM_TRY(layer_vec(k));
-                MM_TRY(apply_A64_sparse(pl, zc.p, tmp.p, on.p + (int64_t)k * K));
-                hipLaunchKernelGGL(k_store_az<double>, dim3(sgx, nl), dim3(256), 0, st, lprob.p + lo,
-                                   (const double*)tmp.p, pl->ooff.p, (int)ns,
+                const int64_t lo_k = lo;
+                MM_TRY(layer_maps(k, 1));
+                MM_TRY(apply_A64_sparse_i(pl, zc.p, tmp.p, on.p + (int64_t)k * K));
+                hipLaunchKernelGGL(k_store_az<double>, dim3(sgx, nl), dim3(256), 0, st,
+                                   lprob.p + lo_k, (const double*)tmp.p, pl->ooff.p, (int)ns,
                                    (const int64_t*)d_azd_off.p, k, azd.p);
                 MM_HIP(hipGetLastError());
-                lo += nl;
             }
         }
     }
     zc.release();
     tmp.release();
     todg.release();
-    xpg.release();
     on.release();
     tick("AZ");
     // per problem: E_b = Z_b^T (AZ)_b on the matrix cores, independent subset, E_b^-1

@@ -362,9 +362,13 @@ int toeplitz_map64(mm_plan_t pl, const double* x, double* z, const int* mask,
                    bool skip_zero = false, const uint8_t* int_on = nullptr);
 int toeplitz_map32(mm_plan_t pl, const double* x, float* z, const int* mask,
                    bool skip_zero = false, const uint8_t* int_on = nullptr);
+// zero-skipping N^-1 P of a map whose Q and U rows are zero (or of an I-only plan's map),
+// given by its I rows xi (n_obs values): no weights are read; int_on as above
+int toeplitz_map64_i(mm_plan_t pl, const double* xi, double* z, const uint8_t* int_on);
 // zero-skipping FP32 N^-1 P of `layers` maps at once (blockIdx.y = layer y): layer y
-// reads the FP64 map x + y x_step (I only) or the packed FP32 map xp + y xp_step (IQU) and
-// the interval flags int_on + y on_step (or none), and writes z + y z_step
+// reads the I rows x + y x_step (xp null: I-only plans, and IQU maps whose Q and U rows
+// are zero; no weights are read) or the packed FP32 IQU map xp + y xp_step, and the
+// interval flags int_on + y on_step (or none), and writes z + y z_step
 int toeplitz_map32_layers(mm_plan_t pl, const double* x, int64_t x_step, const float* xp,
                           int64_t xp_step, float* z, int64_t z_step, const uint8_t* int_on,
                           int64_t on_step, int layers);
@@ -447,5 +451,7 @@ int apply_A32(mm_plan_t pl, const double* x, double* y, const int* mask);
 // int_on (optional): per-interval flags, 0 where P x vanishes on the whole interval
 int apply_A64_sparse(mm_plan_t pl, const double* x, double* y, const uint8_t* int_on = nullptr);
 int apply_A32_sparse(mm_plan_t pl, const double* x, double* y, const uint8_t* int_on = nullptr);
+// the same for a map whose Q and U rows are zero, given by its I rows xi (n_obs values)
+int apply_A64_sparse_i(mm_plan_t pl, const double* xi, double* y, const uint8_t* int_on);
 
 }  // namespace mm

@@ -828,7 +828,8 @@ __device__ __forceinline__ bool load_window(const ToepArgs<T>& a, const CBuf<T>&
 #pragma unroll
             for (int u = 0; u < B; ++u)
                 v[u] = ok[u] ? xx[u].x + ww[u].x * xx[u].y + ww[u].y * xx[u].z : (T)0;
-        } else if constexpr (MODE == 1) {  // map, I only
+        } else if constexpr (MODE == 1) {  // I rows of the map (I-only plans, and IQU maps
+                                           // whose Q and U rows are zero: the I weight is 1)
             const int32_t* cb = a.cid + base;
             int32_t cc[B];
 #pragma unroll
@@ -1555,6 +1556,16 @@ int toeplitz_map64(mm_plan_t pl, const double* x, double* z, const int* mask, bo
     return launch<double>(a, pl->fft64.logm, pl->fft64.n_tiles, pl->stream);
 }
 
+int toeplitz_map64_i(mm_plan_t pl, const double* xi, double* z, const uint8_t* int_on) {
+    auto a = base_args<double>(pl, pl->fft64);
+    a.skip_zero = 1;
+    a.int_on = int_on;
+    a.x = xi;
+    a.mode = 1;
+    a.z = z;
+    return launch<double>(a, pl->fft64.logm, pl->fft64.n_tiles, pl->stream);
+}
+
 int toeplitz_map32(mm_plan_t pl, const double* x, float* z, const int* mask, bool skip_zero,
                    const uint8_t* int_on) {
     auto a = base_args<float>(pl, pl->fft32);
@@ -1579,7 +1590,7 @@ int toeplitz_map32_layers(mm_plan_t pl, const double* x, int64_t x_step, const f
     a.skip_zero = 1;
     a.x = x;
     a.xp = xp;
-    a.mode = pl->n_s == 3 ? 0 : 1;
+    a.mode = xp ? 0 : 1;
     a.z = z;
     a.int_on = int_on;
     a.layers = layers;
