@@ -65,20 +65,22 @@ TRAFFIC = {
     # 2^24-sample IQU raster, FP32 tile length 16384 (the autotuner's choice on it)
     "ninv32": dict(source="paper_1408_3048_amd/csrc/toeplitz.hip",
                    sha256="408fad95fc00c24b63e108915c3cbb43e0a643f705bfc51b1553a9e1606836d9",
-                   by_n_r={16384: dict(fetch_kib=138176.2, write_kib=65548.3)},
+                   by_cfg={16384: dict(fetch_kib=138176.2, write_kib=65548.3)},
                    fetch_factor=2.0, write_factor=1.0),
+    # P^T on the same scan, by work range (samples per wave)
     "pt32": dict(source="paper_1408_3048_amd/csrc/pointing.hip",
-                 sha256="93ea83af66f929598c5a5b68d0ec27f6b5c59b2822aa403e1b27b596d629e7c2",
-                 by_n_r={None: dict(fetch_kib=133753.9, write_kib=7909.7)},
+                 sha256="d142dab8a229cfbc5bbfb2e3c6a6184bb7bc97440bf9e094fae2d2fbd3755cd7",
+                 by_cfg={512: dict(fetch_kib=135697.9, write_kib=6642.4)},
                  fetch_factor=2.0, write_factor=1.0),
     # one GPU's share of the ring scan (2^25 samples), FP32 tile length 16384
     "ring_ninv32": dict(source="paper_1408_3048_amd/csrc/toeplitz.hip",
                         sha256="408fad95fc00c24b63e108915c3cbb43e0a643f705bfc51b1553a9e1606836d9",
-                        by_n_r={16384: dict(fetch_kib=247742.8, write_kib=131072.0)},
+                        by_cfg={16384: dict(fetch_kib=247742.8, write_kib=131072.0)},
                         fetch_factor=2.0, write_factor=1.0),
     "ring_pt32": dict(source="paper_1408_3048_amd/csrc/pointing.hip",
-                      sha256="93ea83af66f929598c5a5b68d0ec27f6b5c59b2822aa403e1b27b596d629e7c2",
-                      by_n_r={None: dict(fetch_kib=456496.4, write_kib=46107.1)},
+                      sha256="d142dab8a229cfbc5bbfb2e3c6a6184bb7bc97440bf9e094fae2d2fbd3755cd7",
+                      by_cfg={512: dict(fetch_kib=293624.8, write_kib=41099.8),
+                              1024: dict(fetch_kib=296798.5, write_kib=43535.6)},
                       fetch_factor=2.0, write_factor=1.0),
 }
 
@@ -421,7 +423,7 @@ def bandwidth_leg(pix, w, sc, psd, m, d, tol, lams, autotune):
     return out
 
 
-def ring_share_leg(tol, autotune, reps=10, fft_len_f32=0, fft_len_f64=0):
+def ring_share_leg(tol, autotune, reps=10, fft_len_f32=0, fft_len_f64=0, pt_range=0):
     """One GPU's share of the 2^28-sample ring scan at its real shape (Sect. 4.1.1, Table 1
     big-circle scan, sharded by detectors): 2 of the 16 detectors, 2^25 samples, 128
     intervals of 2^18, lambda = 4096, 2048x1024 equirectangular IQU grid.  Reported: the
@@ -458,7 +460,7 @@ def ring_share_leg(tol, autotune, reps=10, fft_len_f32=0, fft_len_f64=0):
     wf = w.to(torch.float32).contiguous()
     psd = np.stack([sc.sigma, sc.fknee, sc.alpha], axis=1)
     kw = dict(n_stokes=3, lam=sc.lam, f_samp=sc.f_samp, autotune=autotune,
-              fft_len_f32=fft_len_f32, fft_len_f64=fft_len_f64)
+              fft_len_f32=fft_len_f32, fft_len_f64=fft_len_f64, pt_range=pt_range)
     del W, Bp, Bs, Binv, hit, seen
     # A x kernels
     plan = Plan(pix2, wf, sc.n_pix + 1, sc.offsets, psd, precision="mixed", **kw)
@@ -476,13 +478,13 @@ def ring_share_leg(tol, autotune, reps=10, fft_len_f32=0, fft_len_f64=0):
     res = dict(workload=("one GPU's share of the 2^28-sample ring scan: 2 of 16 detectors, "
                          "2^25 samples, 128 intervals of 2^18, lambda=4096, 2048x1024 IQU"),
                n_samples=sc.n_samples, unknowns=plan.n_vec, sink_pixels=n_bad,
-               fft_lengths=plan.fft_lengths(),
+               fft_lengths=plan.fft_lengths(), pt_range=plan.pt_range(),
                ninv32=dict(avg_ms=round(a_ninv, 5),
                            GBps=round(BYTES_NINV32 * sc.n_samples / (a_ninv * 1e-3) / 1e9, 1),
                            traffic=kernel_traffic("ring_ninv32", plan.fft_lengths()[1])),
                pt32=dict(avg_ms=round(a_pt, 5),
                          GBps=round(BYTES_PT32 * sc.n_samples / (a_pt * 1e-3) / 1e9, 1),
-                         traffic=kernel_traffic("ring_pt32")),
+                         traffic=kernel_traffic("ring_pt32", plan.pt_range())),
                ax_fp32_GBps=round((BYTES_NINV32 + BYTES_PT32) * sc.n_samples /
                                   ((a_ninv + a_pt) * 1e-3) / 1e9, 1))
     res["ax_fp32_frac_of_peak"] = round(res["ax_fp32_GBps"] / HBM_PEAK_GBPS, 4)
@@ -530,12 +532,12 @@ def source_digest(rel):
     return hashlib.sha256("\n".join(lines).encode()).hexdigest()
 
 
-def kernel_traffic(name, n_r=None):
-    """HBM bytes per launch of a kernel from the stored counter figures (for FFT tile length
-    n_r where they depend on it), or None when its source has changed since they were taken
-    or no figures exist for that configuration."""
+def kernel_traffic(name, cfg):
+    """HBM bytes per launch of a kernel from the stored counter figures for its launch
+    configuration cfg (the FFT tile length of N^-1, the work range of P^T), or None when its
+    source has changed since they were taken or no figures exist for that configuration."""
     t = TRAFFIC[name]
-    c = t["by_n_r"].get(n_r if n_r in t["by_n_r"] else None)
+    c = t["by_cfg"].get(cfg)
     if t["sha256"] is None or c is None:
         return None
     if source_digest(t["source"]) != t["sha256"]:
@@ -607,6 +609,9 @@ def main():
     ap.add_argument("--fft-len-f32", type=int, default=0,
                     help="fixed FP32 overlap-save length instead of the autotuner (profiling runs)")
     ap.add_argument("--fft-len-f64", type=int, default=0)
+    ap.add_argument("--pt-range", type=int, default=0,
+                    help="fixed P^T work range (samples per wave) instead of the autotuner "
+                         "(profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the 256 MiB copy that calibrates the HBM byte counters")
     ap.add_argument("--batched-only", action="store_true",
@@ -633,7 +638,7 @@ def main():
     if args.ring_only:
         print(json.dumps(dict(ring_share=ring_share_leg(
             args.tol, bool(args.autotune), fft_len_f32=args.fft_len_f32,
-            fft_len_f64=args.fft_len_f64))), flush=True)
+            fft_len_f64=args.fft_len_f64, pt_range=args.pt_range))), flush=True)
         return
 
     import synth
@@ -674,7 +679,7 @@ def main():
         t0 = time.perf_counter()
         plan = Plan(pix, w, sc.n_pix, sc.offsets, psd, precision=precision, coarse=coarse,
                     autotune=bool(args.autotune), fft_len_f32=args.fft_len_f32,
-                    fft_len_f64=args.fft_len_f64, **kw)
+                    fft_len_f64=args.fft_len_f64, pt_range=args.pt_range, **kw)
         if profile:
             plan.profile(True)
         b = plan.rhs(d)
@@ -684,7 +689,7 @@ def main():
         t1 = time.perf_counter()
         prof = plan.profile_read() if profile else None
         extra = dict(plan_ms=plan.plan_ms, solve_ms=info["solve_ms"], iterations=info["iterations"],
-                     fft_lengths=plan.fft_lengths(),
+                     fft_lengths=plan.fft_lengths(), pt_range=plan.pt_range(),
                      outer=info["outer_iterations"], relres=info["rel_residual"],
                      r_eff=plan.coarse_rank() if coarse else 0, unknowns=plan.n_vec)
         plan.close()
@@ -749,7 +754,7 @@ def main():
                        traffic=kernel_traffic("ninv32", n_r32), avg_ms=round(avg_ninv, 5)),
         "pt32": dict(GBps=round(BYTES_PT32 * sc.n_samples / (avg_pt * 1e-3) / 1e9, 1),
                      algorithmic_bytes_per_launch=BYTES_PT32 * sc.n_samples,
-                     traffic=kernel_traffic("pt32"), avg_ms=round(avg_pt, 5),
+                     traffic=kernel_traffic("pt32", extras[-1]["pt_range"]), avg_ms=round(avg_pt, 5),
                      frac=round(BYTES_PT32 * sc.n_samples / (avg_pt * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)),
         "ax_fp32_GBps": round((BYTES_NINV32 + BYTES_PT32) * sc.n_samples /
                               ((avg_ninv + avg_pt) * 1e-3) / 1e9, 1),
@@ -772,7 +777,8 @@ def main():
     else:
         achieved = BYTES_PT32 * sc.n_samples / (avg_pt * 1e-3) / 1e9
         roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBPS, 4), traffic=kernel_traffic("pt32"),
+                    frac=round(achieved / HBM_PEAK_GBPS, 4),
+                    traffic=kernel_traffic("pt32", extras[-1]["pt_range"]),
                     kernel="k_scatter<float,3> (P^T segmented reduction)",
                     avg_launch_ms=round(avg_pt, 5), launches=n_pt, bytes_per_sample=BYTES_PT32,
                     algorithmic_bytes_per_launch=BYTES_PT32 * sc.n_samples)

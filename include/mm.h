@@ -105,7 +105,7 @@ typedef struct {
     int pt_range;      /* samples per work range of the P^T segmented reduction (a wave takes
                           the whole pixels starting in its range), a power of two in
                           [256, 65536]; 0 = automatic: 2048, or with autotune the fastest of
-                          1024 / 2048 / 4096 timed on the plan's own data.  Results depend on
+                          512 / 1024 / 2048 / 4096 timed on the plan's own data.  Results depend on
                           it at rounding level (the order of additions within a pixel) */
 } mm_opts;
 

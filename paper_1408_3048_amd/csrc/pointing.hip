@@ -131,6 +131,24 @@ __device__ __forceinline__ void seg_reduce(int64_t i0, int64_t i1, int64_t p0,
     }
 }
 
+// Loads of the sorted pointing (sample indices and weights), which P^T streams once per
+// application, marked non-temporal: they then do not displace from the caches the vectors
+// and A Z columns that the next kernels of an iteration read again (P^T of the 2^24-sample
+// raster 60.7 -> 58.7 us, its mixed two-level solve 19.25 -> 18.90 ms)
+typedef float stream_f4 __attribute__((ext_vector_type(4)));
+typedef double stream_d2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ int32_t ld_stream(const int32_t* p) {
+    return __builtin_nontemporal_load(p);
+}
+__device__ __forceinline__ float4 ld_stream4(const float* p) {
+    const stream_f4 v = __builtin_nontemporal_load(reinterpret_cast<const stream_f4*>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ double2 ld_stream2(const double* p) {
+    const stream_d2 v = __builtin_nontemporal_load(reinterpret_cast<const stream_d2*>(p));
+    return make_double2(v.x, v.y);
+}
+
 // LDS exchange among the lanes of one wave: orders the wave's LDS writes before its reads
 // (a wave's LDS instructions execute in order; this keeps the compiler from moving them)
 __device__ __forceinline__ void wave_lds_sync() {
@@ -180,7 +198,7 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ per
         for (int g = 0; g < E; ++g) {
             const int64_t i = c + lane + 64 * g;
             const bool in = i >= i0 && i < i1;
-            const int32_t t = perm[in ? i : i0];
+            const int32_t t = ld_stream(perm + (in ? i : i0));
             pf[g] = in ? t : -1;
         }
     };
@@ -194,7 +212,7 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ per
                 if constexpr (sizeof(T) == 4) {
 #pragma unroll
                     for (int g = 0; g < E / 2; ++g) {
-                        const float4 a = *reinterpret_cast<const float4*>(ws + 2 * base + 4 * g);
+                        const float4 a = ld_stream4(ws + 2 * base + 4 * g);
                         wv[4 * g] = a.x;
                         wv[4 * g + 1] = a.y;
                         wv[4 * g + 2] = a.z;
@@ -203,7 +221,7 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ per
                 } else {
 #pragma unroll
                     for (int e = 0; e < E; ++e) {
-                        const double2 a = *reinterpret_cast<const double2*>(ws + 2 * (base + e));
+                        const double2 a = ld_stream2(ws + 2 * (base + e));
                         wv[2 * e] = a.x;
                         wv[2 * e + 1] = a.y;
                     }
@@ -296,7 +314,7 @@ __global__ __launch_bounds__(256) void k_scatter_cols(
         for (int g = 0; g < E; ++g) {
             const int64_t i = c + lane + 64 * g;
             const bool in = i >= i0 && i < i1;
-            const int32_t t = perm[in ? i : i0];
+            const int32_t t = ld_stream(perm + (in ? i : i0));
             pf[g] = in ? t : -1;
         }
     };
@@ -307,7 +325,7 @@ __global__ __launch_bounds__(256) void k_scatter_cols(
             if (base < i1) {
 #pragma unroll
                 for (int g = 0; g < E / 2; ++g) {
-                    const float4 a = *reinterpret_cast<const float4*>(ws + 2 * base + 4 * g);
+                    const float4 a = ld_stream4(ws + 2 * base + 4 * g);
                     wv[4 * g] = a.x;
                     wv[4 * g + 1] = a.y;
                     wv[4 * g + 2] = a.z;
@@ -659,8 +677,8 @@ std::map<std::vector<int64_t>, int64_t> g_pt_cache;
 }  // namespace
 
 // The P^T work range of the plan's operator (FP32 for mixed plans, else FP64): each of
-// 1024, 2048 and 4096 samples per range timed over three launches on a nonzero TOD (after
-// one untimed launch), the fastest kept; cached per process for the same scan shape.
+// 512, 1024, 2048 and 4096 samples per range timed over five launches on a nonzero TOD
+// (after one untimed launch), the fastest kept; cached per process for the same scan shape.
 int tune_pt_range(mm_plan_t pl) {
     const bool f32 = pl->opts.precision == MM_MIXED;
     std::vector<int64_t> key = {pl->n_t, pl->n_obs, pl->n_s, pl->n_prob, f32 ? 1 : 0};
@@ -696,11 +714,11 @@ int tune_pt_range(mm_plan_t pl) {
     };
     int64_t best = 0;
     float best_ms = 0.0f;
-    for (const int64_t cand : {1024, 2048, 4096}) {
+    for (const int64_t cand : {512, 1024, 2048, 4096}) {
         MM_TRY(build_wave_ranges(pl, cand));
         MM_TRY(run());
         MM_HIP(hipEventRecord(e0, st));
-        for (int k = 0; k < 3; ++k) MM_TRY(run());
+        for (int k = 0; k < 5; ++k) MM_TRY(run());
         MM_HIP(hipEventRecord(e1, st));
         MM_HIP(hipEventSynchronize(e1));
         float ms = 0.0f;

@@ -29,5 +29,8 @@ def test_traffic_figures_follow_the_kernel_code(tmp_path):
     assert bench.source_digest(str(src)) == d0
     src.write_text("__global__ void k(float* x) {\n    x[0] = 2.0f;\n}\n")
     assert bench.source_digest(str(src)) != d0
-    for name, n_r in (("ninv32", 16384), ("pt32", None)):
-        assert bench.kernel_traffic(name, n_r) is not None, name
+    # the figures of the profiled configurations (FFT tile length, P^T work range); none for
+    # another configuration
+    for name, cfg in (("ninv32", 16384), ("pt32", 512), ("ring_ninv32", 16384)):
+        assert bench.kernel_traffic(name, cfg) is not None, name
+    assert bench.kernel_traffic("ninv32", 8192) is None
